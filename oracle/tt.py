@@ -1,0 +1,134 @@
+"""Particle-number blocked matricisations and TT-SVD truncation (oracle).
+
+The k-th matricisation of x in F^L_N (rows alpha_1..alpha_k, columns alpha_{k+1}..alpha_L,
+Section 2.2) is block diagonal in n = number of particles among orbitals 1..k; the
+sector set is K_k = {max(0, N-L+k), ..., min(N, k)} (Section 2.3).  Block n has
+C(k,n) rows and C(L-k, N-n) columns.
+
+trunc(x; eps, cap) is the sequential (left to right) TT-SVD truncation: at each cut
+k = 1..L-1 the current tensor is projected onto the kept left singular vectors of its
+blocked matricisation.  The error bound of eq. ttsvdquasiopt gives
+||x - trunc(x)|| <= eps when each cut discards at most (eps/sqrt(L-1))^2 of squared
+singular values.  Rank selection across sectors (a reading; the paper has no rank cap):
+
+1. singular values <= zero_tol * sigma_max at this cut are dropped as numerical zeros;
+2. the rest are ordered by value, descending; exact ties go to the lower sector n,
+   then to the lower index inside the sector;
+3. s_tol = the least count whose discarded tail has sum sigma^2 <= (eps/sqrt(L-1))^2;
+4. s = min(s_tol, cap), at least 1; "cap bound" is recorded when s_tol > cap.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ZERO_TOL = 1e-12
+
+
+def sectors(L: int, N: int, k: int):
+    return list(range(max(0, N - L + k), min(N, k) + 1))
+
+
+def _popcount_table(bits: int) -> np.ndarray:
+    idx = np.arange(1 << bits, dtype=np.int64)
+    return np.array([bin(int(b)).count("1") for b in idx])
+
+
+def blocks(x: np.ndarray, L: int, N: int, k: int):
+    """{n: (left_idx, right_idx, B_n)} for the k-th matricisation, B_n = rows x cols."""
+    X = x.reshape(1 << (L - k), 1 << k)  # [right bits, left bits]
+    pl = _popcount_table(k)
+    pr = _popcount_table(L - k)
+    out = {}
+    for n in sectors(L, N, k):
+        li = np.nonzero(pl == n)[0]
+        ri = np.nonzero(pr == N - n)[0]
+        out[n] = (li, ri, X[np.ix_(ri, li)].T.copy())
+    return out
+
+
+def select(svals: dict, delta: float, cap: int, zero_tol: float = ZERO_TOL):
+    """Kept count per sector from singular values {n: descending array} (rules 1-4).
+
+    Returns (kept: dict n -> int, cap_bound: bool, margin) where margin is the
+    relative gap between the last kept and the first discarded value (inf if none),
+    used by tests to decide whether the integer decision is well conditioned."""
+    allv = [(s, n, j) for n, sv in svals.items() for j, s in enumerate(sv)]
+    kept = {n: 0 for n in svals}
+    if not allv:
+        return kept, False, math.inf
+    smax = max(s for s, _, _ in allv)
+    if smax <= 0.0:
+        return kept, False, math.inf
+    cand = [t for t in allv if t[0] > zero_tol * smax]
+    cand.sort(key=lambda t: (-t[0], t[1], t[2]))
+    sq = np.array([t[0] ** 2 for t in cand])
+    tail = np.concatenate([np.cumsum(sq[::-1])[::-1], [0.0]])  # tail[s] = sum_{i>=s}
+    s_tol = int(np.argmax(tail <= delta * delta))
+    cap_bound = s_tol > cap
+    s = max(1, min(s_tol, cap))
+    for t in cand[:s]:
+        kept[t[1]] += 1
+    margin = math.inf
+    if s < len(cand):
+        margin = (cand[s - 1][0] - cand[s][0]) / smax
+    return kept, cap_bound, margin
+
+
+def truncate(x: np.ndarray, L: int, N: int, eps: float, cap: int, zero_tol: float = ZERO_TOL):
+    """Sequential TT-SVD truncation.  Returns (y, rho, cap_bound, min_margin, svals).
+
+    rho[k][n] is the kept rank of sector n at cut k (rho[0][0] = rho[L][N] = 1)."""
+    delta = eps / math.sqrt(L - 1) if L > 1 else eps
+    y = x.copy()
+    rho = [dict() for _ in range(L + 1)]
+    rho[0] = {0: 1}
+    rho[L] = {N: 1}
+    cap_bound = False
+    min_margin = math.inf
+    all_svals = []
+    for k in range(1, L):
+        bl = blocks(y, L, N, k)
+        svd = {}
+        sv = {}
+        for n, (li, ri, B) in bl.items():
+            if B.size == 0:
+                svd[n] = (np.zeros((B.shape[0], 0)), np.zeros(0))
+                sv[n] = np.zeros(0)
+                continue
+            U, s, _ = np.linalg.svd(B, full_matrices=False)
+            svd[n] = (U, s)
+            sv[n] = s
+        kept, cb, margin = select(sv, delta, cap, zero_tol)
+        cap_bound |= cb
+        min_margin = min(min_margin, margin)
+        all_svals.append(sv)
+        Y = y.reshape(1 << (L - k), 1 << k)
+        for n, (li, ri, B) in bl.items():
+            U = svd[n][0][:, :kept[n]]
+            Bp = U @ (U.T @ B)
+            Y[np.ix_(ri, li)] = Bp.T
+        y = Y.reshape(-1)
+        rho[k] = dict(kept)
+    return y, rho, cap_bound, min_margin, all_svals
+
+
+def ranks(x: np.ndarray, L: int, N: int, zero_tol: float = ZERO_TOL):
+    """Numerical rank of every sector block at every cut (rho table of x itself)."""
+    rho = [dict() for _ in range(L + 1)]
+    rho[0] = {0: 1}
+    rho[L] = {N: 1}
+    for k in range(1, L):
+        bl = blocks(x, L, N, k)
+        svs = {n: (np.linalg.svd(B, compute_uv=False) if B.size else np.zeros(0))
+               for n, (_, _, B) in bl.items()}
+        smax = max([s.max() for s in svs.values() if s.size] + [0.0])
+        rho[k] = {n: int(np.sum(s > zero_tol * smax)) for n, s in svs.items()}
+    return rho
+
+
+def singular_values(x: np.ndarray, L: int, N: int, k: int):
+    """{n: descending singular values of sector block n at cut k}."""
+    return {n: (np.linalg.svd(B, compute_uv=False) if B.size else np.zeros(0))
+            for n, (_, _, B) in blocks(x, L, N, k).items()}
