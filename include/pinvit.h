@@ -1,0 +1,169 @@
+/*
+ * pinvit.h -- C ABI of the MI355X block-sparse PINVIT library (libpinvit.so).
+ *
+ * The library computes the lowest eigenvalue of a second-quantised fermionic
+ * Hamiltonian restricted to N particles (Section 1.1, eqs. hamil and Hevp),
+ *     H = sum_ij h_ij a_i^* a_j + sum_ijkl v_ijkl a_i^* a_j^* a_k a_l ,
+ * with the state held as a particle-number block-sparse matrix product state
+ * (Section 2.3) and iterated by preconditioned inverse iteration with rank
+ * truncation (Algorithm 2, "perturbed inverse (inner) iteration"), using the
+ * exponential-sum preconditioner of Section 4 (Cor. lrprecond).
+ *
+ * Conventions
+ * -----------
+ * - Orbitals are 0-based: orbital i of the paper is index i-1 here.
+ * - h: L*L doubles, row-major, h[i*L+j] multiplies a_i^* a_j.
+ * - v: L^4 doubles, row-major, v[((i*L+j)*L+k)*L+l] multiplies a_i^* a_j^* a_k a_l
+ *   (the paper's one-half is already inside).  Only the antisymmetrised combination
+ *   enters, as in the paper's sum.
+ * - gamma: shift; the library works with H_gamma = H + gamma (Section 3.1), applied
+ *   as gamma/N added to every h_ii, which equals H + gamma on the N-particle space.
+ * - Block table rho: an (L+1) x (N+1) int32 array, row-major, rho[k*(N+1)+n] is the
+ *   dimension of sector n on bond k (n = number of particles among orbitals 1..k).
+ *   Entries outside K_k = {max(0,N-L+k)..min(N,k)} are 0; rho[0][0] = rho[L][N] = 1.
+ * - MPS data layout (export and import): sites k = 1..L in order; inside a site,
+ *   left sectors n in K_{k-1} ascending; for each, the unoccupied block U_{k,n}
+ *   (rho[k-1][n] x rho[k][n], present when n is in K_k) followed by the occupied
+ *   block O_{k,n} (rho[k-1][n] x rho[k][n+1], present when n+1 is in K_k)
+ *   (eq. blockstructure); each block column-major (rows = left bond), float64.
+ * - MPS handles are small integers owned by a context; every operation that produces
+ *   an MPS returns a new handle.  pv_mps_free releases one.
+ * - Host pointers are owned by the caller and are only read or written during the
+ *   call.  The context owns all device memory and one HIP stream; all calls on a
+ *   context are synchronous with respect to the host on return.
+ * - A context is used by one thread at a time.  Errors never throw across the ABI:
+ *   every call returns a pv_status and pv_last_error() describes the last failure of
+ *   the calling thread.
+ */
+#ifndef PINVIT_H
+#define PINVIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pv_ctx pv_ctx;
+
+typedef enum {
+  PV_OK = 0,
+  PV_EINVAL = -1,    /* invalid argument (sizes, handles, non-finite input) */
+  PV_ENOMEM = -2,    /* device allocation failed */
+  PV_EDEVICE = -3,   /* HIP runtime error or no device */
+  PV_ENOTSPD = -4,   /* t_min <= 0 (D not positive) or 2x2 Ritz pencil not definite */
+  PV_ENOCONV = -5,   /* iteration limit reached before the tolerance (pv_run only) */
+  PV_ESTATE = -6     /* call out of order (e.g. no Hamiltonian set) */
+} pv_status;
+
+/* Parameters of Algorithm 2 (Section 5.3-5.4, Section 7.1.3). */
+typedef struct {
+  int rank_cap;     /* maximal total rank per bond after every truncation (>= 1) */
+  int m_zip;        /* intermediate rank cap of the H application; <= 0: exact */
+  int max_iter;     /* iteration limit */
+  double tau;       /* stop when the eigenvector error bound (eq. everrbound) <= tau */
+  double c0;        /* exponential-sum accuracy (Thm. expsum), the paper uses 0.1 */
+  double c;         /* spectral-equivalence constant of A (eq. specequivA) */
+  double delta;     /* gap constant delta >= lambda_2/(lambda_2-lambda_1) */
+  double eps_num;   /* residual accuracy; <= 0 selects (1-c)/2 (Section 7.1.3) */
+  double t_eig;     /* Rayleigh-quotient truncation slack, the paper uses 1/2 */
+  double c_lower;   /* C_lower of eq. lowerupper (enters alpha_0 only); <= 0: 1 */
+  double c_upper;   /* C_upper of eq. lowerupper; <= 0: 1 */
+  int max_retries;  /* limit of the residual-tolerance reductions per iteration */
+  int precision;    /* 0: float64 everywhere (the only mode implemented) */
+  /* Resume state from a previous pv_run (pv_result fields eta_res, s_last, s_prev);
+   * resume_s <= 0 starts afresh with a trial residual for the first tolerance. */
+  double resume_eta, resume_s, resume_s2;
+} pv_params;
+
+/* One row of the iteration history. */
+typedef struct {
+  double lambda;      /* Rayleigh quotient of H_gamma (eq. exactrq) */
+  double energy;      /* lambda - gamma */
+  double rho;         /* residual bound rho^n (eq. rhobound) */
+  double bound;       /* eigenvector error bound (eq. everrbound), NaN outside its domain */
+  double r_norm;      /* ||r||, r = trunc(H_gamma psi - lambda psi), ||psi|| = 1 */
+  double s_norm;      /* ||S r|| = residual of the preconditioned problem */
+  double eta_res;     /* accepted residual tolerance */
+  double lambda_star; /* lower Ritz value of the 2x2 step (Rem. omegamin) */
+  double eta_psi;     /* truncation tolerance of the update */
+  double seconds;     /* wall time of the iteration */
+  int retries;        /* tolerance reductions (x 4/5) taken */
+  int cap_bound;      /* 1 if any truncation of the iteration was limited by rank_cap */
+  int max_rank;       /* maximal bond rank of the new iterate */
+  int stopped;        /* 1 on the iteration where the tolerance test succeeded */
+} pv_iter;
+
+typedef struct {
+  double energy, lambda, rho, bound;
+  double eta_res, s_last, s_prev;  /* state for resuming (see pv_params) */
+  int iterations;     /* number of history rows written */
+  int converged;
+} pv_result;
+
+const char* pv_last_error(void);
+
+/* Context on HIP device `device`.  Fails with PV_EDEVICE when there is no GPU. */
+pv_status pv_create(pv_ctx** out, int device);
+void pv_destroy(pv_ctx* ctx);
+
+/* Copies h, v; builds the MPO of H_gamma (Thm. opranks, host) and uploads it; computes
+ * theta_i (Section 7.1.1), t_min, t_max and the exponential-sum terms (Section 4.3). */
+pv_status pv_set_hamiltonian(pv_ctx* ctx, int L, int N, const double* h, const double* v,
+                             double gamma);
+
+/* Preconditioner scalars: out[0..6] = t_min, t_max, T, h, alpha_0 (C_lower=C_upper=1
+ * unless set by pv_run), s_min, s_max; m_range[0..1] = M^-, M^+. */
+pv_status pv_precond_info(pv_ctx* ctx, double* out, int* m_range);
+
+/* MPS management.  pv_mps_create copies `n` doubles in the export layout with the
+ * given block table; pv_mps_determinant builds the rank-one determinant with the
+ * listed N occupied orbitals (Section 7.1.4). */
+pv_status pv_mps_create(pv_ctx* ctx, const int32_t* rho, const double* data, size_t n, int* handle);
+pv_status pv_mps_determinant(pv_ctx* ctx, const int32_t* occupied, int* handle);
+pv_status pv_mps_layout(pv_ctx* ctx, int handle, int32_t* rho, size_t* n);
+pv_status pv_mps_download(pv_ctx* ctx, int handle, double* data, size_t n);
+pv_status pv_mps_free(pv_ctx* ctx, int handle);
+
+/* <a|b> (Euclidean inner product) by a transfer sweep. */
+pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out);
+/* <bra|H_gamma|ket> by an environment sweep with the MPO (eq. exactrq, one term). */
+pv_status pv_expect_h(pv_ctx* ctx, int bra, int ket, double* out);
+/* a*x + b*y as block concatenation (Section 2.3: addition = concatenation). */
+pv_status pv_lincomb(pv_ctx* ctx, double a, int x, double b, int y, int* out);
+/* trunc(x; eps, cap): sequential TT-SVD truncation (eq. ttsvdquasiopt), eps/sqrt(L-1)
+ * per bond, at most `cap` total rank per bond.  Result left-orthogonal, norm in the last
+ * core.  *cap_bound (may be NULL) is set to 1 when the cap limited a bond. */
+pv_status pv_round(pv_ctx* ctx, int x, double eps, int cap, int* out, int* cap_bound);
+/* trunc(H_gamma x; eps, cap), H applied site by site with intermediate rank m_zip
+ * (m_zip <= 0: exact product). */
+pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound);
+/* S x by the sorted sequential truncated sum of Lemma truncr with total tolerance eta. */
+pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap_bound);
+
+/* Algorithm 2 from the determinant of the N smallest h_ii (ties: lower index), or from
+ * the MPS `start` when start >= 0.  Writes up to hist_cap history rows; *psi (may be
+ * NULL) receives a handle of the final iterate. */
+pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
+                 pv_iter* hist, int hist_cap, int* psi);
+
+/* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
+ * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk), bytes[i] =
+ * algorithmic bytes, for i < n classes; names via pv_timer_name. */
+pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
+const char* pv_timer_name(int i);
+pv_status pv_timers_reset(pv_ctx* ctx);
+
+/* Host-only diagnostics (no GPU needed). */
+/* Bond dimensions of the MPO of H: dims[0..L] and per-charge counts q=-2..2 in
+ * qdims[(L+1)*5]. */
+pv_status pv_mpo_bond_dims(int L, const double* h, const double* v, int32_t* dims, int32_t* qdims);
+/* Dense 2^L x 2^L matrix of H + gamma/N * sum_i n_i from the MPO, row-major,
+ * index bit i = occupation of orbital i (L <= 8). */
+pv_status pv_mpo_dense(int L, const double* h, const double* v, double diag_shift, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINVIT_H */

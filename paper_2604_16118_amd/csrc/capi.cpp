@@ -1,0 +1,545 @@
+// C ABI (include/pinvit.h) and the driver of Algorithm 2.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+
+#include "engine.hpp"
+
+using namespace pv;
+
+struct pv_ctx {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+pv_status guard(F&& f) {
+  try {
+    f();
+    return PV_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return PV_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    const std::string w = e.what();
+    if (w.rfind("kernel launch", 0) == 0) return PV_EDEVICE;
+    return PV_EINVAL;
+  }
+}
+
+Mps& get(Ctx& c, int h) {
+  auto it = c.mps.find(h);
+  if (it == c.mps.end()) fail(PV_EINVAL, "unknown MPS handle " + std::to_string(h));
+  return *it->second;
+}
+
+int put(Ctx& c, std::unique_ptr<Mps> m) {
+  const int h = c.next_handle++;
+  c.mps[h] = std::move(m);
+  return h;
+}
+
+// ---- exponential sum (Thm. expsum, eqs. expsum and expsumparams) ----
+void expsum_params(double c0, double T, double* h, int* mp, int* mm) {
+  *h = M_PI * M_PI / std::log(8.0 * std::sqrt(2.0) / c0 + 1.0);
+  const double lg = std::fabs(std::log(std::sqrt(M_PI) * c0 / 4.0));
+  *mp = int(std::ceil(std::log(lg) / *h));
+  *mm = -int(std::ceil((2.0 * lg + std::log(T)) / *h));
+}
+
+double expsum(double t, double h, int mp, int mm) {
+  double s = 0.0;
+  for (int m = mm; m <= mp; ++m) s += std::exp(m * h / 2.0) * std::exp(-std::exp(m * h) * t);
+  return h / std::sqrt(M_PI) * s;
+}
+
+// theta_i of Section 7.1.1 with one-based window j = k_i+1 .. k_i+N, k_i = max(0, i-N).
+void setup_precond(Ctx& c, double c0, double cl, double cu) {
+  const int L = c.L, N = c.N;
+  c.theta.assign(L, 0.0);
+  for (int i1 = 1; i1 <= L; ++i1) {
+    const int ki = std::max(0, i1 - N);
+    double acc = c.gamma / N + c.h[size_t(i1 - 1) * L + (i1 - 1)];
+    for (int j1 = ki + 1; j1 <= ki + N; ++j1) {
+      const int i = i1 - 1, j = j1 - 1;
+      auto V = [&](int a, int b, int cc, int d) { return c.v[((size_t(a) * L + b) * L + cc) * L + d]; };
+      acc += V(i, j, j, i) - V(i, j, i, j);
+    }
+    c.theta[i1 - 1] = acc;
+  }
+  std::vector<double> s = c.theta;
+  std::sort(s.begin(), s.end());
+  c.t_min = std::accumulate(s.begin(), s.begin() + N, 0.0);
+  c.t_max = std::accumulate(s.end() - N, s.end(), 0.0);
+  if (!(c.t_min > 0.0)) fail(PV_ENOTSPD, "t_min <= 0: the shift does not make D positive");
+  c.T = c.t_max / c.t_min;
+  expsum_params(c0, c.T, &c.hs, &c.m_plus, &c.m_minus);
+  c.a0 = std::sqrt(2.0 / (c.t_min * (cl * (1 - c0) * (1 - c0) + cu * (1 + c0) * (1 + c0))));
+  c.alpha.clear();
+  c.beta.clear();
+  for (int m = c.m_minus; m <= c.m_plus; ++m) {
+    c.alpha.push_back(c.hs * c.a0 / std::sqrt(M_PI) * std::exp(m * c.hs / 2.0));
+    c.beta.push_back(std::exp(m * c.hs) / c.t_min);
+  }
+  c.s_max = c.a0 * expsum(1.0, c.hs, c.m_plus, c.m_minus);
+  c.s_min = c.a0 * expsum(c.T, c.hs, c.m_plus, c.m_minus);
+}
+
+// b_delta of eq. bbetarho and the eigenvector bound of eq. everrbound.
+double error_bound(double rho, double delta) {
+  if (rho * rho > 1.0 / (4.0 * delta * (delta - 1.0))) return std::numeric_limits<double>::quiet_NaN();
+  const double disc = 1.0 - 4.0 * (delta - 1.0) * delta * rho * rho;
+  const double b = 2.0 * delta / (1.0 + 2.0 * delta * rho * rho + std::sqrt(std::max(disc, 0.0)));
+  const double arg = std::sqrt(delta * b) * rho;
+  if (arg > 1.0) return std::numeric_limits<double>::quiet_NaN();
+  return 2.0 * std::sin(0.5 * std::asin(arg));
+}
+
+// Lower eigenpair of the 2x2 pencil (Rem. omegamin), v^T mm v = 1, v[0] > 0.
+void ritz2(const double hm[3], const double mm[3], double* lam, double v[2]) {
+  // hm = {h00, h01, h11}, mm = {m00, m01, m11}
+  const double a = mm[0] * mm[2] - mm[1] * mm[1];
+  if (!(a > 0.0)) fail(PV_ENOTSPD, "2x2 Ritz pencil is not definite (search direction parallel to iterate)");
+  const double b = -(hm[0] * mm[2] + hm[2] * mm[0] - 2.0 * hm[1] * mm[1]);
+  const double cc = hm[0] * hm[2] - hm[1] * hm[1];
+  const double disc = std::max(b * b - 4.0 * a * cc, 0.0);
+  double r1, r2;
+  if (b < 0) { const double q = -0.5 * (b - std::sqrt(disc)); r1 = q / a; r2 = cc / q; }
+  else { const double q = -0.5 * (b + std::sqrt(disc)); r1 = cc / q; r2 = q / a; }
+  *lam = std::min(r1, r2);
+  const double k00 = hm[0] - *lam * mm[0], k01 = hm[1] - *lam * mm[1], k11 = hm[2] - *lam * mm[2];
+  double v0, v1;
+  if (std::fabs(k00) + std::fabs(k01) >= std::fabs(k01) + std::fabs(k11)) { v0 = -k01; v1 = k00; }
+  else { v0 = k11; v1 = -k01; }
+  const double nn = std::sqrt(v0 * v0 * mm[0] + 2.0 * v0 * v1 * mm[1] + v1 * v1 * mm[2]);
+  v0 /= nn; v1 /= nn;
+  if (v0 < 0 || (v0 == 0 && v1 < 0)) { v0 = -v0; v1 = -v1; }
+  v[0] = v0; v[1] = v1;
+}
+
+double delta_a(double rho, double q) {
+  return (-q * rho + std::sqrt(q * q * rho * rho + (1.0 + rho * rho) * (1.0 - q * q))) / (1.0 + rho * rho);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pv_last_error(void) { return g_err.c_str(); }
+
+pv_status pv_create(pv_ctx** out, int device) {
+  if (!out) { g_err = "null output pointer"; return PV_EINVAL; }
+  *out = nullptr;
+  return guard([&] {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= device || device < 0) {
+      (void)hipGetLastError();
+      fail(PV_EDEVICE, "no HIP device " + std::to_string(device));
+    }
+    PV_HIP(hipSetDevice(device));
+    auto* ctx = new pv_ctx();
+    try {
+      ctx->c.device = device;
+      PV_HIP(hipStreamCreate(&ctx->c.stream));
+      ctx->c.staging.init(size_t(64) << 20);
+    } catch (...) {
+      delete ctx;
+      throw;
+    }
+    *out = ctx;
+  });
+}
+
+void pv_destroy(pv_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
+    for (auto& p : ctx->c.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    hipStream_t s = ctx->c.stream;
+    delete ctx;
+    if (s) (void)hipStreamDestroy(s);
+  } catch (...) {
+  }
+}
+
+pv_status pv_set_hamiltonian(pv_ctx* ctx, int L, int N, const double* h, const double* v, double gamma) {
+  return guard([&] {
+    if (!ctx || !h || !v) fail(PV_EINVAL, "null argument");
+    if (L < 2 || L > 127 || N < 1 || N > L - 1) fail(PV_EINVAL, "need 2 <= L <= 127 and 1 <= N <= L-1");
+    if (!std::isfinite(gamma)) fail(PV_EINVAL, "gamma not finite");
+    const size_t nv = size_t(L) * L * L * L;
+    for (size_t i = 0; i < size_t(L) * L; ++i) if (!std::isfinite(h[i])) fail(PV_EINVAL, "h not finite");
+    for (size_t i = 0; i < nv; ++i) if (!std::isfinite(v[i])) fail(PV_EINVAL, "v not finite");
+    Ctx& c = ctx->c;
+    PV_HIP(hipSetDevice(c.device));
+    c.sync();
+    c.mps.clear();
+    c.L = L; c.N = N; c.gamma = gamma;
+    c.h.assign(h, h + size_t(L) * L);
+    c.v.assign(v, v + nv);
+    Mpo m = build_mpo(L, h, v, gamma / N);
+    c.mpo_w = m.w;
+    c.hmpo = upload_mpo(c, m);
+    c.ident.reset();
+    setup_precond(c, 0.1, 1.0, 1.0);
+  });
+}
+
+pv_status pv_precond_info(pv_ctx* ctx, double* out, int* m_range) {
+  return guard([&] {
+    if (!ctx || !out || !m_range) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    double v[7] = {c.t_min, c.t_max, c.T, c.hs, c.a0, c.s_min, c.s_max};
+    std::memcpy(out, v, sizeof(v));
+    m_range[0] = c.m_minus;
+    m_range[1] = c.m_plus;
+  });
+}
+
+pv_status pv_mps_create(pv_ctx* ctx, const int32_t* rho, const double* data, size_t n, int* handle) {
+  return guard([&] {
+    if (!ctx || !rho || !handle) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    const int L = c.L, N = c.N;
+    std::vector<std::vector<int>> r(L + 1, std::vector<int>(N + 1, 0));
+    Mps probe; probe.L = L; probe.N = N;
+    for (int k = 0; k <= L; ++k)
+      for (int nn = 0; nn <= N; ++nn) {
+        const int x = rho[k * (N + 1) + nn];
+        if (x < 0 || x > (1 << 20)) fail(PV_EINVAL, "block table entry out of range");
+        if (!probe.valid(k, nn) && x != 0) fail(PV_EINVAL, "nonzero rank outside the sector set K_k");
+        r[k][nn] = x;
+      }
+    if (r[0][0] != 1 || r[L][N] != 1) fail(PV_EINVAL, "rho[0][0] and rho[L][N] must be 1");
+    auto m = mps_alloc(c, L, N, r);
+    if (size_t(m->size()) != n) fail(PV_EINVAL, "data length does not match the block table");
+    if (!data && n) fail(PV_EINVAL, "null data");
+    for (size_t i = 0; i < n; ++i) if (!std::isfinite(data[i])) fail(PV_EINVAL, "MPS data not finite");
+    size_t o = 0;
+    for (int k = 1; k <= L; ++k) {
+      const size_t s = size_t(m->site_size(k));
+      if (s) PV_HIP(hipMemcpyAsync(m->site[k - 1].p, data + o, s * 8, hipMemcpyHostToDevice, c.stream));
+      o += s;
+    }
+    c.sync();
+    *handle = put(c, std::move(m));
+  });
+}
+
+pv_status pv_mps_determinant(pv_ctx* ctx, const int32_t* occupied, int* handle) {
+  return guard([&] {
+    if (!ctx || !occupied || !handle) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    std::vector<int> occ(occupied, occupied + c.N);
+    std::vector<int> s = occ;
+    std::sort(s.begin(), s.end());
+    for (int i = 0; i < c.N; ++i)
+      if (s[i] < 0 || s[i] >= c.L || (i && s[i] == s[i - 1])) fail(PV_EINVAL, "occupied orbitals must be N distinct indices in [0, L)");
+    *handle = put(c, mps_determinant(c, occ));
+    c.sync();
+  });
+}
+
+pv_status pv_mps_layout(pv_ctx* ctx, int handle, int32_t* rho, size_t* n) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    Mps& m = get(ctx->c, handle);
+    if (rho)
+      for (int k = 0; k <= m.L; ++k)
+        for (int nn = 0; nn <= m.N; ++nn) rho[k * (m.N + 1) + nn] = m.valid(k, nn) ? m.rho[k][nn] : 0;
+    if (n) *n = size_t(m.size());
+  });
+}
+
+pv_status pv_mps_download(pv_ctx* ctx, int handle, double* data, size_t n) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    Mps& m = get(c, handle);
+    if (size_t(m.size()) != n) fail(PV_EINVAL, "buffer length does not match the MPS size");
+    size_t o = 0;
+    for (int k = 1; k <= m.L; ++k) {
+      const size_t s = size_t(m.site_size(k));
+      if (s) PV_HIP(hipMemcpyAsync(data + o, m.site[k - 1].p, s * 8, hipMemcpyDeviceToHost, c.stream));
+      o += s;
+    }
+    c.sync();
+  });
+}
+
+pv_status pv_mps_free(pv_ctx* ctx, int handle) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    auto it = c.mps.find(handle);
+    if (it == c.mps.end()) fail(PV_EINVAL, "unknown MPS handle");
+    c.sync();
+    c.mps.erase(it);
+  });
+}
+
+pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    *out = dot(ctx->c, get(ctx->c, a), get(ctx->c, b));
+  });
+}
+
+pv_status pv_expect_h(pv_ctx* ctx, int bra, int ket, double* out) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    *out = expect_h(ctx->c, get(ctx->c, bra), get(ctx->c, ket));
+  });
+}
+
+pv_status pv_lincomb(pv_ctx* ctx, double a, int x, double b, int y, int* out) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    if (!std::isfinite(a) || !std::isfinite(b)) fail(PV_EINVAL, "coefficients not finite");
+    auto m = mps_lincomb(ctx->c, a, get(ctx->c, x), b, get(ctx->c, y));
+    ctx->c.sync();
+    *out = put(ctx->c, std::move(m));
+  });
+}
+
+pv_status pv_round(pv_ctx* ctx, int x, double eps, int cap, int* out, int* cap_bound) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    if (!(eps >= 0) || cap < 1) fail(PV_EINVAL, "need eps >= 0 and cap >= 1");
+    bool cb = false;
+    auto m = round_mps(ctx->c, get(ctx->c, x), eps, cap, &cb);
+    ctx->c.sync();
+    *out = put(ctx->c, std::move(m));
+    if (cap_bound) *cap_bound = cb;
+  });
+}
+
+pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    if (!(eps >= 0) || cap < 1) fail(PV_EINVAL, "need eps >= 0 and cap >= 1");
+    bool cb = false;
+    auto m = apply_h(ctx->c, get(ctx->c, x), eps, cap, m_zip, &cb);
+    ctx->c.sync();
+    *out = put(ctx->c, std::move(m));
+    if (cap_bound) *cap_bound = cb;
+  });
+}
+
+pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap_bound) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    if (!(eta >= 0) || cap < 1) fail(PV_EINVAL, "need eta >= 0 and cap >= 1");
+    if (!ctx->c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    bool cb = false;
+    auto m = apply_s(ctx->c, get(ctx->c, x), eta, cap, &cb);
+    ctx->c.sync();
+    *out = put(ctx->c, std::move(m));
+    if (cap_bound) *cap_bound = cb;
+  });
+}
+
+// Algorithm 2 on psi = S x (see the oracle's pinvit module for the step list).
+pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, pv_iter* hist,
+                 int hist_cap, int* psi_out) {
+  return guard([&] {
+    if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    const pv_params p = *prm;
+    if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
+        !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
+      fail(PV_EINVAL, "invalid parameters");
+    if (p.precision != 0) fail(PV_EINVAL, "only precision 0 (float64) is implemented");
+    setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
+    const int L = c.L, N = c.N, cap = p.rank_cap, mz = p.m_zip;
+    const double eps_num = p.eps_num > 0 ? p.eps_num : 0.5 * (1.0 - p.c);
+    const double zeta = eps_num / (1.0 + p.c);
+    double eta = std::numeric_limits<double>::infinity();
+    double s_prev = -1, s_prev2 = -1;
+    if (p.resume_s > 0) {
+      s_prev = p.resume_s;
+      s_prev2 = p.resume_s2;
+      if (p.resume_eta > 0) eta = p.resume_eta;
+    }
+    std::unique_ptr<Mps> psi;
+    if (start >= 0) {
+      const Mps& s0 = get(c, start);
+      psi = mps_scaled_copy(c, s0, 1.0, nullptr);
+    } else {
+      std::vector<int> idx(L);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c.h[size_t(a) * L + a] < c.h[size_t(b) * L + b]; });
+      std::vector<int> occ(idx.begin(), idx.begin() + N);
+      psi = mps_determinant(c, occ);
+    }
+    int rows = 0;
+    *res = pv_result{};
+    for (int it = 0; it < p.max_iter; ++it) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const double nrm = std::sqrt(dot(c, *psi, *psi));
+      if (!(nrm > 0)) fail(PV_ENOCONV, "iterate vanished");
+      psi = mps_scaled_copy(c, *psi, 1.0 / nrm, nullptr);
+      const double lam = expect_h(c, *psi, *psi);
+      double est;
+      if (s_prev < 0) {
+        auto y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
+        auto d0 = mps_lincomb(c, 1.0, *y0, -lam, *psi);
+        auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
+        est = c.s_max * norm_canonical(c, *r0);
+      } else if (s_prev2 <= 0) {
+        est = s_prev;
+      } else {
+        est = s_prev * std::min(1.0, s_prev / s_prev2);
+      }
+      eta = std::min(2.0 * eta, 0.8 * zeta * est);
+      int retries = 0;
+      bool capb = false;
+      std::unique_ptr<Mps> r, s;
+      double ns = 0;
+      while (true) {
+        bool cb1 = false, cb2 = false, cb3 = false;
+        const double e12 = eta / (3.0 * c.s_max);
+        auto y = apply_h(c, *psi, e12, cap, mz, &cb1);
+        auto d = mps_lincomb(c, 1.0, *y, -lam, *psi);
+        y.reset();
+        r = round_mps(c, *d, e12, cap, &cb2);
+        d.reset();
+        s = apply_s(c, *r, eta / 3.0, cap, &cb3);
+        capb = cb1 || cb2 || cb3;
+        ns = norm_canonical(c, *s);
+        if (ns >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries) break;
+        eta *= 0.8;
+        ++retries;
+      }
+      bool cb4 = false;
+      auto pdir = apply_s(c, *s, c.s_max * eta / 3.0, cap, &cb4);
+      const double nr = norm_canonical(c, *r);
+      const double rho = (ns + eta) / (std::sqrt(1.0 - p.c) * std::sqrt(lam));
+      const double bound = error_bound(rho, p.delta);
+      pv_iter rec{};
+      rec.lambda = lam;
+      rec.energy = lam - c.gamma;
+      rec.rho = rho;
+      rec.bound = bound;
+      rec.r_norm = nr;
+      rec.s_norm = ns;
+      rec.eta_res = eta;
+      rec.retries = retries;
+      rec.cap_bound = (capb || cb4) ? 1 : 0;
+      res->energy = rec.energy;
+      res->lambda = lam;
+      res->rho = rho;
+      res->bound = bound;
+      if (bound <= p.tau) {
+        rec.stopped = 1;
+        rec.max_rank = psi->max_rank();
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        break;
+      }
+      const double np = norm_canonical(c, *pdir);
+      if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
+      auto z2 = mps_scaled_copy(c, *pdir, 1.0 / np, nullptr);
+      pdir.reset();
+      const double h12 = expect_h(c, *psi, *z2);
+      const double h22 = expect_h(c, *z2, *z2);
+      const double o12 = dot(c, *psi, *z2);
+      const double hm[3] = {lam, h12, h22}, mm[3] = {1.0, o12, 1.0};
+      double lam_s, v[2];
+      ritz2(hm, mm, &lam_s, v);
+      const double q = std::sqrt(lam_s / (lam_s + p.t_eig * (lam - lam_s)));
+      const double da = delta_a(rho, q);
+      const double eta_in = da * std::sqrt(lam_s) / std::sqrt(1.0 + p.c);
+      const double eta_psi = eta_in * c.s_min;
+      auto comb = mps_lincomb(c, v[0], *psi, v[1], *z2);
+      bool cb5 = false;
+      psi = round_mps(c, *comb, eta_psi, cap, &cb5);
+      c.sync();
+      rec.lambda_star = lam_s;
+      rec.eta_psi = eta_psi;
+      rec.cap_bound |= cb5 ? 1 : 0;
+      rec.max_rank = psi->max_rank();
+      rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (hist && rows < hist_cap) hist[rows] = rec;
+      ++rows;
+      s_prev2 = s_prev;
+      s_prev = ns;
+      res->eta_res = eta;
+      res->s_last = s_prev;
+      res->s_prev = s_prev2;
+    }
+    res->iterations = rows;
+    if (psi_out) *psi_out = put(c, std::move(psi));
+  });
+}
+
+static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce"};
+
+pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    c.sync();
+    for (int i = 0; i < n && i < T_COUNT; ++i) {
+      if (ms) ms[i] = c.t_ms[i];
+      if (flops) flops[i] = c.t_flops[i];
+      if (bytes) bytes[i] = c.t_bytes[i];
+      if (calls) calls[i] = c.t_calls[i];
+    }
+  });
+}
+
+const char* pv_timer_name(int i) { return (i >= 0 && i < T_COUNT) ? kTimerNames[i] : ""; }
+
+pv_status pv_timers_reset(pv_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    c.sync();
+    for (int i = 0; i < T_COUNT; ++i) { c.t_ms[i] = 0; c.t_flops[i] = 0; c.t_bytes[i] = 0; c.t_calls[i] = 0; }
+  });
+}
+
+pv_status pv_mpo_bond_dims(int L, const double* h, const double* v, int32_t* dims, int32_t* qdims) {
+  return guard([&] {
+    if (!h || !v || !dims) fail(PV_EINVAL, "null argument");
+    if (L < 2 || L > 127) fail(PV_EINVAL, "L out of range");
+    Mpo m = build_mpo(L, h, v, 0.0);
+    for (int k = 0; k <= L; ++k) {
+      dims[k] = m.w[k];
+      if (qdims)
+        for (int q = 0; q < 5; ++q) qdims[k * 5 + q] = m.qoff[k][q + 1] - m.qoff[k][q];
+    }
+  });
+}
+
+pv_status pv_mpo_dense(int L, const double* h, const double* v, double diag_shift, double* out) {
+  return guard([&] {
+    if (!h || !v || !out) fail(PV_EINVAL, "null argument");
+    if (L < 1 || L > 8) fail(PV_EINVAL, "dense MPO contraction needs 1 <= L <= 8");
+    Mpo m = build_mpo(L, h, v, diag_shift);
+    mpo_to_dense(m, out);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,1242 @@
+// Runtime pieces (pool, staging, timers) and the block-sparse MPS operations.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace pv {
+
+// ---------------------------------------------------------------- pool
+static size_t size_class(size_t bytes) {
+  if (bytes <= 4096) return 4096;
+  size_t p = 1;
+  while ((p << 1) <= bytes) p <<= 1;
+  const size_t step = std::max<size_t>(p / 8, 256);
+  return (bytes + step - 1) / step * step;
+}
+
+Pool::~Pool() { release(); }
+
+void* Pool::get(size_t bytes) {
+  const size_t cls = size_class(bytes);
+  auto it = free_.find(cls);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    cached_ -= cls;
+    in_use_ += cls;
+    return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, cls);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(PV_ENOMEM, "hipMalloc of " + std::to_string(cls) + " bytes failed");
+    }
+  }
+  in_use_ += cls;
+  return p;
+}
+
+void Pool::put(void* p, size_t bytes) {
+  if (!p) return;
+  const size_t cls = size_class(bytes);
+  free_.emplace(cls, p);
+  in_use_ -= cls;
+  cached_ += cls;
+}
+
+void Pool::release() {
+  for (auto& kv : free_) (void)hipFree(kv.second);
+  free_.clear();
+  cached_ = 0;
+}
+
+Buf::Buf(Pool& pl, size_t count) : pool(&pl), n(count) {
+  p = count ? static_cast<double*>(pl.get(count * sizeof(double))) : nullptr;
+}
+
+Buf& Buf::operator=(Buf&& o) noexcept {
+  if (this != &o) {
+    reset();
+    pool = o.pool; p = o.p; n = o.n;
+    o.p = nullptr; o.n = 0;
+  }
+  return *this;
+}
+
+void Buf::reset() {
+  if (p && pool) pool->put(p, n * sizeof(double));
+  p = nullptr;
+  n = 0;
+}
+
+// ---------------------------------------------------------------- staging
+void Staging::init(size_t cap) {
+  void* p = nullptr;
+  PV_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+  base_ = static_cast<char*>(p);
+  cap_ = cap;
+  used_ = 0;
+}
+Staging::~Staging() {
+  if (base_) (void)hipHostFree(base_);
+}
+void* Staging::put(const void* src, size_t bytes) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (used_ + need > cap_) fail(PV_ENOMEM, "staging area exhausted");
+  void* dst = base_ + used_;
+  std::memcpy(dst, src, bytes);
+  used_ += need;
+  return dst;
+}
+
+// ---------------------------------------------------------------- ctx
+hipEvent_t Ctx::event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PV_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Ctx::begin(int, hipEvent_t& a) {
+  if (!timing) { a = nullptr; return; }
+  a = event();
+  PV_HIP(hipEventRecord(a, stream));
+}
+
+void Ctx::end(int cls, hipEvent_t a, double flops, double bytes) {
+  if (!timing || !a) return;
+  hipEvent_t b = event();
+  PV_HIP(hipEventRecord(b, stream));
+  pending.push_back({cls, a, b, flops, bytes});
+}
+
+void Ctx::sync() {
+  PV_HIP(hipStreamSynchronize(stream));
+  for (auto& p : pending) {
+    float ms = 0.f;
+    PV_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    t_ms[p.cls] += ms;
+    t_flops[p.cls] += p.flops;
+    t_bytes[p.cls] += p.bytes;
+    t_calls[p.cls] += 1;
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+  scratch.clear();
+  staging.reset();
+}
+
+template <class T>
+T* Ctx::upload(const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  const size_t bytes = v.size() * sizeof(T);
+  if (!staging.fits(bytes)) sync();
+  void* host = staging.put(v.data(), bytes);
+  Buf b(pool, (bytes + sizeof(double) - 1) / sizeof(double));
+  PV_HIP(hipMemcpyAsync(b.p, host, bytes, hipMemcpyHostToDevice, stream));
+  T* out = reinterpret_cast<T*>(b.p);
+  scratch.push_back(std::move(b));
+  return out;
+}
+template GemmDesc* Ctx::upload(const std::vector<GemmDesc>&);
+
+static Buf scratch_buf(Ctx& c, size_t n) {
+  return Buf(c.pool, n);
+}
+
+// ---------------------------------------------------------------- MPS basics
+int64_t Mps::site_size(int k) const {
+  int64_t s = 0;
+  for (int n = 0; n <= N; ++n)
+    if (valid(k - 1, n)) s += int64_t(rows(k, n)) * (ucols(k, n) + ocols(k, n));
+  return s;
+}
+int64_t Mps::size() const {
+  int64_t s = 0;
+  for (int k = 1; k <= L; ++k) s += site_size(k);
+  return s;
+}
+int Mps::max_rank() const {
+  int r = 0;
+  for (int k = 0; k <= L; ++k) {
+    int t = 0;
+    for (int n = 0; n <= N; ++n) t += valid(k, n) ? rho[k][n] : 0;
+    r = std::max(r, t);
+  }
+  return r;
+}
+
+static void layout_site(Mps& m, int k) {
+  m.off[k - 1].assign(m.N + 1, 0);
+  int64_t o = 0;
+  for (int n = 0; n <= m.N; ++n) {
+    m.off[k - 1][n] = o;
+    if (m.valid(k - 1, n)) o += int64_t(m.rows(k, n)) * (m.ucols(k, n) + m.ocols(k, n));
+  }
+}
+
+static void alloc_site(Ctx& c, Mps& m, int k) {
+  layout_site(m, k);
+  m.site[k - 1] = Buf(c.pool, size_t(std::max<int64_t>(m.site_size(k), 1)));
+}
+
+std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vector<int>>& rho) {
+  auto m = std::make_unique<Mps>();
+  m->L = L;
+  m->N = N;
+  m->rho = rho;
+  m->site.resize(L);
+  m->off.resize(L);
+  for (int k = 1; k <= L; ++k) alloc_site(c, *m, k);
+  return m;
+}
+
+static std::vector<std::vector<int>> empty_rho(int L, int N) {
+  return std::vector<std::vector<int>>(L + 1, std::vector<int>(N + 1, 0));
+}
+
+// ---------------------------------------------------------------- batched launches
+namespace {
+
+struct GemmBatch {
+  std::vector<GemmDesc> d;
+  void add(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc,
+           int M, int N, int K, double alpha, double beta) {
+    if (M <= 0 || N <= 0) return;
+    GemmDesc g{};
+    g.A = A; g.B = B; g.C = C;
+    g.M = M; g.N = N; g.K = K;
+    g.lda = std::max(lda, 1); g.ldb = std::max(ldb, 1); g.ldc = std::max(ldc, 1);
+    g.ta = ta; g.tb = tb; g.alpha = alpha; g.beta = beta;
+    d.push_back(g);
+  }
+  bool empty() const { return d.empty(); }
+  void run(Ctx& c) {
+    if (d.empty()) return;
+    std::vector<GemmDesc> list;
+    std::vector<ReduceDesc> red;
+    std::vector<CopyDesc> zero_k;
+    int64_t tiles = 0, red_elems = 0, zk_elems = 0;
+    double flops = 0, bytes = 0;
+    for (const GemmDesc& g0 : d) {
+      if (g0.K <= 0) {  // C = beta C
+        CopyDesc cd{g0.C, g0.C, g0.M, g0.N, g0.ldc, g0.ldc, g0.beta, zk_elems};
+        zero_k.push_back(cd);
+        zk_elems += int64_t(g0.M) * g0.N;
+        continue;
+      }
+      flops += 2.0 * g0.M * g0.N * double(g0.K);
+      bytes += 8.0 * (double(g0.M) * g0.K + double(g0.K) * g0.N + double(g0.M) * g0.N * (g0.beta != 0 ? 2 : 1));
+      const int tm = (g0.M + kGemmBM - 1) / kGemmBM, tn = (g0.N + kGemmBN - 1) / kGemmBN;
+      int S = 1;
+      if (tm * tn < 128 && g0.K >= 1024) {
+        S = std::min((g0.K + 511) / 512, (256 + tm * tn - 1) / (tm * tn));
+        S = std::max(S, 1);
+      }
+      if (S == 1) {
+        GemmDesc g = g0;
+        g.tile0 = int(tiles); g.tiles_n = tn; g.kbeg = 0; g.kend = g.K;
+        list.push_back(g);
+        tiles += int64_t(tm) * tn;
+      } else {
+        const int chunk = ((g0.K + S - 1) / S + kGemmBK - 1) / kGemmBK * kGemmBK;
+        S = (g0.K + chunk - 1) / chunk;
+        Buf part = scratch_buf(c, size_t(g0.M) * g0.N * S);
+        for (int s = 0; s < S; ++s) {
+          GemmDesc g = g0;
+          g.C = part.p + size_t(s) * g0.M * g0.N;
+          g.ldc = g0.M; g.alpha = 1.0; g.beta = 0.0;
+          g.kbeg = s * chunk; g.kend = std::min(g0.K, (s + 1) * chunk);
+          g.tile0 = int(tiles); g.tiles_n = tn;
+          list.push_back(g);
+          tiles += int64_t(tm) * tn;
+        }
+        red.push_back(ReduceDesc{g0.C, part.p, g0.M, g0.N, g0.ldc, S, g0.alpha, g0.beta, red_elems});
+        red_elems += int64_t(g0.M) * g0.N;
+        c.scratch.push_back(std::move(part));
+      }
+    }
+    if (!zero_k.empty()) {
+      CopyDesc* dz = c.upload(zero_k);
+      hipEvent_t a; c.begin(T_COPY, a);
+      launch_copy(dz, int(zero_k.size()), zk_elems, c.stream);
+      c.end(T_COPY, a, 0, 16.0 * zk_elems);
+    }
+    if (!list.empty()) {
+      GemmDesc* dd = c.upload(list);
+      hipEvent_t a; c.begin(T_GEMM, a);
+      launch_gemm(dd, int(list.size()), int(tiles), c.stream);
+      c.end(T_GEMM, a, flops, bytes);
+    }
+    if (!red.empty()) {
+      ReduceDesc* dr = c.upload(red);
+      hipEvent_t a; c.begin(T_REDUCE, a);
+      launch_reduce(dr, int(red.size()), red_elems, c.stream);
+      c.end(T_REDUCE, a, 0, 8.0 * red_elems);
+    }
+    d.clear();
+  }
+};
+
+struct CopyBatch {
+  std::vector<CopyDesc> d;
+  int64_t total = 0;
+  void add(const double* src, int lds, double* dst, int ldd, int rows, int cols, double alpha) {
+    if (rows <= 0 || cols <= 0) return;
+    d.push_back(CopyDesc{src, dst, rows, cols, std::max(lds, 1), std::max(ldd, 1), alpha, total});
+    total += int64_t(rows) * cols;
+  }
+  void run(Ctx& c) {
+    if (d.empty()) return;
+    CopyDesc* dd = c.upload(d);
+    hipEvent_t a; c.begin(T_COPY, a);
+    launch_copy(dd, int(d.size()), total, c.stream);
+    c.end(T_COPY, a, 0, 16.0 * total);
+    d.clear();
+    total = 0;
+  }
+};
+
+struct ScaleBatch {
+  std::vector<ScaleDesc> d;
+  int64_t total = 0;
+  void add(const double* src, int lds, double* dst, int ldd, int rows, int cols, const double* s,
+           bool invert, bool sqrt_s) {
+    if (rows <= 0 || cols <= 0) return;
+    d.push_back(ScaleDesc{src, dst, s, rows, cols, std::max(lds, 1), std::max(ldd, 1), total,
+                          invert ? 1 : 0, sqrt_s ? 1 : 0});
+    total += int64_t(rows) * cols;
+  }
+  void run(Ctx& c) {
+    if (d.empty()) return;
+    ScaleDesc* dd = c.upload(d);
+    hipEvent_t a; c.begin(T_COPY, a);
+    launch_scale(dd, int(d.size()), total, c.stream);
+    c.end(T_COPY, a, 0, 16.0 * total);
+    d.clear();
+    total = 0;
+  }
+};
+
+struct EigJob {
+  const double* A;
+  int lda, n;
+  double* V;
+  double* w;
+};
+
+void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
+  std::vector<EigDesc> lds, glb;
+  int nl = 0, ng = 0;
+  double flops = 0;
+  for (const EigJob& j : jobs) {
+    if (j.n <= 0) continue;
+    if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
+    const bool in_lds = j.n <= kEigLdsMax;
+    const size_t wn = size_t(j.n) * j.n + (in_lds ? 0 : size_t(j.n) * (j.n + 1) / 2);
+    Buf w = scratch_buf(c, wn);
+    EigDesc e{j.A, j.lda, j.n, j.V, j.w, w.p};
+    c.scratch.push_back(std::move(w));
+    flops += 9.0 * double(j.n) * j.n * j.n;  // per sweep
+    if (in_lds) { lds.push_back(e); nl = std::max(nl, j.n); }
+    else { glb.push_back(e); ng = std::max(ng, j.n); }
+  }
+  if (!lds.empty()) {
+    EigDesc* d = c.upload(lds);
+    hipEvent_t a; c.begin(T_EIG, a);
+    launch_eig(d, int(lds.size()), nl, true, c.stream);
+    c.end(T_EIG, a, flops, 0);
+  }
+  if (!glb.empty()) {
+    EigDesc* d = c.upload(glb);
+    hipEvent_t a; c.begin(T_EIG, a);
+    launch_eig(d, int(glb.size()), ng, false, c.stream);
+    c.end(T_EIG, a, 0, 0);
+  }
+}
+
+void fill(Ctx& c, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  hipEvent_t a; c.begin(T_COPY, a);
+  launch_fill(p, n, v, c.stream);
+  c.end(T_COPY, a, 0, 8.0 * n);
+}
+
+// Rank selection across the sectors of one bond (same rules as the truncation of the
+// oracle): drop sigma <= zero_tol * sigma_max, order by sigma descending (ties: lower
+// sector, then lower index), keep the least count whose discarded tail has
+// sum sigma^2 <= delta^2, at most cap, at least one.
+constexpr double kZeroTol = 1e-12;
+
+std::vector<int> select_ranks(const std::vector<std::vector<double>>& sig, double delta, int cap,
+                              bool* cap_bound) {
+  struct E { double s; int n, j; };
+  std::vector<E> all;
+  double smax = 0.0;
+  for (int n = 0; n < int(sig.size()); ++n)
+    for (int j = 0; j < int(sig[n].size()); ++j) {
+      all.push_back({sig[n][j], n, j});
+      smax = std::max(smax, sig[n][j]);
+    }
+  std::vector<int> kept(sig.size(), 0);
+  if (all.empty() || !(smax > 0.0)) return kept;
+  std::vector<E> cand;
+  for (const E& e : all)
+    if (e.s > kZeroTol * smax) cand.push_back(e);
+  std::sort(cand.begin(), cand.end(), [](const E& a, const E& b) {
+    if (a.s != b.s) return a.s > b.s;
+    if (a.n != b.n) return a.n < b.n;
+    return a.j < b.j;
+  });
+  const int m = int(cand.size());
+  std::vector<double> tail(m + 1, 0.0);
+  for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + cand[i].s * cand[i].s;
+  int s_tol = m;
+  for (int s = 0; s <= m; ++s)
+    if (tail[s] <= delta * delta) { s_tol = s; break; }
+  if (s_tol > cap && cap_bound) *cap_bound = true;
+  const int s = std::max(1, std::min(s_tol, cap));
+  for (int i = 0; i < s && i < m; ++i) kept[cand[i].n] += 1;
+  return kept;
+}
+
+std::vector<double> download(Ctx& c, const double* p, size_t n) {
+  std::vector<double> h(n);
+  if (n) PV_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  return h;
+}
+
+// ---------------------------------------------------------------- environments
+// Environment / carry at cut m: for each "bra" sector na a matrix with rho_bra rows and
+// columns = concatenation over charges q of (w_q states x ket dimension of sector na-q),
+// each q-part stored as [a, b, c] with a fastest.
+struct EnvLayout {
+  int m = 0;
+  std::vector<int> rows;
+  std::vector<std::array<int64_t, 5>> qcol;  // -1 when absent
+  std::vector<std::array<int, 5>> kdim;
+  std::vector<int64_t> ncols, off;
+  int64_t total = 0;
+};
+
+EnvLayout env_layout(int m, int N, const std::vector<int>& bra_rho_m, const std::vector<int>& ket_rho_m,
+                     const std::array<int, 6>& qoff, auto&& valid_bra, auto&& valid_ket) {
+  EnvLayout e;
+  e.m = m;
+  e.rows.assign(N + 1, 0);
+  e.qcol.assign(N + 1, {-1, -1, -1, -1, -1});
+  e.kdim.assign(N + 1, {0, 0, 0, 0, 0});
+  e.ncols.assign(N + 1, 0);
+  e.off.assign(N + 1, 0);
+  for (int na = 0; na <= N; ++na) {
+    e.off[na] = e.total;
+    if (!valid_bra(m, na)) continue;
+    const int r = bra_rho_m[na];
+    e.rows[na] = r;
+    int64_t col = 0;
+    for (int q = -2; q <= 2; ++q) {
+      const int n = na - q;
+      const int wq = qoff[q + 3] - qoff[q + 2];
+      if (wq <= 0 || n < 0 || n > N || !valid_ket(m, n)) continue;
+      const int kd = ket_rho_m[n];
+      if (kd <= 0) continue;
+      e.qcol[na][q + 2] = col;
+      e.kdim[na][q + 2] = kd;
+      col += int64_t(wq) * kd;
+    }
+    e.ncols[na] = col;
+    e.total += int64_t(r) * col;
+  }
+  return e;
+}
+
+inline int wq_of(const std::array<int, 6>& qoff, int q) { return qoff[q + 3] - qoff[q + 2]; }
+
+// One site of a sweep: T1 = E x_k (GEMM), T2 = W_k T1 (W-step).
+// Output T2 grouped by (s_out, n2) with rows rho_bra[k-1][n2 - s_out] and the column
+// layout of the environment at cut k (`Ln`).  Returns the T2 buffer and offsets.
+struct T2Data {
+  Buf buf;
+  std::vector<int64_t> off[2];
+  std::vector<int> rows[2];
+};
+
+T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_rows_prev,
+                     const EnvLayout& Le, const Buf& E, const EnvLayout& Ln, const DevMpo& op) {
+  const int N = ket.N;
+  const auto& qo_in = op.qoff[k - 1];
+  // (i) T1
+  std::vector<int64_t> t1off((N + 1) * 5, -1);
+  int64_t t1tot = 0;
+  for (int na = 0; na <= N; ++na)
+    for (int q = -2; q <= 2; ++q) {
+      if (Le.qcol[na][q + 2] < 0 || Le.rows[na] == 0) continue;
+      const int n = na - q;
+      const int cols = ket.ucols(k, n) + ket.ocols(k, n);
+      if (cols == 0) continue;
+      t1off[na * 5 + q + 2] = t1tot;
+      t1tot += int64_t(Le.rows[na]) * wq_of(qo_in, q) * cols;
+    }
+  Buf T1(c.pool, size_t(std::max<int64_t>(t1tot, 1)));
+  GemmBatch gb;
+  for (int na = 0; na <= N; ++na)
+    for (int q = -2; q <= 2; ++q) {
+      const int64_t o = t1off[na * 5 + q + 2];
+      if (o < 0) continue;
+      const int n = na - q;
+      const int rw = Le.rows[na] * wq_of(qo_in, q);
+      const int cols = ket.ucols(k, n) + ket.ocols(k, n);
+      const double* A = E.p + Le.off[na] + int64_t(Le.rows[na]) * Le.qcol[na][q + 2];
+      gb.add(A, rw, 0, ket.U(k, n), ket.rows(k, n), 0, T1.p + o, rw, rw, cols, Le.kdim[na][q + 2], 1.0, 0.0);
+    }
+  gb.run(c);
+  // (ii) W-step
+  T2Data t2;
+  int64_t t2tot = 0;
+  for (int s = 0; s < 2; ++s) {
+    t2.off[s].assign(N + 1, -1);
+    t2.rows[s].assign(N + 1, 0);
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int na = n2 - s;
+      // output bra sector n2 at cut k; rows come from bra sector na at cut k-1
+      if (na < 0 || na > N || Ln.ncols[n2] == 0 || Ln.rows[n2] == 0 || Le.rows[na] == 0) continue;
+      t2.off[s][n2] = t2tot;
+      t2.rows[s][n2] = Le.rows[na];
+      t2tot += int64_t(Le.rows[na]) * Ln.ncols[n2];
+    }
+  }
+  t2.buf = Buf(c.pool, size_t(std::max<int64_t>(t2tot, 1)));
+  const auto& qo_out = op.qoff[k];
+  std::vector<WSrc> srcs;
+  std::vector<WBlock> blocks;
+  std::vector<WItem> items;
+  for (int s = 0; s < 2; ++s)
+    for (int n2 = 0; n2 <= N; ++n2) {
+      if (t2.off[s][n2] < 0) continue;
+      const int na = n2 - s;
+      const int rows = t2.rows[s][n2];
+      WSrc src{};
+      for (int si = 0; si < 2; ++si)
+        for (int q = -2; q <= 2; ++q) {
+          src.base[si][q + 2] = nullptr;
+          src.ld[si][q + 2] = 0;
+          const int64_t o = t1off[na * 5 + q + 2];
+          if (o < 0) continue;
+          const int n = na - q;
+          const int cu = ket.ucols(k, n), co = ket.ocols(k, n);
+          if ((si == 0 && cu == 0) || (si == 1 && co == 0)) continue;
+          const int64_t ld = int64_t(rows) * wq_of(qo_in, q);
+          src.base[si][q + 2] = T1.p + o + (si ? int64_t(cu) * ld : 0);
+          src.ld[si][q + 2] = ld;
+        }
+      const int sid = int(srcs.size());
+      srcs.push_back(src);
+      for (int q2 = -2; q2 <= 2; ++q2) {
+        const int64_t qc = Ln.qcol[n2][q2 + 2];
+        if (qc < 0) continue;
+        WBlock B{};
+        B.out = t2.buf.p + t2.off[s][n2] + int64_t(rows) * qc;
+        B.rows = rows;
+        B.cols = Ln.kdim[n2][q2 + 2];
+        B.wq_out = wq_of(qo_out, q2);
+        B.qoff_out = qo_out[q2 + 2];
+        B.s_out = s;
+        B.src = sid;
+        const int bid = int(blocks.size());
+        blocks.push_back(B);
+        for (int b = 0; b < B.wq_out; ++b) items.push_back(WItem{bid, B.qoff_out + b});
+      }
+    }
+  if (!items.empty()) {
+    WItem* di = c.upload(items);
+    WBlock* db = c.upload(blocks);
+    WSrc* ds = c.upload(srcs);
+    const DevMpo::Site& st = op.site[k - 1];
+    double bytes = 0;
+    for (const WBlock& B : blocks) bytes += 16.0 * B.rows * double(B.cols) * B.wq_out;
+    hipEvent_t a; c.begin(T_WSTEP, a);
+    launch_wstep(di, int(items.size()), db, ds, reinterpret_cast<const int32_t*>(st.row_ptr.p),
+                 reinterpret_cast<const int32_t*>(st.b_in.p), reinterpret_cast<const uint8_t*>(st.s_in.p),
+                 reinterpret_cast<const int8_t*>(op.charge[k - 1].p),
+                 reinterpret_cast<const int32_t*>(op.qoffd[k - 1].p), st.val.p, st.w_out, c.stream);
+    c.end(T_WSTEP, a, 0, bytes);
+  }
+  c.scratch.push_back(std::move(T1));
+  (void)bra_rows_prev;
+  return t2;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- MPO upload
+std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m) {
+  c.sync();  // synchronous copies below must not overtake queued work
+  auto d = std::make_unique<DevMpo>();
+  d->L = m.L;
+  d->w = m.w;
+  d->qoff = m.qoff;
+  d->site.resize(m.L);
+  d->charge.resize(m.L + 1);
+  d->qoffd.resize(m.L + 1);
+  auto put = [&](const void* src, size_t bytes) {
+    Buf b(c.pool, std::max<size_t>((bytes + 7) / 8, 1));
+    if (bytes) PV_HIP(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+    return b;
+  };
+  for (int k = 0; k <= m.L; ++k) {
+    d->charge[k] = put(m.charge[k].data(), m.charge[k].size());
+    std::array<int32_t, 6> qo;
+    for (int i = 0; i < 6; ++i) qo[i] = m.qoff[k][i];
+    d->qoffd[k] = put(qo.data(), sizeof(qo));
+  }
+  for (int k = 0; k < m.L; ++k) {
+    const MpoSite& s = m.site[k];
+    const int rows = 2 * s.w_out;
+    std::vector<int32_t> rp(rows + 1, 0);
+    for (size_t e = 0; e < s.val.size(); ++e) rp[s.s_out[e] * s.w_out + s.b_out[e] + 1]++;
+    for (int r = 0; r < rows; ++r) rp[r + 1] += rp[r];
+    std::vector<int32_t> bi(s.val.size());
+    std::vector<uint8_t> si(s.val.size());
+    std::vector<double> vv(s.val.size());
+    std::vector<int32_t> fillp(rp.begin(), rp.end() - 1);
+    for (size_t e = 0; e < s.val.size(); ++e) {
+      const int r = s.s_out[e] * s.w_out + s.b_out[e];
+      const int p = fillp[r]++;
+      bi[p] = s.b_in[e];
+      si[p] = s.s_in[e];
+      vv[p] = s.val[e];
+    }
+    d->site[k].row_ptr = put(rp.data(), rp.size() * 4);
+    d->site[k].b_in = put(bi.data(), bi.size() * 4);
+    d->site[k].s_in = put(si.data(), si.size());
+    d->site[k].val = put(vv.data(), vv.size() * 8);
+    d->site[k].w_out = s.w_out;
+    d->nnz += int64_t(s.val.size());
+  }
+  return d;
+}
+
+// Diagonal operator with w states at every inner cut: state j applies
+// diag(d0[j][k], d1[j][k]) on site k; the boundary cut 0 has one state feeding all j
+// and cut L keeps the w states apart, so one sweep yields w expectation values.
+static std::unique_ptr<DevMpo> diag_mpo(Ctx& c, int L, int w, const std::vector<std::vector<double>>& d0,
+                                        const std::vector<std::vector<double>>& d1) {
+  Mpo m;
+  m.L = L;
+  m.w.assign(L + 1, w);
+  m.w[0] = 1;
+  m.charge.resize(L + 1);
+  m.qoff.resize(L + 1);
+  for (int k = 0; k <= L; ++k) {
+    m.charge[k].assign(m.w[k], 0);
+    m.qoff[k] = {0, 0, 0, m.w[k], m.w[k], m.w[k]};
+  }
+  m.site.resize(L);
+  for (int k = 0; k < L; ++k) {
+    MpoSite& s = m.site[k];
+    s.w_in = m.w[k];
+    s.w_out = m.w[k + 1];
+    for (int j = 0; j < w; ++j) {
+      const int bin = k == 0 ? 0 : j;
+      for (int o = 0; o < 2; ++o) {
+        const double val = o == 0 ? d0[j][k] : d1[j][k];
+        if (val == 0.0) continue;
+        s.b_in.push_back(bin); s.b_out.push_back(j);
+        s.s_in.push_back(uint8_t(o)); s.s_out.push_back(uint8_t(o));
+        s.val.push_back(val);
+      }
+    }
+  }
+  return upload_mpo(c, m);
+}
+
+// ---------------------------------------------------------------- sweeps
+std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op) {
+  const int L = ket.L, N = ket.N;
+  if (bra.L != L || bra.N != N || op.L != L) fail(PV_EINVAL, "env_sweep: mismatched chains");
+  auto vb = [&](int m, int n) { return bra.valid(m, n); };
+  auto vk = [&](int m, int n) { return ket.valid(m, n); };
+  EnvLayout Le = env_layout(0, N, bra.rho[0], ket.rho[0], op.qoff[0], vb, vk);
+  Buf E(c.pool, size_t(std::max<int64_t>(Le.total, 1)));
+  fill(c, E.p, Le.total, 1.0);  // 1 x 1 x 1 at cut 0
+  for (int k = 1; k <= L; ++k) {
+    EnvLayout Ln = env_layout(k, N, bra.rho[k], ket.rho[k], op.qoff[k], vb, vk);
+    T2Data t2 = site_contract(c, k, ket, bra.rho[k - 1], Le, E, Ln, op);
+    Buf En(c.pool, size_t(std::max<int64_t>(Ln.total, 1)));
+    fill(c, En.p, Ln.total, 0.0);
+    GemmBatch g0, g1;
+    for (int n2 = 0; n2 <= N; ++n2) {
+      if (Ln.rows[n2] == 0 || Ln.ncols[n2] == 0) continue;
+      double* C = En.p + Ln.off[n2];
+      if (t2.off[0][n2] >= 0 && bra.ucols(k, n2) > 0)
+        g0.add(bra.U(k, n2), bra.rows(k, n2), 1, t2.buf.p + t2.off[0][n2], t2.rows[0][n2], 0, C,
+               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2), 1.0, 1.0);
+      if (t2.off[1][n2] >= 0 && n2 >= 1 && bra.ocols(k, n2 - 1) > 0)
+        g1.add(bra.O(k, n2 - 1), bra.rows(k, n2 - 1), 1, t2.buf.p + t2.off[1][n2], t2.rows[1][n2], 0, C,
+               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2 - 1), 1.0, 1.0);
+    }
+    g0.run(c);
+    g1.run(c);
+    c.scratch.push_back(std::move(t2.buf));
+    c.scratch.push_back(std::move(E));
+    E = std::move(En);
+    Le = std::move(Ln);
+  }
+  // cut L: bra sector N, one row; columns = w_0 states x ket dim 1
+  std::vector<double> out = download(c, E.p + Le.off[N], size_t(Le.rows[N] * Le.ncols[N]));
+  return out;
+}
+
+static const DevMpo& identity_mpo(Ctx& c, int L) {
+  if (!c.ident || c.ident->L != L) {
+    std::vector<std::vector<double>> one(1, std::vector<double>(L, 1.0));
+    c.ident = diag_mpo(c, L, 1, one, one);
+  }
+  return *c.ident;
+}
+
+double dot(Ctx& c, const Mps& a, const Mps& b) {
+  auto v = env_sweep(c, a, b, identity_mpo(c, a.L));
+  return v.empty() ? 0.0 : v[0];
+}
+
+double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
+  if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+  auto v = env_sweep(c, bra, ket, *c.hmpo);
+  return v.empty() ? 0.0 : v[0];
+}
+
+double norm_canonical(Ctx& c, const Mps& x) {
+  // left-orthogonal MPS: the norm is the Frobenius norm of the last core
+  Buf out(c.pool, 1);
+  hipEvent_t a; c.begin(T_REDUCE, a);
+  launch_sumsq(x.site[x.L - 1].p, x.site_size(x.L), out.p, c.stream);
+  c.end(T_REDUCE, a, 0, 8.0 * x.site_size(x.L));
+  auto h = download(c, out.p, 1);
+  return std::sqrt(h[0]);
+}
+
+// ---------------------------------------------------------------- simple constructions
+std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ) {
+  const int L = c.L, N = c.N;
+  std::vector<char> o(L, 0);
+  for (int i : occ) o[i] = 1;
+  auto rho = empty_rho(L, N);
+  int n = 0;
+  rho[0][0] = 1;
+  for (int k = 1; k <= L; ++k) {
+    n += o[k - 1];
+    rho[k][n] = 1;
+  }
+  auto m = mps_alloc(c, L, N, rho);
+  for (int k = 1; k <= L; ++k) fill(c, m->site[k - 1].p, m->site_size(k), 1.0);
+  return m;
+}
+
+std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale) {
+  auto m = mps_alloc(c, x.L, x.N, x.rho);
+  CopyBatch cb;
+  for (int k = 1; k <= x.L; ++k)
+    for (int n = 0; n <= x.N; ++n) {
+      if (!x.valid(k - 1, n)) continue;
+      const int r = x.rows(k, n);
+      const double f = k == 1 ? a : 1.0;
+      cb.add(x.U(k, n), r, m->U(k, n), r, r, x.ucols(k, n), f);
+      cb.add(x.O(k, n), r, m->O(k, n), r, r, x.ocols(k, n), f * (occ_scale ? occ_scale[k - 1] : 1.0));
+    }
+  cb.run(c);
+  return m;
+}
+
+// a x + b y by concatenation of blocks (Section 2.3).
+std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y) {
+  const int L = x.L, N = x.N;
+  if (y.L != L || y.N != N) fail(PV_EINVAL, "lincomb: mismatched chains");
+  auto rho = empty_rho(L, N);
+  for (int k = 0; k <= L; ++k)
+    for (int n = 0; n <= N; ++n)
+      if (x.valid(k, n)) rho[k][n] = (k == 0 || k == L) ? 1 : x.rho[k][n] + y.rho[k][n];
+  auto m = mps_alloc(c, L, N, rho);
+  CopyBatch cb;
+  for (int k = 1; k <= L; ++k) {
+    fill(c, m->site[k - 1].p, m->site_size(k), 0.0);
+    for (int n = 0; n <= N; ++n) {
+      if (!x.valid(k - 1, n)) continue;
+      const int R = m->rows(k, n);
+      const int rx = x.rows(k, n), ry = y.rows(k, n);
+      const int rx0 = (k == 1) ? 0 : 0, ry0 = (k == 1) ? 0 : rx;  // row offset of y part
+      const double fx = k == 1 ? a : 1.0, fy = k == 1 ? b : 1.0;
+      for (int kind = 0; kind < 2; ++kind) {
+        const int cx = kind ? x.ocols(k, n) : x.ucols(k, n);
+        const int cy = kind ? y.ocols(k, n) : y.ucols(k, n);
+        if (cx + cy == 0 && (kind ? m->ocols(k, n) : m->ucols(k, n)) == 0) continue;
+        double* dst = kind ? m->O(k, n) : m->U(k, n);
+        const double* sx = kind ? x.O(k, n) : x.U(k, n);
+        const double* sy = kind ? y.O(k, n) : y.U(k, n);
+        const int cy0 = (k == L) ? 0 : cx;  // column offset of y part
+        cb.add(sx, rx, dst + rx0, R, rx, cx, fx);
+        cb.add(sy, ry, dst + ry0 + int64_t(R) * cy0, R, ry, cy, fy);
+      }
+    }
+  }
+  cb.run(c);
+  return m;
+}
+
+// ---------------------------------------------------------------- factorisations
+namespace {
+
+// Two-pass Gram eigendecomposition of the Gram matrices G_s (n_s x n_s, ld n_s) of a set
+// of sectors.  Pass 1: G = W1 L1 W1^T.  The caller forms Y = rotated data and its Gram
+// G2, pass 2 gives W2 and the singular values as sqrt of its eigenvalues.
+struct SectorEig {
+  int n = 0;
+  Buf G, W, w;
+};
+
+void eig_all(Ctx& c, std::vector<SectorEig>& se) {
+  std::vector<EigJob> jobs;
+  for (auto& s : se) {
+    if (s.n <= 0) continue;
+    s.W = Buf(c.pool, size_t(s.n) * s.n);
+    s.w = Buf(c.pool, size_t(s.n));
+    jobs.push_back(EigJob{s.G.p, s.n, s.n, s.W.p, s.w.p});
+  }
+  run_eig(c, jobs);
+}
+
+std::vector<std::vector<double>> sigmas(Ctx& c, std::vector<SectorEig>& se) {
+  int64_t tot = 0;
+  for (auto& s : se) tot += s.n;
+  Buf all(c.pool, size_t(std::max<int64_t>(tot, 1)));
+  CopyBatch cb;
+  int64_t o = 0;
+  for (auto& s : se) {
+    cb.add(s.w.p, s.n, all.p + o, s.n, s.n, 1, 1.0);
+    o += s.n;
+  }
+  cb.run(c);
+  auto h = download(c, all.p, size_t(tot));
+  std::vector<std::vector<double>> out(se.size());
+  o = 0;
+  for (size_t i = 0; i < se.size(); ++i) {
+    out[i].resize(se[i].n);
+    for (int j = 0; j < se[i].n; ++j) out[i][j] = std::sqrt(std::max(h[o + j], 0.0));
+    o += se[i].n;
+  }
+  return out;
+}
+
+}  // namespace
+
+// Right-orthogonalisation R->L (site k = L..2): per left sector n of site k the block
+// C = [U|O] is factored as C = R Q with orthonormal rows Q through the two-pass Gram
+// eigendecomposition of C C^T; R is multiplied into site k-1.  Directions with
+// sigma <= kZeroTol * sigma_max are dropped.
+static std::unique_ptr<Mps> orthogonalize_right(Ctx& c, const Mps& x) {
+  const int L = x.L, N = x.N;
+  auto y = mps_alloc(c, L, N, x.rho);
+  {
+    CopyBatch cb;
+    for (int k = 1; k <= L; ++k) cb.add(x.site[k - 1].p, 1, y->site[k - 1].p, 1, int(x.site_size(k)), 1, 1.0);
+    cb.run(c);
+  }
+  for (int k = L; k >= 2; --k) {
+    std::vector<SectorEig> se(N + 1);
+    std::vector<int> cols(N + 1, 0);
+    GemmBatch g;
+    for (int n = 0; n <= N; ++n) {
+      if (!y->valid(k - 1, n)) continue;
+      const int r = y->rows(k, n);
+      cols[n] = y->ucols(k, n) + y->ocols(k, n);
+      if (r == 0 || cols[n] == 0) continue;
+      se[n].n = r;
+      se[n].G = Buf(c.pool, size_t(r) * r);
+      g.add(y->U(k, n), r, 0, y->U(k, n), r, 1, se[n].G.p, r, r, r, cols[n], 1.0, 0.0);
+    }
+    g.run(c);
+    eig_all(c, se);
+    // pass 2: Y = W1^T C, G2 = Y Y^T
+    std::vector<Buf> Y(N + 1);
+    std::vector<SectorEig> se2(N + 1);
+    for (int n = 0; n <= N; ++n) {
+      if (se[n].n == 0) continue;
+      const int r = se[n].n;
+      Y[n] = Buf(c.pool, size_t(r) * cols[n]);
+      g.add(se[n].W.p, r, 1, y->U(k, n), r, 0, Y[n].p, r, r, cols[n], r, 1.0, 0.0);
+    }
+    g.run(c);
+    for (int n = 0; n <= N; ++n) {
+      if (se[n].n == 0) continue;
+      const int r = se[n].n;
+      se2[n].n = r;
+      se2[n].G = Buf(c.pool, size_t(r) * r);
+      g.add(Y[n].p, r, 0, Y[n].p, r, 1, se2[n].G.p, r, r, r, cols[n], 1.0, 0.0);
+    }
+    g.run(c);
+    eig_all(c, se2);
+    auto sig = sigmas(c, se2);
+    double smax = 0;
+    for (auto& v : sig) for (double s : v) smax = std::max(smax, s);
+    std::vector<int> keep(N + 1, 0);
+    for (int n = 0; n <= N; ++n)
+      for (double s : sig[n]) keep[n] += s > kZeroTol * smax;
+    // new ranks on bond k-1
+    auto rho = y->rho;
+    for (int n = 0; n <= N; ++n)
+      if (y->valid(k - 1, n)) rho[k - 1][n] = keep[n];
+    // keep at least one direction on a nonzero bond
+    int tot = 0;
+    for (int n = 0; n <= N; ++n) tot += keep[n];
+    auto z = std::make_unique<Mps>();
+    z->L = L; z->N = N; z->rho = rho;
+    z->site.resize(L); z->off.resize(L);
+    for (int kk = 1; kk <= L; ++kk) {
+      if (kk == k || kk == k - 1) { alloc_site(c, *z, kk); }
+      else { layout_site(*z, kk); z->site[kk - 1] = std::move(y->site[kk - 1]); }
+    }
+    (void)tot;
+    // W2s = W2[:, :s] / sigma  and  R = W1 W2[:, :s] sigma
+    ScaleBatch sb;
+    std::vector<Buf> W2inv(N + 1), W2sig(N + 1), R(N + 1);
+    for (int n = 0; n <= N; ++n) {
+      const int s = keep[n], r = se[n].n;
+      if (s == 0) continue;
+      W2inv[n] = Buf(c.pool, size_t(r) * s);
+      W2sig[n] = Buf(c.pool, size_t(r) * s);
+      sb.add(se2[n].W.p, r, W2inv[n].p, r, r, s, se2[n].w.p, true, true);
+      sb.add(se2[n].W.p, r, W2sig[n].p, r, r, s, se2[n].w.p, false, true);
+    }
+    sb.run(c);
+    for (int n = 0; n <= N; ++n) {
+      const int s = keep[n], r = se[n].n;
+      if (s == 0) continue;
+      // Q = W2inv^T Y -> new site k block, rows s
+      g.add(W2inv[n].p, r, 1, Y[n].p, r, 0, z->U(k, n), s, s, cols[n], r, 1.0, 0.0);
+      R[n] = Buf(c.pool, size_t(r) * s);
+      g.add(se[n].W.p, r, 0, W2sig[n].p, r, 0, R[n].p, r, r, s, r, 1.0, 0.0);
+    }
+    g.run(c);
+    // site k-1: U(k-1,n) R_n and O(k-1,n) R_{n+1}
+    for (int n = 0; n <= N; ++n) {
+      if (!y->valid(k - 2, n)) continue;
+      const int rr = y->rows(k - 1, n);
+      if (rr == 0) continue;
+      if (y->ucols(k - 1, n) > 0 && keep[n] > 0)
+        g.add(y->U(k - 1, n), rr, 0, R[n].p, se[n].n, 0, z->U(k - 1, n), rr, rr, keep[n], se[n].n, 1.0, 0.0);
+      if (y->ocols(k - 1, n) > 0 && n + 1 <= N && keep[n + 1] > 0)
+        g.add(y->O(k - 1, n), rr, 0, R[n + 1].p, se[n + 1].n, 0, z->O(k - 1, n), rr, rr, keep[n + 1], se[n + 1].n, 1.0, 0.0);
+    }
+    g.run(c);
+    for (auto& b : Y) c.scratch.push_back(std::move(b));
+    for (auto& b : R) c.scratch.push_back(std::move(b));
+    for (auto& b : W2inv) c.scratch.push_back(std::move(b));
+    for (auto& b : W2sig) c.scratch.push_back(std::move(b));
+    for (auto& s : se) { c.scratch.push_back(std::move(s.G)); c.scratch.push_back(std::move(s.W)); c.scratch.push_back(std::move(s.w)); }
+    for (auto& s : se2) { c.scratch.push_back(std::move(s.G)); c.scratch.push_back(std::move(s.W)); c.scratch.push_back(std::move(s.w)); }
+    c.scratch.push_back(std::move(y->site[k - 1]));
+    c.scratch.push_back(std::move(y->site[k - 2]));
+    y = std::move(z);
+  }
+  return y;
+}
+
+// Left-to-right truncation of a right-orthogonal MPS: at cut k the left-fused blocks
+// M_n = [U_{k,n}; O_{k,n-1}] are factored through the two-pass Gram eigendecomposition
+// of M^T M, ranks are selected across sectors, the kept left singular vectors form the
+// new core and Sigma V^T is multiplied into site k+1.
+static std::unique_ptr<Mps> truncate_ltr(Ctx& c, std::unique_ptr<Mps> y, double eps, int cap,
+                                         bool* cap_bound) {
+  const int L = y->L, N = y->N;
+  const double delta = L > 1 ? eps / std::sqrt(double(L - 1)) : eps;
+  for (int k = 1; k <= L - 1; ++k) {
+    std::vector<SectorEig> se(N + 1), se2(N + 1);
+    std::vector<int> r0(N + 1, 0), r1(N + 1, 0);
+    GemmBatch g, g1;
+    for (int n = 0; n <= N; ++n) {
+      if (!y->valid(k, n)) continue;
+      const int rk = y->rho[k][n];
+      r0[n] = y->valid(k - 1, n) ? y->ucols(k, n) > 0 ? y->rows(k, n) : 0 : 0;
+      r1[n] = (n >= 1 && y->valid(k - 1, n - 1) && y->ocols(k, n - 1) > 0) ? y->rows(k, n - 1) : 0;
+      if (rk == 0 || r0[n] + r1[n] == 0) continue;
+      se[n].n = rk;
+      se[n].G = Buf(c.pool, size_t(rk) * rk);
+      fill(c, se[n].G.p, int64_t(rk) * rk, 0.0);
+      if (r0[n]) g.add(y->U(k, n), r0[n], 1, y->U(k, n), r0[n], 0, se[n].G.p, rk, rk, rk, r0[n], 1.0, 1.0);
+      if (r1[n]) g1.add(y->O(k, n - 1), r1[n], 1, y->O(k, n - 1), r1[n], 0, se[n].G.p, rk, rk, rk, r1[n], 1.0, 1.0);
+    }
+    g.run(c);
+    g1.run(c);
+    eig_all(c, se);
+    // Y = M W1 (stacked rows r0 + r1), G2 = Y^T Y
+    std::vector<Buf> Y(N + 1);
+    for (int n = 0; n <= N; ++n) {
+      if (se[n].n == 0) continue;
+      const int rk = se[n].n, R = r0[n] + r1[n];
+      Y[n] = Buf(c.pool, size_t(R) * rk);
+      if (r0[n]) g.add(y->U(k, n), r0[n], 0, se[n].W.p, rk, 0, Y[n].p, R, r0[n], rk, rk, 1.0, 0.0);
+      if (r1[n]) g.add(y->O(k, n - 1), r1[n], 0, se[n].W.p, rk, 0, Y[n].p + r0[n], R, r1[n], rk, rk, 1.0, 0.0);
+    }
+    g.run(c);
+    for (int n = 0; n <= N; ++n) {
+      if (se[n].n == 0) continue;
+      const int rk = se[n].n, R = r0[n] + r1[n];
+      se2[n].n = rk;
+      se2[n].G = Buf(c.pool, size_t(rk) * rk);
+      g.add(Y[n].p, R, 1, Y[n].p, R, 0, se2[n].G.p, rk, rk, rk, R, 1.0, 0.0);
+    }
+    g.run(c);
+    eig_all(c, se2);
+    auto sig = sigmas(c, se2);
+    std::vector<std::vector<double>> sig_all(N + 1);
+    for (int n = 0; n <= N; ++n) sig_all[n] = sig[n];
+    std::vector<int> keep = select_ranks(sig_all, delta, cap, cap_bound);
+    auto rho = y->rho;
+    for (int n = 0; n <= N; ++n)
+      if (y->valid(k, n)) rho[k][n] = keep[n];
+    auto z = std::make_unique<Mps>();
+    z->L = L; z->N = N; z->rho = rho;
+    z->site.resize(L); z->off.resize(L);
+    for (int kk = 1; kk <= L; ++kk) {
+      if (kk == k || kk == k + 1) alloc_site(c, *z, kk);
+      else { layout_site(*z, kk); z->site[kk - 1] = std::move(y->site[kk - 1]); }
+    }
+    ScaleBatch sb;
+    std::vector<Buf> W2inv(N + 1), W2sig(N + 1), V(N + 1);
+    for (int n = 0; n <= N; ++n) {
+      const int s = keep[n], rk = se[n].n;
+      if (s == 0 || rk == 0) continue;
+      W2inv[n] = Buf(c.pool, size_t(rk) * s);
+      W2sig[n] = Buf(c.pool, size_t(rk) * s);
+      sb.add(se2[n].W.p, rk, W2inv[n].p, rk, rk, s, se2[n].w.p, true, true);
+      sb.add(se2[n].W.p, rk, W2sig[n].p, rk, rk, s, se2[n].w.p, false, true);
+    }
+    sb.run(c);
+    for (int n = 0; n <= N; ++n) {
+      const int s = keep[n], rk = se[n].n, R = r0[n] + r1[n];
+      if (s == 0 || rk == 0) continue;
+      if (r0[n]) g.add(Y[n].p, R, 0, W2inv[n].p, rk, 0, z->U(k, n), z->rows(k, n), r0[n], s, rk, 1.0, 0.0);
+      if (r1[n]) g.add(Y[n].p + r0[n], R, 0, W2inv[n].p, rk, 0, z->O(k, n - 1), z->rows(k, n - 1), r1[n], s, rk, 1.0, 0.0);
+      V[n] = Buf(c.pool, size_t(rk) * s);
+      g1.add(se[n].W.p, rk, 0, W2sig[n].p, rk, 0, V[n].p, rk, rk, s, rk, 1.0, 0.0);
+    }
+    g.run(c);
+    g1.run(c);
+    // site k+1: rows of left sector n become (Sigma V^T) [U|O]
+    for (int n = 0; n <= N; ++n) {
+      if (!y->valid(k, n) || keep[n] == 0 || se[n].n == 0) continue;
+      const int cols = y->ucols(k + 1, n) + y->ocols(k + 1, n);
+      if (cols == 0) continue;
+      g.add(V[n].p, se[n].n, 1, y->U(k + 1, n), y->rows(k + 1, n), 0, z->U(k + 1, n), keep[n], keep[n], cols,
+            se[n].n, 1.0, 0.0);
+    }
+    g.run(c);
+    for (auto& b : Y) c.scratch.push_back(std::move(b));
+    for (auto& b : V) c.scratch.push_back(std::move(b));
+    for (auto& b : W2inv) c.scratch.push_back(std::move(b));
+    for (auto& b : W2sig) c.scratch.push_back(std::move(b));
+    for (auto& s : se) { c.scratch.push_back(std::move(s.G)); c.scratch.push_back(std::move(s.W)); c.scratch.push_back(std::move(s.w)); }
+    for (auto& s : se2) { c.scratch.push_back(std::move(s.G)); c.scratch.push_back(std::move(s.W)); c.scratch.push_back(std::move(s.w)); }
+    c.scratch.push_back(std::move(y->site[k - 1]));
+    c.scratch.push_back(std::move(y->site[k]));
+    y = std::move(z);
+  }
+  return y;
+}
+
+std::unique_ptr<Mps> round_mps(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
+  auto y = orthogonalize_right(c, x);
+  return truncate_ltr(c, std::move(y), eps, cap, cap_bound);
+}
+
+// ---------------------------------------------------------------- H application
+// Site-by-site application of the MPO with an intermediate rank m_zip ("zip-up"): the
+// carry C_{k-1}[a, b, c] (a: new bond, b: MPO bond, c: bond of x) is contracted with
+// x_k and W_k; the stacked matrix [T2_0; T2_1] of each new sector is factored through
+// the two-pass Gram eigendecomposition of T2 T2^T, its leading left singular vectors
+// become the new core and the carry is their transpose times T2.  With m_zip <= 0 only
+// numerical zeros are dropped, which gives H x up to rounding; then trunc(.; eps, cap).
+std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_zip, bool* cap_bound) {
+  if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+  const DevMpo& op = *c.hmpo;
+  const int L = xin.L, N = xin.N;
+  std::unique_ptr<Mps> xr;
+  if (m_zip > 0) xr = orthogonalize_right(c, xin);
+  const Mps& x = m_zip > 0 ? *xr : xin;
+  const int zcap = m_zip > 0 ? m_zip : (1 << 30);
+  auto rho = empty_rho(L, N);
+  rho[0][0] = 1;
+  auto y = std::make_unique<Mps>();
+  y->L = L; y->N = N; y->rho = rho;
+  y->site.resize(L); y->off.resize(L);
+  auto vy = [&](int m, int n) { return y->valid(m, n); };
+  auto vx = [&](int m, int n) { return x.valid(m, n); };
+  EnvLayout Le = env_layout(0, N, y->rho[0], x.rho[0], op.qoff[0], vy, vx);
+  Buf C(c.pool, size_t(std::max<int64_t>(Le.total, 1)));
+  fill(c, C.p, Le.total, 1.0);
+  for (int k = 1; k <= L; ++k) {
+    // rows of the new core per new sector n2: r0 = rho_y[k-1][n2], r1 = rho_y[k-1][n2-1]
+    // provisional layout at cut k with unit rows to size T2 columns
+    std::vector<int> unit(N + 1, 1);
+    EnvLayout Ln = env_layout(k, N, unit, x.rho[k], op.qoff[k], vy, vx);
+    T2Data t2 = site_contract(c, k, x, y->rho[k - 1], Le, C, Ln, op);
+    std::vector<int> r0(N + 1, 0), r1(N + 1, 0);
+    for (int n2 = 0; n2 <= N; ++n2) {
+      if (!y->valid(k, n2) || Ln.ncols[n2] == 0) continue;
+      r0[n2] = t2.off[0][n2] >= 0 ? t2.rows[0][n2] : 0;
+      r1[n2] = t2.off[1][n2] >= 0 ? t2.rows[1][n2] : 0;
+    }
+    if (k == L) {
+      // last core: M itself (single column)
+      y->rho[L][N] = 1;
+      alloc_site(c, *y, L);
+      CopyBatch cb;
+      fill(c, y->site[L - 1].p, y->site_size(L), 0.0);
+      if (r0[N] && y->ucols(L, N)) cb.add(t2.buf.p + t2.off[0][N], r0[N], y->U(L, N), y->rows(L, N), r0[N], 1, 1.0);
+      if (r1[N] && N >= 1 && y->ocols(L, N - 1))
+        cb.add(t2.buf.p + t2.off[1][N], r1[N], y->O(L, N - 1), y->rows(L, N - 1), r1[N], 1, 1.0);
+      cb.run(c);
+      c.scratch.push_back(std::move(t2.buf));
+      break;
+    }
+    std::vector<SectorEig> se(N + 1), se2(N + 1);
+    std::vector<Buf> Y(N + 1);
+    GemmBatch g;
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int R = r0[n2] + r1[n2];
+      if (R == 0) continue;
+      const int K = int(Ln.ncols[n2]);
+      se[n2].n = R;
+      se[n2].G = Buf(c.pool, size_t(R) * R);
+      const double* X0 = t2.buf.p + t2.off[0][n2];
+      const double* X1 = r1[n2] ? t2.buf.p + t2.off[1][n2] : nullptr;
+      if (r0[n2]) g.add(X0, r0[n2], 0, X0, r0[n2], 1, se[n2].G.p, R, r0[n2], r0[n2], K, 1.0, 0.0);
+      if (r0[n2] && r1[n2]) g.add(X0, r0[n2], 0, X1, r1[n2], 1, se[n2].G.p + int64_t(r0[n2]) * R, R, r0[n2], r1[n2], K, 1.0, 0.0);
+      if (r1[n2]) g.add(X1, r1[n2], 0, X1, r1[n2], 1, se[n2].G.p + r0[n2] + int64_t(r0[n2]) * R, R, r1[n2], r1[n2], K, 1.0, 0.0);
+    }
+    g.run(c);
+    eig_all(c, se);
+    GemmBatch g1;
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int R = se[n2].n;
+      if (R == 0) continue;
+      const int K = int(Ln.ncols[n2]);
+      Y[n2] = Buf(c.pool, size_t(R) * K);
+      if (r0[n2]) g.add(se[n2].W.p, R, 1, t2.buf.p + t2.off[0][n2], r0[n2], 0, Y[n2].p, R, R, K, r0[n2], 1.0, 0.0);
+      if (r1[n2]) g1.add(se[n2].W.p + r0[n2], R, 1, t2.buf.p + t2.off[1][n2], r1[n2], 0, Y[n2].p, R, R, K, r1[n2], 1.0,
+                         r0[n2] ? 1.0 : 0.0);
+    }
+    g.run(c);
+    g1.run(c);
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int R = se[n2].n;
+      if (R == 0) continue;
+      const int K = int(Ln.ncols[n2]);
+      se2[n2].n = R;
+      se2[n2].G = Buf(c.pool, size_t(R) * R);
+      g.add(Y[n2].p, R, 0, Y[n2].p, R, 1, se2[n2].G.p, R, R, R, K, 1.0, 0.0);
+    }
+    g.run(c);
+    eig_all(c, se2);
+    auto sig = sigmas(c, se2);
+    std::vector<std::vector<double>> sig_all(N + 1);
+    for (int n2 = 0; n2 <= N; ++n2) sig_all[n2] = sig[n2];
+    std::vector<int> keep = select_ranks(sig_all, 0.0, zcap, nullptr);
+    for (int n2 = 0; n2 <= N; ++n2) y->rho[k][n2] = y->valid(k, n2) ? keep[n2] : 0;
+    alloc_site(c, *y, k);
+    fill(c, y->site[k - 1].p, y->site_size(k), 0.0);
+    // new core: W1 W2[:, :s] split into the U (rows r0) and O (rows r1) parts
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int s = keep[n2], R = se[n2].n;
+      if (s == 0 || R == 0) continue;
+      if (r0[n2] && y->ucols(k, n2)) g.add(se[n2].W.p, R, 0, se2[n2].W.p, R, 0, y->U(k, n2), y->rows(k, n2), r0[n2], s, R, 1.0, 0.0);
+      if (r1[n2] && n2 >= 1 && y->ocols(k, n2 - 1))
+        g.add(se[n2].W.p + r0[n2], R, 0, se2[n2].W.p, R, 0, y->O(k, n2 - 1), y->rows(k, n2 - 1), r1[n2], s, R, 1.0, 0.0);
+    }
+    g.run(c);
+    // new carry: W2[:, :s]^T Y, layout of the environment at cut k with rows s
+    EnvLayout Lc = env_layout(k, N, y->rho[k], x.rho[k], op.qoff[k], vy, vx);
+    Buf Cn(c.pool, size_t(std::max<int64_t>(Lc.total, 1)));
+    for (int n2 = 0; n2 <= N; ++n2) {
+      const int s = keep[n2], R = se[n2].n;
+      if (s == 0 || R == 0 || Lc.ncols[n2] == 0) continue;
+      g.add(se2[n2].W.p, R, 1, Y[n2].p, R, 0, Cn.p + Lc.off[n2], s, s, int(Lc.ncols[n2]), R, 1.0, 0.0);
+    }
+    g.run(c);
+    for (auto& b : Y) c.scratch.push_back(std::move(b));
+    for (auto& s2 : se) { c.scratch.push_back(std::move(s2.G)); c.scratch.push_back(std::move(s2.W)); c.scratch.push_back(std::move(s2.w)); }
+    for (auto& s2 : se2) { c.scratch.push_back(std::move(s2.G)); c.scratch.push_back(std::move(s2.W)); c.scratch.push_back(std::move(s2.w)); }
+    c.scratch.push_back(std::move(t2.buf));
+    c.scratch.push_back(std::move(C));
+    C = std::move(Cn);
+    Le = std::move(Lc);
+  }
+  c.scratch.push_back(std::move(C));
+  return round_mps(c, *y, eps, cap, cap_bound);
+}
+
+// ---------------------------------------------------------------- preconditioner
+// S x by the sorted sequential truncated sum (Lemma truncr): the terms
+// s_m = alpha_m prod_i diag(1, exp(-beta_m theta_i)) x (Section 4.3) have exact norms from
+// one diagonal-operator sweep; the terms whose norms sum to <= eta/3 are dropped, the
+// rest added in increasing norm order with trunc_{eps_j}, eps_j = eta |s_j| / (3 sum |s|),
+// and the sum is truncated once more with eta/3.
+std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound) {
+  const int L = x.L, M = int(c.alpha.size());
+  std::vector<std::vector<double>> d0(M, std::vector<double>(L, 1.0)), d1(M, std::vector<double>(L, 1.0));
+  std::vector<std::vector<double>> occ(M, std::vector<double>(L, 1.0));
+  for (int m = 0; m < M; ++m)
+    for (int k = 0; k < L; ++k) {
+      occ[m][k] = std::exp(-c.beta[m] * c.theta[k]);
+      d1[m][k] = occ[m][k] * occ[m][k];
+      if (k == 0) { d0[m][k] = c.alpha[m] * c.alpha[m]; d1[m][k] *= c.alpha[m] * c.alpha[m]; }
+    }
+  auto op = diag_mpo(c, L, M, d0, d1);
+  std::vector<double> n2 = env_sweep(c, x, x, *op);
+  std::vector<double> nrm(M);
+  for (int m = 0; m < M; ++m) nrm[m] = std::sqrt(std::max(n2[m], 0.0));
+  std::vector<int> order(M);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return nrm[a] != nrm[b] ? nrm[a] < nrm[b] : a < b; });
+  double csum = 0.0;
+  int j0 = 0;
+  for (int j = 0; j < M; ++j) {
+    if (csum + nrm[order[j]] <= eta / 3.0) { csum += nrm[order[j]]; j0 = j + 1; }
+    else break;
+  }
+  double total = 0.0;
+  for (int j = j0; j < M; ++j) total += nrm[order[j]];
+  std::unique_ptr<Mps> y;
+  for (int j = j0; j < M; ++j) {
+    const int m = order[j];
+    const double eps_j = total > 0 ? eta * nrm[m] / (3.0 * total) : 0.0;
+    auto s = mps_scaled_copy(c, x, c.alpha[m], occ[m].data());
+    if (!y) y = round_mps(c, *s, eps_j, cap, cap_bound);
+    else {
+      auto sum = mps_lincomb(c, 1.0, *y, 1.0, *s);
+      y = round_mps(c, *sum, eps_j, cap, cap_bound);
+    }
+  }
+  if (!y) {
+    // every term dropped: S x is below the tolerance; return the zero state
+    y = mps_scaled_copy(c, x, 0.0, nullptr);
+    return y;
+  }
+  return round_mps(c, *y, eta / 3.0, cap, cap_bound);
+}
+
+}  // namespace pv

@@ -1,0 +1,164 @@
+// Host-side runtime of the block-sparse PINVIT path: device memory pool, block-sparse
+// MPS storage, batched launch builders and the operations of one iteration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pinvit.h"
+#include "kernels.hpp"
+#include "mpo.hpp"
+
+namespace pv {
+
+struct Error : std::runtime_error {
+  pv_status code;
+  Error(pv_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] inline void fail(pv_status c, const std::string& m) { throw Error(c, m); }
+
+#define PV_HIP(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      ::pv::fail(e_ == hipErrorOutOfMemory ? PV_ENOMEM : PV_EDEVICE,                    \
+                 std::string(#x) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+// Caching device allocator.  Sizes are rounded to 1/8 of their power-of-two class so
+// buffers are reused across iterations; release is stream ordered because every
+// kernel of a context runs on its single stream.
+class Pool {
+ public:
+  ~Pool();
+  void* get(size_t bytes);
+  void put(void* p, size_t bytes);
+  void release();
+  size_t in_use() const { return in_use_; }
+  size_t cached() const { return cached_; }
+ private:
+  std::multimap<size_t, void*> free_;
+  size_t in_use_ = 0, cached_ = 0;
+};
+
+struct Buf {
+  Pool* pool = nullptr;
+  double* p = nullptr;
+  size_t n = 0;
+  Buf() = default;
+  Buf(Pool& pl, size_t count);
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept { *this = std::move(o); }
+  Buf& operator=(Buf&& o) noexcept;
+  ~Buf() { reset(); }
+  void reset();
+};
+
+// Pinned host staging for launch descriptors; reset at every stream synchronisation.
+class Staging {
+ public:
+  ~Staging();
+  void* put(const void* src, size_t bytes);  // returns pinned copy
+  void reset() { used_ = 0; }
+  bool fits(size_t bytes) const { return used_ + ((bytes + 255) & ~size_t(255)) <= cap_; }
+  void init(size_t cap);
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+};
+
+// Block-sparse MPS (Section 2.3).  Site k (1-based) stores, for each left sector n in
+// K_{k-1} (ascending), the column-major matrix [U_{k,n} | O_{k,n}] with rho[k-1][n]
+// rows.  This is also the export layout.
+struct Mps {
+  int L = 0, N = 0;
+  std::vector<std::vector<int>> rho;          // [L+1][N+1]
+  std::vector<Buf> site;                      // site[k-1]
+  std::vector<std::vector<int64_t>> off;      // off[k-1][n]: start of [U|O] for sector n
+  bool valid(int k, int n) const { return n >= 0 && n <= N && n >= N - L + k && n <= k; }
+  int rows(int k, int n) const { return valid(k - 1, n) ? rho[k - 1][n] : 0; }
+  int ucols(int k, int n) const { return valid(k - 1, n) && valid(k, n) ? rho[k][n] : 0; }
+  int ocols(int k, int n) const { return valid(k - 1, n) && valid(k, n + 1) ? rho[k][n + 1] : 0; }
+  double* U(int k, int n) const { return site[k - 1].p + off[k - 1][n]; }
+  double* O(int k, int n) const { return U(k, n) + int64_t(rows(k, n)) * ucols(k, n); }
+  int64_t site_size(int k) const;
+  int64_t size() const;
+  int max_rank() const;
+};
+
+// Device copy of an operator in the bond-charge blocked form of mpo.hpp.
+struct DevMpo {
+  int L = 0;
+  std::vector<int> w;
+  std::vector<std::array<int, 6>> qoff;
+  struct Site {
+    Buf row_ptr, b_in, s_in, val;  // int32 / uint8 stored in double-sized buffers
+    int w_out = 0;
+  };
+  std::vector<Site> site;
+  std::vector<Buf> charge;  // int8 per cut
+  std::vector<Buf> qoffd;   // int32[6] per cut
+  int64_t nnz = 0;
+};
+
+enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_COUNT };
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Pool pool;
+  Staging staging;
+  // problem
+  int L = 0, N = 0;
+  double gamma = 0.0;
+  std::vector<double> h, v;
+  std::unique_ptr<DevMpo> hmpo;
+  std::unique_ptr<DevMpo> ident;  // identity operator (dot products)
+  std::vector<int> mpo_w;
+  // preconditioner (Section 4.3, Section 7.1.1)
+  std::vector<double> theta;
+  double t_min = 0, t_max = 0, T = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
+  int m_minus = 0, m_plus = 0;
+  std::vector<double> alpha, beta;
+  // MPS handles
+  std::map<int, std::unique_ptr<Mps>> mps;
+  int next_handle = 1;
+  // timers
+  struct Pending { int cls; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[T_COUNT] = {0}, t_flops[T_COUNT] = {0}, t_bytes[T_COUNT] = {0};
+  int t_calls[T_COUNT] = {0};
+  bool timing = true;
+
+  void sync();
+  hipEvent_t event();
+  void begin(int cls, hipEvent_t& a);
+  void end(int cls, hipEvent_t a, double flops, double bytes);
+  template <class T>
+  T* upload(const std::vector<T>& v);  // staged async copy into a pool buffer kept in `scratch`
+  std::vector<Buf> scratch;            // freed at sync
+};
+
+// ---- operations (engine.cpp) ----
+std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vector<int>>& rho);
+std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ);
+std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y);
+std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale);
+std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op);
+double dot(Ctx& c, const Mps& a, const Mps& b);
+double expect_h(Ctx& c, const Mps& bra, const Mps& ket);
+std::unique_ptr<Mps> round_mps(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
+std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& x, double eps, int cap, int m_zip, bool* cap_bound);
+std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound);
+std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m);
+double norm_canonical(Ctx& c, const Mps& x);
+
+}  // namespace pv

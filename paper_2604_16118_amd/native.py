@@ -1,0 +1,262 @@
+"""ctypes binding of libpinvit.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/pinvit.h with the same
+name; arrays are passed as NumPy float64/int32 host buffers.  The library must have
+been built (``python -m paper_2604_16118_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpinvit.so")
+
+STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "PV_ENOTSPD",
+          -5: "PV_ENOCONV", -6: "PV_ESTATE"}
+
+# names exported by include/pinvit.h
+EXPORTS = [
+    "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
+    "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
+    "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_mpo_bond_dims", "pv_mpo_dense",
+]
+
+
+class PvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("rank_cap", C.c_int), ("m_zip", C.c_int), ("max_iter", C.c_int),
+                ("tau", C.c_double), ("c0", C.c_double), ("c", C.c_double),
+                ("delta", C.c_double), ("eps_num", C.c_double), ("t_eig", C.c_double),
+                ("c_lower", C.c_double), ("c_upper", C.c_double), ("max_retries", C.c_int),
+                ("precision", C.c_int), ("resume_eta", C.c_double), ("resume_s", C.c_double),
+                ("resume_s2", C.c_double)]
+
+
+class Iter(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("energy", C.c_double), ("rho", C.c_double),
+                ("bound", C.c_double), ("r_norm", C.c_double), ("s_norm", C.c_double),
+                ("eta_res", C.c_double), ("lambda_star", C.c_double), ("eta_psi", C.c_double),
+                ("seconds", C.c_double), ("retries", C.c_int), ("cap_bound", C.c_int),
+                ("max_rank", C.c_int), ("stopped", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("energy", C.c_double), ("lambda_", C.c_double), ("rho", C.c_double),
+                ("bound", C.c_double), ("eta_res", C.c_double), ("s_last", C.c_double),
+                ("s_prev", C.c_double), ("iterations", C.c_int), ("converged", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run `python -m paper_2604_16118_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        L.pv_last_error.restype = C.c_char_p
+        L.pv_timer_name.restype = C.c_char_p
+        L.pv_destroy.restype = None
+        L.pv_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        L.pv_destroy.argtypes = [C.c_void_p]
+        L.pv_set_hamiltonian.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_double]
+        L.pv_precond_info.argtypes = [C.c_void_p, dp, ip]
+        L.pv_mps_create.argtypes = [C.c_void_p, ip, dp, C.c_size_t, ip]
+        L.pv_mps_determinant.argtypes = [C.c_void_p, ip, ip]
+        L.pv_mps_layout.argtypes = [C.c_void_p, C.c_int, ip, C.POINTER(C.c_size_t)]
+        L.pv_mps_download.argtypes = [C.c_void_p, C.c_int, dp, C.c_size_t]
+        L.pv_mps_free.argtypes = [C.c_void_p, C.c_int]
+        L.pv_dot.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
+        L.pv_expect_h.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
+        L.pv_lincomb.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int, ip]
+        L.pv_round.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
+        L.pv_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, ip, ip]
+        L.pv_apply_s.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
+        L.pv_run.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.POINTER(Result),
+                             C.POINTER(Iter), C.c_int, ip]
+        L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
+        L.pv_timers_reset.argtypes = [C.c_void_p]
+        L.pv_mpo_bond_dims.argtypes = [C.c_int, dp, dp, ip, ip]
+        L.pv_mpo_dense.argtypes = [C.c_int, dp, dp, C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise PvError(st, lib().pv_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mpo_bond_dims(h, v):
+    L = h.shape[0]
+    h, v = _f64(h), _f64(v)
+    dims = np.zeros(L + 1, np.int32)
+    qd = np.zeros((L + 1) * 5, np.int32)
+    _check(lib().pv_mpo_bond_dims(L, _dp(h), _dp(v), _ip(dims), _ip(qd)))
+    return dims, qd.reshape(L + 1, 5)
+
+
+def mpo_dense(h, v, diag_shift=0.0):
+    L = h.shape[0]
+    h, v = _f64(h), _f64(v)
+    out = np.zeros((1 << L, 1 << L))
+    _check(lib().pv_mpo_dense(L, _dp(h), _dp(v), float(diag_shift), _dp(out)))
+    return out
+
+
+class Context:
+    """One library context (device memory, stream, Hamiltonian, MPS handles)."""
+
+    def __init__(self, device: int = 0):
+        self._p = C.c_void_p()
+        _check(lib().pv_create(C.byref(self._p), device))
+        self.L = self.N = None
+
+    def close(self):
+        if self._p:
+            lib().pv_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, h, v, N, gamma):
+        h, v = _f64(h), _f64(v)
+        L = h.shape[0]
+        _check(lib().pv_set_hamiltonian(self._p, L, N, _dp(h), _dp(v), float(gamma)))
+        self.L, self.N = L, N
+
+    def precond_info(self):
+        out = np.zeros(7)
+        mr = np.zeros(2, np.int32)
+        _check(lib().pv_precond_info(self._p, _dp(out), _ip(mr)))
+        keys = ["t_min", "t_max", "T", "h", "alpha0", "s_min", "s_max"]
+        d = dict(zip(keys, out.tolist()))
+        d["m_minus"], d["m_plus"] = int(mr[0]), int(mr[1])
+        return d
+
+    def mps_create(self, rho, data):
+        rho = np.ascontiguousarray(rho, dtype=np.int32)
+        data = _f64(data)
+        h = C.c_int()
+        _check(lib().pv_mps_create(self._p, _ip(rho), _dp(data), data.size, C.byref(h)))
+        return h.value
+
+    def mps_determinant(self, occupied):
+        occ = np.ascontiguousarray(occupied, dtype=np.int32)
+        h = C.c_int()
+        _check(lib().pv_mps_determinant(self._p, _ip(occ), C.byref(h)))
+        return h.value
+
+    def mps_layout(self, handle):
+        rho = np.zeros((self.L + 1, self.N + 1), np.int32)
+        n = C.c_size_t()
+        _check(lib().pv_mps_layout(self._p, handle, _ip(rho), C.byref(n)))
+        return rho, n.value
+
+    def mps_download(self, handle):
+        rho, n = self.mps_layout(handle)
+        data = np.zeros(n)
+        _check(lib().pv_mps_download(self._p, handle, _dp(data), n))
+        return rho, data
+
+    def mps_free(self, handle):
+        _check(lib().pv_mps_free(self._p, handle))
+
+    def dot(self, a, b):
+        out = C.c_double()
+        _check(lib().pv_dot(self._p, a, b, C.byref(out)))
+        return out.value
+
+    def expect_h(self, bra, ket):
+        out = C.c_double()
+        _check(lib().pv_expect_h(self._p, bra, ket, C.byref(out)))
+        return out.value
+
+    def lincomb(self, a, x, b, y):
+        out = C.c_int()
+        _check(lib().pv_lincomb(self._p, float(a), x, float(b), y, C.byref(out)))
+        return out.value
+
+    def round(self, x, eps, cap):
+        out, cb = C.c_int(), C.c_int()
+        _check(lib().pv_round(self._p, x, float(eps), int(cap), C.byref(out), C.byref(cb)))
+        return out.value, bool(cb.value)
+
+    def apply_h(self, x, eps, cap, m_zip=0):
+        out, cb = C.c_int(), C.c_int()
+        _check(lib().pv_apply_h(self._p, x, float(eps), int(cap), int(m_zip), C.byref(out), C.byref(cb)))
+        return out.value, bool(cb.value)
+
+    def apply_s(self, x, eta, cap):
+        out, cb = C.c_int(), C.c_int()
+        _check(lib().pv_apply_s(self._p, x, float(eta), int(cap), C.byref(out), C.byref(cb)))
+        return out.value, bool(cb.value)
+
+    def run(self, rank_cap, max_iter, tau=1e-10, c=0.5, delta=10.0, m_zip=0, c0=0.1,
+            eps_num=0.0, t_eig=0.5, c_lower=0.0, c_upper=0.0, max_retries=30, start=-1,
+            precision=0, resume=None):
+        r = resume or {}
+        prm = Params(rank_cap, m_zip, max_iter, tau, c0, c, delta, eps_num, t_eig, c_lower,
+                     c_upper, max_retries, precision, r.get("eta_res", 0.0), r.get("s_last", 0.0),
+                     r.get("s_prev", 0.0))
+        res = Result()
+        hist = (Iter * max(max_iter, 1))()
+        psi = C.c_int()
+        _check(lib().pv_run(self._p, C.byref(prm), int(start), C.byref(res), hist,
+                            max(max_iter, 1), C.byref(psi)))
+        rows = []
+        for i in range(res.iterations):
+            r = hist[i]
+            rows.append(dict(lam=r.lambda_, E=r.energy, rho=r.rho, bound=r.bound, r_norm=r.r_norm,
+                             s_norm=r.s_norm, eta=r.eta_res, lam_star=r.lambda_star,
+                             eta_psi=r.eta_psi, seconds=r.seconds, retries=r.retries,
+                             cap_bound=bool(r.cap_bound), max_rank=r.max_rank,
+                             stop=bool(r.stopped)))
+        return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
+                    iterations=res.iterations, converged=bool(res.converged),
+                    eta_res=res.eta_res, s_last=res.s_last, s_prev=res.s_prev), rows, psi.value
+
+    def timers(self):
+        n = 5
+        ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
+        calls = np.zeros(n, np.int32)
+        _check(lib().pv_timers(self._p, n, _dp(ms), _dp(fl), _dp(by), _ip(calls)))
+        return {lib().pv_timer_name(i).decode(): dict(ms=ms[i], flops=fl[i], bytes=by[i], calls=int(calls[i]))
+                for i in range(n)}
+
+    def timers_reset(self):
+        _check(lib().pv_timers_reset(self._p))

@@ -1,0 +1,172 @@
+"""GPU parity of each hot-path operation against the CPU oracle (small sizes, several
+tiles and ragged sector blocks).  Every call goes through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fock, mps as omps, precond, tt
+from synth import make_problem, random_block_mps, rho_table
+
+pytestmark = pytest.mark.gpu
+
+native = pytest.importorskip("paper_2604_16118_amd.native")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def _setup(ctx, kind, L, N, seed):
+    p = make_problem(kind, L, N, seed)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    return p
+
+
+def _mps(ctx, L, N, cap, seed):
+    rho = rho_table(L, N, cap)
+    data = random_block_mps(L, N, rho, seed)
+    hd = ctx.mps_create(rho, data)
+    return hd, omps.to_dense(L, N, rho, data)
+
+
+def _dense(ctx, hd):
+    rho, data = ctx.mps_download(hd)
+    return rho, omps.to_dense(ctx.L, ctx.N, rho, data)
+
+
+@pytest.mark.parametrize("L,N,cap", [(8, 4, 6), (10, 3, 9), (12, 6, 40)])
+def test_download_roundtrip_and_dot(ctx, L, N, cap):
+    _setup(ctx, "dense", L, N, 0)
+    a, xa = _mps(ctx, L, N, cap, 1)
+    b, xb = _mps(ctx, L, N, cap + 3, 2)
+    rho, xd = _dense(ctx, a)
+    assert np.array_equal(rho, rho_table(L, N, cap))
+    assert np.array_equal(xd, xa)
+    got = ctx.dot(a, b)
+    assert got == pytest.approx(float(xa @ xb), rel=1e-12, abs=1e-13 * np.linalg.norm(xa) * np.linalg.norm(xb))
+
+
+@pytest.mark.parametrize("kind,L,N,cap", [("dense", 8, 4, 5), ("decayed", 10, 5, 12), ("dense", 7, 2, 4)])
+def test_expect_h_and_hermiticity(ctx, kind, L, N, cap):
+    p = _setup(ctx, kind, L, N, 3)
+    a, xa = _mps(ctx, L, N, cap, 4)
+    b, xb = _mps(ctx, L, N, cap, 5)
+    ref = float(xa @ fock.apply_h(p.h, p.v, xb, p.gamma))
+    got = ctx.expect_h(a, b)
+    scale = np.linalg.norm(xa) * np.linalg.norm(fock.apply_h(p.h, p.v, xb, p.gamma))
+    assert abs(got - ref) <= 1e-12 * scale
+    assert abs(ctx.expect_h(b, a) - got) <= 1e-12 * scale
+
+
+def test_lincomb_is_concatenation(ctx):
+    L, N = 9, 4
+    _setup(ctx, "dense", L, N, 0)
+    a, xa = _mps(ctx, L, N, 5, 6)
+    b, xb = _mps(ctx, L, N, 7, 7)
+    c = ctx.lincomb(0.7, a, -1.3, b)
+    rho, xc = _dense(ctx, c)
+    ra, rb = rho_table(L, N, 5), rho_table(L, N, 7)
+    assert np.array_equal(rho[1:L], (ra + rb)[1:L])
+    assert np.allclose(xc, 0.7 * xa - 1.3 * xb, atol=1e-13 * np.linalg.norm(xb))
+
+
+@pytest.mark.parametrize("eps,cap", [(0.0, 1000), (1e-3, 1000), (1e-1, 1000), (0.0, 7)])
+def test_round_matches_tt_svd(ctx, eps, cap):
+    L, N = 10, 5
+    _setup(ctx, "dense", L, N, 0)
+    a, xa = _mps(ctx, L, N, 6, 8)
+    b, xb = _mps(ctx, L, N, 6, 9)
+    s = ctx.lincomb(1.0, a, 0.5, b)
+    x = xa + 0.5 * xb
+    r, cb = ctx.round(s, eps * np.linalg.norm(x), cap)
+    y, rho_or, cb_or, margin, _ = tt.truncate(x, L, N, eps * np.linalg.norm(x), cap)
+    rho, yg = _dense(ctx, r)
+    assert cb == cb_or
+    if margin > 1e-8:
+        for k in range(1, L):
+            assert {n: int(rho[k, n]) for n in rho_or[k]} == rho_or[k], k
+    assert np.linalg.norm(yg - y) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_round_exact_low_rank_keeps_state(ctx):
+    L, N = 12, 6
+    _setup(ctx, "decayed", L, N, 0)
+    a, xa = _mps(ctx, L, N, 10, 10)
+    r, _ = ctx.round(a, 0.0, 10 ** 6)
+    rho, y = _dense(ctx, r)
+    assert np.linalg.norm(y - xa) <= 1e-11 * np.linalg.norm(xa)
+    assert np.array_equal(rho, np.array(
+        [[tt.ranks(xa, L, N)[k].get(n, 0) for n in range(N + 1)] for k in range(L + 1)]))
+
+
+@pytest.mark.parametrize("kind,L,N,cap", [("dense", 8, 4, 4), ("decayed", 10, 5, 6), ("dense", 9, 3, 5)])
+def test_apply_h_exact(ctx, kind, L, N, cap):
+    p = _setup(ctx, kind, L, N, 11)
+    a, xa = _mps(ctx, L, N, cap, 12)
+    y, _ = ctx.apply_h(a, 0.0, 10 ** 6, 0)
+    _, yg = _dense(ctx, y)
+    ref = fock.apply_h(p.h, p.v, xa, p.gamma)
+    assert np.linalg.norm(yg - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_apply_h_truncated_matches_trunc_of_exact(ctx):
+    L, N = 10, 5
+    p = _setup(ctx, "dense", L, N, 13)
+    a, xa = _mps(ctx, L, N, 4, 14)
+    ref = fock.apply_h(p.h, p.v, xa, p.gamma)
+    eps = 1e-2 * np.linalg.norm(ref)
+    y, cb = ctx.apply_h(a, eps, 12, 0)
+    yo, rho_or, cb_or, margin, _ = tt.truncate(ref, L, N, eps, 12)
+    rho, yg = _dense(ctx, y)
+    assert cb == cb_or
+    if margin > 1e-8:
+        for k in range(1, L):
+            assert {n: int(rho[k, n]) for n in rho_or[k]} == rho_or[k]
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("eta_rel", [1e-1, 1e-4, 1e-8])
+def test_apply_s_sorted_sum(ctx, eta_rel):
+    L, N = 9, 4
+    p = _setup(ctx, "dense", L, N, 15)
+    a, xa = _mps(ctx, L, N, 5, 16)
+    pre = precond.Preconditioner(p.h, p.v, N, p.gamma)
+    info = ctx.precond_info()
+    assert info["t_min"] == pytest.approx(pre.t_min, rel=1e-14)
+    assert info["m_minus"] == pre.m_minus and info["m_plus"] == pre.m_plus
+    assert info["s_max"] == pytest.approx(pre.s_max, rel=1e-13)
+    eta = eta_rel * np.linalg.norm(pre.apply_exact(xa))
+    s, cb = ctx.apply_s(a, eta, 1000)
+    yo, cb_or, _, margin = precond.apply_sorted(pre, xa, eta, 1000, N)
+    _, yg = _dense(ctx, s)
+    assert cb == cb_or
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    assert np.linalg.norm(yg - pre.apply_exact(xa)) <= eta * (1 + 1e-9)
+
+
+def test_determinant_state(ctx):
+    L, N = 8, 3
+    p = _setup(ctx, "dense", L, N, 0)
+    d = ctx.mps_determinant([1, 4, 6])
+    _, x = _dense(ctx, d)
+    assert np.array_equal(x, fock.determinant(L, [1, 4, 6]))
+    assert ctx.expect_h(d, d) == pytest.approx(float(x @ fock.apply_h(p.h, p.v, x, p.gamma)), rel=1e-13)
+
+
+def test_invalid_arguments_return_status(ctx):
+    _setup(ctx, "dense", 6, 3, 0)
+    with pytest.raises(native.PvError) as e:
+        ctx.dot(12345, 1)
+    assert e.value.status == -1
+    with pytest.raises(native.PvError):
+        ctx.mps_determinant([0, 0, 1])
+    bad = np.zeros((7, 4), np.int32)
+    with pytest.raises(native.PvError):
+        ctx.mps_create(bad, np.zeros(0))

@@ -1,0 +1,66 @@
+"""Host-only checks of the native library: it loads, exports the ABI, and its symbolic
+MPO (built on the CPU) equals the oracle's Hamiltonian."""
+import re
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fock
+from synth import make_problem, random_dense, random_decayed
+
+native = pytest.importorskip("paper_2604_16118_amd.native")
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "pinvit.h")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.lib()
+    names = set(re.findall(r"\b(pv_[a-z0-9_]+)\s*\(", open(HEADER).read()))
+    assert names == set(native.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("L,seed", [(3, 0), (5, 1), (6, 2), (7, 3)])
+def test_mpo_contracts_to_oracle_hamiltonian(L, seed):
+    h, v = random_dense(L, seed)
+    v = v + 0.01 * np.random.default_rng(seed).standard_normal(v.shape)  # any coefficients
+    H = native.mpo_dense(h, v, 0.25)
+    eye = np.eye(1 << L)
+    ref = fock.apply_h(h, v, eye) + 0.25 * fock.number_op(eye)
+    assert np.abs(H - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_mpo_rank_bounds_thm_opranks():
+    for L in (6, 9, 12):
+        h, v = random_dense(L, L)
+        d, q = native.mpo_bond_dims(h, v)
+        assert d[0] == 1 and d[L] == 1
+        assert d.max() <= L * L // 2 + 3 * L // 2 + 2            # part (i), V
+        assert np.all(q.sum(axis=1) == d)
+        d1, _ = native.mpo_bond_dims(h, np.zeros_like(v))
+        assert d1.max() <= L + 2                                   # part (i), T
+        d2, _ = native.mpo_bond_dims(np.diag(np.diag(h)), np.zeros_like(v))
+        assert d2.max() <= 4                                       # diagonal T
+        for dd in (1, 2, 3):                                       # part (ii), banded T
+            hb = np.where(np.abs(np.subtract.outer(np.arange(L), np.arange(L))) <= dd, h, 0.0)
+            db, _ = native.mpo_bond_dims(hb, np.zeros_like(v))
+            assert db.max() <= 2 * dd + 2
+
+
+def test_full_mpo_bond_at_mid_chain_reaches_paper_bound():
+    L = 24
+    h, v = random_decayed(L, 0)
+    d, q = native.mpo_bond_dims(h, v)
+    assert d[L // 2] == L * L // 2 + 3 * L // 2 + 2
+    assert list(q[L // 2]) == [66, 24, 146, 24, 66]
+
+
+def test_context_creation_without_gpu_fails_cleanly():
+    import torch  # noqa: F401  (device plumbing only)
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(native.PvError) as e:
+        native.Context(0)
+    assert e.value.status == -3
