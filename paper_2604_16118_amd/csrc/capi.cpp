@@ -83,8 +83,8 @@ void setup_precond(Ctx& c, double c0, double cl, double cu) {
   c.t_min = std::accumulate(s.begin(), s.begin() + N, 0.0);
   c.t_max = std::accumulate(s.end() - N, s.end(), 0.0);
   if (!(c.t_min > 0.0)) fail(PV_ENOTSPD, "t_min <= 0: the shift does not make D positive");
-  c.T = c.t_max / c.t_min;
-  expsum_params(c0, c.T, &c.hs, &c.m_plus, &c.m_minus);
+  c.T_ratio = c.t_max / c.t_min;
+  expsum_params(c0, c.T_ratio, &c.hs, &c.m_plus, &c.m_minus);
   c.a0 = std::sqrt(2.0 / (c.t_min * (cl * (1 - c0) * (1 - c0) + cu * (1 + c0) * (1 + c0))));
   c.alpha.clear();
   c.beta.clear();
@@ -93,7 +93,7 @@ void setup_precond(Ctx& c, double c0, double cl, double cu) {
     c.beta.push_back(std::exp(m * c.hs) / c.t_min);
   }
   c.s_max = c.a0 * expsum(1.0, c.hs, c.m_plus, c.m_minus);
-  c.s_min = c.a0 * expsum(c.T, c.hs, c.m_plus, c.m_minus);
+  c.s_min = c.a0 * expsum(c.T_ratio, c.hs, c.m_plus, c.m_minus);
 }
 
 // b_delta of eq. bbetarho and the eigenvector bound of eq. everrbound.
@@ -203,7 +203,7 @@ pv_status pv_precond_info(pv_ctx* ctx, double* out, int* m_range) {
     if (!ctx || !out || !m_range) fail(PV_EINVAL, "null argument");
     Ctx& c = ctx->c;
     if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
-    double v[7] = {c.t_min, c.t_max, c.T, c.hs, c.a0, c.s_min, c.s_max};
+    double v[7] = {c.t_min, c.t_max, c.T_ratio, c.hs, c.a0, c.s_min, c.s_max};
     std::memcpy(out, v, sizeof(v));
     m_range[0] = c.m_minus;
     m_range[1] = c.m_plus;

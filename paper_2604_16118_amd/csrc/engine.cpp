@@ -345,7 +345,7 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
   for (const EigJob& j : jobs) {
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
-    const bool in_lds = j.n <= kEigLdsMax;
+    const bool in_lds = eig_fits_lds(j.n);
     const size_t wn = size_t(j.n) * j.n + (in_lds ? 0 : size_t(j.n) * (j.n + 1) / 2);
     Buf w = scratch_buf(c, wn);
     EigDesc e{j.A, j.lda, j.n, j.V, j.w, w.p};

@@ -124,7 +124,7 @@ struct Ctx {
   std::vector<int> mpo_w;
   // preconditioner (Section 4.3, Section 7.1.1)
   std::vector<double> theta;
-  double t_min = 0, t_max = 0, T = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
+  double t_min = 0, t_max = 0, T_ratio = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
   int m_minus = 0, m_plus = 0;
   std::vector<double> alpha, beta;
   // MPS handles

@@ -26,7 +26,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_f64_16x16x4f64.
 // Operand layout of that instruction (wave64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; the 16x16 result lives in 4 doubles per lane, element r of lane l
-// being D[4*(l/16)+r][l%16].
+// being D[4*r + l/16][l%16] (measured with a single-instruction probe on gfx950).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nprob) {
   constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   for (int mi = 0; mi < 2; ++mi)
     for (int nj = 0; nj < 2; ++nj)
       for (int r = 0; r < 4; ++r) {
-        const int i = row0 + wr * 32 + mi * 16 + 4 * lk + r;
+        const int i = row0 + wr * 32 + mi * 16 + 4 * r + lk;
         const int j = col0 + wc * 32 + nj * 16 + li;
         if (i < g.M && j < g.N) {
           double v = g.alpha * acc[mi][nj][r];
@@ -244,17 +244,37 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigDesc* 
   }
 }
 
+// Largest dynamic LDS request accepted for the LDS variant (0 when the opt-in fails).
+static size_t eig_lds_limit() {
+  static size_t limit = size_t(-1);
+  if (limit == size_t(-1)) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+    (void)hipGetLastError();
+    // static LDS of the kernel: rotation tables and the flag
+    const size_t stat = kEigMaxPairs * (2 * sizeof(double) + 2 * sizeof(int)) + 64;
+    size_t want = v > int(stat) ? size_t(v) - stat : 0;
+    if (want > 0 && hipFuncSetAttribute((const void*)jacobi_eig_kernel<true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) != hipSuccess) {
+      (void)hipGetLastError();
+      want = 0;
+    }
+    limit = want;
+  }
+  return limit;
+}
+
+bool eig_fits_lds(int n) {
+  return n <= kEigLdsMax && size_t(n) * (n + 1) / 2 * sizeof(double) <= eig_lds_limit();
+}
+
 void launch_eig(const EigDesc* d, int nprob, int nmax, bool lds, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
   if (lds) {
     const size_t shm = size_t(nmax) * (nmax + 1) / 2 * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      hipFuncSetAttribute((const void*)jacobi_eig_kernel<true>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8 * 1024);
-      attr = true;
-    }
+    if (shm > eig_lds_limit()) throw std::runtime_error("eig: LDS request above the device limit");
     hipLaunchKernelGGL(jacobi_eig_kernel<true>, dim3(nprob), dim3(kEigThreads), shm, s, d, 60);
   } else {
     hipLaunchKernelGGL(jacobi_eig_kernel<false>, dim3(nprob), dim3(kEigThreads), 0, s, d, 60);

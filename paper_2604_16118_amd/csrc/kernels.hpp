@@ -82,6 +82,8 @@ struct ScaleDesc {
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, hipStream_t s);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 void launch_eig(const EigDesc* d_desc, int nprob, int nmax, bool lds, hipStream_t s);
+// True when an n x n problem can use the LDS-resident variant on this device.
+bool eig_fits_lds(int n);
 void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
                   const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
                   const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,
