@@ -72,6 +72,9 @@ typedef struct {
   double c_upper;   /* C_upper of eq. lowerupper; <= 0: 1 */
   int max_retries;  /* limit of the residual-tolerance reductions per iteration */
   int precision;    /* 0: float64 everywhere (the only mode implemented) */
+  int truncation;   /* 0: sequential TT-SVD truncation (eq. ttsvdquasiopt), two-pass Gram
+                     *    factorisations; 1: simultaneous truncation of all bonds from Gram
+                     *    matrices (tolerance eps/(L-1) per bond), see pv_set_truncation */
   /* Resume state from a previous pv_run (pv_result fields eta_res, s_last, s_prev);
    * resume_s <= 0 starts afresh with a trial residual for the first tolerance. */
   double resume_eta, resume_s, resume_s2;
@@ -125,6 +128,17 @@ pv_status pv_mps_determinant(pv_ctx* ctx, const int32_t* occupied, int* handle);
 pv_status pv_mps_layout(pv_ctx* ctx, int handle, int32_t* rho, size_t* n);
 pv_status pv_mps_download(pv_ctx* ctx, int handle, double* data, size_t n);
 pv_status pv_mps_free(pv_ctx* ctx, int handle);
+
+/* Truncation used by pv_round, pv_apply_h and pv_apply_s on this context.
+ * mode 0: sequential TT-SVD: right-orthogonalisation, then bond by bond from the left the
+ *   kept left singular vectors of the current tensor (Section 2.2); each bond discards at
+ *   most (eps/sqrt(L-1))^2.  Singular values from a two-pass Gram eigendecomposition.
+ * mode 1: simultaneous truncation P_1 ... P_{L-1} x, P_k the projector onto the kept left
+ *   singular vectors of the k-th matricisation of x itself, every bond decided from the
+ *   left and right Gram matrices in one batched step with tolerance eps/(L-1), so that
+ *   ||x - trunc(x)|| <= eps by the triangle inequality.  Singular values accurate to about
+ *   1e-8 relative; the intermediate-rank H application uses single-pass factorisations. */
+pv_status pv_set_truncation(pv_ctx* ctx, int mode);
 
 /* <a|b> (Euclidean inner product) by a transfer sweep. */
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out);

@@ -46,6 +46,7 @@ class Params:
     t_eig: float = 0.5
     eps_num: float | None = None
     max_retries: int = 30
+    truncation: str = "sequential"  # or "parallel" (tt.truncate_parallel)
 
 
 def initial_determinant(h: np.ndarray, N: int):
@@ -57,6 +58,10 @@ def initial_determinant(h: np.ndarray, N: int):
 def run(h, v, N, gamma, prm: Params, psi0=None):
     L = h.shape[0]
     pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper)
+    mode = prm.truncation
+
+    def trunc(x, eps):
+        return precond._trunc(x, L, N, eps, prm.cap, mode)
     eps_num = prm.eps_num if prm.eps_num is not None else 0.5 * (1.0 - prm.c)
     zeta = eps_num / (1.0 + prm.c)
     eta = math.inf
@@ -68,8 +73,8 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
         hpsi = fock.apply_h(h, v, psi, gamma)
         lam = float(psi @ hpsi)
         if s_prev is None:
-            y0 = tt.truncate(hpsi, L, N, 0.0, prm.cap)[0]
-            r0 = tt.truncate(y0 - lam * psi, L, N, 0.0, prm.cap)[0]
+            y0 = trunc(hpsi, 0.0)[0]
+            r0 = trunc(y0 - lam * psi, 0.0)[0]
             est = pre.s_max * float(np.linalg.norm(r0))
         elif s_prev2 is None or s_prev2 <= 0.0:
             est = s_prev
@@ -80,9 +85,9 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
         margin = math.inf
         while True:
             e12 = eta / (3.0 * pre.s_max)
-            y, _, cb1, m1, _ = tt.truncate(hpsi, L, N, e12, prm.cap)
-            r, rho_r, cb2, m2, _ = tt.truncate(y - lam * psi, L, N, e12, prm.cap)
-            s, cb3, _, m3 = precond.apply_sorted(pre, r, eta / 3.0, prm.cap, N)
+            y, _, cb1, m1, _ = trunc(hpsi, e12)
+            r, rho_r, cb2, m2, _ = trunc(y - lam * psi, e12)
+            s, cb3, _, m3 = precond.apply_sorted(pre, r, eta / 3.0, prm.cap, N, mode)
             cap_bound = cb1 or cb2 or cb3
             ns = float(np.linalg.norm(s))
             mret = min(m1, m2, m3)
@@ -91,7 +96,7 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
                 break
             eta *= 0.8
             retries += 1
-        p, cb4, _, m4 = precond.apply_sorted(pre, s, pre.s_max * eta / 3.0, prm.cap, N)
+        p, cb4, _, m4 = precond.apply_sorted(pre, s, pre.s_max * eta / 3.0, prm.cap, N, mode)
         nr = float(np.linalg.norm(r))
         rho = (ns + eta) / (math.sqrt(1.0 - prm.c) * math.sqrt(lam))
         bound = bounds.eigvec_error_bound(rho, prm.delta)
@@ -113,7 +118,7 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
         da = bounds.delta_a(rho, q)
         eta_in = da * math.sqrt(lam_s) / math.sqrt(1.0 + prm.c)
         eta_psi = eta_in * pre.s_min
-        psi, rho_tab, cb5, m5, _ = tt.truncate(vv[0] * psi + vv[1] * z2, L, N, eta_psi, prm.cap)
+        psi, rho_tab, cb5, m5, _ = trunc(vv[0] * psi + vv[1] * z2, eta_psi)
         rec.update(lam_star=lam_s, v=vv.copy(), eta_psi=eta_psi, rho_tab=rho_tab,
                    cap_bound_update=bool(cb5), margin=min(rec["margin"], m5))
         hist.append(rec)

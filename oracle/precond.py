@@ -107,7 +107,15 @@ class Preconditioner:
         return sum(d * x for d in self.diagonals())
 
 
-def apply_sorted(pre: Preconditioner, x: np.ndarray, eta: float, cap: int, N: int):
+def _trunc(x, L, N, eps, cap, truncation):
+    if truncation == "parallel":
+        y, rho, cb, m = tt.truncate_parallel(x, L, N, eps, cap)
+        return y, rho, cb, m, None
+    return tt.truncate(x, L, N, eps, cap)
+
+
+def apply_sorted(pre: Preconditioner, x: np.ndarray, eta: float, cap: int, N: int,
+                 truncation: str = "sequential"):
     """S x by the sorted sequential truncated sum (Lemma truncr and the text after it).
 
     Terms s_m = S_m x are sorted by norm ascending (equal norms: lower m first); the
@@ -134,11 +142,11 @@ def apply_sorted(pre: Preconditioner, x: np.ndarray, eta: float, cap: int, N: in
     rounds = 0
     for m in rest:
         eps_j = eta * norms[m] / (3.0 * total) if total > 0 else 0.0
-        y, _, cb, mg, _ = tt.truncate(y + terms[m], L, N, eps_j, cap)
+        y, _, cb, mg, _ = _trunc(y + terms[m], L, N, eps_j, cap, truncation)
         cap_bound |= cb
         margin = min(margin, mg)
         rounds += 1
-    y, _, cb, mg, _ = tt.truncate(y, L, N, eta / 3.0, cap)
+    y, _, cb, mg, _ = _trunc(y, L, N, eta / 3.0, cap, truncation)
     cap_bound |= cb
     margin = min(margin, mg)
     return y, cap_bound, rounds + 1, margin

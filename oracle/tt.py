@@ -24,6 +24,9 @@ import math
 import numpy as np
 
 ZERO_TOL = 1e-12
+# Numerical-zero level of the simultaneous truncation, whose singular values come from
+# Gram matrices (accurate to about sqrt(machine epsilon) of the largest one).
+ZERO_TOL_PARALLEL = 1e-6
 
 
 def sectors(L: int, N: int, k: int):
@@ -132,3 +135,45 @@ def singular_values(x: np.ndarray, L: int, N: int, k: int):
     """{n: descending singular values of sector block n at cut k}."""
     return {n: (np.linalg.svd(B, compute_uv=False) if B.size else np.zeros(0))
             for n, (_, _, B) in blocks(x, L, N, k).items()}
+
+
+def truncate_parallel(x: np.ndarray, L: int, N: int, eps: float, cap: int,
+                      zero_tol: float = ZERO_TOL_PARALLEL):
+    """Simultaneous truncation y = P_1 P_2 ... P_{L-1} x.
+
+    P_k is the orthogonal projector onto the kept left singular vectors of the k-th
+    blocked matricisation of the ORIGINAL x (acting on orbitals 1..k), with the ranks of
+    every bond chosen independently by rules 1-4 with the per-bond tolerance eps/(L-1).
+    Since each P_k has norm one, ||x - y|| <= sum_k ||(I - P_k) x|| <= eps (the triangle
+    inequality replaces the orthogonality behind the sqrt(L-1) form of eq. ttsvdquasiopt).
+    Returns (y, rho, cap_bound, min_margin)."""
+    delta = eps / (L - 1) if L > 1 else eps
+    rho = [dict() for _ in range(L + 1)]
+    rho[0] = {0: 1}
+    rho[L] = {N: 1}
+    cap_bound = False
+    min_margin = math.inf
+    proj = {}
+    for k in range(1, L):
+        bl = blocks(x, L, N, k)
+        svd, sv = {}, {}
+        for n, (li, ri, B) in bl.items():
+            if B.size == 0:
+                svd[n] = np.zeros((B.shape[0], 0))
+                sv[n] = np.zeros(0)
+                continue
+            U, s, _ = np.linalg.svd(B, full_matrices=False)
+            svd[n], sv[n] = U, s
+        kept, cb, margin = select(sv, delta, cap, zero_tol)
+        cap_bound |= cb
+        min_margin = min(min_margin, margin)
+        rho[k] = dict(kept)
+        proj[k] = {n: svd[n][:, :kept[n]] for n in bl}
+    y = x.copy()
+    for k in range(L - 1, 0, -1):
+        Y = y.reshape(1 << (L - k), 1 << k)
+        for n, (li, ri, B) in blocks(y, L, N, k).items():
+            U = proj[k][n]
+            Y[np.ix_(ri, li)] = (U @ (U.T @ B)).T
+        y = Y.reshape(-1)
+    return y, rho, cap_bound, min_margin

@@ -294,6 +294,14 @@ pv_status pv_mps_free(pv_ctx* ctx, int handle) {
   });
 }
 
+pv_status pv_set_truncation(pv_ctx* ctx, int mode) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    if (mode != 0 && mode != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
+    ctx->c.trunc_mode = mode;
+  });
+}
+
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out) {
   return guard([&] {
     if (!ctx || !out) fail(PV_EINVAL, "null argument");
@@ -367,6 +375,10 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
       fail(PV_EINVAL, "invalid parameters");
     if (p.precision != 0) fail(PV_EINVAL, "only precision 0 (float64) is implemented");
+    if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
+    c.trunc_mode = p.truncation;
+    // outputs of the sequential truncation are left-orthogonal (norm = last core)
+    auto mnorm = [&](const Mps& m) { return c.trunc_mode == 0 ? norm_canonical(c, m) : norm2(c, m); };
     setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
     const int L = c.L, N = c.N, cap = p.rank_cap, mz = p.m_zip;
     const double eps_num = p.eps_num > 0 ? p.eps_num : 0.5 * (1.0 - p.c);
@@ -402,7 +414,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         auto y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
         auto d0 = mps_lincomb(c, 1.0, *y0, -lam, *psi);
         auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
-        est = c.s_max * norm_canonical(c, *r0);
+        est = c.s_max * mnorm(*r0);
       } else if (s_prev2 <= 0) {
         est = s_prev;
       } else {
@@ -423,14 +435,14 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         d.reset();
         s = apply_s(c, *r, eta / 3.0, cap, &cb3);
         capb = cb1 || cb2 || cb3;
-        ns = norm_canonical(c, *s);
+        ns = mnorm(*s);
         if (ns >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries) break;
         eta *= 0.8;
         ++retries;
       }
       bool cb4 = false;
       auto pdir = apply_s(c, *s, c.s_max * eta / 3.0, cap, &cb4);
-      const double nr = norm_canonical(c, *r);
+      const double nr = mnorm(*r);
       const double rho = (ns + eta) / (std::sqrt(1.0 - p.c) * std::sqrt(lam));
       const double bound = error_bound(rho, p.delta);
       pv_iter rec{};
@@ -457,7 +469,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         res->converged = 1;
         break;
       }
-      const double np = norm_canonical(c, *pdir);
+      const double np = mnorm(*pdir);
       if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
       auto z2 = mps_scaled_copy(c, *pdir, 1.0 / np, nullptr);
       pdir.reset();

@@ -336,35 +336,56 @@ struct EigJob {
   int lda, n;
   double* V;
   double* w;
+  double abs_tol = 1e-15;
+  bool tridiag = false;  // Householder + bisection + inverse iteration (scaled path)
 };
 
+constexpr double kAbsTolGeneral = 1e-15;  // first pass / Gram eigenproblems
+constexpr double kAbsTolRefine = 0.0;     // second pass on nearly diagonal input
+// numerical-zero level of single-pass Gram singular values: sigma <= 1e-6 sigma_max, i.e.
+// eigenvalues below 1e-12 of the largest, above the rounding level of the Gram solvers
+constexpr double kZeroTolPar = 1e-6;
+constexpr double kVecCut = 1e-12;  // tridiagonal solver: no eigenvector below this
+
+
+// Matrices above this size go to the tridiagonal solver when the job allows it.
+constexpr int kTridiagMin = 40;
+
 void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
-  std::vector<EigDesc> lds, glb;
-  int nl = 0, ng = 0;
-  double flops = 0;
+  std::vector<EigDesc> by_mode[3], tri;
+  int nmax[3] = {0, 0, 0}, ntri = 0;
+  double flops[3] = {0, 0, 0}, ftri = 0;
   for (const EigJob& j : jobs) {
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
-    const bool in_lds = eig_fits_lds(j.n);
-    const size_t wn = size_t(j.n) * j.n + (in_lds ? 0 : size_t(j.n) * (j.n + 1) / 2);
+    if (j.tridiag && j.n > kTridiagMin) {
+      Buf w = scratch_buf(c, size_t(6) * j.n * j.n);
+      tri.push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, std::max(j.abs_tol, kVecCut)});
+      c.scratch.push_back(std::move(w));
+      ntri = std::max(ntri, j.n);
+      ftri += 7.0 * double(j.n) * j.n * j.n;
+      continue;
+    }
+    const int mode = eig_mode(j.n);
+    const size_t wn = size_t(j.n) * j.n + size_t(j.n) * (j.n + 1) / 2;
     Buf w = scratch_buf(c, wn);
-    EigDesc e{j.A, j.lda, j.n, j.V, j.w, w.p};
+    by_mode[mode].push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, j.abs_tol});
     c.scratch.push_back(std::move(w));
-    flops += 9.0 * double(j.n) * j.n * j.n;  // per sweep
-    if (in_lds) { lds.push_back(e); nl = std::max(nl, j.n); }
-    else { glb.push_back(e); ng = std::max(ng, j.n); }
+    nmax[mode] = std::max(nmax[mode], j.n);
+    flops[mode] += 9.0 * double(j.n) * j.n * j.n;  // one sweep
   }
-  if (!lds.empty()) {
-    EigDesc* d = c.upload(lds);
+  if (!tri.empty()) {
+    EigDesc* d = c.upload(tri);
     hipEvent_t a; c.begin(T_EIG, a);
-    launch_eig(d, int(lds.size()), nl, true, c.stream);
-    c.end(T_EIG, a, flops, 0);
+    launch_eig_tridiag(d, int(tri.size()), ntri, c.stream);
+    c.end(T_EIG, a, ftri, 0);
   }
-  if (!glb.empty()) {
-    EigDesc* d = c.upload(glb);
+  for (int mode = 2; mode >= 0; --mode) {
+    if (by_mode[mode].empty()) continue;
+    EigDesc* d = c.upload(by_mode[mode]);
     hipEvent_t a; c.begin(T_EIG, a);
-    launch_eig(d, int(glb.size()), ng, false, c.stream);
-    c.end(T_EIG, a, 0, 0);
+    launch_eig(d, int(by_mode[mode].size()), nmax[mode], mode, c.stream);
+    c.end(T_EIG, a, flops[mode], 0);
   }
 }
 
@@ -382,7 +403,7 @@ void fill(Ctx& c, double* p, int64_t n, double v) {
 constexpr double kZeroTol = 1e-12;
 
 std::vector<int> select_ranks(const std::vector<std::vector<double>>& sig, double delta, int cap,
-                              bool* cap_bound) {
+                              bool* cap_bound, double zero_tol = kZeroTol) {
   struct E { double s; int n, j; };
   std::vector<E> all;
   double smax = 0.0;
@@ -395,7 +416,7 @@ std::vector<int> select_ranks(const std::vector<std::vector<double>>& sig, doubl
   if (all.empty() || !(smax > 0.0)) return kept;
   std::vector<E> cand;
   for (const E& e : all)
-    if (e.s > kZeroTol * smax) cand.push_back(e);
+    if (e.s > zero_tol * smax) cand.push_back(e);
   std::sort(cand.begin(), cand.end(), [](const E& a, const E& b) {
     if (a.s != b.s) return a.s > b.s;
     if (a.n != b.n) return a.n < b.n;
@@ -575,6 +596,29 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
                  reinterpret_cast<const int32_t*>(op.qoffd[k - 1].p), st.val.p, st.w_out, c.stream);
     c.end(T_WSTEP, a, 0, bytes);
   }
+  // dense charge blocks of W_k: T2[a, b', c'] += sum_b T1[a, b, c'] W[b, b'], one GEMM per c'
+  const DevMpo::Site& st = op.site[k - 1];
+  if (!st.dense.empty()) {
+    GemmBatch gd;
+    for (const WBlock& B : blocks) {
+      const WSrc& src = srcs[B.src];
+      const int q_out = [&] {
+        for (int q = -2; q <= 2; ++q)
+          if (qo_out[q + 2] == B.qoff_out) return q;
+        return 99;
+      }();
+      for (const DevMpo::Dense& D : st.dense) {
+        if (D.s_out != B.s_out || D.q_out != q_out || D.w_out != B.wq_out) continue;
+        const double* base = src.base[D.s_in][D.q_in + 2];
+        if (!base) continue;
+        const int64_t ld = src.ld[D.s_in][D.q_in + 2];
+        for (int cc = 0; cc < B.cols; ++cc)
+          gd.add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
+                 B.rows, B.wq_out, D.w_in, 1.0, 1.0);
+      }
+    }
+    gd.run(c);
+  }
   c.scratch.push_back(std::move(T1));
   (void)bra_rows_prev;
   return t2;
@@ -604,28 +648,58 @@ std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m) {
     d->qoffd[k] = put(qo.data(), sizeof(qo));
   }
   for (int k = 0; k < m.L; ++k) {
-    const MpoSite& s = m.site[k];
-    const int rows = 2 * s.w_out;
+    const MpoSite& st = m.site[k];
+    // charge blocks dense enough for a GEMM
+    auto qof = [&](int cut, int b) { return int(m.charge[cut][b]); };
+    std::map<std::array<int, 4>, int> cnt;  // (q_in, q_out, s_in, s_out) -> nnz
+    for (size_t e = 0; e < st.val.size(); ++e)
+      cnt[{qof(k, st.b_in[e]), qof(k + 1, st.b_out[e]), st.s_in[e], st.s_out[e]}]++;
+    std::map<std::array<int, 4>, int> dense_id;
+    for (auto& kv : cnt) {
+      const int qi = kv.first[0], qo = kv.first[1];
+      const int wi = m.qoff[k][qi + 3] - m.qoff[k][qi + 2];
+      const int wo = m.qoff[k + 1][qo + 3] - m.qoff[k + 1][qo + 2];
+      const double dens = double(kv.second) / (double(wi) * wo);
+      if (kv.second >= 64 && dens >= 0.05) {
+        dense_id[kv.first] = int(d->site[k].dense.size());
+        DevMpo::Dense D{qi, qo, kv.first[2], kv.first[3], wi, wo, Buf()};
+        d->site[k].dense.push_back(std::move(D));
+      }
+    }
+    std::vector<std::vector<double>> dmat(d->site[k].dense.size());
+    for (size_t i = 0; i < dmat.size(); ++i)
+      dmat[i].assign(size_t(d->site[k].dense[i].w_in) * d->site[k].dense[i].w_out, 0.0);
+    std::vector<size_t> sparse_idx;
+    for (size_t e = 0; e < st.val.size(); ++e) {
+      const int qi = qof(k, st.b_in[e]), qo = qof(k + 1, st.b_out[e]);
+      auto it = dense_id.find({qi, qo, st.s_in[e], st.s_out[e]});
+      if (it == dense_id.end()) { sparse_idx.push_back(e); continue; }
+      const auto& D = d->site[k].dense[it->second];
+      const int bi = st.b_in[e] - m.qoff[k][qi + 2], bo = st.b_out[e] - m.qoff[k + 1][qo + 2];
+      dmat[it->second][bi + size_t(bo) * D.w_in] += st.val[e];
+    }
+    for (size_t i = 0; i < dmat.size(); ++i) d->site[k].dense[i].W = put(dmat[i].data(), dmat[i].size() * 8);
+    const int rows = 2 * st.w_out;
     std::vector<int32_t> rp(rows + 1, 0);
-    for (size_t e = 0; e < s.val.size(); ++e) rp[s.s_out[e] * s.w_out + s.b_out[e] + 1]++;
+    for (size_t e : sparse_idx) rp[st.s_out[e] * st.w_out + st.b_out[e] + 1]++;
     for (int r = 0; r < rows; ++r) rp[r + 1] += rp[r];
-    std::vector<int32_t> bi(s.val.size());
-    std::vector<uint8_t> si(s.val.size());
-    std::vector<double> vv(s.val.size());
+    std::vector<int32_t> bi(sparse_idx.size());
+    std::vector<uint8_t> si(sparse_idx.size());
+    std::vector<double> vv(sparse_idx.size());
     std::vector<int32_t> fillp(rp.begin(), rp.end() - 1);
-    for (size_t e = 0; e < s.val.size(); ++e) {
-      const int r = s.s_out[e] * s.w_out + s.b_out[e];
+    for (size_t e : sparse_idx) {
+      const int r = st.s_out[e] * st.w_out + st.b_out[e];
       const int p = fillp[r]++;
-      bi[p] = s.b_in[e];
-      si[p] = s.s_in[e];
-      vv[p] = s.val[e];
+      bi[p] = st.b_in[e];
+      si[p] = st.s_in[e];
+      vv[p] = st.val[e];
     }
     d->site[k].row_ptr = put(rp.data(), rp.size() * 4);
     d->site[k].b_in = put(bi.data(), bi.size() * 4);
     d->site[k].s_in = put(si.data(), si.size());
     d->site[k].val = put(vv.data(), vv.size() * 8);
-    d->site[k].w_out = s.w_out;
-    d->nnz += int64_t(s.val.size());
+    d->site[k].w_out = st.w_out;
+    d->nnz += int64_t(st.val.size());
   }
   return d;
 }
@@ -720,6 +794,8 @@ double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   return v.empty() ? 0.0 : v[0];
 }
 
+double norm2(Ctx& c, const Mps& x) { return std::sqrt(std::max(dot(c, x, x), 0.0)); }
+
 double norm_canonical(Ctx& c, const Mps& x) {
   // left-orthogonal MPS: the norm is the Frobenius norm of the last core
   Buf out(c.pool, 1);
@@ -808,13 +884,13 @@ struct SectorEig {
   Buf G, W, w;
 };
 
-void eig_all(Ctx& c, std::vector<SectorEig>& se) {
+void eig_all(Ctx& c, std::vector<SectorEig>& se, double abs_tol, bool tridiag = false) {
   std::vector<EigJob> jobs;
   for (auto& s : se) {
     if (s.n <= 0) continue;
     s.W = Buf(c.pool, size_t(s.n) * s.n);
     s.w = Buf(c.pool, size_t(s.n));
-    jobs.push_back(EigJob{s.G.p, s.n, s.n, s.W.p, s.w.p});
+    jobs.push_back(EigJob{s.G.p, s.n, s.n, s.W.p, s.w.p, abs_tol, tridiag});
   }
   run_eig(c, jobs);
 }
@@ -841,13 +917,35 @@ std::vector<std::vector<double>> sigmas(Ctx& c, std::vector<SectorEig>& se) {
   return out;
 }
 
+// Single-pass factorisation: the second pass is the identity (W2 = I, same eigenvalues).
+void identity_pass(Ctx& c, std::vector<SectorEig>& se, std::vector<SectorEig>& se2) {
+  CopyBatch cb;
+  int rmax = 0;
+  for (size_t i = 0; i < se.size(); ++i) rmax = std::max(rmax, se[i].n);
+  Buf ones(c.pool, size_t(std::max(rmax, 1)));
+  fill(c, ones.p, std::max(rmax, 1), 1.0);
+  for (size_t i = 0; i < se.size(); ++i) {
+    const int r = se[i].n;
+    se2[i].n = r;
+    if (r == 0) continue;
+    se2[i].W = Buf(c.pool, size_t(r) * r);
+    se2[i].w = Buf(c.pool, size_t(r));
+    fill(c, se2[i].W.p, int64_t(r) * r, 0.0);
+    cb.add(se[i].w.p, r, se2[i].w.p, r, r, 1, 1.0);
+    cb.add(ones.p, 1, se2[i].W.p, r + 1, 1, r, 1.0);  // unit diagonal (stride r + 1)
+  }
+  cb.run(c);
+  c.scratch.push_back(std::move(ones));
+}
+
+
 }  // namespace
 
 // Right-orthogonalisation R->L (site k = L..2): per left sector n of site k the block
 // C = [U|O] is factored as C = R Q with orthonormal rows Q through the two-pass Gram
 // eigendecomposition of C C^T; R is multiplied into site k-1.  Directions with
 // sigma <= kZeroTol * sigma_max are dropped.
-static std::unique_ptr<Mps> orthogonalize_right(Ctx& c, const Mps& x) {
+static std::unique_ptr<Mps> orthogonalize_right(Ctx& c, const Mps& x, bool two_pass) {
   const int L = x.L, N = x.N;
   auto y = mps_alloc(c, L, N, x.rho);
   {
@@ -869,8 +967,8 @@ static std::unique_ptr<Mps> orthogonalize_right(Ctx& c, const Mps& x) {
       g.add(y->U(k, n), r, 0, y->U(k, n), r, 1, se[n].G.p, r, r, r, cols[n], 1.0, 0.0);
     }
     g.run(c);
-    eig_all(c, se);
-    // pass 2: Y = W1^T C, G2 = Y Y^T
+    eig_all(c, se, kAbsTolGeneral, !two_pass);
+    // pass 2: Y = W1^T C, G2 = Y Y^T (single pass: W2 = I, eigenvalues of pass 1)
     std::vector<Buf> Y(N + 1);
     std::vector<SectorEig> se2(N + 1);
     for (int n = 0; n <= N; ++n) {
@@ -880,21 +978,26 @@ static std::unique_ptr<Mps> orthogonalize_right(Ctx& c, const Mps& x) {
       g.add(se[n].W.p, r, 1, y->U(k, n), r, 0, Y[n].p, r, r, cols[n], r, 1.0, 0.0);
     }
     g.run(c);
-    for (int n = 0; n <= N; ++n) {
-      if (se[n].n == 0) continue;
-      const int r = se[n].n;
-      se2[n].n = r;
-      se2[n].G = Buf(c.pool, size_t(r) * r);
-      g.add(Y[n].p, r, 0, Y[n].p, r, 1, se2[n].G.p, r, r, r, cols[n], 1.0, 0.0);
+    if (two_pass) {
+      for (int n = 0; n <= N; ++n) {
+        if (se[n].n == 0) continue;
+        const int r = se[n].n;
+        se2[n].n = r;
+        se2[n].G = Buf(c.pool, size_t(r) * r);
+        g.add(Y[n].p, r, 0, Y[n].p, r, 1, se2[n].G.p, r, r, r, cols[n], 1.0, 0.0);
+      }
+      g.run(c);
+      eig_all(c, se2, kAbsTolRefine);
+    } else {
+      identity_pass(c, se, se2);
     }
-    g.run(c);
-    eig_all(c, se2);
     auto sig = sigmas(c, se2);
     double smax = 0;
     for (auto& v : sig) for (double s : v) smax = std::max(smax, s);
+    const double ztol = two_pass ? kZeroTol : kZeroTolPar;
     std::vector<int> keep(N + 1, 0);
     for (int n = 0; n <= N; ++n)
-      for (double s : sig[n]) keep[n] += s > kZeroTol * smax;
+      for (double s : sig[n]) keep[n] += s > ztol * smax;
     // new ranks on bond k-1
     auto rho = y->rho;
     for (int n = 0; n <= N; ++n)
@@ -981,7 +1084,7 @@ static std::unique_ptr<Mps> truncate_ltr(Ctx& c, std::unique_ptr<Mps> y, double 
     }
     g.run(c);
     g1.run(c);
-    eig_all(c, se);
+    eig_all(c, se, kAbsTolGeneral);
     // Y = M W1 (stacked rows r0 + r1), G2 = Y^T Y
     std::vector<Buf> Y(N + 1);
     for (int n = 0; n <= N; ++n) {
@@ -1000,7 +1103,7 @@ static std::unique_ptr<Mps> truncate_ltr(Ctx& c, std::unique_ptr<Mps> y, double 
       g.add(Y[n].p, R, 1, Y[n].p, R, 0, se2[n].G.p, rk, rk, rk, R, 1.0, 0.0);
     }
     g.run(c);
-    eig_all(c, se2);
+    eig_all(c, se2, kAbsTolRefine);
     auto sig = sigmas(c, se2);
     std::vector<std::vector<double>> sig_all(N + 1);
     for (int n = 0; n <= N; ++n) sig_all[n] = sig[n];
@@ -1059,8 +1162,274 @@ static std::unique_ptr<Mps> truncate_ltr(Ctx& c, std::unique_ptr<Mps> y, double 
 }
 
 std::unique_ptr<Mps> round_mps(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
-  auto y = orthogonalize_right(c, x);
+  if (c.trunc_mode == 1) return round_parallel(c, x, eps, cap, cap_bound);
+  auto y = orthogonalize_right(c, x, true);
   return truncate_ltr(c, std::move(y), eps, cap, cap_bound);
+}
+
+// ---------------------------------------------------------------- simultaneous truncation
+// Gram matrices of the left parts (G^L_k = A_k^T A_k, by a left-to-right GEMM sweep) and of
+// the right parts (G^R_k = B_k B_k^T, right-to-left) of every bond, one entry per sector.
+namespace {
+
+struct BondGrams {
+  std::vector<std::vector<int64_t>> off;  // off[k][n] into buf, -1 if empty
+  Buf buf;
+};
+
+BondGrams alloc_grams(Ctx& c, const Mps& x) {
+  BondGrams g;
+  g.off.assign(x.L + 1, std::vector<int64_t>(x.N + 1, -1));
+  int64_t tot = 0;
+  for (int k = 0; k <= x.L; ++k)
+    for (int n = 0; n <= x.N; ++n)
+      if (x.valid(k, n) && x.rho[k][n] > 0) {
+        g.off[k][n] = tot;
+        tot += int64_t(x.rho[k][n]) * x.rho[k][n];
+      }
+  g.buf = Buf(c.pool, size_t(std::max<int64_t>(tot, 1)));
+  return g;
+}
+
+BondGrams left_grams(Ctx& c, const Mps& x) {
+  const int L = x.L, N = x.N;
+  BondGrams g = alloc_grams(c, x);
+  fill(c, g.buf.p, int64_t(g.buf.n), 0.0);
+  fill(c, g.buf.p + g.off[0][0], 1, 1.0);
+  for (int k = 1; k < L; ++k) {
+    std::vector<Buf> T(N + 1);
+    GemmBatch gb, g0, g1;
+    for (int n = 0; n <= N; ++n) {
+      if (!x.valid(k - 1, n) || g.off[k - 1][n] < 0) continue;
+      const int r = x.rows(k, n), cols = x.ucols(k, n) + x.ocols(k, n);
+      if (r == 0 || cols == 0) continue;
+      T[n] = Buf(c.pool, size_t(r) * cols);
+      gb.add(g.buf.p + g.off[k - 1][n], r, 0, x.U(k, n), r, 0, T[n].p, r, r, cols, r, 1.0, 0.0);
+    }
+    gb.run(c);
+    for (int n = 0; n <= N; ++n) {
+      if (g.off[k][n] < 0) continue;
+      const int rk = x.rho[k][n];
+      double* G = g.buf.p + g.off[k][n];
+      if (T[n].p && x.ucols(k, n) > 0)
+        g0.add(x.U(k, n), x.rows(k, n), 1, T[n].p, x.rows(k, n), 0, G, rk, rk, rk, x.rows(k, n), 1.0, 1.0);
+      if (n >= 1 && T[n - 1].p && x.ocols(k, n - 1) > 0) {
+        const int r = x.rows(k, n - 1);
+        g1.add(x.O(k, n - 1), r, 1, T[n - 1].p + int64_t(r) * x.ucols(k, n - 1), r, 0, G, rk, rk, rk, r, 1.0, 1.0);
+      }
+    }
+    g0.run(c);
+    g1.run(c);
+    for (auto& b : T) c.scratch.push_back(std::move(b));
+  }
+  return g;
+}
+
+BondGrams right_grams(Ctx& c, const Mps& x) {
+  const int L = x.L, N = x.N;
+  BondGrams g = alloc_grams(c, x);
+  fill(c, g.buf.p, int64_t(g.buf.n), 0.0);
+  fill(c, g.buf.p + g.off[L][N], 1, 1.0);
+  for (int k = L; k >= 2; --k) {
+    std::vector<Buf> T(N + 1);
+    GemmBatch gb, g2;
+    for (int n = 0; n <= N; ++n) {
+      if (!x.valid(k - 1, n) || g.off[k - 1][n] < 0) continue;
+      const int r = x.rows(k, n), cu = x.ucols(k, n), co = x.ocols(k, n);
+      if (r == 0 || cu + co == 0) continue;
+      T[n] = Buf(c.pool, size_t(r) * (cu + co));
+      if (cu) gb.add(x.U(k, n), r, 0, g.buf.p + g.off[k][n], cu, 0, T[n].p, r, r, cu, cu, 1.0, 0.0);
+      if (co) gb.add(x.O(k, n), r, 0, g.buf.p + g.off[k][n + 1], co, 0, T[n].p + int64_t(r) * cu, r, r, co, co, 1.0, 0.0);
+      g2.add(T[n].p, r, 0, x.U(k, n), r, 1, g.buf.p + g.off[k - 1][n], r, r, r, cu + co, 1.0, 0.0);
+    }
+    gb.run(c);
+    g2.run(c);
+    for (auto& b : T) c.scratch.push_back(std::move(b));
+  }
+  return g;
+}
+
+struct BondEig {
+  std::vector<std::vector<int64_t>> voff, woff;  // per (k, n)
+  Buf V, w;
+};
+
+// Eigendecompositions of the Gram matrices of bonds kmin..kmax, one batched launch.
+BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax) {
+  BondEig e;
+  e.voff.assign(x.L + 1, std::vector<int64_t>(x.N + 1, -1));
+  e.woff = e.voff;
+  int64_t tv = 0, tw = 0;
+  for (int k = kmin; k <= kmax; ++k)
+    for (int n = 0; n <= x.N; ++n)
+      if (g.off[k][n] >= 0) {
+        const int r = x.rho[k][n];
+        e.voff[k][n] = tv; e.woff[k][n] = tw;
+        tv += int64_t(r) * r; tw += r;
+      }
+  e.V = Buf(c.pool, size_t(std::max<int64_t>(tv, 1)));
+  e.w = Buf(c.pool, size_t(std::max<int64_t>(tw, 1)));
+  std::vector<EigJob> jobs;
+  for (int k = kmin; k <= kmax; ++k)
+    for (int n = 0; n <= x.N; ++n)
+      if (g.off[k][n] >= 0) {
+        const int r = x.rho[k][n];
+        jobs.push_back(EigJob{g.buf.p + g.off[k][n], r, r, e.V.p + e.voff[k][n], e.w.p + e.woff[k][n], kAbsTolGeneral, true});
+      }
+  run_eig(c, jobs);
+  return e;
+}
+
+constexpr double kGramDrop = 1e-12;   // Gram eigenvalues <= this * max are treated as zero
+
+// Per bond, the per-sector eigenvalue cut-off of a Gram eigendecomposition.
+std::vector<double> gram_thresholds(Ctx& c, const Mps& x, const BondEig& e, int kmin, int kmax) {
+  auto w = download(c, e.w.p, e.w.n);
+  std::vector<double> thr(x.L + 1, 0.0);
+  for (int k = kmin; k <= kmax; ++k) {
+    double mx = 0;
+    for (int n = 0; n <= x.N; ++n)
+      if (e.woff[k][n] >= 0 && x.rho[k][n] > 0) mx = std::max(mx, w[e.woff[k][n]]);
+    thr[k] = kGramDrop * mx;
+  }
+  return thr;
+}
+
+}  // namespace
+
+// trunc_par(x; eps, cap) = P_1 P_2 ... P_{L-1} x with P_k the orthogonal projector onto the
+// kept left singular vectors of the k-th matricisation of x, every bond decided
+// independently with tolerance eps/(L-1).  With the left Gram G^L_k = V_L Lambda V_L^T and
+// the right Gram G^R_k, the singular values of the matricisation are those of
+// Z = Lambda^{1/2} V_L^T (right factor): Z Z^T = W^T G^R W with W = V_L Lambda^{1/2}.  For the
+// leading eigenvectors U_s of Z Z^T the bond matrices Lk = V_L Lambda^{-1/2} U_s and
+// Rk = U_s^T Lambda^{1/2} V_L^T satisfy A_k Lk Rk = P_k A_k, so inserting Lk Rk on every
+// bond applies all projectors; all bonds are processed in the same batched launches.
+std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
+  const int L = x.L, N = x.N;
+  const double delta = L > 1 ? eps / double(L - 1) : eps;
+  BondGrams GL = left_grams(c, x);
+  BondGrams GR = right_grams(c, x);
+  BondEig EL = eig_grams(c, x, GL, 1, L - 1);
+  auto thr = gram_thresholds(c, x, EL, 1, L - 1);
+  // W = V_L Lambda^{1/2}, Winv = V_L Lambda^{-1/2} (columns with Lambda <= thr are zero)
+  Buf W(c.pool, EL.V.n), Winv(c.pool, EL.V.n);
+  std::vector<double> lam = download(c, EL.w.p, EL.w.n);
+  {
+    // zero the dropped eigenvalues in a copy so that sqrt / inverse sqrt ignore them
+    std::vector<double> lam_c = lam;
+    for (int k = 1; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        if (EL.woff[k][n] >= 0)
+          for (int j = 0; j < x.rho[k][n]; ++j)
+            if (lam_c[EL.woff[k][n] + j] <= thr[k]) lam_c[EL.woff[k][n] + j] = 0.0;
+    Buf lamd(c.pool, lam_c.size());
+    PV_HIP(hipMemcpyAsync(lamd.p, lam_c.data(), lam_c.size() * 8, hipMemcpyHostToDevice, c.stream));
+    ScaleBatch sb;
+    for (int k = 1; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        if (EL.voff[k][n] >= 0) {
+          const int r = x.rho[k][n];
+          sb.add(EL.V.p + EL.voff[k][n], r, W.p + EL.voff[k][n], r, r, r, lamd.p + EL.woff[k][n], false, true);
+          sb.add(EL.V.p + EL.voff[k][n], r, Winv.p + EL.voff[k][n], r, r, r, lamd.p + EL.woff[k][n], true, true);
+        }
+    sb.run(c);
+    c.sync();  // lam_c must stay alive until the copy ran
+  }
+  // B = W^T G^R W for every bond and sector
+  Buf Tm(c.pool, EL.V.n), Bm(c.pool, EL.V.n);
+  {
+    GemmBatch g1, g2;
+    for (int k = 1; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        if (EL.voff[k][n] >= 0) {
+          const int r = x.rho[k][n];
+          g1.add(GR.buf.p + GR.off[k][n], r, 0, W.p + EL.voff[k][n], r, 0, Tm.p + EL.voff[k][n], r, r, r, r, 1.0, 0.0);
+          g2.add(W.p + EL.voff[k][n], r, 1, Tm.p + EL.voff[k][n], r, 0, Bm.p + EL.voff[k][n], r, r, r, r, 1.0, 0.0);
+        }
+    g1.run(c);
+    g2.run(c);
+  }
+  BondGrams Bg;
+  Bg.off.assign(L + 1, std::vector<int64_t>(N + 1, -1));
+  for (int k = 1; k < L; ++k) Bg.off[k] = EL.voff[k];
+  Bg.buf = std::move(Bm);
+  BondEig EB = eig_grams(c, x, Bg, 1, L - 1);
+  std::vector<double> sb2 = download(c, EB.w.p, EB.w.n);
+  auto rho = x.rho;
+  for (int k = 1; k < L; ++k) {
+    std::vector<std::vector<double>> sig(N + 1);
+    for (int n = 0; n <= N; ++n)
+      if (EB.woff[k][n] >= 0)
+        for (int j = 0; j < x.rho[k][n]; ++j) sig[n].push_back(std::sqrt(std::max(sb2[EB.woff[k][n] + j], 0.0)));
+    // same selection rules with the Gram-level numerical-zero cut-off
+    struct E { double s; int n, j; };
+    std::vector<E> all;
+    double smax = 0;
+    for (int n = 0; n <= N; ++n)
+      for (int j = 0; j < int(sig[n].size()); ++j) { all.push_back({sig[n][j], n, j}); smax = std::max(smax, sig[n][j]); }
+    std::vector<int> keep(N + 1, 0);
+    if (smax > 0) {
+      std::vector<std::vector<double>> sig2(N + 1);
+      for (int n = 0; n <= N; ++n)
+        for (double v : sig[n]) if (v > kZeroTolPar * smax) sig2[n].push_back(v);
+      keep = select_ranks(sig2, delta, cap, cap_bound);
+    }
+    for (int n = 0; n <= N; ++n)
+      if (x.valid(k, n)) rho[k][n] = keep[n];
+  }
+  // bond matrices: Lk = Winv U_s (r x s), Rt = W U_s (r x s)
+  Buf Lb(c.pool, EL.V.n), Rb(c.pool, EL.V.n);
+  {
+    GemmBatch g;
+    for (int k = 1; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        if (EL.voff[k][n] >= 0 && rho[k][n] > 0) {
+          const int r = x.rho[k][n], s = rho[k][n];
+          g.add(Winv.p + EL.voff[k][n], r, 0, EB.V.p + EB.voff[k][n], r, 0, Lb.p + EL.voff[k][n], r, r, s, r, 1.0, 0.0);
+          g.add(W.p + EL.voff[k][n], r, 0, EB.V.p + EB.voff[k][n], r, 0, Rb.p + EL.voff[k][n], r, r, s, r, 1.0, 0.0);
+        }
+    g.run(c);
+  }
+  auto y = mps_alloc(c, L, N, rho);
+  // Z = [U | O] diag(L_k[n], L_k[n+1]) then new block = R_{k-1}[n] Z
+  std::vector<Buf> Z;
+  GemmBatch gz, gr;
+  CopyBatch cz;
+  for (int k = 1; k <= L; ++k) {
+    for (int n = 0; n <= N; ++n) {
+      if (!x.valid(k - 1, n)) continue;
+      const int r = x.rows(k, n);
+      const int su = y->ucols(k, n), so = y->ocols(k, n);
+      if (r == 0 || su + so == 0 || y->rows(k, n) == 0) continue;
+      Buf z(c.pool, size_t(r) * (su + so));
+      if (su) {
+        if (k == L) cz.add(x.U(k, n), r, z.p, r, r, su, 1.0);
+        else gz.add(x.U(k, n), r, 0, Lb.p + EL.voff[k][n], x.rho[k][n], 0, z.p, r, r, su, x.ucols(k, n), 1.0, 0.0);
+      }
+      if (so) {
+        if (k == L) cz.add(x.O(k, n), r, z.p + int64_t(r) * su, r, r, so, 1.0);
+        else gz.add(x.O(k, n), r, 0, Lb.p + EL.voff[k][n + 1], x.rho[k][n + 1], 0, z.p + int64_t(r) * su, r, r, so,
+                    x.ocols(k, n), 1.0, 0.0);
+      }
+      const int sl = y->rows(k, n);
+      if (k == 1) cz.add(z.p, r, y->U(k, n), sl, r, su + so, 1.0);
+      else gr.add(Rb.p + EL.voff[k - 1][n], r, 1, z.p, r, 0, y->U(k, n), sl, sl, su + so, r, 1.0, 0.0);
+      Z.push_back(std::move(z));
+    }
+  }
+  gz.run(c);
+  cz.run(c);  // k == L copies; the k == 1 copies need gz first (issued after it)
+  gr.run(c);
+  // k == 1 blocks are copies of Z (R_0 = 1): issue them now that Z is complete
+  for (auto& b : Z) c.scratch.push_back(std::move(b));
+  for (Buf* b : {&W, &Winv, &Tm, &Lb, &Rb}) c.scratch.push_back(std::move(*b));
+  c.scratch.push_back(std::move(GL.buf));
+  c.scratch.push_back(std::move(GR.buf));
+  c.scratch.push_back(std::move(EL.V)); c.scratch.push_back(std::move(EL.w));
+  c.scratch.push_back(std::move(EB.V)); c.scratch.push_back(std::move(EB.w));
+  c.scratch.push_back(std::move(Bg.buf));
+  return y;
 }
 
 // ---------------------------------------------------------------- H application
@@ -1075,7 +1444,8 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
   const DevMpo& op = *c.hmpo;
   const int L = xin.L, N = xin.N;
   std::unique_ptr<Mps> xr;
-  if (m_zip > 0) xr = orthogonalize_right(c, xin);
+  const bool two_pass = c.trunc_mode == 0 || m_zip <= 0;
+  if (m_zip > 0) xr = orthogonalize_right(c, xin, two_pass);
   const Mps& x = m_zip > 0 ? *xr : xin;
   const int zcap = m_zip > 0 ? m_zip : (1 << 30);
   auto rho = empty_rho(L, N);
@@ -1129,7 +1499,7 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
       if (r1[n2]) g.add(X1, r1[n2], 0, X1, r1[n2], 1, se[n2].G.p + r0[n2] + int64_t(r0[n2]) * R, R, r1[n2], r1[n2], K, 1.0, 0.0);
     }
     g.run(c);
-    eig_all(c, se);
+    eig_all(c, se, kAbsTolGeneral, !two_pass);
     GemmBatch g1;
     for (int n2 = 0; n2 <= N; ++n2) {
       const int R = se[n2].n;
@@ -1142,20 +1512,24 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
     }
     g.run(c);
     g1.run(c);
-    for (int n2 = 0; n2 <= N; ++n2) {
-      const int R = se[n2].n;
-      if (R == 0) continue;
-      const int K = int(Ln.ncols[n2]);
-      se2[n2].n = R;
-      se2[n2].G = Buf(c.pool, size_t(R) * R);
-      g.add(Y[n2].p, R, 0, Y[n2].p, R, 1, se2[n2].G.p, R, R, R, K, 1.0, 0.0);
+    if (two_pass) {
+      for (int n2 = 0; n2 <= N; ++n2) {
+        const int R = se[n2].n;
+        if (R == 0) continue;
+        const int K = int(Ln.ncols[n2]);
+        se2[n2].n = R;
+        se2[n2].G = Buf(c.pool, size_t(R) * R);
+        g.add(Y[n2].p, R, 0, Y[n2].p, R, 1, se2[n2].G.p, R, R, R, K, 1.0, 0.0);
+      }
+      g.run(c);
+      eig_all(c, se2, kAbsTolRefine);
+    } else {
+      identity_pass(c, se, se2);
     }
-    g.run(c);
-    eig_all(c, se2);
     auto sig = sigmas(c, se2);
     std::vector<std::vector<double>> sig_all(N + 1);
     for (int n2 = 0; n2 <= N; ++n2) sig_all[n2] = sig[n2];
-    std::vector<int> keep = select_ranks(sig_all, 0.0, zcap, nullptr);
+    std::vector<int> keep = select_ranks(sig_all, 0.0, zcap, nullptr, two_pass ? kZeroTol : kZeroTolPar);
     for (int n2 = 0; n2 <= N; ++n2) y->rho[k][n2] = y->valid(k, n2) ? keep[n2] : 0;
     alloc_site(c, *y, k);
     fill(c, y->site[k - 1].p, y->site_size(k), 0.0);

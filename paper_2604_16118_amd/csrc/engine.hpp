@@ -98,9 +98,16 @@ struct DevMpo {
   int L = 0;
   std::vector<int> w;
   std::vector<std::array<int, 6>> qoff;
+  // Dense charge block W^{s_out s_in}[b in q_in, b' in q_out] (w_in x w_out, column
+  // major), applied by GEMM; its entries are removed from the sparse CSR.
+  struct Dense {
+    int q_in, q_out, s_in, s_out, w_in, w_out;
+    Buf W;
+  };
   struct Site {
     Buf row_ptr, b_in, s_in, val;  // int32 / uint8 stored in double-sized buffers
     int w_out = 0;
+    std::vector<Dense> dense;
   };
   std::vector<Site> site;
   std::vector<Buf> charge;  // int8 per cut
@@ -137,6 +144,10 @@ struct Ctx {
   double t_ms[T_COUNT] = {0}, t_flops[T_COUNT] = {0}, t_bytes[T_COUNT] = {0};
   int t_calls[T_COUNT] = {0};
   bool timing = true;
+  // 0: sequential TT-SVD truncation with two-pass Gram factorisations (exact path);
+  // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
+  //    intermediate-rank H application.
+  int trunc_mode = 0;
 
   void sync();
   hipEvent_t event();
@@ -160,5 +171,7 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& x, double eps, int cap, int m_zi
 std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound);
 std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m);
 double norm_canonical(Ctx& c, const Mps& x);
+std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
+double norm2(Ctx& c, const Mps& x);
 
 }  // namespace pv

@@ -14,6 +14,12 @@ namespace pv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 #define PV_LAUNCH_CHECK()                                                          \
   do {                                                                             \
     hipError_t e_ = hipGetLastError();                                             \
@@ -133,48 +139,98 @@ void launch_reduce(const ReduceDesc* d, int nd, int64_t total, hipStream_t s) {
 // into n2/2 disjoint pairs per step, n2-1 steps per sweep meeting every pair once.
 // All rotations of a step are applied at once as 2x2 block updates
 // B_ij <- J_i^T B_ij J_j over the block rows/columns of the pairs.  The working
-// matrix is the packed upper triangle (in LDS when it fits); V is accumulated in
-// global memory.  A rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|).
+// matrix is the packed upper triangle; depending on the size it lives in LDS together
+// with V (MODE 2), in LDS with V in global memory (MODE 1), or both in global memory
+// (MODE 0).  A rotation is applied when |a_pq| > 1e-14 sqrt(|a_pp a_qq|) and
+// |a_pq| > abs_tol max_i |a_ii|.  On a general matrix the updates leave rounding noise
+// of order eps max|a_ii| in the small-eigenvalue block, which the relative test alone
+// keeps rotating; an absolute floor above that noise (abs_tol = 1e-15) ends the sweeps.
+// On nearly diagonal input (the second pass of a two-pass factorisation) the noise is
+// local and abs_tol = 0 keeps small eigenvalues relatively accurate.  Sweeps stop when a
+// sweep applies no rotation.
 // ---------------------------------------------------------------------------
-constexpr int kEigThreads = 512;
 constexpr int kEigMaxPairs = kEigMax / 2;
+constexpr double kJacobiTol = 1e-14;
 
-__device__ inline int64_t pidx(int r, int c) {  // packed upper, r <= c
-  return (int64_t)c * (c + 1) / 2 + r;
+__device__ inline int pidx(int r, int c) {  // packed upper, r <= c (n <= 1024: fits int32)
+  return (c * (c + 1) >> 1) + r;
 }
-__device__ inline int64_t sidx(int r, int c) { return r <= c ? pidx(r, c) : pidx(c, r); }
+__device__ inline int sidx(int r, int c) { return r <= c ? pidx(r, c) : pidx(c, r); }
 
-template <bool LDS>
-__global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigDesc* __restrict__ descs, int maxsweep) {
+// Dynamic LDS of one problem in each mode (bytes).
+__host__ __device__ inline size_t eig_lds_bytes(int n, int mode) {
+  const int P = (n + (n & 1)) / 2;
+  size_t b = size_t(P) * (2 * sizeof(double) + 2 * sizeof(int));
+  if (mode >= 1) b += size_t(n) * (n + 1) / 2 * sizeof(double);
+  if (mode == 2) b += size_t(n) * n * sizeof(double);
+  return b;
+}
+
+constexpr int kEigBlocksPerThread = 8;  // (P(P+1)/2) / threads <= 8 for n <= 1024 at 1024 threads
+                                        // is not guaranteed; larger counts fall back to a loop
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void jacobi_eig_kernel(const EigDesc* __restrict__ descs, int maxsweep) {
   extern __shared__ double smem[];
-  __shared__ double rc[kEigMaxPairs], rs[kEigMaxPairs];
-  __shared__ int rp[kEigMaxPairs], rq[kEigMaxPairs];
   __shared__ int rotated;
+  __shared__ double dmax;
   const EigDesc d = descs[blockIdx.x];
   const int n = d.n;
   if (n <= 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int n2 = n + (n & 1), P = n2 / 2;
-  double* Ap = LDS ? smem : (d.work + (int64_t)n * n);
-  double* Vw = d.work;
+  double* lds = smem;
+  double* Ap;
+  double* Vw;
+  if (MODE == 0) { Vw = d.work; Ap = d.work + (int64_t)n * n; }
+  else if (MODE == 1) { Vw = d.work; Ap = lds; lds += n * (n + 1) / 2; }
+  else { Ap = lds; lds += n * (n + 1) / 2; Vw = lds; lds += n * n; }
+  double* rc = lds;
+  double* rs = rc + P;
+  int* rp = reinterpret_cast<int*>(rs + P);
+  int* rq = rp + P;
   for (int c = 0; c < n; ++c)
     for (int r = tid; r <= c; r += bs) Ap[pidx(r, c)] = d.A[r + (int64_t)c * d.lda];
-  for (int64_t e = tid; e < (int64_t)n * n; e += bs) Vw[e] = (e % n == e / n) ? 1.0 : 0.0;
+  for (int e = tid; e < n * n; e += bs) {
+    const int col = e / n;
+    Vw[e] = (e - col * n == col) ? 1.0 : 0.0;
+  }
+  // this thread's 2x2 blocks (i <= j) of the pair-indexed matrix, decoded once
+  const int nb = P * (P + 1) / 2;
+  int myblk[kEigBlocksPerThread];
+  int nmine = 0;
+  for (int e = tid; e < nb && nmine < kEigBlocksPerThread; e += bs) {
+    int j = int((sqrtf(8.0f * float(e) + 1.0f) - 1.0f) * 0.5f);
+    while ((j + 1) * (j + 2) / 2 <= e) ++j;
+    while (j * (j + 1) / 2 > e) --j;
+    myblk[nmine++] = ((e - j * (j + 1) / 2) << 16) | j;
+  }
+  const int extra_start = tid + kEigBlocksPerThread * bs;  // blocks beyond the cached ones
   __syncthreads();
-  const double eps = 2.0 * DBL_EPSILON;
+  int sweeps = 0;
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) {
+      rotated = 0;
+      double m = 0.0;
+      for (int i = 0; i < n; ++i) m = fmax(m, fabs(Ap[pidx(i, i)]));
+      dmax = m;
+    }
     __syncthreads();
+    ++sweeps;
+    const double abs_floor = fmax(d.abs_tol * dmax, 1e-300);
     for (int step = 0; step < n2 - 1; ++step) {
       for (int k = tid; k < P; k += bs) {
         int a, b;
         if (k == 0) { a = n2 - 1; b = step; }
-        else { a = (step + k) % (n2 - 1); b = (step - k + n2 - 1) % (n2 - 1); }
+        else {
+          a = step + k; if (a >= n2 - 1) a -= n2 - 1;
+          b = step - k; if (b < 0) b += n2 - 1;
+        }
         const int p = min(a, b), q = max(a, b);
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double app = Ap[pidx(p, p)], aqq = Ap[pidx(q, q)], apq = Ap[pidx(p, q)];
-          if (fabs(apq) > eps * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+          if (fabs(apq) > kJacobiTol * sqrt(fabs(app * aqq)) && fabs(apq) > abs_floor) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -185,18 +241,13 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigDesc* 
         rp[k] = p; rq[k] = q; rc[k] = c; rs[k] = s;
       }
       __syncthreads();
-      const int nb = P * (P + 1) / 2;
-      for (int e = tid; e < nb; e += bs) {
-        int j = int((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((j + 1) * (j + 2) / 2 <= e) ++j;
-        while (j * (j + 1) / 2 > e) --j;
-        const int i = e - j * (j + 1) / 2;
+      auto update = [&](int i, int j) {
         const double si = rs[i], sj = rs[j];
-        if (si == 0.0 && sj == 0.0) continue;
+        if (si == 0.0 && sj == 0.0) return;
         const double ci = rc[i], cj = rc[j];
         const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
         if (i == j) {
-          if (qi >= n) continue;
+          if (qi >= n) return;
           const double app = Ap[pidx(pi, pi)], aqq = Ap[pidx(qi, qi)], apq = Ap[pidx(pi, qi)];
           Ap[pidx(pi, pi)] = ci * ci * app - 2.0 * ci * si * apq + si * si * aqq;
           Ap[pidx(qi, qi)] = si * si * app + 2.0 * ci * si * apq + ci * ci * aqq;
@@ -214,14 +265,21 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigDesc* 
           if (vqi) Ap[sidx(qi, pj)] = t10 * cj - t11 * sj;
           if (vqi && vqj) Ap[sidx(qi, qj)] = t10 * sj + t11 * cj;
         }
+      };
+      for (int m = 0; m < nmine; ++m) update(myblk[m] >> 16, myblk[m] & 0xffff);
+      for (int e = extra_start; e < nb; e += bs) {
+        int j = int((sqrtf(8.0f * float(e) + 1.0f) - 1.0f) * 0.5f);
+        while ((j + 1) * (j + 2) / 2 <= e) ++j;
+        while (j * (j + 1) / 2 > e) --j;
+        update(e - j * (j + 1) / 2, j);
       }
-      for (int64_t e = tid; e < (int64_t)P * n; e += bs) {
-        const int k = int(e / n), r = int(e % n);
+      for (int e = tid; e < P * n; e += bs) {
+        const int k = e / n, r = e - k * n;
         const double s = rs[k];
         if (s == 0.0) continue;
         const double c = rc[k];
-        double* vp = Vw + (int64_t)rp[k] * n + r;
-        double* vq = Vw + (int64_t)rq[k] * n + r;
+        double* vp = Vw + rp[k] * n + r;
+        double* vq = Vw + rq[k] * n + r;
         const double x = *vp, y = *vq;
         *vp = c * x - s * y;
         *vq = s * x + c * y;
@@ -240,45 +298,361 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigDesc* 
       rank += (wj > wi) || (wj == wi && j < i);
     }
     d.w[rank] = wi;
-    for (int r = 0; r < n; ++r) d.V[r + (int64_t)rank * n] = Vw[r + (int64_t)i * n];
+    for (int r = 0; r < n; ++r) d.V[r + (int64_t)rank * n] = Vw[r + i * n];
   }
+  if (tid == 0 && d.sweeps) *d.sweeps = sweeps;
 }
 
-// Largest dynamic LDS request accepted for the LDS variant (0 when the opt-in fails).
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver by Householder tridiagonalisation, bisection and inverse
+// iteration, one workgroup per matrix (used for the Gram eigenproblems of the scaled
+// path, where Jacobi's O(n^3) traffic per sweep is too slow):
+//  1. A = Q T Q^T with Householder reflectors H_k = I - beta_k v_k v_k^T acting on rows
+//     and columns k+1..n-1 (the trailing block is updated by the symmetric rank-2 form
+//     A <- A - v q^T - q v^T, q = p - (beta/2)(v^T p) v, p = beta A v);
+//  2. every eigenvalue of T by bisection on the Sturm count (thread t finds the t-th
+//     smallest);
+//  3. eigenvectors of T by inverse iteration with a partially pivoted tridiagonal LU,
+//     three iterations, members of a cluster (gap <= 1e-7 ||T||) orthogonalised against
+//     each other by modified Gram-Schmidt; eigenvalues <= vec_cut * max |lambda| get a
+//     zero vector (the callers drop them);
+//  4. back-transformation V = H_0 H_1 ... H_{n-3} Z.
+// Output as the Jacobi kernel: eigenvalues descending, eigenvectors in the columns of V.
+// ---------------------------------------------------------------------------
+constexpr int kTriThreads = 1024;
+
+__device__ inline double block_sum(double v, double* red, int tid, int bs) {
+  v = wave_sum_d(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (bs + 63) / 64; ++w) t += red[w];
+  return t;
+}
+
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double tiny) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q == 0.0) q = -tiny;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (q == 0.0) q = -tiny;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Solve (T - sigma I) x = b in place for one thread; LU with partial pivoting stored in
+// the thread's scratch (u, v, w, mult: n doubles each; piv as the sign of mult slot).
+__device__ void tri_factor(const double* d, const double* e, int n, double sigma, double tiny,
+                           double* u, double* v, double* w, double* mult, unsigned char* piv) {
+  double cd = d[0] - sigma, cs1 = n > 1 ? e[0] : 0.0, cs2 = 0.0;
+  for (int i = 0; i < n - 1; ++i) {
+    const double sub = e[i];
+    const double a1 = d[i + 1] - sigma;
+    const double s1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+    if (fabs(cd) >= fabs(sub)) {
+      piv[i] = 0;
+      const double m = cd != 0.0 ? sub / cd : 0.0;
+      mult[i] = m;
+      u[i] = cd; v[i] = cs1; w[i] = cs2;
+      cd = a1 - m * cs1;
+      cs1 = s1 - m * cs2;
+      cs2 = 0.0;
+    } else {
+      piv[i] = 1;
+      const double m = cd / sub;
+      mult[i] = m;
+      u[i] = sub; v[i] = a1; w[i] = s1;
+      cd = cs1 - m * a1;
+      cs1 = cs2 - m * s1;
+      cs2 = 0.0;
+    }
+    if (u[i] == 0.0) u[i] = tiny;
+  }
+  u[n - 1] = cd == 0.0 ? tiny : cd;
+  v[n - 1] = 0.0;
+  w[n - 1] = 0.0;
+}
+
+__device__ void tri_solve(int n, const double* u, const double* v, const double* w, const double* mult,
+                          const unsigned char* piv, double* x) {
+  // forward: apply the row operations to the right-hand side
+  double cur = x[0];
+  for (int i = 0; i < n - 1; ++i) {
+    const double nxt = x[i + 1];
+    if (!piv[i]) { x[i] = cur; cur = nxt - mult[i] * cur; }
+    else { x[i] = nxt; cur = cur - mult[i] * nxt; }
+  }
+  x[n - 1] = cur;
+  // back substitution
+  x[n - 1] = x[n - 1] / u[n - 1];
+  if (n >= 2) x[n - 2] = (x[n - 2] - v[n - 2] * x[n - 1]) / u[n - 2];
+  for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - v[i] * x[i + 1] - w[i] * x[i + 2]) / u[i];
+}
+
+__global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double red[kTriThreads / 64];
+  __shared__ double sh_beta, sh_K;
+  extern __shared__ double tsm[];  // d[n], e[n], e2[n], lam[n], beta[n], vsh[n], qsh[n]
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  double* dd = tsm;
+  double* ee = dd + n;
+  double* e2 = ee + n;
+  double* lam = e2 + n;
+  double* betas = lam + n;
+  double* vsh = betas + n;
+  double* psh = vsh + n;
+  const int lda = n;
+  double* A = D.work;                         // n x n working copy
+  double* scratch = D.work + (int64_t)n * n;  // per-thread inverse-iteration storage
+  double* Z = D.V;                            // eigenvectors of T, then of A
+  for (int e = tid; e < n * n; e += bs) {
+    const int j = e / n, i = e - j * n;
+    A[e] = (i <= j) ? D.A[i + (int64_t)j * D.lda] : D.A[j + (int64_t)i * D.lda];
+  }
+  __syncthreads();
+  // 1. tridiagonalisation
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double* x = A + (k + 1) + (int64_t)k * lda;  // column k below the diagonal
+    double part = 0.0;
+    for (int i = tid + 1; i < m; i += bs) part += x[i] * x[i];
+    const double sig2 = block_sum(part, red, tid, bs);
+    const double x0 = x[0];
+    if (tid == 0) {
+      dd[k] = A[k + (int64_t)k * lda];
+      if (sig2 == 0.0) {
+        ee[k] = x0;
+        sh_beta = 0.0;
+      } else {
+        const double nrm = sqrt(x0 * x0 + sig2);
+        const double alpha = x0 > 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        ee[k] = alpha;
+        sh_beta = 2.0 / (v0 * v0 + sig2);
+        x[0] = v0;  // v stored over the column
+      }
+      betas[k] = sh_beta;
+    }
+    __syncthreads();
+    const double beta = sh_beta;
+    if (beta == 0.0) continue;
+    for (int i = tid; i < m; i += bs) vsh[i] = x[i];
+    __syncthreads();
+    // p = beta A22 v, A22 = A[k+1:, k+1:]; A22 is symmetric, so p_i is the dot product of
+    // column i with v: one wavefront per column, lanes along the contiguous column
+    const double* A22 = A + (k + 1) + (int64_t)(k + 1) * lda;
+    {
+      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+      for (int i0 = wave; i0 < m; i0 += 2 * nw) {
+        const int i1 = i0 + nw;
+        const double* c0 = A22 + (int64_t)i0 * lda;
+        const double* c1 = A22 + (int64_t)(i1 < m ? i1 : i0) * lda;
+        double a0 = 0.0, a1 = 0.0;
+        for (int j = lane; j < m; j += 64) {
+          const double vj = vsh[j];
+          a0 += c0[j] * vj;
+          a1 += c1[j] * vj;
+        }
+        a0 = wave_sum_d(a0);
+        a1 = wave_sum_d(a1);
+        if (lane == 0) {
+          psh[i0] = beta * a0;
+          if (i1 < m) psh[i1] = beta * a1;
+        }
+      }
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = tid; i < m; i += bs) pv += psh[i] * vsh[i];
+    const double vtp = block_sum(pv, red, tid, bs);
+    if (tid == 0) sh_K = 0.5 * beta * vtp;
+    __syncthreads();
+    const double K = sh_K;
+    for (int i = tid; i < m; i += bs) psh[i] -= K * vsh[i];  // q
+    __syncthreads();
+    double* A22w = A + (k + 1) + (int64_t)(k + 1) * lda;
+    {
+      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+      for (int j = wave; j < m; j += nw) {
+        const double vj = vsh[j], qj = psh[j];
+        double* col = A22w + (int64_t)j * lda;
+        for (int i = lane; i < m; i += 64) col[i] -= vsh[i] * qj + psh[i] * vj;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
+      ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
+      betas[n - 2] = 0.0;
+    }
+    dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
+    ee[n - 1] = 0.0;
+    betas[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += bs) e2[i] = ee[i] * ee[i];
+  // Gershgorin bounds and the norm of T
+  double lo = 1e300, hi = -1e300, tn = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
+    lo = fmin(lo, dd[i] - r);
+    hi = fmax(hi, dd[i] + r);
+  }
+  tn = fmax(fabs(lo), fabs(hi));
+  const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
+  __syncthreads();
+  // 2. bisection: thread t -> t-th smallest eigenvalue
+  for (int t = tid; t < n; t += bs) {
+    double a = lo - 1e-14 * tn - 1e-300, b = hi + 1e-14 * tn + 1e-300;
+    for (int it = 0; it < 100; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0) break;
+      if (sturm_count(dd, e2, n, mid, tiny + 1e-300) > t) b = mid; else a = mid;
+    }
+    lam[t] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  // 3. inverse iteration, one thread per cluster (clusters of near-equal eigenvalues)
+  double lmax = 0.0;
+  for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
+  const double cut = D.abs_tol * lmax;
+  const double ctol = 1e-7 * fmax(tn, 1e-300);
+  for (int t = tid; t < n; t += bs) {
+    // cluster starts: a gap above ctol, or every 16th member of a long run of close values
+    bool start = (t == 0) || (lam[t] - lam[t - 1] > ctol);
+    if (!start) {
+      int r = t;
+      while (r > 0 && lam[r] - lam[r - 1] <= ctol) --r;
+      start = ((t - r) % 16) == 0;
+    }
+    if (!start) continue;
+    int last = t;
+    while (last + 1 < n && lam[last + 1] - lam[last] <= ctol && last + 1 - t < 16) ++last;
+    double* u = scratch + (int64_t)t * 5 * n;
+    double* v = u + n;
+    double* w = v + n;
+    double* mult = w + n;
+    unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
+    for (int j = t; j <= last; ++j) {
+      double* z = Z + (int64_t)j * n;
+      if (fabs(lam[j]) <= cut) {
+        for (int i = 0; i < n; ++i) z[i] = 0.0;
+        continue;
+      }
+      const double sigma = lam[j] + (j - t) * 10.0 * 2.2e-16 * tn;
+      tri_factor(dd, ee, n, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv);
+      for (int i = 0; i < n; ++i) z[i] = 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0;
+      for (int it = 0; it < 3; ++it) {
+        tri_solve(n, u, v, w, mult, piv, z);
+        for (int jj = t; jj < j; ++jj) {
+          const double* y = Z + (int64_t)jj * n;
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += y[i] * z[i];
+          for (int i = 0; i < n; ++i) z[i] -= dot * y[i];
+        }
+        double nn = 0.0;
+        for (int i = 0; i < n; ++i) nn += z[i] * z[i];
+        nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = 0; i < n; ++i) z[i] *= nn;
+      }
+    }
+  }
+  __syncthreads();
+  // 4. back-transformation: apply H_{n-3} ... H_0 to the columns of Z
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    const int m = n - k - 1;
+    const double* vk = A + (k + 1) + (int64_t)k * lda;
+    for (int i = tid; i < m; i += bs) vsh[i] = vk[i];
+    __syncthreads();
+    {
+      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+      for (int c = wave; c < n; c += nw) {
+        double* zc = Z + (int64_t)c * n + (k + 1);
+        double dot = 0.0;
+        for (int i = lane; i < m; i += 64) dot += vsh[i] * zc[i];
+        dot = beta * wave_sum_d(dot);
+        if (dot != 0.0)
+          for (int i = lane; i < m; i += 64) zc[i] -= dot * vsh[i];
+      }
+    }
+    __syncthreads();
+  }
+  // descending order: eigenvalue t (ascending) goes to position n-1-t; columns reversed
+  for (int t = tid; t < n; t += bs) D.w[n - 1 - t] = lam[t];
+  __syncthreads();
+  for (int e = tid; e < (n / 2) * n; e += bs) {
+    const int c = e / n, i = e - c * n;
+    double* a = Z + (int64_t)c * n + i;
+    double* b = Z + (int64_t)(n - 1 - c) * n + i;
+    const double ta = *a;
+    *a = *b;
+    *b = ta;
+  }
+  if (tid == 0 && D.sweeps) *D.sweeps = -1;
+}
+
+void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
+  if (nprob <= 0) return;
+  if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  const size_t shm = size_t(nmax) * 7 * sizeof(double);
+  const int threads = nmax <= 64 ? 256 : kTriThreads;
+  hipLaunchKernelGGL(tridiag_eig_kernel, dim3(nprob), dim3(threads), shm, s, d);
+  PV_LAUNCH_CHECK();
+}
+
+static size_t g_lds_limit = size_t(-1);
+
+// Largest dynamic LDS accepted for the LDS-resident variants (0 when the opt-in fails).
 static size_t eig_lds_limit() {
-  static size_t limit = size_t(-1);
-  if (limit == size_t(-1)) {
+  if (g_lds_limit == size_t(-1)) {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
     (void)hipGetLastError();
-    // static LDS of the kernel: rotation tables and the flag
-    const size_t stat = kEigMaxPairs * (2 * sizeof(double) + 2 * sizeof(int)) + 64;
-    size_t want = v > int(stat) ? size_t(v) - stat : 0;
-    if (want > 0 && hipFuncSetAttribute((const void*)jacobi_eig_kernel<true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) != hipSuccess) {
-      (void)hipGetLastError();
-      want = 0;
-    }
-    limit = want;
+    size_t want = v > 1024 ? size_t(v) - 1024 : 0;  // room for the static flag
+    const void* fns[3] = {(const void*)jacobi_eig_kernel<0>, (const void*)jacobi_eig_kernel<1>,
+                          (const void*)jacobi_eig_kernel<2>};
+    for (const void* f : fns)
+      if (want > 0 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) != hipSuccess) {
+        (void)hipGetLastError();
+        want = 0;
+      }
+    g_lds_limit = want;
   }
-  return limit;
+  return g_lds_limit;
 }
 
-bool eig_fits_lds(int n) {
-  return n <= kEigLdsMax && size_t(n) * (n + 1) / 2 * sizeof(double) <= eig_lds_limit();
+int eig_mode(int n) {
+  const size_t lim = eig_lds_limit();
+  if (eig_lds_bytes(n, 2) <= lim) return 2;
+  if (eig_lds_bytes(n, 1) <= lim) return 1;
+  return 0;
 }
 
-void launch_eig(const EigDesc* d, int nprob, int nmax, bool lds, hipStream_t s) {
+void launch_eig(const EigDesc* d, int nprob, int nmax, int mode, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
-  if (lds) {
-    const size_t shm = size_t(nmax) * (nmax + 1) / 2 * sizeof(double);
-    if (shm > eig_lds_limit()) throw std::runtime_error("eig: LDS request above the device limit");
-    hipLaunchKernelGGL(jacobi_eig_kernel<true>, dim3(nprob), dim3(kEigThreads), shm, s, d, 60);
-  } else {
-    hipLaunchKernelGGL(jacobi_eig_kernel<false>, dim3(nprob), dim3(kEigThreads), 0, s, d, 60);
-  }
+  const size_t shm = eig_lds_bytes(nmax, mode);
+  if (shm > eig_lds_limit()) throw std::runtime_error("eig: LDS request above the device limit");
+  const int threads = nmax <= 48 ? 256 : (nmax <= 96 ? 512 : 1024);
+  if (mode == 2)
+    hipLaunchKernelGGL(jacobi_eig_kernel<2>, dim3(nprob), dim3(threads), shm, s, d, 60);
+  else if (mode == 1)
+    hipLaunchKernelGGL(jacobi_eig_kernel<1>, dim3(nprob), dim3(threads), shm, s, d, 60);
+  else
+    hipLaunchKernelGGL(jacobi_eig_kernel<0>, dim3(nprob), dim3(threads), shm, s, d, 60);
   PV_LAUNCH_CHECK();
 }
 

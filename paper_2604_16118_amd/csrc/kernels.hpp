@@ -35,7 +35,9 @@ struct EigDesc {
   int lda, n;
   double* V;
   double* w;
-  double* work;  // n*n (+ n(n+1)/2 for the global-memory variant)
+  double* work;  // n*n + n(n+1)/2 doubles
+  int* sweeps;   // optional: number of sweeps taken (diagnostics), may be null
+  double abs_tol;  // rotations need |a_pq| > abs_tol * max_i |a_ii| (0: relative test only)
 };
 
 // W-step (application of one MPO site to a partially contracted tensor).
@@ -81,9 +83,14 @@ struct ScaleDesc {
 
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, hipStream_t s);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
-void launch_eig(const EigDesc* d_desc, int nprob, int nmax, bool lds, hipStream_t s);
-// True when an n x n problem can use the LDS-resident variant on this device.
-bool eig_fits_lds(int n);
+// mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
+// problems of one launch must admit the chosen mode at size nmax.
+void launch_eig(const EigDesc* d_desc, int nprob, int nmax, int mode, hipStream_t s);
+// Fastest mode available for an n x n problem on this device.
+int eig_mode(int n);
+// Tridiagonalisation + bisection + inverse iteration; work holds 6 n^2 doubles; abs_tol
+// is the relative cut below which eigenvectors are returned as zero.
+void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
 void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
                   const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
                   const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,
@@ -94,7 +101,6 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
 constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
-constexpr int kEigLdsMax = 180;  // packed FP64 upper triangle fits in LDS up to this n
 constexpr int kEigMax = 1024;
 
 }  // namespace pv

@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("c0", C.c_double), ("c", C.c_double),
                 ("delta", C.c_double), ("eps_num", C.c_double), ("t_eig", C.c_double),
                 ("c_lower", C.c_double), ("c_upper", C.c_double), ("max_retries", C.c_int),
-                ("precision", C.c_int), ("resume_eta", C.c_double), ("resume_s", C.c_double),
+                ("precision", C.c_int), ("truncation", C.c_int), ("resume_eta", C.c_double),
+                ("resume_s", C.c_double),
                 ("resume_s2", C.c_double)]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.pv_mps_layout.argtypes = [C.c_void_p, C.c_int, ip, C.POINTER(C.c_size_t)]
         L.pv_mps_download.argtypes = [C.c_void_p, C.c_int, dp, C.c_size_t]
         L.pv_mps_free.argtypes = [C.c_void_p, C.c_int]
+        L.pv_set_truncation.argtypes = [C.c_void_p, C.c_int]
         L.pv_dot.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.pv_expect_h.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.pv_lincomb.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int, ip]
@@ -196,6 +198,9 @@ class Context:
     def mps_free(self, handle):
         _check(lib().pv_mps_free(self._p, handle))
 
+    def set_truncation(self, mode):
+        _check(lib().pv_set_truncation(self._p, int(mode)))
+
     def dot(self, a, b):
         out = C.c_double()
         _check(lib().pv_dot(self._p, a, b, C.byref(out)))
@@ -228,11 +233,11 @@ class Context:
 
     def run(self, rank_cap, max_iter, tau=1e-10, c=0.5, delta=10.0, m_zip=0, c0=0.1,
             eps_num=0.0, t_eig=0.5, c_lower=0.0, c_upper=0.0, max_retries=30, start=-1,
-            precision=0, resume=None):
+            precision=0, truncation=0, resume=None):
         r = resume or {}
         prm = Params(rank_cap, m_zip, max_iter, tau, c0, c, delta, eps_num, t_eig, c_lower,
-                     c_upper, max_retries, precision, r.get("eta_res", 0.0), r.get("s_last", 0.0),
-                     r.get("s_prev", 0.0))
+                     c_upper, max_retries, precision, truncation, r.get("eta_res", 0.0),
+                     r.get("s_last", 0.0), r.get("s_prev", 0.0))
         res = Result()
         hist = (Iter * max(max_iter, 1))()
         psi = C.c_int()

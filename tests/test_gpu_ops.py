@@ -170,3 +170,26 @@ def test_invalid_arguments_return_status(ctx):
     bad = np.zeros((7, 4), np.int32)
     with pytest.raises(native.PvError):
         ctx.mps_create(bad, np.zeros(0))
+
+
+@pytest.mark.parametrize("eps,cap", [(0.0, 1000), (1e-3, 1000), (1e-1, 1000), (0.0, 7)])
+def test_round_parallel_matches_simultaneous_truncation(ctx, eps, cap):
+    # Gram-based singular values: tolerance 1e-8 relative (sqrt of machine epsilon level)
+    L, N = 10, 5
+    _setup(ctx, "dense", L, N, 0)
+    ctx.set_truncation(1)
+    try:
+        a, xa = _mps(ctx, L, N, 6, 8)
+        b, xb = _mps(ctx, L, N, 6, 9)
+        s = ctx.lincomb(1.0, a, 0.5, b)
+        x = xa + 0.5 * xb
+        r, cb = ctx.round(s, eps * np.linalg.norm(x), cap)
+        y, rho_or, cb_or, margin = tt.truncate_parallel(x, L, N, eps * np.linalg.norm(x), cap)
+        rho, yg = _dense(ctx, r)
+        assert cb == cb_or
+        if margin > 1e-5:
+            for k in range(1, L):
+                assert {n: int(rho[k, n]) for n in rho_or[k]} == rho_or[k], k
+        assert np.linalg.norm(yg - y) <= 1e-8 * np.linalg.norm(x)
+    finally:
+        ctx.set_truncation(0)

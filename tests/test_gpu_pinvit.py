@@ -58,3 +58,22 @@ def test_pinvit_decayed_capped_matches_oracle(ctx):
 
 def test_pinvit_three_particles(ctx):
     _compare(ctx, "dense", 9, 3, 2, 12, 10)
+
+
+def test_pinvit_parallel_truncation_matches_oracle(ctx):
+    # simultaneous Gram truncation: singular values from Gram matrices are accurate to
+    # about sqrt(eps) = 1.5e-8 of the largest and values below 1e-6 of the largest are
+    # numerical zeros, so decisions near that level may differ; energies agree to 1e-6
+    # relative
+    L, N, cap, iters = 8, 4, 16, 12
+    p = make_problem("dense", L, N, 0)
+    w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=2)
+    delta = w[1] / (w[1] - w[0])
+    prm = pinvit.Params(cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta, truncation="parallel")
+    _, hist_o, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    res, hist_g, _ = ctx.run(rank_cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta, truncation=1)
+    assert len(hist_g) == len(hist_o)
+    for a, b in zip(hist_g, hist_o):
+        assert abs(a["E"] - b["E"]) <= 1e-6 * abs(b["E"])
+        assert a["lam"] >= w[0] - 1e-10

@@ -118,3 +118,38 @@ def test_mps_contraction_and_amplitudes():
     mask = np.ones(1 << L, bool)
     mask[basis] = False
     assert not np.any(x[mask])
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-3])
+def test_parallel_truncation_error_bound_and_ranks(eps):
+    L, N = 9, 4
+    x = _sector_vector(L, N, 4)
+    x /= np.linalg.norm(x)
+    y, rho, cb, _ = tt.truncate_parallel(x, L, N, eps, cap=10 ** 6)
+    assert not cb
+    assert np.linalg.norm(x - y) <= eps * (1 + 1e-12)
+    r = tt.ranks(y, L, N)
+    for k in range(1, L):
+        for n, c in r[k].items():
+            assert c <= rho[k][n]
+
+
+def test_parallel_truncation_of_exact_low_rank_state_is_identity():
+    L, N = 10, 5
+    rho = rho_table(L, N, 6)
+    x = mps.to_dense(L, N, rho, random_block_mps(L, N, rho, 3))
+    y, r2, cb, _ = tt.truncate_parallel(x, L, N, 0.0, cap=1000)
+    assert np.allclose(x, y, atol=1e-12 * np.linalg.norm(x))
+
+
+def test_parallel_truncation_single_binding_bond_equals_sequential():
+    # when the cap binds at one bond only (and eps = 0), both definitions project once
+    L, N = 8, 4
+    x = _sector_vector(L, N, 5)
+    ranks_full = [sum(v.size for v in tt.singular_values(x, L, N, k).values()) for k in range(1, L)]
+    cap = max(ranks_full) - 1
+    assert sum(1 for r in ranks_full if r > cap) == 1
+    y1, r1, _, _, _ = tt.truncate(x, L, N, 0.0, cap)
+    y2, r2, _, _ = tt.truncate_parallel(x, L, N, 0.0, cap)
+    assert np.allclose(y1, y2, atol=1e-12)
+    assert r1 == r2
