@@ -169,6 +169,14 @@ pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);
 
+/* Symmetric eigenproblem on the device (the eigensolvers behind the Gram
+ * factorisations): A is n x n column-major (upper triangle read), w receives the
+ * eigenvalues descending, V (n x n) the eigenvectors.  method 0: cyclic Jacobi with
+ * relative accuracy on nearly diagonal input; 1: Householder tridiagonalisation,
+ * bisection and inverse iteration (eigenvectors of eigenvalues <= 1e-12 max|lambda|
+ * are returned as zero).  For tests. */
+pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method);
+
 /* Host-only diagnostics (no GPU needed). */
 /* Bond dimensions of the MPO of H: dims[0..L] and per-charge counts q=-2..2 in
  * qdims[(L+1)*5]. */

@@ -505,6 +505,16 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
   });
 }
 
+pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method) {
+  return guard([&] {
+    if (!ctx || !A || !w || !V) fail(PV_EINVAL, "null argument");
+    if (n < 1 || n > kEigMax) fail(PV_EINVAL, "n out of range");
+    if (method != 0 && method != 1) fail(PV_EINVAL, "method must be 0 or 1");
+    for (size_t i = 0; i < size_t(n) * n; ++i) if (!std::isfinite(A[i])) fail(PV_EINVAL, "A not finite");
+    sym_eig(ctx->c, n, A, w, V, method);
+  });
+}
+
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {

@@ -338,6 +338,7 @@ struct EigJob {
   double* w;
   double abs_tol = 1e-15;
   bool tridiag = false;  // Householder + bisection + inverse iteration (scaled path)
+  bool force = false;    // use the tridiagonal solver at any size
 };
 
 constexpr double kAbsTolGeneral = 1e-15;  // first pass / Gram eigenproblems
@@ -358,7 +359,7 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
   for (const EigJob& j : jobs) {
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
-    if (j.tridiag && j.n > kTridiagMin) {
+    if (j.tridiag && (j.n > kTridiagMin || j.force)) {
       Buf w = scratch_buf(c, size_t(6) * j.n * j.n);
       tri.push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, std::max(j.abs_tol, kVecCut)});
       c.scratch.push_back(std::move(w));
@@ -599,8 +600,11 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
   // dense charge blocks of W_k: T2[a, b', c'] += sum_b T1[a, b, c'] W[b, b'], one GEMM per c'
   const DevMpo::Site& st = op.site[k - 1];
   if (!st.dense.empty()) {
-    GemmBatch gd;
+    // several dense blocks may accumulate into one output block: the k-th contribution to
+    // each output goes to launch k, so no launch has two problems writing the same output
+    std::vector<GemmBatch> gd;
     for (const WBlock& B : blocks) {
+      int slot = 0;
       const WSrc& src = srcs[B.src];
       const int q_out = [&] {
         for (int q = -2; q <= 2; ++q)
@@ -612,12 +616,14 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
         const double* base = src.base[D.s_in][D.q_in + 2];
         if (!base) continue;
         const int64_t ld = src.ld[D.s_in][D.q_in + 2];
+        if (int(gd.size()) <= slot) gd.emplace_back();
         for (int cc = 0; cc < B.cols; ++cc)
-          gd.add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
-                 B.rows, B.wq_out, D.w_in, 1.0, 1.0);
+          gd[slot].add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
+                       B.rows, B.wq_out, D.w_in, 1.0, 1.0);
+        ++slot;
       }
     }
-    gd.run(c);
+    for (auto& g : gd) g.run(c);
   }
   c.scratch.push_back(std::move(T1));
   (void)bra_rows_prev;
@@ -792,6 +798,17 @@ double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
   auto v = env_sweep(c, bra, ket, *c.hmpo);
   return v.empty() ? 0.0 : v[0];
+}
+
+void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method) {
+  Buf A(c.pool, size_t(n) * n), V(c.pool, size_t(n) * n), w(c.pool, size_t(n));
+  PV_HIP(hipMemcpyAsync(A.p, A_host, size_t(n) * n * 8, hipMemcpyHostToDevice, c.stream));
+  std::vector<EigJob> jobs{EigJob{A.p, n, n, V.p, w.p, method == 1 ? kVecCut : kAbsTolGeneral, method == 1}};
+  jobs[0].force = method == 1;
+  run_eig(c, jobs);
+  PV_HIP(hipMemcpyAsync(w_host, w.p, size_t(n) * 8, hipMemcpyDeviceToHost, c.stream));
+  PV_HIP(hipMemcpyAsync(V_host, V.p, size_t(n) * n * 8, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
 }
 
 double norm2(Ctx& c, const Mps& x) { return std::sqrt(std::max(dot(c, x, x), 0.0)); }

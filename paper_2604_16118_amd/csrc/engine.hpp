@@ -173,5 +173,6 @@ std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m);
 double norm_canonical(Ctx& c, const Mps& x);
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
 double norm2(Ctx& c, const Mps& x);
+void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method);
 
 }  // namespace pv
