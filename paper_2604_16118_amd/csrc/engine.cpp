@@ -1316,12 +1316,16 @@ std::vector<double> gram_thresholds(Ctx& c, const Mps& x, const BondEig& e, int 
 
 // trunc_par(x; eps, cap) = P_1 P_2 ... P_{L-1} x with P_k the orthogonal projector onto the
 // kept left singular vectors of the k-th matricisation of x, every bond decided
-// independently with tolerance eps/(L-1).  With the left Gram G^L_k = V_L Lambda V_L^T and
-// the right Gram G^R_k, the singular values of the matricisation are those of
-// Z = Lambda^{1/2} V_L^T (right factor): Z Z^T = W^T G^R W with W = V_L Lambda^{1/2}.  For the
-// leading eigenvectors U_s of Z Z^T the bond matrices Lk = V_L Lambda^{-1/2} U_s and
-// Rk = U_s^T Lambda^{1/2} V_L^T satisfy A_k Lk Rk = P_k A_k, so inserting Lk Rk on every
-// bond applies all projectors; all bonds are processed in the same batched launches.
+// independently with tolerance eps/(L-1).  With the left Gram G^L_k = A_k^T A_k factored
+// as W W^T (W = V_L Lambda^{1/2} from its eigendecomposition) one has A_k = Q W^T with Q
+// orthonormal, so the singular values of the matricisation A_k B_k are the square roots
+// of the eigenvalues of M = W^T G^R W (G^R = B_k B_k^T).  For the leading eigenpairs
+// (U_s, Sigma_s^2) of M the bond matrices Lk = G^R W U_s Sigma_s^{-2} and Rk = U_s^T W^T
+// satisfy A_k Lk Rk = Q U_s U_s^T Q^T A_k = P_k A_k, so inserting Lk Rk on every bond
+// applies all projectors; all bonds are processed in the same batched launches.  Only
+// W W^T = G^L is needed (no Lambda^{-1/2}), so eigenvectors of tiny Gram eigenvalues,
+// which a tridiagonal solver determines only up to about eps ||G|| / gap, do not
+// amplify; the inverse Sigma_s^{-2} only involves kept singular values.
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
   const int L = x.L, N = x.N;
   const double delta = L > 1 ? eps / double(L - 1) : eps;
@@ -1329,8 +1333,8 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
   BondGrams GR = right_grams(c, x);
   BondEig EL = eig_grams(c, x, GL, 1, L - 1);
   auto thr = gram_thresholds(c, x, EL, 1, L - 1);
-  // W = V_L Lambda^{1/2}, Winv = V_L Lambda^{-1/2} (columns with Lambda <= thr are zero)
-  Buf W(c.pool, EL.V.n), Winv(c.pool, EL.V.n);
+  // W = V_L Lambda^{1/2} (columns with Lambda <= thr are zero)
+  Buf W(c.pool, EL.V.n);
   std::vector<double> lam = download(c, EL.w.p, EL.w.n);
   {
     // zero the dropped eigenvalues in a copy so that sqrt / inverse sqrt ignore them
@@ -1348,7 +1352,6 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
         if (EL.voff[k][n] >= 0) {
           const int r = x.rho[k][n];
           sb.add(EL.V.p + EL.voff[k][n], r, W.p + EL.voff[k][n], r, r, r, lamd.p + EL.woff[k][n], false, true);
-          sb.add(EL.V.p + EL.voff[k][n], r, Winv.p + EL.voff[k][n], r, r, r, lamd.p + EL.woff[k][n], true, true);
         }
     sb.run(c);
     c.sync();  // lam_c must stay alive until the copy ran
@@ -1395,18 +1398,21 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
     for (int n = 0; n <= N; ++n)
       if (x.valid(k, n)) rho[k][n] = keep[n];
   }
-  // bond matrices: Lk = Winv U_s (r x s), Rt = W U_s (r x s)
+  // bond matrices: Lk = (G^R W) U_s Sigma_s^{-2} (r x s), Rt = W U_s (r x s)
   Buf Lb(c.pool, EL.V.n), Rb(c.pool, EL.V.n);
   {
     GemmBatch g;
+    ScaleBatch sb;
     for (int k = 1; k < L; ++k)
       for (int n = 0; n <= N; ++n)
         if (EL.voff[k][n] >= 0 && rho[k][n] > 0) {
           const int r = x.rho[k][n], s = rho[k][n];
-          g.add(Winv.p + EL.voff[k][n], r, 0, EB.V.p + EB.voff[k][n], r, 0, Lb.p + EL.voff[k][n], r, r, s, r, 1.0, 0.0);
+          g.add(Tm.p + EL.voff[k][n], r, 0, EB.V.p + EB.voff[k][n], r, 0, Lb.p + EL.voff[k][n], r, r, s, r, 1.0, 0.0);
           g.add(W.p + EL.voff[k][n], r, 0, EB.V.p + EB.voff[k][n], r, 0, Rb.p + EL.voff[k][n], r, r, s, r, 1.0, 0.0);
+          sb.add(Lb.p + EL.voff[k][n], r, Lb.p + EL.voff[k][n], r, r, s, EB.w.p + EB.woff[k][n], true, false);
         }
     g.run(c);
+    sb.run(c);
   }
   auto y = mps_alloc(c, L, N, rho);
   // Z = [U | O] diag(L_k[n], L_k[n+1]) then new block = R_{k-1}[n] Z
@@ -1440,7 +1446,7 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
   gr.run(c);
   // k == 1 blocks are copies of Z (R_0 = 1): issue them now that Z is complete
   for (auto& b : Z) c.scratch.push_back(std::move(b));
-  for (Buf* b : {&W, &Winv, &Tm, &Lb, &Rb}) c.scratch.push_back(std::move(*b));
+  for (Buf* b : {&W, &Tm, &Lb, &Rb}) c.scratch.push_back(std::move(*b));
   c.scratch.push_back(std::move(GL.buf));
   c.scratch.push_back(std::move(GR.buf));
   c.scratch.push_back(std::move(EL.V)); c.scratch.push_back(std::move(EL.w));

@@ -393,14 +393,44 @@ __device__ void tri_solve(int n, const double* u, const double* v, const double*
   for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - v[i] * x[i + 1] - w[i] * x[i + 2]) / u[i];
 }
 
+__device__ inline double block_max(double v, double* red, int tid, int bs) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (bs + 63) / 64; ++w) t = fmax(t, red[w]);
+  return t;
+}
+
+// Off-diagonal entries at most this fraction of the largest diagonal entry: the matrix is
+// taken as diagonal (its diagonal has residual <= sqrt(n) * 1e-13 ||A||).
+constexpr double kDiagTol = 1e-13;
+// Off-diagonal entries of T at most this multiple of eps ||T|| split T into blocks.
+constexpr double kSplitTol = 4.0 * 2.220446049250313e-16;
+// Eigenvalues closer than this fraction of ||T|| form a cluster whose inverse-iteration
+// vectors are orthogonalised against each other.
+constexpr double kClusterTol = 1e-7;
+// Clusters up to this size are handled by one thread, longer ones by the workgroup.
+constexpr int kThreadCluster = 16;
+
+__device__ inline void start_vector(double* z, int n, int s, int m, int j) {
+  for (int i = 0; i < n; ++i)
+    z[i] = (i >= s && i < s + m) ? 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0 : 0.0;
+}
+
 __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double red[kTriThreads / 64];
   __shared__ double sh_beta, sh_K;
-  extern __shared__ double tsm[];  // d[n], e[n], e2[n], lam[n], beta[n], vsh[n], qsh[n]
+  __shared__ int sh_nblk, sh_nruns;
+  // d, e, e2, lam, beta, vsh, psh: n doubles each; block starts: n + 1 ints
+  extern __shared__ double tsm[];
   const EigDesc D = descs[blockIdx.x];
   const int n = D.n;
   if (n <= 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
   double* dd = tsm;
   double* ee = dd + n;
   double* e2 = ee + n;
@@ -408,15 +438,33 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
   double* betas = lam + n;
   double* vsh = betas + n;
   double* psh = vsh + n;
+  int* bstart = reinterpret_cast<int*>(psh + n);
   const int lda = n;
   double* A = D.work;                         // n x n working copy
   double* scratch = D.work + (int64_t)n * n;  // per-thread inverse-iteration storage
   double* Z = D.V;                            // eigenvectors of T, then of A
+  double od = 0.0, dg = 0.0;
   for (int e = tid; e < n * n; e += bs) {
     const int j = e / n, i = e - j * n;
-    A[e] = (i <= j) ? D.A[i + (int64_t)j * D.lda] : D.A[j + (int64_t)i * D.lda];
+    const double a = (i <= j) ? D.A[i + (int64_t)j * D.lda] : D.A[j + (int64_t)i * D.lda];
+    A[e] = a;
+    if (i == j) dg = fmax(dg, fabs(a)); else od = fmax(od, fabs(a));
   }
-  __syncthreads();
+  od = block_max(od, red, tid, bs);
+  dg = block_max(dg, red, tid, bs);
+  const bool diagonal = od <= kDiagTol * dg;
+  if (diagonal) {
+    // 0. diagonal to working accuracy: eigenpairs (a_ii, e_i)
+    for (int t = tid; t < n; t += bs) {
+      lam[t] = A[t + (int64_t)t * lda];
+      betas[t] = 0.0;
+    }
+    for (int e = tid; e < n * n; e += bs) {
+      const int j = e / n, i = e - j * n;
+      Z[e] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+  } else {
   // 1. tridiagonalisation
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
@@ -448,24 +496,21 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     // p = beta A22 v, A22 = A[k+1:, k+1:]; A22 is symmetric, so p_i is the dot product of
     // column i with v: one wavefront per column, lanes along the contiguous column
     const double* A22 = A + (k + 1) + (int64_t)(k + 1) * lda;
-    {
-      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-      for (int i0 = wave; i0 < m; i0 += 2 * nw) {
-        const int i1 = i0 + nw;
-        const double* c0 = A22 + (int64_t)i0 * lda;
-        const double* c1 = A22 + (int64_t)(i1 < m ? i1 : i0) * lda;
-        double a0 = 0.0, a1 = 0.0;
-        for (int j = lane; j < m; j += 64) {
-          const double vj = vsh[j];
-          a0 += c0[j] * vj;
-          a1 += c1[j] * vj;
-        }
-        a0 = wave_sum_d(a0);
-        a1 = wave_sum_d(a1);
-        if (lane == 0) {
-          psh[i0] = beta * a0;
-          if (i1 < m) psh[i1] = beta * a1;
-        }
+    for (int i0 = wave; i0 < m; i0 += 2 * nw) {
+      const int i1 = i0 + nw;
+      const double* c0 = A22 + (int64_t)i0 * lda;
+      const double* c1 = A22 + (int64_t)(i1 < m ? i1 : i0) * lda;
+      double a0 = 0.0, a1 = 0.0;
+      for (int j = lane; j < m; j += 64) {
+        const double vj = vsh[j];
+        a0 += c0[j] * vj;
+        a1 += c1[j] * vj;
+      }
+      a0 = wave_sum_d(a0);
+      a1 = wave_sum_d(a1);
+      if (lane == 0) {
+        psh[i0] = beta * a0;
+        if (i1 < m) psh[i1] = beta * a1;
       }
     }
     __syncthreads();
@@ -478,13 +523,10 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     for (int i = tid; i < m; i += bs) psh[i] -= K * vsh[i];  // q
     __syncthreads();
     double* A22w = A + (k + 1) + (int64_t)(k + 1) * lda;
-    {
-      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-      for (int j = wave; j < m; j += nw) {
-        const double vj = vsh[j], qj = psh[j];
-        double* col = A22w + (int64_t)j * lda;
-        for (int i = lane; i < m; i += 64) col[i] -= vsh[i] * qj + psh[i] * vj;
-      }
+    for (int j = wave; j < m; j += nw) {
+      const double vj = vsh[j], qj = psh[j];
+      double* col = A22w + (int64_t)j * lda;
+      for (int i = lane; i < m; i += 64) col[i] -= vsh[i] * qj + psh[i] * vj;
     }
     __syncthreads();
   }
@@ -499,45 +541,69 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     betas[n - 1] = 0.0;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += bs) e2[i] = ee[i] * ee[i];
-  // Gershgorin bounds and the norm of T
-  double lo = 1e300, hi = -1e300, tn = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
-    lo = fmin(lo, dd[i] - r);
-    hi = fmax(hi, dd[i] + r);
-  }
-  tn = fmax(fabs(lo), fabs(hi));
-  const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
+  // Gershgorin bound of ||T||; negligible off-diagonals split T into unreduced blocks
+  double tn = 0.0;
+  for (int i = 0; i < n; ++i)
+    tn = fmax(tn, fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0));
   __syncthreads();
-  // 2. bisection: thread t -> t-th smallest eigenvalue
+  if (tid == 0) {
+    int nb = 0;
+    bstart[nb++] = 0;
+    for (int i = 0; i + 1 < n; ++i)
+      if (fabs(ee[i]) <= kSplitTol * tn) {
+        ee[i] = 0.0;
+        bstart[nb++] = i + 1;
+      }
+    bstart[nb] = n;
+    sh_nblk = nb;
+  }
+  __syncthreads();
+  const int nblk = sh_nblk;
+  for (int i = tid; i < n; i += bs) e2[i] = ee[i] * ee[i];
+  __syncthreads();
+  const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
+  // 2. bisection: position t of block b = [s, s+m) holds the (t-s)-th smallest eigenvalue
+  //    of that block, so eigenvalues ascend within each block
   for (int t = tid; t < n; t += bs) {
+    int lo_b = 0, hi_b = nblk - 1;
+    while (lo_b < hi_b) {
+      const int mid = (lo_b + hi_b + 1) >> 1;
+      if (bstart[mid] <= t) lo_b = mid; else hi_b = mid - 1;
+    }
+    const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
+    if (m == 1) { lam[t] = dd[s]; continue; }
+    double lo = 1e300, hi = -1e300;
+    for (int i = s; i < s + m; ++i) {
+      const double r = (i > s ? fabs(ee[i - 1]) : 0.0) + (i < s + m - 1 ? fabs(ee[i]) : 0.0);
+      lo = fmin(lo, dd[i] - r);
+      hi = fmax(hi, dd[i] + r);
+    }
     double a = lo - 1e-14 * tn - 1e-300, b = hi + 1e-14 * tn + 1e-300;
     for (int it = 0; it < 100; ++it) {
       const double mid = 0.5 * (a + b);
       if (mid <= a || mid >= b) break;
-      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0) break;
-      if (sturm_count(dd, e2, n, mid, tiny + 1e-300) > t) b = mid; else a = mid;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0 || b - a <= 1e-18 * tn) break;
+      if (sturm_count(dd + s, e2 + s, m, mid, tiny + 1e-300) > t - s) b = mid; else a = mid;
     }
     lam[t] = 0.5 * (a + b);
   }
   __syncthreads();
-  // 3. inverse iteration, one thread per cluster (clusters of near-equal eigenvalues)
+  // 3. inverse iteration within each block; vectors vanish outside their block
   double lmax = 0.0;
   for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
   const double cut = D.abs_tol * lmax;
-  const double ctol = 1e-7 * fmax(tn, 1e-300);
+  const double ctol = kClusterTol * fmax(tn, 1e-300);
   for (int t = tid; t < n; t += bs) {
-    // cluster starts: a gap above ctol, or every 16th member of a long run of close values
-    bool start = (t == 0) || (lam[t] - lam[t - 1] > ctol);
-    if (!start) {
-      int r = t;
-      while (r > 0 && lam[r] - lam[r - 1] <= ctol) --r;
-      start = ((t - r) % 16) == 0;
+    int lo_b = 0, hi_b = nblk - 1;
+    while (lo_b < hi_b) {
+      const int mid = (lo_b + hi_b + 1) >> 1;
+      if (bstart[mid] <= t) lo_b = mid; else hi_b = mid - 1;
     }
-    if (!start) continue;
+    const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
+    if (!(t == s || lam[t] - lam[t - 1] > ctol)) continue;  // not the first of its cluster
     int last = t;
-    while (last + 1 < n && lam[last + 1] - lam[last] <= ctol && last + 1 - t < 16) ++last;
+    while (last + 1 < s + m && lam[last + 1] - lam[last] <= ctol) ++last;
+    if (last + 1 - t > kThreadCluster) continue;  // long cluster: workgroup pass below
     double* u = scratch + (int64_t)t * 5 * n;
     double* v = u + n;
     double* w = v + n;
@@ -549,21 +615,98 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
         for (int i = 0; i < n; ++i) z[i] = 0.0;
         continue;
       }
+      if (m == 1) {
+        for (int i = 0; i < n; ++i) z[i] = i == s ? 1.0 : 0.0;
+        continue;
+      }
       const double sigma = lam[j] + (j - t) * 10.0 * 2.2e-16 * tn;
-      tri_factor(dd, ee, n, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv);
-      for (int i = 0; i < n; ++i) z[i] = 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0;
+      tri_factor(dd + s, ee + s, m, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv);
+      start_vector(z, n, s, m, j);
       for (int it = 0; it < 3; ++it) {
-        tri_solve(n, u, v, w, mult, piv, z);
+        tri_solve(m, u, v, w, mult, piv, z + s);
         for (int jj = t; jj < j; ++jj) {
           const double* y = Z + (int64_t)jj * n;
           double dot = 0.0;
-          for (int i = 0; i < n; ++i) dot += y[i] * z[i];
-          for (int i = 0; i < n; ++i) z[i] -= dot * y[i];
+          for (int i = s; i < s + m; ++i) dot += y[i] * z[i];
+          for (int i = s; i < s + m; ++i) z[i] -= dot * y[i];
         }
         double nn = 0.0;
-        for (int i = 0; i < n; ++i) nn += z[i] * z[i];
+        for (int i = s; i < s + m; ++i) nn += z[i] * z[i];
         nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = 0; i < n; ++i) z[i] *= nn;
+        for (int i = s; i < s + m; ++i) z[i] *= nn;
+      }
+    }
+  }
+  __syncthreads();
+  // long clusters: list (first, last, block) in e2, which is free after bisection
+  if (tid == 0) {
+    int nr = 0;
+    for (int b = 0; b < nblk; ++b) {
+      const int s = bstart[b], e = bstart[b + 1];
+      int t = s;
+      while (t < e) {
+        int last = t;
+        while (last + 1 < e && lam[last + 1] - lam[last] <= ctol) ++last;
+        if (last + 1 - t > kThreadCluster) {
+          e2[3 * nr] = t; e2[3 * nr + 1] = last; e2[3 * nr + 2] = b;
+          ++nr;
+        }
+        t = last + 1;
+      }
+    }
+    sh_nruns = nr;
+  }
+  __syncthreads();
+  const int nruns = sh_nruns;
+  for (int q = 0; q < nruns; ++q) {
+    const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
+    const int s = bstart[b], m = bstart[b + 1] - s;
+    double* u = scratch;
+    double* v = u + n;
+    double* w = v + n;
+    double* mult = w + n;
+    unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
+    for (int j = r0; j <= r1; ++j) {
+      double* z = Z + (int64_t)j * n;
+      if (fabs(lam[j]) <= cut) {
+        for (int i = tid; i < n; i += bs) z[i] = 0.0;
+        __syncthreads();
+        continue;
+      }
+      for (int i = tid; i < n; i += bs)
+        z[i] = (i >= s && i < s + m) ? 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0 : 0.0;
+      __syncthreads();
+      for (int it = 0; it < 3; ++it) {
+        if (tid == 0) {
+          if (it == 0)
+            tri_factor(dd + s, ee + s, m, lam[j] + (j - r0) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v, w,
+                       mult, piv);
+          tri_solve(m, u, v, w, mult, piv, z + s);
+        }
+        __syncthreads();
+        // classical Gram-Schmidt against the earlier members, twice
+        for (int pass = 0; pass < 2 && j > r0; ++pass) {
+          for (int jj = r0 + wave; jj < j; jj += nw) {
+            const double* y = Z + (int64_t)jj * n;
+            double dot = 0.0;
+            for (int i = s + lane; i < s + m; i += 64) dot += y[i] * z[i];
+            dot = wave_sum_d(dot);
+            if (lane == 0) psh[jj - r0] = dot;
+          }
+          __syncthreads();
+          for (int i = s + tid; i < s + m; i += bs) {
+            double acc = 0.0;
+            for (int jj = r0; jj < j; ++jj) acc += psh[jj - r0] * Z[i + (int64_t)jj * n];
+            z[i] -= acc;
+          }
+          __syncthreads();
+        }
+        double part = 0.0;
+        for (int i = s + tid; i < s + m; i += bs) part += z[i] * z[i];
+        const double nn2 = block_sum(part, red, tid, bs);
+        const double sc = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
+        for (int i = s + tid; i < s + m; i += bs) z[i] *= sc;
+        __syncthreads();
       }
     }
   }
@@ -576,37 +719,45 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     const double* vk = A + (k + 1) + (int64_t)k * lda;
     for (int i = tid; i < m; i += bs) vsh[i] = vk[i];
     __syncthreads();
-    {
-      const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-      for (int c = wave; c < n; c += nw) {
-        double* zc = Z + (int64_t)c * n + (k + 1);
-        double dot = 0.0;
-        for (int i = lane; i < m; i += 64) dot += vsh[i] * zc[i];
-        dot = beta * wave_sum_d(dot);
-        if (dot != 0.0)
-          for (int i = lane; i < m; i += 64) zc[i] -= dot * vsh[i];
-      }
+    for (int c = wave; c < n; c += nw) {
+      double* zc = Z + (int64_t)c * n + (k + 1);
+      double dot = 0.0;
+      for (int i = lane; i < m; i += 64) dot += vsh[i] * zc[i];
+      dot = beta * wave_sum_d(dot);
+      if (dot != 0.0)
+        for (int i = lane; i < m; i += 64) zc[i] -= dot * vsh[i];
     }
     __syncthreads();
   }
-  // descending order: eigenvalue t (ascending) goes to position n-1-t; columns reversed
-  for (int t = tid; t < n; t += bs) D.w[n - 1 - t] = lam[t];
-  __syncthreads();
-  for (int e = tid; e < (n / 2) * n; e += bs) {
-    const int c = e / n, i = e - c * n;
-    double* a = Z + (int64_t)c * n + i;
-    double* b = Z + (int64_t)(n - 1 - c) * n + i;
-    const double ta = *a;
-    *a = *b;
-    *b = ta;
+  }  // !diagonal
+  // eigenvalues at or below the cut carry zero vectors
+  double lmx = 0.0;
+  for (int i = 0; i < n; ++i) lmx = fmax(lmx, fabs(lam[i]));
+  const double vcut = D.abs_tol * lmx;
+  // 5. descending order (ties: lower position first); Z goes through the working copy
+  for (int e = tid; e < n * n; e += bs) {
+    const int c = e / n;
+    A[e] = fabs(lam[c]) <= vcut ? 0.0 : Z[e];
   }
-  if (tid == 0 && D.sweeps) *D.sweeps = -1;
+  for (int t = tid; t < n; t += bs) {
+    int rank = 0;
+    const double lt = lam[t];
+    for (int u = 0; u < n; ++u) rank += (lam[u] > lt) || (lam[u] == lt && u < t);
+    e2[t] = rank;
+  }
+  __syncthreads();
+  for (int t = tid; t < n; t += bs) D.w[int(e2[t])] = lam[t];
+  for (int e = tid; e < n * n; e += bs) {
+    const int c = e / n, i = e - c * n;
+    Z[i + (int64_t)int(e2[c]) * n] = A[e];
+  }
+  if (tid == 0 && D.sweeps) *D.sweeps = diagonal ? 0 : -1;
 }
 
 void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
-  const size_t shm = size_t(nmax) * 7 * sizeof(double);
+  const size_t shm = size_t(nmax) * 7 * sizeof(double) + size_t(nmax + 1) * sizeof(int);
   const int threads = nmax <= 64 ? 256 : kTriThreads;
   hipLaunchKernelGGL(tridiag_eig_kernel, dim3(nprob), dim3(threads), shm, s, d);
   PV_LAUNCH_CHECK();
