@@ -3,9 +3,10 @@
 A step is one iteration of Algorithm 2 (Rayleigh quotient, H psi by the site-by-site
 MPO application, residual truncation, two sorted preconditioner sums, the 2x2 Ritz step
 and the truncated update) on the L=48, N=24 decayed-integral Hamiltonian with rank cap
-512, all in float64.  Warmup iterations grow the ranks from the starting determinant to
-the cap; then exactly `--steps` iterations are timed (one pv_run call bracketed by
-stream synchronisations, the iteration state carried over from the warmup).
+512 and zip-up cap 512, all in float64, with the simultaneous (Gram) truncation.  Warmup
+iterations grow the ranks from the starting determinant to the cap; then exactly
+`--steps` iterations are timed (one pv_run call bracketed by stream synchronisations, the
+iteration state carried over from the warmup).
 
 Prints one JSON line; the dominant kernel's roofline comes from the library's HIP-event
 timers over the timed region.
@@ -13,6 +14,7 @@ timers over the timed region.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -26,6 +28,60 @@ PEAK = {  # MI355X published peaks
     "fp64_vector_tflops": 78.6,
     "hbm_gbs": 8000.0,
 }
+# library timer class -> (HIP kernel, roofline bound)
+KERNELS = {
+    "gemm_f64_mfma": ("gemm_f64_kernel", "mfma"),
+    "tridiag_eig_f64": ("tridiag_eig_kernel", "alu"),
+    "jacobi_eig_f64": ("jacobi_eig_kernel", "alu"),
+    "mpo_wstep": ("wstep_kernel", "hbm"),
+    "copy_scale": ("copy_kernel/scale_kernel", "hbm"),
+    "reduce": ("reduce_kernel", "hbm"),
+}
+
+
+TIMED_RANGE = "pinvit_timed"
+
+
+def _roctx():
+    """roctx range markers (seen by rocprofv3 --marker-trace); None when unavailable."""
+    for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"):
+        try:
+            lib = ctypes.CDLL(name)
+            lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            return lib
+        except OSError:
+            continue
+    return None
+
+
+def summarize(db: str) -> str:
+    """Per-kernel statistics from a rocprofv3 database: the whole run and the dispatches
+    that started inside the timed roctx range."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    rng = cur.execute("select start, end from regions where name = ?", (TIMED_RANGE,)).fetchall()
+    out = []
+    windows = [("whole run", None)] + [(f"timed range '{TIMED_RANGE}'", r) for r in rng[:1]]
+    for title, r in windows:
+        q = "select name, count(*), sum(duration), avg(duration) from kernels"
+        args = ()
+        if r is not None:
+            q += " where start >= ? and start <= ?"
+            args = r
+        q += " group by name order by sum(duration) desc"
+        rows = cur.execute(q, args).fetchall()
+        tot = sum(x[2] for x in rows) or 1
+        out.append(f"### {title}\n")
+        if r is not None:
+            out.append(f"wall {1e-9 * (r[1] - r[0]):.3f} s\n")
+        out.append("| kernel | calls | total ms | avg us | % |\n|---|---:|---:|---:|---:|")
+        for name, n, d, a in rows:
+            short = name.split("(")[0]
+            out.append(f"| {short} | {n} | {1e-6 * d:.1f} | {1e-3 * a:.1f} | {100.0 * d / tot:.1f} |")
+        out.append("")
+    return "\n".join(out)
 
 
 def cpu_baseline(target_seconds: float = 15.0):
@@ -47,7 +103,7 @@ def cpu_baseline(target_seconds: float = 15.0):
     iters = 0
     n = 2
     while True:
-        prm = pinvit.Params(cap=cap, max_iter=n, tau=0.0, c=0.5, delta=10.0)
+        prm = pinvit.Params(cap=cap, max_iter=n, tau=0.0, c=0.5, delta=10.0, truncation="parallel")
         t1 = time.perf_counter()
         _, hist, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
         dt = time.perf_counter() - t1
@@ -70,7 +126,11 @@ def main():
     ap.add_argument("--cap", type=int, default=512)
     ap.add_argument("--m-zip", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
     a = ap.parse_args()
+    if a.summarize:
+        print(summarize(a.summarize))
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -83,24 +143,30 @@ def main():
     t = time.perf_counter()
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
     print(f"# setup {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip)
+    common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
     t = time.perf_counter()
     res_w, hist_w, psi = ctx.run(max_iter=a.warmup, **common)
     print(f"# warmup {a.warmup} it {time.perf_counter() - t:.1f}s ranks {[r['max_rank'] for r in hist_w]}",
           file=sys.stderr, flush=True)
     ctx.timers_reset()
+    rtx = _roctx()
+    if rtx:
+        rtx.roctxRangePushA(TIMED_RANGE.encode())
     t0 = time.perf_counter()
     res, hist, psi2 = ctx.run(max_iter=a.steps, start=psi, resume=res_w, **common)
     t1 = time.perf_counter()
+    if rtx:
+        rtx.roctxRangePop()
     tm = ctx.timers()
     elapsed = t1 - t0
     steps = len(hist)
     # dominant kernel class over the timed region
     dom_name, dom = max(tm.items(), key=lambda kv: kv[1]["ms"])
-    if dom_name.startswith("gemm"):
+    kernel, bound = KERNELS[dom_name]
+    if bound == "mfma":
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s"}
-    elif dom_name.startswith("jacobi"):
+    elif bound == "alu":
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp64_vector_tflops"], "unit": "TFLOP/s"}
     else:
@@ -108,7 +174,8 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = dom_name
+    roof["kernel"] = kernel
+    roof["launches"] = dom["calls"]
     roof["avg_launch_ms"] = dom["ms"] / max(dom["calls"], 1)
     g = tm["gemm_f64_mfma"]
     out = {

@@ -163,8 +163,10 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
                  pv_iter* hist, int hist_cap, int* psi);
 
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
- * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk), bytes[i] =
- * algorithmic bytes, for i < n classes; names via pv_timer_name. */
+ * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
+ * 10/3 n^3 each), bytes[i] = algorithmic bytes, for i < n classes (six classes: grouped
+ * GEMM, Jacobi eigensolver, MPO W-step, copy/scale, reduction, tridiagonal eigensolver);
+ * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);

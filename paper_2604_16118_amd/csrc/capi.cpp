@@ -515,7 +515,8 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
   });
 }
 
-static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce"};
+static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
+                                            "tridiag_eig_f64"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

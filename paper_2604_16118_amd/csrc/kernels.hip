@@ -407,13 +407,26 @@ __device__ inline double block_max(double v, double* red, int tid, int bs) {
 // Off-diagonal entries at most this fraction of the largest diagonal entry: the matrix is
 // taken as diagonal (its diagonal has residual <= sqrt(n) * 1e-13 ||A||).
 constexpr double kDiagTol = 1e-13;
+// A spectrum inside the disc |lambda - mu| <= kShiftTol |mu| (mu the mean diagonal entry,
+// radius by Gershgorin) is computed as mu + eig(A - mu I): a Gram matrix of nearly
+// orthonormal vectors then becomes an ordinary problem instead of one huge cluster.
+constexpr double kShiftTol = 1e-3;
 // Off-diagonal entries of T at most this multiple of eps ||T|| split T into blocks.
 constexpr double kSplitTol = 4.0 * 2.220446049250313e-16;
-// Eigenvalues closer than this fraction of ||T|| form a cluster whose inverse-iteration
-// vectors are orthogonalised against each other.
+// Neighbouring eigenvalues (both above the zero cut) closer than
+// min(kClusterTol ||T||, kClusterRel max|lambda|) form a cluster whose inverse-iteration
+// vectors are orthogonalised against each other.  Outside clusters a vector is accurate to
+// about eps ||T|| / gap: orthogonal to ~1e-9 where |lambda| >= 1e-5 ||T||, and in the graded
+// tail only as far as eps ||T|| / (0.01 |lambda|), which weighted by sqrt(|lambda|) (as in
+// a Gram factor V Lambda^{1/2}) stays below ~1e-9 ||T||.
 constexpr double kClusterTol = 1e-7;
+constexpr double kClusterRel = 1e-2;
 // Clusters up to this size are handled by one thread, longer ones by the workgroup.
 constexpr int kThreadCluster = 16;
+
+__device__ inline bool linked(double a, double b, double cut, double ctol) {
+  return fabs(a) > cut && fabs(b) > cut && b - a <= fmin(ctol, kClusterRel * fmax(fabs(a), fabs(b)));
+}
 
 __device__ inline void start_vector(double* z, int n, int s, int m, int j) {
   for (int i = 0; i < n; ++i)
@@ -465,6 +478,20 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     }
     __syncthreads();
   } else {
+  double dsum = 0.0;
+  for (int t = tid; t < n; t += bs) dsum += A[t + (int64_t)t * lda];
+  const double mu = block_sum(dsum, red, tid, bs) / n;
+  double rad = 0.0;
+  for (int j = tid; j < n; j += bs) {
+    double r = fabs(A[j + (int64_t)j * lda] - mu);
+    for (int i = 0; i < n; ++i) r += i == j ? 0.0 : fabs(A[i + (int64_t)j * lda]);
+    rad = fmax(rad, r);
+  }
+  rad = block_max(rad, red, tid, bs);
+  const double shift = rad <= kShiftTol * fabs(mu) ? mu : 0.0;
+  if (shift != 0.0)
+    for (int t = tid; t < n; t += bs) A[t + (int64_t)t * lda] -= shift;
+  __syncthreads();
   // 1. tridiagonalisation
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
@@ -591,7 +618,8 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
   // 3. inverse iteration within each block; vectors vanish outside their block
   double lmax = 0.0;
   for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
-  const double cut = D.abs_tol * lmax;
+  // with a shift every |eigenvalue| of A is at least (1 - kShiftTol) |mu|: nothing is cut
+  const double cut = shift != 0.0 ? 0.0 : D.abs_tol * lmax;
   const double ctol = kClusterTol * fmax(tn, 1e-300);
   for (int t = tid; t < n; t += bs) {
     int lo_b = 0, hi_b = nblk - 1;
@@ -600,9 +628,9 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
       if (bstart[mid] <= t) lo_b = mid; else hi_b = mid - 1;
     }
     const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
-    if (!(t == s || lam[t] - lam[t - 1] > ctol)) continue;  // not the first of its cluster
+    if (t > s && linked(lam[t - 1], lam[t], cut, ctol)) continue;  // not the first of its cluster
     int last = t;
-    while (last + 1 < s + m && lam[last + 1] - lam[last] <= ctol) ++last;
+    while (last + 1 < s + m && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
     if (last + 1 - t > kThreadCluster) continue;  // long cluster: workgroup pass below
     double* u = scratch + (int64_t)t * 5 * n;
     double* v = u + n;
@@ -638,7 +666,10 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     }
   }
   __syncthreads();
-  // long clusters: list (first, last, block) in e2, which is free after bisection
+  // long clusters: (first, last, block) listed in e2 (free after bisection), members
+  // flagged in vsh (free until the back-transformation)
+  for (int i = tid; i < n; i += bs) vsh[i] = 0.0;
+  __syncthreads();
   if (tid == 0) {
     int nr = 0;
     for (int b = 0; b < nblk; ++b) {
@@ -646,9 +677,10 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
       int t = s;
       while (t < e) {
         int last = t;
-        while (last + 1 < e && lam[last + 1] - lam[last] <= ctol) ++last;
+        while (last + 1 < e && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
         if (last + 1 - t > kThreadCluster) {
           e2[3 * nr] = t; e2[3 * nr + 1] = last; e2[3 * nr + 2] = b;
+          for (int q = t; q <= last; ++q) vsh[q] = 1.0;
           ++nr;
         }
         t = last + 1;
@@ -658,33 +690,40 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
   }
   __syncthreads();
   const int nruns = sh_nruns;
-  for (int q = 0; q < nruns; ++q) {
-    const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
-    const int s = bstart[b], m = bstart[b + 1] - s;
-    double* u = scratch;
-    double* v = u + n;
-    double* w = v + n;
-    double* mult = w + n;
-    unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
-    for (int j = r0; j <= r1; ++j) {
-      double* z = Z + (int64_t)j * n;
-      if (fabs(lam[j]) <= cut) {
-        for (int i = tid; i < n; i += bs) z[i] = 0.0;
-        __syncthreads();
-        continue;
+  // simultaneous inverse iteration: every member solves with its own shift in parallel,
+  // then each cluster is orthonormalised by the workgroup (classical Gram-Schmidt, twice)
+  for (int it = 0; it < 3 && nruns > 0; ++it) {
+    for (int p = tid; p < n; p += bs) {
+      if (vsh[p] == 0.0) continue;
+      int lo_b = 0, hi_b = nblk - 1;
+      while (lo_b < hi_b) {
+        const int mid = (lo_b + hi_b + 1) >> 1;
+        if (bstart[mid] <= p) lo_b = mid; else hi_b = mid - 1;
       }
-      for (int i = tid; i < n; i += bs)
-        z[i] = (i >= s && i < s + m) ? 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0 : 0.0;
-      __syncthreads();
-      for (int it = 0; it < 3; ++it) {
-        if (tid == 0) {
-          if (it == 0)
-            tri_factor(dd + s, ee + s, m, lam[j] + (j - r0) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v, w,
-                       mult, piv);
-          tri_solve(m, u, v, w, mult, piv, z + s);
-        }
-        __syncthreads();
-        // classical Gram-Schmidt against the earlier members, twice
+      const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
+      double* u = scratch + (int64_t)p * 5 * n;
+      double* v = u + n;
+      double* w = v + n;
+      double* mult = w + n;
+      unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
+      double* z = Z + (int64_t)p * n;
+      if (it == 0) {
+        tri_factor(dd + s, ee + s, m, lam[p] + (p - s) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v, w, mult,
+                   piv);
+        start_vector(z, n, s, m, p);
+      }
+      tri_solve(m, u, v, w, mult, piv, z + s);
+      double nn = 0.0;
+      for (int i = s; i < s + m; ++i) nn += z[i] * z[i];
+      nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = s; i < s + m; ++i) z[i] *= nn;
+    }
+    __syncthreads();
+    for (int q = 0; q < nruns; ++q) {
+      const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
+      const int s = bstart[b], m = bstart[b + 1] - s;
+      for (int j = r0; j <= r1; ++j) {
+        double* z = Z + (int64_t)j * n;
         for (int pass = 0; pass < 2 && j > r0; ++pass) {
           for (int jj = r0 + wave; jj < j; jj += nw) {
             const double* y = Z + (int64_t)jj * n;
@@ -729,6 +768,8 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     }
     __syncthreads();
   }
+  for (int t = tid; t < n; t += bs) lam[t] += shift;
+  __syncthreads();
   }  // !diagonal
   // eigenvalues at or below the cut carry zero vectors
   double lmx = 0.0;

@@ -265,7 +265,7 @@ class Context:
         return w, V
 
     def timers(self):
-        n = 5
+        n = 6
         ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
         calls = np.zeros(n, np.int32)
         _check(lib().pv_timers(self._p, n, _dp(ms), _dp(fl), _dp(by), _ip(calls)))

@@ -55,6 +55,10 @@ CASES = {
     "degenerate": lambda n, rng: _spectrum(np.repeat(np.arange(1, 1 + (n + 2) // 3), 3)[:n].astype(float), n, rng),
     "cluster": lambda n, rng: _spectrum(np.concatenate([1 + 1e-11 * np.arange(n // 2), np.linspace(2, 3, n - n // 2)]), n, rng),
     "blockdiag": _block_diag,
+    # Gram matrices of nearly orthonormal vectors: identity plus 1e-12 noise, and a
+    # narrow band about 5 (spread 1e-6)
+    "near_identity": lambda n, rng: np.eye(n) + 1e-12 * _rand_sym(n, rng),
+    "narrow_band": lambda n, rng: 5 * np.eye(n) + 1e-6 * _rand_sym(n, rng),
 }
 
 
@@ -71,11 +75,12 @@ def _cluster_width(wr, tol):
 
 def _check(A, w, V, method):
     """Jacobi (method 0): eigenpairs to working accuracy, V orthogonal to 1e-10.
-    Tridiagonal (method 1): inverse-iteration vectors resolve eigenvalue gaps down to
-    1e-7 ||A||, so orthogonality is about eps ||A|| / 1e-7 (tolerance 5e-8); inside a
-    chain of eigenvalues closer than that the vectors span the chain's invariant subspace,
-    so the residual is bounded by the chain's width; eigenvalues at or below
-    1e-12 max |lambda| carry zero vectors."""
+    Tridiagonal (method 1): inverse iteration resolves a gap g_j = min(1e-7 ||A||,
+    0.01 |lambda_j|) to each neighbour, so |v_i^T v_j| is about eps ||A|| / min(g_i, g_j)
+    (tolerance 100 eps ||A|| / min(g_i, g_j)); vectors of closer eigenvalues are
+    orthogonalised against each other and span their chain's invariant subspace, so the
+    residual is bounded by the chain's width; V Lambda V^T reproduces A to 1e-10 ||A||;
+    eigenvalues at or below 1e-12 max |lambda| carry zero vectors."""
     n = A.shape[0]
     wr = np.linalg.eigvalsh(A)[::-1]
     an = max(np.abs(wr).max(), 1e-300)
@@ -84,17 +89,21 @@ def _check(A, w, V, method):
     assert np.abs(w - wr).max() <= 1e-12 * an * sz
     if method == 0:
         keep = np.arange(n)
-        res_tol, orth_tol = 1e-11 * an * sz, 1e-10 * sz
+        res_tol = 1e-11 * an * sz
+        orth_tol = np.full((n, n), 1e-10 * sz)
     else:
         keep = np.nonzero(np.abs(w) > 1e-12 * an)[0]
         for j in np.setdiff1d(np.arange(n), keep):
             assert np.linalg.norm(V[:, j]) == 0.0
         res_tol = 1e-11 * an * sz + _cluster_width(wr, 1e-7 * an)
-        orth_tol = 5e-8
+        g = np.minimum(1e-7 * an, 1e-2 * np.abs(w[keep]))
+        orth_tol = 100 * 2.2e-16 * an / np.minimum.outer(g, g) + 1e-10 * sz
+        recon = (V[:, keep] * w[keep]) @ V[:, keep].T
+        assert np.abs(recon - A).max() <= 1e-10 * an * sz
     Vk = V[:, keep]
     res = A @ Vk - Vk * w[keep]
     assert np.abs(res).max() <= res_tol
-    assert np.abs(Vk.T @ Vk - np.eye(len(keep))).max() <= orth_tol
+    assert np.all(np.abs(Vk.T @ Vk - np.eye(len(keep))) <= orth_tol)
 
 
 @pytest.mark.parametrize("method", [0, 1])
