@@ -364,7 +364,7 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
     if (j.tridiag && (j.n > kTridiagMin || j.force)) {
-      Buf w = scratch_buf(c, size_t(6) * j.n * j.n);
+      Buf w = scratch_buf(c, tri_work_doubles(j.n));
       tri.push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, std::max(j.abs_tol, kVecCut)});
       c.scratch.push_back(std::move(w));
       ntri = std::max(ntri, j.n);

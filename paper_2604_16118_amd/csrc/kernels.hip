@@ -14,6 +14,15 @@ namespace pv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Pointers read from descriptors are generic to the compiler, which then emits FLAT memory
+// instructions; those count against the LDS wait counter as well, so every wait for an LDS
+// read would also wait for outstanding global loads and stores.  Kernels therefore cast
+// descriptor pointers into the global address space.
+#define PV_GLOBAL __attribute__((address_space(1)))
+typedef PV_GLOBAL double gdouble;
+typedef PV_GLOBAL const double gcdouble;
+template <class T> __device__ inline PV_GLOBAL T* gbl(T* p) { return (PV_GLOBAL T*)p; }
+
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -45,6 +54,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
     if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
   }
   const GemmDesc g = descs[lo];
+  gcdouble* gA = gbl(g.A);
+  gcdouble* gB = gbl(g.B);
+  gdouble* gC = gbl(g.C);
   const int t = tile - g.tile0;
   const int row0 = (t / g.tiles_n) * BM, col0 = (t % g.tiles_n) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -61,7 +73,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
       const int gi = row0 + i, gk = k0 + k;
       double v = 0.0;
       if (gi < g.M && gk < g.kend)
-        v = g.ta ? g.A[gk + (int64_t)gi * g.lda] : g.A[gi + (int64_t)gk * g.lda];
+        v = g.ta ? gA[gk + (int64_t)gi * g.lda] : gA[gi + (int64_t)gk * g.lda];
       As[k][i] = v;
     }
     for (int e = tid; e < BN * BK; e += 256) {
@@ -70,7 +82,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
       const int gj = col0 + j, gk = k0 + k;
       double v = 0.0;
       if (gj < g.N && gk < g.kend)
-        v = g.tb ? g.B[gj + (int64_t)gk * g.ldb] : g.B[gk + (int64_t)gj * g.ldb];
+        v = g.tb ? gB[gj + (int64_t)gk * g.ldb] : gB[gk + (int64_t)gj * g.ldb];
       Bs[k][j] = v;
     }
     __syncthreads();
@@ -94,7 +106,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
         const int j = col0 + wc * 32 + nj * 16 + li;
         if (i < g.M && j < g.N) {
           double v = g.alpha * acc[mi][nj][r];
-          double* c = g.C + i + (int64_t)j * g.ldc;
+          gdouble* c = gC + i + (int64_t)j * g.ldc;
           if (g.beta != 0.0) v += g.beta * *c;
           *c = v;
         }
@@ -120,8 +132,9 @@ __global__ void reduce_kernel(const ReduceDesc* __restrict__ d, int nd, int64_t 
   const int i = int(x % r.M), j = int(x / r.M);
   const int64_t mn = (int64_t)r.M * r.N;
   double acc = 0.0;
-  for (int s = 0; s < r.S; ++s) acc += r.P[s * mn + x];
-  double* c = r.C + i + (int64_t)j * r.ldc;
+  gcdouble* P = gbl(r.P);
+  for (int s = 0; s < r.S; ++s) acc += P[s * mn + x];
+  gdouble* c = gbl(r.C) + i + (int64_t)j * r.ldc;
   double v = r.alpha * acc;
   if (r.beta != 0.0) v += r.beta * *c;
   *c = v;
@@ -316,10 +329,15 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(const EigDesc* __restr
 //     three iterations, members of a cluster (gap <= 1e-7 ||T||) orthogonalised against
 //     each other by modified Gram-Schmidt; eigenvalues <= vec_cut * max |lambda| get a
 //     zero vector (the callers drop them);
-//  4. back-transformation V = H_0 H_1 ... H_{n-3} Z.
-// Output as the Jacobi kernel: eigenvalues descending, eigenvectors in the columns of V.
+//  4. back-transformation V = H_0 H_1 ... H_{n-3} Z, in which every wavefront carries two
+//     columns of Z in registers through all reflectors (no workgroup barriers, n/8
+//     workgroups per matrix).
+// Three launches (reduction, eigenpairs of T, back-transformation), each kernel with its
+// own register budget.  Output as the Jacobi kernel: eigenvalues descending, eigenvectors
+// in the columns of V.
 // ---------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
+constexpr int kBackRows = kEigMax / 64;  // rows per lane when a wavefront holds a column
 
 __device__ inline double block_sum(double v, double* red, int tid, int bs) {
   v = wave_sum_d(v);
@@ -331,67 +349,93 @@ __device__ inline double block_sum(double v, double* red, int tid, int bs) {
   return t;
 }
 
+// Number of eigenvalues of T below x (negative pivots of the LDL^T factorisation of T - x).
+// Pivots smaller than tiny in magnitude are replaced by -tiny; 1/q comes from the hardware
+// reciprocal refined by two Newton steps r <- r (2 - q r), which leaves a relative error of
+// a few ulps (a small relative perturbation of e_i^2, as the division itself makes).
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double tiny) {
   int cnt = 0;
   double q = d[0] - x;
-  if (q == 0.0) q = -tiny;
+  if (fabs(q) < tiny) q = -tiny;
   cnt += q < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (q == 0.0) q = -tiny;
+    double r = __builtin_amdgcn_rcp(q);
+    r = r * fma(-q, r, 2.0);
+    r = r * fma(-q, r, 2.0);
+    q = (d[i] - x) - e2[i - 1] * r;
+    if (fabs(q) < tiny) q = -tiny;
     cnt += q < 0.0;
   }
   return cnt;
 }
 
-// Solve (T - sigma I) x = b in place for one thread; LU with partial pivoting stored in
-// the thread's scratch (u, v, w, mult: n doubles each; piv as the sign of mult slot).
+// Solve (T - sigma I) x = b in place for one thread: LU with partial pivoting of the
+// tridiagonal matrix (the pivot rows carry one extra superdiagonal).  Every array has
+// element i at [i * ld]: slots of neighbouring threads are interleaved so that a
+// wavefront's accesses are contiguous.  u holds the reciprocals of the pivots.
 __device__ void tri_factor(const double* d, const double* e, int n, double sigma, double tiny,
-                           double* u, double* v, double* w, double* mult, unsigned char* piv) {
+                           gdouble* u, gdouble* v, gdouble* w, gdouble* mult, gdouble* piv, int64_t ld) {
   double cd = d[0] - sigma, cs1 = n > 1 ? e[0] : 0.0, cs2 = 0.0;
   for (int i = 0; i < n - 1; ++i) {
     const double sub = e[i];
     const double a1 = d[i + 1] - sigma;
     const double s1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+    double ui, vi, wi;
     if (fabs(cd) >= fabs(sub)) {
-      piv[i] = 0;
+      piv[i * ld] = 0.0;
       const double m = cd != 0.0 ? sub / cd : 0.0;
-      mult[i] = m;
-      u[i] = cd; v[i] = cs1; w[i] = cs2;
+      mult[i * ld] = m;
+      ui = cd; vi = cs1; wi = cs2;
       cd = a1 - m * cs1;
       cs1 = s1 - m * cs2;
       cs2 = 0.0;
     } else {
-      piv[i] = 1;
+      piv[i * ld] = 1.0;
       const double m = cd / sub;
-      mult[i] = m;
-      u[i] = sub; v[i] = a1; w[i] = s1;
+      mult[i * ld] = m;
+      ui = sub; vi = a1; wi = s1;
       cd = cs1 - m * a1;
       cs1 = cs2 - m * s1;
       cs2 = 0.0;
     }
-    if (u[i] == 0.0) u[i] = tiny;
+    u[i * ld] = 1.0 / (ui == 0.0 ? tiny : ui);
+    v[i * ld] = vi;
+    w[i * ld] = wi;
   }
-  u[n - 1] = cd == 0.0 ? tiny : cd;
-  v[n - 1] = 0.0;
-  w[n - 1] = 0.0;
+  u[(n - 1) * ld] = 1.0 / (cd == 0.0 ? tiny : cd);
+  v[(n - 1) * ld] = 0.0;
+  w[(n - 1) * ld] = 0.0;
 }
 
-__device__ void tri_solve(int n, const double* u, const double* v, const double* w, const double* mult,
-                          const unsigned char* piv, double* x) {
+__device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble* mult, gcdouble* piv, gdouble* x,
+                          int64_t ld) {
   // forward: apply the row operations to the right-hand side
   double cur = x[0];
+#pragma unroll 4
   for (int i = 0; i < n - 1; ++i) {
-    const double nxt = x[i + 1];
-    if (!piv[i]) { x[i] = cur; cur = nxt - mult[i] * cur; }
-    else { x[i] = nxt; cur = cur - mult[i] * nxt; }
+    const double nxt = x[(i + 1) * ld];
+    const double m = mult[i * ld];
+    if (piv[i * ld] == 0.0) { x[i * ld] = cur; cur = nxt - m * cur; }
+    else { x[i * ld] = nxt; cur = cur - m * nxt; }
   }
-  x[n - 1] = cur;
   // back substitution
-  x[n - 1] = x[n - 1] / u[n - 1];
-  if (n >= 2) x[n - 2] = (x[n - 2] - v[n - 2] * x[n - 1]) / u[n - 2];
-  for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - v[i] * x[i + 1] - w[i] * x[i + 2]) / u[i];
+  double x1 = cur * u[(n - 1) * ld];
+  x[(n - 1) * ld] = x1;
+  if (n < 2) return;
+  double x0 = (x[(n - 2) * ld] - v[(n - 2) * ld] * x1) * u[(n - 2) * ld];
+  x[(n - 2) * ld] = x0;
+#pragma unroll 4
+  for (int i = n - 3; i >= 0; --i) {
+    const double xi = (x[i * ld] - v[i * ld] * x0 - w[i * ld] * x1) * u[i * ld];
+    x[i * ld] = xi;
+    x1 = x0;
+    x0 = xi;
+  }
 }
+
+constexpr int kRedThreads = 512;  // reduction kernel: 8 wavefronts with room for 256 VGPRs
+constexpr int kRedCols = 4;  // columns per wavefront group in the reduction pass
+constexpr int kRedChunks = 4;  // 64-row chunks per iteration of that pass
 
 __device__ inline double block_max(double v, double* red, int tid, int bs) {
 #pragma unroll
@@ -428,56 +472,61 @@ __device__ inline bool linked(double a, double b, double cut, double ctol) {
   return fabs(a) > cut && fabs(b) > cut && b - a <= fmin(ctol, kClusterRel * fmax(fabs(a), fabs(b)));
 }
 
-__device__ inline void start_vector(double* z, int n, int s, int m, int j) {
-  for (int i = 0; i < n; ++i)
-    z[i] = (i >= s && i < s + m) ? 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0 : 0.0;
+__device__ inline double start_value(int i, int j) {
+  return 1.0 + 0.37 * (double)((i * 7919 + j * 104729) % 101) / 101.0;
 }
 
-__global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc* __restrict__ descs) {
-  __shared__ double red[kTriThreads / 64];
-  __shared__ double sh_beta, sh_K;
-  __shared__ int sh_nblk, sh_nruns;
-  // d, e, e2, lam, beta, vsh, psh: n doubles each; block starts: n + 1 ints
+
+// Work layout of one problem (doubles): [0, n^2) working copy, reflectors below the
+// diagonal; [n^2, 6 n^2) per-thread inverse-iteration storage (during the reduction: the
+// per-column products); [6 n^2, 7 n^2) eigenvectors of T in descending order; then beta_k,
+// the diagonal d and off-diagonal e of T (n each) and the applied shift.
+
+// 1. Reduction to tridiagonal form, one workgroup per matrix.  Step k forms the reflector
+//    H_k = I - beta v v^T from column k, p = beta A22 v, K = beta/2 p^T v, q = p - K v; its
+//    rank-2 update A22 <- A22 - v q^T - q v^T is applied lazily, in the next step's single
+//    pass over the trailing lower triangle, which also forms that step's product: column j
+//    contributes sum_{i>=j} a_ij v_i to p_j (a wavefront reduction) and a_ij v_j to p_i for
+//    i > j (accumulated per wavefront in LDS, summed in a fixed order).  A matrix whose
+//    off-diagonal part is negligible is passed on as T = diag(A);
+//    a narrow spectrum is shifted by its mean diagonal entry first.
+__global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double red[kRedThreads / 64];
+  // v and q of the current and previous step, column products, next column (6 n doubles),
+  // nw x n partial products
   extern __shared__ double tsm[];
   const EigDesc D = descs[blockIdx.x];
   const int n = D.n;
   if (n <= 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-  double* dd = tsm;
-  double* ee = dd + n;
-  double* e2 = ee + n;
-  double* lam = e2 + n;
-  double* betas = lam + n;
-  double* vsh = betas + n;
-  double* psh = vsh + n;
-  int* bstart = reinterpret_cast<int*>(psh + n);
   const int lda = n;
-  double* A = D.work;                         // n x n working copy
-  double* scratch = D.work + (int64_t)n * n;  // per-thread inverse-iteration storage
-  double* Z = D.V;                            // eigenvectors of T, then of A
+  const int64_t nn0 = (int64_t)n * n;
+  gdouble* A = gbl(D.work);
+  gdouble* betas = A + 7 * nn0;
+  gdouble* dd = betas + n;
+  gdouble* ee = dd + n;
+  gdouble* shift_out = ee + n;
+  gcdouble* Ain = gbl(D.A);
   double od = 0.0, dg = 0.0;
   for (int e = tid; e < n * n; e += bs) {
     const int j = e / n, i = e - j * n;
-    const double a = (i <= j) ? D.A[i + (int64_t)j * D.lda] : D.A[j + (int64_t)i * D.lda];
+    const double a = (i <= j) ? Ain[i + (int64_t)j * D.lda] : Ain[j + (int64_t)i * D.lda];
     A[e] = a;
     if (i == j) dg = fmax(dg, fabs(a)); else od = fmax(od, fabs(a));
   }
   od = block_max(od, red, tid, bs);
   dg = block_max(dg, red, tid, bs);
-  const bool diagonal = od <= kDiagTol * dg;
-  if (diagonal) {
-    // 0. diagonal to working accuracy: eigenpairs (a_ii, e_i)
+  if (od <= kDiagTol * dg) {
+    // 0. diagonal to working accuracy: T = diag(A), no reflectors
     for (int t = tid; t < n; t += bs) {
-      lam[t] = A[t + (int64_t)t * lda];
+      dd[t] = A[t + (int64_t)t * lda];
+      ee[t] = 0.0;
       betas[t] = 0.0;
     }
-    for (int e = tid; e < n * n; e += bs) {
-      const int j = e / n, i = e - j * n;
-      Z[e] = i == j ? 1.0 : 0.0;
-    }
-    __syncthreads();
-  } else {
+    if (tid == 0) *shift_out = 0.0;
+    return;
+  }
   double dsum = 0.0;
   for (int t = tid; t < n; t += bs) dsum += A[t + (int64_t)t * lda];
   const double mu = block_sum(dsum, red, tid, bs) / n;
@@ -491,73 +540,152 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
   const double shift = rad <= kShiftTol * fabs(mu) ? mu : 0.0;
   if (shift != 0.0)
     for (int t = tid; t < n; t += bs) A[t + (int64_t)t * lda] -= shift;
+  if (tid == 0) *shift_out = shift;
+  // v of step k at tsm + (k & 1) n, q at tsm + (2 + (k & 1)) n
+  double* pd = tsm + 4 * n;   // per-column dot products
+  double* nxt = tsm + 5 * n;  // column k + 1 as left by the pass of step k
+  double* pw = tsm + 6 * n;   // nw x n partial products
+  for (int i = tid; i < n; i += bs) { tsm[n + i] = 0.0; tsm[3 * n + i] = 0.0; }
   __syncthreads();
-  // 1. tridiagonalisation
   for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    double* x = A + (k + 1) + (int64_t)k * lda;  // column k below the diagonal
-    double part = 0.0;
-    for (int i = tid + 1; i < m; i += bs) part += x[i] * x[i];
-    const double sig2 = block_sum(part, red, tid, bs);
-    const double x0 = x[0];
-    if (tid == 0) {
-      dd[k] = A[k + (int64_t)k * lda];
-      if (sig2 == 0.0) {
-        ee[k] = x0;
-        sh_beta = 0.0;
-      } else {
-        const double nrm = sqrt(x0 * x0 + sig2);
-        const double alpha = x0 > 0.0 ? -nrm : nrm;
-        const double v0 = x0 - alpha;
-        ee[k] = alpha;
-        sh_beta = 2.0 / (v0 * v0 + sig2);
-        x[0] = v0;  // v stored over the column
+    double* vk = tsm + (k & 1) * n;
+    double* qk = tsm + (2 + (k & 1)) * n;
+    const double* vp = tsm + ((k + 1) & 1) * n;
+    const double* qp = tsm + (2 + ((k + 1) & 1)) * n;
+    // column k (rows >= k) brought up to date and turned into the reflector by wave 0;
+    // its lanes exchange values through vk in LDS (in order within a wavefront)
+    if (wave == 0) {
+      gdouble* col = A + (int64_t)k * lda;
+      const double vpk = vp[k], qpk = qp[k];
+      double part = 0.0;
+      for (int i = k + lane; i < n; i += 64) {
+        const double a = (k == 0 ? col[i] : nxt[i]) - vp[i] * qpk - qp[i] * vpk;
+        col[i] = a;
+        vk[i] = a;
+        if (i >= k + 2) part += a * a;
       }
-      betas[k] = sh_beta;
+      const double sig2 = wave_sum_d(part);
+      __builtin_amdgcn_wave_barrier();
+      const double x0 = vk[k + 1], akk = vk[k];
+      double beta = 0.0, v0 = x0, alpha = x0;
+      if (sig2 != 0.0) {
+        const double nrm = sqrt(x0 * x0 + sig2);
+        alpha = x0 > 0.0 ? -nrm : nrm;
+        v0 = x0 - alpha;
+        beta = 2.0 / (v0 * v0 + sig2);
+      }
+      if (lane == 0) {
+        ee[k] = alpha;
+        dd[k] = akk;
+        betas[k] = beta;
+        red[0] = beta;
+        if (beta != 0.0) col[k + 1] = v0;  // v stored over the column
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int i = lane; i < n; i += 64)
+        vk[i] = (beta == 0.0 || i <= k) ? 0.0 : (i == k + 1 ? v0 : vk[i]);
     }
     __syncthreads();
-    const double beta = sh_beta;
-    if (beta == 0.0) continue;
-    for (int i = tid; i < m; i += bs) vsh[i] = x[i];
-    __syncthreads();
-    // p = beta A22 v, A22 = A[k+1:, k+1:]; A22 is symmetric, so p_i is the dot product of
-    // column i with v: one wavefront per column, lanes along the contiguous column
-    const double* A22 = A + (k + 1) + (int64_t)(k + 1) * lda;
-    for (int i0 = wave; i0 < m; i0 += 2 * nw) {
-      const int i1 = i0 + nw;
-      const double* c0 = A22 + (int64_t)i0 * lda;
-      const double* c1 = A22 + (int64_t)(i1 < m ? i1 : i0) * lda;
-      double a0 = 0.0, a1 = 0.0;
-      for (int j = lane; j < m; j += 64) {
-        const double vj = vsh[j];
-        a0 += c0[j] * vj;
-        a1 += c1[j] * vj;
+    const double beta = red[0];
+    // fused pass over columns j > k, rows i >= j; wavefront w takes columns
+    // k + 1 + w + nw c in groups of kRedCols, rows in tiles of kRedChunks 64-row chunks;
+    // the loads of the next tile are issued before the stores of the current one (loads
+    // and stores share one completion counter, so a load issued after a store would wait
+    // for it); a_ij v_j terms go to the wavefront's own LDS row pw[w] (in order within the
+    // wavefront)
+    double* pwr = pw + wave * n;
+    for (int i = k + 1 + lane; i < n; i += 64) pwr[i] = 0.0;
+    const int64_t cstep = (int64_t)nw * lda;
+    int j0 = k + 1 + wave, i0 = j0;
+    double cur[kRedChunks][kRedCols];
+    auto load_tile = [&](double (&t)[kRedChunks][kRedCols], int tj0, int ti0) {
+      gcdouble* colj = A + (int64_t)tj0 * lda;
+#pragma unroll
+      for (int h = 0; h < kRedChunks; ++h) {
+        const int i = ti0 + 64 * h + lane;
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) t[h][c] = (i < n && i >= tj0 + c * nw) ? colj[i + c * cstep] : 0.0;
       }
-      a0 = wave_sum_d(a0);
-      a1 = wave_sum_d(a1);
-      if (lane == 0) {
-        psh[i0] = beta * a0;
-        if (i1 < m) psh[i1] = beta * a1;
+    };
+    double vj[kRedCols], vpj[kRedCols], qpj[kRedCols], dot[kRedCols];
+    auto start_group = [&](int tj0) {
+#pragma unroll
+      for (int c = 0; c < kRedCols; ++c) {
+        const int jc = tj0 + c * nw;
+        const bool ok = jc < n;
+        vj[c] = ok ? vk[jc] : 0.0;
+        vpj[c] = ok ? vp[jc] : 0.0;
+        qpj[c] = ok ? qp[jc] : 0.0;
+        dot[c] = 0.0;
       }
+    };
+    if (j0 < n) {
+      start_group(j0);
+      load_tile(cur, j0, i0);
+    }
+    while (j0 < n) {
+      int nj0 = j0, ni0 = i0 + 64 * kRedChunks;
+      if (ni0 >= n) { nj0 = j0 + kRedCols * nw; ni0 = nj0; }
+      double nxtt[kRedChunks][kRedCols];
+      if (nj0 < n) load_tile(nxtt, nj0, ni0);
+      gdouble* colj = A + (int64_t)j0 * lda;
+#pragma unroll
+      for (int h = 0; h < kRedChunks; ++h) {
+        const int i = i0 + 64 * h + lane;
+        if (i >= n) continue;
+        const double vki = vk[i], vpi = vp[i], qpi = qp[i];
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) {
+          const int jc = j0 + c * nw;
+          if (i >= jc) {
+            const double x = cur[h][c] - vpi * qpj[c] - qpi * vpj[c];
+            colj[i + c * cstep] = x;
+            if (jc == k + 1) nxt[i] = x;
+            dot[c] += x * vki;
+            if (i > jc) acc += x * vj[c];
+          }
+        }
+        pwr[i] += acc;
+      }
+      if (nj0 != j0) {  // group finished
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) {
+          const double d = wave_sum_d(dot[c]);
+          if (lane == 0 && j0 + c * nw < n) pd[j0 + c * nw] = d;
+        }
+        if (nj0 < n) start_group(nj0);
+      }
+#pragma unroll
+      for (int h = 0; h < kRedChunks; ++h)
+#pragma unroll
+        for (int c = 0; c < kRedCols; ++c) cur[h][c] = nxtt[h][c];
+      j0 = nj0;
+      i0 = ni0;
     }
     __syncthreads();
     double pv = 0.0;
-    for (int i = tid; i < m; i += bs) pv += psh[i] * vsh[i];
-    const double vtp = block_sum(pv, red, tid, bs);
-    if (tid == 0) sh_K = 0.5 * beta * vtp;
-    __syncthreads();
-    const double K = sh_K;
-    for (int i = tid; i < m; i += bs) psh[i] -= K * vsh[i];  // q
-    __syncthreads();
-    double* A22w = A + (k + 1) + (int64_t)(k + 1) * lda;
-    for (int j = wave; j < m; j += nw) {
-      const double vj = vsh[j], qj = psh[j];
-      double* col = A22w + (int64_t)j * lda;
-      for (int i = lane; i < m; i += 64) col[i] -= vsh[i] * qj + psh[i] * vj;
+    for (int i = k + 1 + tid; i < n; i += bs) {
+      double p = pd[i];
+      for (int w2 = 0; w2 < nw; ++w2) p += pw[w2 * n + i];
+      p *= beta;
+      qk[i] = p;
+      pv += p * vk[i];
     }
+    for (int i = tid; i <= k && i < n; i += bs) qk[i] = 0.0;
+    const double vtp = block_sum(pv, red, tid, bs);
+    const double K = 0.5 * beta * vtp;
+    for (int i = k + 1 + tid; i < n; i += bs) qk[i] -= K * vk[i];
     __syncthreads();
   }
   if (tid == 0) {
+    if (n >= 3) {  // the last step's update on the trailing 2 x 2 block
+      const int k = n - 3;
+      const double* vp = tsm + (k & 1) * n;
+      const double* qp = tsm + (2 + (k & 1)) * n;
+      for (int j = n - 2; j < n; ++j)
+        for (int i = j; i < n; ++i) A[i + (int64_t)j * lda] -= vp[i] * qp[j] + qp[i] * vp[j];
+    }
     if (n >= 2) {
       dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
       ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
@@ -566,6 +694,39 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
     ee[n - 1] = 0.0;
     betas[n - 1] = 0.0;
+  }
+}
+
+// 2.-3. Eigenvalues (bisection) and eigenvectors (inverse iteration) of T, one workgroup
+// per matrix; the vectors go to the work area in descending order of the eigenvalues.
+__global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double red[kTriThreads / 64];
+  __shared__ int sh_nblk, sh_nruns;
+  // d, e, e2, lam, vsh, psh: n doubles each; block starts: n + 1 ints
+  extern __shared__ double tsm[];
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+  const int64_t nn0 = (int64_t)n * n;
+  double* dd = tsm;
+  double* ee = dd + n;
+  double* e2 = ee + n;
+  double* lam = e2 + n;
+  double* vsh = lam + n;
+  double* psh = vsh + n;
+  int* bstart = reinterpret_cast<int*>(psh + n);
+  gdouble* W = gbl(D.work);
+  gdouble* scratch = W + nn0;  // per-thread inverse-iteration storage
+  // eigenvectors of T, stored transposed (element i of vector t at Z[i * n + t]) so that
+  // threads working on neighbouring vectors touch neighbouring addresses
+  gdouble* Z = gbl(D.V);
+  gcdouble* gd = W + 7 * nn0 + n;
+  const double shift = gd[2 * n];  // beta_k, then d, e, shift
+  for (int i = tid; i < n; i += bs) {
+    dd[i] = gd[i];
+    ee[i] = gd[n + i];
   }
   __syncthreads();
   // Gershgorin bound of ||T||; negligible off-diagonals split T into unreduced blocks
@@ -621,6 +782,8 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
   // with a shift every |eigenvalue| of A is at least (1 - kShiftTol) |mu|: nothing is cut
   const double cut = shift != 0.0 ? 0.0 : D.abs_tol * lmax;
   const double ctol = kClusterTol * fmax(tn, 1e-300);
+  const int64_t ld = n;
+  const int64_t nn = (int64_t)n * n;
   for (int t = tid; t < n; t += bs) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
@@ -632,42 +795,38 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     int last = t;
     while (last + 1 < s + m && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
     if (last + 1 - t > kThreadCluster) continue;  // long cluster: workgroup pass below
-    double* u = scratch + (int64_t)t * 5 * n;
-    double* v = u + n;
-    double* w = v + n;
-    double* mult = w + n;
-    unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
+    gdouble* u = scratch + t;  // slot t, interleaved with the other threads' slots
+    gdouble* v = u + nn;
+    gdouble* w = v + nn;
+    gdouble* mult = w + nn;
+    gdouble* piv = mult + nn;
     for (int j = t; j <= last; ++j) {
-      double* z = Z + (int64_t)j * n;
-      if (fabs(lam[j]) <= cut) {
-        for (int i = 0; i < n; ++i) z[i] = 0.0;
-        continue;
-      }
-      if (m == 1) {
-        for (int i = 0; i < n; ++i) z[i] = i == s ? 1.0 : 0.0;
+      gdouble* z = Z + j;  // element i at z[i * ld]
+      if (fabs(lam[j]) <= cut || m == 1) {
+        for (int i = 0; i < n; ++i) z[i * ld] = (m == 1 && fabs(lam[j]) > cut && i == s) ? 1.0 : 0.0;
         continue;
       }
       const double sigma = lam[j] + (j - t) * 10.0 * 2.2e-16 * tn;
-      tri_factor(dd + s, ee + s, m, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv);
-      start_vector(z, n, s, m, j);
+      tri_factor(dd + s, ee + s, m, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv, ld);
+      for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, j) : 0.0;
       for (int it = 0; it < 3; ++it) {
-        tri_solve(m, u, v, w, mult, piv, z + s);
+        tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
         for (int jj = t; jj < j; ++jj) {
-          const double* y = Z + (int64_t)jj * n;
+          gcdouble* y = Z + jj;
           double dot = 0.0;
-          for (int i = s; i < s + m; ++i) dot += y[i] * z[i];
-          for (int i = s; i < s + m; ++i) z[i] -= dot * y[i];
+          for (int i = s; i < s + m; ++i) dot += y[i * ld] * z[i * ld];
+          for (int i = s; i < s + m; ++i) z[i * ld] -= dot * y[i * ld];
         }
-        double nn = 0.0;
-        for (int i = s; i < s + m; ++i) nn += z[i] * z[i];
-        nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = s; i < s + m; ++i) z[i] *= nn;
+        double q = 0.0;
+        for (int i = s; i < s + m; ++i) q += z[i * ld] * z[i * ld];
+        q = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+        for (int i = s; i < s + m; ++i) z[i * ld] *= q;
       }
     }
   }
   __syncthreads();
   // long clusters: (first, last, block) listed in e2 (free after bisection), members
-  // flagged in vsh (free until the back-transformation)
+  // flagged in vsh
   for (int i = tid; i < n; i += bs) vsh[i] = 0.0;
   __syncthreads();
   if (tid == 0) {
@@ -701,85 +860,64 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
         if (bstart[mid] <= p) lo_b = mid; else hi_b = mid - 1;
       }
       const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
-      double* u = scratch + (int64_t)p * 5 * n;
-      double* v = u + n;
-      double* w = v + n;
-      double* mult = w + n;
-      unsigned char* piv = reinterpret_cast<unsigned char*>(mult + n);
-      double* z = Z + (int64_t)p * n;
+      gdouble* u = scratch + p;
+      gdouble* v = u + nn;
+      gdouble* w = v + nn;
+      gdouble* mult = w + nn;
+      gdouble* piv = mult + nn;
+      gdouble* z = Z + p;
       if (it == 0) {
         tri_factor(dd + s, ee + s, m, lam[p] + (p - s) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v, w, mult,
-                   piv);
-        start_vector(z, n, s, m, p);
+                   piv, ld);
+        for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, p) : 0.0;
       }
-      tri_solve(m, u, v, w, mult, piv, z + s);
-      double nn = 0.0;
-      for (int i = s; i < s + m; ++i) nn += z[i] * z[i];
-      nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = s; i < s + m; ++i) z[i] *= nn;
+      tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
+      double q = 0.0;
+      for (int i = s; i < s + m; ++i) q += z[i * ld] * z[i * ld];
+      q = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+      for (int i = s; i < s + m; ++i) z[i * ld] *= q;
     }
     __syncthreads();
     for (int q = 0; q < nruns; ++q) {
       const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
       const int s = bstart[b], m = bstart[b + 1] - s;
       for (int j = r0; j <= r1; ++j) {
-        double* z = Z + (int64_t)j * n;
+        gdouble* z = Z + j;
         for (int pass = 0; pass < 2 && j > r0; ++pass) {
           for (int jj = r0 + wave; jj < j; jj += nw) {
-            const double* y = Z + (int64_t)jj * n;
+            gcdouble* y = Z + jj;
             double dot = 0.0;
-            for (int i = s + lane; i < s + m; i += 64) dot += y[i] * z[i];
+            for (int i = s + lane; i < s + m; i += 64) dot += y[i * ld] * z[i * ld];
             dot = wave_sum_d(dot);
             if (lane == 0) psh[jj - r0] = dot;
           }
           __syncthreads();
           for (int i = s + tid; i < s + m; i += bs) {
             double acc = 0.0;
-            for (int jj = r0; jj < j; ++jj) acc += psh[jj - r0] * Z[i + (int64_t)jj * n];
-            z[i] -= acc;
+            for (int jj = r0; jj < j; ++jj) acc += psh[jj - r0] * Z[i * ld + jj];
+            z[i * ld] -= acc;
           }
           __syncthreads();
         }
         double part = 0.0;
-        for (int i = s + tid; i < s + m; i += bs) part += z[i] * z[i];
+        for (int i = s + tid; i < s + m; i += bs) part += z[i * ld] * z[i * ld];
         const double nn2 = block_sum(part, red, tid, bs);
         const double sc = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
-        for (int i = s + tid; i < s + m; i += bs) z[i] *= sc;
+        for (int i = s + tid; i < s + m; i += bs) z[i * ld] *= sc;
         __syncthreads();
       }
     }
   }
   __syncthreads();
-  // 4. back-transformation: apply H_{n-3} ... H_0 to the columns of Z
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = betas[k];
-    if (beta == 0.0) continue;
-    const int m = n - k - 1;
-    const double* vk = A + (k + 1) + (int64_t)k * lda;
-    for (int i = tid; i < m; i += bs) vsh[i] = vk[i];
-    __syncthreads();
-    for (int c = wave; c < n; c += nw) {
-      double* zc = Z + (int64_t)c * n + (k + 1);
-      double dot = 0.0;
-      for (int i = lane; i < m; i += 64) dot += vsh[i] * zc[i];
-      dot = beta * wave_sum_d(dot);
-      if (dot != 0.0)
-        for (int i = lane; i < m; i += 64) zc[i] -= dot * vsh[i];
-    }
-    __syncthreads();
-  }
   for (int t = tid; t < n; t += bs) lam[t] += shift;
   __syncthreads();
-  }  // !diagonal
   // eigenvalues at or below the cut carry zero vectors
   double lmx = 0.0;
   for (int i = 0; i < n; ++i) lmx = fmax(lmx, fabs(lam[i]));
   const double vcut = D.abs_tol * lmx;
-  // 5. descending order (ties: lower position first); Z goes through the working copy
-  for (int e = tid; e < n * n; e += bs) {
-    const int c = e / n;
-    A[e] = fabs(lam[c]) <= vcut ? 0.0 : Z[e];
-  }
+  // descending order (ties: lower position first) into the eigenvector area of T
+  gdouble* ZT = W + 6 * nn0;
+  gdouble* wout = gbl(D.w);
   for (int t = tid; t < n; t += bs) {
     int rank = 0;
     const double lt = lam[t];
@@ -787,20 +925,101 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_eig_kernel(const EigDesc*
     e2[t] = rank;
   }
   __syncthreads();
-  for (int t = tid; t < n; t += bs) D.w[int(e2[t])] = lam[t];
+  for (int t = tid; t < n; t += bs) wout[int(e2[t])] = lam[t];
   for (int e = tid; e < n * n; e += bs) {
-    const int c = e / n, i = e - c * n;
-    Z[i + (int64_t)int(e2[c]) * n] = A[e];
+    const int i = e / n, c = e - i * n;  // Z is transposed: element i of vector c at Z[i n + c]
+    ZT[i + (int64_t)int(e2[c]) * n] = fabs(lam[c]) <= vcut ? 0.0 : Z[e];
   }
-  if (tid == 0 && D.sweeps) *D.sweeps = diagonal ? 0 : -1;
+  if (tid == 0 && D.sweeps) *D.sweeps = -1;
+}
+
+// 4. Back-transformation V = H_0 ... H_{n-3} Z_T: wavefront w of workgroup (x, p) owns
+// columns 8x + 2w and 8x + 2w + 1 of problem p, lane l holds rows l + 64 j (j < 16).
+__global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __restrict__ descs) {
+  const EigDesc D = descs[blockIdx.y];
+  const int n = D.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = 8 * blockIdx.x + 2 * wave;
+  if (c0 >= n) return;
+  const bool two = c0 + 1 < n;
+  const int64_t nn0 = (int64_t)n * n;
+  gcdouble* A = gbl(D.work);
+  gcdouble* ZT = A + 6 * nn0;
+  gcdouble* betas = A + 7 * nn0;
+  gdouble* Vout = gbl(D.V);
+  double z0[kBackRows], z1[kBackRows];
+#pragma unroll
+  for (int j = 0; j < kBackRows; ++j) {
+    const int r = lane + 64 * j;
+    z0[j] = r < n ? ZT[r + (int64_t)c0 * n] : 0.0;
+    z1[j] = (r < n && two) ? ZT[r + (int64_t)(c0 + 1) * n] : 0.0;
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    gcdouble* vk = A + (int64_t)k * n;  // v_r = A[r, k] for r > k
+    double v[kBackRows];
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kBackRows; ++j) {
+      const int r = lane + 64 * j;
+      v[j] = (r > k && r < n) ? vk[r] : 0.0;
+      d0 += v[j] * z0[j];
+      d1 += v[j] * z1[j];
+    }
+    d0 = beta * wave_sum_d(d0);
+    d1 = beta * wave_sum_d(d1);
+#pragma unroll
+    for (int j = 0; j < kBackRows; ++j) {
+      z0[j] -= d0 * v[j];
+      z1[j] -= d1 * v[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kBackRows; ++j) {
+    const int r = lane + 64 * j;
+    if (r < n) {
+      Vout[r + (int64_t)c0 * n] = z0[j];
+      if (two) Vout[r + (int64_t)(c0 + 1) * n] = z1[j];
+    }
+  }
+}
+
+static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : (nmax <= 512 ? kTriThreads : 512); }
+
+// LDS bytes: reduction (6 + nw) n doubles; vectors 6 n doubles + (n + 1) ints.
+static size_t tridiag_reduce_lds(int n, int threads) { return size_t(6 + threads / 64) * n * sizeof(double); }
+static size_t tridiag_vec_lds(int n) { return size_t(6) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
+
+static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
+  if (shm <= 65536) return;
+  if (*granted == 0) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+    (void)hipGetLastError();
+    const size_t want = v > 1024 ? size_t(v) - 1024 : 0;
+    if (want > 0 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
+      *granted = want;
+    (void)hipGetLastError();
+  }
+  if (shm > *granted) throw std::runtime_error("eig: tridiagonal solver needs more LDS than the device grants");
 }
 
 void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
-  const size_t shm = size_t(nmax) * 7 * sizeof(double) + size_t(nmax + 1) * sizeof(int);
-  const int threads = nmax <= 64 ? 256 : kTriThreads;
-  hipLaunchKernelGGL(tridiag_eig_kernel, dim3(nprob), dim3(threads), shm, s, d);
+  const int threads = tridiag_threads(nmax);
+  const int rthreads = nmax <= 64 ? 256 : kRedThreads;
+  static size_t granted_reduce = 0, granted_vec = 0;
+  const size_t shm_r = tridiag_reduce_lds(nmax, rthreads), shm_v = tridiag_vec_lds(nmax);
+  lds_opt_in((const void*)tridiag_reduce_kernel, shm_r, &granted_reduce);
+  lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
+  hipLaunchKernelGGL(tridiag_reduce_kernel, dim3(nprob), dim3(rthreads), shm_r, s, d);
+  PV_LAUNCH_CHECK();
+  hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
+  PV_LAUNCH_CHECK();
+  hipLaunchKernelGGL(tridiag_back_kernel, dim3((nmax + 7) / 8, nprob), dim3(256), 0, s, d);
   PV_LAUNCH_CHECK();
 }
 

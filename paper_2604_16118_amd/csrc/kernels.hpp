@@ -88,9 +88,11 @@ void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t 
 void launch_eig(const EigDesc* d_desc, int nprob, int nmax, int mode, hipStream_t s);
 // Fastest mode available for an n x n problem on this device.
 int eig_mode(int n);
-// Tridiagonalisation + bisection + inverse iteration; work holds 6 n^2 doubles; abs_tol
-// is the relative cut below which eigenvectors are returned as zero.
+// Tridiagonalisation, bisection + inverse iteration, back-transformation (three
+// launches); work holds tri_work_doubles(n) doubles; abs_tol is the relative cut below
+// which eigenvectors are returned as zero.
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
+inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(3) * n + 1; }
 void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
                   const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
                   const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,
