@@ -36,6 +36,7 @@ KERNELS = {
     "mpo_wstep": ("wstep_kernel", "hbm"),
     "copy_scale": ("copy_kernel/scale_kernel", "hbm"),
     "reduce": ("reduce_kernel", "hbm"),
+    "cholesky_f64": ("chol_panel_kernel", "alu"),
 }
 
 
@@ -199,6 +200,10 @@ def main():
         "energy": res["energy"],
         "max_rank": max([r["max_rank"] for r in hist] + [0]),
         "timers_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
+        "kernel_classes": {k: {"ms": round(v["ms"], 3), "calls": v["calls"],
+                               "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 4),
+                               "gbs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 2)}
+                           for k, v in tm.items()},
         "roofline": roof,
     }
     ctx.close()

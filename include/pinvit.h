@@ -164,9 +164,10 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
 
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
- * 10/3 n^3 each), bytes[i] = algorithmic bytes, for i < n classes (six classes: grouped
- * GEMM, Jacobi eigensolver, MPO W-step, copy/scale, reduction, tridiagonal eigensolver);
- * names via pv_timer_name. */
+ * 10/3 n^3 each; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic bytes,
+ * for i < n classes (seven classes: grouped GEMM, Jacobi eigensolver, MPO W-step,
+ * copy/scale, reduction, tridiagonal eigensolver, Cholesky panels); names via
+ * pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);
@@ -178,6 +179,13 @@ pv_status pv_timers_reset(pv_ctx* ctx);
  * bisection and inverse iteration (eigenvectors of eigenvalues <= 1e-12 max|lambda|
  * are returned as zero).  For tests. */
 pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method);
+
+/* Cholesky factor of a symmetric positive semidefinite matrix on the device (the factor
+ * of the left Gram matrices in the simultaneous truncation): A is n x n column-major
+ * (lower triangle read), W (n x n) receives a lower triangular W with W W^T = A up to
+ * the columns whose pivot falls to 1e-12 of their diagonal entry, which are zero.  For
+ * tests. */
+pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W);
 
 /* Host-only diagnostics (no GPU needed). */
 /* Bond dimensions of the MPO of H: dims[0..L] and per-charge counts q=-2..2 in

@@ -515,8 +515,17 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
   });
 }
 
+pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
+  return guard([&] {
+    if (!ctx || !A || !W) fail(PV_EINVAL, "null argument");
+    if (n < 1 || n > kEigMax) fail(PV_EINVAL, "n out of range");
+    for (size_t i = 0; i < size_t(n) * n; ++i) if (!std::isfinite(A[i])) fail(PV_EINVAL, "A not finite");
+    cholesky(ctx->c, n, A, W);
+  });
+}
+
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
-                                            "tridiag_eig_f64"};
+                                            "tridiag_eig_f64", "cholesky_f64"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

@@ -394,6 +394,55 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
   }
 }
 
+// W W^T ~ G for every job (G symmetric positive semidefinite, n x n, ld n; W lower
+// triangular, n x n, numerically dependent columns zero): panel kernels interleaved with
+// batched trailing GEMMs.
+struct CholJob {
+  const double* G;
+  int n;
+  double* W;
+};
+
+void chol_all(Ctx& c, const std::vector<CholJob>& jobs) {
+  std::vector<CholDesc> d;
+  CopyBatch cp;
+  int nmax = 0;
+  int64_t ndg = 0;
+  for (const CholJob& j : jobs) ndg += std::max(j.n, 0);
+  Buf dg = scratch_buf(c, size_t(std::max<int64_t>(ndg, 1)));
+  ndg = 0;
+  for (const CholJob& j : jobs) {
+    if (j.n <= 0) continue;
+    cp.add(j.G, j.n, j.W, j.n, j.n, j.n, 1.0);
+    d.push_back(CholDesc{j.W, dg.p + ndg, j.n, j.n});
+    ndg += j.n;
+    nmax = std::max(nmax, j.n);
+  }
+  c.scratch.push_back(std::move(dg));
+  if (d.empty()) return;
+  cp.run(c);
+  CholDesc* dd = c.upload(d);
+  for (int j0 = 0; j0 < nmax; j0 += kCholB) {
+    double fl = 0;
+    for (const CholDesc& x : d) {
+      const int jb = std::min(kCholB, x.n - j0);
+      if (jb > 0) fl += double(jb) * jb * jb / 3.0 + double(x.n - j0 - jb) * jb * jb;
+    }
+    hipEvent_t a; c.begin(T_CHOL, a);
+    launch_chol_panel(dd, int(d.size()), j0, c.stream);
+    c.end(T_CHOL, a, fl, 0);
+    GemmBatch g;
+    for (const CholDesc& x : d) {
+      const int m2 = x.n - j0 - kCholB;
+      if (m2 <= 0) continue;
+      const int64_t o = j0 + kCholB;
+      g.add(x.A + o + int64_t(j0) * x.n, x.n, 0, x.A + o + int64_t(j0) * x.n, x.n, 1, x.A + o + o * x.n, x.n, m2, m2,
+            kCholB, -1.0, 1.0);
+    }
+    g.run(c);
+  }
+}
+
 void fill(Ctx& c, double* p, int64_t n, double v) {
   if (n <= 0) return;
   hipEvent_t a; c.begin(T_COPY, a);
@@ -812,6 +861,14 @@ void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host
   run_eig(c, jobs);
   PV_HIP(hipMemcpyAsync(w_host, w.p, size_t(n) * 8, hipMemcpyDeviceToHost, c.stream));
   PV_HIP(hipMemcpyAsync(V_host, V.p, size_t(n) * n * 8, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+}
+
+void cholesky(Ctx& c, int n, const double* A_host, double* W_host) {
+  Buf A(c.pool, size_t(n) * n), W(c.pool, size_t(n) * n);
+  PV_HIP(hipMemcpyAsync(A.p, A_host, size_t(n) * n * 8, hipMemcpyHostToDevice, c.stream));
+  chol_all(c, {CholJob{A.p, n, W.p}});
+  PV_HIP(hipMemcpyAsync(W_host, W.p, size_t(n) * n * 8, hipMemcpyDeviceToHost, c.stream));
   c.sync();
 }
 
@@ -1301,64 +1358,44 @@ BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax) 
   return e;
 }
 
-constexpr double kGramDrop = 1e-12;   // Gram eigenvalues <= this * max are treated as zero
-
-// Per bond, the per-sector eigenvalue cut-off of a Gram eigendecomposition.
-std::vector<double> gram_thresholds(Ctx& c, const Mps& x, const BondEig& e, int kmin, int kmax) {
-  auto w = download(c, e.w.p, e.w.n);
-  std::vector<double> thr(x.L + 1, 0.0);
-  for (int k = kmin; k <= kmax; ++k) {
-    double mx = 0;
-    for (int n = 0; n <= x.N; ++n)
-      if (e.woff[k][n] >= 0 && x.rho[k][n] > 0) mx = std::max(mx, w[e.woff[k][n]]);
-    thr[k] = kGramDrop * mx;
-  }
-  return thr;
-}
-
 }  // namespace
 
 // trunc_par(x; eps, cap) = P_1 P_2 ... P_{L-1} x with P_k the orthogonal projector onto the
 // kept left singular vectors of the k-th matricisation of x, every bond decided
 // independently with tolerance eps/(L-1).  With the left Gram G^L_k = A_k^T A_k factored
-// as W W^T (W = V_L Lambda^{1/2} from its eigendecomposition) one has A_k = Q W^T with Q
-// orthonormal, so the singular values of the matricisation A_k B_k are the square roots
-// of the eigenvalues of M = W^T G^R W (G^R = B_k B_k^T).  For the leading eigenpairs
+// as W W^T (any factor: here its Cholesky factor, columns whose pivot is at the level of
+// rounding dropped) one has A_k = Q W^T with Q orthonormal, so
+// the singular values of the matricisation A_k B_k are the square roots of the
+// eigenvalues of M = W^T G^R W (G^R = B_k B_k^T).  For the leading eigenpairs
 // (U_s, Sigma_s^2) of M the bond matrices Lk = G^R W U_s Sigma_s^{-2} and Rk = U_s^T W^T
 // satisfy A_k Lk Rk = Q U_s U_s^T Q^T A_k = P_k A_k, so inserting Lk Rk on every bond
-// applies all projectors; all bonds are processed in the same batched launches.  Only
-// W W^T = G^L is needed (no Lambda^{-1/2}), so eigenvectors of tiny Gram eigenvalues,
-// which a tridiagonal solver determines only up to about eps ||G|| / gap, do not
-// amplify; the inverse Sigma_s^{-2} only involves kept singular values.
+// applies all projectors; all bonds are processed in the same batched launches.  No
+// inverse of W or of a Gram eigenvalue appears; the inverse Sigma_s^{-2} only involves
+// kept singular values.
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
   const int L = x.L, N = x.N;
   const double delta = L > 1 ? eps / double(L - 1) : eps;
   BondGrams GL = left_grams(c, x);
   BondGrams GR = right_grams(c, x);
-  BondEig EL = eig_grams(c, x, GL, 1, L - 1);
-  auto thr = gram_thresholds(c, x, EL, 1, L - 1);
-  // W = V_L Lambda^{1/2} (columns with Lambda <= thr are zero)
+  // W W^T = G^L (+ kCholShift max diag) by a blocked Cholesky factorisation; offsets of the
+  // r x r blocks of every bond and sector
+  BondEig EL;
+  EL.voff.assign(L + 1, std::vector<int64_t>(N + 1, -1));
+  int64_t tv = 0;
+  for (int k = 1; k < L; ++k)
+    for (int n = 0; n <= N; ++n)
+      if (GL.off[k][n] >= 0) {
+        EL.voff[k][n] = tv;
+        tv += int64_t(x.rho[k][n]) * x.rho[k][n];
+      }
+  EL.V = Buf(c.pool, size_t(std::max<int64_t>(tv, 1)));
   Buf W(c.pool, EL.V.n);
-  std::vector<double> lam = download(c, EL.w.p, EL.w.n);
   {
-    // zero the dropped eigenvalues in a copy so that sqrt / inverse sqrt ignore them
-    std::vector<double> lam_c = lam;
+    std::vector<CholJob> jobs;
     for (int k = 1; k < L; ++k)
       for (int n = 0; n <= N; ++n)
-        if (EL.woff[k][n] >= 0)
-          for (int j = 0; j < x.rho[k][n]; ++j)
-            if (lam_c[EL.woff[k][n] + j] <= thr[k]) lam_c[EL.woff[k][n] + j] = 0.0;
-    Buf lamd(c.pool, lam_c.size());
-    PV_HIP(hipMemcpyAsync(lamd.p, lam_c.data(), lam_c.size() * 8, hipMemcpyHostToDevice, c.stream));
-    ScaleBatch sb;
-    for (int k = 1; k < L; ++k)
-      for (int n = 0; n <= N; ++n)
-        if (EL.voff[k][n] >= 0) {
-          const int r = x.rho[k][n];
-          sb.add(EL.V.p + EL.voff[k][n], r, W.p + EL.voff[k][n], r, r, r, lamd.p + EL.woff[k][n], false, true);
-        }
-    sb.run(c);
-    c.sync();  // lam_c must stay alive until the copy ran
+        if (EL.voff[k][n] >= 0) jobs.push_back(CholJob{GL.buf.p + GL.off[k][n], x.rho[k][n], W.p + EL.voff[k][n]});
+    chol_all(c, jobs);
   }
   // B = W^T G^R W for every bond and sector
   Buf Tm(c.pool, EL.V.n), Bm(c.pool, EL.V.n);

@@ -560,30 +560,34 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
       double part = 0.0;
       for (int i = k + lane; i < n; i += 64) {
         const double a = (k == 0 ? col[i] : nxt[i]) - vp[i] * qpk - qp[i] * vpk;
-        col[i] = a;
         vk[i] = a;
         if (i >= k + 2) part += a * a;
       }
       const double sig2 = wave_sum_d(part);
       __builtin_amdgcn_wave_barrier();
       const double x0 = vk[k + 1], akk = vk[k];
-      double beta = 0.0, v0 = x0, alpha = x0;
+      // reflector H = I - beta v v^T with v = (x - alpha e_1) / (x0 - alpha), so v_{k+1} = 1,
+      // |v_i| <= 1 and beta = 2 v0^2 / (v0^2 + sig2) lies in [1, 2] however small x is
+      double beta = 0.0, alpha = x0, inv = 0.0;
       if (sig2 != 0.0) {
         const double nrm = sqrt(x0 * x0 + sig2);
         alpha = x0 > 0.0 ? -nrm : nrm;
-        v0 = x0 - alpha;
-        beta = 2.0 / (v0 * v0 + sig2);
+        const double v0 = x0 - alpha;  // |v0| >= nrm
+        beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
+        inv = 1.0 / v0;
       }
       if (lane == 0) {
         ee[k] = alpha;
         dd[k] = akk;
         betas[k] = beta;
         red[0] = beta;
-        if (beta != 0.0) col[k + 1] = v0;  // v stored over the column
       }
       __builtin_amdgcn_wave_barrier();
-      for (int i = lane; i < n; i += 64)
-        vk[i] = (beta == 0.0 || i <= k) ? 0.0 : (i == k + 1 ? v0 : vk[i]);
+      for (int i = lane; i < n; i += 64) {
+        const double v = (beta == 0.0 || i <= k) ? 0.0 : (i == k + 1 ? 1.0 : vk[i] * inv);
+        vk[i] = v;
+        if (beta != 0.0 && i > k) col[i] = v;  // v stored below the diagonal
+      }
     }
     __syncthreads();
     const double beta = red[0];
@@ -1023,6 +1027,80 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
   PV_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// Panel of the blocked Cholesky factorisation (one workgroup per matrix).  The first panel
+// saves the original diagonal.  Wave 0 factors the kCholB x kCholB diagonal block in LDS
+// (lanes along rows), dropping columns whose pivot is at most kCholDrop times their
+// original diagonal entry; every thread then solves one row of the block below it,
+// x L11^T = a, by forward substitution (dropped columns give zeros).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void chol_panel_kernel(const CholDesc* __restrict__ descs, int j0) {
+  __shared__ double L11[kCholB][kCholB + 1];
+  __shared__ double dref[kCholB];
+  const CholDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (j0 >= n) return;
+  gdouble* A = gbl(D.A);
+  const int lda = D.lda;
+  const int tid = threadIdx.x, bs = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int jb = min(kCholB, n - j0);
+  gdouble* dg = gbl(D.dg);
+  if (j0 == 0) {
+    for (int i = tid; i < n; i += bs) dg[i] = A[i + (int64_t)i * lda];
+    __syncthreads();
+  }
+  for (int c = tid; c < jb; c += bs) dref[c] = dg[j0 + c];
+  for (int e = tid; e < jb * jb; e += bs) {
+    const int r = e % jb, c = e / jb;
+    L11[r][c] = r >= c ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    for (int k = 0; k < jb; ++k) {
+      const double d = L11[k][k];
+      const double l = d > kCholDrop * dref[k] ? sqrt(d) : 0.0;
+      const double inv = l > 0.0 ? 1.0 / l : 0.0;
+      __builtin_amdgcn_wave_barrier();
+      if (lane > k && lane < jb) L11[lane][k] *= inv;
+      if (lane == 0) L11[k][k] = l;
+      __builtin_amdgcn_wave_barrier();
+      for (int c = k + 1; c < jb; ++c)
+        if (lane >= c && lane < jb) L11[lane][c] -= L11[lane][k] * L11[c][k];
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  // the panel columns: zero above the diagonal, L11 on the diagonal block
+  for (int e = tid; e < (j0 + jb) * jb; e += bs) {
+    const int c = e / (j0 + jb), i = e - c * (j0 + jb);
+    A[i + (int64_t)(j0 + c) * lda] = i < j0 + c ? 0.0 : L11[i - j0][c];
+  }
+  // rows below the diagonal block
+  for (int i = j0 + jb + tid; i < n; i += bs) {
+    double x[kCholB];
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c) x[c] = c < jb ? A[i + (int64_t)(j0 + c) * lda] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c) {
+      if (c >= jb) continue;
+      double s = x[c];
+#pragma unroll
+      for (int k = 0; k < kCholB; ++k)
+        if (k < c) s -= x[k] * L11[c][k];
+      x[c] = L11[c][c] > 0.0 ? s / L11[c][c] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c)
+      if (c < jb) A[i + (int64_t)(j0 + c) * lda] = x[c];
+  }
+}
+
+void launch_chol_panel(const CholDesc* d, int nprob, int j0, hipStream_t s) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(chol_panel_kernel, dim3(nprob), dim3(256), 0, s, d, j0);
+  PV_LAUNCH_CHECK();
+}
+
 static size_t g_lds_limit = size_t(-1);
 
 // Largest dynamic LDS accepted for the LDS-resident variants (0 when the opt-in fails).
@@ -1070,6 +1148,12 @@ void launch_eig(const EigDesc* d, int nprob, int nmax, int mode, hipStream_t s) 
 // ---------------------------------------------------------------------------
 // W-step: one workgroup per (output block, output state b').
 // ---------------------------------------------------------------------------
+constexpr int kWElems = 8;  // output elements per thread per chunk of the W-step
+
+// One workgroup per (output block, output state b'): every thread owns kWElems elements
+// (a, c') of the block, computes their coordinates once per chunk and runs through the
+// CSR entries of row (s_out, b'), so the entry metadata is read once per chunk and the
+// kWElems gathers of an entry are issued together.
 __global__ __launch_bounds__(256) void wstep_kernel(const WItem* __restrict__ items,
                                                     const WBlock* __restrict__ blocks,
                                                     const WSrc* __restrict__ srcs,
@@ -1085,21 +1169,36 @@ __global__ __launch_bounds__(256) void wstep_kernel(const WItem* __restrict__ it
   const int row = B.s_out * w_out + it.bprime;
   const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
   const int bl = it.bprime - B.qoff_out;
-  const int64_t n = (int64_t)B.rows * B.cols;
-  const int64_t ldo = (int64_t)B.rows * B.wq_out;
-  for (int64_t x = threadIdx.x; x < n; x += blockDim.x) {
-    const int a = int(x % B.rows);
-    const int64_t c = x / B.rows;
-    double acc = 0.0;
+  const int rows = B.rows;
+  const int n = rows * B.cols;
+  const int64_t ldo = (int64_t)rows * B.wq_out;
+  gdouble* out = gbl(B.out) + (int64_t)rows * bl;
+  for (int x0 = 0; x0 < n; x0 += 256 * kWElems) {
+    int ar[kWElems], cr[kWElems];
+    double acc[kWElems];
+#pragma unroll
+    for (int r = 0; r < kWElems; ++r) {
+      const int x = x0 + r * 256 + (int)threadIdx.x;
+      ar[r] = x < n ? x % rows : 0;
+      cr[r] = x < n ? x / rows : 0;
+      acc[r] = 0.0;
+    }
     for (int e = e0; e < e1; ++e) {
       const int b = b_in[e];
       const int q = q_in[b] + 2;
       const int si = s_in[e];
       const double* base = S.base[si][q];
       if (base == nullptr) continue;
-      acc += val[e] * base[a + (int64_t)B.rows * (b - qoff_in[q]) + S.ld[si][q] * c];
+      const double v = val[e];
+      const int64_t ld = S.ld[si][q];
+      gcdouble* src = gbl(base) + (int64_t)rows * (b - qoff_in[q]);
+#pragma unroll
+      for (int r = 0; r < kWElems; ++r)
+        if (x0 + r * 256 + (int)threadIdx.x < n) acc[r] += v * src[ar[r] + ld * cr[r]];
     }
-    B.out[a + (int64_t)B.rows * bl + ldo * c] = acc;
+#pragma unroll
+    for (int r = 0; r < kWElems; ++r)
+      if (x0 + r * 256 + (int)threadIdx.x < n) out[ar[r] + ldo * cr[r]] = acc[r];
   }
 }
 

@@ -93,6 +93,22 @@ int eig_mode(int n);
 // which eigenvectors are returned as zero.
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
 inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(3) * n + 1; }
+// Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in
+// place (lower triangle; the upper triangle is zeroed).  A column whose pivot (Schur
+// complement diagonal) is at most kCholDrop times its original diagonal entry depends
+// linearly on the earlier columns to working accuracy and is set to zero, so the residual
+// A - W W^T stays at that level.  One launch per panel of kCholB columns: the panel kernel
+// factors the diagonal block and solves for the rows below it; the caller applies the
+// trailing update A22 -= L21 L21^T (a GEMM) before the next panel.  dg (n doubles) keeps
+// the original diagonal.
+struct CholDesc {
+  double* A;
+  double* dg;
+  int n, lda;
+};
+constexpr int kCholB = 32;
+constexpr double kCholDrop = 1e-12;
+void launch_chol_panel(const CholDesc* d, int nprob, int j0, hipStream_t s);
 void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
                   const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
                   const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,

@@ -48,6 +48,14 @@ def _block_diag(n, rng):
     return a[np.ix_(p, p)]
 
 
+def _zero_rows(n, rng):
+    a = _gram(n, max(1, n // 2), rng, graded=True)
+    z = rng.random(n) < 0.3
+    a[z, :] = 0.0
+    a[:, z] = 0.0
+    return a
+
+
 CASES = {
     "rand": lambda n, rng: _rand_sym(n, rng),
     "gram_rankdef": lambda n, rng: _gram(n, max(1, n // 5), rng),
@@ -58,6 +66,9 @@ CASES = {
     # Gram matrices of nearly orthonormal vectors: identity plus 1e-12 noise, and a
     # narrow band about 5 (spread 1e-6)
     "near_identity": lambda n, rng: np.eye(n) + 1e-12 * _rand_sym(n, rng),
+    # congruence W^T G W with a triangular factor W that has zero columns: exact zero rows
+    # and columns scattered through the matrix
+    "zero_rows": lambda n, rng: _zero_rows(n, rng),
     "narrow_band": lambda n, rng: 5 * np.eye(n) + 1e-6 * _rand_sym(n, rng),
 }
 

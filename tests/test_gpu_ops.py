@@ -193,3 +193,26 @@ def test_round_parallel_matches_simultaneous_truncation(ctx, eps, cap):
         assert np.linalg.norm(yg - y) <= 1e-8 * np.linalg.norm(x)
     finally:
         ctx.set_truncation(0)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-2])
+def test_round_parallel_large_sectors(ctx, eps):
+    # L=14, N=7: sector blocks up to 35 per state, 70 after the sum, so the Gram factors
+    # take several Cholesky panels and the eigenproblems the tridiagonal solver
+    L, N = 14, 7
+    _setup(ctx, "decayed", L, N, 0)
+    ctx.set_truncation(1)
+    try:
+        a, xa = _mps(ctx, L, N, 200, 21)
+        b, xb = _mps(ctx, L, N, 200, 22)
+        s = ctx.lincomb(1.0, a, -0.7, b)
+        x = xa - 0.7 * xb
+        r, cb = ctx.round(s, eps * np.linalg.norm(x), 10 ** 6)
+        y, rho_or, cb_or, margin = tt.truncate_parallel(x, L, N, eps * np.linalg.norm(x), 10 ** 6)
+        rho, yg = _dense(ctx, r)
+        assert np.linalg.norm(yg - y) <= 1e-8 * np.linalg.norm(x)
+        if margin > 1e-5:
+            for k in range(1, L):
+                assert {n: int(rho[k, n]) for n in rho_or[k]} == rho_or[k], k
+    finally:
+        ctx.set_truncation(0)
