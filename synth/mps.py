@@ -46,9 +46,36 @@ def layout(L: int, N: int, rho):
     return out
 
 
-def random_block_mps(L: int, N: int, rho, seed: int) -> np.ndarray:
+def random_block_mps(L: int, N: int, rho, seed: int, isometric: bool = False) -> np.ndarray:
+    """Random cores in export layout.  isometric=True draws, for every site k and right
+    sector n, the stacked blocks [U(k, n); O(k, n - 1)] as a random matrix with orthonormal
+    columns (Q of a Gaussian matrix; a scaled Gaussian when it has fewer rows than
+    columns), which gives states whose left parts are orthonormal: a well-conditioned gauge
+    like that of truncated iterates, without which Gram-based singular values lose accuracy
+    in proportion to the gauge's condition."""
     rng = np.random.default_rng(seed)
-    parts = []
-    for _, _, _, r, c in layout(L, N, rho):
-        parts.append(rng.standard_normal(r * c) / math.sqrt(max(r, 1)))
-    return np.concatenate(parts) if parts else np.zeros(0)
+    if not isometric:
+        parts = []
+        for _, _, _, r, c in layout(L, N, rho):
+            parts.append(rng.standard_normal(r * c) / math.sqrt(max(r, 1)))
+        return np.concatenate(parts) if parts else np.zeros(0)
+    blocks = {}
+    for k in range(1, L + 1):
+        left = set(sectors(L, N, k - 1))
+        for n in sectors(L, N, k):
+            parts = [(n, 0)] if n in left else []
+            if n - 1 in left:
+                parts.append((n - 1, 1))
+            rows = [int(rho[k - 1][m]) for m, _ in parts]
+            R, c = sum(rows), int(rho[k][n])
+            g = rng.standard_normal((R, c))
+            if R >= c and c > 0:
+                q, _ = np.linalg.qr(g)
+            else:
+                q = g / math.sqrt(max(R, 1))
+            r0 = 0
+            for (m, kind), r in zip(parts, rows):
+                blocks[(k, m, kind)] = q[r0:r0 + r, :]
+                r0 += r
+    out = [blocks[(k, n, kind)].reshape(-1, order="F") for k, n, kind, _, _ in layout(L, N, rho)]
+    return np.concatenate(out) if out else np.zeros(0)
