@@ -62,7 +62,8 @@ def summarize(db: str) -> str:
 
     con = sqlite3.connect(db)
     cur = con.cursor()
-    rng = cur.execute("select start, end from regions where name = ?", (TIMED_RANGE,)).fetchall()
+    rng = cur.execute("select start, end from regions where name = ? or extdata like ?",
+                      (TIMED_RANGE, f'%"message":"{TIMED_RANGE}"%')).fetchall()
     out = []
     windows = [("whole run", None)] + [(f"timed range '{TIMED_RANGE}'", r) for r in rng[:1]]
     for title, r in windows:
