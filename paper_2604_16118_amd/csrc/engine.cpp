@@ -541,6 +541,19 @@ EnvLayout env_layout(int m, int N, const std::vector<int>& bra_rho_m, const std:
 
 inline int wq_of(const std::array<int, 6>& qoff, int q) { return qoff[q + 3] - qoff[q + 2]; }
 
+// One output block of the W-step (output sector n2 and s_out, output charge q', all its
+// w_{q'} states b') and the T1 slices it reads: base[s_in][q_in + 2] points at the part of
+// T1 with physical index s_in and input charge q_in (null if absent), ld is its stride
+// between consecutive c'.
+struct WBlock {
+  double* out;
+  int rows, cols, wq_out, qoff_out, s_out, src;
+};
+struct WSrc {
+  const double* base[2][5];
+  int64_t ld[2][5];
+};
+
 // One site of a sweep: T1 = E x_k (GEMM), T2 = W_k T1 (W-step).
 // Output T2 grouped by (s_out, n2) with rows rho_bra[k-1][n2 - s_out] and the column
 // layout of the environment at cut k (`Ln`).  Returns the T2 buffer and offsets.
@@ -596,9 +609,13 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
   }
   t2.buf = Buf(c.pool, size_t(std::max<int64_t>(t2tot, 1)));
   const auto& qo_out = op.qoff[k];
+  const DevMpo::Site& st = op.site[k - 1];
+  const std::vector<int8_t>& chg_in = op.charge[k - 1];
   std::vector<WSrc> srcs;
   std::vector<WBlock> blocks;
-  std::vector<WItem> items;
+  std::vector<WTask> tasks;
+  std::vector<WEntry> entries;
+  double bytes = 0;
   for (int s = 0; s < 2; ++s)
     for (int n2 = 0; n2 <= N; ++n2) {
       if (t2.off[s][n2] < 0) continue;
@@ -631,27 +648,35 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
         B.qoff_out = qo_out[q2 + 2];
         B.s_out = s;
         B.src = sid;
-        const int bid = int(blocks.size());
         blocks.push_back(B);
-        for (int b = 0; b < B.wq_out; ++b) items.push_back(WItem{bid, B.qoff_out + b});
+        const int nel = rows * B.cols;
+        if (nel == 0) continue;
+        for (int b = 0; b < B.wq_out; ++b) {
+          // sparse entries of row (s_out, b') resolved to source slices of T1
+          const int row = s * st.w_out + B.qoff_out + b;
+          const int e0 = int(entries.size());
+          for (int e = st.row_ptr[row]; e < st.row_ptr[row + 1]; ++e) {
+            const int bi = st.b_in[e];
+            const int q = chg_in[bi] + 2;
+            const double* base = src.base[st.s_in[e]][q];
+            if (!base) continue;
+            entries.push_back(WEntry{base + int64_t(rows) * (bi - qo_in[q]), src.ld[st.s_in[e]][q], st.val[e]});
+          }
+          const int e1 = int(entries.size());
+          bytes += 8.0 * nel * (e1 - e0 + 1);
+          for (int x0 = 0; x0 < nel; x0 += kWTask)
+            tasks.push_back(WTask{B.out + int64_t(rows) * b, int64_t(rows) * B.wq_out, rows, nel, x0, e0, e1});
+        }
       }
     }
-  if (!items.empty()) {
-    WItem* di = c.upload(items);
-    WBlock* db = c.upload(blocks);
-    WSrc* ds = c.upload(srcs);
-    const DevMpo::Site& st = op.site[k - 1];
-    double bytes = 0;
-    for (const WBlock& B : blocks) bytes += 16.0 * B.rows * double(B.cols) * B.wq_out;
+  if (!tasks.empty()) {
+    WTask* dt = c.upload(tasks);
+    WEntry* de = c.upload(entries);
     hipEvent_t a; c.begin(T_WSTEP, a);
-    launch_wstep(di, int(items.size()), db, ds, reinterpret_cast<const int32_t*>(st.row_ptr.p),
-                 reinterpret_cast<const int32_t*>(st.b_in.p), reinterpret_cast<const uint8_t*>(st.s_in.p),
-                 reinterpret_cast<const int8_t*>(op.charge[k - 1].p),
-                 reinterpret_cast<const int32_t*>(op.qoffd[k - 1].p), st.val.p, st.w_out, c.stream);
+    launch_wstep(dt, int(tasks.size()), de, c.stream);
     c.end(T_WSTEP, a, 0, bytes);
   }
   // dense charge blocks of W_k: T2[a, b', c'] += sum_b T1[a, b, c'] W[b, b'], one GEMM per c'
-  const DevMpo::Site& st = op.site[k - 1];
   if (!st.dense.empty()) {
     // several dense blocks may accumulate into one output block: the k-th contribution to
     // each output goes to launch k, so no launch has two problems writing the same output
@@ -694,18 +719,12 @@ std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m) {
   d->qoff = m.qoff;
   d->site.resize(m.L);
   d->charge.resize(m.L + 1);
-  d->qoffd.resize(m.L + 1);
   auto put = [&](const void* src, size_t bytes) {
     Buf b(c.pool, std::max<size_t>((bytes + 7) / 8, 1));
     if (bytes) PV_HIP(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
     return b;
   };
-  for (int k = 0; k <= m.L; ++k) {
-    d->charge[k] = put(m.charge[k].data(), m.charge[k].size());
-    std::array<int32_t, 6> qo;
-    for (int i = 0; i < 6; ++i) qo[i] = m.qoff[k][i];
-    d->qoffd[k] = put(qo.data(), sizeof(qo));
-  }
+  for (int k = 0; k <= m.L; ++k) d->charge[k].assign(m.charge[k].begin(), m.charge[k].end());
   for (int k = 0; k < m.L; ++k) {
     const MpoSite& st = m.site[k];
     // charge blocks dense enough for a GEMM
@@ -753,10 +772,10 @@ std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m) {
       si[p] = st.s_in[e];
       vv[p] = st.val[e];
     }
-    d->site[k].row_ptr = put(rp.data(), rp.size() * 4);
-    d->site[k].b_in = put(bi.data(), bi.size() * 4);
-    d->site[k].s_in = put(si.data(), si.size());
-    d->site[k].val = put(vv.data(), vv.size() * 8);
+    d->site[k].row_ptr = std::move(rp);
+    d->site[k].b_in = std::move(bi);
+    d->site[k].s_in = std::move(si);
+    d->site[k].val = std::move(vv);
     d->site[k].w_out = st.w_out;
     d->nnz += int64_t(st.val.size());
   }

@@ -104,14 +104,17 @@ struct DevMpo {
     int q_in, q_out, s_in, s_out, w_in, w_out;
     Buf W;
   };
+  // Sparse part (entries not in a dense block) as CSR over rows s_out * w_out + b_out,
+  // kept on the host: the W-step resolves it into source pointers per launch.
   struct Site {
-    Buf row_ptr, b_in, s_in, val;  // int32 / uint8 stored in double-sized buffers
+    std::vector<int32_t> row_ptr, b_in;
+    std::vector<uint8_t> s_in;
+    std::vector<double> val;
     int w_out = 0;
     std::vector<Dense> dense;
   };
   std::vector<Site> site;
-  std::vector<Buf> charge;  // int8 per cut
-  std::vector<Buf> qoffd;   // int32[6] per cut
+  std::vector<std::vector<int8_t>> charge;  // charge of every state, per cut
   int64_t nnz = 0;
 };
 

@@ -1148,67 +1148,40 @@ void launch_eig(const EigDesc* d, int nprob, int nmax, int mode, hipStream_t s) 
 // ---------------------------------------------------------------------------
 // W-step: one workgroup per (output block, output state b').
 // ---------------------------------------------------------------------------
-constexpr int kWElems = 8;  // output elements per thread per chunk of the W-step
-
-// One workgroup per (output block, output state b'): every thread owns kWElems elements
-// (a, c') of the block, computes their coordinates once per chunk and runs through the
-// CSR entries of row (s_out, b'), so the entry metadata is read once per chunk and the
-// kWElems gathers of an entry are issued together.
-__global__ __launch_bounds__(256) void wstep_kernel(const WItem* __restrict__ items,
-                                                    const WBlock* __restrict__ blocks,
-                                                    const WSrc* __restrict__ srcs,
-                                                    const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ b_in,
-                                                    const uint8_t* __restrict__ s_in,
-                                                    const int8_t* __restrict__ q_in,
-                                                    const int32_t* __restrict__ qoff_in,
-                                                    const double* __restrict__ val, int w_out) {
-  const WItem it = items[blockIdx.x];
-  const WBlock B = blocks[it.block];
-  const WSrc& S = srcs[B.src];
-  const int row = B.s_out * w_out + it.bprime;
-  const int e0 = row_ptr[row], e1 = row_ptr[row + 1];
-  const int bl = it.bprime - B.qoff_out;
-  const int rows = B.rows;
-  const int n = rows * B.cols;
-  const int64_t ldo = (int64_t)rows * B.wq_out;
-  gdouble* out = gbl(B.out) + (int64_t)rows * bl;
-  for (int x0 = 0; x0 < n; x0 += 256 * kWElems) {
-    int ar[kWElems], cr[kWElems];
-    double acc[kWElems];
+// One workgroup per task: every thread owns kWElems elements of the task, computes their
+// coordinates once and accumulates over the task's entries (read as uniform loads), so
+// the kWElems gathers of an entry are issued together.  Tasks without entries write zeros.
+__global__ __launch_bounds__(256) void wstep_kernel(const WTask* __restrict__ tasks,
+                                                    const WEntry* __restrict__ entries) {
+  const WTask t = tasks[blockIdx.x];
+  const int rows = t.rows;
+  int ar[kWElems], cr[kWElems];
+  bool ok[kWElems];
+  double acc[kWElems];
 #pragma unroll
-    for (int r = 0; r < kWElems; ++r) {
-      const int x = x0 + r * 256 + (int)threadIdx.x;
-      ar[r] = x < n ? x % rows : 0;
-      cr[r] = x < n ? x / rows : 0;
-      acc[r] = 0.0;
-    }
-    for (int e = e0; e < e1; ++e) {
-      const int b = b_in[e];
-      const int q = q_in[b] + 2;
-      const int si = s_in[e];
-      const double* base = S.base[si][q];
-      if (base == nullptr) continue;
-      const double v = val[e];
-      const int64_t ld = S.ld[si][q];
-      gcdouble* src = gbl(base) + (int64_t)rows * (b - qoff_in[q]);
-#pragma unroll
-      for (int r = 0; r < kWElems; ++r)
-        if (x0 + r * 256 + (int)threadIdx.x < n) acc[r] += v * src[ar[r] + ld * cr[r]];
-    }
+  for (int r = 0; r < kWElems; ++r) {
+    const int x = t.x0 + r * 256 + (int)threadIdx.x;
+    ok[r] = x < t.n;
+    ar[r] = ok[r] ? x % rows : 0;
+    cr[r] = ok[r] ? x / rows : 0;
+    acc[r] = 0.0;
+  }
+  for (int e = t.e0; e < t.e1; ++e) {
+    const WEntry E = entries[e];
+    gcdouble* src = gbl(E.src);
 #pragma unroll
     for (int r = 0; r < kWElems; ++r)
-      if (x0 + r * 256 + (int)threadIdx.x < n) out[ar[r] + ldo * cr[r]] = acc[r];
+      if (ok[r]) acc[r] += E.val * src[ar[r] + E.ld * cr[r]];
   }
+  gdouble* out = gbl(t.out);
+#pragma unroll
+  for (int r = 0; r < kWElems; ++r)
+    if (ok[r]) out[ar[r] + t.ldo * cr[r]] = acc[r];
 }
 
-void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
-                  const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
-                  const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,
-                  hipStream_t s) {
-  if (nitems <= 0) return;
-  hipLaunchKernelGGL(wstep_kernel, dim3(nitems), dim3(256), 0, s, items, blocks, srcs, row_ptr,
-                     b_in, s_in, q_in, qoff_in, val, w_out);
+void launch_wstep(const WTask* tasks, int ntasks, const WEntry* entries, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(wstep_kernel, dim3(ntasks), dim3(256), 0, s, tasks, entries);
   PV_LAUNCH_CHECK();
 }
 

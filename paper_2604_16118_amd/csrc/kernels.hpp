@@ -40,26 +40,22 @@ struct EigDesc {
   double abs_tol;  // rotations need |a_pq| > abs_tol * max_i |a_ii| (0: relative test only)
 };
 
-// W-step (application of one MPO site to a partially contracted tensor).
-// Output block: T2[a, b', c'] (a < rows, b' < wq_out, c' < cols), column-major in
-// (a, b', c').  For output state b' (global index bglob), with local operator
-// entries of row (s_out, bglob) in the CSR arrays: value += val * src[s_in][q_in].
-struct WBlock {
+// W-step (application of one MPO site to a partially contracted tensor).  Task t writes
+// the elements x in [x0, min(x0 + kWTask, n)) of one output block, x = a + rows c',
+// out[a + ldo c'] = sum over the task's entries e of val_e * src_e[a + ld_e c'].  The host
+// resolves the MPO's sparse entries into (source pointer, stride, coefficient) triples.
+struct WEntry {
+  const double* src;
+  int64_t ld;
+  double val;
+};
+struct WTask {
   double* out;
-  int rows, cols, wq_out, qoff_out;
-  int s_out;
-  int src;  // index of the WSrc table row (8 entries: s_in*4... see kernels.hip)
+  int64_t ldo;
+  int rows, n, x0, e0, e1;
 };
-struct WSrc {
-  const double* base[2][5];  // [s_in][q_in + 2], null if absent
-  int64_t ld[2][5];          // stride between consecutive c' (rows * w_q of the source)
-  int rows_w[2][5];          // rows of the source (must equal the output rows)
-  int col0[2][5];            // first column of the s_in part in the source block
-};
-struct WItem {
-  int block;
-  int bprime;  // global state index at the output cut
-};
+constexpr int kWElems = 8;              // output elements per thread
+constexpr int kWTask = 256 * kWElems;   // output elements per task (one workgroup)
 
 // Batched copies dst = alpha * src of r x c sub-blocks (column-major).
 struct CopyDesc {
@@ -109,10 +105,7 @@ struct CholDesc {
 constexpr int kCholB = 32;
 constexpr double kCholDrop = 1e-12;
 void launch_chol_panel(const CholDesc* d, int nprob, int j0, hipStream_t s);
-void launch_wstep(const WItem* items, int nitems, const WBlock* blocks, const WSrc* srcs,
-                  const int32_t* row_ptr, const int32_t* b_in, const uint8_t* s_in,
-                  const int8_t* q_in, const int32_t* qoff_in, const double* val, int w_out,
-                  hipStream_t s);
+void launch_wstep(const WTask* tasks, int ntasks, const WEntry* entries, hipStream_t s);
 void launch_copy(const CopyDesc* d, int nd, int64_t total, hipStream_t s);
 void launch_scale(const ScaleDesc* d, int nd, int64_t total, hipStream_t s);
 void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
