@@ -45,8 +45,11 @@ __device__ inline double wave_sum_d(double v) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nprob) {
   constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread per K-tile
+  // double-buffered K-tiles: the global loads of tile t+1 are held in registers while the
+  // MFMAs of tile t run, then written to the other LDS buffer (one barrier per K-tile)
+  __shared__ double As[2][BK][BM + 1];
+  __shared__ double Bs[2][BK][BN + 1];
   const int tile = blockIdx.x;
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
@@ -62,42 +65,63 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
+  // per-thread element coordinates inside a K-tile (fastest index along contiguous memory)
+  int ai[LA], ak[LA], bj[LB], bk[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int e = tid + 256 * r;
+    if (!g.ta) { ai[r] = e % BM; ak[r] = e / BM; } else { ak[r] = e % BK; ai[r] = e / BK; }
+  }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int e = tid + 256 * r;
+    if (!g.tb) { bk[r] = e % BK; bj[r] = e / BK; } else { bj[r] = e % BN; bk[r] = e / BN; }
+  }
+  double ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int gi = row0 + ai[r], gk = k0 + ak[r];
+      ra[r] = (gi < g.M && gk < g.kend) ? (g.ta ? gA[gk + (int64_t)gi * g.lda] : gA[gi + (int64_t)gk * g.lda]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int gj = col0 + bj[r], gk = k0 + bk[r];
+      rb[r] = (gj < g.N && gk < g.kend) ? (g.tb ? gB[gj + (int64_t)gk * g.ldb] : gB[gk + (int64_t)gj * g.ldb]) : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) As[buf][ak[r]][ai[r]] = ra[r];
+#pragma unroll
+    for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = rb[r];
+  };
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
+  int buf = 0;
+  if (g.kbeg < g.kend) {
+    load(g.kbeg);
+    stage(0);
+  }
+  __syncthreads();
   for (int k0 = g.kbeg; k0 < g.kend; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      int i, k;
-      if (!g.ta) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
-      const int gi = row0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < g.M && gk < g.kend)
-        v = g.ta ? gA[gk + (int64_t)gi * g.lda] : gA[gi + (int64_t)gk * g.lda];
-      As[k][i] = v;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int j, k;
-      if (!g.tb) { k = e % BK; j = e / BK; } else { j = e % BN; k = e / BN; }
-      const int gj = col0 + j, gk = k0 + k;
-      double v = 0.0;
-      if (gj < g.N && gk < g.kend)
-        v = g.tb ? gB[gj + (int64_t)gk * g.ldb] : gB[gk + (int64_t)gj * g.ldb];
-      Bs[k][j] = v;
-    }
-    __syncthreads();
+    const bool more = k0 + BK < g.kend;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double a0 = As[kk + lk][wr * 32 + li];
-      double a1 = As[kk + lk][wr * 32 + 16 + li];
-      double b0 = Bs[kk + lk][wc * 32 + li];
-      double b1 = Bs[kk + lk][wc * 32 + 16 + li];
+      const double a0 = As[buf][kk + lk][wr * 32 + li];
+      const double a1 = As[buf][kk + lk][wr * 32 + 16 + li];
+      const double b0 = Bs[buf][kk + lk][wc * 32 + li];
+      const double b1 = Bs[buf][kk + lk][wc * 32 + 16 + li];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   for (int mi = 0; mi < 2; ++mi)
     for (int nj = 0; nj < 2; ++nj)
