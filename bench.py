@@ -26,17 +26,19 @@ sys.path.insert(0, ROOT)
 PEAK = {  # MI355X published peaks
     "fp64_mfma_tflops": 78.6,
     "fp64_vector_tflops": 78.6,
+    "fp32_mfma_tflops": 157.3,
     "hbm_gbs": 8000.0,
 }
 # library timer class -> (HIP kernel, roofline bound)
 KERNELS = {
-    "gemm_f64_mfma": ("gemm_f64_kernel", "mfma"),
+    "gemm_f64_mfma": ("gemm_kernel<0>", "mfma"),
     "tridiag_eig_f64": ("tridiag_eig_kernel", "alu"),
     "jacobi_eig_f64": ("jacobi_eig_kernel", "alu"),
     "mpo_wstep": ("wstep_kernel", "hbm"),
     "copy_scale": ("copy_kernel/scale_kernel", "hbm"),
     "reduce": ("reduce_kernel", "hbm"),
     "cholesky_f64": ("chol_panel_kernel", "alu"),
+    "gemm_f32_mfma": ("gemm_kernel<1>", "mfma32"),
 }
 
 
@@ -128,6 +130,7 @@ def main():
     ap.add_argument("--cap", type=int, default=512)
     ap.add_argument("--m-zip", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
     a = ap.parse_args()
     if a.summarize:
@@ -145,29 +148,40 @@ def main():
     t = time.perf_counter()
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
     print(f"# setup {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
-    t = time.perf_counter()
-    res_w, hist_w, psi = ctx.run(max_iter=a.warmup, **common)
-    print(f"# warmup {a.warmup} it {time.perf_counter() - t:.1f}s ranks {[r['max_rank'] for r in hist_w]}",
-          file=sys.stderr, flush=True)
-    ctx.timers_reset()
     rtx = _roctx()
-    if rtx:
-        rtx.roctxRangePushA(TIMED_RANGE.encode())
-    t0 = time.perf_counter()
-    res, hist, psi2 = ctx.run(max_iter=a.steps, start=psi, resume=res_w, **common)
-    t1 = time.perf_counter()
-    if rtx:
-        rtx.roctxRangePop()
-    tm = ctx.timers()
-    elapsed = t1 - t0
+
+    def run_mode(precision: int, mark: bool):
+        common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1,
+                      precision=precision)
+        t = time.perf_counter()
+        res_w, hist_w, psi = ctx.run(max_iter=a.warmup, **common)
+        print(f"# precision {precision}: warmup {a.warmup} it {time.perf_counter() - t:.1f}s ranks "
+              f"{[r['max_rank'] for r in hist_w]}", file=sys.stderr, flush=True)
+        ctx.timers_reset()
+        if mark and rtx:
+            rtx.roctxRangePushA(TIMED_RANGE.encode())
+        t0 = time.perf_counter()
+        res, hist, psi2 = ctx.run(max_iter=a.steps, start=psi, resume=res_w, **common)
+        t1 = time.perf_counter()
+        if mark and rtx:
+            rtx.roctxRangePop()
+        tm = ctx.timers()
+        ctx.mps_free(psi)
+        ctx.mps_free(psi2)
+        return dict(elapsed=t1 - t0, res=res, hist=hist, timers=tm)
+
+    r64 = run_mode(0, True)
+    r32 = None if a.no_mixed else run_mode(1, False)
+    tm = r64["timers"]
+    res, hist, elapsed = r64["res"], r64["hist"], r64["elapsed"]
     steps = len(hist)
     # dominant kernel class over the timed region
     dom_name, dom = max(tm.items(), key=lambda kv: kv[1]["ms"])
     kernel, bound = KERNELS[dom_name]
-    if bound == "mfma":
+    if bound in ("mfma", "mfma32"):
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s"}
+        peak = PEAK["fp64_mfma_tflops"] if bound == "mfma" else PEAK["fp32_mfma_tflops"]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     elif bound == "alu":
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp64_vector_tflops"], "unit": "TFLOP/s"}
@@ -207,6 +221,23 @@ def main():
                            for k, v in tm.items()},
         "roofline": roof,
     }
+    if r32 is not None:
+        h32, t32 = r32["hist"], r32["timers"]
+        g32 = t32["gemm_f32_mfma"]
+        n = min(len(h32), len(hist))
+        out["mixed_fp32"] = {
+            "what": "operator contractions (H psi, Ritz sandwiches) on float32 MFMA with float32 "
+                    "accumulation; truncation, norms, Rayleigh quotient and residual in float64; "
+                    "same start, warmup and steps as the float64 run",
+            "value": len(h32) / r32["elapsed"],
+            "unit": "iter/s",
+            "ms_per_step": 1e3 * r32["elapsed"] / max(len(h32), 1),
+            "block_gemm_tflops_f32": g32["flops"] / max(g32["ms"], 1e-9) / 1e9,
+            "energy": r32["res"]["energy"],
+            "dE_vs_fp64": abs(r32["res"]["energy"] - res["energy"]),
+            "dE_vs_fp64_max_over_steps": max([abs(h32[i]["E"] - hist[i]["E"]) for i in range(n)] + [0.0]),
+            "timers_ms": {k: round(v["ms"], 3) for k, v in t32.items()},
+        }
     ctx.close()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -71,7 +71,11 @@ typedef struct {
   double c_lower;   /* C_lower of eq. lowerupper (enters alpha_0 only); <= 0: 1 */
   double c_upper;   /* C_upper of eq. lowerupper; <= 0: 1 */
   int max_retries;  /* limit of the residual-tolerance reductions per iteration */
-  int precision;    /* 0: float64 everywhere (the only mode implemented) */
+  int precision;    /* 0: float64 everywhere; 1: the operator contractions of H psi and of
+                     *    the two Ritz sandwiches run on float32 MFMA (operands rounded to
+                     *    float32, float32 accumulation), while truncations, norms, the
+                     *    Rayleigh quotient lambda and the residual stay float64; other
+                     *    values give PV_EINVAL */
   int truncation;   /* 0: sequential TT-SVD truncation (eq. ttsvdquasiopt), two-pass Gram
                      *    factorisations; 1: simultaneous truncation of all bonds from Gram
                      *    matrices (tolerance eps/(L-1) per bond), see pv_set_truncation */
@@ -165,9 +169,9 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
  * 10/3 n^3 each; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic bytes,
- * for i < n classes (seven classes: grouped GEMM, Jacobi eigensolver, MPO W-step,
- * copy/scale, reduction, tridiagonal eigensolver, Cholesky panels); names via
- * pv_timer_name. */
+ * for i < n classes (eight classes: grouped GEMM float64, Jacobi eigensolver, MPO W-step,
+ * copy/scale, reduction, tridiagonal eigensolver, Cholesky panels, grouped GEMM float32);
+ * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);

@@ -364,6 +364,14 @@ pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap
 }
 
 // Algorithm 2 on psi = S x (see the oracle's pinvit module for the step list).
+// While alive, operator contractions use float32 MFMA if the run asked for it.
+struct LowPrecision {
+  Ctx& c;
+  bool old;
+  explicit LowPrecision(Ctx& cx) : c(cx), old(cx.lowp) { c.lowp = c.prec == 1; }
+  ~LowPrecision() { c.lowp = old; }
+};
+
 pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, pv_iter* hist,
                  int hist_cap, int* psi_out) {
   return guard([&] {
@@ -374,7 +382,9 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
     if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
       fail(PV_EINVAL, "invalid parameters");
-    if (p.precision != 0) fail(PV_EINVAL, "only precision 0 (float64) is implemented");
+    if (p.precision != 0 && p.precision != 1)
+      fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32 contractions)");
+    c.prec = p.precision;
     if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
     c.trunc_mode = p.truncation;
     // outputs of the sequential truncation are left-orthogonal (norm = last core)
@@ -411,7 +421,11 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       const double lam = expect_h(c, *psi, *psi);
       double est;
       if (s_prev < 0) {
-        auto y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
+        std::unique_ptr<Mps> y0;
+        {
+          LowPrecision lp(c);
+          y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
+        }
         auto d0 = mps_lincomb(c, 1.0, *y0, -lam, *psi);
         auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
         est = c.s_max * mnorm(*r0);
@@ -428,7 +442,11 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       while (true) {
         bool cb1 = false, cb2 = false, cb3 = false;
         const double e12 = eta / (3.0 * c.s_max);
-        auto y = apply_h(c, *psi, e12, cap, mz, &cb1);
+        std::unique_ptr<Mps> y;
+        {
+          LowPrecision lp(c);
+          y = apply_h(c, *psi, e12, cap, mz, &cb1);
+        }
         auto d = mps_lincomb(c, 1.0, *y, -lam, *psi);
         y.reset();
         r = round_mps(c, *d, e12, cap, &cb2);
@@ -473,8 +491,12 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
       auto z2 = mps_scaled_copy(c, *pdir, 1.0 / np, nullptr);
       pdir.reset();
-      const double h12 = expect_h(c, *psi, *z2);
-      const double h22 = expect_h(c, *z2, *z2);
+      double h12, h22;
+      {
+        LowPrecision lp(c);  // the Ritz sandwiches may use the low-precision contractions
+        h12 = expect_h(c, *psi, *z2);
+        h22 = expect_h(c, *z2, *z2);
+      }
       const double o12 = dot(c, *psi, *z2);
       const double hm[3] = {lam, h12, h22}, mm[3] = {1.0, o12, 1.0};
       double lam_s, v[2];
@@ -525,7 +547,7 @@ pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
 }
 
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
-                                            "tridiag_eig_f64", "cholesky_f64"};
+                                            "tridiag_eig_f64", "cholesky_f64", "gemm_f32_mfma"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

@@ -213,6 +213,7 @@ namespace {
 
 struct GemmBatch {
   std::vector<GemmDesc> d;
+  int prec = 0;  // 1: float32 MFMA (operator contractions in the mixed-precision mode)
   void add(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc,
            int M, int N, int K, double alpha, double beta) {
     if (M <= 0 || N <= 0) return;
@@ -277,9 +278,10 @@ struct GemmBatch {
     }
     if (!list.empty()) {
       GemmDesc* dd = c.upload(list);
-      hipEvent_t a; c.begin(T_GEMM, a);
-      launch_gemm(dd, int(list.size()), int(tiles), c.stream);
-      c.end(T_GEMM, a, flops, bytes);
+      const int cls = prec ? T_GEMM32 : T_GEMM;
+      hipEvent_t a; c.begin(cls, a);
+      launch_gemm(dd, int(list.size()), int(tiles), prec, c.stream);
+      c.end(cls, a, flops, bytes);
     }
     if (!red.empty()) {
       ReduceDesc* dr = c.upload(red);
@@ -581,6 +583,7 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
     }
   Buf T1(c.pool, size_t(std::max<int64_t>(t1tot, 1)));
   GemmBatch gb;
+  gb.prec = c.lowp ? 1 : 0;
   for (int na = 0; na <= N; ++na)
     for (int q = -2; q <= 2; ++q) {
       const int64_t o = t1off[na * 5 + q + 2];
@@ -694,7 +697,10 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
         const double* base = src.base[D.s_in][D.q_in + 2];
         if (!base) continue;
         const int64_t ld = src.ld[D.s_in][D.q_in + 2];
-        if (int(gd.size()) <= slot) gd.emplace_back();
+        if (int(gd.size()) <= slot) {
+          gd.emplace_back();
+          gd.back().prec = c.lowp ? 1 : 0;
+        }
         for (int cc = 0; cc < B.cols; ++cc)
           gd[slot].add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
                        B.rows, B.wq_out, D.w_in, 1.0, 1.0);

@@ -118,7 +118,7 @@ struct DevMpo {
   int64_t nnz = 0;
 };
 
-enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_COUNT };
+enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_COUNT };
 
 struct Ctx {
   int device = 0;
@@ -131,6 +131,11 @@ struct Ctx {
   std::vector<double> h, v;
   std::unique_ptr<DevMpo> hmpo;
   std::unique_ptr<DevMpo> ident;  // identity operator (dot products)
+  // precision of the contractions: 0 float64; 1 float32 MFMA for the operator contractions
+  // (H psi and the Ritz sandwiches) while truncations, norms and the Rayleigh quotient stay
+  // float64.  lowp is set while a float32-eligible contraction runs.
+  int prec = 0;
+  bool lowp = false;
   std::vector<int> mpo_w;
   // preconditioner (Section 4.3, Section 7.1.1)
   std::vector<double> theta;

@@ -8,6 +8,7 @@
 #include <stdexcept>
 #include <string>
 
+#include <type_traits>
 #include "kernels.hpp"
 
 namespace pv {
@@ -38,18 +39,23 @@ __device__ inline double wave_sum_d(double v) {
 
 // ---------------------------------------------------------------------------
 // Grouped GEMM.  One workgroup (4 waves) computes a 64x64 tile of one problem;
-// each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_f64_16x16x4f64.
-// Operand layout of that instruction (wave64): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; the 16x16 result lives in 4 doubles per lane, element r of lane l
-// being D[4*r + l/16][l%16] (measured with a single-instruction probe on gfx950).
+// each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_f64_16x16x4f64 (or
+// v_mfma_f32_16x16x4f32 in the float32 variant).  Operand layout of both (wave64): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; the 16x16 result lives in 4 values per lane,
+// element r of lane l being D[4r + l/16][l%16] for float64 and D[4(l/16) + r][l%16] for
+// float32 (both measured with single-instruction probes on gfx950).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nprob) {
+template <int PREC>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob) {
+  // PREC 0: float64 operands on v_mfma_f64_16x16x4f64; PREC 1: operands rounded to float32
+  // on v_mfma_f32_16x16x4f32 with float32 accumulation (C stays float64 in memory)
+  typedef typename std::conditional<PREC == 0, double, float>::type T;
   constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread per K-tile
   // double-buffered K-tiles: the global loads of tile t+1 are held in registers while the
   // MFMAs of tile t run, then written to the other LDS buffer (one barrier per K-tile)
-  __shared__ double As[2][BK][BM + 1];
-  __shared__ double Bs[2][BK][BN + 1];
+  __shared__ T As[2][BK][BM + 1];
+  __shared__ T Bs[2][BK][BN + 1];
   const int tile = blockIdx.x;
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
@@ -92,13 +98,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) As[buf][ak[r]][ai[r]] = ra[r];
+    for (int r = 0; r < LA; ++r) As[buf][ak[r]][ai[r]] = T(ra[r]);
 #pragma unroll
-    for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = rb[r];
+    for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = T(rb[r]);
   };
-  d4 acc[2][2];
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  T4 acc[2][2];
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = T4{0, 0, 0, 0};
   int buf = 0;
   if (g.kbeg < g.kend) {
     load(g.kbeg);
@@ -110,14 +117,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
     if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const double a0 = As[buf][kk + lk][wr * 32 + li];
-      const double a1 = As[buf][kk + lk][wr * 32 + 16 + li];
-      const double b0 = Bs[buf][kk + lk][wc * 32 + li];
-      const double b1 = Bs[buf][kk + lk][wc * 32 + 16 + li];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = As[buf][kk + lk][wr * 32 + li];
+      const T a1 = As[buf][kk + lk][wr * 32 + 16 + li];
+      const T b0 = Bs[buf][kk + lk][wc * 32 + li];
+      const T b1 = Bs[buf][kk + lk][wc * 32 + 16 + li];
+      if constexpr (PREC == 0) {
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      } else {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
     }
     if (more) stage(buf ^ 1);
     __syncthreads();
@@ -126,10 +140,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   for (int mi = 0; mi < 2; ++mi)
     for (int nj = 0; nj < 2; ++nj)
       for (int r = 0; r < 4; ++r) {
-        const int i = row0 + wr * 32 + mi * 16 + 4 * r + lk;
+        // result element r of lane l: row 4r + l/16 (float64 instruction), row
+        // 4 (l/16) + r (float32 instruction), column l % 16 (measured on gfx950)
+        const int i = row0 + wr * 32 + mi * 16 + (PREC == 0 ? 4 * r + lk : 4 * lk + r);
         const int j = col0 + wc * 32 + nj * 16 + li;
         if (i < g.M && j < g.N) {
-          double v = g.alpha * acc[mi][nj][r];
+          double v = g.alpha * double(acc[mi][nj][r]);
           gdouble* c = gC + i + (int64_t)j * g.ldc;
           if (g.beta != 0.0) v += g.beta * *c;
           *c = v;
@@ -137,9 +153,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
       }
 }
 
-void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, hipStream_t s) {
+void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s) {
   if (total_tiles <= 0) return;
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+  if (prec == 0)
+    hipLaunchKernelGGL(gemm_kernel<0>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+  else
+    hipLaunchKernelGGL(gemm_kernel<1>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
   PV_LAUNCH_CHECK();
 }
 

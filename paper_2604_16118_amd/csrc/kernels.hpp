@@ -77,7 +77,8 @@ struct ScaleDesc {
   int sqrt_s;  // 1: use sqrt(max(s[j], 0))
 };
 
-void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, hipStream_t s);
+// prec 0: float64 MFMA; prec 1: operands rounded to float32, float32 MFMA accumulation.
+void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 // mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
 // problems of one launch must admit the chosen mode at size nmax.

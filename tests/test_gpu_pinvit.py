@@ -77,3 +77,31 @@ def test_pinvit_parallel_truncation_matches_oracle(ctx):
     for a, b in zip(hist_g, hist_o):
         assert abs(a["E"] - b["E"]) <= 1e-6 * abs(b["E"])
         assert a["lam"] >= w[0] - 1e-10
+
+
+@pytest.mark.parametrize("kind,L,N,seed,cap,iters", [("dense", 8, 4, 0, 16, 20), ("decayed", 12, 6, 0, 24, 12)])
+def test_pinvit_float32_contractions_track_float64(ctx, kind, L, N, seed, cap, iters):
+    # mixed precision: H psi and the Ritz sandwiches on float32 MFMA, lambda, truncations
+    # and norms in float64; every energy is the float64 Rayleigh quotient of its iterate, so
+    # it stays above the ground state and follows the float64 run to 1e-6 relative
+    p = make_problem(kind, L, N, seed)
+    w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=2)
+    delta = w[1] / (w[1] - w[0])
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    kw = dict(rank_cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta, truncation=1)
+    _, h64, _ = ctx.run(precision=0, **kw)
+    _, h32, _ = ctx.run(precision=1, **kw)
+    assert len(h32) == len(h64)
+    for a, b in zip(h32, h64):
+        assert a["lam"] >= w[0] - 1e-10
+        assert abs(a["E"] - b["E"]) <= 1e-6 * abs(b["E"])
+    t = ctx.timers()
+    assert t["gemm_f32_mfma"]["calls"] > 0
+
+
+def test_precision_bf16_is_rejected(ctx):
+    p = make_problem("dense", 6, 3, 0)
+    ctx.set_hamiltonian(p.h, p.v, 3, p.gamma)
+    with pytest.raises(native.PvError) as e:
+        ctx.run(rank_cap=4, max_iter=1, tau=1e-12, c=0.5, delta=10.0, precision=2)
+    assert e.value.status == -1
