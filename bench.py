@@ -32,7 +32,9 @@ PEAK = {  # MI355X published peaks
 # library timer class -> (HIP kernel, roofline bound)
 KERNELS = {
     "gemm_f64_mfma": ("gemm_kernel<0>", "mfma"),
-    "tridiag_eig_f64": ("tridiag_eig_kernel", "alu"),
+    "tridiag_reduce_f64": ("tridiag_reduce_kernel", "hbm"),
+    "tridiag_vectors_f64": ("tridiag_vec_kernel", "alu"),
+    "tridiag_back_f64": ("tridiag_back_kernel", "alu"),
     "jacobi_eig_f64": ("jacobi_eig_kernel", "alu"),
     "mpo_wstep": ("wstep_kernel", "hbm"),
     "copy_scale": ("copy_kernel/scale_kernel", "hbm"),

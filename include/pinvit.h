@@ -169,9 +169,10 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
  * 10/3 n^3 each; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic bytes,
- * for i < n classes (eight classes: grouped GEMM float64, Jacobi eigensolver, MPO W-step,
- * copy/scale, reduction, tridiagonal eigensolver, Cholesky panels, grouped GEMM float32);
- * names via pv_timer_name. */
+ * for i < n classes (ten classes: grouped GEMM float64, Jacobi eigensolver, MPO W-step,
+ * copy/scale, split-K reduction, tridiagonal reduction, Cholesky panels, grouped GEMM
+ * float32, eigenvectors of the tridiagonal matrix, back-transformation); names via
+ * pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);

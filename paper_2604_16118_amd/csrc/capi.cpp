@@ -547,7 +547,8 @@ pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
 }
 
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
-                                            "tridiag_eig_f64", "cholesky_f64", "gemm_f32_mfma"};
+                                            "tridiag_reduce_f64", "cholesky_f64", "gemm_f32_mfma",
+                                            "tridiag_vectors_f64", "tridiag_back_f64"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

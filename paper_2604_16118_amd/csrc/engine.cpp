@@ -361,7 +361,7 @@ constexpr double kEigFlops = 10.0 / 3.0;
 void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
   std::vector<EigDesc> by_mode[3], tri;
   int nmax[3] = {0, 0, 0}, ntri = 0;
-  double flops[3] = {0, 0, 0}, ftri = 0;
+  double flops[3] = {0, 0, 0}, ftri = 0, btri = 0;
   for (const EigJob& j : jobs) {
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
@@ -371,6 +371,7 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
       c.scratch.push_back(std::move(w));
       ntri = std::max(ntri, j.n);
       ftri += kEigFlops * double(j.n) * j.n * j.n;
+      btri += 8.0 / 3.0 * double(j.n) * j.n * j.n;  // lower trailing triangle read + written per step
       continue;
     }
     const int mode = eig_mode(j.n);
@@ -383,9 +384,17 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
   }
   if (!tri.empty()) {
     EigDesc* d = c.upload(tri);
+    // per phase: reduction 4/3 n^3 flops, back-transformation 2 n^3 (the eigenvector phase
+    // is counted without flops)
     hipEvent_t a; c.begin(T_TRI, a);
-    launch_eig_tridiag(d, int(tri.size()), ntri, c.stream);
-    c.end(T_TRI, a, ftri, 0);
+    launch_eig_tridiag(d, int(tri.size()), ntri, 1, c.stream);
+    c.end(T_TRI, a, ftri * 0.4, btri);
+    c.begin(T_TRIVEC, a);
+    launch_eig_tridiag(d, int(tri.size()), ntri, 2, c.stream);
+    c.end(T_TRIVEC, a, 0, 0);
+    c.begin(T_TRIBACK, a);
+    launch_eig_tridiag(d, int(tri.size()), ntri, 4, c.stream);
+    c.end(T_TRIBACK, a, ftri * 0.6, 0);
   }
   for (int mode = 2; mode >= 0; --mode) {
     if (by_mode[mode].empty()) continue;

@@ -1053,7 +1053,7 @@ static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
   if (shm > *granted) throw std::runtime_error("eig: tridiagonal solver needs more LDS than the device grants");
 }
 
-void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
+void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
   const int threads = tridiag_threads(nmax);
@@ -1062,12 +1062,18 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
   const size_t shm_r = tridiag_reduce_lds(nmax, rthreads), shm_v = tridiag_vec_lds(nmax);
   lds_opt_in((const void*)tridiag_reduce_kernel, shm_r, &granted_reduce);
   lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
-  hipLaunchKernelGGL(tridiag_reduce_kernel, dim3(nprob), dim3(rthreads), shm_r, s, d);
-  PV_LAUNCH_CHECK();
-  hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
-  PV_LAUNCH_CHECK();
-  hipLaunchKernelGGL(tridiag_back_kernel, dim3((nmax + 7) / 8, nprob), dim3(256), 0, s, d);
-  PV_LAUNCH_CHECK();
+  if (phases & 1) {
+    hipLaunchKernelGGL(tridiag_reduce_kernel, dim3(nprob), dim3(rthreads), shm_r, s, d);
+    PV_LAUNCH_CHECK();
+  }
+  if (phases & 2) {
+    hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
+    PV_LAUNCH_CHECK();
+  }
+  if (phases & 4) {
+    hipLaunchKernelGGL(tridiag_back_kernel, dim3((nmax + 7) / 8, nprob), dim3(256), 0, s, d);
+    PV_LAUNCH_CHECK();
+  }
 }
 
 // ---------------------------------------------------------------------------

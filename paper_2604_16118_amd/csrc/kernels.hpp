@@ -85,10 +85,11 @@ void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t 
 void launch_eig(const EigDesc* d_desc, int nprob, int nmax, int mode, hipStream_t s);
 // Fastest mode available for an n x n problem on this device.
 int eig_mode(int n);
-// Tridiagonalisation, bisection + inverse iteration, back-transformation (three
-// launches); work holds tri_work_doubles(n) doubles; abs_tol is the relative cut below
-// which eigenvectors are returned as zero.
-void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
+// Tridiagonalisation (phase bit 1), bisection + inverse iteration (bit 2),
+// back-transformation (bit 4), one launch each, in that order; work holds
+// tri_work_doubles(n) doubles; abs_tol is the relative cut below which eigenvectors are
+// returned as zero.
+void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
 inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(3) * n + 1; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in
 // place (lower triangle; the upper triangle is zeroed).  A column whose pivot (Schur
