@@ -45,6 +45,67 @@ KERNELS = {
 
 
 TIMED_RANGE = "pinvit_timed"
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_16118_amd", "csrc", "kernels.hip")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+
+
+def _kernel_hash() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _counter_rows(path: str):
+    import csv
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            yield int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])
+
+
+def pmc_traffic(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str,
+                bench_json: str, cal_bytes: int, commands: str) -> dict:
+    """HBM traffic per launch of the dominant kernel of a bench run from two rocprofv3
+    --pmc passes of the same deterministic command (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch).  Each counter is scaled by the ratio of the true size to what it reads for a
+    plain device copy of cal_bytes bytes (the largest dispatch of the calibration run).  The
+    timed launches are the last `launches` dispatches of the kernel, since the timed steps
+    end the program."""
+    with open(bench_json) as f:
+        b = json.loads(f.read().strip().splitlines()[-1])
+    kernel, n = b["roofline"]["kernel"], b["roofline"]["launches"]
+
+    def factor(path):
+        v = max(c for _, _, c in _counter_rows(path))
+        return cal_bytes / 1024.0 / v
+
+    ff, fw = factor(cal_fetch_csv), factor(cal_write_csv)
+
+    def per_launch(path, fac):
+        vals = sorted((d, c) for d, k, c in _counter_rows(path) if k.split("(")[0].endswith(kernel))
+        vals = [c for _, c in vals[-n:]]
+        assert len(vals) == n, f"{path}: {len(vals)} dispatches of {kernel}, expected {n}"
+        return sum(vals) * 1024.0 * fac / n
+
+    rd, wr = per_launch(fetch_csv, ff), per_launch(write_csv, fw)
+    alg = b["roofline"]["achieved"] * 1e9 * b["roofline"]["avg_launch_ms"] * 1e-3 \
+        if b["roofline"]["unit"] == "GB/s" else None
+    return {"kernel": kernel, "kernel_source_sha256": _kernel_hash(), "launches": n,
+            "fetch_factor": ff, "write_factor": fw, "read_bytes_per_launch": rd,
+            "write_bytes_per_launch": wr, "traffic_bytes_per_launch": rd + wr,
+            "algorithmic_bytes_per_launch": alg, "workload": b["config"]["workload"],
+            "commands": commands}
+
+
+def traffic_record(kernel: str):
+    """Counter-derived HBM bytes per launch for `kernel`, or None when none was taken or
+    the kernel source changed since."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(TRAFFIC_DIR, "*_traffic.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("kernel") == kernel and rec.get("kernel_source_sha256") == _kernel_hash():
+            return rec
+    return None
 
 
 def _roctx():
@@ -134,9 +195,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
+    ap.add_argument("--pmc-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV", "BENCH_JSON"),
+                    help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--cal-bytes", type=int, default=2 ** 30, help="size of the calibration copy")
+    ap.add_argument("--commands", default="", help="commands that produced the counter CSVs (recorded)")
     a = ap.parse_args()
     if a.summarize:
         print(summarize(a.summarize))
+        return
+    if a.pmc_traffic:
+        print(json.dumps(pmc_traffic(*a.pmc_traffic, cal_bytes=a.cal_bytes, commands=a.commands), indent=1))
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -191,7 +259,9 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    rec = traffic_record(kernel)
+    roof["traffic"] = rec["traffic_bytes_per_launch"] if rec else None
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["kernel"] = kernel
     roof["launches"] = dom["calls"]
     roof["avg_launch_ms"] = dom["ms"] / max(dom["calls"], 1)
