@@ -32,9 +32,11 @@ PEAK = {  # MI355X published peaks
 # library timer class -> (HIP kernel, roofline bound)
 KERNELS = {
     "gemm_f64_mfma": ("gemm_kernel<0>", "mfma"),
-    "tridiag_reduce_f64": ("tridiag_reduce_kernel", "hbm"),
+    "tridiag_reduce_f64": ("tridiag_panel_kernel", "hbm"),
+    "tridiag_update_gemm_f64": ("gemm_kernel<2>", "mfma"),
     "tridiag_vectors_f64": ("tridiag_vec_kernel", "alu"),
     "tridiag_back_f64": ("tridiag_back_kernel", "alu"),
+    "tridiag_values_f64": ("tridiag_values_kernel", "alu"),
     "jacobi_eig_f64": ("jacobi_eig_kernel", "alu"),
     "mpo_wstep": ("wstep_kernel", "hbm"),
     "copy_scale": ("copy_kernel/scale_kernel", "hbm"),

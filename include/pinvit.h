@@ -168,11 +168,14 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
 
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
- * 10/3 n^3 each; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic bytes,
- * for i < n classes (ten classes: grouped GEMM float64, Jacobi eigensolver, MPO W-step,
- * copy/scale, split-K reduction, tridiagonal reduction, Cholesky panels, grouped GEMM
- * float32, eigenvectors of the tridiagonal matrix, back-transformation); names via
- * pv_timer_name. */
+ * Jacobi 10/3 n^3 each; tridiagonal solver: panel kernels 2/3 n^3 flops and 4/3 n^3
+ * bytes (the symmetric products), trailing updates as GEMMs, back-transformation 2 n^2 k
+ * for k wanted vectors; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic
+ * bytes, for i < n classes (twelve classes: grouped GEMM float64, Jacobi eigensolver, MPO
+ * W-step, copy/scale, split-K reduction, tridiagonal reduction panels, Cholesky panels,
+ * grouped GEMM float32, eigenvectors of the tridiagonal matrix, back-transformation,
+ * eigenvalues of the tridiagonal matrix, trailing updates of the tridiagonal reduction);
+ * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);
@@ -184,6 +187,12 @@ pv_status pv_timers_reset(pv_ctx* ctx);
  * bisection and inverse iteration (eigenvectors of eigenvalues <= 1e-12 max|lambda|
  * are returned as zero).  For tests. */
 pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method);
+
+/* As pv_sym_eig with method 1, but eigenvectors only for the nvec largest eigenvalues
+ * (0 <= nvec <= n; columns nvec.. of V are zero; all n eigenvalues are returned).  The
+ * truncations use this form: they select ranks from the eigenvalues first and compute
+ * the kept vectors only.  PV_EINVAL for nvec outside [0, n].  For tests. */
+pv_status pv_sym_eig_top(pv_ctx* ctx, int n, const double* A, double* w, double* V, int nvec);
 
 /* Cholesky factor of a symmetric positive semidefinite matrix on the device (the factor
  * of the left Gram matrices in the simultaneous truncation): A is n x n column-major

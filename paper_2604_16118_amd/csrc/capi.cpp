@@ -537,6 +537,16 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
   });
 }
 
+pv_status pv_sym_eig_top(pv_ctx* ctx, int n, const double* A, double* w, double* V, int nvec) {
+  return guard([&] {
+    if (!ctx || !A || !w || !V) fail(PV_EINVAL, "null argument");
+    if (n < 1 || n > kEigMax) fail(PV_EINVAL, "n out of range");
+    if (nvec < 0 || nvec > n) fail(PV_EINVAL, "nvec must lie in [0, n]");
+    for (size_t i = 0; i < size_t(n) * n; ++i) if (!std::isfinite(A[i])) fail(PV_EINVAL, "A not finite");
+    sym_eig(ctx->c, n, A, w, V, 1, nvec);
+  });
+}
+
 pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
   return guard([&] {
     if (!ctx || !A || !W) fail(PV_EINVAL, "null argument");
@@ -548,7 +558,8 @@ pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
 
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
                                             "tridiag_reduce_f64", "cholesky_f64", "gemm_f32_mfma",
-                                            "tridiag_vectors_f64", "tridiag_back_f64"};
+                                            "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64",
+                                            "tridiag_update_gemm_f64"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

@@ -214,6 +214,7 @@ namespace {
 struct GemmBatch {
   std::vector<GemmDesc> d;
   int prec = 0;  // 1: float32 MFMA (operator contractions in the mixed-precision mode)
+  int cls = -1;  // timer class (default: by precision)
   void add(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc,
            int M, int N, int K, double alpha, double beta) {
     if (M <= 0 || N <= 0) return;
@@ -278,10 +279,10 @@ struct GemmBatch {
     }
     if (!list.empty()) {
       GemmDesc* dd = c.upload(list);
-      const int cls = prec ? T_GEMM32 : T_GEMM;
-      hipEvent_t a; c.begin(cls, a);
+      const int tc = cls >= 0 ? cls : (prec ? T_GEMM32 : T_GEMM);
+      hipEvent_t a; c.begin(tc, a);
       launch_gemm(dd, int(list.size()), int(tiles), prec, c.stream);
-      c.end(cls, a, flops, bytes);
+      c.end(tc, a, flops, bytes);
     }
     if (!red.empty()) {
       ReduceDesc* dr = c.upload(red);
@@ -358,20 +359,36 @@ constexpr int kTridiagMin = 40;
 // (the same count is used for the Jacobi kernel, which does more work).
 constexpr double kEigFlops = 10.0 / 3.0;
 
-void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
-  std::vector<EigDesc> by_mode[3], tri;
-  int nmax[3] = {0, 0, 0}, ntri = 0;
+// Eigenproblems of one batch.  The tridiagonal ones keep their work areas here between
+// the eigenvalue launches and the eigenvector launches.
+struct EigPlan {
+  std::vector<EigDesc> tri;
+  std::vector<int> job;  // job index of each tridiagonal problem
+  std::vector<Buf> work;
+  int ntri = 0;
+};
+
+// Eigenvalues of every job; the Jacobi problems (small, or not flagged tridiagonal) also
+// get all their eigenvectors here.
+EigPlan run_eig_values(Ctx& c, const std::vector<EigJob>& jobs) {
+  EigPlan plan;
+  std::vector<EigDesc> by_mode[3];
+  int nmax[3] = {0, 0, 0};
   double flops[3] = {0, 0, 0}, ftri = 0, btri = 0;
-  for (const EigJob& j : jobs) {
+  for (size_t ji = 0; ji < jobs.size(); ++ji) {
+    const EigJob& j = jobs[ji];
     if (j.n <= 0) continue;
     if (j.n > kEigMax) fail(PV_EINVAL, "eigenproblem of size " + std::to_string(j.n) + " exceeds the supported maximum");
     if (j.tridiag && (j.n > kTridiagMin || j.force)) {
-      Buf w = scratch_buf(c, tri_work_doubles(j.n));
-      tri.push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, std::max(j.abs_tol, kVecCut)});
-      c.scratch.push_back(std::move(w));
-      ntri = std::max(ntri, j.n);
-      ftri += kEigFlops * double(j.n) * j.n * j.n;
-      btri += 8.0 / 3.0 * double(j.n) * j.n * j.n;  // lower trailing triangle read + written per step
+      Buf w(c.pool, tri_work_doubles(j.n));
+      plan.tri.push_back(EigDesc{j.A, j.lda, j.n, j.V, j.w, w.p, nullptr, std::max(j.abs_tol, kVecCut)});
+      plan.job.push_back(int(ji));
+      plan.work.push_back(std::move(w));
+      plan.ntri = std::max(plan.ntri, j.n);
+      // panel kernels: the symmetric products over the stored trailing lower triangle,
+      // 4 flops and 8 bytes per element read (the rank-2k updates are counted as GEMMs)
+      ftri += 2.0 / 3.0 * double(j.n) * j.n * j.n;
+      btri += 4.0 / 3.0 * double(j.n) * j.n * j.n;
       continue;
     }
     const int mode = eig_mode(j.n);
@@ -382,19 +399,42 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
     nmax[mode] = std::max(nmax[mode], j.n);
     flops[mode] += kEigFlops * double(j.n) * j.n * j.n;
   }
-  if (!tri.empty()) {
-    EigDesc* d = c.upload(tri);
-    // per phase: reduction 4/3 n^3 flops, back-transformation 2 n^3 (the eigenvector phase
-    // is counted without flops)
-    hipEvent_t a; c.begin(T_TRI, a);
-    launch_eig_tridiag(d, int(tri.size()), ntri, 1, c.stream);
-    c.end(T_TRI, a, ftri * 0.4, btri);
-    c.begin(T_TRIVEC, a);
-    launch_eig_tridiag(d, int(tri.size()), ntri, 2, c.stream);
-    c.end(T_TRIVEC, a, 0, 0);
-    c.begin(T_TRIBACK, a);
-    launch_eig_tridiag(d, int(tri.size()), ntri, 4, c.stream);
-    c.end(T_TRIBACK, a, ftri * 0.6, 0);
+  if (!plan.tri.empty()) {
+    EigDesc* d = c.upload(plan.tri);
+    const int np = int(plan.tri.size());
+    double bprep = 0;
+    for (const EigDesc& e : plan.tri) bprep += 16.0 * double(e.n) * e.n;
+    hipEvent_t a;
+    c.begin(T_COPY, a);
+    launch_tri_prepare(d, np, plan.ntri, c.stream);
+    c.end(T_COPY, a, 0, bprep);
+    // blocked reduction: panel kernel, then the trailing update of every problem as a GEMM
+    const double nsteps = std::max(plan.ntri - 2, 1);
+    for (int k0 = 0; k0 + 2 < plan.ntri; k0 += kTriPanel) {
+      const double share = std::min<double>(kTriPanel, plan.ntri - 2 - k0) / nsteps;
+      c.begin(T_TRI, a);
+      launch_tri_panel(d, np, plan.ntri, k0, c.stream);
+      c.end(T_TRI, a, ftri * share, btri * share);
+      GemmBatch g;
+      g.cls = T_TRIGEMM;
+      g.prec = 2;
+      for (const EigDesc& e : plan.tri) {
+        const int n = e.n;
+        if (k0 + 2 >= n) continue;
+        const int nbe = std::min(kTriPanel, n - 2 - k0);
+        const int o = k0 + nbe, m2 = n - o;
+        double* P1 = e.work + int64_t(n) * n;
+        double* P2 = P1 + int64_t(2) * nbe * n;
+        g.add(P1 + o, n, 0, P2 + o, n, 1, e.work + o + int64_t(o) * n, n, m2, m2, 2 * nbe, -1.0, 1.0);
+      }
+      g.run(c);
+    }
+    c.begin(T_COPY, a);
+    launch_tri_finish(d, np, c.stream);
+    c.end(T_COPY, a, 0, 0);
+    c.begin(T_TRIVAL, a);
+    launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 2, c.stream);
+    c.end(T_TRIVAL, a, 0, 0);
   }
   for (int mode = 2; mode >= 0; --mode) {
     if (by_mode[mode].empty()) continue;
@@ -403,6 +443,34 @@ void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
     launch_eig(d, int(by_mode[mode].size()), nmax[mode], mode, c.stream);
     c.end(T_EIG, a, flops[mode], 0);
   }
+  return plan;
+}
+
+// Eigenvectors of the tridiagonal problems of a plan: for job j the nvec[j] leading ones
+// (all when nvec is null), the other columns of V zero.
+void run_eig_vectors(Ctx& c, EigPlan& plan, const std::vector<int>* nvec) {
+  if (plan.tri.empty()) return;
+  double fb = 0;
+  for (size_t i = 0; i < plan.tri.size(); ++i) {
+    EigDesc& e = plan.tri[i];
+    e.nvec = nvec ? std::min(std::max((*nvec)[plan.job[i]], 0), e.n) : e.n;
+    fb += 2.0 * double(e.n) * e.n * e.nvec;
+  }
+  EigDesc* d = c.upload(plan.tri);
+  hipEvent_t a; c.begin(T_TRIVEC, a);
+  launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 4, c.stream);
+  c.end(T_TRIVEC, a, 0, 0);
+  c.begin(T_TRIBACK, a);
+  launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 8, c.stream);
+  c.end(T_TRIBACK, a, fb, 0);
+  for (Buf& w : plan.work) c.scratch.push_back(std::move(w));
+  plan.work.clear();
+  plan.tri.clear();
+}
+
+void run_eig(Ctx& c, const std::vector<EigJob>& jobs) {
+  EigPlan plan = run_eig_values(c, jobs);
+  run_eig_vectors(c, plan, nullptr);
 }
 
 // W W^T ~ G for every job (G symmetric positive semidefinite, n x n, ld n; W lower
@@ -887,12 +955,18 @@ double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   return v.empty() ? 0.0 : v[0];
 }
 
-void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method) {
+void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method, int nvec) {
   Buf A(c.pool, size_t(n) * n), V(c.pool, size_t(n) * n), w(c.pool, size_t(n));
   PV_HIP(hipMemcpyAsync(A.p, A_host, size_t(n) * n * 8, hipMemcpyHostToDevice, c.stream));
   std::vector<EigJob> jobs{EigJob{A.p, n, n, V.p, w.p, method == 1 ? kVecCut : kAbsTolGeneral, method == 1}};
   jobs[0].force = method == 1;
-  run_eig(c, jobs);
+  if (method == 1 && nvec >= 0) {
+    EigPlan plan = run_eig_values(c, jobs);
+    std::vector<int> nv{nvec};
+    run_eig_vectors(c, plan, &nv);
+  } else {
+    run_eig(c, jobs);
+  }
   PV_HIP(hipMemcpyAsync(w_host, w.p, size_t(n) * 8, hipMemcpyDeviceToHost, c.stream));
   PV_HIP(hipMemcpyAsync(V_host, V.p, size_t(n) * n * 8, hipMemcpyDeviceToHost, c.stream));
   c.sync();
@@ -1366,8 +1440,10 @@ struct BondEig {
   Buf V, w;
 };
 
-// Eigendecompositions of the Gram matrices of bonds kmin..kmax, one batched launch.
-BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax) {
+// Eigendecompositions of the Gram matrices of bonds kmin..kmax, one batched launch.  With
+// `values_only` the tridiagonal problems stop after their eigenvalues; their vectors come
+// from run_eig_vectors on the returned plan (job order: bonds ascending, sectors ascending).
+BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax, EigPlan* values_only = nullptr) {
   BondEig e;
   e.voff.assign(x.L + 1, std::vector<int64_t>(x.N + 1, -1));
   e.woff = e.voff;
@@ -1388,7 +1464,8 @@ BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax) 
         const int r = x.rho[k][n];
         jobs.push_back(EigJob{g.buf.p + g.off[k][n], r, r, e.V.p + e.voff[k][n], e.w.p + e.woff[k][n], kAbsTolGeneral, true});
       }
-  run_eig(c, jobs);
+  if (values_only) *values_only = run_eig_values(c, jobs);
+  else run_eig(c, jobs);
   return e;
 }
 
@@ -1449,7 +1526,8 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
   Bg.off.assign(L + 1, std::vector<int64_t>(N + 1, -1));
   for (int k = 1; k < L; ++k) Bg.off[k] = EL.voff[k];
   Bg.buf = std::move(Bm);
-  BondEig EB = eig_grams(c, x, Bg, 1, L - 1);
+  EigPlan plan;
+  BondEig EB = eig_grams(c, x, Bg, 1, L - 1, &plan);
   std::vector<double> sb2 = download(c, EB.w.p, EB.w.n);
   auto rho = x.rho;
   for (int k = 1; k < L; ++k) {
@@ -1472,6 +1550,14 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
     }
     for (int n = 0; n <= N; ++n)
       if (x.valid(k, n)) rho[k][n] = keep[n];
+  }
+  // eigenvectors of the kept singular values only
+  {
+    std::vector<int> nvec;
+    for (int k = 1; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        if (Bg.off[k][n] >= 0) nvec.push_back(rho[k][n]);
+    run_eig_vectors(c, plan, &nvec);
   }
   // bond matrices: Lk = (G^R W) U_s Sigma_s^{-2} (r x s), Rt = W U_s (r x s)
   Buf Lb(c.pool, EL.V.n), Rb(c.pool, EL.V.n);
@@ -1597,7 +1683,56 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
       if (r1[n2]) g.add(X1, r1[n2], 0, X1, r1[n2], 1, se[n2].G.p + r0[n2] + int64_t(r0[n2]) * R, R, r1[n2], r1[n2], K, 1.0, 0.0);
     }
     g.run(c);
-    eig_all(c, se, kAbsTolGeneral, !two_pass);
+    if (!two_pass) {
+      // single pass: eigenvalues, rank selection, then only the kept eigenvectors; the new
+      // core is W[:, :s] and the new carry W[:, :s]^T T2
+      std::vector<EigJob> jobs(N + 1);
+      for (int n2 = 0; n2 <= N; ++n2) {
+        if (se[n2].n <= 0) continue;
+        se[n2].W = Buf(c.pool, size_t(se[n2].n) * se[n2].n);
+        se[n2].w = Buf(c.pool, size_t(se[n2].n));
+        jobs[n2] = EigJob{se[n2].G.p, se[n2].n, se[n2].n, se[n2].W.p, se[n2].w.p, kAbsTolGeneral, true};
+      }
+      EigPlan plan = run_eig_values(c, jobs);
+      auto sig = sigmas(c, se);
+      std::vector<int> keep = select_ranks(sig, 0.0, zcap, nullptr, kZeroTolPar);
+      std::vector<int> nvec(N + 1, 0);
+      for (int n2 = 0; n2 <= N; ++n2) nvec[n2] = se[n2].n > 0 ? keep[n2] : 0;
+      run_eig_vectors(c, plan, &nvec);
+      for (int n2 = 0; n2 <= N; ++n2) y->rho[k][n2] = y->valid(k, n2) ? keep[n2] : 0;
+      alloc_site(c, *y, k);
+      fill(c, y->site[k - 1].p, y->site_size(k), 0.0);
+      CopyBatch cb;
+      for (int n2 = 0; n2 <= N; ++n2) {
+        const int s = keep[n2], R = se[n2].n;
+        if (s == 0 || R == 0) continue;
+        if (r0[n2] && y->ucols(k, n2)) cb.add(se[n2].W.p, R, y->U(k, n2), y->rows(k, n2), r0[n2], s, 1.0);
+        if (r1[n2] && n2 >= 1 && y->ocols(k, n2 - 1))
+          cb.add(se[n2].W.p + r0[n2], R, y->O(k, n2 - 1), y->rows(k, n2 - 1), r1[n2], s, 1.0);
+      }
+      cb.run(c);
+      EnvLayout Lc = env_layout(k, N, y->rho[k], x.rho[k], op.qoff[k], vy, vx);
+      Buf Cn(c.pool, size_t(std::max<int64_t>(Lc.total, 1)));
+      GemmBatch g1;
+      for (int n2 = 0; n2 <= N; ++n2) {
+        const int s = keep[n2], R = se[n2].n;
+        if (s == 0 || R == 0 || Lc.ncols[n2] == 0) continue;
+        const int K = int(Lc.ncols[n2]);
+        double* out = Cn.p + Lc.off[n2];
+        if (r0[n2]) g.add(se[n2].W.p, R, 1, t2.buf.p + t2.off[0][n2], r0[n2], 0, out, s, s, K, r0[n2], 1.0, 0.0);
+        if (r1[n2]) g1.add(se[n2].W.p + r0[n2], R, 1, t2.buf.p + t2.off[1][n2], r1[n2], 0, out, s, s, K, r1[n2], 1.0,
+                           r0[n2] ? 1.0 : 0.0);
+      }
+      g.run(c);
+      g1.run(c);
+      for (auto& s2 : se) { c.scratch.push_back(std::move(s2.G)); c.scratch.push_back(std::move(s2.W)); c.scratch.push_back(std::move(s2.w)); }
+      c.scratch.push_back(std::move(t2.buf));
+      c.scratch.push_back(std::move(C));
+      C = std::move(Cn);
+      Le = std::move(Lc);
+      continue;
+    }
+    eig_all(c, se, kAbsTolGeneral);
     GemmBatch g1;
     for (int n2 = 0; n2 <= N; ++n2) {
       const int R = se[n2].n;

@@ -118,7 +118,7 @@ struct DevMpo {
   int64_t nnz = 0;
 };
 
-enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_COUNT };
+enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_TRIVAL, T_TRIGEMM, T_COUNT };
 
 struct Ctx {
   int device = 0;
@@ -181,7 +181,7 @@ std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m);
 double norm_canonical(Ctx& c, const Mps& x);
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
 double norm2(Ctx& c, const Mps& x);
-void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method);
+void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method, int nvec = -1);
 void cholesky(Ctx& c, int n, const double* A_host, double* W_host);
 
 }  // namespace pv

@@ -48,8 +48,11 @@ __device__ inline double wave_sum_d(double v) {
 template <int PREC>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob) {
   // PREC 0: float64 operands on v_mfma_f64_16x16x4f64; PREC 1: operands rounded to float32
-  // on v_mfma_f32_16x16x4f32 with float32 accumulation (C stays float64 in memory)
-  typedef typename std::conditional<PREC == 0, double, float>::type T;
+  // on v_mfma_f32_16x16x4f32 with float32 accumulation (C stays float64 in memory);
+  // PREC 2: the float64 kernel again, a separate instance for the trailing updates of the
+  // tridiagonal reduction so that profiles tell the two uses apart
+  constexpr bool F64 = PREC != 1;
+  typedef typename std::conditional<F64, double, float>::type T;
   constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread per K-tile
   // double-buffered K-tiles: the global loads of tile t+1 are held in registers while the
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
       const T a1 = As[buf][kk + lk][wr * 32 + 16 + li];
       const T b0 = Bs[buf][kk + lk][wc * 32 + li];
       const T b1 = Bs[buf][kk + lk][wc * 32 + 16 + li];
-      if constexpr (PREC == 0) {
+      if constexpr (F64) {
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         // result element r of lane l: row 4r + l/16 (float64 instruction), row
         // 4 (l/16) + r (float32 instruction), column l % 16 (measured on gfx950)
-        const int i = row0 + wr * 32 + mi * 16 + (PREC == 0 ? 4 * r + lk : 4 * lk + r);
+        const int i = row0 + wr * 32 + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r);
         const int j = col0 + wc * 32 + nj * 16 + li;
         if (i < g.M && j < g.N) {
           double v = g.alpha * double(acc[mi][nj][r]);
@@ -157,8 +160,10 @@ void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, h
   if (total_tiles <= 0) return;
   if (prec == 0)
     hipLaunchKernelGGL(gemm_kernel<0>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
-  else
+  else if (prec == 1)
     hipLaunchKernelGGL(gemm_kernel<1>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+  else
+    hipLaunchKernelGGL(gemm_kernel<2>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
   PV_LAUNCH_CHECK();
 }
 
@@ -476,7 +481,7 @@ __device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble
   }
 }
 
-constexpr int kRedThreads = 512;  // reduction kernel: 8 wavefronts with room for 256 VGPRs
+constexpr int kRedThreads = 512;  // reduction kernels: 8 wavefronts with room for 256 VGPRs
 constexpr int kRedCols = 4;  // columns per wavefront group in the reduction pass
 constexpr int kRedChunks = 4;  // 64-row chunks per iteration of that pass
 
@@ -522,34 +527,35 @@ __device__ inline double start_value(int i, int j) {
 
 // Work layout of one problem (doubles): [0, n^2) working copy, reflectors below the
 // diagonal; [n^2, 6 n^2) per-thread inverse-iteration storage (during the reduction: the
-// per-column products); [6 n^2, 7 n^2) eigenvectors of T in descending order; then beta_k,
-// the diagonal d and off-diagonal e of T (n each) and the applied shift.
+// current panel's vectors); [6 n^2, 7 n^2) eigenvectors of T in descending order; then beta_k,
+// the diagonal d and off-diagonal e of T (n each), the applied shift, the eigenvalues of T
+// in bisection order and their descending ranks (n each).
 
-// 1. Reduction to tridiagonal form, one workgroup per matrix.  Step k forms the reflector
-//    H_k = I - beta v v^T from column k, p = beta A22 v, K = beta/2 p^T v, q = p - K v; its
-//    rank-2 update A22 <- A22 - v q^T - q v^T is applied lazily, in the next step's single
-//    pass over the trailing lower triangle, which also forms that step's product: column j
-//    contributes sum_{i>=j} a_ij v_i to p_j (a wavefront reduction) and a_ij v_j to p_i for
-//    i > j (accumulated per wavefront in LDS, summed in a fixed order).  A matrix whose
-//    off-diagonal part is negligible is passed on as T = diag(A);
-//    a narrow spectrum is shifted by its mean diagonal entry first.
-__global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDesc* __restrict__ descs) {
+// Layout after the reduction, past the eigenvector area of T (doubles): beta_k, d, e (n
+// each), the applied shift, then the eigenvalues of T in bisection order and the
+// descending rank of each (n each).
+__device__ inline gdouble* tri_tail(gdouble* W, int n) { return W + 7 * (int64_t)n * n; }
+// 1 when the reduction found the input diagonal (T = diag(A), no reflectors); kept in the
+// rank area of the tail, which the eigenvalue phase overwrites.
+__device__ inline gdouble* tri_diag_flag(gdouble* W, int n) { return tri_tail(W, n) + 4 * n + 1; }
+
+// 1. Blocked reduction to tridiagonal form (one workgroup per matrix per launch).
+//
+// 1a. Preparation: working copy of A (both triangles, from the upper triangle of the
+//     input); a matrix whose off-diagonal part is negligible is passed on as T = diag(A);
+//     a narrow spectrum is shifted by its mean diagonal entry.
+__global__ __launch_bounds__(kRedThreads) void tridiag_prepare_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double red[kRedThreads / 64];
-  // v and q of the current and previous step, column products, next column (6 n doubles),
-  // nw x n partial products
-  extern __shared__ double tsm[];
   const EigDesc D = descs[blockIdx.x];
   const int n = D.n;
   if (n <= 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
   const int lda = n;
-  const int64_t nn0 = (int64_t)n * n;
   gdouble* A = gbl(D.work);
-  gdouble* betas = A + 7 * nn0;
-  gdouble* dd = betas + n;
-  gdouble* ee = dd + n;
-  gdouble* shift_out = ee + n;
+  gdouble* tail = tri_tail(A, n);
+  gdouble* betas = tail;
+  gdouble* dd = tail + n;
+  gdouble* ee = tail + 2 * n;
   gcdouble* Ain = gbl(D.A);
   double od = 0.0, dg = 0.0;
   for (int e = tid; e < n * n; e += bs) {
@@ -561,13 +567,15 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
   od = block_max(od, red, tid, bs);
   dg = block_max(dg, red, tid, bs);
   if (od <= kDiagTol * dg) {
-    // 0. diagonal to working accuracy: T = diag(A), no reflectors
     for (int t = tid; t < n; t += bs) {
       dd[t] = A[t + (int64_t)t * lda];
       ee[t] = 0.0;
       betas[t] = 0.0;
     }
-    if (tid == 0) *shift_out = 0.0;
+    if (tid == 0) {
+      tail[3 * n] = 0.0;
+      *tri_diag_flag(A, n) = 1.0;
+    }
     return;
   }
   double dsum = 0.0;
@@ -583,63 +591,109 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
   const double shift = rad <= kShiftTol * fabs(mu) ? mu : 0.0;
   if (shift != 0.0)
     for (int t = tid; t < n; t += bs) A[t + (int64_t)t * lda] -= shift;
-  if (tid == 0) *shift_out = shift;
-  // v of step k at tsm + (k & 1) n, q at tsm + (2 + (k & 1)) n
-  double* pd = tsm + 4 * n;   // per-column dot products
-  double* nxt = tsm + 5 * n;  // column k + 1 as left by the pass of step k
-  double* pw = tsm + 6 * n;   // nw x n partial products
-  for (int i = tid; i < n; i += bs) { tsm[n + i] = 0.0; tsm[3 * n + i] = 0.0; }
-  __syncthreads();
-  for (int k = 0; k + 2 < n; ++k) {
-    double* vk = tsm + (k & 1) * n;
-    double* qk = tsm + (2 + (k & 1)) * n;
-    const double* vp = tsm + ((k + 1) & 1) * n;
-    const double* qp = tsm + (2 + ((k + 1) & 1)) * n;
-    // column k (rows >= k) brought up to date and turned into the reflector by wave 0;
-    // its lanes exchange values through vk in LDS (in order within a wavefront)
-    if (wave == 0) {
-      gdouble* col = A + (int64_t)k * lda;
-      const double vpk = vp[k], qpk = qp[k];
-      double part = 0.0;
-      for (int i = k + lane; i < n; i += 64) {
-        const double a = (k == 0 ? col[i] : nxt[i]) - vp[i] * qpk - qp[i] * vpk;
-        vk[i] = a;
-        if (i >= k + 2) part += a * a;
-      }
-      const double sig2 = wave_sum_d(part);
-      __builtin_amdgcn_wave_barrier();
-      const double x0 = vk[k + 1], akk = vk[k];
-      // reflector H = I - beta v v^T with v = (x - alpha e_1) / (x0 - alpha), so v_{k+1} = 1,
-      // |v_i| <= 1 and beta = 2 v0^2 / (v0^2 + sig2) lies in [1, 2] however small x is
-      double beta = 0.0, alpha = x0, inv = 0.0;
-      if (sig2 != 0.0) {
-        const double nrm = sqrt(x0 * x0 + sig2);
-        alpha = x0 > 0.0 ? -nrm : nrm;
-        const double v0 = x0 - alpha;  // |v0| >= nrm
-        beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
-        inv = 1.0 / v0;
-      }
-      if (lane == 0) {
-        ee[k] = alpha;
-        dd[k] = akk;
-        betas[k] = beta;
-        red[0] = beta;
-      }
-      __builtin_amdgcn_wave_barrier();
-      for (int i = lane; i < n; i += 64) {
-        const double v = (beta == 0.0 || i <= k) ? 0.0 : (i == k + 1 ? 1.0 : vk[i] * inv);
-        vk[i] = v;
-        if (beta != 0.0 && i > k) col[i] = v;  // v stored below the diagonal
-      }
+  if (tid == 0) {
+    tail[3 * n] = shift;
+    *tri_diag_flag(A, n) = 0.0;
+  }
+}
+
+// 1b. One panel: steps k = k0 .. k0 + nbe - 1 (nbe = min(kTriPanel, n - 2 - k0)).  Step k
+//     takes column k of the matrix as updated by all earlier steps, forms the reflector
+//     H_k = I - beta v v^T (v_{k+1} = 1, |v_i| <= 1, beta in [1, 2]), stores v below the
+//     diagonal, and computes p = A_k v, q = beta p - (beta^2/2)(p^T v) v, so that step k's
+//     update is A <- A - v q^T - q v^T.  The stored matrix only carries the updates of
+//     earlier panels; within the panel
+//       A_k = A_stored - sum_{j < k} (v_j q_j^T + q_j v_j^T),
+//     so p is the product of the stored trailing lower triangle with v (one read-only pass:
+//     a_ij adds a_ij v_i to p_j and a_ij v_j to p_i for i > j) minus the panel terms, and
+//     the next column is corrected the same way.  The panel's v and q go to
+//     P1 = [V | Q] and P2 = [Q | V] (n x 2 nbe each, after the working copy), from which
+//     the caller applies A22 <- A22 - P1 P2^T to the trailing block (a GEMM) before the
+//     next panel.
+__global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDesc* __restrict__ descs, int k0) {
+  __shared__ double red[kRedThreads / 64];
+  // v, next column, column products: n doubles each; panel dot products 2 kTriPanel;
+  // nw x n per-wavefront row products
+  extern __shared__ double tsm[];
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (k0 + 2 >= n) return;
+  const int nbe = min(kTriPanel, n - 2 - k0);
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+  const int lda = n;
+  const int64_t nn0 = (int64_t)n * n;
+  gdouble* A = gbl(D.work);
+  gdouble* tail = tri_tail(A, n);
+  gdouble* betas = tail;
+  gdouble* dd = tail + n;
+  gdouble* ee = tail + 2 * n;
+  gdouble* P1 = A + nn0;
+  gdouble* P2 = P1 + (int64_t)2 * nbe * n;
+  if (*tri_diag_flag(A, n) != 0.0) {  // nothing to reduce: the trailing update is zero
+    for (int64_t e = tid; e < (int64_t)4 * nbe * n; e += bs) P1[e] = 0.0;
+    return;
+  }
+  double* vk = tsm;
+  double* nxt = vk + n;
+  double* pd = nxt + n;
+  double* xw = pd + n;
+  double* xv = xw + kTriPanel;
+  double* pw = xv + kTriPanel;
+  // column k0 as left by the earlier panels; row i is owned by thread i mod bs throughout
+  for (int i = tid; i < n; i += bs) nxt[i] = i >= k0 ? A[i + (int64_t)k0 * lda] : 0.0;
+  for (int j = 0; j < nbe; ++j) {
+    const int k = k0 + j;
+    double part = 0.0;
+    for (int i = tid; i < n; i += bs)
+      if (i >= k + 2) part += nxt[i] * nxt[i];
+    const double sig2 = block_sum(part, red, tid, bs);  // also publishes nxt
+    const double x0 = nxt[k + 1], akk = nxt[k];
+    double beta = 0.0, alpha = x0, inv = 0.0;
+    if (sig2 != 0.0) {
+      const double nrm = sqrt(x0 * x0 + sig2);
+      alpha = x0 > 0.0 ? -nrm : nrm;
+      const double v0 = x0 - alpha;  // |v0| >= nrm
+      beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
+      inv = 1.0 / v0;
+    }
+    if (tid == 0) {
+      ee[k] = alpha;
+      dd[k] = akk;
+      betas[k] = beta;
+    }
+    gdouble* Vj = P1 + (int64_t)j * n;
+    gdouble* Qj = P1 + (int64_t)(nbe + j) * n;
+    gdouble* Qj2 = P2 + (int64_t)j * n;
+    gdouble* Vj2 = P2 + (int64_t)(nbe + j) * n;
+    for (int i = tid; i < n; i += bs) {
+      const double v = (beta == 0.0 || i <= k) ? 0.0 : (i == k + 1 ? 1.0 : nxt[i] * inv);
+      vk[i] = v;
+      if (beta != 0.0 && i > k) A[i + (int64_t)k * lda] = v;  // v stored below the diagonal
+      Vj[i] = v;
+      Vj2[i] = v;
     }
     __syncthreads();
-    const double beta = red[0];
-    // fused pass over columns j > k, rows i >= j; wavefront w takes columns
-    // k + 1 + w + nw c in groups of kRedCols, rows in tiles of kRedChunks 64-row chunks;
-    // the loads of the next tile are issued before the stores of the current one (loads
-    // and stores share one completion counter, so a load issued after a store would wait
-    // for it); a_ij v_j terms go to the wavefront's own LDS row pw[w] (in order within the
-    // wavefront)
+    // dot products of v with the panel's earlier vectors (rows > k)
+    for (int jj = wave; jj < j; jj += nw) {
+      gcdouble* Vc = P1 + (int64_t)jj * n;
+      gcdouble* Qc = P1 + (int64_t)(nbe + jj) * n;
+      double a = 0.0, b = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) {
+        a += Qc[i] * vk[i];
+        b += Vc[i] * vk[i];
+      }
+      a = wave_sum_d(a);
+      b = wave_sum_d(b);
+      if (lane == 0) {
+        xw[jj] = a;
+        xv[jj] = b;
+      }
+    }
+    // read-only pass over the stored trailing lower triangle: wavefront w takes columns
+    // k + 1 + w + nw c in groups of kRedCols, rows in tiles of kRedChunks 64-row chunks,
+    // the next tile's loads issued before the current one is consumed; a_ij v_j terms go
+    // to the wavefront's own LDS row pw[w] (in order within the wavefront)
     double* pwr = pw + wave * n;
     for (int i = k + 1 + lane; i < n; i += 64) pwr[i] = 0.0;
     const int64_t cstep = (int64_t)nw * lda;
@@ -654,15 +708,12 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
         for (int c = 0; c < kRedCols; ++c) t[h][c] = (i < n && i >= tj0 + c * nw) ? colj[i + c * cstep] : 0.0;
       }
     };
-    double vj[kRedCols], vpj[kRedCols], qpj[kRedCols], dot[kRedCols];
+    double vj[kRedCols], dot[kRedCols];
     auto start_group = [&](int tj0) {
 #pragma unroll
       for (int c = 0; c < kRedCols; ++c) {
         const int jc = tj0 + c * nw;
-        const bool ok = jc < n;
-        vj[c] = ok ? vk[jc] : 0.0;
-        vpj[c] = ok ? vp[jc] : 0.0;
-        qpj[c] = ok ? qp[jc] : 0.0;
+        vj[c] = jc < n ? vk[jc] : 0.0;
         dot[c] = 0.0;
       }
     };
@@ -675,23 +726,18 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
       if (ni0 >= n) { nj0 = j0 + kRedCols * nw; ni0 = nj0; }
       double nxtt[kRedChunks][kRedCols];
       if (nj0 < n) load_tile(nxtt, nj0, ni0);
-      gdouble* colj = A + (int64_t)j0 * lda;
 #pragma unroll
       for (int h = 0; h < kRedChunks; ++h) {
         const int i = i0 + 64 * h + lane;
         if (i >= n) continue;
-        const double vki = vk[i], vpi = vp[i], qpi = qp[i];
+        const double vki = vk[i];
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < kRedCols; ++c) {
           const int jc = j0 + c * nw;
-          if (i >= jc) {
-            const double x = cur[h][c] - vpi * qpj[c] - qpi * vpj[c];
-            colj[i + c * cstep] = x;
-            if (jc == k + 1) nxt[i] = x;
-            dot[c] += x * vki;
-            if (i > jc) acc += x * vj[c];
-          }
+          const double x = cur[h][c];  // zero outside the triangle
+          dot[c] += x * vki;
+          if (i > jc) acc += x * vj[c];
         }
         pwr[i] += acc;
       }
@@ -711,72 +757,72 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_reduce_kernel(const EigDe
       i0 = ni0;
     }
     __syncthreads();
+    // p = A_k v (beta p kept in pd), and the panel terms of the next column
+    const bool more = j + 1 < nbe;
     double pv = 0.0;
-    for (int i = k + 1 + tid; i < n; i += bs) {
+    for (int i = tid; i < n; i += bs) {
+      if (i <= k) continue;
       double p = pd[i];
       for (int w2 = 0; w2 < nw; ++w2) p += pw[w2 * n + i];
+      double cn = 0.0;
+      for (int jj = 0; jj < j; ++jj) {
+        const double vi = P1[i + (int64_t)jj * n], qi = P1[i + (int64_t)(nbe + jj) * n];
+        p -= vi * xw[jj] + qi * xv[jj];
+        if (more) cn += vi * P1[k + 1 + (int64_t)(nbe + jj) * n] + qi * P1[k + 1 + (int64_t)jj * n];
+      }
       p *= beta;
-      qk[i] = p;
+      pd[i] = p;
+      if (more) nxt[i] = cn;
       pv += p * vk[i];
     }
-    for (int i = tid; i <= k && i < n; i += bs) qk[i] = 0.0;
-    const double vtp = block_sum(pv, red, tid, bs);
+    const double vtp = block_sum(pv, red, tid, bs);  // also publishes pd
     const double K = 0.5 * beta * vtp;
-    for (int i = k + 1 + tid; i < n; i += bs) qk[i] -= K * vk[i];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 3) {  // the last step's update on the trailing 2 x 2 block
-      const int k = n - 3;
-      const double* vp = tsm + (k & 1) * n;
-      const double* qp = tsm + (2 + (k & 1)) * n;
-      for (int j = n - 2; j < n; ++j)
-        for (int i = j; i < n; ++i) A[i + (int64_t)j * lda] -= vp[i] * qp[j] + qp[i] * vp[j];
+    const double q1 = pd[k + 1] - K * vk[k + 1];
+    for (int i = tid; i < n; i += bs) {
+      const double q = i <= k ? 0.0 : pd[i] - K * vk[i];
+      Qj[i] = q;
+      Qj2[i] = q;
+      // column k + 1 after step k, rows >= k + 1
+      if (more && i > k) nxt[i] = A[i + (int64_t)(k + 1) * lda] - nxt[i] - vk[i] * q1 - q * vk[k + 1];
     }
-    if (n >= 2) {
-      dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * lda];
-      ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * lda];
-      betas[n - 2] = 0.0;
-    }
-    dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda];
-    ee[n - 1] = 0.0;
-    betas[n - 1] = 0.0;
   }
 }
 
-// 2.-3. Eigenvalues (bisection) and eigenvectors (inverse iteration) of T, one workgroup
-// per matrix; the vectors go to the work area in descending order of the eigenvalues.
-__global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc* __restrict__ descs) {
-  __shared__ double red[kTriThreads / 64];
-  __shared__ int sh_nblk, sh_nruns;
-  // d, e, e2, lam, vsh, psh: n doubles each; block starts: n + 1 ints
-  extern __shared__ double tsm[];
-  const EigDesc D = descs[blockIdx.x];
+// 1c. Last 2 x 2 block (or the single entry) of T, after the last trailing update.
+__global__ void tridiag_finish_kernel(const EigDesc* __restrict__ descs, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const EigDesc D = descs[p];
   const int n = D.n;
   if (n <= 0) return;
+  gdouble* A = gbl(D.work);
+  if (*tri_diag_flag(A, n) != 0.0) return;
+  gdouble* tail = tri_tail(A, n);
+  gdouble* betas = tail;
+  gdouble* dd = tail + n;
+  gdouble* ee = tail + 2 * n;
+  if (n >= 2) {
+    dd[n - 2] = A[(n - 2) + (int64_t)(n - 2) * n];
+    ee[n - 2] = A[(n - 1) + (int64_t)(n - 2) * n];
+    betas[n - 2] = 0.0;
+  }
+  dd[n - 1] = A[(n - 1) + (int64_t)(n - 1) * n];
+  ee[n - 1] = 0.0;
+  betas[n - 1] = 0.0;
+}
+
+
+// Load d, e of T into LDS, bound ||T|| (Gershgorin) and split T at negligible off-diagonal
+// entries into unreduced blocks (starts in bstart, count returned); e2 = e^2.
+__device__ int tri_blocks(const EigDesc& D, int n, double* dd, double* ee, double* e2, int* bstart, int* sh_nblk,
+                          double* tn_out) {
   const int tid = threadIdx.x, bs = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
-  const int64_t nn0 = (int64_t)n * n;
-  double* dd = tsm;
-  double* ee = dd + n;
-  double* e2 = ee + n;
-  double* lam = e2 + n;
-  double* vsh = lam + n;
-  double* psh = vsh + n;
-  int* bstart = reinterpret_cast<int*>(psh + n);
-  gdouble* W = gbl(D.work);
-  gdouble* scratch = W + nn0;  // per-thread inverse-iteration storage
-  // eigenvectors of T, stored transposed (element i of vector t at Z[i * n + t]) so that
-  // threads working on neighbouring vectors touch neighbouring addresses
-  gdouble* Z = gbl(D.V);
-  gcdouble* gd = W + 7 * nn0 + n;
-  const double shift = gd[2 * n];  // beta_k, then d, e, shift
+  gcdouble* gd = tri_tail(gbl(D.work), n) + n;
   for (int i = tid; i < n; i += bs) {
     dd[i] = gd[i];
     ee[i] = gd[n + i];
   }
   __syncthreads();
-  // Gershgorin bound of ||T||; negligible off-diagonals split T into unreduced blocks
   double tn = 0.0;
   for (int i = 0; i < n; ++i)
     tn = fmax(tn, fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0));
@@ -790,15 +836,37 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
         bstart[nb++] = i + 1;
       }
     bstart[nb] = n;
-    sh_nblk = nb;
+    *sh_nblk = nb;
   }
   __syncthreads();
-  const int nblk = sh_nblk;
   for (int i = tid; i < n; i += bs) e2[i] = ee[i] * ee[i];
   __syncthreads();
+  *tn_out = tn;
+  return *sh_nblk;
+}
+
+// 2. Eigenvalues of T by bisection, one workgroup per matrix: position t of block b = [s, s+m)
+//    holds the (t-s)-th smallest eigenvalue of that block.  The eigenvalues plus the shift go
+//    to w in descending order; the unshifted values and their ranks stay in the work area
+//    for the eigenvector phase.
+__global__ __launch_bounds__(kTriThreads) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ int sh_nblk;
+  // d, e, e2, lam: n doubles each; block starts: n + 1 ints
+  extern __shared__ double tsm[];
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  double* dd = tsm;
+  double* ee = dd + n;
+  double* e2 = ee + n;
+  double* lam = e2 + n;
+  int* bstart = reinterpret_cast<int*>(lam + n);
+  gdouble* tail = tri_tail(gbl(D.work), n);
+  const double shift = tail[3 * n];
+  double tn = 0.0;
+  const int nblk = tri_blocks(D, n, dd, ee, e2, bstart, &sh_nblk, &tn);
   const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
-  // 2. bisection: position t of block b = [s, s+m) holds the (t-s)-th smallest eigenvalue
-  //    of that block, so eigenvalues ascend within each block
   for (int t = tid; t < n; t += bs) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
@@ -823,6 +891,61 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
     lam[t] = 0.5 * (a + b);
   }
   __syncthreads();
+  gdouble* glam = tail + 3 * n + 1;
+  gdouble* grank = glam + n;
+  gdouble* wout = gbl(D.w);
+  for (int t = tid; t < n; t += bs) {
+    // descending order of the shifted values (ties: lower position first)
+    const double lt = lam[t] + shift;
+    int rank = 0;
+    for (int u = 0; u < n; ++u) {
+      const double lu = lam[u] + shift;
+      rank += (lu > lt) || (lu == lt && u < t);
+    }
+    glam[t] = lam[t];
+    grank[t] = rank;
+    wout[rank] = lt;
+  }
+}
+
+// 3. Eigenvectors of T by inverse iteration for the eigenvalues of descending rank below
+//    nvec (all when nvec < 0), one workgroup per matrix; the vectors go to the work area in
+//    descending order, the other columns are not written.
+__global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double red[kTriThreads / 64];
+  __shared__ int sh_nblk, sh_nruns;
+  // d, e, e2, lam, vsh, psh, rank: n doubles each; block starts: n + 1 ints
+  extern __shared__ double tsm[];
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  const int nvec = D.nvec < 0 ? n : min(D.nvec, n);
+  if (nvec == 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+  const int64_t nn0 = (int64_t)n * n;
+  double* dd = tsm;
+  double* ee = dd + n;
+  double* e2 = ee + n;
+  double* lam = e2 + n;
+  double* vsh = lam + n;
+  double* psh = vsh + n;
+  double* rk = psh + n;
+  int* bstart = reinterpret_cast<int*>(rk + n);
+  gdouble* W = gbl(D.work);
+  gdouble* scratch = W + nn0;  // per-thread inverse-iteration storage
+  // eigenvectors of T, stored transposed (element i of vector t at Z[i * n + t]) so that
+  // threads working on neighbouring vectors touch neighbouring addresses
+  gdouble* Z = gbl(D.V);
+  gcdouble* tail = tri_tail(W, n);
+  const double shift = tail[3 * n];
+  for (int i = tid; i < n; i += bs) {
+    lam[i] = tail[3 * n + 1 + i];
+    rk[i] = tail[4 * n + 1 + i];
+  }
+  double tn = 0.0;
+  const int nblk = tri_blocks(D, n, dd, ee, e2, bstart, &sh_nblk, &tn);
+  (void)e2;
   // 3. inverse iteration within each block; vectors vanish outside their block
   double lmax = 0.0;
   for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
@@ -848,6 +971,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
     gdouble* mult = w + nn;
     gdouble* piv = mult + nn;
     for (int j = t; j <= last; ++j) {
+      if (rk[j] >= nvec) continue;
       gdouble* z = Z + j;  // element i at z[i * ld]
       if (fabs(lam[j]) <= cut || m == 1) {
         for (int i = 0; i < n; ++i) z[i * ld] = (m == 1 && fabs(lam[j]) > cut && i == s) ? 1.0 : 0.0;
@@ -859,6 +983,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
       for (int it = 0; it < 3; ++it) {
         tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
         for (int jj = t; jj < j; ++jj) {
+          if (rk[jj] >= nvec) continue;
           gcdouble* y = Z + jj;
           double dot = 0.0;
           for (int i = s; i < s + m; ++i) dot += y[i * ld] * z[i * ld];
@@ -886,7 +1011,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
         while (last + 1 < e && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
         if (last + 1 - t > kThreadCluster) {
           e2[3 * nr] = t; e2[3 * nr + 1] = last; e2[3 * nr + 2] = b;
-          for (int q = t; q <= last; ++q) vsh[q] = 1.0;
+          for (int q = t; q <= last; ++q) vsh[q] = rk[q] < nvec ? 1.0 : 0.0;
           ++nr;
         }
         t = last + 1;
@@ -929,11 +1054,16 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
       const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
       const int s = bstart[b], m = bstart[b + 1] - s;
       for (int j = r0; j <= r1; ++j) {
+        if (vsh[j] == 0.0) continue;
         gdouble* z = Z + j;
         for (int pass = 0; pass < 2 && j > r0; ++pass) {
           for (int jj = r0 + wave; jj < j; jj += nw) {
             gcdouble* y = Z + jj;
             double dot = 0.0;
+            if (vsh[jj] == 0.0) {
+              if (lane == 0) psh[jj - r0] = 0.0;
+              continue;
+            }
             for (int i = s + lane; i < s + m; i += 64) dot += y[i * ld] * z[i * ld];
             dot = wave_sum_d(dot);
             if (lane == 0) psh[jj - r0] = dot;
@@ -941,7 +1071,8 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
           __syncthreads();
           for (int i = s + tid; i < s + m; i += bs) {
             double acc = 0.0;
-            for (int jj = r0; jj < j; ++jj) acc += psh[jj - r0] * Z[i * ld + jj];
+            for (int jj = r0; jj < j; ++jj)
+              if (vsh[jj] != 0.0) acc += psh[jj - r0] * Z[i * ld + jj];
             z[i * ld] -= acc;
           }
           __syncthreads();
@@ -956,28 +1087,17 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
     }
   }
   __syncthreads();
-  for (int t = tid; t < n; t += bs) lam[t] += shift;
-  __syncthreads();
   // eigenvalues at or below the cut carry zero vectors
   double lmx = 0.0;
-  for (int i = 0; i < n; ++i) lmx = fmax(lmx, fabs(lam[i]));
+  for (int i = 0; i < n; ++i) lmx = fmax(lmx, fabs(lam[i] + shift));
   const double vcut = D.abs_tol * lmx;
-  // descending order (ties: lower position first) into the eigenvector area of T
+  // descending order into the eigenvector area of T, wanted columns only
   gdouble* ZT = W + 6 * nn0;
-  gdouble* wout = gbl(D.w);
-  for (int t = tid; t < n; t += bs) {
-    int rank = 0;
-    const double lt = lam[t];
-    for (int u = 0; u < n; ++u) rank += (lam[u] > lt) || (lam[u] == lt && u < t);
-    e2[t] = rank;
-  }
-  __syncthreads();
-  for (int t = tid; t < n; t += bs) wout[int(e2[t])] = lam[t];
   for (int e = tid; e < n * n; e += bs) {
     const int i = e / n, c = e - i * n;  // Z is transposed: element i of vector c at Z[i n + c]
-    ZT[i + (int64_t)int(e2[c]) * n] = fabs(lam[c]) <= vcut ? 0.0 : Z[e];
+    const int rc = int(rk[c]);
+    if (rc < nvec) ZT[i + (int64_t)rc * n] = fabs(lam[c] + shift) <= vcut ? 0.0 : Z[e];
   }
-  if (tid == 0 && D.sweeps) *D.sweeps = -1;
 }
 
 // 4. Back-transformation V = H_0 ... H_{n-3} Z_T: wavefront w of workgroup (x, p) owns
@@ -988,12 +1108,20 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = 8 * blockIdx.x + 2 * wave;
   if (c0 >= n) return;
-  const bool two = c0 + 1 < n;
+  gdouble* Vout = gbl(D.V);
+  const int nvec = D.nvec < 0 ? n : min(D.nvec, n);
+  if (c0 >= nvec) {  // columns beyond the wanted ones are zero
+    for (int r = lane; r < n; r += 64) {
+      Vout[r + (int64_t)c0 * n] = 0.0;
+      if (c0 + 1 < n) Vout[r + (int64_t)(c0 + 1) * n] = 0.0;
+    }
+    return;
+  }
+  const bool two = c0 + 1 < nvec;
   const int64_t nn0 = (int64_t)n * n;
   gcdouble* A = gbl(D.work);
   gcdouble* ZT = A + 6 * nn0;
   gcdouble* betas = A + 7 * nn0;
-  gdouble* Vout = gbl(D.V);
   double z0[kBackRows], z1[kBackRows];
 #pragma unroll
   for (int j = 0; j < kBackRows; ++j) {
@@ -1027,16 +1155,21 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
     const int r = lane + 64 * j;
     if (r < n) {
       Vout[r + (int64_t)c0 * n] = z0[j];
-      if (two) Vout[r + (int64_t)(c0 + 1) * n] = z1[j];
+      if (c0 + 1 < n) Vout[r + (int64_t)(c0 + 1) * n] = two ? z1[j] : 0.0;
     }
   }
 }
 
-static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : (nmax <= 512 ? kTriThreads : 512); }
+static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : kTriThreads; }
+static int panel_threads(int nmax) { return nmax <= 64 ? 256 : kRedThreads; }
 
-// LDS bytes: reduction (6 + nw) n doubles; vectors 6 n doubles + (n + 1) ints.
-static size_t tridiag_reduce_lds(int n, int threads) { return size_t(6 + threads / 64) * n * sizeof(double); }
-static size_t tridiag_vec_lds(int n) { return size_t(6) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
+// LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 4 n doubles and vectors 7 n
+// doubles, each with n + 1 ints.
+static size_t tridiag_panel_lds(int n, int threads) {
+  return (size_t(3 + threads / 64) * n + 2 * kTriPanel) * sizeof(double);
+}
+static size_t tridiag_values_lds(int n) { return size_t(4) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
+static size_t tridiag_vec_lds(int n) { return size_t(7) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
 
 static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
   if (shm <= 65536) return;
@@ -1053,24 +1186,48 @@ static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
   if (shm > *granted) throw std::runtime_error("eig: tridiagonal solver needs more LDS than the device grants");
 }
 
+void launch_tri_prepare(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
+  if (nprob <= 0) return;
+  if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  hipLaunchKernelGGL(tridiag_prepare_kernel, dim3(nprob), dim3(nmax <= 64 ? 256 : kRedThreads), 0, s, d);
+  PV_LAUNCH_CHECK();
+}
+
+void launch_tri_panel(const EigDesc* d, int nprob, int nmax, int k0, hipStream_t s) {
+  if (nprob <= 0 || k0 + 2 >= nmax) return;
+  if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  static size_t granted = 0;
+  const int threads = panel_threads(nmax);
+  const size_t shm = tridiag_panel_lds(nmax, threads);
+  lds_opt_in((const void*)tridiag_panel_kernel, shm, &granted);
+  hipLaunchKernelGGL(tridiag_panel_kernel, dim3(nprob), dim3(threads), shm, s, d, k0);
+  PV_LAUNCH_CHECK();
+}
+
+void launch_tri_finish(const EigDesc* d, int nprob, hipStream_t s) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(tridiag_finish_kernel, dim3((nprob + 63) / 64), dim3(64), 0, s, d, nprob);
+  PV_LAUNCH_CHECK();
+}
+
 void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  if (phases & 1) throw std::runtime_error("eig: the reduction runs through the panel launchers");
   const int threads = tridiag_threads(nmax);
-  const int rthreads = nmax <= 64 ? 256 : kRedThreads;
-  static size_t granted_reduce = 0, granted_vec = 0;
-  const size_t shm_r = tridiag_reduce_lds(nmax, rthreads), shm_v = tridiag_vec_lds(nmax);
-  lds_opt_in((const void*)tridiag_reduce_kernel, shm_r, &granted_reduce);
+  static size_t granted_values = 0, granted_vec = 0;
+  const size_t shm_w = tridiag_values_lds(nmax), shm_v = tridiag_vec_lds(nmax);
+  lds_opt_in((const void*)tridiag_values_kernel, shm_w, &granted_values);
   lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
-  if (phases & 1) {
-    hipLaunchKernelGGL(tridiag_reduce_kernel, dim3(nprob), dim3(rthreads), shm_r, s, d);
-    PV_LAUNCH_CHECK();
-  }
   if (phases & 2) {
-    hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
+    hipLaunchKernelGGL(tridiag_values_kernel, dim3(nprob), dim3(threads), shm_w, s, d);
     PV_LAUNCH_CHECK();
   }
   if (phases & 4) {
+    hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
+    PV_LAUNCH_CHECK();
+  }
+  if (phases & 8) {
     hipLaunchKernelGGL(tridiag_back_kernel, dim3((nmax + 7) / 8, nprob), dim3(256), 0, s, d);
     PV_LAUNCH_CHECK();
   }

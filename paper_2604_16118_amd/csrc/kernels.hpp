@@ -38,6 +38,9 @@ struct EigDesc {
   double* work;  // n*n + n(n+1)/2 doubles
   int* sweeps;   // optional: number of sweeps taken (diagnostics), may be null
   double abs_tol;  // rotations need |a_pq| > abs_tol * max_i |a_ii| (0: relative test only)
+  // tridiagonal solver: eigenvectors for the nvec largest eigenvalues only (negative: all);
+  // the other columns of V are zero.  The Jacobi solver always returns all.
+  int nvec = -1;
 };
 
 // W-step (application of one MPO site to a partially contracted tensor).  Task t writes
@@ -77,7 +80,9 @@ struct ScaleDesc {
   int sqrt_s;  // 1: use sqrt(max(s[j], 0))
 };
 
-// prec 0: float64 MFMA; prec 1: operands rounded to float32, float32 MFMA accumulation.
+// prec 0: float64 MFMA; prec 1: operands rounded to float32, float32 MFMA accumulation;
+// prec 2: float64 MFMA, the instance used for the trailing updates of the tridiagonal
+// reduction.
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 // mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
@@ -85,12 +90,22 @@ void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t 
 void launch_eig(const EigDesc* d_desc, int nprob, int nmax, int mode, hipStream_t s);
 // Fastest mode available for an n x n problem on this device.
 int eig_mode(int n);
-// Tridiagonalisation (phase bit 1), bisection + inverse iteration (bit 2),
-// back-transformation (bit 4), one launch each, in that order; work holds
-// tri_work_doubles(n) doubles; abs_tol is the relative cut below which eigenvectors are
-// returned as zero.
+// Tridiagonal eigensolver.  Reduction: launch_tri_prepare, then for k0 = 0, kTriPanel, ...
+// while k0 + 2 < nmax one launch_tri_panel followed by the trailing update of every
+// problem with k0 + 2 < n, A[o:, o:] -= P1[o:, :] P2[o:, :]^T with o = k0 + nbe,
+// nbe = min(kTriPanel, n - 2 - k0), P1 = work + n^2, P2 = P1 + 2 nbe n (ld n, 2 nbe columns),
+// then launch_tri_finish.  After it, launch_eig_tridiag runs eigenvalues by bisection
+// (phase bit 2), eigenvectors by inverse iteration (bit 4) and the back-transformation
+// (bit 8), one launch each, in that order (the eigenvalues are final after bit 2, so a
+// caller may read them and set nvec before the vector phases).  work holds
+// tri_work_doubles(n) doubles and carries the state between launches; abs_tol is the
+// relative cut below which eigenvectors are returned as zero.
+constexpr int kTriPanel = 32;
+void launch_tri_prepare(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
+void launch_tri_panel(const EigDesc* d_desc, int nprob, int nmax, int k0, hipStream_t s);
+void launch_tri_finish(const EigDesc* d_desc, int nprob, hipStream_t s);
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
-inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(3) * n + 1; }
+inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 1; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in
 // place (lower triangle; the upper triangle is zeroed).  A column whose pivot (Schur
 // complement diagonal) is at most kCholDrop times its original diagonal entry depends

@@ -22,7 +22,7 @@ EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
-    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
+        L.pv_sym_eig_top.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.pv_mpo_bond_dims.argtypes = [C.c_int, dp, dp, ip, ip]
         L.pv_mpo_dense.argtypes = [C.c_int, dp, dp, C.c_double, dp]
@@ -257,12 +258,18 @@ class Context:
                     iterations=res.iterations, converged=bool(res.converged),
                     eta_res=res.eta_res, s_last=res.s_last, s_prev=res.s_prev), rows, psi.value
 
-    def sym_eig(self, A, method):
+    def sym_eig(self, A, method, nvec=None):
         A = _f64(np.asfortranarray(A))
         n = A.shape[0]
         w = np.zeros(n)
         V = np.zeros((n, n), order="F")
-        _check(lib().pv_sym_eig(self._p, n, _dp(A.ravel(order="F")), _dp(w), V.ctypes.data_as(C.POINTER(C.c_double)), int(method)))
+        Vp = V.ctypes.data_as(C.POINTER(C.c_double))
+        if nvec is None:
+            _check(lib().pv_sym_eig(self._p, n, _dp(A.ravel(order="F")), _dp(w), Vp, int(method)))
+        else:
+            if method != 1:
+                raise ValueError("a partial eigenvector set needs method 1")
+            _check(lib().pv_sym_eig_top(self._p, n, _dp(A.ravel(order="F")), _dp(w), Vp, int(nvec)))
         return w, V
 
     def cholesky(self, A):
@@ -273,7 +280,7 @@ class Context:
         return W
 
     def timers(self):
-        n = 10
+        n = 12
         ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
         calls = np.zeros(n, np.int32)
         _check(lib().pv_timers(self._p, n, _dp(ms), _dp(fl), _dp(by), _ip(calls)))

@@ -138,3 +138,33 @@ def test_sym_eig_zero_and_diagonal(ctx, method):
     assert np.abs(w - d[::-1]).max() <= 1e-14 * 5
     nz = np.abs(w) > 1e-12 * 5
     assert np.abs(np.abs(V[:, nz]).max(axis=0) - 1).max() <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["rand", "gram_graded", "cluster", "degenerate", "zero_rows"])
+@pytest.mark.parametrize("n,nvec", [(41, 0), (41, 7), (130, 65), (257, 1), (257, 256), (300, 300)])
+def test_sym_eig_top(ctx, kind, n, nvec):
+    """Leading eigenvectors only: the eigenvalues are those of the full solve, the first
+    nvec columns pass the same checks, the rest are zero."""
+    rng = np.random.default_rng(7000 + n + 13 * nvec + sorted(CASES).index(kind))
+    A = CASES[kind](n, rng)
+    A = (A + A.T) / 2
+    w_all, V_all = ctx.sym_eig(A, 1)
+    w, V = ctx.sym_eig(A, 1, nvec=nvec)
+    assert np.array_equal(w, w_all)
+    assert np.all(V[:, nvec:] == 0.0)
+    # the computed columns come from the same inverse iteration, except inside clusters
+    # cut by nvec, where they are orthogonalised against fewer members
+    wr = np.linalg.eigvalsh(A)[::-1]
+    an = max(np.abs(wr).max(), 1e-300)
+    keep = [j for j in range(nvec) if abs(w[j]) > 1e-12 * an]
+    Vk = V[:, keep]
+    res = A @ Vk - Vk * w[keep]
+    assert np.abs(res).max(initial=0.0) <= 1e-11 * an * max(1.0, n / 100) + _cluster_width(wr, 1e-7 * an)
+    g = np.minimum(1e-7 * an, 1e-2 * np.abs(w[keep]))
+    orth_tol = 100 * 2.2e-16 * an / np.minimum.outer(g, g) + 1e-10 * max(1.0, n / 100)
+    assert np.all(np.abs(Vk.T @ Vk - np.eye(len(keep))) <= orth_tol)
+
+
+def test_sym_eig_top_rejects_bad_count(ctx):
+    with pytest.raises(Exception):
+        ctx.sym_eig(np.eye(4), 1, nvec=5)
