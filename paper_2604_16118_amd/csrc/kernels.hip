@@ -482,8 +482,11 @@ __device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble
 }
 
 constexpr int kRedThreads = 512;  // reduction kernels: 8 wavefronts with room for 256 VGPRs
+// Panel kernel: 16 wavefronts (128 VGPRs each) with tiles of 3 x kRedCols loads in flight;
+// more wavefronts beat deeper tiles for this latency-bound pass (measured on gfx950)
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelChunks = 3;
 constexpr int kRedCols = 4;  // columns per wavefront group in the reduction pass
-constexpr int kRedChunks = 4;  // 64-row chunks per iteration of that pass
 
 __device__ inline double block_max(double v, double* red, int tid, int bs) {
 #pragma unroll
@@ -610,8 +613,9 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_prepare_kernel(const EigD
 //     P1 = [V | Q] and P2 = [Q | V] (n x 2 nbe each, after the working copy), from which
 //     the caller applies A22 <- A22 - P1 P2^T to the trailing block (a GEMM) before the
 //     next panel.
-__global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDesc* __restrict__ descs, int k0) {
-  __shared__ double red[kRedThreads / 64];
+__global__ __launch_bounds__(kPanelThreads) void tridiag_panel_kernel(const EigDesc* __restrict__ descs, int k0) {
+  __shared__ double red[kPanelThreads / 64];
+  __shared__ double rowc[2 * kTriPanel];  // row k + 1 of the panel: Q, then V
   // v, next column, column products: n doubles each; panel dot products 2 kTriPanel;
   // nw x n per-wavefront row products
   extern __shared__ double tsm[];
@@ -675,13 +679,30 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDes
     }
     __syncthreads();
     // dot products of v with the panel's earlier vectors (rows > k)
+    if (tid < j) {
+      rowc[tid] = P1[k + 1 + (int64_t)(nbe + tid) * n];
+      rowc[kTriPanel + tid] = P1[k + 1 + (int64_t)tid * n];
+    }
     for (int jj = wave; jj < j; jj += nw) {
       gcdouble* Vc = P1 + (int64_t)jj * n;
       gcdouble* Qc = P1 + (int64_t)(nbe + jj) * n;
       double a = 0.0, b = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) {
-        a += Qc[i] * vk[i];
-        b += Vc[i] * vk[i];
+      // the loads of a 256-row pass are issued before they are used (addresses clamped)
+      for (int i0 = k + 1; i0 < n; i0 += 256) {
+        double qa[4], va[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ic = min(i0 + 64 * u + lane, n - 1);
+          qa[u] = Qc[ic];
+          va[u] = Vc[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u + lane;
+          const double vi = i < n ? vk[i] : 0.0;
+          a += qa[u] * vi;
+          b += va[u] * vi;
+        }
       }
       a = wave_sum_d(a);
       b = wave_sum_d(b);
@@ -691,18 +712,18 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDes
       }
     }
     // read-only pass over the stored trailing lower triangle: wavefront w takes columns
-    // k + 1 + w + nw c in groups of kRedCols, rows in tiles of kRedChunks 64-row chunks,
+    // k + 1 + w + nw c in groups of kRedCols, rows in tiles of kPanelChunks 64-row chunks,
     // the next tile's loads issued before the current one is consumed; a_ij v_j terms go
     // to the wavefront's own LDS row pw[w] (in order within the wavefront)
     double* pwr = pw + wave * n;
     for (int i = k + 1 + lane; i < n; i += 64) pwr[i] = 0.0;
     const int64_t cstep = (int64_t)nw * lda;
     int j0 = k + 1 + wave, i0 = j0;
-    double cur[kRedChunks][kRedCols];
-    auto load_tile = [&](double (&t)[kRedChunks][kRedCols], int tj0, int ti0) {
+    double cur[kPanelChunks][kRedCols];
+    auto load_tile = [&](double (&t)[kPanelChunks][kRedCols], int tj0, int ti0) {
       gcdouble* colj = A + (int64_t)tj0 * lda;
 #pragma unroll
-      for (int h = 0; h < kRedChunks; ++h) {
+      for (int h = 0; h < kPanelChunks; ++h) {
         const int i = ti0 + 64 * h + lane;
 #pragma unroll
         for (int c = 0; c < kRedCols; ++c) t[h][c] = (i < n && i >= tj0 + c * nw) ? colj[i + c * cstep] : 0.0;
@@ -722,12 +743,12 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDes
       load_tile(cur, j0, i0);
     }
     while (j0 < n) {
-      int nj0 = j0, ni0 = i0 + 64 * kRedChunks;
+      int nj0 = j0, ni0 = i0 + 64 * kPanelChunks;
       if (ni0 >= n) { nj0 = j0 + kRedCols * nw; ni0 = nj0; }
-      double nxtt[kRedChunks][kRedCols];
+      double nxtt[kPanelChunks][kRedCols];
       if (nj0 < n) load_tile(nxtt, nj0, ni0);
 #pragma unroll
-      for (int h = 0; h < kRedChunks; ++h) {
+      for (int h = 0; h < kPanelChunks; ++h) {
         const int i = i0 + 64 * h + lane;
         if (i >= n) continue;
         const double vki = vk[i];
@@ -750,7 +771,7 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDes
         if (nj0 < n) start_group(nj0);
       }
 #pragma unroll
-      for (int h = 0; h < kRedChunks; ++h)
+      for (int h = 0; h < kPanelChunks; ++h)
 #pragma unroll
         for (int c = 0; c < kRedCols; ++c) cur[h][c] = nxtt[h][c];
       j0 = nj0;
@@ -765,10 +786,22 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_panel_kernel(const EigDes
       double p = pd[i];
       for (int w2 = 0; w2 < nw; ++w2) p += pw[w2 * n + i];
       double cn = 0.0;
-      for (int jj = 0; jj < j; ++jj) {
-        const double vi = P1[i + (int64_t)jj * n], qi = P1[i + (int64_t)(nbe + jj) * n];
-        p -= vi * xw[jj] + qi * xv[jj];
-        if (more) cn += vi * P1[k + 1 + (int64_t)(nbe + jj) * n] + qi * P1[k + 1 + (int64_t)jj * n];
+      // panel terms in groups of 4 columns, each group's loads issued first
+      for (int jb = 0; jb < j; jb += 4) {
+        double va[4], qa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = min(jb + u, j - 1);
+          va[u] = P1[i + (int64_t)jj * n];
+          qa[u] = P1[i + (int64_t)(nbe + jj) * n];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (jb + u >= j) break;
+          const int jj = jb + u;
+          p -= va[u] * xw[jj] + qa[u] * xv[jj];
+          cn += va[u] * rowc[jj] + qa[u] * rowc[kTriPanel + jj];
+        }
       }
       p *= beta;
       pd[i] = p;
@@ -1161,7 +1194,7 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
 }
 
 static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : kTriThreads; }
-static int panel_threads(int nmax) { return nmax <= 64 ? 256 : kRedThreads; }
+static int panel_threads(int nmax) { return nmax <= 64 ? 256 : kPanelThreads; }
 
 // LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 4 n doubles and vectors 7 n
 // doubles, each with n + 1 ints.
