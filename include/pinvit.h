@@ -188,6 +188,15 @@ pv_status pv_timers_reset(pv_ctx* ctx);
  * are returned as zero).  For tests. */
 pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method);
 
+/* C = alpha op(A) op(B) + beta C on the device through the grouped block GEMM of the
+ * operator contractions (the tile shape and split-K choice are the library's own):
+ * column-major host arrays, op(A) = A (M x K, ld lda) for ta = 0 or A^T (A is K x M) for
+ * ta = 1, likewise op(B) (K x N) with tb; C is M x N with ld ldc.  precision 0: float64
+ * MFMA; 1: operands rounded to float32, float32 accumulation.  PV_EINVAL for bad sizes,
+ * leading dimensions or flags.  For tests. */
+pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb,
+                  int tb, double* C, int ldc, double alpha, double beta, int precision);
+
 /* As pv_sym_eig with method 1, but eigenvectors only for the nvec largest eigenvalues
  * (0 <= nvec <= n; columns nvec.. of V are zero; all n eigenvalues are returned).  The
  * truncations use this form: they select ranks from the eigenvalues first and compute

@@ -537,6 +537,18 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
   });
 }
 
+pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb,
+                  int tb, double* C, int ldc, double alpha, double beta, int precision) {
+  return guard([&] {
+    if (!ctx || !C || (K > 0 && (!A || !B))) fail(PV_EINVAL, "null argument");
+    if (M < 1 || N < 1 || K < 0) fail(PV_EINVAL, "sizes out of range");
+    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) fail(PV_EINVAL, "ta, tb must be 0 or 1");
+    if (lda < (ta ? K : M) || lda < 1 || ldb < (tb ? N : K) || ldb < 1 || ldc < M) fail(PV_EINVAL, "leading dimension too small");
+    if (precision != 0 && precision != 1) fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32)");
+    gemm_host(ctx->c, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, precision);
+  });
+}
+
 pv_status pv_sym_eig_top(pv_ctx* ctx, int n, const double* A, double* w, double* V, int nvec) {
   return guard([&] {
     if (!ctx || !A || !w || !V) fail(PV_EINVAL, "null argument");

@@ -278,6 +278,7 @@ struct GemmBatch {
       c.end(T_COPY, a, 0, 16.0 * zk_elems);
     }
     if (!list.empty()) {
+      if (tiles > INT32_MAX) fail(PV_EINVAL, "GEMM batch too large for one launch");
       GemmDesc* dd = c.upload(list);
       const int tc = cls >= 0 ? cls : (prec ? T_GEMM32 : T_GEMM);
       hipEvent_t a; c.begin(tc, a);
@@ -969,6 +970,21 @@ void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host
   }
   PV_HIP(hipMemcpyAsync(w_host, w.p, size_t(n) * 8, hipMemcpyDeviceToHost, c.stream));
   PV_HIP(hipMemcpyAsync(V_host, V.p, size_t(n) * n * 8, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+}
+
+void gemm_host(Ctx& c, int M, int N, int K, const double* A_host, int lda, int ta, const double* B_host, int ldb,
+               int tb, double* C_host, int ldc, double alpha, double beta, int precision) {
+  const size_t na = size_t(lda) * (ta ? M : K), nb = size_t(ldb) * (tb ? K : N), nc = size_t(ldc) * N;
+  Buf A(c.pool, std::max<size_t>(na, 1)), B(c.pool, std::max<size_t>(nb, 1)), C(c.pool, std::max<size_t>(nc, 1));
+  if (na) PV_HIP(hipMemcpyAsync(A.p, A_host, na * 8, hipMemcpyHostToDevice, c.stream));
+  if (nb) PV_HIP(hipMemcpyAsync(B.p, B_host, nb * 8, hipMemcpyHostToDevice, c.stream));
+  PV_HIP(hipMemcpyAsync(C.p, C_host, nc * 8, hipMemcpyHostToDevice, c.stream));
+  GemmBatch g;
+  g.prec = precision;
+  g.add(A.p, lda, ta, B.p, ldb, tb, C.p, ldc, M, N, K, alpha, beta);
+  g.run(c);
+  PV_HIP(hipMemcpyAsync(C_host, C.p, nc * 8, hipMemcpyDeviceToHost, c.stream));
   c.sync();
 }
 

@@ -182,6 +182,8 @@ double norm_canonical(Ctx& c, const Mps& x);
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
 double norm2(Ctx& c, const Mps& x);
 void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method, int nvec = -1);
+void gemm_host(Ctx& c, int M, int N, int K, const double* A_host, int lda, int ta, const double* B_host, int ldb,
+               int tb, double* C_host, int ldc, double alpha, double beta, int precision);
 void cholesky(Ctx& c, int n, const double* A_host, double* W_host);
 
 }  // namespace pv

@@ -38,28 +38,40 @@ __device__ inline double wave_sum_d(double v) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// Grouped GEMM.  One workgroup (4 waves) computes a 64x64 tile of one problem;
-// each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_f64_16x16x4f64 (or
-// v_mfma_f32_16x16x4f32 in the float32 variant).  Operand layout of both (wave64): lane l
-// supplies A[l%16][l/16] and B[l/16][l%16]; the 16x16 result lives in 4 values per lane,
-// element r of lane l being D[4r + l/16][l%16] for float64 and D[4(l/16) + r][l%16] for
-// float32 (both measured with single-instruction probes on gfx950).
+// Grouped GEMM.  One workgroup (4 waves, 2 x 2) computes a BM x BN tile of one problem;
+// each wave owns a (BM/2) x (BN/2) quadrant as (BM/32) x (BN/32) tiles of
+// v_mfma_f64_16x16x4f64 (or v_mfma_f32_16x16x4f32 in the float32 variant).  Operand
+// layout of both (wave64): lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 16x16
+// result lives in 4 values per lane, element r of lane l being D[4r + l/16][l%16] for
+// float64 and D[4(l/16) + r][l%16] for float32 (both measured with single-instruction
+// probes on gfx950).  The tile is 64 x 64 (BM x BN): measured on the L=48 workload, 128 x 64,
+// 64 x 128 and larger tiles lose more to the lower occupancy than they save in re-reads.
 // ---------------------------------------------------------------------------
-template <int PREC>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob) {
+template <int PREC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob, int ntiles) {
   // PREC 0: float64 operands on v_mfma_f64_16x16x4f64; PREC 1: operands rounded to float32
   // on v_mfma_f32_16x16x4f32 with float32 accumulation (C stays float64 in memory);
   // PREC 2: the float64 kernel again, a separate instance for the trailing updates of the
   // tridiagonal reduction so that profiles tell the two uses apart
   constexpr bool F64 = PREC != 1;
   typedef typename std::conditional<F64, double, float>::type T;
-  constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
+  constexpr int BK = kGemmBK;
+  constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread per K-tile
   // double-buffered K-tiles: the global loads of tile t+1 are held in registers while the
   // MFMAs of tile t run, then written to the other LDS buffer (one barrier per K-tile)
   __shared__ T As[2][BK][BM + 1];
   __shared__ T Bs[2][BK][BN + 1];
-  const int tile = blockIdx.x;
+  // XCD-aware order: workgroup b runs on XCD b % 8.  Tiles are dealt to the XCDs in groups
+  // of kGemmGroup consecutive ones (same row block of A, consecutive column blocks), so a
+  // group shares one L2 while every XCD still gets an even mix of the problems; the
+  // ragged end keeps the plain order.
+  const int b = blockIdx.x, span = 8 * kGemmGroup;
+  int tile = b;
+  if (b < ntiles / span * span) {
+    const int base = b - b % span, r = b - base;
+    tile = base + (r & 7) * kGemmGroup + (r >> 3);
+  }
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -106,9 +118,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = T(rb[r]);
   };
   typedef T T4 __attribute__((ext_vector_type(4)));
-  T4 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = T4{0, 0, 0, 0};
+  T4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = T4{0, 0, 0, 0};
   int buf = 0;
   if (g.kbeg < g.kend) {
     load(g.kbeg);
@@ -120,33 +134,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const T a0 = As[buf][kk + lk][wr * 32 + li];
-      const T a1 = As[buf][kk + lk][wr * 32 + 16 + li];
-      const T b0 = Bs[buf][kk + lk][wc * 32 + li];
-      const T b1 = Bs[buf][kk + lk][wc * 32 + 16 + li];
-      if constexpr (F64) {
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-      } else {
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-      }
+      T af[TM], bf[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) af[a] = As[buf][kk + lk][wr * (BM / 2) + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bf[b] = Bs[buf][kk + lk][wc * (BN / 2) + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          if constexpr (F64)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
     }
     if (more) stage(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-  for (int mi = 0; mi < 2; ++mi)
-    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+  for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < TN; ++nj)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         // result element r of lane l: row 4r + l/16 (float64 instruction), row
         // 4 (l/16) + r (float32 instruction), column l % 16 (measured on gfx950)
-        const int i = row0 + wr * 32 + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r);
-        const int j = col0 + wc * 32 + nj * 16 + li;
+        const int i = row0 + wr * (BM / 2) + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r);
+        const int j = col0 + wc * (BN / 2) + nj * 16 + li;
         if (i < g.M && j < g.N) {
           double v = g.alpha * double(acc[mi][nj][r]);
           gdouble* c = gC + i + (int64_t)j * g.ldc;
@@ -158,12 +174,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s) {
   if (total_tiles <= 0) return;
+  const dim3 g(total_tiles), b(256);
   if (prec == 0)
-    hipLaunchKernelGGL(gemm_kernel<0>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+    hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   else if (prec == 1)
-    hipLaunchKernelGGL(gemm_kernel<1>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+    hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   else
-    hipLaunchKernelGGL(gemm_kernel<2>, dim3(total_tiles), dim3(256), 0, s, d_desc, nprob);
+    hipLaunchKernelGGL((gemm_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   PV_LAUNCH_CHECK();
 }
 

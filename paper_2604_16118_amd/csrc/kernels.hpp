@@ -129,6 +129,7 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
 constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
+constexpr int kGemmGroup = 4;  // consecutive tiles kept on one XCD
 constexpr int kEigMax = 1024;
 
 }  // namespace pv

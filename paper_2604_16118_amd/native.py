@@ -22,7 +22,7 @@ EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
-    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
 
@@ -92,6 +92,8 @@ def lib():
         L.pv_timers_reset.argtypes = [C.c_void_p]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_sym_eig_top.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
+        L.pv_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int,
+                              dp, C.c_int, C.c_double, C.c_double, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.pv_mpo_bond_dims.argtypes = [C.c_int, dp, dp, ip, ip]
         L.pv_mpo_dense.argtypes = [C.c_int, dp, dp, C.c_double, dp]
@@ -271,6 +273,21 @@ class Context:
                 raise ValueError("a partial eigenvector set needs method 1")
             _check(lib().pv_sym_eig_top(self._p, n, _dp(A.ravel(order="F")), _dp(w), Vp, int(nvec)))
         return w, V
+
+    def gemm(self, A, B, Cin=None, ta=False, tb=False, alpha=1.0, beta=0.0, precision=0):
+        """alpha op(A) op(B) + beta C on the device (column-major copies of the operands)."""
+        A = _f64(np.asfortranarray(A))
+        B = _f64(np.asfortranarray(B))
+        M = A.shape[1] if ta else A.shape[0]
+        K = A.shape[0] if ta else A.shape[1]
+        N = B.shape[0] if tb else B.shape[1]
+        if (B.shape[1] if tb else B.shape[0]) != K:
+            raise ValueError("inner dimensions differ")
+        Cm = np.zeros((M, N), order="F") if Cin is None else np.array(Cin, dtype=np.float64, order="F", copy=True)
+        _check(lib().pv_gemm(self._p, M, N, K, _dp(A.ravel(order="F")), A.shape[0], int(bool(ta)),
+                             _dp(B.ravel(order="F")), B.shape[0], int(bool(tb)),
+                             _dp(Cm), M, float(alpha), float(beta), int(precision)))
+        return Cm
 
     def cholesky(self, A):
         A = _f64(np.asfortranarray(A))
