@@ -185,6 +185,54 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"in {dt:.2f} s (L=48 is beyond a dense 2^L vector)"}
 
 
+def batch_bench(a):
+    """Many independent Hamiltonians at once: problem b draws L from {12, 16, ..., 32} and a
+    rank cap from [32, 256] with a generator seeded by b (N = L/2, decayed integrals with
+    seed b); every problem runs `steps` iterations from its determinant with the
+    simultaneous truncation.  Timed: all problems one after another on one context each,
+    then all of them through pv_run_batch."""
+    import numpy as np
+
+    from paper_2604_16118_amd import native
+    from synth import make_problem
+
+    specs = []
+    for b in range(a.batch):
+        rng = np.random.default_rng(b)
+        L = int(rng.choice(np.arange(12, 33, 4)))
+        cap = int(rng.integers(32, 257))
+        specs.append((L, L // 2, cap, b))
+    ctxs = []
+    for L, N, cap, seed in specs:
+        p = make_problem("decayed", L, N, seed)
+        c = native.Context(0)
+        c.set_hamiltonian(p.h, p.v, N, p.gamma)
+        ctxs.append(c)
+    params = [dict(rank_cap=cap, max_iter=a.steps, tau=0.0, c=0.5, delta=10.0, m_zip=cap, truncation=1)
+              for _, _, cap, _ in specs]
+    # warm-up: code objects and memory pools of every context
+    native.run_batch(ctxs, [dict(p, max_iter=1) for p in params])
+    t0 = time.perf_counter()
+    seq = [c.run(**p)[0] for c, p in zip(ctxs, params)]
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bat = native.run_batch(ctxs, params)
+    t_bat = time.perf_counter() - t0
+    same = all(x["energy"] == y["energy"] for x, y in zip(seq, bat))
+    iters = sum(r["iterations"] for r in bat)
+    for c in ctxs:
+        c.close()
+    out = {"metric": "batched PINVIT iterations/s (independent Hamiltonians, one GPU)",
+           "value": iters / t_bat, "unit": "iter/s", "n_gpus": 1, "steps": a.steps,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{a.batch} decayed-integral Hamiltonians, L in {{12..32 step 4}}, N=L/2, "
+                                  f"rank cap in [32, 256], seeds 0..{a.batch - 1}, {a.steps} iterations each",
+                      "problems": a.batch},
+           "sequential_iter_per_s": iters / t_seq, "speedup_vs_sequential": t_seq / t_bat,
+           "energies_identical": same}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +244,8 @@ def main():
     ap.add_argument("--m-zip", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
+    ap.add_argument("--batch", type=int, default=0, metavar="B",
+                    help="instead of the L=48 run: B independent Hamiltonians, sequential vs pv_run_batch")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
     ap.add_argument("--pmc-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV", "BENCH_JSON"),
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
@@ -211,6 +261,9 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.batch > 0:
+        batch_bench(a)
+        return
 
     from paper_2604_16118_amd import native
     from synth import make_problem

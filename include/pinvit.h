@@ -166,6 +166,17 @@ pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap
 pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
                  pv_iter* hist, int hist_cap, int* psi);
 
+/* Batched independent problems (many Hamiltonians of uneven size at once): runs pv_run from
+ * the determinant on each of the `count` distinct contexts ctxs[i] (each with its
+ * Hamiltonian already set) with parameters prm[i], writing res[i] and, when status is not
+ * NULL, status[i].  Each context keeps its own HIP stream and memory pool; up to 16 host
+ * threads drive them at once, so the device overlaps the kernels of different problems.
+ * The results are those of pv_run on each context alone (the kernels are deterministic).
+ * Returns PV_OK when every problem succeeded, else the status of the first failed problem,
+ * whose message pv_last_error gives; PV_EINVAL for null pointers or a repeated context.
+ * A context must not be used by another thread during the call. */
+pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_result* res, pv_status* status);
+
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
  * Jacobi 10/3 n^3 each; tridiagonal solver: panel kernels 2/3 n^3 flops and 4/3 n^3

@@ -1,11 +1,15 @@
 // C ABI (include/pinvit.h) and the driver of Algorithm 2.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <set>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -524,6 +528,40 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
     }
     res->iterations = rows;
     if (psi_out) *psi_out = put(c, std::move(psi));
+  });
+}
+
+pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_result* res, pv_status* status) {
+  return guard([&] {
+    if (count < 0) fail(PV_EINVAL, "negative problem count");
+    if (count == 0) return;
+    if (!ctxs || !prm || !res) fail(PV_EINVAL, "null argument");
+    std::set<pv_ctx*> seen;
+    for (int i = 0; i < count; ++i) {
+      if (!ctxs[i]) fail(PV_EINVAL, "null context in the batch");
+      if (!seen.insert(ctxs[i]).second) fail(PV_EINVAL, "a context appears twice in the batch");
+    }
+    // problems are independent: each runs pv_run on its own context (own stream and memory
+    // pool) in a worker thread, so the device interleaves the kernels of different problems
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int workers = std::min<int>(count, int(std::min(hw, 16u)));
+    std::vector<pv_status> st(count, PV_OK);
+    std::vector<std::string> msg(count);
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int w = 0; w < workers; ++w)
+      pool.emplace_back([&] {
+        for (int i; (i = next.fetch_add(1)) < count;) {
+          const int dev = ctxs[i]->c.device;
+          st[i] = hipSetDevice(dev) == hipSuccess ? pv_run(ctxs[i], &prm[i], -1, &res[i], nullptr, 0, nullptr)
+                                                  : PV_EDEVICE;
+          if (st[i] != PV_OK) msg[i] = pv_last_error();
+        }
+      });
+    for (auto& t : pool) t.join();
+    if (status) std::copy(st.begin(), st.end(), status);
+    for (int i = 0; i < count; ++i)
+      if (st[i] != PV_OK) fail(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
   });
 }
 

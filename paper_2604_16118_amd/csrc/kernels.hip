@@ -5,6 +5,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -1221,8 +1222,12 @@ static size_t tridiag_panel_lds(int n, int threads) {
 static size_t tridiag_values_lds(int n) { return size_t(4) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
 static size_t tridiag_vec_lds(int n) { return size_t(7) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
 
+// One-time kernel attribute set-up, shared by contexts that run in parallel host threads.
+static std::mutex g_attr_mutex;
+
 static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
   if (shm <= 65536) return;
+  std::lock_guard<std::mutex> lock(g_attr_mutex);
   if (*granted == 0) {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
@@ -1361,6 +1366,7 @@ static size_t g_lds_limit = size_t(-1);
 
 // Largest dynamic LDS accepted for the LDS-resident variants (0 when the opt-in fails).
 static size_t eig_lds_limit() {
+  std::lock_guard<std::mutex> lock(g_attr_mutex);
   if (g_lds_limit == size_t(-1)) {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);

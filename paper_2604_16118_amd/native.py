@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_batch",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -88,6 +88,7 @@ def lib():
         L.pv_apply_s.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
         L.pv_run.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.POINTER(Result),
                              C.POINTER(Iter), C.c_int, ip]
+        L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
@@ -104,6 +105,32 @@ def lib():
 def _check(st):
     if st != 0:
         raise PvError(st, lib().pv_last_error().decode())
+
+
+def make_params(rank_cap, max_iter, tau=1e-10, c=0.5, delta=10.0, m_zip=0, c0=0.1, eps_num=0.0,
+                t_eig=0.5, c_lower=0.0, c_upper=0.0, max_retries=30, precision=0, truncation=0,
+                resume=None):
+    """pv_params of one run (defaults as in Context.run)."""
+    r = resume or {}
+    return Params(rank_cap, m_zip, max_iter, tau, c0, c, delta, eps_num, t_eig, c_lower,
+                  c_upper, max_retries, precision, truncation, r.get("eta_res", 0.0),
+                  r.get("s_last", 0.0), r.get("s_prev", 0.0))
+
+
+def run_batch(contexts, params):
+    """pv_run_batch: every context (Hamiltonian set) runs from its determinant with its own
+    keyword arguments (those of Context.run), concurrently.  Returns one result dict per
+    problem."""
+    n = len(contexts)
+    if len(params) != n:
+        raise ValueError("one parameter set per context")
+    ptrs = (C.c_void_p * max(n, 1))(*[ctx._p for ctx in contexts])
+    prm = (Params * max(n, 1))(*[make_params(**p) for p in params])
+    res = (Result * max(n, 1))()
+    st = (C.c_int * max(n, 1))()
+    _check(lib().pv_run_batch(ptrs, n, prm, res, st))
+    return [dict(energy=r.energy, lam=r.lambda_, rho=r.rho, bound=r.bound, iterations=r.iterations,
+                 converged=bool(r.converged)) for r in res[:n]]
 
 
 def _dp(a):
@@ -239,10 +266,8 @@ class Context:
     def run(self, rank_cap, max_iter, tau=1e-10, c=0.5, delta=10.0, m_zip=0, c0=0.1,
             eps_num=0.0, t_eig=0.5, c_lower=0.0, c_upper=0.0, max_retries=30, start=-1,
             precision=0, truncation=0, resume=None):
-        r = resume or {}
-        prm = Params(rank_cap, m_zip, max_iter, tau, c0, c, delta, eps_num, t_eig, c_lower,
-                     c_upper, max_retries, precision, truncation, r.get("eta_res", 0.0),
-                     r.get("s_last", 0.0), r.get("s_prev", 0.0))
+        prm = make_params(rank_cap, max_iter, tau, c, delta, m_zip, c0, eps_num, t_eig, c_lower,
+                          c_upper, max_retries, precision, truncation, resume)
         res = Result()
         hist = (Iter * max(max_iter, 1))()
         psi = C.c_int()
