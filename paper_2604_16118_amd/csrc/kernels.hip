@@ -477,7 +477,7 @@ __device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble
                           int64_t ld) {
   // forward: apply the row operations to the right-hand side
   double cur = x[0];
-#pragma unroll 4
+#pragma unroll 8
   for (int i = 0; i < n - 1; ++i) {
     const double nxt = x[(i + 1) * ld];
     const double m = mult[i * ld];
@@ -490,7 +490,7 @@ __device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble
   if (n < 2) return;
   double x0 = (x[(n - 2) * ld] - v[(n - 2) * ld] * x1) * u[(n - 2) * ld];
   x[(n - 2) * ld] = x0;
-#pragma unroll 4
+#pragma unroll 8
   for (int i = n - 3; i >= 0; --i) {
     const double xi = (x[i * ld] - v[i * ld] * x0 - w[i * ld] * x1) * u[i * ld];
     x[i * ld] = xi;
@@ -536,6 +536,10 @@ constexpr double kClusterTol = 1e-7;
 constexpr double kClusterRel = 1e-2;
 // Clusters up to this size are handled by one thread, longer ones by the workgroup.
 constexpr int kThreadCluster = 16;
+// Inverse-iteration solves per vector outside long clusters: with an eigenvalue from
+// bisection (error ~ eps ||T||) each solve shrinks the components along the other
+// eigenvectors by about eps ||T|| / gap, so two solves suffice at the cluster threshold.
+constexpr int kInvIters = 2;
 
 __device__ inline bool linked(double a, double b, double cut, double ctol) {
   return fabs(a) > cut && fabs(b) > cut && b - a <= fmin(ctol, kClusterRel * fmax(fabs(a), fabs(b)));
@@ -1031,7 +1035,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
       const double sigma = lam[j] + (j - t) * 10.0 * 2.2e-16 * tn;
       tri_factor(dd + s, ee + s, m, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv, ld);
       for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, j) : 0.0;
-      for (int it = 0; it < 3; ++it) {
+      for (int it = 0; it < kInvIters; ++it) {
         tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
         for (int jj = t; jj < j; ++jj) {
           if (rk[jj] >= nvec) continue;
