@@ -154,21 +154,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     __syncthreads();
     buf ^= 1;
   }
+  // result element r of lane l: row 4r + l/16 (float64 instruction), row 4 (l/16) + r
+  // (float32 instruction), column l % 16 (measured on gfx950).  With beta != 0 all loads of C
+  // are issued before any is used, so their latencies overlap.
+  auto row_of = [&](int mi, int r) { return row0 + wr * (BM / 2) + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r); };
+  auto col_of = [&](int nj) { return col0 + wc * (BN / 2) + nj * 16 + li; };
+  double cold[TM][TN][4];
+  if (g.beta != 0.0) {
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < TN; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row_of(mi, r), j = col_of(nj);
+          const int ic = min(i, g.M - 1), jc = min(j, g.N - 1);
+          cold[mi][nj][r] = gC[ic + (int64_t)jc * g.ldc];
+        }
+  }
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int nj = 0; nj < TN; ++nj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // result element r of lane l: row 4r + l/16 (float64 instruction), row
-        // 4 (l/16) + r (float32 instruction), column l % 16 (measured on gfx950)
-        const int i = row0 + wr * (BM / 2) + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r);
-        const int j = col0 + wc * (BN / 2) + nj * 16 + li;
+        const int i = row_of(mi, r), j = col_of(nj);
         if (i < g.M && j < g.N) {
           double v = g.alpha * double(acc[mi][nj][r]);
-          gdouble* c = gC + i + (int64_t)j * g.ldc;
-          if (g.beta != 0.0) v += g.beta * *c;
-          *c = v;
+          if (g.beta != 0.0) v += g.beta * cold[mi][nj][r];
+          gC[i + (int64_t)j * g.ldc] = v;
         }
       }
 }
