@@ -417,6 +417,8 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(const EigDesc* __restr
 // in the columns of V.
 // ---------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
+constexpr int kValuesPositions = 256;  // eigenvalues (threads) per workgroup of the bisection
+constexpr int kVectorPositions = 64;   // eigenvectors (threads) per workgroup of inverse iteration
 constexpr int kBackRows = kEigMax / 64;  // rows per lane when a wavefront holds a column
 
 __device__ inline double block_sum(double v, double* red, int tid, int bs) {
@@ -914,36 +916,35 @@ __device__ int tri_blocks(const EigDesc& D, int n, double* dd, double* ee, doubl
   return *sh_nblk;
 }
 
-// 2. Eigenvalues of T by bisection, one workgroup per matrix: position t of block b = [s, s+m)
-//    holds the (t-s)-th smallest eigenvalue of that block.  The eigenvalues plus the shift go
-//    to w in descending order; the unshifted values and their ranks stay in the work area
-//    for the eigenvector phase.
-__global__ __launch_bounds__(kTriThreads) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
+// 2. Eigenvalues of T by bisection: gridDim.x workgroups per matrix (blockIdx.y), each taking
+//    one contiguous range of positions; position t of block b = [s, s+m) holds the
+//    (t-s)-th smallest eigenvalue of that block.  The unshifted values go to the work area.
+__global__ __launch_bounds__(kValuesPositions) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
   __shared__ int sh_nblk;
-  // d, e, e2, lam: n doubles each; block starts: n + 1 ints
+  // d, e, e2: n doubles each; block starts: n + 1 ints
   extern __shared__ double tsm[];
-  const EigDesc D = descs[blockIdx.x];
+  const EigDesc D = descs[blockIdx.y];
   const int n = D.n;
-  if (n <= 0) return;
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int t0 = blockIdx.x * chunk, t1 = min(n, t0 + chunk);
+  if (n <= 0 || t0 >= t1) return;
   const int tid = threadIdx.x, bs = blockDim.x;
   double* dd = tsm;
   double* ee = dd + n;
   double* e2 = ee + n;
-  double* lam = e2 + n;
-  int* bstart = reinterpret_cast<int*>(lam + n);
-  gdouble* tail = tri_tail(gbl(D.work), n);
-  const double shift = tail[3 * n];
+  int* bstart = reinterpret_cast<int*>(e2 + n);
+  gdouble* glam = tri_tail(gbl(D.work), n) + 3 * n + 1;
   double tn = 0.0;
   const int nblk = tri_blocks(D, n, dd, ee, e2, bstart, &sh_nblk, &tn);
   const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
-  for (int t = tid; t < n; t += bs) {
+  for (int t = t0 + tid; t < t1; t += bs) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
       const int mid = (lo_b + hi_b + 1) >> 1;
       if (bstart[mid] <= t) lo_b = mid; else hi_b = mid - 1;
     }
     const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
-    if (m == 1) { lam[t] = dd[s]; continue; }
+    if (m == 1) { glam[t] = dd[s]; continue; }
     double lo = 1e300, hi = -1e300;
     for (int i = s; i < s + m; ++i) {
       const double r = (i > s ? fabs(ee[i - 1]) : 0.0) + (i < s + m - 1 ? fabs(ee[i]) : 0.0);
@@ -957,37 +958,56 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_values_kernel(const EigDe
       if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0 || b - a <= 1e-18 * tn) break;
       if (sturm_count(dd + s, e2 + s, m, mid, tiny + 1e-300) > t - s) b = mid; else a = mid;
     }
-    lam[t] = 0.5 * (a + b);
+    glam[t] = 0.5 * (a + b);
   }
-  __syncthreads();
+}
+
+// 2b. Descending ranks of the eigenvalues, the output w (eigenvalues plus the shift, in
+//     descending order; ties: lower position first) and the cut below which eigenvectors
+//     are returned as zero; one workgroup per matrix.
+__global__ __launch_bounds__(kTriThreads) void tridiag_rank_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double red[kTriThreads / 64];
+  extern __shared__ double tsm[];  // n shifted eigenvalues
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  gdouble* tail = tri_tail(gbl(D.work), n);
+  const double shift = tail[3 * n];
   gdouble* glam = tail + 3 * n + 1;
   gdouble* grank = glam + n;
   gdouble* wout = gbl(D.w);
+  double* lam = tsm;
+  double mx = 0.0;
+  for (int i = tid; i < n; i += bs) {
+    lam[i] = glam[i] + shift;
+    mx = fmax(mx, fabs(lam[i]));
+  }
+  mx = block_max(mx, red, tid, bs);  // also publishes lam
+  if (tid == 0) tail[5 * n + 1] = D.abs_tol * mx;
   for (int t = tid; t < n; t += bs) {
-    // descending order of the shifted values (ties: lower position first)
-    const double lt = lam[t] + shift;
+    const double lt = lam[t];
     int rank = 0;
-    for (int u = 0; u < n; ++u) {
-      const double lu = lam[u] + shift;
-      rank += (lu > lt) || (lu == lt && u < t);
-    }
-    glam[t] = lam[t];
+    for (int u = 0; u < n; ++u) rank += (lam[u] > lt) || (lam[u] == lt && u < t);
     grank[t] = rank;
     wout[rank] = lt;
   }
 }
 
 // 3. Eigenvectors of T by inverse iteration for the eigenvalues of descending rank below
-//    nvec (all when nvec < 0), one workgroup per matrix; the vectors go to the work area in
-//    descending order, the other columns are not written.
-__global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc* __restrict__ descs) {
+//    nvec (all when nvec < 0): gridDim.x workgroups per matrix (blockIdx.y), each taking
+//    the clusters that start in its range of positions; the vectors are left transposed in
+//    V, and tridiag_sort_kernel orders them.
+__global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double red[kTriThreads / 64];
   __shared__ int sh_nblk, sh_nruns;
   // d, e, e2, lam, vsh, psh, rank: n doubles each; block starts: n + 1 ints
   extern __shared__ double tsm[];
-  const EigDesc D = descs[blockIdx.x];
+  const EigDesc D = descs[blockIdx.y];
   const int n = D.n;
-  if (n <= 0) return;
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int t0 = blockIdx.x * chunk, t1 = min(n, t0 + chunk);
+  if (n <= 0 || t0 >= t1) return;
   const int nvec = D.nvec < 0 ? n : min(D.nvec, n);
   if (nvec == 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -1023,7 +1043,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
   const double ctol = kClusterTol * fmax(tn, 1e-300);
   const int64_t ld = n;
   const int64_t nn = (int64_t)n * n;
-  for (int t = tid; t < n; t += bs) {
+  for (int t = t0 + tid; t < t1; t += bs) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
       const int mid = (lo_b + hi_b + 1) >> 1;
@@ -1078,7 +1098,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
       while (t < e) {
         int last = t;
         while (last + 1 < e && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
-        if (last + 1 - t > kThreadCluster) {
+        if (last + 1 - t > kThreadCluster && t >= t0 && t < t1) {
           e2[3 * nr] = t; e2[3 * nr + 1] = last; e2[3 * nr + 2] = b;
           for (int q = t; q <= last; ++q) vsh[q] = rk[q] < nvec ? 1.0 : 0.0;
           ++nr;
@@ -1155,17 +1175,47 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_vec_kernel(const EigDesc*
       }
     }
   }
-  __syncthreads();
-  // eigenvalues at or below the cut carry zero vectors
-  double lmx = 0.0;
-  for (int i = 0; i < n; ++i) lmx = fmax(lmx, fabs(lam[i] + shift));
-  const double vcut = D.abs_tol * lmx;
-  // descending order into the eigenvector area of T, wanted columns only
+}
+
+// 3b. The eigenvectors of T in descending order of their eigenvalues into the work area:
+//     columns of rank below nvec, zero below the cut.  Each workgroup moves a tile of 32
+//     positions x 64 rows through LDS (coalesced on both sides).
+__global__ __launch_bounds__(256) void tridiag_sort_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double tile[32][65];
+  __shared__ int rks[32];
+  __shared__ int keep[32];
+  const EigDesc D = descs[blockIdx.z];
+  const int n = D.n;
+  const int c0 = blockIdx.x * 32, i0 = blockIdx.y * 64;
+  if (c0 >= n || i0 >= n) return;
+  const int nvec = D.nvec < 0 ? n : min(D.nvec, n);
+  if (nvec == 0) return;
+  const int tid = threadIdx.x;
+  const int64_t nn0 = (int64_t)n * n;
+  gdouble* W = gbl(D.work);
+  gcdouble* tail = tri_tail(W, n);
+  const double shift = tail[3 * n], vcut = tail[5 * n + 1];
+  gcdouble* glam = tail + 3 * n + 1;
+  gcdouble* grank = glam + n;
+  gcdouble* Z = gbl(D.V);  // element i of vector c at Z[i n + c]
   gdouble* ZT = W + 6 * nn0;
-  for (int e = tid; e < n * n; e += bs) {
-    const int i = e / n, c = e - i * n;  // Z is transposed: element i of vector c at Z[i n + c]
-    const int rc = int(rk[c]);
-    if (rc < nvec) ZT[i + (int64_t)rc * n] = fabs(lam[c] + shift) <= vcut ? 0.0 : Z[e];
+  if (tid < 32) {
+    const int c = c0 + tid;
+    rks[tid] = c < n ? int(grank[c]) : n;
+    keep[tid] = c < n && fabs(glam[c] + shift) > vcut;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = tid + 256 * j, q = e & 31, r = e >> 5;
+    const int i = i0 + r, c = c0 + q;
+    tile[q][r] = (i < n && c < n) ? Z[(int64_t)i * n + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = tid + 256 * j, r = e & 63, q = e >> 6;
+    const int i = i0 + r, c = c0 + q;
+    if (i < n && c < n && rks[q] < nvec) ZT[i + (int64_t)rks[q] * n] = keep[q] ? tile[q][r] : 0.0;
   }
 }
 
@@ -1232,12 +1282,12 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
 static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : kTriThreads; }
 static int panel_threads(int nmax) { return nmax <= 64 ? 256 : kPanelThreads; }
 
-// LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 4 n doubles and vectors 7 n
-// doubles, each with n + 1 ints.
+// LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 3 n doubles and vectors 7 n
+// doubles, each with n + 1 ints; ranks n doubles.
 static size_t tridiag_panel_lds(int n, int threads) {
   return (size_t(3 + threads / 64) * n + 2 * kTriPanel) * sizeof(double);
 }
-static size_t tridiag_values_lds(int n) { return size_t(4) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
+static size_t tridiag_values_lds(int n) { return size_t(3) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
 static size_t tridiag_vec_lds(int n) { return size_t(7) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
 
 // One-time kernel attribute set-up, shared by contexts that run in parallel host threads.
@@ -1293,11 +1343,20 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipSt
   lds_opt_in((const void*)tridiag_values_kernel, shm_w, &granted_values);
   lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
   if (phases & 2) {
-    hipLaunchKernelGGL(tridiag_values_kernel, dim3(nprob), dim3(threads), shm_w, s, d);
+    // one thread per eigenvalue, kValuesPositions per workgroup, several workgroups per matrix
+    const int parts = (nmax + kValuesPositions - 1) / kValuesPositions;
+    hipLaunchKernelGGL(tridiag_values_kernel, dim3(parts, nprob), dim3(kValuesPositions), shm_w, s, d);
+    PV_LAUNCH_CHECK();
+    hipLaunchKernelGGL(tridiag_rank_kernel, dim3(nprob), dim3(threads), size_t(nmax) * sizeof(double), s, d);
     PV_LAUNCH_CHECK();
   }
   if (phases & 4) {
-    hipLaunchKernelGGL(tridiag_vec_kernel, dim3(nprob), dim3(threads), shm_v, s, d);
+    // the factor and solves of one vector stream through global memory: spread the
+    // vectors of a matrix over several CUs
+    const int parts = (nmax + kVectorPositions - 1) / kVectorPositions;
+    hipLaunchKernelGGL(tridiag_vec_kernel, dim3(parts, nprob), dim3(kVectorPositions), shm_v, s, d);
+    PV_LAUNCH_CHECK();
+    hipLaunchKernelGGL(tridiag_sort_kernel, dim3((nmax + 31) / 32, (nmax + 63) / 64, nprob), dim3(256), 0, s, d);
     PV_LAUNCH_CHECK();
   }
   if (phases & 8) {

@@ -105,7 +105,7 @@ void launch_tri_prepare(const EigDesc* d_desc, int nprob, int nmax, hipStream_t 
 void launch_tri_panel(const EigDesc* d_desc, int nprob, int nmax, int k0, hipStream_t s);
 void launch_tri_finish(const EigDesc* d_desc, int nprob, hipStream_t s);
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
-inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 1; }
+inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 2; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in
 // place (lower triangle; the upper triangle is zeroed).  A column whose pivot (Schur
 // complement diagonal) is at most kCholDrop times its original diagonal entry depends
