@@ -550,8 +550,11 @@ constexpr double kSplitTol = 4.0 * 2.220446049250313e-16;
 // a Gram factor V Lambda^{1/2}) stays below ~1e-9 ||T||.
 constexpr double kClusterTol = 1e-7;
 constexpr double kClusterRel = 1e-2;
-// Clusters up to this size are handled by one thread, longer ones by the workgroup.
-constexpr int kThreadCluster = 16;
+// Clusters up to this size are handled by one thread, longer ones by the workgroup (one
+// thread per member, orthogonalisation by the workgroup): a thread that works through a
+// cluster alone serialises its members' solves and their strided orthogonalisation, which
+// was measured to set the length of whole launches.
+constexpr int kThreadCluster = 1;
 // Inverse-iteration solves per vector outside long clusters: with an eigenvalue from
 // bisection (error ~ eps ||T||) each solve shrinks the components along the other
 // eigenvectors by about eps ||T|| / gap, so two solves suffice at the cluster threshold.
@@ -1021,6 +1024,7 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
   double* psh = vsh + n;
   double* rk = psh + n;
   int* bstart = reinterpret_cast<int*>(rk + n);
+  int* runs = bstart + n + 1;  // workgroup clusters: (first, last, block), at most n/2 of them
   gdouble* W = gbl(D.work);
   gdouble* scratch = W + nn0;  // per-thread inverse-iteration storage
   // eigenvectors of T, stored transposed (element i of vector t at Z[i * n + t]) so that
@@ -1086,8 +1090,7 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
     }
   }
   __syncthreads();
-  // long clusters: (first, last, block) listed in e2 (free after bisection), members
-  // flagged in vsh
+  // workgroup clusters: (first, last, block) listed in runs, members flagged in vsh
   for (int i = tid; i < n; i += bs) vsh[i] = 0.0;
   __syncthreads();
   if (tid == 0) {
@@ -1099,8 +1102,9 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
         int last = t;
         while (last + 1 < e && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
         if (last + 1 - t > kThreadCluster && t >= t0 && t < t1) {
-          e2[3 * nr] = t; e2[3 * nr + 1] = last; e2[3 * nr + 2] = b;
-          for (int q = t; q <= last; ++q) vsh[q] = rk[q] < nvec ? 1.0 : 0.0;
+          runs[3 * nr] = t; runs[3 * nr + 1] = last; runs[3 * nr + 2] = b;
+          // members flagged by their 1-based offset in the cluster (0: not wanted)
+          for (int q = t; q <= last; ++q) vsh[q] = rk[q] < nvec ? double(q - t + 1) : 0.0;
           ++nr;
         }
         t = last + 1;
@@ -1128,8 +1132,9 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
       gdouble* piv = mult + nn;
       gdouble* z = Z + p;
       if (it == 0) {
-        tri_factor(dd + s, ee + s, m, lam[p] + (p - s) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v, w, mult,
-                   piv, ld);
+        // members' shifts spread by their offset in the cluster, as in the single-thread path
+        tri_factor(dd + s, ee + s, m, lam[p] + (vsh[p] - 1.0) * 10.0 * 2.2e-16 * tn, fmax(tn * 1e-15, 1e-300), u, v,
+                   w, mult, piv, ld);
         for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, p) : 0.0;
       }
       tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
@@ -1140,7 +1145,7 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
     }
     __syncthreads();
     for (int q = 0; q < nruns; ++q) {
-      const int r0 = int(e2[3 * q]), r1 = int(e2[3 * q + 1]), b = int(e2[3 * q + 2]);
+      const int r0 = runs[3 * q], r1 = runs[3 * q + 1], b = runs[3 * q + 2];
       const int s = bstart[b], m = bstart[b + 1] - s;
       for (int j = r0; j <= r1; ++j) {
         if (vsh[j] == 0.0) continue;
@@ -1282,13 +1287,15 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
 static int tridiag_threads(int nmax) { return nmax <= 64 ? 256 : kTriThreads; }
 static int panel_threads(int nmax) { return nmax <= 64 ? 256 : kPanelThreads; }
 
-// LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 3 n doubles and vectors 7 n
-// doubles, each with n + 1 ints; ranks n doubles.
+// LDS bytes: panel (3 + nw) n + 2 kTriPanel doubles; values 3 n doubles with n + 1 ints;
+// vectors 7 n doubles with n + 1 + 3 (n/2 + 1) ints; ranks n doubles.
 static size_t tridiag_panel_lds(int n, int threads) {
   return (size_t(3 + threads / 64) * n + 2 * kTriPanel) * sizeof(double);
 }
 static size_t tridiag_values_lds(int n) { return size_t(3) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
-static size_t tridiag_vec_lds(int n) { return size_t(7) * n * sizeof(double) + size_t(n + 1) * sizeof(int); }
+static size_t tridiag_vec_lds(int n) {
+  return size_t(7) * n * sizeof(double) + size_t(n + 1 + 3 * (n / 2 + 1)) * sizeof(int);
+}
 
 // One-time kernel attribute set-up, shared by contexts that run in parallel host threads.
 static std::mutex g_attr_mutex;
