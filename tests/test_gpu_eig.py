@@ -70,6 +70,10 @@ CASES = {
     # and columns scattered through the matrix
     "zero_rows": lambda n, rng: _zero_rows(n, rng),
     "narrow_band": lambda n, rng: 5 * np.eye(n) + 1e-6 * _rand_sym(n, rng),
+    # n/2 pairs 1e-12 apart: the largest possible number of eigenvector clusters (each pair
+    # is solved and orthogonalised cooperatively)
+    "pairs": lambda n, rng: _spectrum(np.repeat(np.linspace(1, 2, (n + 1) // 2), 2)[:n]
+                                      + 1e-12 * np.tile([0.0, 1.0], (n + 1) // 2)[:n], n, rng),
 }
 
 
