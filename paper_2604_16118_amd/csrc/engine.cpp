@@ -251,6 +251,9 @@ struct GemmBatch {
       if (S == 1) {
         GemmDesc g = g0;
         g.tile0 = int(tiles); g.tiles_n = tn; g.kbeg = 0; g.kend = g.K;
+        // the operand along the longer tile dimension is the big one: keep the tiles that
+        // share one of its blocks next to each other
+        g.tiles_m = tm; g.colmajor = tm < tn;
         list.push_back(g);
         tiles += int64_t(tm) * tn;
       } else {
@@ -262,7 +265,7 @@ struct GemmBatch {
           g.C = part.p + size_t(s) * g0.M * g0.N;
           g.ldc = g0.M; g.alpha = 1.0; g.beta = 0.0;
           g.kbeg = s * chunk; g.kend = std::min(g0.K, (s + 1) * chunk);
-          g.tile0 = int(tiles); g.tiles_n = tn;
+          g.tile0 = int(tiles); g.tiles_n = tn; g.tiles_m = tm; g.colmajor = 0;
           list.push_back(g);
           tiles += int64_t(tm) * tn;
         }

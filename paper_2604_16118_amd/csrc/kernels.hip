@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   gcdouble* gB = gbl(g.B);
   gdouble* gC = gbl(g.C);
   const int t = tile - g.tile0;
-  const int row0 = (t / g.tiles_n) * BM, col0 = (t % g.tiles_n) * BN;
+  const int row0 = (g.colmajor ? t % g.tiles_m : t / g.tiles_n) * BM;
+  const int col0 = (g.colmajor ? t / g.tiles_m : t % g.tiles_n) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;

@@ -17,6 +17,10 @@ struct GemmDesc {
   int ta, tb;
   double alpha, beta;
   int tile0, tiles_n, kbeg, kend;
+  // tile order: 0 = row blocks slowest (tiles sharing a row block of A are neighbours),
+  // 1 = row blocks fastest (tiles sharing a column block of B are neighbours); tiles_m =
+  // number of row blocks
+  int tiles_m, colmajor;
 };
 
 // Split-K reduction: C = alpha * sum_s P[s] + beta * C, P[s] is M x N with ld M.
