@@ -109,6 +109,21 @@ typedef struct {
   int converged;
 } pv_result;
 
+/* One step m of the outer iteration (Algorithm 3). */
+typedef struct {
+  double eta;         /* eta^m (eta^0 = 1/(2 theta)) */
+  double tau;         /* eigenvector tolerance of the inner run, eta^m/(2(1+(1+alpha)kappa)) */
+  double lambda;      /* Rayleigh quotient at the end of the inner run */
+  double energy;      /* lambda - gamma */
+  double rho;         /* residual bound rho of the inner run's last iteration */
+  double rel_bound;   /* relative eigenvalue bound of eq. releigerr (NaN outside its domain) */
+  double trunc_eps;   /* psi-space tolerance s_min theta eta^m of the outer truncation (0 on the last step) */
+  int inner_iterations;
+  int cap_bound;      /* 1 if the outer truncation was limited by rank_cap */
+  int max_rank;       /* maximal bond rank after the step */
+  int stopped;        /* 1 on the step whose eigenvalue bound met tol */
+} pv_outer_iter;
+
 const char* pv_last_error(void);
 
 /* Context on HIP device `device`.  Fails with PV_EDEVICE when there is no GPU. */
@@ -165,6 +180,19 @@ pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap
  * NULL) receives a handle of the final iterate. */
 pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
                  pv_iter* hist, int hist_cap, int* psi);
+
+/* Outer iteration (Algorithm 3, Section 5.6, Thm. quasioptr) from the determinant:
+ * kappa = sqrt((1+c)/(1-c)) sqrt(L-1) (eq. kappadef), theta = (1+alpha) kappa /
+ * (2 (1 + (1+alpha) kappa)), eta^0 = 1/(2 theta).  Step m runs Algorithm 2 (pv_run with
+ * prm, tau replaced by eta^m/(2(1+(1+alpha)kappa)), at most prm->max_iter iterations) from
+ * the current iterate; it stops when the relative eigenvalue bound of eq. releigerr of
+ * the last residual bound is below tol; otherwise the normalised iterate is truncated with
+ * tolerance s_min theta eta^m (rank cap prm->rank_cap) and eta is halved.  Writes up to
+ * hist_cap rows; res->iterations = outer steps taken, res->converged = 1 when tol was met;
+ * *psi (may be NULL) receives the final iterate.  PV_EINVAL for alpha <= 0, tol <= 0 or
+ * max_outer < 1; errors of an inner run are returned with the step named. */
+pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double tol, int max_outer,
+                       pv_result* res, pv_outer_iter* hist, int hist_cap, int* psi);
 
 /* Batched independent problems (many Hamiltonians of uneven size at once): runs pv_run from
  * the determinant on each of the `count` distinct contexts ctxs[i] (each with its

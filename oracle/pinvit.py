@@ -22,6 +22,8 @@ One iteration (every step on full vectors, truncations by ``tt.truncate``):
 7. eta_in = Delta ||x_*||_A/sqrt(1+c) with Delta from sqrt(1-Delta^2) - rho Delta =
    sqrt(lam_*/(lam_* + t_eig (lambda - lam_*))) (Lemma on iterate truncation);
    psi <- trunc_{s_min eta_in}(v_1 psi + v_2 p/||p||).
+
+``run_outer`` is Algorithm 3 (outer iteration, Section 5.6 / Thm. quasioptr) on top of it.
 """
 from __future__ import annotations
 
@@ -124,3 +126,45 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
         hist.append(rec)
         s_prev2, s_prev = s_prev, ns
     return psi, hist, pre
+
+
+def outer_constants(L: int, c: float, alpha: float):
+    """kappa of eq. kappadef, theta and eta_0 of Algorithm 3 (D = 1)."""
+    kappa = math.sqrt((1.0 + c) / (1.0 - c)) * math.sqrt(L - 1)
+    ak = (1.0 + alpha) * kappa
+    theta = ak / (2.0 * (1.0 + ak))
+    return kappa, theta, 1.0 / (2.0 * theta)
+
+
+def run_outer(h, v, N, gamma, prm: Params, alpha: float = 1.0, tol: float = 1e-8, max_outer: int = 20):
+    """Algorithm 3: for m = 0, 1, ...: y+ = PINVIT(y^m) run until the eigenvector bound of
+    eq. everrbound is below tau_m = eta^m / (2 (1 + (1+alpha) kappa)); stop when the
+    relative eigenvalue bound of eq. releigerr of its last residual bound rho is below tol;
+    otherwise y^{m+1} = trunc_{theta eta^m}(y+) and eta^{m+1} = eta^m / 2.  Iterates are
+    normalised; the truncation tolerance is converted to psi = S x with s_min, as for the
+    inner iterate truncation (a reading)."""
+    L = h.shape[0]
+    kappa, theta, eta = outer_constants(L, prm.c, alpha)
+    ak = (1.0 + alpha) * kappa
+    psi = None
+    outer = []
+    for m in range(max_outer):
+        tau_m = eta / (2.0 * (1.0 + ak))
+        inner = dataclasses.replace(prm, tau=tau_m)
+        y, hist, pre = run(h, v, N, gamma, inner, psi0=psi)
+        last = hist[-1]
+        rel = bounds.rel_eig_bound(last["rho"], prm.delta)
+        rec = dict(m=m, eta=eta, tau=tau_m, inner=len(hist), lam=last["lam"], E=last["E"],
+                   rho=last["rho"], rel_bound=rel, converged_inner=bool(last.get("stop")))
+        y = y / np.linalg.norm(y)
+        if rel < tol:
+            rec["stop"] = True
+            outer.append(rec)
+            return y, outer
+        eps = pre.s_min * theta * eta
+        psi, rho_tab, cb, margin, _ = precond._trunc(y, L, N, eps, prm.cap, prm.truncation)
+        rec.update(trunc_eps=eps, rho_tab=rho_tab, cap_bound=bool(cb), margin=margin,
+                   trunc_err=float(np.linalg.norm(psi - y)))
+        outer.append(rec)
+        eta *= 0.5
+    return psi, outer

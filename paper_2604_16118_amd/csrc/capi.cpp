@@ -110,6 +110,15 @@ double error_bound(double rho, double delta) {
   return 2.0 * std::sin(0.5 * std::asin(arg));
 }
 
+// Relative eigenvalue bound of eq. releigerr, b_delta(rho) rho^2 / (1 - b_delta(rho) rho^2)
+// (NaN outside the domain of b_delta).
+double rel_eig_bound(double rho, double delta) {
+  const double disc = 1.0 - 4.0 * (delta - 1.0) * delta * rho * rho;
+  if (disc < 0.0) return std::numeric_limits<double>::quiet_NaN();
+  const double b = 2.0 * delta / (1.0 + 2.0 * delta * rho * rho + std::sqrt(disc));
+  return b * rho * rho / (1.0 - b * rho * rho);
+}
+
 // Lower eigenpair of the 2x2 pencil (Rem. omegamin), v^T mm v = 1, v[0] > 0.
 void ritz2(const double hm[3], const double mm[3], double* lam, double v[2]) {
   // hm = {h00, h01, h11}, mm = {m00, m01, m11}
@@ -528,6 +537,80 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
     }
     res->iterations = rows;
     if (psi_out) *psi_out = put(c, std::move(psi));
+  });
+}
+
+// Algorithm 3 (outer iteration): PINVIT to the eigenvector tolerance
+// tau_m = eta^m / (2 (1 + (1+alpha) kappa)), kappa of eq. kappadef, stop when the relative
+// eigenvalue bound of eq. releigerr is below tol, else truncate the normalised iterate
+// with theta eta^m (converted to psi = S x with s_min) and halve eta (Thm. quasioptr).
+pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double tol, int max_outer,
+                       pv_result* res, pv_outer_iter* hist, int hist_cap, int* psi_out) {
+  return guard([&] {
+    if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
+    if (!(alpha > 0) || !(tol > 0) || max_outer < 1) fail(PV_EINVAL, "need alpha > 0, tol > 0, max_outer >= 1");
+    if (!(prm->c > 0 && prm->c < 1)) fail(PV_EINVAL, "invalid parameters");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    const pv_params p = *prm;
+    const double kappa = std::sqrt((1.0 + p.c) / (1.0 - p.c)) * std::sqrt(double(std::max(c.L - 1, 1)));
+    const double ak = (1.0 + alpha) * kappa;
+    const double theta = ak / (2.0 * (1.0 + ak));
+    double eta = 1.0 / (2.0 * theta);
+    *res = pv_result{};
+    int start = -1, rows = 0;
+    std::vector<pv_iter> ih(size_t(std::max(p.max_iter, 1)));
+    for (int m = 0; m < max_outer; ++m) {
+      pv_params inner = p;
+      inner.tau = eta / (2.0 * (1.0 + ak));
+      inner.resume_eta = inner.resume_s = inner.resume_s2 = 0.0;  // every inner run starts afresh
+      pv_result r{};
+      int y = -1;
+      const pv_status st = pv_run(ctx, &inner, start, &r, ih.data(), int(ih.size()), &y);
+      if (st != PV_OK) fail(st, std::string("inner iteration of outer step ") + std::to_string(m) + ": " + pv_last_error());
+      if (start >= 0) c.mps.erase(start);
+      if (r.iterations < 1) fail(PV_EINVAL, "inner iteration limit must be at least 1");
+      const pv_iter& last = ih[size_t(std::min(r.iterations, int(ih.size())) - 1)];
+      pv_outer_iter rec{};
+      rec.eta = eta;
+      rec.tau = inner.tau;
+      rec.lambda = last.lambda;
+      rec.energy = last.energy;
+      rec.rho = last.rho;
+      rec.rel_bound = rel_eig_bound(last.rho, p.delta);
+      rec.inner_iterations = r.iterations;
+      const double ny = norm2(c, get(c, y));
+      if (!(ny > 0)) fail(PV_ENOCONV, "iterate vanished");
+      auto yn = mps_scaled_copy(c, get(c, y), 1.0 / ny, nullptr);
+      c.mps.erase(y);
+      res->energy = last.energy;
+      res->lambda = last.lambda;
+      res->rho = last.rho;
+      res->bound = last.bound;
+      if (rec.rel_bound < tol) {
+        rec.stopped = 1;
+        rec.max_rank = yn->max_rank();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        start = put(c, std::move(yn));
+        break;
+      }
+      const double eps = c.s_min * theta * eta;
+      bool cb = false;
+      auto t = round_mps(c, *yn, eps, p.rank_cap, &cb);
+      c.sync();
+      rec.trunc_eps = eps;
+      rec.cap_bound = cb ? 1 : 0;
+      rec.max_rank = t->max_rank();
+      if (hist && rows < hist_cap) hist[rows] = rec;
+      ++rows;
+      start = put(c, std::move(t));
+      eta *= 0.5;
+    }
+    res->iterations = rows;
+    if (psi_out) *psi_out = start;
+    else if (start >= 0) c.mps.erase(start);
   });
 }
 

@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_batch",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_batch",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -47,6 +47,13 @@ class Iter(C.Structure):
                 ("bound", C.c_double), ("r_norm", C.c_double), ("s_norm", C.c_double),
                 ("eta_res", C.c_double), ("lambda_star", C.c_double), ("eta_psi", C.c_double),
                 ("seconds", C.c_double), ("retries", C.c_int), ("cap_bound", C.c_int),
+                ("max_rank", C.c_int), ("stopped", C.c_int)]
+
+
+class OuterIter(C.Structure):
+    _fields_ = [("eta", C.c_double), ("tau", C.c_double), ("lambda_", C.c_double),
+                ("energy", C.c_double), ("rho", C.c_double), ("rel_bound", C.c_double),
+                ("trunc_eps", C.c_double), ("inner_iterations", C.c_int), ("cap_bound", C.c_int),
                 ("max_rank", C.c_int), ("stopped", C.c_int)]
 
 
@@ -88,6 +95,8 @@ def lib():
         L.pv_apply_s.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
         L.pv_run.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.POINTER(Result),
                              C.POINTER(Iter), C.c_int, ip]
+        L.pv_run_outer.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, C.c_double, C.c_int,
+                                   C.POINTER(Result), C.POINTER(OuterIter), C.c_int, ip]
         L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
@@ -284,6 +293,22 @@ class Context:
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
                     iterations=res.iterations, converged=bool(res.converged),
                     eta_res=res.eta_res, s_last=res.s_last, s_prev=res.s_prev), rows, psi.value
+
+    def run_outer(self, alpha=1.0, tol=1e-8, max_outer=20, **kw):
+        """Algorithm 3 (pv_run_outer); keyword arguments as in run (max_iter: per outer step).
+        Returns (result dict, outer-step rows, handle of the final iterate)."""
+        kw.setdefault("max_iter", 50)
+        prm = make_params(**kw)
+        res = Result()
+        hist = (OuterIter * max_outer)()
+        psi = C.c_int()
+        _check(lib().pv_run_outer(self._p, C.byref(prm), float(alpha), float(tol), int(max_outer),
+                                  C.byref(res), hist, int(max_outer), C.byref(psi)))
+        rows = [dict(eta=h.eta, tau=h.tau, lam=h.lambda_, E=h.energy, rho=h.rho, rel_bound=h.rel_bound,
+                     trunc_eps=h.trunc_eps, inner=h.inner_iterations, cap_bound=bool(h.cap_bound),
+                     max_rank=h.max_rank, stop=bool(h.stopped)) for h in hist[:res.iterations]]
+        return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, steps=res.iterations,
+                    converged=bool(res.converged)), rows, psi.value
 
     def sym_eig(self, A, method, nvec=None):
         A = _f64(np.asfortranarray(A))

@@ -105,3 +105,36 @@ def test_precision_bf16_is_rejected(ctx):
     with pytest.raises(native.PvError) as e:
         ctx.run(rank_cap=4, max_iter=1, tau=1e-12, c=0.5, delta=10.0, precision=2)
     assert e.value.status == -1
+
+
+def test_outer_iteration_matches_oracle(ctx):
+    """Algorithm 3 on the GPU against the oracle's: the same outer steps (inner iteration
+    counts, energies within 1e-10 relative, eta and tau), and the final eigenvalue within
+    the requested relative tolerance of exact diagonalisation."""
+    from oracle import fock
+    p = make_problem("dense", 8, 4, 0)
+    w = fock.lowest_eigs(p.h, p.v, 4, p.gamma, k=2)
+    delta = w[1] / (w[1] - w[0])
+    prm = pinvit.Params(cap=16, max_iter=40, c=0.5, delta=delta)
+    _, outer_o = pinvit.run_outer(p.h, p.v, 4, p.gamma, prm, alpha=1.0, tol=1e-9, max_outer=12)
+    ctx.set_hamiltonian(p.h, p.v, 4, p.gamma)
+    res, outer_g, psi = ctx.run_outer(alpha=1.0, tol=1e-9, max_outer=12, rank_cap=16, max_iter=40,
+                                      c=0.5, delta=delta)
+    ctx.mps_free(psi)
+    assert res["converged"] and outer_g[-1]["stop"]
+    assert len(outer_g) == len(outer_o)
+    for g, o in zip(outer_g, outer_o):
+        assert g["inner"] == o["inner"]
+        assert g["eta"] == pytest.approx(o["eta"], rel=1e-14)
+        assert g["tau"] == pytest.approx(o["tau"], rel=1e-14)
+        assert abs(g["E"] - o["E"]) <= 1e-10 * abs(o["E"])
+    assert abs(res["lam"] - w[0]) < 1e-9 * w[0]
+
+
+def test_outer_iteration_rejects_bad_arguments(ctx):
+    p = make_problem("dense", 6, 3, 0)
+    ctx.set_hamiltonian(p.h, p.v, 3, p.gamma)
+    with pytest.raises(native.PvError):
+        ctx.run_outer(alpha=0.0, rank_cap=8)
+    with pytest.raises(native.PvError):
+        ctx.run_outer(tol=-1.0, rank_cap=8)

@@ -51,3 +51,35 @@ def test_noninteracting_limit():
     psi, hist, _ = pinvit.run(p.h, v, 3, p.gamma, prm)
     assert abs(hist[-1]["E"] - e0) <= 1e-9 * abs(e0)
 
+
+
+def test_outer_iteration_against_exact_diagonalisation():
+    """Algorithm 3: the returned eigenvalue meets |lambda - lambda_1| < lambda_1 tol (its
+    stated output guarantee), the relative bound of eq. releigerr bounds the true error at
+    every outer step, every outer truncation stays within its tolerance, eta halves, and
+    the inner tolerance is eta^m / (2 (1 + (1+alpha) kappa))."""
+    from oracle import bounds
+    p = make_problem("dense", 8, 4, 0)
+    l1, delta = _exact(p, 4)
+    prm = pinvit.Params(cap=16, max_iter=40, c=0.5, delta=delta)
+    alpha, tol = 1.0, 1e-9
+    psi, outer = pinvit.run_outer(p.h, p.v, 4, p.gamma, prm, alpha=alpha, tol=tol, max_outer=12)
+    assert outer[-1].get("stop")
+    lam = outer[-1]["lam"]
+    assert abs(lam - l1) < l1 * tol
+    kappa = math.sqrt(3.0) * math.sqrt(7.0)            # eq. kappadef with c = 1/2, K = 8
+    theta = 2 * kappa / (2 * (1 + 2 * kappa))
+    assert outer[0]["eta"] == pytest.approx(1 / (2 * theta), rel=1e-15)
+    for a, b in zip(outer, outer[1:]):
+        assert b["eta"] == pytest.approx(0.5 * a["eta"], rel=1e-15)
+    for r in outer:
+        assert r["tau"] == pytest.approx(r["eta"] / (2 * (1 + 2 * kappa)), rel=1e-15)
+        if not math.isnan(r["rel_bound"]):
+            assert (r["lam"] - l1) / l1 <= r["rel_bound"] * (1 + 1e-9)
+        if "trunc_eps" in r:
+            assert r["trunc_err"] <= r["trunc_eps"] * (1 + 1e-9)
+    # the normalised result is close to the ground state
+    w, V = np.linalg.eigh(fock.sector_hamiltonian(p.h, p.v, 4, p.gamma))
+    u = np.zeros_like(psi)
+    u[fock.sector_basis(8, 4)] = V[:, 0]
+    assert abs(abs(float(psi @ u)) - 1.0) <= 1e-6
