@@ -125,6 +125,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = T4{0, 0, 0, 0};
+  // 16 x 16 sub-tiles that lie wholly outside C (edge tiles of a problem) are skipped:
+  // the conditions are the same for the whole wavefront
+  bool rv[TM], cv[TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) rv[a] = row0 + wr * (BM / 2) + a * 16 < g.M;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) cv[b] = col0 + wc * (BN / 2) + b * 16 < g.N;
   int buf = 0;
   if (g.kbeg < g.kend) {
     load(g.kbeg);
@@ -145,6 +152,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
+          if (!(rv[a] && cv[b])) continue;
           if constexpr (F64)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
           else
