@@ -559,6 +559,12 @@ pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double t
     double eta = 1.0 / (2.0 * theta);
     *res = pv_result{};
     int start = -1, rows = 0;
+    // the intermediate iterate is released if a step fails
+    struct Release {
+      Ctx& c;
+      int* h;
+      ~Release() { if (*h >= 0) c.mps.erase(*h); }
+    } release{c, &start};
     std::vector<pv_iter> ih(size_t(std::max(p.max_iter, 1)));
     for (int m = 0; m < max_outer; ++m) {
       pv_params inner = p;
@@ -569,6 +575,7 @@ pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double t
       const pv_status st = pv_run(ctx, &inner, start, &r, ih.data(), int(ih.size()), &y);
       if (st != PV_OK) fail(st, std::string("inner iteration of outer step ") + std::to_string(m) + ": " + pv_last_error());
       if (start >= 0) c.mps.erase(start);
+      start = y;  // released by `release` should a later step fail
       if (r.iterations < 1) fail(PV_EINVAL, "inner iteration limit must be at least 1");
       const pv_iter& last = ih[size_t(std::min(r.iterations, int(ih.size())) - 1)];
       pv_outer_iter rec{};
@@ -579,10 +586,11 @@ pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double t
       rec.rho = last.rho;
       rec.rel_bound = rel_eig_bound(last.rho, p.delta);
       rec.inner_iterations = r.iterations;
-      const double ny = norm2(c, get(c, y));
+      const double ny = norm2(c, get(c, start));
       if (!(ny > 0)) fail(PV_ENOCONV, "iterate vanished");
-      auto yn = mps_scaled_copy(c, get(c, y), 1.0 / ny, nullptr);
-      c.mps.erase(y);
+      auto yn = mps_scaled_copy(c, get(c, start), 1.0 / ny, nullptr);
+      c.mps.erase(start);
+      start = -1;
       res->energy = last.energy;
       res->lambda = last.lambda;
       res->rho = last.rho;
@@ -609,8 +617,10 @@ pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double t
       eta *= 0.5;
     }
     res->iterations = rows;
-    if (psi_out) *psi_out = start;
-    else if (start >= 0) c.mps.erase(start);
+    if (psi_out) {
+      *psi_out = start;
+      start = -1;  // handed to the caller
+    }
   });
 }
 
