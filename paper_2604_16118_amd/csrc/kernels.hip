@@ -1521,12 +1521,37 @@ __global__ __launch_bounds__(256) void wstep_kernel(const WTask* __restrict__ ta
     cr[r] = ok[r] ? x / rows : 0;
     acc[r] = 0.0;
   }
-  for (int e = t.e0; e < t.e1; ++e) {
+  // entries four at a time with all their loads issued together; lanes past the end of the
+  // block read element (0, 0) of the source and are not stored, so no load is guarded.  The
+  // terms are added in entry order either way.
+  int e = t.e0;
+  for (; e + 4 <= t.e1; e += 4) {
+    const WEntry E0 = entries[e], E1 = entries[e + 1], E2 = entries[e + 2], E3 = entries[e + 3];
+    gcdouble* s0 = gbl(E0.src);
+    gcdouble* s1 = gbl(E1.src);
+    gcdouble* s2 = gbl(E2.src);
+    gcdouble* s3 = gbl(E3.src);
+    double x0[kWElems], x1[kWElems], x2[kWElems], x3[kWElems];
+#pragma unroll
+    for (int r = 0; r < kWElems; ++r) {
+      x0[r] = s0[ar[r] + E0.ld * cr[r]];
+      x1[r] = s1[ar[r] + E1.ld * cr[r]];
+      x2[r] = s2[ar[r] + E2.ld * cr[r]];
+      x3[r] = s3[ar[r] + E3.ld * cr[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < kWElems; ++r) {
+      acc[r] += E0.val * x0[r];
+      acc[r] += E1.val * x1[r];
+      acc[r] += E2.val * x2[r];
+      acc[r] += E3.val * x3[r];
+    }
+  }
+  for (; e < t.e1; ++e) {
     const WEntry E = entries[e];
     gcdouble* src = gbl(E.src);
 #pragma unroll
-    for (int r = 0; r < kWElems; ++r)
-      if (ok[r]) acc[r] += E.val * src[ar[r] + E.ld * cr[r]];
+    for (int r = 0; r < kWElems; ++r) acc[r] += E.val * src[ar[r] + E.ld * cr[r]];
   }
   gdouble* out = gbl(t.out);
 #pragma unroll
