@@ -426,7 +426,16 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(const EigDesc* __restr
 // in the columns of V.
 // ---------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
-constexpr int kValuesPositions = 256;  // eigenvalues (threads) per workgroup of the bisection
+constexpr int kValuesThreads = 256;  // threads per workgroup of the bisection
+// Multisection: kSectLanes lanes of a wavefront share one eigenvalue and each evaluates the
+// Sturm count at kSectPoints points per round (interleaved, so their latencies overlap); a
+// round cuts the bracket into kSectLanes * kSectPoints + 1 equal parts, four bits instead
+// of the one bit of bisection, and so shortens each eigenvalue's chain of dependent sweeps.
+constexpr int kSectLanes = 8;
+constexpr int kSectPoints = 2;
+constexpr int kSectQ = kSectLanes * kSectPoints;
+constexpr int kValuesPositions = kValuesThreads / kSectLanes;  // eigenvalues per workgroup
+static_assert(64 % kSectLanes == 0, "a multisection group lies within one wavefront");
 constexpr int kVectorPositions = 64;   // eigenvectors (threads) per workgroup of inverse iteration
 constexpr int kBackRows = kEigMax / 64;  // rows per lane when a wavefront holds a column
 
@@ -440,24 +449,33 @@ __device__ inline double block_sum(double v, double* red, int tid, int bs) {
   return t;
 }
 
-// Number of eigenvalues of T below x (negative pivots of the LDL^T factorisation of T - x).
+// Number of eigenvalues of T below x (negative pivots of the LDL^T factorisation of T - x)
+// at P points at once, the P recurrences interleaved so that their latencies overlap.
 // Pivots smaller than tiny in magnitude are replaced by -tiny; 1/q comes from the hardware
 // reciprocal refined by two Newton steps r <- r (2 - q r), which leaves a relative error of
 // a few ulps (a small relative perturbation of e_i^2, as the division itself makes).
-__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double tiny) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < tiny) q = -tiny;
-  cnt += q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    double r = __builtin_amdgcn_rcp(q);
-    r = r * fma(-q, r, 2.0);
-    r = r * fma(-q, r, 2.0);
-    q = (d[i] - x) - e2[i - 1] * r;
-    if (fabs(q) < tiny) q = -tiny;
-    cnt += q < 0.0;
+template <int P>
+__device__ inline void sturm_counts(const double* d, const double* e2, int n, const double (&x)[P], double tiny,
+                                    int (&cnt)[P]) {
+  double q[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    q[p] = d[0] - x[p];
+    if (fabs(q[p]) < tiny) q[p] = -tiny;
+    cnt[p] = q[p] < 0.0;
   }
-  return cnt;
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double r = __builtin_amdgcn_rcp(q[p]);
+      r = r * fma(-q[p], r, 2.0);
+      r = r * fma(-q[p], r, 2.0);
+      q[p] = (di - x[p]) - ei * r;
+      if (fabs(q[p]) < tiny) q[p] = -tiny;
+      cnt[p] += q[p] < 0.0;
+    }
+  }
 }
 
 // Solve (T - sigma I) x = b in place for one thread: LU with partial pivoting of the
@@ -928,10 +946,14 @@ __device__ int tri_blocks(const EigDesc& D, int n, double* dd, double* ee, doubl
   return *sh_nblk;
 }
 
-// 2. Eigenvalues of T by bisection: gridDim.x workgroups per matrix (blockIdx.y), each taking
-//    one contiguous range of positions; position t of block b = [s, s+m) holds the
-//    (t-s)-th smallest eigenvalue of that block.  The unshifted values go to the work area.
-__global__ __launch_bounds__(kValuesPositions) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
+// 2. Eigenvalues of T by multisection: gridDim.x workgroups per matrix (blockIdx.y), each
+//    taking one contiguous range of positions, one group of kSectLanes lanes per position;
+//    position t of block b = [s, s+m) holds the (t-s)-th smallest eigenvalue of that block.
+//    The bracket [a, b) keeps count(a) <= t-s < count(b); each round moves b to the first
+//    of the kSectQ points whose count exceeds t-s and a to the point before it.  Every lane
+//    of a group computes the same points from the same bracket, so the group stays in step.
+//    The unshifted values go to the work area.
+__global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
   __shared__ int sh_nblk;
   // d, e, e2: n doubles each; block starts: n + 1 ints
   extern __shared__ double tsm[];
@@ -940,7 +962,6 @@ __global__ __launch_bounds__(kValuesPositions) void tridiag_values_kernel(const 
   const int chunk = (n + gridDim.x - 1) / gridDim.x;
   const int t0 = blockIdx.x * chunk, t1 = min(n, t0 + chunk);
   if (n <= 0 || t0 >= t1) return;
-  const int tid = threadIdx.x, bs = blockDim.x;
   double* dd = tsm;
   double* ee = dd + n;
   double* e2 = ee + n;
@@ -949,14 +970,20 @@ __global__ __launch_bounds__(kValuesPositions) void tridiag_values_kernel(const 
   double tn = 0.0;
   const int nblk = tri_blocks(D, n, dd, ee, e2, bstart, &sh_nblk, &tn);
   const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
-  for (int t = t0 + tid; t < t1; t += bs) {
+  const int sub = threadIdx.x % kSectLanes, grp = threadIdx.x / kSectLanes;
+  const int gbase = (threadIdx.x & 63) - sub;  // first lane of the group in its wavefront
+  constexpr uint64_t kGroupMask = kSectLanes == 64 ? ~0ull : (1ull << kSectLanes) - 1;
+  for (int t = t0 + grp; t < t1; t += kValuesPositions) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
       const int mid = (lo_b + hi_b + 1) >> 1;
       if (bstart[mid] <= t) lo_b = mid; else hi_b = mid - 1;
     }
     const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
-    if (m == 1) { glam[t] = dd[s]; continue; }
+    if (m == 1) {
+      if (sub == 0) glam[t] = dd[s];
+      continue;
+    }
     double lo = 1e300, hi = -1e300;
     for (int i = s; i < s + m; ++i) {
       const double r = (i > s ? fabs(ee[i - 1]) : 0.0) + (i < s + m - 1 ? fabs(ee[i]) : 0.0);
@@ -964,13 +991,34 @@ __global__ __launch_bounds__(kValuesPositions) void tridiag_values_kernel(const 
       hi = fmax(hi, dd[i] + r);
     }
     double a = lo - 1e-14 * tn - 1e-300, b = hi + 1e-14 * tn + 1e-300;
+    const int target = t - s;
     for (int it = 0; it < 100; ++it) {
       const double mid = 0.5 * (a + b);
       if (mid <= a || mid >= b) break;
       if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0 || b - a <= 1e-18 * tn) break;
-      if (sturm_count(dd + s, e2 + s, m, mid, tiny + 1e-300) > t - s) b = mid; else a = mid;
+      const double h = (b - a) * (1.0 / (kSectQ + 1));
+      auto point = [&](int j) { return fmin(fmax(a + (j + 1) * h, a), b); };
+      double x[kSectPoints];
+      int cnt[kSectPoints];
+#pragma unroll
+      for (int p = 0; p < kSectPoints; ++p) x[p] = point(sub * kSectPoints + p);
+      sturm_counts<kSectPoints>(dd + s, e2 + s, m, x, tiny + 1e-300, cnt);
+      int first = kSectPoints;  // this lane's first point above the target count
+#pragma unroll
+      for (int p = kSectPoints - 1; p >= 0; --p)
+        if (cnt[p] > target) first = p;
+      const uint64_t above = (__ballot(first < kSectPoints) >> gbase) & kGroupMask;
+      if (above == 0) {
+        a = point(kSectQ - 1);
+      } else {
+        const int l = __builtin_ctzll(above);
+        const int j = l * kSectPoints + __shfl(first, gbase + l, 64);
+        const double na = j > 0 ? point(j - 1) : a;
+        b = point(j);
+        a = na;
+      }
     }
-    glam[t] = 0.5 * (a + b);
+    if (sub == 0) glam[t] = 0.5 * (a + b);
   }
 }
 
@@ -1359,9 +1407,9 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipSt
   lds_opt_in((const void*)tridiag_values_kernel, shm_w, &granted_values);
   lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
   if (phases & 2) {
-    // one thread per eigenvalue, kValuesPositions per workgroup, several workgroups per matrix
+    // one lane group per eigenvalue, kValuesPositions per workgroup, several workgroups per matrix
     const int parts = (nmax + kValuesPositions - 1) / kValuesPositions;
-    hipLaunchKernelGGL(tridiag_values_kernel, dim3(parts, nprob), dim3(kValuesPositions), shm_w, s, d);
+    hipLaunchKernelGGL(tridiag_values_kernel, dim3(parts, nprob), dim3(kValuesThreads), shm_w, s, d);
     PV_LAUNCH_CHECK();
     hipLaunchKernelGGL(tridiag_rank_kernel, dim3(nprob), dim3(threads), size_t(nmax) * sizeof(double), s, d);
     PV_LAUNCH_CHECK();
