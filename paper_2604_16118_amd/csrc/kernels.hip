@@ -516,30 +516,76 @@ __device__ void tri_factor(const double* d, const double* e, int n, double sigma
   w[(n - 1) * ld] = 0.0;
 }
 
-__device__ void tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble* mult, gcdouble* piv, gdouble* x,
-                          int64_t ld) {
+// Solve with the factors of tri_factor for the right-hand side scale * x, in place; returns
+// the squared norm of the solution.  The loads of kSolveBatch rows are issued before the
+// first of them is used, so a pass waits once per batch rather than once per row.
+constexpr int kSolveBatch = 8;
+__device__ double tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble* mult, gcdouble* piv, gdouble* x,
+                            int64_t ld, double scale) {
   // forward: apply the row operations to the right-hand side
-  double cur = x[0];
-#pragma unroll 8
-  for (int i = 0; i < n - 1; ++i) {
-    const double nxt = x[(i + 1) * ld];
-    const double m = mult[i * ld];
-    if (piv[i * ld] == 0.0) { x[i * ld] = cur; cur = nxt - m * cur; }
+  double cur = scale * x[0];
+  auto forward = [&](int i, double nx, double m, double pv) {
+    const double nxt = scale * nx;
+    if (pv == 0.0) { x[i * ld] = cur; cur = nxt - m * cur; }
     else { x[i * ld] = nxt; cur = cur - m * nxt; }
+  };
+  int i = 0;
+  for (; i + kSolveBatch <= n - 1; i += kSolveBatch) {
+    double nx[kSolveBatch], mm[kSolveBatch], pp[kSolveBatch];
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) {
+      nx[b] = x[(i + 1 + b) * ld];
+      mm[b] = mult[(i + b) * ld];
+      pp[b] = piv[(i + b) * ld];
+    }
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) forward(i + b, nx[b], mm[b], pp[b]);
   }
+  for (; i < n - 1; ++i) forward(i, x[(i + 1) * ld], mult[i * ld], piv[i * ld]);
   // back substitution
   double x1 = cur * u[(n - 1) * ld];
   x[(n - 1) * ld] = x1;
-  if (n < 2) return;
+  double q = x1 * x1;
+  if (n < 2) return q;
   double x0 = (x[(n - 2) * ld] - v[(n - 2) * ld] * x1) * u[(n - 2) * ld];
   x[(n - 2) * ld] = x0;
-#pragma unroll 8
-  for (int i = n - 3; i >= 0; --i) {
-    const double xi = (x[i * ld] - v[i * ld] * x0 - w[i * ld] * x1) * u[i * ld];
-    x[i * ld] = xi;
+  q += x0 * x0;
+  auto backward = [&](int r, double xr, double vr, double wr, double ur) {
+    const double xi = (xr - vr * x0 - wr * x1) * ur;
+    x[r * ld] = xi;
+    q += xi * xi;
     x1 = x0;
     x0 = xi;
+  };
+  i = n - 3;
+  for (; i + 1 >= kSolveBatch; i -= kSolveBatch) {
+    double xx[kSolveBatch], vv[kSolveBatch], ww[kSolveBatch], uu[kSolveBatch];
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) {
+      const int64_t o = (i - b) * ld;
+      xx[b] = x[o];
+      vv[b] = v[o];
+      ww[b] = w[o];
+      uu[b] = u[o];
+    }
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) backward(i - b, xx[b], vv[b], ww[b], uu[b]);
   }
+  for (; i >= 0; --i) backward(i, x[i * ld], v[i * ld], w[i * ld], u[i * ld]);
+  return q;
+}
+
+// x <- scale * x for n elements at stride ld, kSolveBatch loads at a time.
+__device__ void strided_scale(int n, gdouble* x, int64_t ld, double scale) {
+  int i = 0;
+  for (; i + kSolveBatch <= n; i += kSolveBatch) {
+    double xx[kSolveBatch];
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) xx[b] = x[(i + b) * ld];
+#pragma unroll
+    for (int b = 0; b < kSolveBatch; ++b) x[(i + b) * ld] = scale * xx[b];
+  }
+  for (; i < n; ++i) x[i * ld] *= scale;
 }
 
 constexpr int kRedThreads = 512;  // reduction kernels: 8 wavefronts with room for 256 VGPRs
@@ -577,13 +623,12 @@ constexpr double kSplitTol = 4.0 * 2.220446049250313e-16;
 // a Gram factor V Lambda^{1/2}) stays below ~1e-9 ||T||.
 constexpr double kClusterTol = 1e-7;
 constexpr double kClusterRel = 1e-2;
-// Clusters up to this size are handled by one thread, longer ones by the workgroup (one
-// thread per member, orthogonalisation by the workgroup): a thread that works through a
-// cluster alone serialises its members' solves and their strided orthogonalisation, which
-// was measured to set the length of whole launches.
-constexpr int kThreadCluster = 1;
-// Inverse-iteration solves per vector outside long clusters: with an eigenvalue from
-// bisection (error ~ eps ||T||) each solve shrinks the components along the other
+// Eigenvalues without a close neighbour get their vector from one thread; clusters of two or
+// more go to the workgroup (one thread per member, orthogonalisation by the workgroup): a
+// thread that works through a cluster alone serialises its members' solves and their strided
+// orthogonalisation, which was measured to set the length of whole launches.
+// Inverse-iteration solves per vector outside clusters: with an eigenvalue from
+// multisection (error ~ eps ||T||) each solve shrinks the components along the other
 // eigenvectors by about eps ||T|| / gap, so two solves suffice at the cluster threshold.
 constexpr int kInvIters = 2;
 
@@ -1112,39 +1157,27 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
     }
     const int s = bstart[lo_b], m = bstart[lo_b + 1] - s;
     if (t > s && linked(lam[t - 1], lam[t], cut, ctol)) continue;  // not the first of its cluster
-    int last = t;
-    while (last + 1 < s + m && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
-    if (last + 1 - t > kThreadCluster) continue;  // long cluster: workgroup pass below
+    if (t + 1 < s + m && linked(lam[t], lam[t + 1], cut, ctol)) continue;  // cluster: workgroup pass below
+    if (rk[t] >= nvec) continue;
+    gdouble* z = Z + t;  // element i at z[i * ld]
+    if (fabs(lam[t]) <= cut || m == 1) {
+      for (int i = 0; i < n; ++i) z[i * ld] = (m == 1 && fabs(lam[t]) > cut && i == s) ? 1.0 : 0.0;
+      continue;
+    }
     gdouble* u = scratch + t;  // slot t, interleaved with the other threads' slots
     gdouble* v = u + nn;
     gdouble* w = v + nn;
     gdouble* mult = w + nn;
     gdouble* piv = mult + nn;
-    for (int j = t; j <= last; ++j) {
-      if (rk[j] >= nvec) continue;
-      gdouble* z = Z + j;  // element i at z[i * ld]
-      if (fabs(lam[j]) <= cut || m == 1) {
-        for (int i = 0; i < n; ++i) z[i * ld] = (m == 1 && fabs(lam[j]) > cut && i == s) ? 1.0 : 0.0;
-        continue;
-      }
-      const double sigma = lam[j] + (j - t) * 10.0 * 2.2e-16 * tn;
-      tri_factor(dd + s, ee + s, m, sigma, fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv, ld);
-      for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, j) : 0.0;
-      for (int it = 0; it < kInvIters; ++it) {
-        tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
-        for (int jj = t; jj < j; ++jj) {
-          if (rk[jj] >= nvec) continue;
-          gcdouble* y = Z + jj;
-          double dot = 0.0;
-          for (int i = s; i < s + m; ++i) dot += y[i * ld] * z[i * ld];
-          for (int i = s; i < s + m; ++i) z[i * ld] -= dot * y[i * ld];
-        }
-        double q = 0.0;
-        for (int i = s; i < s + m; ++i) q += z[i * ld] * z[i * ld];
-        q = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
-        for (int i = s; i < s + m; ++i) z[i * ld] *= q;
-      }
+    tri_factor(dd + s, ee + s, m, lam[t], fmax(tn * 1e-15, 1e-300), u, v, w, mult, piv, ld);
+    for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, t) : 0.0;
+    // each solve takes the previous solution scaled to unit norm as its right-hand side
+    double sc = 1.0;
+    for (int it = 0; it < kInvIters; ++it) {
+      const double q = tri_solve(m, u, v, w, mult, piv, z + s * ld, ld, sc);
+      sc = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
     }
+    strided_scale(m, z + s * ld, ld, sc);
   }
   __syncthreads();
   // workgroup clusters: (first, last, block) listed in runs, members flagged in vsh
@@ -1158,7 +1191,7 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
       while (t < e) {
         int last = t;
         while (last + 1 < e && linked(lam[last], lam[last + 1], cut, ctol)) ++last;
-        if (last + 1 - t > kThreadCluster && t >= t0 && t < t1) {
+        if (last > t && t >= t0 && t < t1) {
           runs[3 * nr] = t; runs[3 * nr + 1] = last; runs[3 * nr + 2] = b;
           // members flagged by their 1-based offset in the cluster (0: not wanted)
           for (int q = t; q <= last; ++q) vsh[q] = rk[q] < nvec ? double(q - t + 1) : 0.0;
@@ -1194,11 +1227,8 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
                    w, mult, piv, ld);
         for (int i = 0; i < n; ++i) z[i * ld] = (i >= s && i < s + m) ? start_value(i, p) : 0.0;
       }
-      tri_solve(m, u, v, w, mult, piv, z + s * ld, ld);
-      double q = 0.0;
-      for (int i = s; i < s + m; ++i) q += z[i * ld] * z[i * ld];
-      q = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
-      for (int i = s; i < s + m; ++i) z[i * ld] *= q;
+      // the workgroup normalises each member after its orthogonalisation below
+      tri_solve(m, u, v, w, mult, piv, z + s * ld, ld, 1.0);
     }
     __syncthreads();
     for (int q = 0; q < nruns; ++q) {
