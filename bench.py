@@ -47,6 +47,13 @@ KERNELS = {
 
 
 TIMED_RANGE = "pinvit_timed"
+# Kernel classes timed with HIP events inside the timed region.  Each timed launch records two
+# events on the stream, a few microseconds of host time per launch; the grouped GEMMs, copies
+# and split-K reductions (about 25,000 launches in three L=48 iterations) are left out there
+# and timed in an instrumented pass of as many further steps, which gives the per-class
+# breakdown.
+LIVE_CLASSES = ("jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "cholesky_f64", "tridiag_vectors_f64",
+                "tridiag_back_f64", "tridiag_values_f64")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_16118_amd", "csrc", "kernels.hip")
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
@@ -283,6 +290,7 @@ def main():
         print(f"# precision {precision}: warmup {a.warmup} it {time.perf_counter() - t:.1f}s ranks "
               f"{[r['max_rank'] for r in hist_w]}", file=sys.stderr, flush=True)
         ctx.timers_reset()
+        ctx.set_timed_classes(LIVE_CLASSES)
         if mark and rtx:
             rtx.roctxRangePushA(TIMED_RANGE.encode())
         t0 = time.perf_counter()
@@ -290,18 +298,25 @@ def main():
         t1 = time.perf_counter()
         if mark and rtx:
             rtx.roctxRangePop()
+        live = ctx.timers()
+        # instrumented pass: as many further steps with every kernel class timed
+        ctx.timers_reset()
+        ctx.set_timed_classes(None)
+        res_i, _, psi3 = ctx.run(max_iter=a.steps, start=psi2, resume=res, **common)
         tm = ctx.timers()
-        ctx.mps_free(psi)
-        ctx.mps_free(psi2)
-        return dict(elapsed=t1 - t0, res=res, hist=hist, timers=tm)
+        for q in (psi, psi2, psi3):
+            ctx.mps_free(q)
+        return dict(elapsed=t1 - t0, res=res, hist=hist, timers=tm, live=live)
 
     r64 = run_mode(0, True)
     r32 = None if a.no_mixed else run_mode(1, False)
-    tm = r64["timers"]
+    tm, live = r64["timers"], r64["live"]
     res, hist, elapsed = r64["res"], r64["hist"], r64["elapsed"]
     steps = len(hist)
-    # dominant kernel class over the timed region
-    dom_name, dom = max(tm.items(), key=lambda kv: kv[1]["ms"])
+    # dominant kernel class (instrumented pass); its launches are timed live in the timed
+    # region when it is one of LIVE_CLASSES
+    dom_name = max(tm.items(), key=lambda kv: kv[1]["ms"])[0]
+    dom = live[dom_name] if dom_name in LIVE_CLASSES else tm[dom_name]
     kernel, bound = KERNELS[dom_name]
     if bound in ("mfma", "mfma32"):
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
@@ -320,6 +335,8 @@ def main():
     roof["kernel"] = kernel
     roof["launches"] = dom["calls"]
     roof["avg_launch_ms"] = dom["ms"] / max(dom["calls"], 1)
+    roof["timing"] = ("HIP events on its launches in the timed region" if dom_name in LIVE_CLASSES
+                      else "HIP events on its launches in the instrumented pass")
     g = tm["gemm_f64_mfma"]
     out = {
         "metric": "PINVIT iters/s + block-GEMM TFLOP/s at L=48,N=24,r=512; |dE| vs FP64",
@@ -342,6 +359,9 @@ def main():
         "energy": res["energy"],
         "max_rank": max([r["max_rank"] for r in hist] + [0]),
         "timers_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
+        "timers_note": f"timers_ms, kernel_classes and block_gemm_tflops: an instrumented pass of "
+                       f"{steps} further steps with every kernel class timed; the timed region times "
+                       f"only {', '.join(LIVE_CLASSES)}",
         "kernel_classes": {k: {"ms": round(v["ms"], 3), "calls": v["calls"],
                                "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 4),
                                "gbs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 2)}

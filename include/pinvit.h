@@ -218,6 +218,11 @@ pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
 pv_status pv_timers_reset(pv_ctx* ctx);
+/* Which kernel classes are timed: bit i of mask enables class i (pv_timer_name(i)); the
+ * default is every class.  Each timed launch records two HIP events, which costs the host
+ * a few microseconds per launch; classes left out accumulate nothing.  Takes effect for
+ * the launches after the call (the context's stream is synchronised first). */
+pv_status pv_set_timer_mask(pv_ctx* ctx, uint32_t mask);
 
 /* Symmetric eigenproblem on the device (the eigensolvers behind the Gram
  * factorisations): A is n x n column-major (upper triangle read), w receives the

@@ -720,6 +720,14 @@ pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes
 
 const char* pv_timer_name(int i) { return (i >= 0 && i < T_COUNT) ? kTimerNames[i] : ""; }
 
+pv_status pv_set_timer_mask(pv_ctx* ctx, uint32_t mask) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    ctx->c.sync();
+    ctx->c.timer_mask = mask;
+  });
+}
+
 pv_status pv_timers_reset(pv_ctx* ctx) {
   return guard([&] {
     if (!ctx) fail(PV_EINVAL, "null context");

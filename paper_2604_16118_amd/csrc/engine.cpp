@@ -109,14 +109,14 @@ hipEvent_t Ctx::event() {
   return e;
 }
 
-void Ctx::begin(int, hipEvent_t& a) {
-  if (!timing) { a = nullptr; return; }
+void Ctx::begin(int cls, hipEvent_t& a) {
+  if (!((timer_mask >> cls) & 1u)) { a = nullptr; return; }
   a = event();
   PV_HIP(hipEventRecord(a, stream));
 }
 
 void Ctx::end(int cls, hipEvent_t a, double flops, double bytes) {
-  if (!timing || !a) return;
+  if (!a) return;
   hipEvent_t b = event();
   PV_HIP(hipEventRecord(b, stream));
   pending.push_back({cls, a, b, flops, bytes});
@@ -282,11 +282,19 @@ struct GemmBatch {
     }
     if (!list.empty()) {
       if (tiles > INT32_MAX) fail(PV_EINVAL, "GEMM batch too large for one launch");
-      GemmDesc* dd = c.upload(list);
       const int tc = cls >= 0 ? cls : (prec ? T_GEMM32 : T_GEMM);
-      hipEvent_t a; c.begin(tc, a);
-      launch_gemm(dd, int(list.size()), int(tiles), prec, c.stream);
-      c.end(tc, a, flops, bytes);
+      if (list.size() <= size_t(kGemmPack)) {  // descriptors in the kernel arguments
+        GemmPack pack{};
+        std::copy(list.begin(), list.end(), pack.d);
+        hipEvent_t a; c.begin(tc, a);
+        launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream);
+        c.end(tc, a, flops, bytes);
+      } else {
+        GemmDesc* dd = c.upload(list);
+        hipEvent_t a; c.begin(tc, a);
+        launch_gemm(dd, int(list.size()), int(tiles), prec, c.stream);
+        c.end(tc, a, flops, bytes);
+      }
     }
     if (!red.empty()) {
       ReduceDesc* dr = c.upload(red);

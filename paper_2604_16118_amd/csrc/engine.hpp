@@ -151,7 +151,8 @@ struct Ctx {
   std::vector<hipEvent_t> event_pool;
   double t_ms[T_COUNT] = {0}, t_flops[T_COUNT] = {0}, t_bytes[T_COUNT] = {0};
   int t_calls[T_COUNT] = {0};
-  bool timing = true;
+  // kernel classes timed with HIP events (bit c: class c); an untimed launch records no event
+  uint32_t timer_mask = ~0u;
   // 0: sequential TT-SVD truncation with two-pass Gram factorisations (exact path);
   // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
   //    intermediate-rank H application.

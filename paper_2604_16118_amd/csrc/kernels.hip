@@ -48,8 +48,22 @@ __device__ inline double wave_sum_d(double v) {
 // probes on gfx950).  The tile is 64 x 64 (BM x BN): measured on the L=48 workload, 128 x 64,
 // 64 x 128 and larger tiles lose more to the lower occupancy than they save in re-reads.
 // ---------------------------------------------------------------------------
+// XCD-aware order: workgroup b runs on XCD b % 8.  Tiles are dealt to the XCDs in groups of
+// kGemmGroup consecutive ones (same row block of A, consecutive column blocks), so a group
+// shares one L2 while every XCD still gets an even mix of the problems; the ragged end keeps
+// the plain order.
+__device__ inline int gemm_tile_of_block(int ntiles) {
+  const int b = blockIdx.x, span = 8 * kGemmGroup;
+  int tile = b;
+  if (b < ntiles / span * span) {
+    const int base = b - b % span, r = b - base;
+    tile = base + (r & 7) * kGemmGroup + (r >> 3);
+  }
+  return tile;
+}
+
 template <int PREC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob, int ntiles) {
+__device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
   // PREC 0: float64 operands on v_mfma_f64_16x16x4f64; PREC 1: operands rounded to float32
   // on v_mfma_f32_16x16x4f32 with float32 accumulation (C stays float64 in memory);
   // PREC 2: the float64 kernel again, a separate instance for the trailing updates of the
@@ -63,22 +77,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   // MFMAs of tile t run, then written to the other LDS buffer (one barrier per K-tile)
   __shared__ T As[2][BK][BM + 1];
   __shared__ T Bs[2][BK][BN + 1];
-  // XCD-aware order: workgroup b runs on XCD b % 8.  Tiles are dealt to the XCDs in groups
-  // of kGemmGroup consecutive ones (same row block of A, consecutive column blocks), so a
-  // group shares one L2 while every XCD still gets an even mix of the problems; the
-  // ragged end keeps the plain order.
-  const int b = blockIdx.x, span = 8 * kGemmGroup;
-  int tile = b;
-  if (b < ntiles / span * span) {
-    const int base = b - b % span, r = b - base;
-    tile = base + (r & 7) * kGemmGroup + (r >> 3);
-  }
-  int lo = 0, hi = nprob - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc g = descs[lo];
   gcdouble* gA = gbl(g.A);
   gcdouble* gB = gbl(g.B);
   gdouble* gC = gbl(g.C);
@@ -194,6 +192,43 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
           gC[i + (int64_t)j * g.ldc] = v;
         }
       }
+}
+
+template <int PREC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob, int ntiles) {
+  const int tile = gemm_tile_of_block(ntiles);
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc g = descs[lo];
+  gemm_tile<PREC, BM, BN>(g, tile);
+}
+
+// The same with the descriptors in the kernel arguments (at most kGemmPack problems): no
+// upload has to precede the launch.
+template <int PREC, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_packed_kernel(const GemmPack pack, int nprob, int ntiles) {
+  const int tile = gemm_tile_of_block(ntiles);
+  int lo = 0;
+  for (int p = 1; p < nprob; ++p)
+    if (pack.d[p].tile0 <= tile) lo = p;
+  const GemmDesc g = pack.d[lo];
+  gemm_tile<PREC, BM, BN>(g, tile);
+}
+
+void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  if (nprob < 1 || nprob > kGemmPack) throw std::runtime_error("gemm: a packed launch takes 1 to kGemmPack problems");
+  const dim3 g(total_tiles), b(256);
+  if (prec == 0)
+    hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+  else if (prec == 1)
+    hipLaunchKernelGGL((gemm_packed_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+  else
+    hipLaunchKernelGGL((gemm_packed_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+  PV_LAUNCH_CHECK();
 }
 
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s) {

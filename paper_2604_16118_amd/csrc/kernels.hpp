@@ -88,6 +88,12 @@ struct ScaleDesc {
 // prec 2: float64 MFMA, the instance used for the trailing updates of the tridiagonal
 // reduction.
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s);
+// Batches of at most kGemmPack problems pass their descriptors in the kernel arguments.
+constexpr int kGemmPack = 16;
+struct GemmPack {
+  GemmDesc d[kGemmPack];
+};
+void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 // mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
 // problems of one launch must admit the chosen mode at size nmax.

@@ -22,7 +22,7 @@ EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_batch",
-    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
 
@@ -100,6 +100,7 @@ def lib():
         L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
+        L.pv_set_timer_mask.argtypes = [C.c_void_p, C.c_uint32]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_sym_eig_top.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int,
@@ -356,3 +357,15 @@ class Context:
 
     def timers_reset(self):
         _check(lib().pv_timers_reset(self._p))
+
+    def set_timed_classes(self, names=None):
+        """Time only the named kernel classes (None: all of them)."""
+        if names is None:
+            mask = 0xFFFFFFFF
+        else:
+            index = {lib().pv_timer_name(i).decode(): i for i in range(32) if lib().pv_timer_name(i)}
+            unknown = set(names) - set(index)
+            if unknown:
+                raise ValueError(f"unknown kernel classes {sorted(unknown)}")
+            mask = sum(1 << index[n] for n in set(names))
+        _check(lib().pv_set_timer_mask(self._p, mask))
