@@ -234,8 +234,8 @@ struct GemmBatch {
     int64_t tiles = 0, red_elems = 0, zk_elems = 0;
     double flops = 0, bytes = 0;
     for (const GemmDesc& g0 : d) {
-      if (g0.K <= 0) {  // C = beta C
-        CopyDesc cd{g0.C, g0.C, g0.M, g0.N, g0.ldc, g0.ldc, g0.beta, zk_elems};
+      if (g0.K <= 0) {  // C = beta C (beta 0: C cleared without reading it)
+        CopyDesc cd{g0.beta != 0.0 ? g0.C : nullptr, g0.C, g0.M, g0.N, g0.ldc, g0.ldc, g0.beta, zk_elems};
         zero_k.push_back(cd);
         zk_elems += int64_t(g0.M) * g0.N;
         continue;
@@ -313,6 +313,20 @@ struct CopyBatch {
     if (rows <= 0 || cols <= 0) return;
     d.push_back(CopyDesc{src, dst, rows, cols, std::max(lds, 1), std::max(ldd, 1), alpha, total});
     total += int64_t(rows) * cols;
+  }
+  // n elements of p at stride ld set to v
+  void add_fill_strided(double* p, int ld, int n, double v) {
+    if (n <= 0) return;
+    d.push_back(CopyDesc{nullptr, p, 1, n, 1, std::max(ld, 1), v, total});
+    total += n;
+  }
+  // n elements of p set to v (through the same launch as the copies)
+  void add_fill(double* p, int64_t n, double v) {
+    for (int64_t o = 0; o < n; o += int64_t(1) << 30) {
+      const int m = int(std::min<int64_t>(n - o, int64_t(1) << 30));
+      d.push_back(CopyDesc{nullptr, p + o, m, 1, m, m, v, total});
+      total += m;
+    }
   }
   void run(Ctx& c) {
     if (d.empty()) return;
@@ -924,18 +938,23 @@ std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevM
     EnvLayout Ln = env_layout(k, N, bra.rho[k], ket.rho[k], op.qoff[k], vb, vk);
     T2Data t2 = site_contract(c, k, ket, bra.rho[k - 1], Le, E, Ln, op);
     Buf En(c.pool, size_t(std::max<int64_t>(Ln.total, 1)));
-    fill(c, En.p, Ln.total, 0.0);
+    // the first product into a block overwrites it (beta 0); blocks without one are cleared
     GemmBatch g0, g1;
+    CopyBatch zero;
     for (int n2 = 0; n2 <= N; ++n2) {
       if (Ln.rows[n2] == 0 || Ln.ncols[n2] == 0) continue;
       double* C = En.p + Ln.off[n2];
-      if (t2.off[0][n2] >= 0 && bra.ucols(k, n2) > 0)
+      const bool p0 = t2.off[0][n2] >= 0 && bra.ucols(k, n2) > 0;
+      const bool p1 = t2.off[1][n2] >= 0 && n2 >= 1 && bra.ocols(k, n2 - 1) > 0;
+      if (p0)
         g0.add(bra.U(k, n2), bra.rows(k, n2), 1, t2.buf.p + t2.off[0][n2], t2.rows[0][n2], 0, C,
-               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2), 1.0, 1.0);
-      if (t2.off[1][n2] >= 0 && n2 >= 1 && bra.ocols(k, n2 - 1) > 0)
+               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2), 1.0, 0.0);
+      if (p1)
         g1.add(bra.O(k, n2 - 1), bra.rows(k, n2 - 1), 1, t2.buf.p + t2.off[1][n2], t2.rows[1][n2], 0, C,
-               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2 - 1), 1.0, 1.0);
+               Ln.rows[n2], Ln.rows[n2], int(Ln.ncols[n2]), bra.rows(k, n2 - 1), 1.0, p0 ? 1.0 : 0.0);
+      if (!p0 && !p1) zero.add_fill(C, int64_t(Ln.rows[n2]) * Ln.ncols[n2], 0.0);
     }
+    zero.run(c);
     g0.run(c);
     g1.run(c);
     c.scratch.push_back(std::move(t2.buf));
@@ -1060,9 +1079,10 @@ std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const
     for (int n = 0; n <= N; ++n)
       if (x.valid(k, n)) rho[k][n] = (k == 0 || k == L) ? 1 : x.rho[k][n] + y.rho[k][n];
   auto m = mps_alloc(c, L, N, rho);
-  CopyBatch cb;
+  CopyBatch zero, cb;  // every site cleared in one launch, then the blocks copied in
+  for (int k = 1; k <= L; ++k) zero.add_fill(m->site[k - 1].p, m->site_size(k), 0.0);
+  zero.run(c);
   for (int k = 1; k <= L; ++k) {
-    fill(c, m->site[k - 1].p, m->site_size(k), 0.0);
     for (int n = 0; n <= N; ++n) {
       if (!x.valid(k - 1, n)) continue;
       const int R = m->rows(k, n);
@@ -1132,23 +1152,19 @@ std::vector<std::vector<double>> sigmas(Ctx& c, std::vector<SectorEig>& se) {
 
 // Single-pass factorisation: the second pass is the identity (W2 = I, same eigenvalues).
 void identity_pass(Ctx& c, std::vector<SectorEig>& se, std::vector<SectorEig>& se2) {
-  CopyBatch cb;
-  int rmax = 0;
-  for (size_t i = 0; i < se.size(); ++i) rmax = std::max(rmax, se[i].n);
-  Buf ones(c.pool, size_t(std::max(rmax, 1)));
-  fill(c, ones.p, std::max(rmax, 1), 1.0);
+  CopyBatch zero, cb;  // W2 = 0 in one launch, then the unit diagonals and the eigenvalues
   for (size_t i = 0; i < se.size(); ++i) {
     const int r = se[i].n;
     se2[i].n = r;
     if (r == 0) continue;
     se2[i].W = Buf(c.pool, size_t(r) * r);
     se2[i].w = Buf(c.pool, size_t(r));
-    fill(c, se2[i].W.p, int64_t(r) * r, 0.0);
+    zero.add_fill(se2[i].W.p, int64_t(r) * r, 0.0);
     cb.add(se[i].w.p, r, se2[i].w.p, r, r, 1, 1.0);
-    cb.add(ones.p, 1, se2[i].W.p, r + 1, 1, r, 1.0);  // unit diagonal (stride r + 1)
+    cb.add_fill_strided(se2[i].W.p, r + 1, r, 1.0);  // unit diagonal (stride r + 1)
   }
+  zero.run(c);
   cb.run(c);
-  c.scratch.push_back(std::move(ones));
 }
 
 
@@ -1291,9 +1307,10 @@ static std::unique_ptr<Mps> truncate_ltr(Ctx& c, std::unique_ptr<Mps> y, double 
       if (rk == 0 || r0[n] + r1[n] == 0) continue;
       se[n].n = rk;
       se[n].G = Buf(c.pool, size_t(rk) * rk);
-      fill(c, se[n].G.p, int64_t(rk) * rk, 0.0);
-      if (r0[n]) g.add(y->U(k, n), r0[n], 1, y->U(k, n), r0[n], 0, se[n].G.p, rk, rk, rk, r0[n], 1.0, 1.0);
-      if (r1[n]) g1.add(y->O(k, n - 1), r1[n], 1, y->O(k, n - 1), r1[n], 0, se[n].G.p, rk, rk, rk, r1[n], 1.0, 1.0);
+      // the first product overwrites G (beta 0), the second accumulates
+      if (r0[n]) g.add(y->U(k, n), r0[n], 1, y->U(k, n), r0[n], 0, se[n].G.p, rk, rk, rk, r0[n], 1.0, 0.0);
+      if (r1[n])
+        g1.add(y->O(k, n - 1), r1[n], 1, y->O(k, n - 1), r1[n], 0, se[n].G.p, rk, rk, rk, r1[n], 1.0, r0[n] ? 1.0 : 0.0);
     }
     g.run(c);
     g1.run(c);

@@ -1692,7 +1692,7 @@ __global__ void copy_kernel(const CopyDesc* __restrict__ d, int nd, int64_t tota
   const CopyDesc c = d[lo];
   const int64_t x = e - c.elem0;
   const int i = int(x % c.rows), j = int(x / c.rows);
-  c.dst[i + (int64_t)j * c.ldd] = c.alpha * c.src[i + (int64_t)j * c.lds];
+  c.dst[i + (int64_t)j * c.ldd] = c.src ? c.alpha * c.src[i + (int64_t)j * c.lds] : c.alpha;
 }
 
 void launch_copy(const CopyDesc* d, int nd, int64_t total, hipStream_t s) {

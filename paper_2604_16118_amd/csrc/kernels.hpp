@@ -64,7 +64,8 @@ struct WTask {
 constexpr int kWElems = 8;              // output elements per thread
 constexpr int kWTask = 256 * kWElems;   // output elements per task (one workgroup)
 
-// Batched copies dst = alpha * src of r x c sub-blocks (column-major).
+// Batched copies dst = alpha * src of r x c sub-blocks (column-major); a null src fills the
+// block with alpha.
 struct CopyDesc {
   const double* src;
   double* dst;
