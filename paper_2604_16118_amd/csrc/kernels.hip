@@ -695,6 +695,95 @@ __device__ inline gdouble* tri_diag_flag(gdouble* W, int n) { return tri_tail(W,
 // 1a. Preparation: working copy of A (both triangles, from the upper triangle of the
 //     input); a matrix whose off-diagonal part is negligible is passed on as T = diag(A);
 //     a narrow spectrum is shifted by its mean diagonal entry.
+//
+//     The copy runs on 32 x 32 tiles of the upper triangle, many workgroups per matrix: a
+//     tile is read along its columns, written in place and, through LDS, transposed into
+//     the lower triangle.  Each tile also leaves the largest diagonal and off-diagonal
+//     magnitudes and its share of the off-diagonal absolute row sums (the Gershgorin
+//     radii): entry [b][x] of the partial sums holds what tile row or column block b
+//     contributes to row x, so every entry has exactly one writer.  A second kernel, one
+//     workgroup per matrix, reduces those partials and takes the decisions.
+constexpr int kPrepTile = 32;
+__device__ inline int prep_tiles(int n) { return (n + kPrepTile - 1) / kPrepTile; }
+// partial row sums (tiles(n) x n) and the per-tile maxima (2 per tile pair), past the
+// working copy in the area the later phases use as scratch
+__device__ inline gdouble* prep_rowsums(gdouble* W, int n) { return W + (int64_t)n * n; }
+__device__ inline gdouble* prep_maxima(gdouble* W, int n) { return prep_rowsums(W, n) + (int64_t)prep_tiles(n) * n; }
+
+__global__ __launch_bounds__(256) void tridiag_copy_kernel(const EigDesc* __restrict__ descs) {
+  __shared__ double tile[kPrepTile][kPrepTile + 1];  // tile[c][r] = A[r, c] of the input
+  __shared__ double red[2][4];
+  const EigDesc D = descs[blockIdx.y];
+  const int n = D.n;
+  const int T = prep_tiles(n);
+  const int p = blockIdx.x;
+  if (n <= 0 || p >= T * (T + 1) / 2) return;
+  // tile pair p -> (bi, bj), bi <= bj, p = bj (bj + 1) / 2 + bi
+  int bj = int((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while (bj * (bj + 1) / 2 > p) --bj;
+  while ((bj + 1) * (bj + 2) / 2 <= p) ++bj;
+  const int bi = p - bj * (bj + 1) / 2;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int r0 = bi * kPrepTile, c0 = bj * kPrepTile;
+  gcdouble* Ain = gbl(D.A);
+  gdouble* A = gbl(D.work);
+  double dg = 0.0, od = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPrepTile / 8; ++q) {
+    const int cl = ty + 8 * q, r = r0 + tx, c = c0 + cl;
+    const bool ok = r < n && c < n && r <= c;
+    const double v = ok ? Ain[r + (int64_t)c * D.lda] : 0.0;
+    tile[cl][tx] = v;
+    if (ok) {
+      A[r + (int64_t)c * n] = v;
+      if (r == c) dg = fmax(dg, fabs(v)); else od = fmax(od, fabs(v));
+    }
+  }
+  __syncthreads();
+  // transposed part: A[c, r] = A[r, c] for r < c, written along c
+#pragma unroll
+  for (int q = 0; q < kPrepTile / 8; ++q) {
+    const int rl = ty + 8 * q, r = r0 + rl, c = c0 + tx;
+    if (r < n && c < n && r < c) A[c + (int64_t)r * n] = tile[tx][rl];
+  }
+  // off-diagonal absolute sums: column c of the tile (rows r < c) and row r (columns c > r)
+  gdouble* P = prep_rowsums(A, n);
+  if (tid < 2 * kPrepTile) {
+    const int x = tid & 31;
+    double sum = 0.0;
+    if (tid < kPrepTile) {
+      for (int rl = 0; rl < kPrepTile; ++rl)
+        if (r0 + rl < c0 + x) sum += fabs(tile[x][rl]);
+    } else {
+      for (int cl = 0; cl < kPrepTile; ++cl)
+        if (c0 + cl > r0 + x) sum += fabs(tile[cl][x]);
+    }
+    if (bi == bj) {  // both sums belong to row x of the same block
+      const double other = __shfl_xor(sum, 32, 64);
+      if (tid < kPrepTile && r0 + x < n) P[(int64_t)bi * n + r0 + x] = sum + other;
+    } else if (tid < kPrepTile) {
+      if (c0 + x < n) P[(int64_t)bi * n + c0 + x] = sum;
+    } else {
+      if (r0 + x < n) P[(int64_t)bj * n + r0 + x] = sum;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    dg = fmax(dg, __shfl_xor(dg, off, 64));
+    od = fmax(od, __shfl_xor(od, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = dg;
+    red[1][tid >> 6] = od;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    gdouble* M = prep_maxima(A, n);
+    M[2 * p] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+    M[2 * p + 1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+  }
+}
+
 __global__ __launch_bounds__(kRedThreads) void tridiag_prepare_kernel(const EigDesc* __restrict__ descs) {
   __shared__ double red[kRedThreads / 64];
   const EigDesc D = descs[blockIdx.x];
@@ -707,13 +796,13 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_prepare_kernel(const EigD
   gdouble* betas = tail;
   gdouble* dd = tail + n;
   gdouble* ee = tail + 2 * n;
-  gcdouble* Ain = gbl(D.A);
+  const int T = prep_tiles(n), np = T * (T + 1) / 2;
+  gcdouble* P = prep_rowsums(A, n);
+  gcdouble* M = prep_maxima(A, n);
   double od = 0.0, dg = 0.0;
-  for (int e = tid; e < n * n; e += bs) {
-    const int j = e / n, i = e - j * n;
-    const double a = (i <= j) ? Ain[i + (int64_t)j * D.lda] : Ain[j + (int64_t)i * D.lda];
-    A[e] = a;
-    if (i == j) dg = fmax(dg, fabs(a)); else od = fmax(od, fabs(a));
+  for (int t = tid; t < np; t += bs) {
+    dg = fmax(dg, M[2 * t]);
+    od = fmax(od, M[2 * t + 1]);
   }
   od = block_max(od, red, tid, bs);
   dg = block_max(dg, red, tid, bs);
@@ -735,7 +824,7 @@ __global__ __launch_bounds__(kRedThreads) void tridiag_prepare_kernel(const EigD
   double rad = 0.0;
   for (int j = tid; j < n; j += bs) {
     double r = fabs(A[j + (int64_t)j * lda] - mu);
-    for (int i = 0; i < n; ++i) r += i == j ? 0.0 : fabs(A[i + (int64_t)j * lda]);
+    for (int b = 0; b < T; ++b) r += P[(int64_t)b * n + j];
     rad = fmax(rad, r);
   }
   rad = block_max(rad, red, tid, bs);
@@ -1441,6 +1530,9 @@ static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
 void launch_tri_prepare(const EigDesc* d, int nprob, int nmax, hipStream_t s) {
   if (nprob <= 0) return;
   if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  const int T = (nmax + kPrepTile - 1) / kPrepTile;
+  hipLaunchKernelGGL(tridiag_copy_kernel, dim3(T * (T + 1) / 2, nprob), dim3(256), 0, s, d);
+  PV_LAUNCH_CHECK();
   hipLaunchKernelGGL(tridiag_prepare_kernel, dim3(nprob), dim3(nmax <= 64 ? 256 : kRedThreads), 0, s, d);
   PV_LAUNCH_CHECK();
 }
