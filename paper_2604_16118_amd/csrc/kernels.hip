@@ -441,23 +441,25 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(const EigDesc* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigensolver by Householder tridiagonalisation, bisection and inverse
-// iteration, one workgroup per matrix (used for the Gram eigenproblems of the scaled
-// path, where Jacobi's O(n^3) traffic per sweep is too slow):
+// Symmetric eigensolver by Householder tridiagonalisation, multisection and inverse
+// iteration (used for the Gram eigenproblems of the scaled path, where Jacobi's O(n^3)
+// traffic per sweep is too slow):
 //  1. A = Q T Q^T with Householder reflectors H_k = I - beta_k v_k v_k^T acting on rows
 //     and columns k+1..n-1 (the trailing block is updated by the symmetric rank-2 form
-//     A <- A - v q^T - q v^T, q = p - (beta/2)(v^T p) v, p = beta A v);
-//  2. every eigenvalue of T by bisection on the Sturm count (thread t finds the t-th
-//     smallest);
-//  3. eigenvectors of T by inverse iteration with a partially pivoted tridiagonal LU,
-//     three iterations, members of a cluster (gap <= 1e-7 ||T||) orthogonalised against
-//     each other by modified Gram-Schmidt; eigenvalues <= vec_cut * max |lambda| get a
-//     zero vector (the callers drop them);
+//     A <- A - v q^T - q v^T, q = p - (beta/2)(v^T p) v, p = beta A v), blocked in panels
+//     of kTriPanel columns whose trailing updates are GEMMs;
+//  2. every eigenvalue of T by multisection on the Sturm count (a group of lanes per
+//     eigenvalue);
+//  3. eigenvectors of T by inverse iteration with a partially pivoted tridiagonal LU: two
+//     solves for an isolated eigenvalue, three for the members of a cluster (gap <= 1e-7
+//     ||T||), which the workgroup orthogonalises against each other by classical
+//     Gram-Schmidt applied twice; eigenvalues <= vec_cut * max |lambda| get a zero vector
+//     (the callers drop them);
 //  4. back-transformation V = H_0 H_1 ... H_{n-3} Z, in which every wavefront carries two
 //     columns of Z in registers through all reflectors (no workgroup barriers, n/8
-//     workgroups per matrix).
-// Three launches (reduction, eigenpairs of T, back-transformation), each kernel with its
-// own register budget.  Output as the Jacobi kernel: eigenvalues descending, eigenvectors
+//     workgroups per matrix; four columns per wavefront, with half the waves, measured
+//     slower).
+// Each phase is its own launch with its own register budget.  Output as the Jacobi kernel: eigenvalues descending, eigenvectors
 // in the columns of V.
 // ---------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;
