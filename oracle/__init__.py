@@ -19,7 +19,9 @@ Everything here is plain float64 NumPy on full occupation-number vectors of leng
                  terms (Section 4.3), the sorted sequential sum of Lemma truncr.
 * ``bounds``  -- a-posteriori quantities of Section 5.4 (b_delta, eq. everrbound).
 * ``pinvit``  -- Algorithm 2 (perturbed inverse iteration) in the physical variable
-                 psi = S x.
+                 psi = S x; Algorithm 3 (outer iteration) on top of it.
+* ``subspace`` -- Algorithm 4 (perturbed inverse subspace iteration, Section 6) on D
+                 columns kept as separate vectors.
 * ``mps``     -- contraction of an exported block-sparse MPS to its dense vector
                  (eq. mps with the block structure of eq. blockstructure).
 

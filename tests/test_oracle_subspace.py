@@ -1,0 +1,70 @@
+"""Pins of the oracle's Algorithm 4 (subspace iteration, Section 6): against exact
+diagonalisation of the N-particle sector, the min-max property of Ritz values, the
+one-column case (Algorithm 2), and the starting determinants."""
+import numpy as np
+import pytest
+
+from oracle import fock, pinvit, subspace
+from synth import make_problem
+
+
+@pytest.fixture(scope="module")
+def l8():
+    p = make_problem("decayed", 8, 4, 0)
+    ed = fock.lowest_eigs(p.h, p.v, 4, p.gamma, 4)
+    prm = pinvit.Params(cap=64, max_iter=36, tau=1e-12)
+    X, hist, _ = subspace.run_subspace(p.h, p.v, 4, p.gamma, prm, 3)
+    return p, ed, X, hist
+
+
+def test_subspace_reaches_the_lowest_eigenvalues(l8):
+    p, ed, X, hist = l8
+    lam = hist[-1]["lam"]
+    # the lowest two converge fast; the third more slowly (its gap to the fourth is smaller)
+    assert abs(lam[0] - ed[0]) <= 1e-10 * abs(ed[0])
+    assert abs(lam[1] - ed[1]) <= 1e-8 * abs(ed[1])
+    assert abs(lam[2] - ed[2]) <= 1e-3 * abs(ed[2])
+
+
+def test_ritz_values_bound_the_eigenvalues_from_above(l8):
+    # min-max: the i-th Ritz value of any D-dimensional subspace is >= the i-th eigenvalue
+    p, ed, X, hist = l8
+    for rec in hist:
+        lam = rec["lam"]
+        assert np.all(np.diff(lam) >= 0)
+        assert np.all(lam >= ed[:3] - 1e-11 * np.abs(ed[:3]))
+        if "lam_star" in rec:
+            assert np.all(rec["lam_star"] >= ed[:3] - 1e-11 * np.abs(ed[:3]))
+            # the 2D-dimensional Ritz space contains span Psi: its values are not larger
+            assert np.all(rec["lam_star"] <= lam + 1e-11 * np.abs(lam))
+
+
+def test_one_column_is_algorithm_2():
+    p = make_problem("decayed", 8, 4, 1)
+    prm = pinvit.Params(cap=64, max_iter=8, tau=1e-12)
+    _, h1, _ = subspace.run_subspace(p.h, p.v, 4, p.gamma, prm, 1)
+    _, h2, _ = pinvit.run(p.h, p.v, 4, p.gamma, prm)
+    assert len(h1) == len(h2)
+    for a, b in zip(h1, h2):
+        assert abs(a["E"][0] - b["E"]) <= 1e-12 * abs(b["E"])
+        assert abs(a["rho"][0] - b["rho"]) <= 1e-9 * b["rho"]
+
+
+def test_start_determinants_are_the_lowest_single_excitations():
+    h = np.diag([0.0, 1.0, 2.5, 3.0, 3.2, 9.0])
+    dets = subspace.start_determinants(h, 3, 4)
+    assert dets[0] == [0, 1, 2]
+    # excitations i -> a ordered by h_aa - h_ii: 2->3 (0.5), 2->4 (0.7), 1->3 (2.0)
+    assert dets[1:] == [[0, 1, 3], [0, 1, 4], [0, 2, 3]]
+    for d in dets:
+        assert len(set(d)) == 3
+
+
+def test_rank_cap_keeps_ritz_values_above_the_eigenvalues():
+    # with a binding rank cap the iterates are truncated, the min-max bound still holds
+    p = make_problem("decayed", 8, 4, 2)
+    ed = fock.lowest_eigs(p.h, p.v, 4, p.gamma, 2)
+    prm = pinvit.Params(cap=4, max_iter=10, tau=1e-12)
+    _, hist, _ = subspace.run_subspace(p.h, p.v, 4, p.gamma, prm, 2)
+    for rec in hist:
+        assert np.all(rec["lam"] >= ed - 1e-11 * np.abs(ed))
