@@ -124,6 +124,26 @@ typedef struct {
   int stopped;        /* 1 on the step whose eigenvalue bound met tol */
 } pv_outer_iter;
 
+/* Largest number of columns of the subspace iteration. */
+#define PV_SUBSPACE_MAX_D 8
+
+/* One row of the subspace iteration history (Algorithm 4); entries i >= D are unused. */
+typedef struct {
+  double lambda[PV_SUBSPACE_MAX_D];      /* Rayleigh quotients of the E-orthonormal Ritz basis, ascending */
+  double energy[PV_SUBSPACE_MAX_D];      /* lambda - gamma */
+  double rho[PV_SUBSPACE_MAX_D];         /* residual bound of each column (eq. rhobound) */
+  double s_norm[PV_SUBSPACE_MAX_D];      /* ||S r_i|| */
+  double lambda_star[PV_SUBSPACE_MAX_D]; /* lowest D Ritz values of the 2D-dimensional step */
+  double bound;       /* eigenvector error bound of column 1 (eq. everrbound), NaN outside its domain */
+  double eta_res;     /* accepted residual tolerance (per column) */
+  double eta_psi;     /* truncation tolerance of each new column */
+  double seconds;     /* wall time of the iteration */
+  int retries;        /* tolerance reductions (x 4/5) taken */
+  int cap_bound;      /* 1 if any truncation of the iteration was limited by rank_cap */
+  int max_rank;       /* maximal bond rank over the new columns */
+  int stopped;        /* 1 on the iteration where the tolerance test succeeded */
+} pv_subspace_iter;
+
 const char* pv_last_error(void);
 
 /* Context on HIP device `device`.  Fails with PV_EDEVICE when there is no GPU. */
@@ -193,6 +213,29 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
  * max_outer < 1; errors of an inner run are returned with the step named. */
 pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double tol, int max_outer,
                        pv_result* res, pv_outer_iter* hist, int hist_cap, int* psi);
+
+/* Algorithm 4 (perturbed inverse subspace iteration, Section 6) on D columns, 1 <= D <=
+ * PV_SUBSPACE_MAX_D, in the physical variable psi = S x like pv_run.  The columns are kept
+ * as D block-sparse MPS rather than one joint MPS with an index core (Section 6.2): the
+ * normalisation Psi <- Psi V of each iteration is carried as a D x D coefficient matrix
+ * and applied exactly (MPS concatenation) where a column is needed, and every truncation
+ * of the iterate acts on each column with the whole tolerance.  Per iteration: D x D
+ * Rayleigh-Ritz on the current columns (E-orthonormal Ritz basis, Rayleigh quotients
+ * ascending); per column the residual and its preconditioned forms as in pv_run (one
+ * tolerance eta_res for all columns, reduced while the smallest ||S r_i|| is below
+ * (1 + 1/zeta) eta_res); termination on the eigenvector bound of column 1; a 2D x 2D
+ * Rayleigh-Ritz step on the columns and their normalised directions S^2 r_i; the new
+ * columns truncated with s_min eta_in, eta_in the smallest of the per-column tolerances
+ * of Algorithm 4.  The small generalised eigenproblems are solved on the host.
+ * starts: D MPS handles of the starting columns (not consumed), or NULL for the
+ * determinant of the N smallest h_ii and its D-1 single excitations i -> a of smallest
+ * h_aa - h_ii (ties: lower i, then lower a).  res describes column 1 (energy, lambda,
+ * rho, bound); hist receives up to hist_cap rows; psi (NULL or D ints) receives handles of
+ * the final columns (the Ritz basis of the last iteration when it stopped, else the last
+ * truncated update).  PV_EINVAL for a D out of range or invalid parameters, PV_ESTATE
+ * without a Hamiltonian, PV_ENOTSPD when a Gram or Ritz pencil is not positive definite. */
+pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* starts, pv_result* res,
+                          pv_subspace_iter* hist, int hist_cap, int* psi);
 
 /* Batched independent problems (many Hamiltonians of uneven size at once): runs pv_run from
  * the determinant on each of the `count` distinct contexts ctxs[i] (each with its

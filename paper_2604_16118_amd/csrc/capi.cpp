@@ -145,6 +145,137 @@ double delta_a(double rho, double q) {
   return (-q * rho + std::sqrt(q * q * rho * rho + (1.0 + rho * rho) * (1.0 - q * q))) / (1.0 + rho * rho);
 }
 
+// Lowest k eigenpairs of the symmetric pencil (B, M), n x n row-major, M positive definite:
+// M = L L^T (Cholesky), cyclic Jacobi on L^{-1} B L^{-T}, eigenvalues ascending, vectors
+// V (n x k, row-major) with V^T M V = I; the entry of largest magnitude of each vector
+// (the first on ties) is made positive.  For the small Rayleigh-Ritz problems of the
+// subspace iteration (n <= 2 PV_SUBSPACE_MAX_D).
+void small_pencil(int n, const std::vector<double>& B, const std::vector<double>& M, int k, std::vector<double>& w,
+                  std::vector<double>& V) {
+  std::vector<double> L(size_t(n) * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = M[size_t(j) * n + j];
+    for (int q = 0; q < j; ++q) d -= L[size_t(j) * n + q] * L[size_t(j) * n + q];
+    if (!(d > 0.0)) fail(PV_ENOTSPD, "Rayleigh-Ritz pencil: Gram matrix is not positive definite");
+    L[size_t(j) * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double s = M[size_t(i) * n + j];
+      for (int q = 0; q < j; ++q) s -= L[size_t(i) * n + q] * L[size_t(j) * n + q];
+      L[size_t(i) * n + j] = s / L[size_t(j) * n + j];
+    }
+  }
+  // X = L^{-1} B (forward substitution per column), A = X L^{-T} = L^{-1} X^T (B symmetric)
+  auto lsolve = [&](std::vector<double>& Y) {  // Y <- L^{-1} Y, Y n x n row-major
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        double s = Y[size_t(i) * n + c];
+        for (int q = 0; q < i; ++q) s -= L[size_t(i) * n + q] * Y[size_t(q) * n + c];
+        Y[size_t(i) * n + c] = s / L[size_t(i) * n + i];
+      }
+  };
+  std::vector<double> A(B);
+  lsolve(A);
+  std::vector<double> At(size_t(n) * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) At[size_t(i) * n + j] = A[size_t(j) * n + i];
+  lsolve(At);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double m = 0.5 * (At[size_t(i) * n + j] + At[size_t(j) * n + i]);
+      At[size_t(i) * n + j] = At[size_t(j) * n + i] = m;
+    }
+  std::vector<double> U(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) U[size_t(i) * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double a = At[size_t(i) * n + j] * At[size_t(i) * n + j];
+        tot += a;
+        if (i != j) off += a;
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = At[size_t(p) * n + q];
+        if (apq == 0.0) continue;
+        const double th = (At[size_t(q) * n + q] - At[size_t(p) * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(1.0 + th * th));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+        for (int r = 0; r < n; ++r) {  // columns p, q
+          const double x = At[size_t(r) * n + p], y = At[size_t(r) * n + q];
+          At[size_t(r) * n + p] = cs * x - sn * y;
+          At[size_t(r) * n + q] = sn * x + cs * y;
+        }
+        for (int r = 0; r < n; ++r) {  // rows p, q
+          const double x = At[size_t(p) * n + r], y = At[size_t(q) * n + r];
+          At[size_t(p) * n + r] = cs * x - sn * y;
+          At[size_t(q) * n + r] = sn * x + cs * y;
+        }
+        for (int r = 0; r < n; ++r) {
+          const double x = U[size_t(r) * n + p], y = U[size_t(r) * n + q];
+          U[size_t(r) * n + p] = cs * x - sn * y;
+          U[size_t(r) * n + q] = sn * x + cs * y;
+        }
+      }
+  }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return At[size_t(a) * n + a] < At[size_t(b) * n + b]; });
+  w.assign(k, 0.0);
+  V.assign(size_t(n) * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    const int e = order[j];
+    w[j] = At[size_t(e) * n + e];
+    // V[:, j] = L^{-T} U[:, e] (back substitution)
+    for (int i = n - 1; i >= 0; --i) {
+      double s = U[size_t(i) * n + e];
+      for (int q = i + 1; q < n; ++q) s -= L[size_t(q) * n + i] * V[size_t(q) * k + j];
+      V[size_t(i) * k + j] = s / L[size_t(i) * n + i];
+    }
+    int im = 0;
+    for (int i = 1; i < n; ++i)
+      if (std::fabs(V[size_t(i) * k + j]) > std::fabs(V[size_t(im) * k + j])) im = i;
+    if (V[size_t(im) * k + j] < 0)
+      for (int i = 0; i < n; ++i) V[size_t(i) * k + j] = -V[size_t(i) * k + j];
+  }
+}
+
+// Starting columns of the subspace iteration: the determinant of the N smallest h_ii (ties
+// to the lower index) and its single excitations i -> a in order of h_aa - h_ii (ties: lower
+// i, then lower a).
+std::vector<std::vector<int>> subspace_starts(const std::vector<double>& h, int L, int N, int D) {
+  std::vector<int> idx(L);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h[size_t(a) * L + a] < h[size_t(b) * L + b]; });
+  std::vector<int> occ(idx.begin(), idx.begin() + N);
+  std::sort(occ.begin(), occ.end());
+  std::vector<char> in(L, 0);
+  for (int o : occ) in[o] = 1;
+  struct Ex { double d; int i, a; };
+  std::vector<Ex> ex;
+  for (int i : occ)
+    for (int a = 0; a < L; ++a)
+      if (!in[a]) ex.push_back({h[size_t(a) * L + a] - h[size_t(i) * L + i], i, a});
+  std::stable_sort(ex.begin(), ex.end(), [](const Ex& x, const Ex& y) {
+    if (x.d != y.d) return x.d < y.d;
+    if (x.i != y.i) return x.i < y.i;
+    return x.a < y.a;
+  });
+  if (int(ex.size()) < D - 1) fail(PV_EINVAL, "not enough single excitations for D starting columns");
+  std::vector<std::vector<int>> out{occ};
+  for (int t = 0; t + 1 < D; ++t) {
+    std::vector<int> o;
+    for (int x : occ)
+      if (x != ex[t].i) o.push_back(x);
+    o.push_back(ex[t].a);
+    std::sort(o.begin(), o.end());
+    out.push_back(o);
+  }
+  return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -696,6 +827,245 @@ pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
     if (n < 1 || n > kEigMax) fail(PV_EINVAL, "n out of range");
     for (size_t i = 0; i < size_t(n) * n; ++i) if (!std::isfinite(A[i])) fail(PV_EINVAL, "A not finite");
     cholesky(ctx->c, n, A, W);
+  });
+}
+
+// Algorithm 4 (subspace iteration, Section 6) on D separate columns; see the header for the
+// readings.  Phi holds the columns as stored; the Rayleigh-Ritz coefficients C of an
+// iteration give the E-orthonormal basis psi_i = sum_j C_ji phi_j, formed exactly (MPS
+// concatenation) where H, the residual or the update need it.
+pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* starts, pv_result* res,
+                          pv_subspace_iter* hist, int hist_cap, int* psi_out) {
+  return guard([&] {
+    if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
+    if (D < 1 || D > PV_SUBSPACE_MAX_D) fail(PV_EINVAL, "D out of range");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    const pv_params p = *prm;
+    if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
+        !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
+      fail(PV_EINVAL, "invalid parameters");
+    if (p.precision != 0 && p.precision != 1)
+      fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32 contractions)");
+    if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
+    c.prec = p.precision;
+    c.trunc_mode = p.truncation;
+    auto mnorm = [&](const Mps& m) { return c.trunc_mode == 0 ? norm_canonical(c, m) : norm2(c, m); };
+    setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
+    const int cap = p.rank_cap, mz = p.m_zip;
+    const double eps_num = p.eps_num > 0 ? p.eps_num : 0.5 * (1.0 - p.c);
+    const double zeta = eps_num / (1.0 + p.c);
+    double eta = std::numeric_limits<double>::infinity();
+    double s_prev = -1, s_prev2 = -1;
+    std::vector<std::unique_ptr<Mps>> phi(D);
+    if (starts) {
+      for (int i = 0; i < D; ++i) phi[i] = mps_scaled_copy(c, get(c, starts[i]), 1.0, nullptr);
+    } else {
+      const auto dets = subspace_starts(c.h, c.L, c.N, D);
+      for (int i = 0; i < D; ++i) phi[i] = mps_determinant(c, dets[i]);
+    }
+    // sum_j a_j x_j by concatenation (exact)
+    auto combine = [&](const std::vector<const Mps*>& xs, const std::vector<double>& a) {
+      std::unique_ptr<Mps> acc = mps_scaled_copy(c, *xs[0], a[0], nullptr);
+      for (size_t j = 1; j < xs.size(); ++j) acc = mps_lincomb(c, 1.0, *acc, a[j], *xs[j]);
+      return acc;
+    };
+    std::vector<const Mps*> phip(D);
+    int rows = 0;
+    *res = pv_result{};
+    std::vector<std::unique_ptr<Mps>> psi(D);
+    for (int it = 0; it < p.max_iter; ++it) {
+      const auto t0 = std::chrono::steady_clock::now();
+      pv_subspace_iter rec{};
+      for (int i = 0; i < D; ++i) phip[i] = phi[i].get();
+      // 1. Rayleigh-Ritz on span phi: Hm C = Em C Lambda, C^T Em C = I
+      std::vector<double> Hm(size_t(D) * D), Em(size_t(D) * D);
+      for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j) {
+          Hm[size_t(i) * D + j] = Hm[size_t(j) * D + i] = expect_h(c, *phi[i], *phi[j]);
+          Em[size_t(i) * D + j] = Em[size_t(j) * D + i] = dot(c, *phi[i], *phi[j]);
+        }
+      std::vector<double> lam, Cm;
+      small_pencil(D, Hm, Em, D, lam, Cm);
+      for (int i = 0; i < D; ++i) {
+        std::vector<double> a(D);
+        for (int j = 0; j < D; ++j) a[j] = Cm[size_t(j) * D + i];
+        psi[i] = combine(phip, a);
+        if (!(lam[i] > 0)) fail(PV_ENOTSPD, "Rayleigh quotient is not positive (H_gamma not positive definite)");
+      }
+      // 2. start value of eta_res
+      double est = 0.0;
+      if (s_prev < 0) {
+        for (int i = 0; i < D; ++i) {
+          std::unique_ptr<Mps> y0;
+          {
+            LowPrecision lp(c);
+            y0 = apply_h(c, *psi[i], 0.0, cap, mz, nullptr);
+          }
+          auto d0 = mps_lincomb(c, 1.0, *y0, -lam[i], *psi[i]);
+          auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
+          est = std::max(est, c.s_max * mnorm(*r0));
+        }
+      } else if (s_prev2 <= 0) {
+        est = s_prev;
+      } else {
+        est = s_prev * std::min(1.0, s_prev / s_prev2);
+      }
+      eta = std::min(2.0 * eta, 0.8 * zeta * est);
+      // 3.-4. residuals r_i, s_i = S r_i; eta reduced while the smallest ||s_i|| is too small
+      int retries = 0;
+      bool capb = false;
+      std::vector<std::unique_ptr<Mps>> s(D);
+      std::vector<double> ns(D);
+      while (true) {
+        capb = false;
+        const double e12 = eta / (3.0 * c.s_max);
+        double nmin = std::numeric_limits<double>::infinity();
+        for (int i = 0; i < D; ++i) {
+          bool cb1 = false, cb2 = false, cb3 = false;
+          std::unique_ptr<Mps> y;
+          {
+            LowPrecision lp(c);
+            y = apply_h(c, *psi[i], e12, cap, mz, &cb1);
+          }
+          auto d = mps_lincomb(c, 1.0, *y, -lam[i], *psi[i]);
+          y.reset();
+          auto r = round_mps(c, *d, e12, cap, &cb2);
+          d.reset();
+          s[i] = apply_s(c, *r, eta / 3.0, cap, &cb3);
+          ns[i] = mnorm(*s[i]);
+          nmin = std::min(nmin, ns[i]);
+          capb = capb || cb1 || cb2 || cb3;
+        }
+        if (nmin >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries) break;
+        eta *= 0.8;
+        ++retries;
+      }
+      std::vector<double> rho(D);
+      for (int i = 0; i < D; ++i) rho[i] = (ns[i] + eta) / (std::sqrt(1.0 - p.c) * std::sqrt(lam[i]));
+      const double bound = error_bound(rho[0], p.delta);
+      for (int i = 0; i < D; ++i) {
+        rec.lambda[i] = lam[i];
+        rec.energy[i] = lam[i] - c.gamma;
+        rec.rho[i] = rho[i];
+        rec.s_norm[i] = ns[i];
+      }
+      rec.bound = bound;
+      rec.eta_res = eta;
+      rec.retries = retries;
+      rec.cap_bound = capb ? 1 : 0;
+      res->energy = lam[0] - c.gamma;
+      res->lambda = lam[0];
+      res->rho = rho[0];
+      res->bound = bound;
+      res->eta_res = eta;
+      if (bound <= p.tau) {
+        rec.stopped = 1;
+        int mr = 0;
+        for (int i = 0; i < D; ++i) mr = std::max(mr, psi[i]->max_rank());
+        rec.max_rank = mr;
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        for (int i = 0; i < D; ++i) phi[i] = std::move(psi[i]);
+        break;
+      }
+      // 6. directions p_i / ||p_i|| and the 2D x 2D Rayleigh-Ritz step on (psi, p)
+      std::vector<std::unique_ptr<Mps>> pd(D);
+      bool cb4 = false;
+      for (int i = 0; i < D; ++i) {
+        bool cb = false;
+        auto pp = apply_s(c, *s[i], c.s_max * eta / 3.0, cap, &cb);
+        cb4 = cb4 || cb;
+        const double np = mnorm(*pp);
+        if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
+        pd[i] = mps_scaled_copy(c, *pp, 1.0 / np, nullptr);
+        s[i].reset();
+      }
+      const int n2 = 2 * D;
+      std::vector<double> B(size_t(n2) * n2, 0.0), M(size_t(n2) * n2, 0.0);
+      {
+        LowPrecision lp(c);  // the Ritz sandwiches may use the low-precision contractions
+        // <phi_j | H | p_k>, <p_i | H | p_k>
+        std::vector<double> hp(size_t(D) * D), op(size_t(D) * D);
+        for (int j = 0; j < D; ++j)
+          for (int k = 0; k < D; ++k) {
+            hp[size_t(j) * D + k] = expect_h(c, *phi[j], *pd[k]);
+            op[size_t(j) * D + k] = dot(c, *phi[j], *pd[k]);
+          }
+        for (int i = 0; i < D; ++i)
+          for (int k = i; k < D; ++k) {
+            B[size_t(D + i) * n2 + D + k] = B[size_t(D + k) * n2 + D + i] = expect_h(c, *pd[i], *pd[k]);
+            M[size_t(D + i) * n2 + D + k] = M[size_t(D + k) * n2 + D + i] = dot(c, *pd[i], *pd[k]);
+          }
+        for (int i = 0; i < D; ++i) {
+          B[size_t(i) * n2 + i] = lam[i];
+          M[size_t(i) * n2 + i] = 1.0;
+          for (int k = 0; k < D; ++k) {
+            double bh = 0.0, bo = 0.0;
+            for (int j = 0; j < D; ++j) {
+              bh += Cm[size_t(j) * D + i] * hp[size_t(j) * D + k];
+              bo += Cm[size_t(j) * D + i] * op[size_t(j) * D + k];
+            }
+            B[size_t(i) * n2 + D + k] = B[size_t(D + k) * n2 + i] = bh;
+            M[size_t(i) * n2 + D + k] = M[size_t(D + k) * n2 + i] = bo;
+          }
+        }
+      }
+      std::vector<double> lam_s, W;
+      small_pencil(n2, B, M, D, lam_s, W);
+      // 7. truncation tolerance: the smallest of the per-column tolerances
+      double eta_in = std::numeric_limits<double>::infinity();
+      for (int i = 0; i < D; ++i) {
+        const double q = std::sqrt(lam_s[i] / (lam_s[i] + p.t_eig * (lam[i] - lam_s[i])));
+        eta_in = std::min(eta_in, delta_a(rho[i], q) * std::sqrt(lam_s[i]) / std::sqrt(1.0 + p.c));
+      }
+      const double eta_psi = eta_in * c.s_min;
+      // new column i = sum_j (C W1)_ji phi_j + sum_k W2_ki p_k, truncated
+      std::vector<const Mps*> terms(n2);
+      for (int j = 0; j < D; ++j) {
+        terms[j] = phi[j].get();
+        terms[D + j] = pd[j].get();
+      }
+      std::vector<std::unique_ptr<Mps>> next(D);
+      bool cb5 = false;
+      int mr = 0;
+      for (int i = 0; i < D; ++i) {
+        std::vector<double> a(n2, 0.0);
+        for (int j = 0; j < D; ++j) {
+          double v = 0.0;
+          for (int l = 0; l < D; ++l) v += Cm[size_t(j) * D + l] * W[size_t(l) * D + i];
+          a[j] = v;
+          a[D + j] = W[size_t(D + j) * D + i];
+        }
+        auto comb = combine(terms, a);
+        bool cb = false;
+        next[i] = round_mps(c, *comb, eta_psi, cap, &cb);
+        cb5 = cb5 || cb;
+        mr = std::max(mr, next[i]->max_rank());
+      }
+      for (int i = 0; i < D; ++i) {
+        phi[i] = std::move(next[i]);
+        psi[i].reset();
+      }
+      c.sync();
+      for (int i = 0; i < D; ++i) rec.lambda_star[i] = lam_s[i];
+      rec.eta_psi = eta_psi;
+      rec.cap_bound |= (cb4 || cb5) ? 1 : 0;
+      rec.max_rank = mr;
+      rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (hist && rows < hist_cap) hist[rows] = rec;
+      ++rows;
+      s_prev2 = s_prev;
+      s_prev = *std::max_element(ns.begin(), ns.end());
+      res->s_last = s_prev;
+      res->s_prev = s_prev2;
+    }
+    res->iterations = rows;
+    if (psi_out)
+      for (int i = 0; i < D; ++i) psi_out[i] = put(c, std::move(phi[i]));
   });
 }
 

@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_batch",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_batch",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -55,6 +55,17 @@ class OuterIter(C.Structure):
                 ("energy", C.c_double), ("rho", C.c_double), ("rel_bound", C.c_double),
                 ("trunc_eps", C.c_double), ("inner_iterations", C.c_int), ("cap_bound", C.c_int),
                 ("max_rank", C.c_int), ("stopped", C.c_int)]
+
+
+SUBSPACE_MAX_D = 8
+
+
+class SubspaceIter(C.Structure):
+    _fields_ = [("lambda_", C.c_double * SUBSPACE_MAX_D), ("energy", C.c_double * SUBSPACE_MAX_D),
+                ("rho", C.c_double * SUBSPACE_MAX_D), ("s_norm", C.c_double * SUBSPACE_MAX_D),
+                ("lambda_star", C.c_double * SUBSPACE_MAX_D), ("bound", C.c_double),
+                ("eta_res", C.c_double), ("eta_psi", C.c_double), ("seconds", C.c_double),
+                ("retries", C.c_int), ("cap_bound", C.c_int), ("max_rank", C.c_int), ("stopped", C.c_int)]
 
 
 class Result(C.Structure):
@@ -97,6 +108,8 @@ def lib():
                              C.POINTER(Iter), C.c_int, ip]
         L.pv_run_outer.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, C.c_double, C.c_int,
                                    C.POINTER(Result), C.POINTER(OuterIter), C.c_int, ip]
+        L.pv_run_subspace.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, ip, C.POINTER(Result),
+                                      C.POINTER(SubspaceIter), C.c_int, ip]
         L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
@@ -310,6 +323,29 @@ class Context:
                      max_rank=h.max_rank, stop=bool(h.stopped)) for h in hist[:res.iterations]]
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, steps=res.iterations,
                     converged=bool(res.converged)), rows, psi.value
+
+    def run_subspace(self, D, starts=None, **kw):
+        """Algorithm 4 (pv_run_subspace) on D columns; keyword arguments as in run.  Returns
+        (result dict of column 1, rows, handles of the D final columns)."""
+        if not 1 <= D <= SUBSPACE_MAX_D:
+            raise ValueError(f"D must be in 1..{SUBSPACE_MAX_D}")
+        kw.setdefault("max_iter", 20)
+        n = max(kw["max_iter"], 1)
+        prm = make_params(**kw)
+        res = Result()
+        hist = (SubspaceIter * n)()
+        out = (C.c_int * D)()
+        st = None if starts is None else (C.c_int * D)(*[int(s) for s in starts])
+        _check(lib().pv_run_subspace(self._p, C.byref(prm), int(D), st, C.byref(res), hist, n, out))
+        rows = []
+        for h in hist[:res.iterations]:
+            rows.append(dict(lam=np.array(h.lambda_[:D]), E=np.array(h.energy[:D]), rho=np.array(h.rho[:D]),
+                             s_norm=np.array(h.s_norm[:D]), lam_star=np.array(h.lambda_star[:D]),
+                             bound=h.bound, eta=h.eta_res, eta_psi=h.eta_psi, seconds=h.seconds,
+                             retries=h.retries, cap_bound=bool(h.cap_bound), max_rank=h.max_rank,
+                             stop=bool(h.stopped)))
+        return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
+                    iterations=res.iterations, converged=bool(res.converged)), rows, list(out)
 
     def sym_eig(self, A, method, nvec=None):
         A = _f64(np.asfortranarray(A))
