@@ -192,6 +192,41 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"in {dt:.2f} s (L=48 is beyond a dense 2^L vector)"}
 
 
+def subspace_bench(a):
+    """Algorithm 4 on D columns (pv_run_subspace): decayed integrals (seed 0) at the given
+    L, N, rank cap and m_zip, simultaneous truncation.  `warmup` iterations from the D
+    starting determinants, then `steps` timed iterations from the columns they leave (the
+    first timed iteration repeats the trial pass that starts eta_res)."""
+    from paper_2604_16118_amd import native
+    from synth import make_problem
+
+    D = a.subspace
+    p = make_problem("decayed", a.L, a.N, 0)
+    ctx = native.Context(0)
+    ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
+    common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
+    ctx.set_timed_classes(LIVE_CLASSES)
+    _, hw, cols = ctx.run_subspace(D, max_iter=a.warmup, **common)
+    print(f"# subspace D={D}: warmup {a.warmup} it, ranks {[r['max_rank'] for r in hw]}", file=sys.stderr, flush=True)
+    ctx.timers_reset()
+    t0 = time.perf_counter()
+    res, hist, cols2 = ctx.run_subspace(D, starts=cols, max_iter=a.steps, **common)
+    t1 = time.perf_counter()
+    for h in cols + cols2:
+        ctx.mps_free(h)
+    ctx.close()
+    out = {"metric": f"subspace PINVIT (Alg. 4) iterations/s, D={D} columns", "value": len(hist) / (t1 - t0),
+           "unit": "iter/s", "n_gpus": 1, "steps": len(hist), "warmup": a.warmup,
+           "ms_per_step": 1e3 * (t1 - t0) / max(len(hist), 1), "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"Algorithm 4, D={D}, decayed integrals L={a.L} N={a.N} seed 0, rank cap "
+                                  f"{a.cap}, m_zip {a.m_zip}, simultaneous truncation", "L": a.L, "N": a.N,
+                      "D": D, "rank_cap": a.cap, "m_zip": a.m_zip},
+           "energies": [float(x) for x in hist[-1]["E"]] if hist else [],
+           "max_rank": max([r["max_rank"] for r in hist] + [0])}
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(a):
     """Many independent Hamiltonians at once: problem b draws L from {12, 16, ..., 32} and a
     rank cap from [32, 256] with a generator seeded by b (N = L/2, decayed integrals with
@@ -253,6 +288,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
     ap.add_argument("--batch", type=int, default=0, metavar="B",
                     help="instead of the L=48 run: B independent Hamiltonians, sequential vs pv_run_batch")
+    ap.add_argument("--subspace", type=int, default=0, metavar="D",
+                    help="instead of the L=48 run: Algorithm 4 on D columns at --L/--N/--cap/--m-zip")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
     ap.add_argument("--pmc-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV", "BENCH_JSON"),
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
@@ -270,6 +307,9 @@ def main():
         sys.exit(2)
     if a.batch > 0:
         batch_bench(a)
+        return
+    if a.subspace > 0:
+        subspace_bench(a)
         return
 
     from paper_2604_16118_amd import native
