@@ -22,6 +22,9 @@ Everything here is plain float64 NumPy on full occupation-number vectors of leng
                  psi = S x; Algorithm 3 (outer iteration) on top of it.
 * ``subspace`` -- Algorithm 4 (perturbed inverse subspace iteration, Section 6) on D
                  columns kept as separate vectors.
+* ``zform``   -- Algorithm 2 on the paper's own variable x: products with A and E summed
+                 term by term (eq. exactrq), the residual as the sorted sum of its
+                 M^2 terms (Lemma truncr).
 * ``mps``     -- contraction of an exported block-sparse MPS to its dense vector
                  (eq. mps with the block structure of eq. blockstructure).
 
