@@ -214,6 +214,20 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
 pv_status pv_run_outer(pv_ctx* ctx, const pv_params* prm, double alpha, double tol, int max_outer,
                        pv_result* res, pv_outer_iter* hist, int hist_cap, int* psi);
 
+/* Algorithm 2 on the paper's own variable x (the "z-form"), for checking the psi-form of
+ * pv_run on small problems.  The products with A = S H_gamma S and E = S^2 are summed term
+ * by term over the pairs of rank-one terms S_k of S (eq. exactrq); the residual is the sorted
+ * sequential truncated sum of its (M^+ - M^- + 1)^2 terms S_k (H_gamma - lambda) S_k' x,
+ * each formed exactly (Lemma truncr and the recipe after it), and eta_res starts from their
+ * norms (eq. startetar); x is normalised in the A-norm; the Ritz step uses {x, r/||r||};
+ * the update x <- trunc_{eta_in}(x_*) truncates x itself.  Each H application is exact up to
+ * m_zip (<= 0: exact) and numerically zero singular values, so the sizes are limited by the
+ * eigensolver (n <= 1024 per sector Gram): L up to about 10 at small ranks.  hist rows use
+ * pv_iter with s_norm = r_norm = ||res_eta(x)|| and eta_psi = eta_in; x (NULL or one int)
+ * receives a handle of the final iterate (in the variable x).  Errors as pv_run. */
+pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, pv_iter* hist,
+                       int hist_cap, int* x);
+
 /* Algorithm 4 (perturbed inverse subspace iteration, Section 6) on D columns, 1 <= D <=
  * PV_SUBSPACE_MAX_D, in the physical variable psi = S x like pv_run.  The columns are kept
  * as D block-sparse MPS rather than one joint MPS with an index core (Section 6.2): the

@@ -830,6 +830,187 @@ pv_status pv_cholesky(pv_ctx* ctx, int n, const double* A, double* W) {
   });
 }
 
+// Algorithm 2 on x (z-form): term-by-term products with A and E and the sorted sum of the
+// M^2 residual terms; see the header.
+pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, pv_iter* hist,
+                       int hist_cap, int* x_out) {
+  return guard([&] {
+    if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    const pv_params p = *prm;
+    if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
+        !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
+      fail(PV_EINVAL, "invalid parameters");
+    if (p.precision != 0) fail(PV_EINVAL, "the z-form runs in float64 only");
+    if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
+    c.prec = 0;
+    c.trunc_mode = p.truncation;
+    auto mnorm = [&](const Mps& m) { return c.trunc_mode == 0 ? norm_canonical(c, m) : norm2(c, m); };
+    setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
+    const int L = c.L, N = c.N, cap = p.rank_cap, M = int(c.alpha.size());
+    const int exact_cap = 1 << 30;
+    std::vector<std::vector<double>> occ(M, std::vector<double>(L));
+    for (int m = 0; m < M; ++m)
+      for (int k = 0; k < L; ++k) occ[m][k] = std::exp(-c.beta[m] * c.theta[k]);
+    auto term = [&](const Mps& x, int m) { return mps_scaled_copy(c, x, c.alpha[m], occ[m].data()); };
+    // <a, A b> and <a, E b>, summed over all pairs (k, k')
+    auto products = [&](const Mps& a, const Mps& b, double* ha, double* ea) {
+      std::vector<std::unique_ptr<Mps>> sa(M), sb(M);
+      for (int m = 0; m < M; ++m) {
+        sa[m] = term(a, m);
+        sb[m] = term(b, m);
+      }
+      double h = 0.0, e = 0.0;
+      for (int k = 0; k < M; ++k)
+        for (int k2 = 0; k2 < M; ++k2) {
+          h += expect_h(c, *sa[k], *sb[k2]);
+          e += dot(c, *sa[k], *sb[k2]);
+        }
+      *ha = h;
+      *ea = e;
+    };
+    const double eps_num = p.eps_num > 0 ? p.eps_num : 0.5 * (1.0 - p.c);
+    const double zeta = eps_num / (1.0 + p.c);
+    double eta = std::numeric_limits<double>::infinity();
+    std::unique_ptr<Mps> x;
+    if (start >= 0) {
+      x = mps_scaled_copy(c, get(c, start), 1.0, nullptr);
+    } else {
+      std::vector<int> idx(L);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c.h[size_t(a) * L + a] < c.h[size_t(b) * L + b]; });
+      x = mps_determinant(c, std::vector<int>(idx.begin(), idx.begin() + N));
+    }
+    struct Term {
+      double norm;
+      int k, k2;
+      std::unique_ptr<Mps> s;
+    };
+    int rows = 0;
+    *res = pv_result{};
+    for (int it = 0; it < p.max_iter; ++it) {
+      const auto t0 = std::chrono::steady_clock::now();
+      double num, den;
+      products(*x, *x, &num, &den);
+      if (!(num > 0 && den > 0)) fail(PV_ENOTSPD, "iterate has no positive A-norm");
+      const double lam = num / den;
+      x = mps_scaled_copy(c, *x, 1.0 / std::sqrt(num), nullptr);
+      // residual terms S_k (H - lambda) S_k' x, exact
+      std::vector<Term> terms;
+      double est = 0.0;
+      for (int k2 = 0; k2 < M; ++k2) {
+        auto u = term(*x, k2);
+        auto hu = apply_h(c, *u, 0.0, exact_cap, p.m_zip, nullptr);
+        auto g = mps_lincomb(c, 1.0, *hu, -lam, *u);
+        for (int k = 0; k < M; ++k) {
+          auto s = term(*g, k);
+          const double n = std::sqrt(std::max(dot(c, *s, *s), 0.0));
+          est += n;
+          terms.push_back(Term{n, k, k2, std::move(s)});
+        }
+      }
+      std::sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
+        if (a.norm != b.norm) return a.norm < b.norm;
+        if (a.k != b.k) return a.k < b.k;
+        return a.k2 < b.k2;
+      });
+      eta = std::min(2.0 * eta, 0.8 * zeta * est);
+      int retries = 0;
+      bool capb = false;
+      std::unique_ptr<Mps> r;
+      double nr = 0.0;
+      while (true) {
+        capb = false;
+        double csum = 0.0;
+        size_t j0 = 0;
+        for (size_t j = 0; j < terms.size(); ++j) {
+          if (csum + terms[j].norm <= eta / 3.0) { csum += terms[j].norm; j0 = j + 1; }
+          else break;
+        }
+        double total = 0.0;
+        for (size_t j = j0; j < terms.size(); ++j) total += terms[j].norm;
+        std::unique_ptr<Mps> y;
+        for (size_t j = j0; j < terms.size(); ++j) {
+          const double eps_j = total > 0 ? eta * terms[j].norm / (3.0 * total) : 0.0;
+          bool cb = false;
+          if (!y) y = round_mps(c, *terms[j].s, eps_j, cap, &cb);
+          else {
+            auto sum = mps_lincomb(c, 1.0, *y, 1.0, *terms[j].s);
+            y = round_mps(c, *sum, eps_j, cap, &cb);
+          }
+          capb = capb || cb;
+        }
+        if (y) {
+          bool cb = false;
+          r = round_mps(c, *y, eta / 3.0, cap, &cb);
+          capb = capb || cb;
+          nr = mnorm(*r);
+        } else {
+          r = mps_scaled_copy(c, *x, 0.0, nullptr);
+          nr = 0.0;
+        }
+        if (nr >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries) break;
+        eta *= 0.8;
+        ++retries;
+      }
+      terms.clear();
+      const double rho = (nr + eta) / std::sqrt(1.0 - p.c);
+      const double bound = error_bound(rho, p.delta);
+      pv_iter rec{};
+      rec.lambda = lam;
+      rec.energy = lam - c.gamma;
+      rec.rho = rho;
+      rec.bound = bound;
+      rec.r_norm = nr;
+      rec.s_norm = nr;
+      rec.eta_res = eta;
+      rec.retries = retries;
+      rec.cap_bound = capb ? 1 : 0;
+      res->energy = rec.energy;
+      res->lambda = lam;
+      res->rho = rho;
+      res->bound = bound;
+      res->eta_res = eta;
+      if (bound <= p.tau) {
+        rec.stopped = 1;
+        rec.max_rank = x->max_rank();
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        break;
+      }
+      if (!(nr > 0)) fail(PV_ENOCONV, "residual vanished before the tolerance test succeeded");
+      auto rh = mps_scaled_copy(c, *r, 1.0 / nr, nullptr);
+      r.reset();
+      double h01, e01, h11, e11;
+      products(*x, *rh, &h01, &e01);
+      products(*rh, *rh, &h11, &e11);
+      // x has unit A-norm: <x, A x> = 1 and <x, E x> = den / num
+      const double hm[3] = {1.0, h01, h11}, mm[3] = {den / num, e01, e11};
+      double lam_s, z[2];
+      ritz2(hm, mm, &lam_s, z);
+      const double q = std::sqrt(lam_s / (lam_s + p.t_eig * (lam - lam_s)));
+      const double eta_in = delta_a(rho, q) * std::sqrt(lam_s) / std::sqrt(1.0 + p.c);
+      auto comb = mps_lincomb(c, z[0], *x, z[1], *rh);
+      bool cb5 = false;
+      x = round_mps(c, *comb, eta_in, cap, &cb5);
+      c.sync();
+      rec.lambda_star = lam_s;
+      rec.eta_psi = eta_in;
+      rec.cap_bound |= cb5 ? 1 : 0;
+      rec.max_rank = x->max_rank();
+      rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (hist && rows < hist_cap) hist[rows] = rec;
+      ++rows;
+    }
+    res->iterations = rows;
+    if (x_out) *x_out = put(c, std::move(x));
+  });
+}
+
 // Algorithm 4 (subspace iteration, Section 6) on D separate columns; see the header for the
 // readings.  Phi holds the columns as stored; the Rayleigh-Ritz coefficients C of an
 // iteration give the E-orthonormal basis psi_i = sum_j C_ji phi_j, formed exactly (MPS

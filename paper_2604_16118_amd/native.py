@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_batch",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_zform", "pv_run_batch",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -108,6 +108,8 @@ def lib():
                              C.POINTER(Iter), C.c_int, ip]
         L.pv_run_outer.argtypes = [C.c_void_p, C.POINTER(Params), C.c_double, C.c_double, C.c_int,
                                    C.POINTER(Result), C.POINTER(OuterIter), C.c_int, ip]
+        L.pv_run_zform.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.POINTER(Result),
+                                   C.POINTER(Iter), C.c_int, ip]
         L.pv_run_subspace.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, ip, C.POINTER(Result),
                                       C.POINTER(SubspaceIter), C.c_int, ip]
         L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
@@ -323,6 +325,23 @@ class Context:
                      max_rank=h.max_rank, stop=bool(h.stopped)) for h in hist[:res.iterations]]
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, steps=res.iterations,
                     converged=bool(res.converged)), rows, psi.value
+
+    def run_zform(self, start=-1, **kw):
+        """Algorithm 2 on the variable x (pv_run_zform); keyword arguments as in run.  Returns
+        (result dict, rows, handle of the final iterate)."""
+        kw.setdefault("max_iter", 20)
+        n = max(kw["max_iter"], 1)
+        prm = make_params(**kw)
+        res = Result()
+        hist = (Iter * n)()
+        x = C.c_int()
+        _check(lib().pv_run_zform(self._p, C.byref(prm), int(start), C.byref(res), hist, n, C.byref(x)))
+        rows = [dict(lam=r.lambda_, E=r.energy, rho=r.rho, bound=r.bound, r_norm=r.r_norm, eta=r.eta_res,
+                     lam_star=r.lambda_star, eta_in=r.eta_psi, seconds=r.seconds, retries=r.retries,
+                     cap_bound=bool(r.cap_bound), max_rank=r.max_rank, stop=bool(r.stopped))
+                for r in hist[:res.iterations]]
+        return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
+                    iterations=res.iterations, converged=bool(res.converged)), rows, x.value
 
     def run_subspace(self, D, starts=None, **kw):
         """Algorithm 4 (pv_run_subspace) on D columns; keyword arguments as in run.  Returns
