@@ -192,6 +192,41 @@ def cpu_baseline(target_seconds: float = 15.0):
                       f"in {dt:.2f} s (L=48 is beyond a dense 2^L vector)"}
 
 
+def zform_bench(a):
+    """The deviation of the psi-form from the paper's z-form: pv_run and pv_run_zform from the
+    same determinant on decayed integrals (seed 0) at --L/--N/--cap/--m-zip, `steps`
+    iterations each, sequential truncation, default tolerances.  Reports both energy
+    sequences, the largest per-iteration difference, the ranks and the iteration rates."""
+    from paper_2604_16118_amd import native
+    from synth import make_problem
+
+    p = make_problem("decayed", a.L, a.N, 0)
+    ctx = native.Context(0)
+    ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
+    kw = dict(rank_cap=a.cap, max_iter=a.steps, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=0)
+    ctx.set_timed_classes(LIVE_CLASSES)
+    t0 = time.perf_counter()
+    _, hz, x = ctx.run_zform(**kw)
+    t1 = time.perf_counter()
+    _, hp, psi = ctx.run(**kw)
+    t2 = time.perf_counter()
+    ctx.mps_free(x)
+    ctx.mps_free(psi)
+    ctx.close()
+    n = min(len(hz), len(hp))
+    out = {"metric": "z-form PINVIT iterations/s and its energy deviation from the psi-form", "value": len(hz) / (t1 - t0),
+           "unit": "iter/s", "n_gpus": 1, "steps": len(hz), "warmup": 0, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"Algorithm 2 on x (term-by-term products, sorted residual terms) against psi = S x, "
+                                  f"decayed integrals L={a.L} N={a.N} seed 0, rank cap {a.cap}, m_zip {a.m_zip}",
+                      "L": a.L, "N": a.N, "rank_cap": a.cap, "m_zip": a.m_zip},
+           "psi_form_iter_per_s": len(hp) / (t2 - t1),
+           "energies_z": [r["E"] for r in hz], "energies_psi": [r["E"] for r in hp],
+           "max_abs_dE": max([abs(hz[i]["E"] - hp[i]["E"]) for i in range(n)] + [0.0]),
+           "max_rank_z": [r["max_rank"] for r in hz], "max_rank_psi": [r["max_rank"] for r in hp]}
+    print(json.dumps(out), flush=True)
+
+
 def subspace_bench(a):
     """Algorithm 4 on D columns (pv_run_subspace): decayed integrals (seed 0) at the given
     L, N, rank cap and m_zip, simultaneous truncation.  `warmup` iterations from the D
@@ -288,6 +323,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
     ap.add_argument("--batch", type=int, default=0, metavar="B",
                     help="instead of the L=48 run: B independent Hamiltonians, sequential vs pv_run_batch")
+    ap.add_argument("--zform", action="store_true",
+                    help="instead of the L=48 run: z-form against psi-form at --L/--N/--cap/--m-zip")
     ap.add_argument("--subspace", type=int, default=0, metavar="D",
                     help="instead of the L=48 run: Algorithm 4 on D columns at --L/--N/--cap/--m-zip")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
@@ -310,6 +347,9 @@ def main():
         return
     if a.subspace > 0:
         subspace_bench(a)
+        return
+    if a.zform:
+        zform_bench(a)
         return
 
     from paper_2604_16118_amd import native
