@@ -310,11 +310,15 @@ void pv_destroy(pv_ctx* ctx) {
   try {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.side_stream) (void)hipStreamSynchronize(ctx->c.side_stream);
     for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
     for (auto& p : ctx->c.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
-    hipStream_t s = ctx->c.stream;
+    if (ctx->c.fork_event) (void)hipEventDestroy(ctx->c.fork_event);
+    if (ctx->c.join_event) (void)hipEventDestroy(ctx->c.join_event);
+    hipStream_t s = ctx->c.stream, s2 = ctx->c.side_stream;
     delete ctx;
     if (s) (void)hipStreamDestroy(s);
+    if (s2) (void)hipStreamDestroy(s2);
   } catch (...) {
   }
 }
@@ -777,8 +781,11 @@ pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_
       pool.emplace_back([&] {
         for (int i; (i = next.fetch_add(1)) < count;) {
           const int dev = ctxs[i]->c.device;
+          // one stream per problem: with many contexts a second stream each measured slower
+          ctxs[i]->c.use_side = false;
           st[i] = hipSetDevice(dev) == hipSuccess ? pv_run(ctxs[i], &prm[i], -1, &res[i], nullptr, 0, nullptr)
                                                   : PV_EDEVICE;
+          ctxs[i]->c.use_side = true;
           if (st[i] != PV_OK) msg[i] = pv_last_error();
         }
       });

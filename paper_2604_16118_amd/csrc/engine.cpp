@@ -47,14 +47,24 @@ void* Pool::get(size_t bytes) {
 void Pool::put(void* p, size_t bytes) {
   if (!p) return;
   const size_t cls = size_class(bytes);
-  free_.emplace(cls, p);
   in_use_ -= cls;
   cached_ += cls;
+  if (holding_) held_.emplace_back(cls, p);
+  else free_.emplace(cls, p);
+}
+
+void Pool::hold(bool on) {
+  holding_ = on;
+  if (on) return;
+  for (auto& kv : held_) free_.emplace(kv.first, kv.second);
+  held_.clear();
 }
 
 void Pool::release() {
   for (auto& kv : free_) (void)hipFree(kv.second);
+  for (auto& kv : held_) (void)hipFree(kv.second);
   free_.clear();
+  held_.clear();
   cached_ = 0;
 }
 
@@ -122,7 +132,31 @@ void Ctx::end(int cls, hipEvent_t a, double flops, double bytes) {
   pending.push_back({cls, a, b, flops, bytes});
 }
 
+void Ctx::fork() {
+  if (!side_stream) {
+    PV_HIP(hipStreamCreate(&side_stream));
+    PV_HIP(hipEventCreateWithFlags(&fork_event, hipEventDisableTiming));
+    PV_HIP(hipEventCreateWithFlags(&join_event, hipEventDisableTiming));
+  }
+  main_stream = stream;
+  PV_HIP(hipEventRecord(fork_event, main_stream));
+  PV_HIP(hipStreamWaitEvent(side_stream, fork_event, 0));
+  pool.hold(true);
+  stream = side_stream;
+}
+
+void Ctx::unfork() { stream = main_stream; }
+
+void Ctx::join() {
+  stream = main_stream;
+  PV_HIP(hipEventRecord(join_event, side_stream));
+  PV_HIP(hipStreamWaitEvent(main_stream, join_event, 0));
+  pool.hold(false);
+}
+
 void Ctx::sync() {
+  if (side_stream) PV_HIP(hipStreamSynchronize(side_stream));
+  if (main_stream && main_stream != stream) PV_HIP(hipStreamSynchronize(main_stream));
   PV_HIP(hipStreamSynchronize(stream));
   for (auto& p : pending) {
     float ms = 0.f;
@@ -1530,8 +1564,28 @@ BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax, 
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
   const int L = x.L, N = x.N;
   const double delta = L > 1 ? eps / double(L - 1) : eps;
-  BondGrams GL = left_grams(c, x);
+  // the right Grams (a chain over k = L..2) run on the side stream beside the left Grams
+  // (k = 1..L-1) and their Cholesky factorisations
+  struct SideChain {
+    Ctx& c;
+    bool joined;
+    explicit SideChain(Ctx& cx) : c(cx), joined(!cx.use_side) {
+      if (!joined) c.fork();
+    }
+    void unfork() {
+      if (!joined) c.unfork();
+    }
+    void join() {
+      if (!joined) c.join();
+      joined = true;
+    }
+    ~SideChain() {
+      if (!joined) try { c.join(); } catch (...) {}
+    }
+  } side(c);
   BondGrams GR = right_grams(c, x);
+  side.unfork();
+  BondGrams GL = left_grams(c, x);
   // W W^T = G^L (+ kCholShift max diag) by a blocked Cholesky factorisation; offsets of the
   // r x r blocks of every bond and sector
   BondEig EL;
@@ -1552,6 +1606,7 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
         if (EL.voff[k][n] >= 0) jobs.push_back(CholJob{GL.buf.p + GL.off[k][n], x.rho[k][n], W.p + EL.voff[k][n]});
     chol_all(c, jobs);
   }
+  side.join();
   // B = W^T G^R W for every bond and sector
   Buf Tm(c.pool, EL.V.n), Bm(c.pool, EL.V.n);
   {

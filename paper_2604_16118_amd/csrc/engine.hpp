@@ -32,18 +32,23 @@ struct Error : std::runtime_error {
   } while (0)
 
 // Caching device allocator.  Sizes are rounded to 1/8 of their power-of-two class so
-// buffers are reused across iterations; release is stream ordered because every
-// kernel of a context runs on its single stream.
+// buffers are reused across iterations; release is stream ordered because the kernels of a
+// context run on its main stream.  While a side stream runs beside it (Ctx::fork .. join)
+// released blocks are held back until the join, after which every later launch is ordered
+// behind the work of both streams.
 class Pool {
  public:
   ~Pool();
   void* get(size_t bytes);
   void put(void* p, size_t bytes);
   void release();
+  void hold(bool on);  // on: keep released blocks aside; off: make them reusable
   size_t in_use() const { return in_use_; }
   size_t cached() const { return cached_; }
  private:
   std::multimap<size_t, void*> free_;
+  std::vector<std::pair<size_t, void*>> held_;
+  bool holding_ = false;
   size_t in_use_ = 0, cached_ = 0;
 };
 
@@ -157,6 +162,16 @@ struct Ctx {
   // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
   //    intermediate-rank H application.
   int trunc_mode = 0;
+
+  // side stream for an independent chain of launches: fork() orders it behind the main
+  // stream's work so far and redirects `stream` to it; unfork() restores the main stream;
+  // join() orders the main stream behind the side stream's work
+  hipStream_t main_stream = nullptr, side_stream = nullptr;
+  bool use_side = true;  // off while many contexts share the device (pv_run_batch)
+  hipEvent_t fork_event = nullptr, join_event = nullptr;
+  void fork();
+  void unfork();
+  void join();
 
   void sync();
   hipEvent_t event();
