@@ -501,8 +501,7 @@ __device__ inline void sturm_counts(const double* d, const double* e2, int n, co
     if (fabs(q[p]) < tiny) q[p] = -tiny;
     cnt[p] = q[p] < 0.0;
   }
-  for (int i = 1; i < n; ++i) {
-    const double di = d[i], ei = e2[i - 1];
+  auto step = [&](double di, double ei) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       double r = __builtin_amdgcn_rcp(q[p]);
@@ -512,7 +511,18 @@ __device__ inline void sturm_counts(const double* d, const double* e2, int n, co
       if (fabs(q[p]) < tiny) q[p] = -tiny;
       cnt[p] += q[p] < 0.0;
     }
+  };
+  // the LDS operands of four steps are read before the first of them is used
+  int i = 1;
+  for (; i + 4 <= n; i += 4) {
+    const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+    step(d0, f0);
+    step(d1, f1);
+    step(d2, f2);
+    step(d3, f3);
   }
+  for (; i < n; ++i) step(d[i], e2[i - 1]);
 }
 
 // Solve (T - sigma I) x = b in place for one thread: LU with partial pivoting of the
