@@ -532,10 +532,7 @@ __device__ inline void sturm_counts(const double* d, const double* e2, int n, co
 __device__ void tri_factor(const double* d, const double* e, int n, double sigma, double tiny,
                            gdouble* u, gdouble* v, gdouble* w, gdouble* mult, gdouble* piv, int64_t ld) {
   double cd = d[0] - sigma, cs1 = n > 1 ? e[0] : 0.0, cs2 = 0.0;
-  for (int i = 0; i < n - 1; ++i) {
-    const double sub = e[i];
-    const double a1 = d[i + 1] - sigma;
-    const double s1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+  auto step = [&](int i, double sub, double a1, double s1) {
     double ui, vi, wi;
     if (fabs(cd) >= fabs(sub)) {
       piv[i * ld] = 0.0;
@@ -557,7 +554,21 @@ __device__ void tri_factor(const double* d, const double* e, int n, double sigma
     u[i * ld] = 1.0 / (ui == 0.0 ? tiny : ui);
     v[i * ld] = vi;
     w[i * ld] = wi;
+  };
+  // the LDS operands of four steps are read before the first of them is used
+  int i = 0;
+  for (; i + 4 < n - 1; i += 4) {
+    double sb[4], a[4], s[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      sb[b] = e[i + b];
+      a[b] = d[i + b + 1] - sigma;
+      s[b] = e[i + b + 1];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) step(i + b, sb[b], a[b], s[b]);
   }
+  for (; i < n - 1; ++i) step(i, e[i], d[i + 1] - sigma, (i + 1 < n - 1) ? e[i + 1] : 0.0);
   u[(n - 1) * ld] = 1.0 / (cd == 0.0 ? tiny : cd);
   v[(n - 1) * ld] = 0.0;
   w[(n - 1) * ld] = 0.0;
