@@ -64,3 +64,23 @@ def test_context_creation_without_gpu_fails_cleanly():
     with pytest.raises(native.PvError) as e:
         native.Context(0)
     assert e.value.status == -3
+
+
+def test_drivers_reject_null_arguments_without_touching_a_device():
+    """The iteration drivers and the timing switch validate their pointers before any HIP
+    call: a null context is PV_EINVAL with a message, on a machine without a GPU too."""
+    import ctypes as C
+    L = native.lib()
+    prm = native.make_params(8, 2)
+    res = native.Result()
+    hist = (native.Iter * 2)()
+    shist = (native.SubspaceIter * 2)()
+    out = (C.c_int * 2)()
+    calls = [
+        lambda: L.pv_run_zform(None, C.byref(prm), -1, C.byref(res), hist, 2, out),
+        lambda: L.pv_run_subspace(None, C.byref(prm), 2, None, C.byref(res), shist, 2, out),
+        lambda: L.pv_set_timer_mask(None, 1),
+    ]
+    for call in calls:
+        assert call() == -1
+        assert L.pv_last_error()
