@@ -88,3 +88,21 @@ def test_subspace_rejects_bad_arguments(ctx):
             ctx.run_subspace(D, rank_cap=8, max_iter=2)
     with pytest.raises(native.PvError):
         ctx.run_subspace(2, rank_cap=8, max_iter=2, c=1.5)
+
+
+def test_subspace_continues_from_returned_columns(ctx):
+    # starting columns are copied, not consumed; a continuation keeps the Rayleigh quotients
+    # above the exact eigenvalues and goes on lowering the first one
+    p = make_problem("decayed", 8, 4, 5)
+    w = fock.lowest_eigs(p.h, p.v, 4, p.gamma, k=2)
+    ctx.set_hamiltonian(p.h, p.v, 4, p.gamma)
+    kw = dict(rank_cap=16, tau=1e-12, c=0.5, delta=10.0)
+    _, h1, cols = ctx.run_subspace(2, max_iter=3, **kw)
+    _, h2, cols2 = ctx.run_subspace(2, starts=cols, max_iter=3, **kw)
+    assert h2[-1]["lam"][0] < h1[0]["lam"][0]
+    for r in h1 + h2:
+        assert np.all(r["lam"] >= w - 1e-11 * np.abs(w))
+    for h in cols:  # still valid after the second run
+        assert ctx.dot(h, h) > 0
+    for h in cols + cols2:
+        ctx.mps_free(h)
