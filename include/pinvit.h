@@ -197,7 +197,10 @@ pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap
 
 /* Algorithm 2 from the determinant of the N smallest h_ii (ties: lower index), or from
  * the MPS `start` when start >= 0.  Writes up to hist_cap history rows; *psi (may be
- * NULL) receives a handle of the final iterate. */
+ * NULL) receives a handle of the final iterate.  The run stops (converged) when the
+ * eigenvector bound meets tau, or when the search direction S^2 r vanishes under the
+ * truncation tolerances (the iterate is then an eigenvector to those tolerances, as on a
+ * sector of dimension 2). */
 pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res,
                  pv_iter* hist, int hist_cap, int* psi);
 

@@ -19,6 +19,8 @@ One iteration (every step on full vectors, truncations by ``tt.truncate``):
 5. rho^n = (1-c)^{-1/2} (||s|| + eta)/||x||_A (eq. rhobound); stop when the bound of
    eq. everrbound is <= tau.
 6. p = S_sorted(s; s_max eta/3); 2x2 Ritz problem on {psi, p/||p||} (Rem. omegamin).
+   If p vanishes (the residual fell below the truncation tolerances, as happens on a
+   sector of dimension 2), psi is an eigenvector to those tolerances and the run stops.
 7. eta_in = Delta ||x_*||_A/sqrt(1+c) with Delta from sqrt(1-Delta^2) - rho Delta =
    sqrt(lam_*/(lam_* + t_eig (lambda - lam_*))) (Lemma on iterate truncation);
    psi <- trunc_{s_min eta_in}(v_1 psi + v_2 p/||p||).
@@ -110,6 +112,13 @@ def run(h, v, N, gamma, prm: Params, psi0=None):
             hist.append(rec)
             break
         npn = float(np.linalg.norm(p))
+        if npn == 0.0:
+            # the direction vanished under the truncation tolerances: psi is an eigenvector
+            # to those tolerances and the iteration stops (a reading for this degenerate case)
+            rec["stop"] = True
+            rec["direction_vanished"] = True
+            hist.append(rec)
+            break
         z2 = p / npn
         hz2 = fock.apply_h(h, v, z2, gamma)
         o12 = float(psi @ z2)

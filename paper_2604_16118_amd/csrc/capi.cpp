@@ -636,7 +636,18 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         break;
       }
       const double np = mnorm(*pdir);
-      if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
+      if (!(np > 0)) {
+        // the direction vanished under the truncation tolerances: psi is an eigenvector to
+        // those tolerances, the run stops (as on a sector of dimension 2)
+        rec.stopped = 1;
+        rec.max_rank = psi->max_rank();
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        break;
+      }
       auto z2 = mps_scaled_copy(c, *pdir, 1.0 / np, nullptr);
       pdir.reset();
       double h12, h22;
@@ -954,7 +965,7 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
           capb = capb || cb;
           nr = mnorm(*r);
         } else {
-          r = mps_scaled_copy(c, *x, 0.0, nullptr);
+          r = mps_zero_like(c, *x);
           nr = 0.0;
         }
         if (nr >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries) break;

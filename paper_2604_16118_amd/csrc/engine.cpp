@@ -1089,6 +1089,16 @@ std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ) {
   return m;
 }
 
+// The zero state in the layout of x: every core cleared, so that the norm read from the
+// last core (the norm of a left-orthogonal chain) is zero as well.
+std::unique_ptr<Mps> mps_zero_like(Ctx& c, const Mps& x) {
+  auto m = mps_alloc(c, x.L, x.N, x.rho);
+  CopyBatch zero;
+  for (int k = 1; k <= x.L; ++k) zero.add_fill(m->site[k - 1].p, m->site_size(k), 0.0);
+  zero.run(c);
+  return m;
+}
+
 std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale) {
   auto m = mps_alloc(c, x.L, x.N, x.rho);
   CopyBatch cb;
@@ -1939,8 +1949,7 @@ std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* ca
   }
   if (!y) {
     // every term dropped: S x is below the tolerance; return the zero state
-    y = mps_scaled_copy(c, x, 0.0, nullptr);
-    return y;
+    return mps_zero_like(c, x);
   }
   return round_mps(c, *y, eta / 3.0, cap, cap_bound);
 }

@@ -187,6 +187,7 @@ std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vect
 std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ);
 std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y);
 std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale);
+std::unique_ptr<Mps> mps_zero_like(Ctx& c, const Mps& x);
 std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op);
 double dot(Ctx& c, const Mps& a, const Mps& b);
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket);

@@ -1,0 +1,54 @@
+"""GPU Algorithm 2 against the oracle at the edges of the particle-number structure: one
+particle, one hole and the shortest chains, where most sectors of a bond are empty and
+blocks are 1 x 1.  Energies of every iteration within 1e-10 (relative), as in the main
+parity tests; with one particle the two-body part vanishes, so the run ends at the lowest
+eigenvalue of h + gamma."""
+import numpy as np
+import pytest
+
+from oracle import fock, pinvit
+from synth import make_problem
+
+pytestmark = pytest.mark.gpu
+
+native = pytest.importorskip("paper_2604_16118_amd.native")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def _compare(ctx, kind, L, N, seed, cap, iters, truncation=0):
+    p = make_problem(kind, L, N, seed)
+    w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=2)
+    delta = w[1] / (w[1] - w[0])
+    prm = pinvit.Params(cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta,
+                        truncation="parallel" if truncation else "sequential")
+    _, hist_o, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    _, hist_g, psi = ctx.run(rank_cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta, truncation=truncation)
+    ctx.mps_free(psi)
+    assert len(hist_g) == len(hist_o)
+    for a, b in zip(hist_g, hist_o):
+        assert abs(a["E"] - b["E"]) <= 1e-10 * abs(b["E"]), (a["E"], b["E"])
+        assert a["retries"] == b["retries"]
+        assert a["lam"] >= w[0] - 1e-12
+    return p, hist_g, w
+
+
+@pytest.mark.parametrize("L,N", [(2, 1), (3, 1), (3, 2), (6, 1), (6, 5)])
+@pytest.mark.parametrize("truncation", [0, 1])
+def test_edge_particle_numbers_match_oracle(ctx, L, N, truncation):
+    _compare(ctx, "dense", L, N, 3, 8, 6, truncation)
+
+
+def test_single_particle_reaches_lowest_orbital_energy(ctx):
+    p, hist, w = _compare(ctx, "decayed", 8, 1, 0, 8, 30)
+    e_h = np.linalg.eigvalsh(p.h)[0]
+    assert abs(hist[-1]["E"] - e_h) <= 1e-8 * max(1.0, abs(e_h))
