@@ -249,8 +249,12 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
  * h_aa - h_ii (ties: lower i, then lower a).  res describes column 1 (energy, lambda,
  * rho, bound); hist receives up to hist_cap rows; psi (NULL or D ints) receives handles of
  * the final columns (the Ritz basis of the last iteration when it stopped, else the last
- * truncated update).  PV_EINVAL for a D out of range or invalid parameters, PV_ESTATE
- * without a Hamiltonian, PV_ENOTSPD when a Gram or Ritz pencil is not positive definite. */
+ * truncated update).  The run also stops (converged) when every direction vanishes under
+ * the truncation tolerances (the columns then span an invariant subspace to those
+ * tolerances); PV_ENOCONV when only some vanish.  PV_EINVAL for a D out of range, a
+ * sector of dimension below 2D (the 2D Ritz vectors would be dependent) or invalid
+ * parameters, PV_ESTATE without a Hamiltonian, PV_ENOTSPD when a Gram or Ritz pencil is
+ * not positive definite. */
 pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* starts, pv_result* res,
                           pv_subspace_iter* hist, int hist_cap, int* psi);
 

@@ -24,7 +24,10 @@ One iteration:
 4. While min_i ||s_i|| < (1 + 1/zeta) eta (and no cap bound): eta <- 4/5 eta, redo 3.
 5. rho_i = (1-c)^{-1/2} (||s_i|| + eta)/||x_i||_A; the eigenvector bound of the first
    column decides termination (eq. everrbound).
-6. p_i = S_sorted(s_i; s_max eta/3).  Rayleigh-Ritz on the 2D vectors
+6. p_i = S_sorted(s_i; s_max eta/3); if every p_i vanished under the truncation
+   tolerances the columns span an invariant subspace to those tolerances and the
+   iteration stops (a reading for this degenerate case; a run where only some vanish is
+   rejected).  Rayleigh-Ritz on the 2D vectors
    (psi_1..psi_D, p_1/||p_1||..p_D/||p_D||): B W = M W Lambda_*, lowest D eigenvalues,
    W^T M W = I (the rescaling by the norms of eq. subspacerescale is the normalisation of
    the p_i; the psi_i are E-normalised already).
@@ -77,6 +80,8 @@ def run_subspace(h, v, N, gamma, prm: Params, D: int, X0=None):
     residual bounds), bound (first column), eta, retries, and after a Ritz step lam_star
     and eta_psi."""
     L = h.shape[0]
+    if 2 * D > math.comb(L, N):
+        raise ValueError("the 2D Ritz vectors need a sector of dimension at least 2D")
     pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper)
     mode = prm.truncation
 
@@ -138,10 +143,16 @@ def run_subspace(h, v, N, gamma, prm: Params, D: int, X0=None):
             hist.append(rec)
             return Psi, hist, pre
         # 6. Ritz step on (Psi, P / ||P||)
-        P = []
-        for i in range(D):
-            p, _, _, _ = precond.apply_sorted(pre, S[i], pre.s_max * eta / 3.0, prm.cap, N, mode)
-            P.append(p / np.linalg.norm(p))
+        P = [precond.apply_sorted(pre, S[i], pre.s_max * eta / 3.0, prm.cap, N, mode)[0] for i in range(D)]
+        npn = [float(np.linalg.norm(p)) for p in P]
+        if all(n == 0.0 for n in npn):
+            rec["stop"] = True
+            rec["direction_vanished"] = True
+            hist.append(rec)
+            return Psi, hist, pre
+        if any(n == 0.0 for n in npn):
+            raise RuntimeError("a search direction vanished while others did not")
+        P = [p / n for p, n in zip(P, npn)]
         Bas = np.concatenate([Psi, np.stack(P, axis=1)], axis=1)
         HBas = np.concatenate([HPsi, np.stack([fock.apply_h(h, v, p, gamma) for p in P], axis=1)], axis=1)
         B = Bas.T @ HBas

@@ -1040,6 +1040,12 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
     if (D < 1 || D > PV_SUBSPACE_MAX_D) fail(PV_EINVAL, "D out of range");
     Ctx& c = ctx->c;
     if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    {
+      // the 2D Ritz vectors are dependent in a sector of dimension below 2D
+      double dim = 1.0;
+      for (int i = 1; i <= c.N; ++i) dim = dim * double(c.L - c.N + i) / double(i);
+      if (2.0 * D > dim + 0.5) fail(PV_EINVAL, "the 2D Ritz vectors need a sector of dimension at least 2D");
+    }
     const pv_params p = *prm;
     if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
@@ -1173,16 +1179,34 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
       }
       // 6. directions p_i / ||p_i|| and the 2D x 2D Rayleigh-Ritz step on (psi, p)
       std::vector<std::unique_ptr<Mps>> pd(D);
+      std::vector<double> np(D);
       bool cb4 = false;
+      int vanished = 0;
       for (int i = 0; i < D; ++i) {
         bool cb = false;
-        auto pp = apply_s(c, *s[i], c.s_max * eta / 3.0, cap, &cb);
+        pd[i] = apply_s(c, *s[i], c.s_max * eta / 3.0, cap, &cb);
         cb4 = cb4 || cb;
-        const double np = mnorm(*pp);
-        if (!(np > 0)) fail(PV_ENOCONV, "search direction vanished");
-        pd[i] = mps_scaled_copy(c, *pp, 1.0 / np, nullptr);
+        np[i] = mnorm(*pd[i]);
+        vanished += !(np[i] > 0);
         s[i].reset();
       }
+      if (vanished == D) {
+        // every direction vanished under the truncation tolerances: the columns span an
+        // invariant subspace to those tolerances and the run stops
+        rec.stopped = 1;
+        int mr = 0;
+        for (int i = 0; i < D; ++i) mr = std::max(mr, psi[i]->max_rank());
+        rec.max_rank = mr;
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        for (int i = 0; i < D; ++i) phi[i] = std::move(psi[i]);
+        break;
+      }
+      if (vanished) fail(PV_ENOCONV, "a search direction vanished while others did not");
+      for (int i = 0; i < D; ++i) pd[i] = mps_scaled_copy(c, *pd[i], 1.0 / np[i], nullptr);
       const int n2 = 2 * D;
       std::vector<double> B(size_t(n2) * n2, 0.0), M(size_t(n2) * n2, 0.0);
       {

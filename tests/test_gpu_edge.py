@@ -2,11 +2,12 @@
 particle, one hole and the shortest chains, where most sectors of a bond are empty and
 blocks are 1 x 1.  Energies of every iteration within 1e-10 (relative), as in the main
 parity tests; with one particle the two-body part vanishes, so the run ends at the lowest
-eigenvalue of h + gamma."""
+eigenvalue of h + gamma.  Algorithm 4 on sectors of dimension 2D: one Ritz step spans the
+sector, the directions then vanish and the run stops; below 2D it is rejected."""
 import numpy as np
 import pytest
 
-from oracle import fock, pinvit
+from oracle import fock, pinvit, subspace
 from synth import make_problem
 
 pytestmark = pytest.mark.gpu
@@ -52,3 +53,31 @@ def test_single_particle_reaches_lowest_orbital_energy(ctx):
     p, hist, w = _compare(ctx, "decayed", 8, 1, 0, 8, 30)
     e_h = np.linalg.eigvalsh(p.h)[0]
     assert abs(hist[-1]["E"] - e_h) <= 1e-8 * max(1.0, abs(e_h))
+
+
+@pytest.mark.parametrize("L,N,D", [(2, 1, 1), (4, 1, 2), (4, 2, 3), (6, 5, 3)])
+@pytest.mark.parametrize("truncation", [0, 1])
+def test_subspace_on_a_sector_of_dimension_2d(ctx, L, N, D, truncation):
+    p = make_problem("dense", L, N, 3)
+    w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=D)
+    prm = pinvit.Params(cap=8, max_iter=6, tau=1e-12, c=0.5, delta=10.0,
+                        truncation="parallel" if truncation else "sequential")
+    _, hist_o, _ = subspace.run_subspace(p.h, p.v, N, p.gamma, prm, D)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    res, hist_g, handles = ctx.run_subspace(D, rank_cap=8, max_iter=6, tau=1e-12, c=0.5, delta=10.0,
+                                            truncation=truncation)
+    for h in handles:
+        ctx.mps_free(h)
+    assert res["converged"] and len(hist_g) == len(hist_o) == 2
+    assert hist_g[-1]["stop"]
+    for a, b in zip(hist_g, hist_o):
+        np.testing.assert_allclose(a["E"], b["E"], rtol=1e-10, atol=0)
+        assert a["retries"] == b["retries"]
+    np.testing.assert_allclose(hist_g[0]["lam_star"], w, rtol=1e-10, atol=0)
+
+
+def test_subspace_rejects_a_sector_below_2d(ctx):
+    p = make_problem("dense", 3, 1, 3)
+    ctx.set_hamiltonian(p.h, p.v, 1, p.gamma)
+    with pytest.raises(native.PvError, match="PV_EINVAL"):
+        ctx.run_subspace(2, rank_cap=8, max_iter=2)

@@ -1,6 +1,8 @@
 """Pins of the oracle's Algorithm 4 (subspace iteration, Section 6): against exact
 diagonalisation of the N-particle sector, the min-max property of Ritz values, the
 one-column case (Algorithm 2), and the starting determinants."""
+import math
+
 import numpy as np
 import pytest
 
@@ -68,3 +70,23 @@ def test_rank_cap_keeps_ritz_values_above_the_eigenvalues():
     _, hist, _ = subspace.run_subspace(p.h, p.v, 4, p.gamma, prm, 2)
     for rec in hist:
         assert np.all(rec["lam"] >= ed - 1e-11 * np.abs(ed))
+
+
+def test_sector_of_dimension_2d_is_solved_in_one_step():
+    # with 2D equal to the sector dimension the Ritz basis of the first step spans the
+    # sector: its Ritz values are the D lowest eigenvalues, and the next directions vanish
+    for L, N, D in [(4, 1, 2), (4, 2, 3), (6, 5, 3)]:
+        p = make_problem("dense", L, N, 3)
+        assert 2 * D == math.comb(L, N)
+        w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=D)
+        prm = pinvit.Params(cap=8, max_iter=8, tau=1e-12, c=0.5, delta=10.0)
+        _, hist, _ = subspace.run_subspace(p.h, p.v, N, p.gamma, prm, D)
+        assert len(hist) == 2 and hist[-1]["stop"] and hist[-1]["direction_vanished"]
+        assert np.allclose(hist[0]["lam_star"], w, rtol=1e-12, atol=0)
+        assert np.allclose(hist[-1]["lam"], w, rtol=1e-12, atol=0)
+
+
+def test_sector_below_2d_is_rejected():
+    p = make_problem("dense", 3, 1, 3)
+    with pytest.raises(ValueError):
+        subspace.run_subspace(p.h, p.v, 1, p.gamma, pinvit.Params(cap=8, max_iter=2), 2)
