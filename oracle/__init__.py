@@ -25,6 +25,9 @@ Everything here is plain float64 NumPy on full occupation-number vectors of leng
 * ``zform``   -- Algorithm 2 on the paper's own variable x: products with A and E summed
                  term by term (eq. exactrq), the residual as the sorted sum of its
                  M^2 terms (Lemma truncr).
+* ``learned`` -- learned correction of the preconditioner's diagonal theta_i per (site,
+                 particles before it): network forward and backward, Adam training on
+                 the misfit to the exact diagonal (an extension, not in the paper).
 * ``mps``     -- contraction of an exported block-sparse MPS to its dense vector
                  (eq. mps with the block structure of eq. blockstructure).
 

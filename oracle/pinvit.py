@@ -51,6 +51,7 @@ class Params:
     eps_num: float | None = None
     max_retries: int = 30
     truncation: str = "sequential"  # or "parallel" (tt.truncate_parallel)
+    correction: object = None  # L x (N+1) learned correction of theta (oracle.learned)
 
 
 def initial_determinant(h: np.ndarray, N: int):
@@ -61,7 +62,7 @@ def initial_determinant(h: np.ndarray, N: int):
 
 def run(h, v, N, gamma, prm: Params, psi0=None):
     L = h.shape[0]
-    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper)
+    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper, prm.correction)
     mode = prm.truncation
 
     def trunc(x, eps):

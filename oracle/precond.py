@@ -73,11 +73,19 @@ def c_const(c0: float, c_lower: float, c_upper: float) -> float:
 class Preconditioner:
     """All scalars of S for one problem."""
 
-    def __init__(self, h, v, N, gamma, c0=0.1, c_lower=1.0, c_upper=1.0):
+    def __init__(self, h, v, N, gamma, c0=0.1, c_lower=1.0, c_upper=1.0, delta=None):
+        """delta: None, or an L x (N+1) correction of theta_i per (site, particles on the
+        sites before it) (``oracle.learned``); t_min and t_max then follow from the
+        corrected diagonal."""
         self.L = h.shape[0]
         self.N = N
         self.th = theta(h, v, N, gamma)
-        self.t_min, self.t_max = t_range(self.th, N)
+        self.delta = None if delta is None else np.asarray(delta, dtype=np.float64).reshape(self.L, N + 1)
+        if self.delta is None:
+            self.t_min, self.t_max = t_range(self.th, N)
+        else:
+            from .learned import t_range as t_range_corrected
+            self.t_min, self.t_max = t_range_corrected(self.th, self.delta, N)
         if not self.t_min > 0.0:
             raise ValueError("t_min <= 0: the shift does not make D positive")
         self.T = self.t_max / self.t_min
@@ -99,8 +107,14 @@ class Preconditioner:
         L = self.L
         idx = np.arange(1 << L, dtype=np.int64)
         occ_sum = np.zeros(1 << L)
+        left = np.zeros(1 << L, dtype=np.int64)  # particles on the sites before i
         for i in range(L):
-            occ_sum += ((idx >> i) & 1) * self.th[i]
+            bit = (idx >> i) & 1
+            if self.delta is None:
+                occ_sum += bit * self.th[i]
+            else:
+                occ_sum += bit * (self.th[i] + self.delta[i, np.minimum(left, self.N)])
+            left += bit
         return [a * np.exp(-b * occ_sum) for a, b in zip(self.alpha, self.beta)]
 
     def apply_exact(self, x):

@@ -82,7 +82,7 @@ def run_subspace(h, v, N, gamma, prm: Params, D: int, X0=None):
     L = h.shape[0]
     if 2 * D > math.comb(L, N):
         raise ValueError("the 2D Ritz vectors need a sector of dimension at least 2D")
-    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper)
+    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper, prm.correction)
     mode = prm.truncation
 
     def trunc(x, eps):

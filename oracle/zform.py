@@ -84,7 +84,7 @@ def run_z(h, v, N, gamma, prm: Params, x0=None):
     rho, bound, r_norm, eta, retries, cap_bound, terms_dropped, and after a Ritz step
     lam_star and eta_in."""
     L = h.shape[0]
-    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper)
+    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper, prm.correction)
     mode = prm.truncation
     eps_num = prm.eps_num if prm.eps_num is not None else 0.5 * (1.0 - prm.c)
     zeta = eps_num / (1.0 + prm.c)

@@ -15,3 +15,4 @@ from .integrals import (  # noqa: F401
     shift_lower_bound,
 )
 from .mps import rho_table, random_block_mps, layout  # noqa: F401,E402
+from .learned import N_FEAT, WIDTH, N_PARAMS, init_params, sample_determinants  # noqa: F401,E402
