@@ -258,6 +258,41 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
 pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* starts, pv_result* res,
                           pv_subspace_iter* hist, int hist_cap, int* psi);
 
+/* Learned correction of the preconditioner diagonal (an extension, not in the paper).
+ * The correction Delta (L x (N+1), row-major, entry [i][n]) changes theta_i to
+ * theta_i + Delta_{i,n} on the occupied state of site i when n particles sit on the sites
+ * before it, so each term alpha_m exp(-beta_m d) of S stays a product of site factors;
+ * t_min and t_max become the extremes of the corrected diagonal d over the N-particle
+ * determinants, and alpha_m, beta_m, s_min, s_max follow from them as for the plain S.
+ *
+ * pv_set_correction: delta (host, L (N+1) doubles, copied) is used by pv_run,
+ * pv_run_outer, pv_run_subspace and pv_apply_s until cleared by NULL or a new
+ * Hamiltonian; pv_run_zform then fails with PV_ESTATE.  PV_EINVAL for non-finite entries,
+ * PV_ENOTSPD when some theta_i + Delta_{i,n} (n < N) is not positive.
+ *
+ * The network: per row (i, n) the six features theta_i/tbar, h_ii/tbar, n/N, i/L, <n_i>
+ * of the iterate and lambda/(N tbar) (tbar = mean |theta_i|, lambda the Rayleigh quotient
+ * of the iterate), two hidden layers of PV_MLP_WIDTH units with tanh and a linear output
+ * z; Delta = (min_i theta_i / 2) tanh(z) (zero when min theta_i <= 0).  params holds
+ * PV_MLP_PARAMS float32 values: W1 (width x 6, row-major), b1, W2 (width x width,
+ * row-major), b2, W3, b3.  The passes use the parameters rounded to bfloat16 and float32
+ * MFMA products.  psi: the iterate whose densities and Rayleigh quotient enter the
+ * features, or -1 for the start determinant of pv_run.
+ *
+ * pv_learned_correction: writes Delta (L (N+1) doubles) to delta.
+ * pv_learned_train: `steps` Adam steps (beta1 0.9, beta2 0.999, epsilon 1e-8, learning
+ * rate lr, zero initial moments) on loss = mean_b (d(m_b) - <m_b|H + gamma|m_b>)^2 / tbar^2
+ * over the nmask determinants m_b (bit i = orbital i; each must hold N particles within
+ * the L <= 64 orbitals).  params is updated in place; loss (NULL or steps + 1 doubles)
+ * receives the loss before each step and after the last; grad (NULL or PV_MLP_PARAMS
+ * doubles) the gradient at the final parameters. */
+#define PV_MLP_WIDTH 256
+#define PV_MLP_PARAMS (PV_MLP_WIDTH * 6 + PV_MLP_WIDTH + PV_MLP_WIDTH * PV_MLP_WIDTH + PV_MLP_WIDTH + PV_MLP_WIDTH + 1)
+pv_status pv_set_correction(pv_ctx* ctx, const double* delta);
+pv_status pv_learned_correction(pv_ctx* ctx, const float* params, int psi, double* delta);
+pv_status pv_learned_train(pv_ctx* ctx, float* params, int psi, const uint64_t* masks, int nmask, int steps,
+                           float lr, double* loss, double* grad);
+
 /* Batched independent problems (many Hamiltonians of uneven size at once): runs pv_run from
  * the determinant on each of the `count` distinct contexts ctxs[i] (each with its
  * Hamiltonian already set) with parameters prm[i], writing res[i] and, when status is not

@@ -69,7 +69,8 @@ double expsum(double t, double h, int mp, int mm) {
 }
 
 // theta_i of Section 7.1.1 with one-based window j = k_i+1 .. k_i+N, k_i = max(0, i-N).
-void setup_precond(Ctx& c, double c0, double cl, double cu) {
+// theta_i of Section 7.1.1 into c.theta
+void compute_theta(Ctx& c) {
   const int L = c.L, N = c.N;
   c.theta.assign(L, 0.0);
   for (int i1 = 1; i1 <= L; ++i1) {
@@ -82,10 +83,32 @@ void setup_precond(Ctx& c, double c0, double cl, double cu) {
     }
     c.theta[i1 - 1] = acc;
   }
-  std::vector<double> s = c.theta;
-  std::sort(s.begin(), s.end());
-  c.t_min = std::accumulate(s.begin(), s.begin() + N, 0.0);
-  c.t_max = std::accumulate(s.end() - N, s.end(), 0.0);
+}
+
+void setup_precond(Ctx& c, double c0, double cl, double cu) {
+  const int L = c.L, N = c.N;
+  compute_theta(c);
+  if (c.corr.empty()) {
+    std::vector<double> s = c.theta;
+    std::sort(s.begin(), s.end());
+    c.t_min = std::accumulate(s.begin(), s.begin() + N, 0.0);
+    c.t_max = std::accumulate(s.end() - N, s.end(), 0.0);
+  } else {
+    // extremes of sum_{i occ} (theta_i + Delta_{i, particles before i}) over the
+    // N-particle determinants: shortest and longest path over (site, particles placed)
+    const double inf = std::numeric_limits<double>::infinity();
+    std::vector<double> lo(N + 1, inf), hi(N + 1, -inf);
+    lo[0] = hi[0] = 0.0;
+    for (int i = 0; i < L; ++i)
+      for (int n = N; n >= 1; --n) {
+        const double w = c.theta[i] + c.corr[size_t(i) * (N + 1) + n - 1];
+        if (!(w > 0)) fail(PV_ENOTSPD, "corrected theta is not positive");
+        lo[n] = std::min(lo[n], lo[n - 1] + w);
+        hi[n] = std::max(hi[n], hi[n - 1] + w);
+      }
+    c.t_min = lo[N];
+    c.t_max = hi[N];
+  }
   if (!(c.t_min > 0.0)) fail(PV_ENOTSPD, "t_min <= 0: the shift does not make D positive");
   c.T_ratio = c.t_max / c.t_min;
   expsum_params(c0, c.T_ratio, &c.hs, &c.m_plus, &c.m_minus);
@@ -336,6 +359,7 @@ pv_status pv_set_hamiltonian(pv_ctx* ctx, int L, int N, const double* h, const d
     c.sync();
     c.mps.clear();
     c.L = L; c.N = N; c.gamma = gamma;
+    c.corr.clear();  // a correction belongs to one Hamiltonian
     c.h.assign(h, h + size_t(L) * L);
     c.v.assign(v, v + nv);
     Mpo m = build_mpo(L, h, v, gamma / N);
@@ -856,6 +880,7 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
     if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
     Ctx& c = ctx->c;
     if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (!c.corr.empty()) fail(PV_ESTATE, "the z-form does not take a learned correction");
     const pv_params p = *prm;
     if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
@@ -1026,6 +1051,74 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
     }
     res->iterations = rows;
     if (x_out) *x_out = put(c, std::move(x));
+  });
+}
+
+// Learned correction of theta (an extension): see the header.
+pv_status pv_set_correction(pv_ctx* ctx, const double* delta) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (!delta) {
+      c.corr.clear();
+      return;
+    }
+    const size_t n = size_t(c.L) * (c.N + 1);
+    for (size_t e = 0; e < n; ++e)
+      if (!std::isfinite(delta[e])) fail(PV_EINVAL, "correction is not finite");
+    std::vector<double> keep(delta, delta + n);
+    compute_theta(c);
+    for (int i = 0; i < c.L; ++i)
+      for (int k = 0; k < c.N; ++k)
+        if (!(c.theta[i] + keep[size_t(i) * (c.N + 1) + k] > 0))
+          fail(PV_ENOTSPD, "corrected theta is not positive");
+    c.corr = std::move(keep);
+  });
+}
+
+// the iterate the features describe (psi, or the start determinant of pv_run) and its
+// Rayleigh quotient
+static std::unique_ptr<Mps> feature_state(Ctx& c, int psi, double* lam) {
+  std::unique_ptr<Mps> x;
+  if (psi >= 0) {
+    x = mps_scaled_copy(c, get(c, psi), 1.0, nullptr);
+  } else {
+    std::vector<int> idx(c.L);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return c.h[size_t(a) * c.L + a] < c.h[size_t(b) * c.L + b]; });
+    x = mps_determinant(c, std::vector<int>(idx.begin(), idx.begin() + c.N));
+  }
+  const double nx = dot(c, *x, *x);
+  if (!(nx > 0)) fail(PV_EINVAL, "zero state");
+  *lam = expect_h(c, *x, *x) / nx;
+  return x;
+}
+
+pv_status pv_learned_correction(pv_ctx* ctx, const float* params, int psi, double* delta) {
+  return guard([&] {
+    if (!ctx || !params || !delta) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    compute_theta(c);
+    double lam = 0;
+    auto x = feature_state(c, psi, &lam);
+    learned_correction(c, params, *x, lam, c.theta, delta);
+  });
+}
+
+pv_status pv_learned_train(pv_ctx* ctx, float* params, int psi, const uint64_t* masks, int nmask, int steps,
+                           float lr, double* loss, double* grad) {
+  return guard([&] {
+    if (!ctx || !params || (nmask > 0 && !masks)) fail(PV_EINVAL, "null argument");
+    if (nmask < 1 || steps < 0 || !(lr >= 0)) fail(PV_EINVAL, "need nmask >= 1, steps >= 0, lr >= 0");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (c.L > 64) fail(PV_EINVAL, "sample masks hold at most 64 orbitals");
+    compute_theta(c);
+    double lam = 0;
+    auto x = feature_state(c, psi, &lam);
+    learned_train(c, params, *x, lam, c.theta, masks, nmask, steps, lr, loss, grad);
   });
 }
 

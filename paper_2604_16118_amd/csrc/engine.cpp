@@ -1,5 +1,6 @@
 // Runtime pieces (pool, staging, timers) and the block-sparse MPS operations.
 #include "engine.hpp"
+#include "learned.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -1099,6 +1100,22 @@ std::unique_ptr<Mps> mps_zero_like(Ctx& c, const Mps& x) {
   return m;
 }
 
+// a x with the occupied block of site k in left sector n scaled by occ[(k-1)(N+1) + n]
+std::unique_ptr<Mps> mps_sector_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ) {
+  auto m = mps_alloc(c, x.L, x.N, x.rho);
+  CopyBatch cb;
+  for (int k = 1; k <= x.L; ++k)
+    for (int n = 0; n <= x.N; ++n) {
+      if (!x.valid(k - 1, n)) continue;
+      const int r = x.rows(k, n);
+      const double f = k == 1 ? a : 1.0;
+      cb.add(x.U(k, n), r, m->U(k, n), r, r, x.ucols(k, n), f);
+      cb.add(x.O(k, n), r, m->O(k, n), r, r, x.ocols(k, n), f * occ[size_t(k - 1) * (x.N + 1) + n]);
+    }
+  cb.run(c);
+  return m;
+}
+
 std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale) {
   auto m = mps_alloc(c, x.L, x.N, x.rho);
   CopyBatch cb;
@@ -1911,7 +1928,49 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
 // one diagonal-operator sweep; the terms whose norms sum to <= eta/3 are dropped, the
 // rest added in increasing norm order with trunc_{eps_j}, eps_j = eta |s_j| / (3 sum |s|),
 // and the sum is truncated once more with eta/3.
+// The M terms alpha_m exp(-beta_m d) of S with the learned correction of theta per (site,
+// particles before it): the occupied block of site k in left sector n is scaled by
+// exp(-beta_m (theta_k + Delta_{k,n})).  The term norms come from the scaled copies.
+static std::unique_ptr<Mps> apply_s_corrected(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound) {
+  const int L = x.L, N = x.N, M = int(c.alpha.size());
+  std::vector<std::unique_ptr<Mps>> terms(M);
+  std::vector<double> nrm(M);
+  std::vector<double> occ(size_t(L) * (N + 1));
+  for (int m = 0; m < M; ++m) {
+    for (int k = 0; k < L; ++k)
+      for (int n = 0; n <= N; ++n)
+        occ[size_t(k) * (N + 1) + n] = std::exp(-c.beta[m] * (c.theta[k] + c.corr[size_t(k) * (N + 1) + n]));
+    terms[m] = mps_sector_scaled_copy(c, x, c.alpha[m], occ.data());
+    nrm[m] = norm2(c, *terms[m]);
+  }
+  std::vector<int> order(M);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return nrm[a] != nrm[b] ? nrm[a] < nrm[b] : a < b; });
+  double csum = 0.0;
+  int j0 = 0;
+  for (int j = 0; j < M; ++j) {
+    if (csum + nrm[order[j]] <= eta / 3.0) { csum += nrm[order[j]]; j0 = j + 1; }
+    else break;
+  }
+  double total = 0.0;
+  for (int j = j0; j < M; ++j) total += nrm[order[j]];
+  std::unique_ptr<Mps> y;
+  for (int j = j0; j < M; ++j) {
+    const int m = order[j];
+    const double eps_j = total > 0 ? eta * nrm[m] / (3.0 * total) : 0.0;
+    if (!y) y = round_mps(c, *terms[m], eps_j, cap, cap_bound);
+    else {
+      auto sum = mps_lincomb(c, 1.0, *y, 1.0, *terms[m]);
+      y = round_mps(c, *sum, eps_j, cap, cap_bound);
+    }
+    terms[m].reset();
+  }
+  if (!y) return mps_zero_like(c, x);
+  return round_mps(c, *y, eta / 3.0, cap, cap_bound);
+}
+
 std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound) {
+  if (!c.corr.empty()) return apply_s_corrected(c, x, eta, cap, cap_bound);
   const int L = x.L, M = int(c.alpha.size());
   std::vector<std::vector<double>> d0(M, std::vector<double>(L, 1.0)), d1(M, std::vector<double>(L, 1.0));
   std::vector<std::vector<double>> occ(M, std::vector<double>(L, 1.0));
@@ -1952,6 +2011,179 @@ std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* ca
     return mps_zero_like(c, x);
   }
   return round_mps(c, *y, eta / 3.0, cap, cap_bound);
+}
+
+
+// ---------------------------------------------------------------- learned correction
+// <n_i> of x for every site in one diagonal-operator sweep (channel i: 0 on the empty and
+// 1 on the occupied state of site i, 1 elsewhere), divided by <x|x>.
+std::vector<double> densities(Ctx& c, const Mps& x) {
+  const int L = x.L;
+  std::vector<std::vector<double>> d0(L, std::vector<double>(L, 1.0)), d1(L, std::vector<double>(L, 1.0));
+  for (int i = 0; i < L; ++i) d0[i][i] = 0.0;
+  auto op = diag_mpo(c, L, L, d0, d1);
+  std::vector<double> v = env_sweep(c, x, x, *op);
+  const double nx = dot(c, x, x);
+  if (!(nx > 0)) fail(PV_EINVAL, "densities of a zero state");
+  v.resize(L);
+  for (double& d : v) d /= nx;
+  return v;
+}
+
+namespace {
+
+// Device state of one network evaluation over the R = L(N+1) feature rows.
+struct Mlp {
+  Ctx& c;
+  int L, N, R;
+  double tbar, dmax;
+  Buf wq, X, H1, H2, z, tz, delta, G, dz, dA2, dA1, grad, dev;
+  Mlp(Ctx& cc, const Mps& x, double lam, const std::vector<double>& th) : c(cc), L(x.L), N(x.N) {
+    R = L * (N + 1);
+    tbar = 0.0;
+    double tmin = th[0];
+    for (double t : th) { tbar += std::fabs(t); tmin = std::min(tmin, t); }
+    tbar /= L;
+    if (!(tbar > 0)) fail(PV_EINVAL, "theta vanishes");
+    dmax = tmin > 0 ? 0.5 * tmin : 0.0;
+    auto dens = densities(c, x);
+    std::vector<double> host(3 * size_t(L));
+    for (int i = 0; i < L; ++i) {
+      host[i] = th[i];
+      host[L + i] = c.h[size_t(i) * L + i];
+      host[2 * L + i] = dens[i];
+    }
+    dev = Buf(c.pool, host.size());
+    PV_HIP(hipMemcpyAsync(dev.p, host.data(), host.size() * 8, hipMemcpyHostToDevice, c.stream));
+    wq = Buf(c.pool, size_t(kMlpParams));
+    X = Buf(c.pool, size_t(kMlpFeat) * R);
+    H1 = Buf(c.pool, size_t(kMlpWidth) * R);
+    H2 = Buf(c.pool, size_t(kMlpWidth) * R);
+    z = Buf(c.pool, R);
+    tz = Buf(c.pool, R);
+    delta = Buf(c.pool, R);
+    launch_mlp_features(dev.p, dev.p + L, dev.p + 2 * L, L, N, tbar, lam, X.p, c.stream);
+    c.sync();  // the host staging vector goes out of scope
+  }
+  const double* W1() const { return wq.p; }
+  const double* b1() const { return W1() + kMlpWidth * kMlpFeat; }
+  const double* W2() const { return b1() + kMlpWidth; }
+  const double* b2() const { return W2() + kMlpWidth * kMlpWidth; }
+  const double* W3() const { return b2() + kMlpWidth; }
+  const double* b3() const { return W3() + kMlpWidth; }
+  // the matrix products in float32 MFMA with float32 accumulation
+  void gemm(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc, int M, int Nn,
+            int K) {
+    GemmBatch g;
+    g.prec = 1;
+    g.add(A, lda, ta, B, ldb, tb, C, ldc, M, Nn, K, 1.0, 0.0);
+    g.run(c);
+  }
+  void forward() {
+    const int W = kMlpWidth;
+    gemm(W1(), kMlpFeat, 1, X.p, kMlpFeat, 0, H1.p, W, W, R, kMlpFeat);
+    launch_mlp_bias_tanh(H1.p, b1(), W, R, W, c.stream);
+    gemm(W2(), W, 1, H1.p, W, 0, H2.p, W, W, R, W);
+    launch_mlp_bias_tanh(H2.p, b2(), W, R, W, c.stream);
+    gemm(W3(), W, 1, H2.p, W, 0, z.p, 1, 1, R, W);
+    launch_mlp_output(z.p, b3(), R, dmax, tz.p, delta.p, c.stream);
+  }
+  // gradient of the loss with respect to the parameters from G = d loss / d delta
+  void backward() {
+    const int W = kMlpWidth;
+    if (!grad.p) {
+      dz = Buf(c.pool, R);
+      dA2 = Buf(c.pool, size_t(W) * R);
+      dA1 = Buf(c.pool, size_t(W) * R);
+      grad = Buf(c.pool, size_t(kMlpParams));
+    }
+    double* gW1 = grad.p;
+    double* gb1 = gW1 + W * kMlpFeat;
+    double* gW2 = gb1 + W;
+    double* gb2 = gW2 + W * W;
+    double* gW3 = gb2 + W;
+    double* gb3 = gW3 + W;
+    launch_mlp_dz(G.p, tz.p, R, dmax, dz.p, c.stream);
+    gemm(H2.p, W, 0, dz.p, R, 0, gW3, W, W, 1, R);
+    launch_mlp_rowsum(dz.p, 1, R, 1, gb3, c.stream);
+    gemm(W3(), W, 0, dz.p, 1, 0, dA2.p, W, W, R, 1);
+    launch_mlp_tanh_grad(dA2.p, H2.p, int64_t(W) * R, c.stream);
+    gemm(H1.p, W, 0, dA2.p, W, 1, gW2, W, W, W, R);
+    launch_mlp_rowsum(dA2.p, W, R, W, gb2, c.stream);
+    gemm(W2(), W, 0, dA2.p, W, 0, dA1.p, W, W, R, W);
+    launch_mlp_tanh_grad(dA1.p, H1.p, int64_t(W) * R, c.stream);
+    gemm(X.p, kMlpFeat, 0, dA1.p, W, 1, gW1, kMlpFeat, kMlpFeat, W, R);
+    launch_mlp_rowsum(dA1.p, W, R, W, gb1, c.stream);
+  }
+};
+
+}  // namespace
+
+void learned_correction(Ctx& c, const float* params, const Mps& x, double lam, const std::vector<double>& th,
+                        double* delta) {
+  Mlp net(c, x, lam, th);
+  Buf w(c.pool, size_t((kMlpParams + 1) / 2));
+  PV_HIP(hipMemcpyAsync(w.p, params, size_t(kMlpParams) * 4, hipMemcpyHostToDevice, c.stream));
+  launch_mlp_round(reinterpret_cast<const float*>(w.p), kMlpParams, net.wq.p, c.stream);
+  net.forward();
+  PV_HIP(hipMemcpyAsync(delta, net.delta.p, size_t(net.R) * 8, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+}
+
+void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::vector<double>& th,
+                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad) {
+  const int L = x.L, N = x.N;
+  for (int b = 0; b < nmask; ++b) {
+    if (L < 64 && (masks[b] >> L) != 0) fail(PV_EINVAL, "a sample occupies an orbital beyond L");
+    if (__builtin_popcountll(masks[b]) != N) fail(PV_EINVAL, "a sample is not an N-particle determinant");
+  }
+  Mlp net(c, x, lam, th);
+  const size_t pf = size_t((kMlpParams + 1) / 2);  // float32 arrays in double-sized units
+  Buf w(c.pool, pf), mom(c.pool, 2 * pf), mk(c.pool, std::max(nmask, 1)), jk(c.pool, size_t(L) * L),
+      target(c.pool, std::max(nmask, 1)), lossd(c.pool, size_t(steps) + 1);
+  float* wf = reinterpret_cast<float*>(w.p);
+  float* m1 = reinterpret_cast<float*>(mom.p);
+  float* m2 = m1 + kMlpParams;
+  fill(c, mom.p, int64_t(2 * pf), 0.0);
+  fill(c, lossd.p, steps + 1, 0.0);
+  std::vector<double> jkh(size_t(L) * L, 0.0);
+  for (int i = 0; i < L; ++i)
+    for (int j = 0; j < L; ++j) {
+      auto V = [&](int a, int b2, int cc, int d) { return c.v[((size_t(a) * L + b2) * L + cc) * L + d]; };
+      jkh[i + size_t(j) * L] = V(i, j, j, i) - V(i, j, i, j);
+    }
+  PV_HIP(hipMemcpyAsync(w.p, params, size_t(kMlpParams) * 4, hipMemcpyHostToDevice, c.stream));
+  if (nmask) PV_HIP(hipMemcpyAsync(mk.p, masks, size_t(nmask) * 8, hipMemcpyHostToDevice, c.stream));
+  PV_HIP(hipMemcpyAsync(jk.p, jkh.data(), jkh.size() * 8, hipMemcpyHostToDevice, c.stream));
+  const uint64_t* md = reinterpret_cast<const uint64_t*>(mk.p);
+  launch_mlp_target(md, nmask, net.dev.p + L, jk.p, c.gamma, L, target.p, c.stream);
+  launch_mlp_round(wf, kMlpParams, net.wq.p, c.stream);
+  net.G = Buf(c.pool, net.R);
+  const double B = std::max(nmask, 1);
+  const double scale = 2.0 / (B * net.tbar * net.tbar), lscale = 1.0 / (B * net.tbar * net.tbar);
+  auto misfit = [&](int t) {
+    net.forward();
+    fill(c, net.G.p, net.R, 0.0);
+    launch_mlp_misfit(md, nmask, net.dev.p, net.delta.p, target.p, L, N, scale, lscale, net.G.p, lossd.p + t,
+                      c.stream);
+  };
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float p1 = 1.0f, p2 = 1.0f;
+  for (int t = 0; t < steps; ++t) {
+    misfit(t);
+    net.backward();
+    p1 *= b1;
+    p2 *= b2;
+    launch_mlp_adam(wf, m1, m2, net.grad.p, kMlpParams, lr, b1, b2, eps, 1.0f - p1, 1.0f - p2, net.wq.p, c.stream);
+  }
+  misfit(steps);
+  if (grad) {
+    net.backward();
+    PV_HIP(hipMemcpyAsync(grad, net.grad.p, size_t(kMlpParams) * 8, hipMemcpyDeviceToHost, c.stream));
+  }
+  if (loss) PV_HIP(hipMemcpyAsync(loss, lossd.p, (size_t(steps) + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  PV_HIP(hipMemcpyAsync(params, w.p, size_t(kMlpParams) * 4, hipMemcpyDeviceToHost, c.stream));
+  c.sync();
 }
 
 }  // namespace pv

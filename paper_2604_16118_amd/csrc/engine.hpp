@@ -144,6 +144,7 @@ struct Ctx {
   std::vector<int> mpo_w;
   // preconditioner (Section 4.3, Section 7.1.1)
   std::vector<double> theta;
+  std::vector<double> corr;  // learned correction of theta, L x (N+1) row-major; empty: none
   double t_min = 0, t_max = 0, T_ratio = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
   int m_minus = 0, m_plus = 0;
   std::vector<double> alpha, beta;
@@ -188,6 +189,13 @@ std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ);
 std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y);
 std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale);
 std::unique_ptr<Mps> mps_zero_like(Ctx& c, const Mps& x);
+std::unique_ptr<Mps> mps_sector_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ);
+std::vector<double> densities(Ctx& c, const Mps& x);
+// learned correction of theta (th: theta_i, L values; hd: h_ii; lam: Rayleigh quotient of x)
+void learned_correction(Ctx& c, const float* params, const Mps& x, double lam, const std::vector<double>& th,
+                        double* delta);
+void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::vector<double>& th,
+                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad);
 std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op);
 double dot(Ctx& c, const Mps& a, const Mps& b);
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket);

@@ -22,8 +22,13 @@ EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_zform", "pv_run_batch",
+    "pv_set_correction", "pv_learned_correction", "pv_learned_train",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
+
+
+MLP_WIDTH = 256
+MLP_PARAMS = MLP_WIDTH * 6 + MLP_WIDTH + MLP_WIDTH * MLP_WIDTH + MLP_WIDTH + MLP_WIDTH + 1
 
 
 class PvError(RuntimeError):
@@ -325,6 +330,44 @@ class Context:
                      max_rank=h.max_rank, stop=bool(h.stopped)) for h in hist[:res.iterations]]
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, steps=res.iterations,
                     converged=bool(res.converged)), rows, psi.value
+
+    def set_correction(self, delta=None):
+        """Learned correction Delta (L x (N+1)) of the preconditioner diagonal, or None to
+        clear it (pv_set_correction)."""
+        if delta is None:
+            _check(lib().pv_set_correction(self._p, None))
+            return
+        d = np.ascontiguousarray(delta, dtype=np.float64).reshape(-1)
+        if d.size != self.L * (self.N + 1):
+            raise ValueError("correction must have L (N+1) entries")
+        _check(lib().pv_set_correction(self._p, d.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def learned_correction(self, params, psi=-1):
+        """Delta (L x (N+1)) of the network with float32 parameters `params` for the iterate
+        psi (-1: the start determinant) (pv_learned_correction)."""
+        w = np.ascontiguousarray(params, dtype=np.float32)
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"params must have {MLP_PARAMS} entries")
+        out = np.zeros(self.L * (self.N + 1))
+        _check(lib().pv_learned_correction(self._p, w.ctypes.data_as(C.POINTER(C.c_float)), int(psi),
+                                           out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(self.L, self.N + 1)
+
+    def learned_train(self, params, masks, steps, lr=1e-3, psi=-1, want_grad=False):
+        """Adam steps on the diagonal misfit over the determinants `masks` (uint64)
+        (pv_learned_train).  Returns (new float32 parameters, losses (steps + 1), gradient at
+        the final parameters or None)."""
+        w = np.array(params, dtype=np.float32, copy=True)
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"params must have {MLP_PARAMS} entries")
+        m = np.ascontiguousarray(masks, dtype=np.uint64)
+        loss = np.zeros(int(steps) + 1)
+        grad = np.zeros(MLP_PARAMS) if want_grad else None
+        _check(lib().pv_learned_train(self._p, w.ctypes.data_as(C.POINTER(C.c_float)), int(psi),
+                                      m.ctypes.data_as(C.POINTER(C.c_uint64)), int(m.size), int(steps),
+                                      C.c_float(lr), loss.ctypes.data_as(C.POINTER(C.c_double)),
+                                      grad.ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None))
+        return w, loss, grad
 
     def run_zform(self, start=-1, **kw):
         """Algorithm 2 on the variable x (pv_run_zform); keyword arguments as in run.  Returns

@@ -1,0 +1,167 @@
+"""GPU learned preconditioner correction (pv_set_correction, pv_learned_correction,
+pv_learned_train) against the oracle (oracle.learned): the network output for the start
+determinant and for a multi-determinant iterate, the misfit and its gradient, the training
+trajectory, and Algorithm 2 / Algorithm 4 runs with a correction against the oracle's runs
+with the same table (energies within 1e-10 relative).  The network runs on float32 MFMA
+products, so its outputs are compared at float32 tolerances."""
+import numpy as np
+import pytest
+
+from oracle import fock, learned, pinvit, precond, subspace
+from oracle import mps as omps
+from synth import init_params, make_problem, sample_determinants
+
+pytestmark = pytest.mark.gpu
+
+native = pytest.importorskip("paper_2604_16118_amd.native")
+
+L, N = 8, 4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return make_problem("decayed", L, N, 0)
+
+
+def _oracle_features(p, x):
+    th = precond.theta(p.h, p.v, N, p.gamma)
+    lam = float(x @ fock.apply_h(p.h, p.v, x, p.gamma)) / float(x @ x)
+    return th, learned.features(th, np.diag(p.h), learned.densities(x), lam, N)
+
+
+def _start(p):
+    return fock.determinant(L, pinvit.initial_determinant(p.h, N))
+
+
+def test_network_output_for_the_start_determinant(ctx, prob):
+    p = prob
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    w = init_params(1, out_scale=1.0)
+    got = ctx.learned_correction(w, -1)
+    th, X = _oracle_features(p, _start(p))
+    dm = learned.delta_max(th)
+    want = learned.correction(w, X, dm, L, N)
+    assert np.abs(want).max() > 1e-3 * dm  # a nontrivial output
+    np.testing.assert_allclose(got, want, rtol=0, atol=2e-5 * dm)
+
+
+def test_network_output_for_an_iterate(ctx, prob):
+    p = prob
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    _, _, psi = ctx.run(rank_cap=16, max_iter=2, tau=0.0)
+    try:
+        rho, data = ctx.mps_download(psi)
+        x = omps.to_dense(L, N, rho, data)
+        w = init_params(2, out_scale=1.0)
+        got = ctx.learned_correction(w, psi)
+    finally:
+        ctx.mps_free(psi)
+    th, X = _oracle_features(p, x)
+    assert 0 < X[:, 4].min() < X[:, 4].max() < 1  # fractional densities
+    dm = learned.delta_max(th)
+    np.testing.assert_allclose(got, learned.correction(w, X, dm, L, N), rtol=0, atol=2e-5 * dm)
+
+
+def test_misfit_and_gradient(ctx, prob):
+    p = prob
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    masks = sample_determinants(L, N, 200, seed=3, start=pinvit.initial_determinant(p.h, N))
+    w = init_params(3, out_scale=1.0)
+    w1, loss, grad = ctx.learned_train(w, masks, steps=0, want_grad=True)
+    np.testing.assert_array_equal(w1, w)
+    th, X = _oracle_features(p, _start(p))
+    tg = learned.exact_diagonal(p.h, p.v, p.gamma, masks)
+    lo, go = learned.loss_grad(w, X, learned.delta_max(th), th, masks, tg, N)
+    assert loss[0] == pytest.approx(lo, rel=1e-5)
+    assert np.linalg.norm(grad - go) <= 1e-4 * np.linalg.norm(go)
+
+
+def test_training_trajectory(ctx, prob):
+    p = prob
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    masks = sample_determinants(L, N, 200, seed=4, start=pinvit.initial_determinant(p.h, N))
+    w0 = init_params(0)
+    w, loss, _ = ctx.learned_train(w0, masks, steps=25, lr=1e-3)
+    th, X = _oracle_features(p, _start(p))
+    tg = learned.exact_diagonal(p.h, p.v, p.gamma, masks)
+    wo, lo = learned.train(w0, X, learned.delta_max(th), th, masks, tg, N, steps=25, lr=1e-3)
+    assert loss[-1] < 0.8 * loss[0]
+    np.testing.assert_allclose(loss[:3], lo[:3], rtol=1e-4)
+    np.testing.assert_allclose(loss[-1], lo[-1], rtol=5e-2)
+
+
+def _table(p, seed=0, steps=20):
+    th, X = _oracle_features(p, _start(p))
+    masks = sample_determinants(L, N, 200, seed=seed, start=pinvit.initial_determinant(p.h, N))
+    tg = learned.exact_diagonal(p.h, p.v, p.gamma, masks)
+    dm = learned.delta_max(th)
+    w, _ = learned.train(init_params(seed, out_scale=1.0), X, dm, th, masks, tg, N, steps=steps, lr=1e-3)
+    return learned.correction(w, X, dm, L, N)
+
+
+@pytest.mark.parametrize("truncation", [0, 1])
+def test_run_with_correction_matches_oracle(ctx, prob, truncation):
+    p = prob
+    corr = _table(p)
+    w2 = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=2)
+    delta = w2[1] / (w2[1] - w2[0])
+    prm = pinvit.Params(cap=24, max_iter=6, tau=1e-12, delta=delta, correction=corr,
+                        truncation="parallel" if truncation else "sequential")
+    _, hist_o, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    ctx.set_correction(corr)
+    try:
+        _, hist_g, psi = ctx.run(rank_cap=24, max_iter=6, tau=1e-12, delta=delta, truncation=truncation)
+        ctx.mps_free(psi)
+    finally:
+        ctx.set_correction(None)
+    tol = 1e-10 if truncation == 0 else 1e-6
+    assert len(hist_g) == len(hist_o)
+    for a, b in zip(hist_g, hist_o):
+        assert abs(a["E"] - b["E"]) <= tol * abs(b["E"]), (a["E"], b["E"])
+        assert a["retries"] == b["retries"]
+
+
+def test_subspace_with_correction_matches_oracle(ctx, prob):
+    p = prob
+    corr = _table(p, seed=1)
+    prm = pinvit.Params(cap=24, max_iter=4, tau=1e-12, delta=10.0, correction=corr)
+    _, hist_o, _ = subspace.run_subspace(p.h, p.v, N, p.gamma, prm, 2)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    ctx.set_correction(corr)
+    try:
+        _, hist_g, handles = ctx.run_subspace(2, rank_cap=24, max_iter=4, tau=1e-12, delta=10.0)
+        for h in handles:
+            ctx.mps_free(h)
+    finally:
+        ctx.set_correction(None)
+    assert len(hist_g) == len(hist_o)
+    for a, b in zip(hist_g, hist_o):
+        np.testing.assert_allclose(a["E"], b["E"], rtol=1e-10, atol=0)
+
+
+def test_correction_errors(ctx, prob):
+    p = prob
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    th = precond.theta(p.h, p.v, N, p.gamma)
+    bad = np.zeros((L, N + 1))
+    bad[0, 0] = -2.0 * th[0]
+    with pytest.raises(native.PvError, match="PV_ENOTSPD"):
+        ctx.set_correction(bad)
+    ctx.set_correction(np.zeros((L, N + 1)))
+    with pytest.raises(native.PvError, match="PV_ESTATE"):
+        ctx.run_zform(rank_cap=8, max_iter=1)
+    ctx.set_correction(None)
+    bad_masks = np.array([0b111], dtype=np.uint64)  # three particles, N = 4
+    with pytest.raises(native.PvError, match="PV_EINVAL"):
+        ctx.learned_train(init_params(0), bad_masks, steps=1)
