@@ -240,25 +240,38 @@ def learned_bench(a):
     from paper_2604_16118_amd import native
     from synth import init_params, make_problem, sample_determinants
 
-    p = make_problem("decayed", a.L, a.N, 0)
     ctx = native.Context(0)
+    # training problems: the evaluation problem itself, or decayed problems of the sizes
+    # in --train-L (N = L/2, seed 0) one after another
+    train_sizes = [int(s) for s in a.train_L.split(",") if s] or [a.L]
+    w = init_params(0)
+    losses, t_train = [], 0.0
+    for Lt in train_sizes:
+        Nt = a.N if Lt == a.L else Lt // 2
+        pt = make_problem("decayed", Lt, Nt, 0)
+        ctx.set_hamiltonian(pt.h, pt.v, Nt, pt.gamma)
+        start = sorted(np.argsort(np.diag(pt.h), kind="stable")[:Nt].tolist())
+        masks = sample_determinants(Lt, Nt, 4096, seed=0, start=start)
+        ctx.learned_train(w, masks, steps=1)  # warm the kernels (the parameters are not kept)
+        t0 = time.perf_counter()
+        w, loss, _ = ctx.learned_train(w, masks, steps=a.train_steps, lr=1e-3)
+        t_train += time.perf_counter() - t0
+        losses.append([Lt, loss[0], loss[-1]])
+    p = make_problem("decayed", a.L, a.N, 0)
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
-    start = sorted(np.argsort(np.diag(p.h), kind="stable")[:a.N].tolist())
-    masks = sample_determinants(a.L, a.N, 4096, seed=0, start=start)
-    w0 = init_params(0)
-    ctx.learned_train(w0, masks, steps=1)  # warm the kernels
-    t0 = time.perf_counter()
-    w, loss, _ = ctx.learned_train(w0, masks, steps=a.train_steps, lr=1e-3)
-    t1 = time.perf_counter()
     corr = ctx.learned_correction(w, -1)
+    t0, t1 = 0.0, t_train
+    loss = [losses[0][1], losses[-1][2]]
     print(f"# trained {a.train_steps} steps in {t1 - t0:.2f}s, loss {loss[0]:.4g} -> {loss[-1]:.4g}, "
           f"max |Delta| {np.abs(corr).max():.4g}", file=sys.stderr, flush=True)
     kw = dict(rank_cap=a.cap, max_iter=a.steps, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
+    print(f"# evaluation L={a.L} N={a.N}: plain run", file=sys.stderr, flush=True)
     t2 = time.perf_counter()
     _, hp, x = ctx.run(**kw)
     t3 = time.perf_counter()
     ctx.mps_free(x)
     ctx.set_correction(corr)
+    print(f"# evaluation: corrected run", file=sys.stderr, flush=True)
     t4 = time.perf_counter()
     _, hl, x = ctx.run(**kw)
     t5 = time.perf_counter()
@@ -269,14 +282,26 @@ def learned_bench(a):
         r = [x["r_norm"] for x in h]
         return (r[-1] / r[0]) ** (1.0 / max(len(r) - 1, 1))
 
+    def to_target(h):
+        """(iterations, seconds) until ||r|| <= --target-res, or None when not reached"""
+        t = 0.0
+        for i, x in enumerate(h):
+            t += x["seconds"]
+            if x["r_norm"] <= a.target_res:
+                return [i + 1, t]
+        return None
+
     out = {"metric": "learned-correction training steps/s and residual reduction per iteration against the plain S",
-           "value": a.train_steps / (t1 - t0), "unit": "train steps/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
+           "value": a.train_steps * len(train_sizes) / (t1 - t0), "unit": "train steps/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
            "higher_is_better": True, "dtype": "f32 network (bf16 weights), f64 PINVIT", "data": "synthetic",
            "config": {"workload": f"network of two 256-wide tanh layers over L(N+1) = {a.L * (a.N + 1)} rows, "
                                   f"4096 sampled determinants; Algorithm 2 on decayed integrals L={a.L} N={a.N} "
                                   f"seed 0, rank cap {a.cap}, m_zip {a.m_zip}",
-                      "L": a.L, "N": a.N, "rank_cap": a.cap, "m_zip": a.m_zip, "train_steps": a.train_steps},
-           "loss_first_last": [loss[0], loss[-1]], "max_abs_correction": float(np.abs(corr).max()),
+                      "L": a.L, "N": a.N, "rank_cap": a.cap, "m_zip": a.m_zip, "train_steps": a.train_steps,
+                      "train_L": train_sizes},
+           "loss_first_last": [loss[0], loss[-1]], "train_losses": losses, "max_abs_correction": float(np.abs(corr).max()),
+           "target_residual": a.target_res, "to_target_plain": to_target(hp), "to_target_learned": to_target(hl),
+           "last_r_norm_plain": hp[-1]["r_norm"], "last_r_norm_learned": hl[-1]["r_norm"],
            "residual_rate_plain": rate(hp), "residual_rate_learned": rate(hl),
            "energies_plain": [r["E"] for r in hp], "energies_learned": [r["E"] for r in hl],
            "iter_per_s_plain": len(hp) / (t3 - t2), "iter_per_s_learned": len(hl) / (t5 - t4)}
@@ -389,6 +414,8 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="train the learned preconditioner correction and compare runs with and without it")
     ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-L", default="", help="comma-separated training sizes (default: the evaluation problem)")
+    ap.add_argument("--target-res", type=float, default=1e-6, help="residual norm the --learned runs are timed to")
     ap.add_argument("--summarize", metavar="ROCPD_DB", help="print kernel statistics of a rocprofv3 database and exit")
     ap.add_argument("--pmc-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV", "BENCH_JSON"),
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
