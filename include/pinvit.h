@@ -267,7 +267,9 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
  *
  * pv_set_correction: delta (host, L (N+1) doubles, copied) is used by pv_run,
  * pv_run_outer, pv_run_subspace and pv_apply_s until cleared by NULL or a new
- * Hamiltonian; pv_run_zform then fails with PV_ESTATE.  PV_EINVAL for non-finite entries,
+ * Hamiltonian; pv_run_zform then fails with PV_ESTATE.  Like pv_set_hamiltonian it sets
+ * up S with c0 = 0.1 for pv_apply_s and pv_precond_info (the runs set it up from their
+ * own parameters).  PV_EINVAL for non-finite entries,
  * PV_ENOTSPD when some theta_i + Delta_{i,n} (n < N) is not positive.
  *
  * The network: per row (i, n) the six features theta_i/tbar, h_ii/tbar, n/N, i/L, <n_i>

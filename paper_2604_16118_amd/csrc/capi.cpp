@@ -1062,6 +1062,7 @@ pv_status pv_set_correction(pv_ctx* ctx, const double* delta) {
     if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
     if (!delta) {
       c.corr.clear();
+      setup_precond(c, 0.1, 1.0, 1.0);  // the default preconditioner, as after pv_set_hamiltonian
       return;
     }
     const size_t n = size_t(c.L) * (c.N + 1);
@@ -1074,6 +1075,7 @@ pv_status pv_set_correction(pv_ctx* ctx, const double* delta) {
         if (!(c.theta[i] + keep[size_t(i) * (c.N + 1) + k] > 0))
           fail(PV_ENOTSPD, "corrected theta is not positive");
     c.corr = std::move(keep);
+    setup_precond(c, 0.1, 1.0, 1.0);  // pv_apply_s and pv_precond_info see the corrected S
   });
 }
 

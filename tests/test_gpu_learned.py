@@ -9,7 +9,7 @@ import pytest
 
 from oracle import fock, learned, pinvit, precond, subspace
 from oracle import mps as omps
-from synth import init_params, make_problem, sample_determinants
+from synth import init_params, make_problem, random_block_mps, rho_table, sample_determinants
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +107,38 @@ def _table(p, seed=0, steps=20):
     dm = learned.delta_max(th)
     w, _ = learned.train(init_params(seed, out_scale=1.0), X, dm, th, masks, tg, N, steps=steps, lr=1e-3)
     return learned.correction(w, X, dm, L, N)
+
+
+@pytest.mark.parametrize("eta_rel", [1e-2, 1e-5])
+def test_apply_s_with_correction(ctx, eta_rel):
+    # the sorted sum of the corrected terms against the oracle's, on a random block MPS
+    Ls, Ns = 9, 4
+    p = make_problem("dense", Ls, Ns, 15)
+    th = precond.theta(p.h, p.v, Ns, p.gamma)
+    corr = 0.5 * learned.delta_max(th) * np.random.default_rng(7).uniform(-1, 1, size=(Ls, Ns + 1))
+    ctx.set_hamiltonian(p.h, p.v, Ns, p.gamma)
+    ctx.set_correction(corr)
+    rho = rho_table(Ls, Ns, 16)
+    data = random_block_mps(Ls, Ns, rho, 5)
+    a = ctx.mps_create(rho, data)
+    try:
+        xa = omps.to_dense(Ls, Ns, rho, data)
+        pre = precond.Preconditioner(p.h, p.v, Ns, p.gamma, delta=corr)
+        info = ctx.precond_info()
+        assert info["t_min"] == pytest.approx(pre.t_min, rel=1e-13)
+        assert info["s_max"] == pytest.approx(pre.s_max, rel=1e-13)
+        eta = eta_rel * np.linalg.norm(pre.apply_exact(xa))
+        s, cb = ctx.apply_s(a, eta, 1000)
+        yo, cb_or, _, _ = precond.apply_sorted(pre, xa, eta, 1000, Ns)
+        rs, ds = ctx.mps_download(s)
+        yg = omps.to_dense(Ls, Ns, rs, ds)
+        ctx.mps_free(s)
+    finally:
+        ctx.mps_free(a)
+        ctx.set_correction(None)
+    assert cb == cb_or
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    assert np.linalg.norm(yg - pre.apply_exact(xa)) <= eta * (1 + 1e-9)
 
 
 @pytest.mark.parametrize("truncation", [0, 1])
