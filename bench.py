@@ -154,7 +154,7 @@ def summarize(db: str) -> str:
             out.append(f"wall {1e-9 * (r[1] - r[0]):.3f} s\n")
         out.append("| kernel | calls | total ms | avg us | % |\n|---|---:|---:|---:|---:|")
         for name, n, d, a in rows:
-            short = name.split("(")[0]
+            short = name.replace("(anonymous namespace)::", "").split("(")[0]
             out.append(f"| {short} | {n} | {1e-6 * d:.1f} | {1e-3 * a:.1f} | {100.0 * d / tot:.1f} |")
         out.append("")
     return "\n".join(out)

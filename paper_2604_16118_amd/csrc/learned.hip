@@ -64,28 +64,41 @@ __global__ void target_kernel(const uint64_t* masks, int B, const double* hd, co
   target[b] = e;
 }
 
+// one thread per sample; the workgroup accumulates its samples' contributions to G and
+// to the loss in LDS (R + 1 doubles of dynamic shared memory), then adds them to global
+// memory once per entry
 __global__ void misfit_kernel(const uint64_t* masks, int B, const double* th, const double* delta,
                               const double* target, int L, int N, double scale, double lscale, double* G,
                               double* loss) {
+  extern __shared__ double acc[];
+  const int R = L * (N + 1);
+  for (int r = threadIdx.x; r <= R; r += blockDim.x) acc[r] = 0.0;
+  __syncthreads();
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const uint64_t m = masks[b];
-  double d = 0.0;
-  int n = 0;
-  for (int i = 0; i < L && n <= N; ++i) {
-    if (!((m >> i) & 1u)) continue;
-    if (n < N) d += th[i] + delta[i * (N + 1) + n];
-    ++n;
+  if (b < B) {
+    const uint64_t m = masks[b];
+    double d = 0.0;
+    int n = 0;
+    for (int i = 0; i < L && n <= N; ++i) {
+      if (!((m >> i) & 1u)) continue;
+      if (n < N) d += th[i] + delta[i * (N + 1) + n];
+      ++n;
+    }
+    if (n == N) {  // an N-particle determinant (others do not contribute)
+      const double e = d - target[b];
+      n = 0;
+      for (int i = 0; i < L; ++i) {
+        if (!((m >> i) & 1u)) continue;
+        atomicAdd(acc + i * (N + 1) + n, scale * e);
+        ++n;
+      }
+      atomicAdd(acc + R, lscale * e * e);
+    }
   }
-  if (n != N) return;  // not an N-particle determinant: no contribution
-  const double e = d - target[b];
-  n = 0;
-  for (int i = 0; i < L; ++i) {
-    if (!((m >> i) & 1u)) continue;
-    atomicAdd(G + i * (N + 1) + n, scale * e);
-    ++n;
-  }
-  atomicAdd(loss, lscale * e * e);
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (acc[r] != 0.0) atomicAdd(G + r, acc[r]);
+  if (threadIdx.x == 0) atomicAdd(loss, acc[R]);
 }
 
 __global__ void dz_kernel(const double* G, const double* tz, int R, double dmax, double* dz) {
@@ -100,12 +113,24 @@ __global__ void tanh_grad_kernel(double* dA, const double* H, int64_t n) {
   dA[e] *= 1.0 - H[e] * H[e];
 }
 
+// 64 rows per workgroup: lane l takes row 64 blockIdx.x + l, the four wavefronts take
+// every fourth column, eight independent partial sums per thread; LDS sums the wavefronts
 __global__ void rowsum_kernel(const double* A, int rows, int cols, int ld, double* out) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= rows) return;
-  double s = 0.0;
-  for (int c = 0; c < cols; ++c) s += A[u + (int64_t)c * ld];
-  out[u] = s;
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int u = blockIdx.x * 64 + lane;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (u < rows) {
+    int c = w;
+    for (; c + 28 < cols; c += 32) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += A[u + (int64_t)(c + 4 * k) * ld];
+    }
+    for (; c < cols; c += 4) s[0] += A[u + (int64_t)c * ld];
+  }
+  part[w][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  __syncthreads();
+  if (w == 0 && u < rows) out[u] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 __global__ void adam_kernel(float* w, float* m, float* v, const double* g, int64_t P, float lr, float b1, float b2,
@@ -153,9 +178,10 @@ void launch_mlp_target(const uint64_t* masks, int B, const double* hd, const dou
 
 void launch_mlp_misfit(const uint64_t* masks, int B, const double* th, const double* delta, const double* target,
                        int L, int N, double scale, double lscale, double* G, double* loss, hipStream_t s) {
+  const size_t shm = (size_t(L) * (N + 1) + 1) * sizeof(double);  // at most 64 x 65 + 1 doubles
   if (B > 0)
-    hipLaunchKernelGGL(misfit_kernel, dim3(blocks(B)), dim3(kThreads), 0, s, masks, B, th, delta, target, L, N, scale,
-                       lscale, G, loss);
+    hipLaunchKernelGGL(misfit_kernel, dim3(blocks(B)), dim3(kThreads), shm, s, masks, B, th, delta, target, L, N,
+                       scale, lscale, G, loss);
 }
 
 void launch_mlp_dz(const double* G, const double* tz, int R, double dmax, double* dz, hipStream_t s) {
@@ -167,7 +193,7 @@ void launch_mlp_tanh_grad(double* dA, const double* H, int64_t n, hipStream_t s)
 }
 
 void launch_mlp_rowsum(const double* A, int rows, int cols, int ld, double* out, hipStream_t s) {
-  if (rows > 0) hipLaunchKernelGGL(rowsum_kernel, dim3(blocks(rows)), dim3(kThreads), 0, s, A, rows, cols, ld, out);
+  if (rows > 0) hipLaunchKernelGGL(rowsum_kernel, dim3((rows + 63) / 64), dim3(256), 0, s, A, rows, cols, ld, out);
 }
 
 void launch_mlp_adam(float* w, float* m, float* v, const double* g, int64_t P, float lr, float b1, float b2,
