@@ -197,3 +197,29 @@ def test_correction_errors(ctx, prob):
     bad_masks = np.array([0b111], dtype=np.uint64)  # three particles, N = 4
     with pytest.raises(native.PvError, match="PV_EINVAL"):
         ctx.learned_train(init_params(0), bad_masks, steps=1)
+
+
+def test_batch_keeps_each_context_correction():
+    # two contexts, one with a correction: the batched runs equal the individual ones
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    p = make_problem("decayed", L, N, 0)
+    corr = _table(p)
+    ctxs = [native.Context(0), native.Context(0)]
+    try:
+        for c in ctxs:
+            c.set_hamiltonian(p.h, p.v, N, p.gamma)
+        ctxs[1].set_correction(corr)
+        kw = dict(rank_cap=16, max_iter=4, tau=0.0, delta=10.0)
+        single = []
+        for c in ctxs:
+            res, _, psi = c.run(**kw)
+            c.mps_free(psi)
+            single.append(res["energy"])
+        batch = native.run_batch(ctxs, [kw, kw])
+        assert [r["energy"] for r in batch] == single
+        assert single[0] != single[1]  # the correction changed the path
+    finally:
+        for c in ctxs:
+            c.close()
