@@ -287,7 +287,9 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
  * over the nmask determinants m_b (bit i = orbital i; each must hold N particles within
  * the L <= 64 orbitals).  params is updated in place; loss (NULL or steps + 1 doubles)
  * receives the loss before each step and after the last; grad (NULL or PV_MLP_PARAMS
- * doubles) the gradient at the final parameters. */
+ * doubles) the gradient at the final parameters.  PV_EINVAL for nmask < 1, steps < 0,
+ * lr < 0, L > 64 or a mask with the wrong particle number; the Adam moments start at
+ * zero on every call. */
 #define PV_MLP_WIDTH 256
 #define PV_MLP_PARAMS (PV_MLP_WIDTH * 6 + PV_MLP_WIDTH + PV_MLP_WIDTH * PV_MLP_WIDTH + PV_MLP_WIDTH + PV_MLP_WIDTH + 1)
 pv_status pv_set_correction(pv_ctx* ctx, const double* delta);
