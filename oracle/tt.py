@@ -79,6 +79,25 @@ def select(svals: dict, delta: float, cap: int, zero_tol: float = ZERO_TOL):
     return kept, cap_bound, margin
 
 
+def select_floor(svals: dict, delta: float, cap: int, zero_tol: float = ZERO_TOL_PARALLEL):
+    """``select`` for singular values that are only accurate to a numerical-zero level
+    zero_tol * sigma_max (those of the simultaneous truncation, from Gram matrices).
+    The values at or below that level are dropped as zeros, as in ``select``; since
+    their weight is not known to be zero, the tolerance counts as met only when their
+    sum of squares is at most delta^2 as well (for delta > 0; delta = 0 asks for the
+    numerically exact truncation).  Otherwise "cap bound" is reported:
+    the truncation could not certify its tolerance, which stops the retry loop of
+    Algorithm 2 like a binding rank cap."""
+    kept, cap_bound, margin = select(svals, delta, cap, zero_tol)
+    allv = [s for sv in svals.values() for s in sv]
+    if allv:
+        smax = max(allv)
+        floor2 = sum(s * s for s in allv if s <= zero_tol * smax)
+        if smax > 0 and delta > 0 and floor2 > delta * delta:
+            cap_bound = True
+    return kept, cap_bound, margin
+
+
 def truncate(x: np.ndarray, L: int, N: int, eps: float, cap: int, zero_tol: float = ZERO_TOL):
     """Sequential TT-SVD truncation.  Returns (y, rho, cap_bound, min_margin, svals).
 
@@ -143,11 +162,14 @@ def truncate_parallel(x: np.ndarray, L: int, N: int, eps: float, cap: int,
 
     P_k is the orthogonal projector onto the kept left singular vectors of the k-th
     blocked matricisation of the ORIGINAL x (acting on orbitals 1..k), with the ranks of
-    every bond chosen independently by rules 1-4 with the per-bond tolerance eps/(L-1).
-    Since each P_k has norm one, ||x - y|| <= sum_k ||(I - P_k) x|| <= eps (the triangle
-    inequality replaces the orthogonality behind the sqrt(L-1) form of eq. ttsvdquasiopt).
+    every bond chosen independently by ``select_floor`` with the per-bond tolerance
+    eps/sqrt(L-1).  The error splits orthogonally: x - P_1 Y = (I - P_1) x + P_1 (x - Y)
+    with Y = P_2 ... P_{L-1} x, the two parts in complementary ranges, so
+    ||x - y||^2 <= ||(I - P_1) x||^2 + ||x - Y||^2 <= sum_k ||(I - P_k) x||^2, and each
+    term is the discarded tail of bond k: the first inequality of eq. ttsvdquasiopt
+    holds for these projectors too, and ||x - y|| <= eps.
     Returns (y, rho, cap_bound, min_margin)."""
-    delta = eps / (L - 1) if L > 1 else eps
+    delta = eps / math.sqrt(L - 1) if L > 1 else eps
     rho = [dict() for _ in range(L + 1)]
     rho[0] = {0: 1}
     rho[L] = {N: 1}
@@ -164,7 +186,7 @@ def truncate_parallel(x: np.ndarray, L: int, N: int, eps: float, cap: int,
                 continue
             U, s, _ = np.linalg.svd(B, full_matrices=False)
             svd[n], sv[n] = U, s
-        kept, cb, margin = select(sv, delta, cap, zero_tol)
+        kept, cb, margin = select_floor(sv, delta, cap, zero_tol)
         cap_bound |= cb
         min_margin = min(min_margin, margin)
         rho[k] = dict(kept)

@@ -153,3 +153,32 @@ def test_parallel_truncation_single_binding_bond_equals_sequential():
     y2, r2, _, _ = tt.truncate_parallel(x, L, N, 0.0, cap)
     assert np.allclose(y1, y2, atol=1e-12)
     assert r1 == r2
+
+
+@pytest.mark.parametrize("eps", [0.02, 0.1, 0.2])
+def test_parallel_truncation_keeps_the_least_ranks_of_the_sqrt_split(eps):
+    """Each bond of the simultaneous truncation keeps the least count whose discarded tail
+    of x's own singular values is at most eps^2/(L-1) (eq. ttsvdquasiopt read for the
+    projectors P_k: x - P_1 Y is an orthogonal sum), and the error obeys
+    ||x - y||^2 <= sum of the tails <= eps^2.  A split eps/(L-1) would keep more."""
+    L, N = 9, 4
+    # a state with decaying singular values: low-rank parts of decreasing weight
+    x = sum(w * mps.to_dense(L, N, rho_table(L, N, r), random_block_mps(L, N, rho_table(L, N, r), 20 + r))
+            for w, r in ((1.0, 2), (0.3, 4), (0.1, 8))) + 0.02 * _sector_vector(L, N, 7)
+    x /= np.linalg.norm(x)
+    y, rho, cb, _ = tt.truncate_parallel(x, L, N, eps, cap=10 ** 6)
+    assert not cb
+    d2 = eps * eps / (L - 1)
+    tails = 0.0
+    looser = 0
+    for k in range(1, L):
+        sv = np.sort(np.concatenate([s for s in tt.singular_values(x, L, N, k).values()]))[::-1]
+        s = sum(rho[k].values())
+        tail = float(np.sum(sv[s:] ** 2))
+        assert tail <= d2 * (1 + 1e-12)
+        assert float(np.sum(sv[s - 1:] ** 2)) > d2
+        tails += tail
+        s_lin = int(np.argmax(np.concatenate([np.cumsum((sv ** 2)[::-1])[::-1], [0.0]]) <= (eps / (L - 1)) ** 2))
+        looser += s_lin > s
+    assert np.linalg.norm(x - y) ** 2 <= tails * (1 + 1e-10) <= eps * eps * (1 + 1e-10)
+    assert looser > 0  # the split eps/(L-1) would keep more
