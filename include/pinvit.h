@@ -78,7 +78,7 @@ typedef struct {
                      *    values give PV_EINVAL */
   int truncation;   /* 0: sequential TT-SVD truncation (eq. ttsvdquasiopt), two-pass Gram
                      *    factorisations; 1: simultaneous truncation of all bonds from Gram
-                     *    matrices (tolerance eps/(L-1) per bond), see pv_set_truncation */
+                     *    matrices (tolerance eps/sqrt(L-1) per bond), see pv_set_truncation */
   /* Resume state from a previous pv_run (pv_result fields eta_res, s_last, s_prev);
    * resume_s <= 0 starts afresh with a trial residual for the first tolerance. */
   double resume_eta, resume_s, resume_s2;
@@ -97,9 +97,18 @@ typedef struct {
   double eta_psi;     /* truncation tolerance of the update */
   double seconds;     /* wall time of the iteration */
   int retries;        /* tolerance reductions (x 4/5) taken */
-  int cap_bound;      /* 1 if any truncation of the iteration was limited by rank_cap */
+  int cap_bound;      /* 1 if any truncation of the iteration was limited by rank_cap, the
+                       * intermediate rank m_zip dropped a singular value, or a simultaneous
+                       * truncation could not certify its tolerance (see pv_set_truncation) */
   int max_rank;       /* maximal bond rank of the new iterate */
   int stopped;        /* 1 on the iteration where the tolerance test succeeded */
+  int zip_bound;      /* 1 if m_zip dropped a singular value above the numerical-zero level in
+                       * the H application of the accepted residual: r is then not within
+                       * eta_res of H_gamma psi - lambda psi, rho and bound are estimates, and
+                       * the run does not stop on them */
+  double zip_discard; /* sqrt of the sum of the squared singular values that m_zip dropped
+                       * there, in the panels' own metric (the discarded part of H psi is
+                       * that weight times at most the norm of the operator's right parts) */
 } pv_iter;
 
 typedef struct {
@@ -174,9 +183,13 @@ pv_status pv_mps_free(pv_ctx* ctx, int handle);
  *   most (eps/sqrt(L-1))^2.  Singular values from a two-pass Gram eigendecomposition.
  * mode 1: simultaneous truncation P_1 ... P_{L-1} x, P_k the projector onto the kept left
  *   singular vectors of the k-th matricisation of x itself, every bond decided from the
- *   left and right Gram matrices in one batched step with tolerance eps/(L-1), so that
- *   ||x - trunc(x)|| <= eps by the triangle inequality.  Singular values accurate to about
- *   1e-8 relative; the intermediate-rank H application uses single-pass factorisations. */
+ *   left and right Gram matrices in one batched step with tolerance eps/sqrt(L-1); since
+ *   x - P_1 Y = (I - P_1) x + P_1 (x - Y) is an orthogonal sum, ||x - trunc(x)||^2 is at
+ *   most the sum of the bonds' discarded tails (eq. ttsvdquasiopt).  Singular values are
+ *   accurate to about 1e-8 of the largest; those at or below 1e-6 of it are numerical
+ *   zeros, and when their weight exceeds a bond's share of eps^2 the tolerance is not
+ *   certified and cap_bound is reported.  The intermediate-rank H application uses
+ *   single-pass factorisations. */
 pv_status pv_set_truncation(pv_ctx* ctx, int mode);
 
 /* <a|b> (Euclidean inner product) by a transfer sweep. */
@@ -189,9 +202,16 @@ pv_status pv_lincomb(pv_ctx* ctx, double a, int x, double b, int y, int* out);
  * per bond, at most `cap` total rank per bond.  Result left-orthogonal, norm in the last
  * core.  *cap_bound (may be NULL) is set to 1 when the cap limited a bond. */
 pv_status pv_round(pv_ctx* ctx, int x, double eps, int cap, int* out, int* cap_bound);
-/* trunc(H_gamma x; eps, cap), H applied site by site with intermediate rank m_zip
- * (m_zip <= 0: exact product). */
-pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound);
+/* trunc(H_gamma x; eps, cap), H applied site by site (Section 2.4, applied one site at a
+ * time) with intermediate rank m_zip (m_zip <= 0: exact product up to numerical zeros):
+ * x is made right-orthogonal, then at site k the carry is contracted with x_k and the MPO
+ * core and the panel of every new sector is factorised; across the sectors the m_zip
+ * largest singular values are kept.  The intermediate result is Q Q^T H x for the
+ * orthonormal left basis Q it builds.  *cap_bound (may be NULL) is set when the cap or
+ * m_zip limited a rank; *zip_discard (may be NULL) receives the square root of the sum
+ * of the squared singular values that m_zip dropped, in the panels' own metric. */
+pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound,
+                     double* zip_discard);
 /* S x by the sorted sequential truncated sum of Lemma truncr with total tolerance eta. */
 pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap_bound);
 

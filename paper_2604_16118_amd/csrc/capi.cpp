@@ -510,12 +510,15 @@ pv_status pv_round(pv_ctx* ctx, int x, double eps, int cap, int* out, int* cap_b
   });
 }
 
-pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound) {
+pv_status pv_apply_h(pv_ctx* ctx, int x, double eps, int cap, int m_zip, int* out, int* cap_bound,
+                     double* zip_discard) {
   return guard([&] {
     if (!ctx || !out) fail(PV_EINVAL, "null argument");
     if (!(eps >= 0) || cap < 1) fail(PV_EINVAL, "need eps >= 0 and cap >= 1");
     bool cb = false;
-    auto m = apply_h(ctx->c, get(ctx->c, x), eps, cap, m_zip, &cb);
+    double zd2 = 0.0;
+    auto m = apply_h(ctx->c, get(ctx->c, x), eps, cap, m_zip, &cb, &zd2);
+    if (zip_discard) *zip_discard = std::sqrt(zd2);
     ctx->c.sync();
     *out = put(ctx->c, std::move(m));
     if (cap_bound) *cap_bound = cb;
@@ -610,14 +613,15 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       int retries = 0;
       bool capb = false;
       std::unique_ptr<Mps> r, s;
-      double ns = 0;
+      double ns = 0, zd2 = 0;
       while (true) {
         bool cb1 = false, cb2 = false, cb3 = false;
         const double e12 = eta / (3.0 * c.s_max);
         std::unique_ptr<Mps> y;
+        zd2 = 0.0;
         {
           LowPrecision lp(c);
-          y = apply_h(c, *psi, e12, cap, mz, &cb1);
+          y = apply_h(c, *psi, e12, cap, mz, &cb1, &zd2);
         }
         auto d = mps_lincomb(c, 1.0, *y, -lam, *psi);
         y.reset();
@@ -645,11 +649,15 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       rec.eta_res = eta;
       rec.retries = retries;
       rec.cap_bound = (capb || cb4) ? 1 : 0;
+      rec.zip_discard = std::sqrt(zd2);
+      rec.zip_bound = zd2 > 0.0 ? 1 : 0;
       res->energy = rec.energy;
       res->lambda = lam;
       res->rho = rho;
       res->bound = bound;
-      if (bound <= p.tau) {
+      // with a binding intermediate rank the residual is not within eta_res of the true
+      // one, so the bound is not certified and the run does not stop on it
+      if (bound <= p.tau && !rec.zip_bound) {
         rec.stopped = 1;
         rec.max_rank = psi->max_rank();
         c.sync();

@@ -628,6 +628,19 @@ std::vector<int> select_ranks(const std::vector<std::vector<double>>& sig, doubl
   return kept;
 }
 
+// Sum of the squares of the singular values above the numerical-zero level that a rank
+// selection left out (sig[n] descending; keep[n] leading values of sector n kept).
+double dropped_weight(const std::vector<std::vector<double>>& sig, const std::vector<int>& keep, double zero_tol) {
+  double smax = 0.0;
+  for (const auto& v : sig)
+    for (double x : v) smax = std::max(smax, x);
+  double d2 = 0.0;
+  for (size_t n = 0; n < sig.size(); ++n)
+    for (size_t j = size_t(std::max(keep[n], 0)); j < sig[n].size(); ++j)
+      if (sig[n][j] > zero_tol * smax) d2 += sig[n][j] * sig[n][j];
+  return d2;
+}
+
 std::vector<double> download(Ctx& c, const double* p, size_t n) {
   std::vector<double> h(n);
   if (n) PV_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -1590,7 +1603,10 @@ BondEig eig_grams(Ctx& c, const Mps& x, const BondGrams& g, int kmin, int kmax, 
 // kept singular values.
 std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound) {
   const int L = x.L, N = x.N;
-  const double delta = L > 1 ? eps / double(L - 1) : eps;
+  // x - P_1 Y = (I - P_1) x + P_1 (x - Y), Y = P_2 ... P_{L-1} x, splits into parts with
+  // complementary ranges, so ||x - y||^2 <= sum_k ||(I - P_k) x||^2 (the first inequality
+  // of eq. ttsvdquasiopt) and eps/sqrt(L-1) per bond gives ||x - y|| <= eps
+  const double delta = L > 1 ? eps / std::sqrt(double(L - 1)) : eps;
   // the right Grams (a chain over k = L..2) run on the side stream beside the left Grams
   // (k = 1..L-1) and their Cholesky factorisations
   struct SideChain {
@@ -1670,9 +1686,16 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
     std::vector<int> keep(N + 1, 0);
     if (smax > 0) {
       std::vector<std::vector<double>> sig2(N + 1);
+      double floor2 = 0.0;  // weight of the values at the numerical-zero level
       for (int n = 0; n <= N; ++n)
-        for (double v : sig[n]) if (v > kZeroTolPar * smax) sig2[n].push_back(v);
+        for (double v : sig[n]) {
+          if (v > kZeroTolPar * smax) sig2[n].push_back(v);
+          else floor2 += v * v;
+        }
       keep = select_ranks(sig2, delta, cap, cap_bound);
+      // the dropped zero-level values are only known to that level: the tolerance is
+      // certified only when their weight fits in it too (exact requests, delta = 0, aside)
+      if (delta > 0 && floor2 > delta * delta && cap_bound) *cap_bound = true;
     }
     for (int n = 0; n <= N; ++n)
       if (x.valid(k, n)) rho[k][n] = keep[n];
@@ -1749,7 +1772,8 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
 // the two-pass Gram eigendecomposition of T2 T2^T, its leading left singular vectors
 // become the new core and the carry is their transpose times T2.  With m_zip <= 0 only
 // numerical zeros are dropped, which gives H x up to rounding; then trunc(.; eps, cap).
-std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_zip, bool* cap_bound) {
+std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_zip, bool* cap_bound,
+                             double* zip_disc2) {
   if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
   const DevMpo& op = *c.hmpo;
   const int L = xin.L, N = xin.N;
@@ -1758,6 +1782,7 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
   if (m_zip > 0) xr = orthogonalize_right(c, xin, two_pass);
   const Mps& x = m_zip > 0 ? *xr : xin;
   const int zcap = m_zip > 0 ? m_zip : (1 << 30);
+  double disc2 = 0.0;  // squared singular values the intermediate rank dropped
   auto rho = empty_rho(L, N);
   rho[0][0] = 1;
   auto y = std::make_unique<Mps>();
@@ -1822,6 +1847,7 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
       EigPlan plan = run_eig_values(c, jobs);
       auto sig = sigmas(c, se);
       std::vector<int> keep = select_ranks(sig, 0.0, zcap, nullptr, kZeroTolPar);
+      disc2 += dropped_weight(sig, keep, kZeroTolPar);
       std::vector<int> nvec(N + 1, 0);
       for (int n2 = 0; n2 <= N; ++n2) nvec[n2] = se[n2].n > 0 ? keep[n2] : 0;
       run_eig_vectors(c, plan, &nvec);
@@ -1889,6 +1915,7 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
     std::vector<std::vector<double>> sig_all(N + 1);
     for (int n2 = 0; n2 <= N; ++n2) sig_all[n2] = sig[n2];
     std::vector<int> keep = select_ranks(sig_all, 0.0, zcap, nullptr, two_pass ? kZeroTol : kZeroTolPar);
+    disc2 += dropped_weight(sig_all, keep, two_pass ? kZeroTol : kZeroTolPar);
     for (int n2 = 0; n2 <= N; ++n2) y->rho[k][n2] = y->valid(k, n2) ? keep[n2] : 0;
     alloc_site(c, *y, k);
     fill(c, y->site[k - 1].p, y->site_size(k), 0.0);
@@ -1919,6 +1946,10 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
     Le = std::move(Lc);
   }
   c.scratch.push_back(std::move(C));
+  // a binding intermediate rank is reported like a binding rank cap: the result is no
+  // longer within eps of H x, so the tolerance of the caller is not certified
+  if (disc2 > 0.0 && cap_bound) *cap_bound = true;
+  if (zip_disc2) *zip_disc2 += disc2;
   return round_mps(c, *y, eps, cap, cap_bound);
 }
 

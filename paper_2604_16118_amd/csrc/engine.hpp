@@ -200,7 +200,11 @@ std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevM
 double dot(Ctx& c, const Mps& a, const Mps& b);
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket);
 std::unique_ptr<Mps> round_mps(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
-std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& x, double eps, int cap, int m_zip, bool* cap_bound);
+// trunc(H x; eps, cap) with intermediate rank m_zip; *zip_disc2 (may be null) is
+// incremented by the sum of the squared singular values that m_zip dropped in the panels
+// (in their own metric), and *cap_bound is set when that sum is positive.
+std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& x, double eps, int cap, int m_zip, bool* cap_bound,
+                             double* zip_disc2 = nullptr);
 std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* cap_bound);
 std::unique_ptr<DevMpo> upload_mpo(Ctx& c, const Mpo& m);
 double norm_canonical(Ctx& c, const Mps& x);

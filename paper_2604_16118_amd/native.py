@@ -52,7 +52,8 @@ class Iter(C.Structure):
                 ("bound", C.c_double), ("r_norm", C.c_double), ("s_norm", C.c_double),
                 ("eta_res", C.c_double), ("lambda_star", C.c_double), ("eta_psi", C.c_double),
                 ("seconds", C.c_double), ("retries", C.c_int), ("cap_bound", C.c_int),
-                ("max_rank", C.c_int), ("stopped", C.c_int)]
+                ("max_rank", C.c_int), ("stopped", C.c_int), ("zip_bound", C.c_int),
+                ("zip_discard", C.c_double)]
 
 
 class OuterIter(C.Structure):
@@ -107,7 +108,8 @@ def lib():
         L.pv_expect_h.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.pv_lincomb.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int, ip]
         L.pv_round.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
-        L.pv_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, ip, ip]
+        L.pv_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, ip, ip,
+                                 C.POINTER(C.c_double)]
         L.pv_apply_s.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip]
         L.pv_run.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.POINTER(Result),
                              C.POINTER(Iter), C.c_int, ip]
@@ -283,9 +285,14 @@ class Context:
         _check(lib().pv_round(self._p, x, float(eps), int(cap), C.byref(out), C.byref(cb)))
         return out.value, bool(cb.value)
 
-    def apply_h(self, x, eps, cap, m_zip=0):
-        out, cb = C.c_int(), C.c_int()
-        _check(lib().pv_apply_h(self._p, x, float(eps), int(cap), int(m_zip), C.byref(out), C.byref(cb)))
+    def apply_h(self, x, eps, cap, m_zip=0, with_discard=False):
+        """(handle, cap_bound) of trunc(H x); with_discard also returns the weight m_zip
+        dropped (pv_apply_h's zip_discard)."""
+        out, cb, zd = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().pv_apply_h(self._p, x, float(eps), int(cap), int(m_zip), C.byref(out), C.byref(cb),
+                                C.byref(zd)))
+        if with_discard:
+            return out.value, bool(cb.value), zd.value
         return out.value, bool(cb.value)
 
     def apply_s(self, x, eta, cap):
@@ -310,7 +317,8 @@ class Context:
                              s_norm=r.s_norm, eta=r.eta_res, lam_star=r.lambda_star,
                              eta_psi=r.eta_psi, seconds=r.seconds, retries=r.retries,
                              cap_bound=bool(r.cap_bound), max_rank=r.max_rank,
-                             stop=bool(r.stopped)))
+                             stop=bool(r.stopped), zip_bound=bool(r.zip_bound),
+                             zip_disc=r.zip_discard))
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
                     iterations=res.iterations, converged=bool(res.converged),
                     eta_res=res.eta_res, s_last=res.s_last, s_prev=res.s_prev), rows, psi.value
