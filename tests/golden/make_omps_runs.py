@@ -1,0 +1,61 @@
+"""Writes the stored Algorithm 2 histories of the block-sparse MPS oracle that the GPU
+parity tests compare with (runs too long to repeat inside a test).
+
+Usage:  python tests/golden/make_omps_runs.py [name ...]   (default: every run below)
+
+Each run writes tests/golden/omps_<name>.json: the parameters and, per iteration, the
+energy, Rayleigh quotient, residual bound, norms, tolerance, retries, flags and the block
+table of the new iterate.  Only the oracle (oracle.bsmps) and the input generators
+(synth) are called.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import bsmps, pinvit  # noqa: E402
+from synth import make_problem  # noqa: E402
+
+# the plain float64 workload at L = 24: decayed integrals seed 0, N = 12, rank cap 128,
+# the exact H application (m_zip <= 0: intermediate ranks up to the full sector
+# dimensions, at most 4096 per bond), sequential truncation, 50 iterations
+RUNS = {
+    "L24_N12_cap128_exact": dict(kind="decayed", L=24, N=12, seed=0, cap=128, m_zip=0, iters=50,
+                                 truncation="sequential", c=0.5, delta=10.0, tau=0.0),
+}
+
+
+def make(name: str) -> str:
+    cfg = RUNS[name]
+    p = make_problem(cfg["kind"], cfg["L"], cfg["N"], cfg["seed"])
+    prm = pinvit.Params(cap=cfg["cap"], max_iter=cfg["iters"], tau=cfg["tau"], c=cfg["c"],
+                        delta=cfg["delta"], truncation=cfg["truncation"])
+    out = os.path.join(HERE, f"omps_{name}.json")
+    rows = []
+    t0 = time.time()
+
+    def record(rec, psi):
+        rows.append(rec)
+        print(f"# {name}: iteration {rec['it']} E={rec['E']:.12f} retries={rec['retries']} "
+              f"max_rank={rec['max_rank']} ({time.time() - t0:.0f}s)", flush=True)
+
+    _, hist, _ = bsmps.run(p.h, p.v, cfg["N"], p.gamma, prm, m_zip=cfg["m_zip"], callback=record)
+    keep = ("it", "lam", "E", "rho", "r_norm", "s_norm", "eta", "retries", "cap_bound", "zip_bound",
+            "zip_disc", "max_rank", "lam_star", "eta_psi")
+    data = {"name": name, "config": cfg, "gamma": p.gamma,
+            "history": [{**{k: (bool(r[k]) if isinstance(r[k], bool) else r[k]) for k in keep if k in r},
+                         "rho_tab": [[int(v) for v in row] for row in r["rho_tab"]] if "rho_tab" in r else None}
+                        for r in hist]}
+    with open(out, "w") as f:
+        json.dump(data, f, indent=0)
+    return out
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(RUNS)):
+        print(make(name), flush=True)

@@ -1,0 +1,123 @@
+"""GPU parity against the block-sparse MPS oracle (oracle/bsmps.py) where the dense oracle
+cannot go: the H application with a binding intermediate rank m_zip, Algorithm 2 runs
+with m_zip and the rank cap both binding, and the plain float64 workload at L = 24 (rank
+cap 128, exact H application, 50 iterations) against the oracle's stored history."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bsmps, pinvit
+from synth import make_problem, random_block_mps, rho_table
+
+pytestmark = pytest.mark.gpu
+
+native = pytest.importorskip("paper_2604_16118_amd.native")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("m_zip", [6, 16, 40, "exact"])
+def test_apply_h_with_binding_m_zip_matches_oracle(ctx, m_zip):
+    L, N = 12, 6
+    p = make_problem("decayed", L, N, 0)
+    rho = rho_table(L, N, 20)
+    data = random_block_mps(L, N, rho, 3, isometric=True)
+    x = bsmps.from_export(L, N, rho, data)
+    mpo = bsmps.build_mpo(p.h, p.v, p.gamma / N)
+    exact_rank = bsmps.zipup(x, mpo, 0)[0].max_rank()
+    binding = m_zip != "exact"
+    m_zip = exact_rank if m_zip == "exact" else m_zip
+    y_o, cb_o, d2 = bsmps.apply_h(x, mpo, 0.0, 10 ** 6, m_zip)
+    ref = bsmps.to_dense(y_o)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    ctx.set_truncation(0)
+    h = ctx.mps_create(rho, data)
+    y, cb, disc = ctx.apply_h(h, 0.0, 10 ** 6, m_zip, with_discard=True)
+    rr, dd = ctx.mps_download(y)
+    got = bsmps.to_dense(bsmps.from_export(L, N, rr, dd))
+    ctx.mps_free(h)
+    ctx.mps_free(y)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert cb == cb_o
+    assert disc == pytest.approx(math.sqrt(d2), rel=1e-8, abs=1e-12 * np.linalg.norm(ref))
+    assert (disc > 0) == binding and cb == binding
+
+
+def _compare_runs(ctx, kind, L, N, seed, cap, m_zip, iters, mode, tol):
+    p = make_problem(kind, L, N, seed)
+    prm = pinvit.Params(cap=cap, max_iter=iters, tau=0.0, c=0.5, delta=10.0, truncation=mode)
+    psi_o, hist_o, _ = bsmps.run(p.h, p.v, N, p.gamma, prm, m_zip=m_zip)
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    _, hist_g, psi = ctx.run(rank_cap=cap, max_iter=iters, tau=0.0, c=0.5, delta=10.0, m_zip=m_zip,
+                             truncation=0 if mode == "sequential" else 1)
+    assert len(hist_g) == len(hist_o)
+    for a, b in zip(hist_g, hist_o):
+        assert abs(a["E"] - b["E"]) <= tol * abs(b["E"]), (a["E"], b["E"])
+        if tol <= 1e-10:
+            assert a["retries"] == b["retries"]
+            assert a["cap_bound"] == b["cap_bound"]
+            assert a["zip_bound"] == b["zip_bound"]
+            assert a["zip_disc"] == pytest.approx(b["zip_disc"], rel=1e-6, abs=1e-12)
+            assert a["max_rank"] == b["max_rank"]
+    rr, dd = ctx.mps_download(psi)
+    ctx.mps_free(psi)
+    x = bsmps.from_export(L, N, rr, dd)
+    ov = bsmps.dot(x, psi_o) / (bsmps.norm(x) * bsmps.norm(psi_o))
+    assert abs(abs(ov) - 1) <= (1e-8 if tol <= 1e-10 else 1e-4)
+    return hist_g
+
+
+def test_run_with_binding_m_zip_and_cap_matches_oracle_L12(ctx):
+    hist = _compare_runs(ctx, "decayed", 12, 6, 0, 24, 16, 8, "sequential", 1e-10)
+    assert all(r["zip_bound"] for r in hist) and all(r["cap_bound"] for r in hist[2:])
+
+
+def test_run_with_binding_m_zip_and_cap_matches_oracle_L16(ctx):
+    hist = _compare_runs(ctx, "decayed", 16, 8, 0, 48, 32, 6, "sequential", 1e-10)
+    assert all(r["zip_bound"] for r in hist[1:])
+
+
+def test_run_with_binding_m_zip_simultaneous_truncation(ctx):
+    # single-pass factorisations and the simultaneous truncation: the GPU's singular
+    # values are accurate to about 1e-8 of the largest, the oracle's to rounding
+    _compare_runs(ctx, "decayed", 12, 6, 0, 24, 16, 8, "parallel", 1e-6)
+
+
+@pytest.mark.timeout(600)
+def test_plain_float64_L24_cap128_50_iterations_matches_oracle(ctx):
+    """The plain float64 workload at L = 24 (N = 12, decayed integrals seed 0, rank cap
+    128, exact H application, sequential truncation, 50 iterations) against the history
+    the block-sparse oracle stored (tests/golden/make_omps_runs.py): every energy within
+    1e-10 relative, the same retries, cap flags and block tables of the iterates."""
+    path = os.path.join(GOLDEN, "omps_L24_N12_cap128_exact.json")
+    with open(path) as f:
+        gold = json.load(f)
+    cfg = gold["config"]
+    p = make_problem(cfg["kind"], cfg["L"], cfg["N"], cfg["seed"])
+    assert p.gamma == pytest.approx(gold["gamma"], rel=1e-15)
+    ctx.set_hamiltonian(p.h, p.v, cfg["N"], p.gamma)
+    print(f"# L24 cap128: {cfg['iters']} iterations", flush=True)
+    _, hist, psi = ctx.run(rank_cap=cfg["cap"], max_iter=cfg["iters"], tau=cfg["tau"], c=cfg["c"],
+                           delta=cfg["delta"], m_zip=cfg["m_zip"], truncation=0)
+    ctx.mps_free(psi)
+    ho = gold["history"]
+    assert len(hist) == len(ho) == cfg["iters"]
+    for a, b in zip(hist, ho):
+        assert abs(a["E"] - b["E"]) <= 1e-10 * abs(b["E"]), (b["it"], a["E"], b["E"])
+        assert a["retries"] == b["retries"]
+        assert a["cap_bound"] == b["cap_bound"]
+        assert a["max_rank"] == b["max_rank"]
+        assert a["rho"] == pytest.approx(b["rho"], rel=1e-6)

@@ -84,3 +84,17 @@ def test_drivers_reject_null_arguments_without_touching_a_device():
     for call in calls:
         assert call() == -1
         assert L.pv_last_error()
+
+
+@pytest.mark.parametrize("kind,L", [("dense", 8), ("decayed", 12), ("decayed", 16)])
+def test_mpo_bond_states_match_the_block_sparse_oracle(kind, L):
+    """The library's MPO and the block-sparse oracle's (built independently from the same
+    keying of the bond states) have the same number of states of every charge on every
+    cut, so the intermediate-rank H application factorises panels with the same columns."""
+    from oracle import bsmps
+    p = make_problem(kind, L, L // 2, 0)
+    d, q = native.mpo_bond_dims(p.h, p.v)
+    mpo = bsmps.build_mpo(p.h, p.v, 0.0)
+    for m in range(L + 1):
+        assert d[m] == mpo.w(m)
+        assert list(q[m]) == [mpo.wq(m, c) for c in (-2, -1, 0, 1, 2)]
