@@ -398,18 +398,11 @@ def trunc(x: BMps, eps: float, cap: int, mode: str = "sequential"):
 
 # ---------------------------------------------------------------- matrix product operator
 
-_CRE, _ANN = 0, 1
-_I2 = np.eye(2)
-_S2 = np.diag([1.0, -1.0])
-_A2 = np.array([[0.0, 1.0], [0.0, 0.0]])   # a: |0><1|, entry [s_out, s_in]
-_AT2 = _A2.T.copy()                       # a^*: |1><0|
-
-
 class Mpo:
     """Sites m = 0..L-1 (orbital m+1).  ``q[m]``: charge of every bond state at cut m
     (ascending); ``blocks[m][(q_in, q_out, s_out, s_in)]``: dense matrix over the states
     of charge q_in at cut m (rows) and of charge q_out at cut m+1 (columns); ``keys[m]``
-    the state keys (for inspection)."""
+    the state codes of ``_cut_states`` (for inspection)."""
 
     def __init__(self, L, q, blocks, keys):
         self.L, self.q, self.blocks, self.keys = L, q, blocks, keys
@@ -448,134 +441,183 @@ class Mpo:
         return ops[0]
 
 
-def _terms(h, v, shift):
-    """Terms (coefficient, [(type, orbital), ...]) of H + shift sum_i n_i in product order:
-    h_ij a_i^* a_j, and w_ijkl a_i^* a_j^* a_k a_l for i < j, k < l with
-    w_ijkl = v_ijkl - v_jikl - v_ijlk + v_jilk; exact zeros are skipped."""
+def _term_arrays(h, v, shift):
+    """The terms of H + shift sum_i n_i as arrays, in product order: h_ij a_i^* a_j for all
+    (i, j) (row-major), then w_ijkl a_i^* a_j^* a_k a_l for i < j, k < l (pairs row-major,
+    the created pair outer) with w_ijkl = v_ijkl - v_jikl - v_ijlk + v_jilk (the two-body
+    sum of eq. hamil antisymmetrised); exact zeros are skipped.  Returns (coef (T,),
+    cre (T, 4) bool: creator in that slot, pos (T, 4): orbital, -1 for an empty slot)."""
     L = h.shape[0]
-    coef, ops = [], []
-    for i in range(L):
-        for j in range(L):
-            c = h[i, j] + (shift if i == j else 0.0)
-            if c != 0.0:
-                coef.append(c)
-                ops.append(((_CRE, i), (_ANN, j)))
+    h1 = h + shift * np.eye(L)
+    i1, j1 = np.nonzero(h1 != 0.0)
     w = v - v.transpose(1, 0, 2, 3) - v.transpose(0, 1, 3, 2) + v.transpose(1, 0, 3, 2)
-    iu = [(i, j) for i in range(L) for j in range(i + 1, L)]
-    for i, j in iu:
-        for k, l in iu:
-            c = w[i, j, k, l]
-            if c != 0.0:
-                coef.append(c)
-                ops.append(((_CRE, i), (_CRE, j), (_ANN, k), (_ANN, l)))
-    return np.array(coef), ops
+    pi, pj = np.triu_indices(L, 1)
+    w2 = w[pi[:, None], pj[:, None], pi[None, :], pj[None, :]]  # [created pair, annihilated pair]
+    a2, b2 = np.nonzero(w2 != 0.0)
+    coef = np.concatenate([h1[i1, j1], w2[a2, b2]])
+    n1, n2 = len(i1), len(a2)
+    pos = np.full((n1 + n2, 4), -1, dtype=np.int64)
+    pos[:n1, 0], pos[:n1, 1] = i1, j1
+    pos[n1:, 0], pos[n1:, 1], pos[n1:, 2], pos[n1:, 3] = pi[a2], pj[a2], pi[b2], pj[b2]
+    cre = np.zeros((n1 + n2, 4), dtype=bool)
+    cre[:n1, 0] = True
+    cre[n1:, 0] = cre[n1:, 1] = True
+    return coef, cre, pos
 
 
-def _key(ops, m, L):
-    """Bond state of a term at cut m (sites < m on the left).  'I': no operator on the
-    left yet; 'F': all on the left; otherwise the term is keyed by the operators on the
-    side with fewer of them (on a tie: the left side when 2m < L, else the right side),
-    ('L', left ops) or ('R', right ops), in product order."""
-    left = tuple(o for o in ops if o[1] < m)
-    right = tuple(o for o in ops if o[1] >= m)
-    if not left:
-        return ("I",)
-    if not right:
-        return ("F",)
-    if len(left) < len(right) or (len(left) == len(right) and 2 * m < L):
-        return ("L", left)
-    return ("R", right)
+_KIND_I, _KIND_F, _KIND_L, _KIND_R = 0, 1, 2, 3
 
 
-def _charge(key):
-    """Particle-number change of the left part of every term through this state."""
-    if key[0] in ("I", "F"):
-        return 0
-    d = sum(1 if t == _CRE else -1 for t, _ in key[1])
-    return d if key[0] == "L" else -d
+def _cut_states(cre, pos, m, L):
+    """Bond state of every term at cut m (orbitals < m on the left), as (kind, code, charge).
+    kind 'I': no operator on the left yet; 'F': all of them on the left; otherwise the
+    term is keyed by the operators on the side with fewer of them (on a tie: the left side
+    when 2m < L, else the right side), kind 'L' (left operators) or 'R' (right ones).
+    The key's operators (at most two: the two-body terms have four) in product order,
+    each as 1 + creator * L + orbital, give the code; the charge is the change of the
+    particle number that the term's operators left of the cut make."""
+    valid = pos >= 0
+    left = valid & (pos < m)
+    nl = left.sum(axis=1)
+    nr = valid.sum(axis=1) - nl
+    kind = np.where(nl == 0, _KIND_I, np.where(nr == 0, _KIND_F,
+                    np.where((nl < nr) | ((nl == nr) & (2 * m < L)), _KIND_L, _KIND_R)))
+    keyop = np.where((kind == _KIND_L)[:, None], left, np.where((kind == _KIND_R)[:, None], valid & ~left, False))
+    e = np.where(keyop, 1 + cre * L + pos, 0)
+    rank = np.cumsum(keyop, axis=1)  # 1 for the key's first operator, 2 for its second
+    if np.any(rank[:, -1] > 2):
+        raise RuntimeError("a bond key holds more than two operators")
+    first = (e * (keyop & (rank == 1))).sum(axis=1)
+    second = (e * (keyop & (rank == 2))).sum(axis=1)
+    base = 2 * L + 1
+    code = (kind * base + first) * base + second
+    dq = (np.where(cre, 1, -1) * left).sum(axis=1)
+    return kind, code, dq
 
 
-def _factor(ops, m):
-    """Factor of the Kronecker product on site m: a_p = S x..x S (sites < p) x A (site p)
-    x I (sites > p) (eq. anniloperator), multiplied in product order."""
-    f = _I2
-    for t, p in ops:
-        if p < m:
-            g = _I2
-        elif p == m:
-            g = _AT2 if t == _CRE else _A2
-        else:
-            g = _S2
-        f = f @ g
-    return f
+def _site_factors(cre, pos, m):
+    """(T, 2, 2), entry [s_out, s_in]: factor of every term's Kronecker product on site m,
+    the ordered product over its operators of S (orbital above m), a or a^* (orbital m),
+    I (below m or no operator): a_p = S x .. x S (sites < p) x A (site p) x I (sites > p),
+    eq. anniloperator."""
+    T = pos.shape[0]
+    f00, f01, f10, f11 = np.ones(T), np.zeros(T), np.zeros(T), np.ones(T)
+    for slot in range(4):
+        p, c = pos[:, slot], cre[:, slot]
+        at = p == m
+        # entries of g: I = [[1,0],[0,1]], S = [[1,0],[0,-1]], a = [[0,1],[0,0]], a^* = [[0,0],[1,0]]
+        g00 = np.where(at, 0.0, 1.0)
+        g01 = (at & ~c).astype(np.float64)
+        g10 = (at & c).astype(np.float64)
+        g11 = np.where(at, 0.0, np.where(p > m, -1.0, 1.0))
+        f00, f01, f10, f11 = (f00 * g00 + f01 * g10, f00 * g01 + f01 * g11,
+                              f10 * g00 + f11 * g10, f10 * g01 + f11 * g11)
+    return np.stack([np.stack([f00, f01], axis=1), np.stack([f10, f11], axis=1)], axis=1)
 
 
 def build_mpo(h, v, shift=0.0):
     """MPO of H + shift sum_i n_i (shift = gamma/N gives H + gamma on F_N).
 
-    Every term is c * (x)_m f(m) with the Kronecker factors f(m) of ``_factor``.  Its bond
-    state at cut m is ``_key``; the states of one cut are those of all terms, ordered by
-    (charge, key).  A term's path of states has one site where it passes from a
-    left-type state ('I' or 'L') to a right-type state ('R' or 'F'); there its
-    coefficient enters: W[b, b'] += c r f(m).  On every other site the entry W[b, b'] is
-    shared by all terms with that pair of states; it is taken as the factor of the first
-    such term, and each other term's factor equals it up to a sign; r is the product of
-    those signs along the term's path.  A state's left (or right) path is fixed by its
-    key, so the product along every path is a sum of whole terms, and the MPO equals
+    Every term is c * (x)_m f(m) with the site factors f(m) of ``_site_factors``.  Its bond
+    state at cut m is given by ``_cut_states``; the states of a cut are those of all terms,
+    ordered by (charge, code).  Along the cuts a term's state is left-type ('I', 'L') up
+    to one site and right-type ('R', 'F') after it; on that site its coefficient enters:
+    W[b, b'] += c r f(m).  On every other site the entry W[b, b'] is shared by all terms
+    with that pair of states: it is the factor of the first such term (in term order),
+    and each other term's factor equals it up to a sign; r is the product of those signs
+    over the term's other sites.  A left-type state fixes the states before it (its key
+    holds the operators left of the cut) and a right-type one those after it, so every
+    path through the MPO is the path of whole terms and the MPO equals
     sum_t c_t (x)_m f_t(m)."""
     L = h.shape[0]
-    coef, terms = _terms(h, v, shift)
-    keys = []
-    for m in range(L + 1):
-        ks = {_key(t, m, L) for t in terms}
-        if m == 0:
-            ks.add(("I",))
-        if m == L:
-            ks.add(("F",))
-        keys.append(sorted(ks, key=lambda k: (_charge(k), repr(k))))
-    index = [{k: i for i, k in enumerate(ks)} for ks in keys]
-    qs = [np.array([_charge(k) for k in ks]) for ks in keys]
-    canon = [dict() for _ in range(L)]
-    trans = [dict() for _ in range(L)]
-    for c, t in zip(coef, terms):
-        path = [index[m][_key(t, m, L)] for m in range(L + 1)]
-        left_type = [keys[m][path[m]][0] in ("I", "L") for m in range(L + 1)]
-        mstar = next(m for m in range(L) if left_type[m] and not left_type[m + 1])
-        r = 1.0
-        for m in range(L):
-            if m == mstar:
-                continue
-            f = _factor(t, m)
-            pair = (path[m], path[m + 1])
-            g = canon[m].setdefault(pair, f)
-            sgn = 1.0 if np.array_equal(f, g) else (-1.0 if np.array_equal(f, -g) else 0.0)
-            if sgn == 0.0:
-                raise RuntimeError(f"shared MPO entry differs by more than a sign at site {m}")
-            r *= sgn
-        pair = (path[mstar], path[mstar + 1])
-        trans[mstar][pair] = trans[mstar].get(pair, 0.0) + c * r * _factor(t, mstar)
+    coef, cre, pos = _term_arrays(h, v, shift)
+    T = len(coef)
+    qs, keys, idx_prev, lt_prev = [], [], None, None
+    rsign = np.ones(T)
+    mstar = np.full(T, -1)
+    b_in = np.zeros(T, dtype=np.int64)
+    b_out = np.zeros(T, dtype=np.int64)
+    f_trans = np.zeros((T, 2, 2))
     blocks = []
-    for m in range(L):
-        pos_in = {i: int(np.sum(qs[m][:i] == qs[m][i])) for i in range(len(qs[m]))}
-        pos_out = {i: int(np.sum(qs[m + 1][:i] == qs[m + 1][i])) for i in range(len(qs[m + 1]))}
+    for m in range(L + 1):
+        kind, code, dq = _cut_states(cre, pos, m, L)
+        uc, first, inv = np.unique(code, return_index=True, return_inverse=True)
+        uq = dq[first]
+        order = np.lexsort((uc, uq))          # states by (charge, code)
+        rank = np.empty_like(order)
+        rank[order] = np.arange(len(order))
+        idx = rank[inv]
+        qs.append(uq[order])
+        keys.append(uc[order])
+        lt = (kind == _KIND_I) | (kind == _KIND_L)
+        if m == 0 and not np.all(kind == _KIND_I):
+            raise RuntimeError("a term has an operator left of the chain")
+        if m > 0:
+            site = m - 1
+            f = _site_factors(cre, pos, site)
+            trans = lt_prev & ~lt
+            if np.any(trans & (mstar >= 0)) or np.any(~lt_prev & lt):
+                raise RuntimeError("a term's state returns to the left type")
+            mstar[trans] = site
+            b_in[trans], b_out[trans] = idx_prev[trans], idx[trans]
+            f_trans[trans] = f[trans]
+            # shared entries: pairs of states of the non-transition terms
+            nt = np.nonzero(~trans)[0]
+            wo = len(keys[m])
+            pc = idx_prev[nt] * wo + idx[nt]
+            up, pfirst, pinv = np.unique(pc, return_index=True, return_inverse=True)
+            canon = f[nt][pfirst]
+            ft = f[nt]
+            same = np.all(ft == canon[pinv], axis=(1, 2))
+            flip = np.all(ft == -canon[pinv], axis=(1, 2))
+            if not np.all(same | flip):
+                raise RuntimeError(f"shared MPO entry differs by more than a sign at site {site}")
+            rsign[nt[flip]] *= -1.0
+            blocks.append([(up // wo, up % wo, canon)])
+        idx_prev, lt_prev = idx, lt
+    if np.any(mstar < 0):
+        raise RuntimeError("a term never enters its coefficient")
+    # transition entries: c r f(m*) summed over the terms with the same site and states
+    val = (coef * rsign)[:, None, None] * f_trans
+    for site in range(L):
+        sel = np.nonzero(mstar == site)[0]
+        if len(sel) == 0:
+            continue
+        wo = len(keys[site + 1])
+        pc = b_in[sel] * wo + b_out[sel]
+        up, pinv = np.unique(pc, return_inverse=True)
+        acc = np.zeros((len(up), 2, 2))
+        np.add.at(acc, pinv, val[sel])
+        blocks[site].append((up // wo, up % wo, acc))
+    # charge blocks (q_in, q_out, s_out, s_in) -> dense (w_q_in x w_q_out)
+    out = []
+    for site in range(L):
+        qi_all, qo_all = qs[site], qs[site + 1]
+        pos_in = np.zeros(len(qi_all), dtype=np.int64)
+        pos_out = np.zeros(len(qo_all), dtype=np.int64)
+        for q in range(-2, 3):
+            pos_in[qi_all == q] = np.arange(int(np.sum(qi_all == q)))
+            pos_out[qo_all == q] = np.arange(int(np.sum(qo_all == q)))
         bl = {}
-        entries = dict(canon[m])
-        for pair, f in trans[m].items():
-            entries[pair] = entries.get(pair, 0.0) + f
-        for (b, bp), f in entries.items():
-            qi, qo = int(qs[m][b]), int(qs[m + 1][bp])
+        for b, bp, F in blocks[site]:
             for so in (0, 1):
                 for si in (0, 1):
-                    if f[so, si] == 0.0:
+                    val_e = F[:, so, si]
+                    nz = np.nonzero(val_e != 0.0)[0]
+                    if len(nz) == 0:
                         continue
-                    if qo - qi != so - si:
+                    qi, qo = qi_all[b[nz]], qo_all[bp[nz]]
+                    if np.any(qo - qi != so - si):
                         raise RuntimeError("MPO entry violates particle-number conservation")
-                    key = (qi, qo, so, si)
-                    if key not in bl:
-                        bl[key] = np.zeros((int(np.sum(qs[m] == qi)), int(np.sum(qs[m + 1] == qo))))
-                    bl[key][pos_in[b], pos_out[bp]] += f[so, si]
-        blocks.append(bl)
-    return Mpo(L, qs, blocks, keys)
+                    for q_in in np.unique(qi):
+                        sel = nz[qi == q_in]
+                        q_out = int(q_in) + so - si
+                        key = (int(q_in), q_out, so, si)
+                        if key not in bl:
+                            bl[key] = np.zeros((int(np.sum(qi_all == q_in)), int(np.sum(qo_all == q_out))))
+                        np.add.at(bl[key], (pos_in[b[sel]], pos_out[bp[sel]]), val_e[sel])
+        out.append(bl)
+    return Mpo(L, qs, out, keys)
 
 
 # ---------------------------------------------------------------- operator application

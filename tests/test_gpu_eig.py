@@ -132,6 +132,18 @@ def test_sym_eig(ctx, method, kind, n):
     _check(A, w, V, method)
 
 
+@pytest.mark.parametrize("kind", sorted(CASES))
+@pytest.mark.parametrize("n", [538, 1024])
+def test_sym_eig_at_gram_sizes_of_the_workload(ctx, kind, n):
+    """The tridiagonal solver at the sizes the L = 48, cap 512 Grams reach (about 538) and
+    at its limit of 1024."""
+    rng = np.random.default_rng(1000 * n + sorted(CASES).index(kind))
+    A = CASES[kind](n, rng)
+    A = (A + A.T) / 2
+    w, V = ctx.sym_eig(A, 1)
+    _check(A, w, V, 1)
+
+
 @pytest.mark.parametrize("method", [0, 1])
 def test_sym_eig_zero_and_diagonal(ctx, method):
     n = 50
@@ -145,7 +157,8 @@ def test_sym_eig_zero_and_diagonal(ctx, method):
 
 
 @pytest.mark.parametrize("kind", ["rand", "gram_graded", "cluster", "degenerate", "zero_rows"])
-@pytest.mark.parametrize("n,nvec", [(41, 0), (41, 7), (130, 65), (257, 1), (257, 256), (300, 300)])
+@pytest.mark.parametrize("n,nvec", [(41, 0), (41, 7), (130, 65), (257, 1), (257, 256), (300, 300), (538, 270),
+                                    (1024, 512), (1024, 1024)])
 def test_sym_eig_top(ctx, kind, n, nvec):
     """Leading eigenvectors only: the eigenvalues are those of the full solve, the first
     nvec columns pass the same checks, the rest are zero."""
