@@ -370,6 +370,21 @@ pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, in
  * the kept vectors only.  PV_EINVAL for nvec outside [0, n].  For tests. */
 pv_status pv_sym_eig_top(pv_ctx* ctx, int n, const double* A, double* w, double* V, int nvec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the eigensolver of pv_sym_eig with
+ * method 1, on device buffers, allocating nothing.  A (n x n, column-major, upper triangle
+ * read), w (n, eigenvalues descending) and V (n x n, eigenvectors; those of eigenvalues
+ * <= 1e-12 max|lambda| are zero) are device pointers owned by the caller; the call runs on
+ * the context's stream and has finished when it returns (make the inputs ready first).
+ * The work area (7 n^2 + 5 n + 2 doubles) and the launch descriptor live in a file-scope
+ * device array sized for n <= PV_NOALLOC_MAX_N (about 14.7 MB, held on every device the
+ * library runs on until the process ends); PV_EINVAL for larger n.  Every call on one
+ * device shares that array, so calls that overlap on one device (several contexts or
+ * threads at once) race; no kernel timing is recorded.  No hipMalloc, hipFree or HIP
+ * event creation happens inside the call. */
+#define PV_NOALLOC_MAX_N 512
+pv_status pv_sym_eig_noalloc(pv_ctx* ctx, int n, const double* A, double* w, double* V);
+
 /* Cholesky factor of a symmetric positive semidefinite matrix on the device (the factor
  * of the left Gram matrices in the simultaneous truncation): A is n x n column-major
  * (lower triangle read), W (n x n) receives a lower triangular W with W W^T = A up to

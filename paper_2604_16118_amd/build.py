@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpinvit.so")
-SOURCES = ["kernels.hip", "learned.hip", "mpo.cpp", "engine.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "learned.hip", "noalloc.hip", "mpo.cpp", "engine.cpp", "capi.cpp"]
 
 
 def hipcc() -> str:

@@ -320,6 +320,7 @@ pv_status pv_create(pv_ctx** out, int device) {
       ctx->c.device = device;
       PV_HIP(hipStreamCreate(&ctx->c.stream));
       ctx->c.staging.init(size_t(64) << 20);
+      (void)noalloc_scratch(device);  // the allocation-free entry point's array on this device
     } catch (...) {
       delete ctx;
       throw;
@@ -846,6 +847,13 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
     if (method != 0 && method != 1) fail(PV_EINVAL, "method must be 0 or 1");
     for (size_t i = 0; i < size_t(n) * n; ++i) if (!std::isfinite(A[i])) fail(PV_EINVAL, "A not finite");
     sym_eig(ctx->c, n, A, w, V, method);
+  });
+}
+
+pv_status pv_sym_eig_noalloc(pv_ctx* ctx, int n, const double* A, double* w, double* V) {
+  return guard([&] {
+    if (!ctx || !A || !w || !V) fail(PV_EINVAL, "null argument");
+    sym_eig_noalloc(ctx->c, n, A, w, V);
   });
 }
 

@@ -429,6 +429,63 @@ struct EigPlan {
   int ntri = 0;
 };
 
+}  // namespace
+
+// Tridiagonal solver, first half, for the problems `tri` (host copies of the descriptors)
+// whose device copy is `d`: reduction (preparation, panels with trailing GEMM updates,
+// finish) and the eigenvalues.  ftri/btri: algorithmic flops and bytes of the panels.
+void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri, double ftri, double btri) {
+  const int np = int(tri.size());
+  double bprep = 0;
+  for (const EigDesc& e : tri) bprep += 16.0 * double(e.n) * e.n;
+  hipEvent_t a;
+  c.begin(T_COPY, a);
+  launch_tri_prepare(d, np, ntri, c.stream);
+  c.end(T_COPY, a, 0, bprep);
+  // blocked reduction: panel kernel, then the trailing update of every problem as a GEMM
+  const double nsteps = std::max(ntri - 2, 1);
+  for (int k0 = 0; k0 + 2 < ntri; k0 += kTriPanel) {
+    const double share = std::min<double>(kTriPanel, ntri - 2 - k0) / nsteps;
+    c.begin(T_TRI, a);
+    launch_tri_panel(d, np, ntri, k0, c.stream);
+    c.end(T_TRI, a, ftri * share, btri * share);
+    GemmBatch g;
+    g.cls = T_TRIGEMM;
+    g.prec = 2;
+    for (const EigDesc& e : tri) {
+      const int n = e.n;
+      if (k0 + 2 >= n) continue;
+      const int nbe = std::min(kTriPanel, n - 2 - k0);
+      const int o = k0 + nbe, m2 = n - o;
+      double* P1 = e.work + int64_t(n) * n;
+      double* P2 = P1 + int64_t(2) * nbe * n;
+      g.add(P1 + o, n, 0, P2 + o, n, 1, e.work + o + int64_t(o) * n, n, m2, m2, 2 * nbe, -1.0, 1.0);
+    }
+    g.run(c);
+  }
+  c.begin(T_COPY, a);
+  launch_tri_finish(d, np, c.stream);
+  c.end(T_COPY, a, 0, 0);
+  c.begin(T_TRIVAL, a);
+  launch_eig_tridiag(d, np, ntri, 2, c.stream);
+  c.end(T_TRIVAL, a, 0, 0);
+}
+
+// Second half: eigenvectors by inverse iteration and the back-transformation, for the
+// d[i].nvec leading eigenvalues of each problem (the device descriptors carry nvec).
+void tri_vectors(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri) {
+  double fb = 0;
+  for (const EigDesc& e : tri) fb += 2.0 * double(e.n) * e.n * e.nvec;
+  hipEvent_t a; c.begin(T_TRIVEC, a);
+  launch_eig_tridiag(d, int(tri.size()), ntri, 4, c.stream);
+  c.end(T_TRIVEC, a, 0, 0);
+  c.begin(T_TRIBACK, a);
+  launch_eig_tridiag(d, int(tri.size()), ntri, 8, c.stream);
+  c.end(T_TRIBACK, a, fb, 0);
+}
+
+namespace {
+
 // Eigenvalues of every job; the Jacobi problems (small, or not flagged tridiagonal) also
 // get all their eigenvectors here.
 EigPlan run_eig_values(Ctx& c, const std::vector<EigJob>& jobs) {
@@ -462,40 +519,7 @@ EigPlan run_eig_values(Ctx& c, const std::vector<EigJob>& jobs) {
   }
   if (!plan.tri.empty()) {
     EigDesc* d = c.upload(plan.tri);
-    const int np = int(plan.tri.size());
-    double bprep = 0;
-    for (const EigDesc& e : plan.tri) bprep += 16.0 * double(e.n) * e.n;
-    hipEvent_t a;
-    c.begin(T_COPY, a);
-    launch_tri_prepare(d, np, plan.ntri, c.stream);
-    c.end(T_COPY, a, 0, bprep);
-    // blocked reduction: panel kernel, then the trailing update of every problem as a GEMM
-    const double nsteps = std::max(plan.ntri - 2, 1);
-    for (int k0 = 0; k0 + 2 < plan.ntri; k0 += kTriPanel) {
-      const double share = std::min<double>(kTriPanel, plan.ntri - 2 - k0) / nsteps;
-      c.begin(T_TRI, a);
-      launch_tri_panel(d, np, plan.ntri, k0, c.stream);
-      c.end(T_TRI, a, ftri * share, btri * share);
-      GemmBatch g;
-      g.cls = T_TRIGEMM;
-      g.prec = 2;
-      for (const EigDesc& e : plan.tri) {
-        const int n = e.n;
-        if (k0 + 2 >= n) continue;
-        const int nbe = std::min(kTriPanel, n - 2 - k0);
-        const int o = k0 + nbe, m2 = n - o;
-        double* P1 = e.work + int64_t(n) * n;
-        double* P2 = P1 + int64_t(2) * nbe * n;
-        g.add(P1 + o, n, 0, P2 + o, n, 1, e.work + o + int64_t(o) * n, n, m2, m2, 2 * nbe, -1.0, 1.0);
-      }
-      g.run(c);
-    }
-    c.begin(T_COPY, a);
-    launch_tri_finish(d, np, c.stream);
-    c.end(T_COPY, a, 0, 0);
-    c.begin(T_TRIVAL, a);
-    launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 2, c.stream);
-    c.end(T_TRIVAL, a, 0, 0);
+    tri_values(c, plan.tri, d, plan.ntri, ftri, btri);
   }
   for (int mode = 2; mode >= 0; --mode) {
     if (by_mode[mode].empty()) continue;
@@ -511,19 +535,12 @@ EigPlan run_eig_values(Ctx& c, const std::vector<EigJob>& jobs) {
 // (all when nvec is null), the other columns of V zero.
 void run_eig_vectors(Ctx& c, EigPlan& plan, const std::vector<int>* nvec) {
   if (plan.tri.empty()) return;
-  double fb = 0;
   for (size_t i = 0; i < plan.tri.size(); ++i) {
     EigDesc& e = plan.tri[i];
     e.nvec = nvec ? std::min(std::max((*nvec)[plan.job[i]], 0), e.n) : e.n;
-    fb += 2.0 * double(e.n) * e.n * e.nvec;
   }
   EigDesc* d = c.upload(plan.tri);
-  hipEvent_t a; c.begin(T_TRIVEC, a);
-  launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 4, c.stream);
-  c.end(T_TRIVEC, a, 0, 0);
-  c.begin(T_TRIBACK, a);
-  launch_eig_tridiag(d, int(plan.tri.size()), plan.ntri, 8, c.stream);
-  c.end(T_TRIBACK, a, fb, 0);
+  tri_vectors(c, plan.tri, d, plan.ntri);
   for (Buf& w : plan.work) c.scratch.push_back(std::move(w));
   plan.work.clear();
   plan.tri.clear();
@@ -1032,6 +1049,16 @@ double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
   auto v = env_sweep(c, bra, ket, *c.hmpo);
   return v.empty() ? 0.0 : v[0];
+}
+
+void sym_eig_tridiag_device(Ctx& c, int n, const double* A, double* w, double* V, double* work, EigDesc* desc) {
+  std::vector<EigDesc> tri{EigDesc{A, n, n, V, w, work, nullptr, kVecCut, n}};
+  if (!c.staging.fits(sizeof(EigDesc))) c.sync();
+  void* host = c.staging.put(tri.data(), sizeof(EigDesc));
+  PV_HIP(hipMemcpyAsync(desc, host, sizeof(EigDesc), hipMemcpyHostToDevice, c.stream));
+  tri_values(c, tri, desc, n, 2.0 / 3.0 * double(n) * n * n, 4.0 / 3.0 * double(n) * n * n);
+  tri_vectors(c, tri, desc, n);
+  c.sync();
 }
 
 void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host, int method, int nvec) {

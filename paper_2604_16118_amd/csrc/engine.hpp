@@ -214,5 +214,19 @@ void sym_eig(Ctx& c, int n, const double* A_host, double* w_host, double* V_host
 void gemm_host(Ctx& c, int M, int N, int K, const double* A_host, int lda, int ta, const double* B_host, int ldb,
                int tb, double* C_host, int ldc, double alpha, double beta, int precision);
 void cholesky(Ctx& c, int n, const double* A_host, double* W_host);
+// Tridiagonal solver launches shared by the batched eigenproblems and the single-problem
+// paths: reduction and eigenvalues, then the d[i].nvec leading eigenvectors.
+void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri, double ftri, double btri);
+void tri_vectors(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri);
+// All eigenpairs of the n x n matrix A (device, column-major, upper triangle read) by the
+// tridiagonal solver into w, V (device), with the caller's work area (tri_work_doubles(n)
+// doubles) and descriptor slot (device); allocates nothing; synchronous.
+void sym_eig_tridiag_device(Ctx& c, int n, const double* A, double* w, double* V, double* work, EigDesc* desc);
+// Device address of the file-scope work array of the allocation-free eigensolver entry
+// point on `device` (looked up once per device; called by pv_create).
+double* noalloc_scratch(int device);
+// pv_sym_eig_noalloc: the tridiagonal solver on device buffers with its work area in that
+// array (n <= PV_NOALLOC_MAX_N, PV_EINVAL beyond).
+void sym_eig_noalloc(Ctx& c, int n, const double* A, double* w, double* V);
 
 }  // namespace pv

@@ -23,7 +23,7 @@ EXPORTS = [
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_zform", "pv_run_batch",
     "pv_set_correction", "pv_learned_correction", "pv_learned_train",
-    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
 
@@ -125,6 +125,7 @@ def lib():
         L.pv_set_timer_mask.argtypes = [C.c_void_p, C.c_uint32]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_sym_eig_top.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
+        L.pv_sym_eig_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
         L.pv_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int,
                               dp, C.c_int, C.c_double, C.c_double, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
@@ -430,6 +431,10 @@ class Context:
                 raise ValueError("a partial eigenvector set needs method 1")
             _check(lib().pv_sym_eig_top(self._p, n, _dp(A.ravel(order="F")), _dp(w), Vp, int(nvec)))
         return w, V
+
+    def sym_eig_noalloc(self, n, A_ptr, w_ptr, V_ptr):
+        """pv_sym_eig_noalloc on device buffers given as integer addresses (the caller's)."""
+        _check(lib().pv_sym_eig_noalloc(self._p, int(n), C.c_void_p(A_ptr), C.c_void_p(w_ptr), C.c_void_p(V_ptr)))
 
     def gemm(self, A, B, Cin=None, ta=False, tb=False, alpha=1.0, beta=0.0, precision=0):
         """alpha op(A) op(B) + beta C on the device (column-major copies of the operands)."""
