@@ -160,36 +160,89 @@ def summarize(db: str) -> str:
     return "\n".join(out)
 
 
-def cpu_baseline(target_seconds: float = 15.0):
-    """The oracle (dense-vector Algorithm 2, float64 NumPy) on the largest member of the
-    same integral family it handles in seconds per iteration (L=12, N=6, cap 64)."""
-    import numpy as np
-
-    from oracle import pinvit
-    from synth import make_problem
-
+def _blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        return max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    L, N, cap = 12, 6, 64
-    p = make_problem("decayed", L, N, 0)
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(p, N, rho, data, gpu_sweep_s: float, gpu_iter_s: float):
+    """The block-sparse oracle (oracle/bsmps.py, float64 NumPy) on the benchmark's own
+    workload.  Sample: the exact Rayleigh quotient <psi|H_gamma|psi> (the environment
+    sweep that starts every iteration, row A1) of the GPU's iterate after the warmup
+    (ranks at the cap), on all BLAS threads and on one.  One whole iteration of the oracle
+    at this size takes minutes, so the rate is scaled to iterations: the sample's seconds
+    times the GPU's ratio of an iteration to the same sweep (both measured here)."""
+    from oracle import bsmps
+
     t0 = time.perf_counter()
-    iters = 0
-    n = 2
-    while True:
-        prm = pinvit.Params(cap=cap, max_iter=n, tau=0.0, c=0.5, delta=10.0, truncation="parallel")
-        t1 = time.perf_counter()
-        _, hist, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
-        dt = time.perf_counter() - t1
-        iters = len(hist)
-        if time.perf_counter() - t0 > target_seconds or n >= 64:
-            break
-        n *= 2
-    return {"value": iters / dt, "unit": "iter/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"dense-vector oracle, decayed integrals L={L} N={N} cap {cap}, {iters} iterations "
-                      f"in {dt:.2f} s (L=48 is beyond a dense 2^L vector)"}
+    mpo = bsmps.build_mpo(p.h, p.v, p.gamma / N)
+    t_mpo = time.perf_counter() - t0
+    x = bsmps.from_export(len(p.h), N, rho, data)
+    nrm = bsmps.norm(x)
+
+    def sweep():
+        t = time.perf_counter()
+        lam = bsmps.expect(x, x, mpo) / (nrm * nrm)
+        return time.perf_counter() - t, lam
+
+    threads = _blas_threads()
+    t_all, lam = sweep()
+    t_one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t_one, lam1 = sweep()
+    except Exception:  # pragma: no cover
+        pass
+    ratio = gpu_iter_s / gpu_sweep_s
+    return {"value": 1.0 / (t_all * ratio), "unit": "iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"block-sparse oracle, exact Rayleigh quotient of the GPU iterate after the warmup "
+                      f"(L={len(p.h)}, N={N}, max rank {int(max(sum(r) for r in rho))}): {t_all:.2f} s on "
+                      f"{threads} threads" + (f", {t_one:.2f} s on 1 thread" if t_one else "") +
+                      f"; scaled by the GPU's iteration/sweep time ratio {ratio:.1f}",
+            "sample_seconds": t_all, "sample_seconds_1thread": t_one,
+            "value_1thread": (1.0 / (t_one * ratio)) if t_one else None,
+            "gpu_sample_seconds": gpu_sweep_s, "gpu_iteration_seconds": gpu_iter_s,
+            "oracle_mpo_build_seconds": t_mpo, "lambda_oracle": lam}
+
+
+def checkpoint_steps(ctx, psi0, res0, steps, precisions, **common):
+    """One iteration from each of `steps` consecutive float64 checkpoints (the float64
+    chain from psi0 with its resume state res0) in every precision of `precisions`:
+    the energy (float64 Rayleigh quotient) of each new iterate against the float64 one."""
+    rows = []
+    psi, res, own = psi0, res0, False
+    for j in range(steps):
+        r64, _, q64 = ctx.run(max_iter=1, start=psi, resume=res, precision=0, **common)
+        e64 = ctx.energy(q64)
+        row = {"checkpoint": j, "E_fp64": e64}
+        for prec in precisions:
+            _, _, q = ctx.run(max_iter=1, start=psi, resume=res, precision=prec, **common)
+            row[f"dE_prec{prec}"] = abs(ctx.energy(q) - e64)
+            ctx.mps_free(q)
+        rows.append(row)
+        if own:
+            ctx.mps_free(psi)
+        psi, res, own = q64, r64, True
+    if own:
+        ctx.mps_free(psi)
+    return rows
+
+
+def copy_calibration(nbytes: int):
+    """A plain device copy of nbytes (torch's copy of one float64 buffer into another),
+    three times: the reference for scaling the FETCH_SIZE and WRITE_SIZE counters of a
+    rocprofv3 --pmc pass to bytes (see pmc_traffic)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 3, "check": float(dst[-1].item())}), flush=True)
 
 
 def zform_bench(a):
@@ -404,7 +457,11 @@ def main():
     ap.add_argument("--cap", type=int, default=512)
     ap.add_argument("--m-zip", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction run")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction runs")
+    ap.add_argument("--checkpoints", type=int, default=2,
+                    help="float64 checkpoints from which one step per precision is compared")
+    ap.add_argument("--mode0-steps", type=int, default=0,
+                    help="iterations of the sequential-truncation leg at the bench size (0: skip; minutes each)")
     ap.add_argument("--batch", type=int, default=0, metavar="B",
                     help="instead of the L=48 run: B independent Hamiltonians, sequential vs pv_run_batch")
     ap.add_argument("--zform", action="store_true",
@@ -421,7 +478,12 @@ def main():
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--cal-bytes", type=int, default=2 ** 30, help="size of the calibration copy")
     ap.add_argument("--commands", default="", help="commands that produced the counter CSVs (recorded)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     a = ap.parse_args()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.summarize:
         print(summarize(a.summarize))
         return
@@ -454,7 +516,7 @@ def main():
     print(f"# setup {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     rtx = _roctx()
 
-    def run_mode(precision: int, mark: bool):
+    def run_mode(precision: int, mark: bool, keep_warm: bool = False):
         common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1,
                       precision=precision)
         t = time.perf_counter()
@@ -476,12 +538,47 @@ def main():
         ctx.set_timed_classes(None)
         res_i, _, psi3 = ctx.run(max_iter=a.steps, start=psi2, resume=res, **common)
         tm = ctx.timers()
-        for q in (psi, psi2, psi3):
+        for q in ((psi2, psi3) if keep_warm else (psi, psi2, psi3)):
             ctx.mps_free(q)
-        return dict(elapsed=t1 - t0, res=res, hist=hist, timers=tm, live=live)
+        out = dict(elapsed=t1 - t0, res=res, hist=hist, timers=tm, live=live)
+        if keep_warm:
+            out.update(psi_w=psi, res_w=res_w)
+        return out
 
-    r64 = run_mode(0, True)
+    r64 = run_mode(0, True, keep_warm=True)
+    psi_w, res_w = r64["psi_w"], r64["res_w"]
+    common1 = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
+    # the same sweep the CPU baseline samples, and the precision error from shared checkpoints
+    t = time.perf_counter()
+    for _ in range(3):
+        ctx.expect_h(psi_w, psi_w)
+    gpu_sweep_s = (time.perf_counter() - t) / 3
+    print(f"# float64 run done ({r64['elapsed']:.1f}s timed); Rayleigh-quotient sweep {gpu_sweep_s * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    ck = [] if a.no_mixed else checkpoint_steps(ctx, psi_w, res_w, a.checkpoints, (1,), **common1)
+    print(f"# checkpoint steps done: {ck}", file=sys.stderr, flush=True)
+    # truncation mode 0 (sequential TT-SVD, the float64 parity path) from the same checkpoint
+    mode0 = None
+    if a.mode0_steps > 0:
+        ctx.timers_reset()
+        t = time.perf_counter()
+        r0, h0, q0 = ctx.run(max_iter=a.mode0_steps, start=psi_w, resume=res_w, rank_cap=a.cap, tau=0.0, c=0.5,
+                             delta=10.0, m_zip=a.m_zip, truncation=0)
+        el0 = time.perf_counter() - t
+        print(f"# sequential-truncation leg: {len(h0)} iterations in {el0:.1f}s", file=sys.stderr, flush=True)
+        ctx.mps_free(q0)
+        tm0 = ctx.timers()
+        g0 = tm0["gemm_f64_mfma"]
+        mode0 = {"what": "the same workload with the sequential TT-SVD truncation (two-pass Gram factorisations), "
+                         "from the float64 iterate after the warmup",
+                 "value": len(h0) / el0, "unit": "iter/s", "steps": len(h0), "ms_per_step": 1e3 * el0 / len(h0),
+                 "energies": [r["E"] for r in h0], "cap_bound": [r["cap_bound"] for r in h0],
+                 "block_gemm_tflops": g0["flops"] / max(g0["ms"], 1e-9) / 1e9,
+                 "timers_ms": {k: round(v["ms"], 3) for k, v in tm0.items()}}
+    rho_w, data_w = ctx.mps_download(psi_w)
+    ctx.mps_free(psi_w)
     r32 = None if a.no_mixed else run_mode(1, False)
+    print("# float32 run done", file=sys.stderr, flush=True)
     tm, live = r64["timers"], r64["live"]
     res, hist, elapsed = r64["res"], r64["hist"], r64["elapsed"]
     steps = len(hist)
@@ -523,11 +620,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"PINVIT L={a.L} N={a.N} rank cap {a.cap} m_zip {a.m_zip}, decayed "
-                               f"integrals seed 0, float64", "L": a.L, "N": a.N, "rank_cap": a.cap,
-                   "m_zip": a.m_zip},
+        "config": {"workload": f"PINVIT (Algorithm 2) L={a.L} N={a.N} rank cap {a.cap} m_zip {a.m_zip}, "
+                               f"decayed integrals seed 0, float64, simultaneous truncation (mode 1)",
+                   "L": a.L, "N": a.N, "rank_cap": a.cap, "m_zip": a.m_zip, "truncation": "simultaneous (mode 1)"},
         "block_gemm_tflops": g["flops"] / max(g["ms"], 1e-9) / 1e9,
-        "dE_vs_fp64": 0.0,
+        "dE_vs_fp64": None,
+        "dE_note": "this line runs float64 throughout (dE 0 by construction); the mixed-precision error is "
+                   "mixed_fp32.dE_checkpoint, measured from shared float64 checkpoints",
         "energy": res["energy"],
         "max_rank": max([r["max_rank"] for r in hist] + [0]),
         "timers_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
@@ -553,13 +652,20 @@ def main():
             "ms_per_step": 1e3 * r32["elapsed"] / max(len(h32), 1),
             "block_gemm_tflops_f32": g32["flops"] / max(g32["ms"], 1e-9) / 1e9,
             "energy": r32["res"]["energy"],
-            "dE_vs_fp64": abs(r32["res"]["energy"] - res["energy"]),
-            "dE_vs_fp64_max_over_steps": max([abs(h32[i]["E"] - hist[i]["E"]) for i in range(n)] + [0.0]),
+            "dE_checkpoint": max([r["dE_prec1"] for r in ck] + [0.0]),
+            "dE_checkpoint_rows": ck,
+            "dE_checkpoint_note": "one iteration from each float64 checkpoint in both precisions; the "
+                                  "energy (float64 Rayleigh quotient) of the new iterates compared",
+            "dE_trajectory_after_steps": abs(r32["res"]["energy"] - res["energy"]),
+            "dE_trajectory_max_over_steps": max([abs(h32[i]["E"] - hist[i]["E"]) for i in range(n)] + [0.0]),
             "timers_ms": {k: round(v["ms"], 3) for k, v in t32.items()},
         }
+    if mode0 is not None:
+        out["mode0_sequential"] = mode0
     ctx.close()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        print("# oracle baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, a.N, rho_w, data_w, gpu_sweep_s, elapsed / max(steps, 1))
     print(json.dumps(out), flush=True)
 
 

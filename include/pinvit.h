@@ -29,8 +29,9 @@
  * - MPS handles are small integers owned by a context; every operation that produces
  *   an MPS returns a new handle.  pv_mps_free releases one.
  * - Host pointers are owned by the caller and are only read or written during the
- *   call.  The context owns all device memory and one HIP stream; all calls on a
- *   context are synchronous with respect to the host on return.
+ *   call.  The context owns all device memory and one HIP stream (or uses the caller's,
+ *   see pv_create); all calls on a context are synchronous with respect to the host on
+ *   return.
  * - A context is used by one thread at a time.  Errors never throw across the ABI:
  *   every call returns a pv_status and pv_last_error() describes the last failure of
  *   the calling thread.
@@ -155,8 +156,12 @@ typedef struct {
 
 const char* pv_last_error(void);
 
-/* Context on HIP device `device`.  Fails with PV_EDEVICE when there is no GPU. */
-pv_status pv_create(pv_ctx** out, int device);
+/* Context on HIP device `device`.  stream: a hipStream_t of the caller on that device
+ * that every launch of the context goes to (the caller keeps ownership and must keep it
+ * alive until pv_destroy), or NULL for a stream the context creates and destroys.  The
+ * simultaneous truncation also forks work to a side stream of its own, ordered by events
+ * before and after.  Fails with PV_EDEVICE when there is no GPU. */
+pv_status pv_create(pv_ctx** out, int device, void* stream);
 void pv_destroy(pv_ctx* ctx);
 
 /* Copies h, v; builds the MPO of H_gamma (Thm. opranks, host) and uploads it; computes

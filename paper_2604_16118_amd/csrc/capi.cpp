@@ -305,7 +305,7 @@ extern "C" {
 
 const char* pv_last_error(void) { return g_err.c_str(); }
 
-pv_status pv_create(pv_ctx** out, int device) {
+pv_status pv_create(pv_ctx** out, int device, void* stream) {
   if (!out) { g_err = "null output pointer"; return PV_EINVAL; }
   *out = nullptr;
   return guard([&] {
@@ -318,7 +318,12 @@ pv_status pv_create(pv_ctx** out, int device) {
     auto* ctx = new pv_ctx();
     try {
       ctx->c.device = device;
-      PV_HIP(hipStreamCreate(&ctx->c.stream));
+      if (stream) {
+        ctx->c.stream = static_cast<hipStream_t>(stream);  // the caller's: not destroyed here
+        ctx->c.own_stream = false;
+      } else {
+        PV_HIP(hipStreamCreate(&ctx->c.stream));
+      }
       ctx->c.staging.init(size_t(64) << 20);
       (void)noalloc_scratch(device);  // the allocation-free entry point's array on this device
     } catch (...) {
@@ -339,7 +344,7 @@ void pv_destroy(pv_ctx* ctx) {
     for (auto& p : ctx->c.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->c.fork_event) (void)hipEventDestroy(ctx->c.fork_event);
     if (ctx->c.join_event) (void)hipEventDestroy(ctx->c.join_event);
-    hipStream_t s = ctx->c.stream, s2 = ctx->c.side_stream;
+    hipStream_t s = ctx->c.own_stream ? ctx->c.stream : nullptr, s2 = ctx->c.side_stream;
     delete ctx;
     if (s) (void)hipStreamDestroy(s);
     if (s2) (void)hipStreamDestroy(s2);

@@ -128,6 +128,7 @@ enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = true;  // false when the caller passed its stream to pv_create
   Pool pool;
   Staging staging;
   // problem

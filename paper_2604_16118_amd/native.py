@@ -94,7 +94,7 @@ def lib():
         L.pv_last_error.restype = C.c_char_p
         L.pv_timer_name.restype = C.c_char_p
         L.pv_destroy.restype = None
-        L.pv_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        L.pv_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]
         L.pv_destroy.argtypes = [C.c_void_p]
         L.pv_set_hamiltonian.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_double]
         L.pv_precond_info.argtypes = [C.c_void_p, dp, ip]
@@ -198,9 +198,11 @@ def mpo_dense(h, v, diag_shift=0.0):
 class Context:
     """One library context (device memory, stream, Hamiltonian, MPS handles)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, stream: int = 0):
+        """stream: address of a hipStream_t of the caller (e.g. torch.cuda.Stream's
+        cuda_stream) that the context launches on, or 0 for its own."""
         self._p = C.c_void_p()
-        _check(lib().pv_create(C.byref(self._p), device))
+        _check(lib().pv_create(C.byref(self._p), device, C.c_void_p(stream or None)))
         self.L = self.N = None
 
     def close(self):
@@ -224,7 +226,7 @@ class Context:
         h, v = _f64(h), _f64(v)
         L = h.shape[0]
         _check(lib().pv_set_hamiltonian(self._p, L, N, _dp(h), _dp(v), float(gamma)))
-        self.L, self.N = L, N
+        self.L, self.N, self.gamma = L, N, float(gamma)
 
     def precond_info(self):
         out = np.zeros(7)
@@ -270,6 +272,10 @@ class Context:
         out = C.c_double()
         _check(lib().pv_dot(self._p, a, b, C.byref(out)))
         return out.value
+
+    def energy(self, h):
+        """<h|H_gamma|h>/<h|h> - gamma (float64 sweeps on the device)."""
+        return self.expect_h(h, h) / self.dot(h, h) - self.gamma
 
     def expect_h(self, bra, ket):
         out = C.c_double()

@@ -223,3 +223,21 @@ def test_round_parallel_large_sectors(ctx, eps):
                 assert {n: int(rho[k, n]) for n in rho_or[k]} == rho_or[k], k
     finally:
         ctx.set_truncation(0)
+
+
+def test_context_on_a_caller_stream():
+    """pv_create with the caller's stream: every launch goes there and the results equal
+    those of a context with its own stream; the stream outlives the context."""
+    import torch
+    p = make_problem("dense", 8, 4, 0)
+    s = torch.cuda.Stream()
+    kw = dict(rank_cap=16, max_iter=4, tau=0.0, c=0.5, delta=10.0)
+    with native.Context(0, stream=s.cuda_stream) as c1, native.Context(0) as c2:
+        c1.set_hamiltonian(p.h, p.v, 4, p.gamma)
+        c2.set_hamiltonian(p.h, p.v, 4, p.gamma)
+        _, h1, q1 = c1.run(**kw)
+        _, h2, q2 = c2.run(**kw)
+        assert [r["E"] for r in h1] == [r["E"] for r in h2]
+        c1.mps_free(q1)
+        c2.mps_free(q2)
+    s.synchronize()
