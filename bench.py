@@ -27,6 +27,7 @@ PEAK = {  # MI355X published peaks
     "fp64_mfma_tflops": 78.6,
     "fp64_vector_tflops": 78.6,
     "fp32_mfma_tflops": 157.3,
+    "bf16_mfma_tflops": 2500.0,
     "hbm_gbs": 8000.0,
 }
 # library timer class -> (HIP kernel, roofline bound)
@@ -43,6 +44,7 @@ KERNELS = {
     "reduce": ("reduce_kernel", "hbm"),
     "cholesky_f64": ("chol_panel_kernel", "alu"),
     "gemm_f32_mfma": ("gemm_kernel<1>", "mfma32"),
+    "gemm_bf16_mfma": ("gemm_kernel<3>", "mfma_bf16"),
 }
 
 
@@ -230,6 +232,33 @@ def checkpoint_steps(ctx, psi0, res0, steps, precisions, **common):
     if own:
         ctx.mps_free(psi)
     return rows
+
+
+def precision_bench(a):
+    """The error of the low-precision contractions from shared float64 checkpoints at
+    --L/--N/--cap/--m-zip (decayed integrals seed 0, simultaneous truncation): `warmup`
+    float64 iterations, then one iteration in each precision from each of `checkpoints`
+    consecutive float64 iterates; the float64 Rayleigh quotients of the new iterates are
+    compared.  Also the time of those single steps."""
+    from paper_2604_16118_amd import native
+    from synth import make_problem
+
+    p = make_problem("decayed", a.L, a.N, 0)
+    ctx = native.Context(0)
+    ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
+    common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
+    res_w, hist_w, psi = ctx.run(max_iter=a.warmup, precision=0, **common)
+    print(f"# warmup ranks {[r['max_rank'] for r in hist_w]}", file=sys.stderr, flush=True)
+    rows = checkpoint_steps(ctx, psi, res_w, a.checkpoints, (1, 2), **common)
+    ctx.mps_free(psi)
+    ctx.close()
+    out = {"metric": "energy change of one low-precision iteration from a float64 checkpoint",
+           "config": {"workload": f"PINVIT L={a.L} N={a.N} rank cap {a.cap} m_zip {a.m_zip}, decayed integrals "
+                                  f"seed 0, simultaneous truncation, {a.warmup} float64 warmup iterations"},
+           "rows": rows,
+           "max_dE_float32": max(r["dE_prec1"] for r in rows),
+           "max_dE_bfloat16": max(r["dE_prec2"] for r in rows)}
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration(nbytes: int):
@@ -478,6 +507,8 @@ def main():
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--cal-bytes", type=int, default=2 ** 30, help="size of the calibration copy")
     ap.add_argument("--commands", default="", help="commands that produced the counter CSVs (recorded)")
+    ap.add_argument("--precision-checkpoints", action="store_true",
+                    help="instead of the timed run: one low-precision step from each float64 checkpoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     a = ap.parse_args()
@@ -504,6 +535,9 @@ def main():
         return
     if a.learned:
         learned_bench(a)
+        return
+    if a.precision_checkpoints:
+        precision_bench(a)
         return
 
     from paper_2604_16118_amd import native
@@ -555,7 +589,7 @@ def main():
     gpu_sweep_s = (time.perf_counter() - t) / 3
     print(f"# float64 run done ({r64['elapsed']:.1f}s timed); Rayleigh-quotient sweep {gpu_sweep_s * 1e3:.1f} ms",
           file=sys.stderr, flush=True)
-    ck = [] if a.no_mixed else checkpoint_steps(ctx, psi_w, res_w, a.checkpoints, (1,), **common1)
+    ck = [] if a.no_mixed else checkpoint_steps(ctx, psi_w, res_w, a.checkpoints, (1, 2), **common1)
     print(f"# checkpoint steps done: {ck}", file=sys.stderr, flush=True)
     # truncation mode 0 (sequential TT-SVD, the float64 parity path) from the same checkpoint
     mode0 = None
@@ -579,6 +613,8 @@ def main():
     ctx.mps_free(psi_w)
     r32 = None if a.no_mixed else run_mode(1, False)
     print("# float32 run done", file=sys.stderr, flush=True)
+    r16 = None if a.no_mixed else run_mode(2, False)
+    print("# bfloat16 run done", file=sys.stderr, flush=True)
     tm, live = r64["timers"], r64["live"]
     res, hist, elapsed = r64["res"], r64["hist"], r64["elapsed"]
     steps = len(hist)
@@ -659,6 +695,23 @@ def main():
             "dE_trajectory_after_steps": abs(r32["res"]["energy"] - res["energy"]),
             "dE_trajectory_max_over_steps": max([abs(h32[i]["E"] - hist[i]["E"]) for i in range(n)] + [0.0]),
             "timers_ms": {k: round(v["ms"], 3) for k, v in t32.items()},
+        }
+    if r16 is not None:
+        h16, t16 = r16["hist"], r16["timers"]
+        g16 = t16["gemm_bf16_mfma"]
+        n = min(len(h16), len(hist))
+        out["mixed_bf16"] = {
+            "what": "operator contractions (H psi, Ritz sandwiches) with operands rounded to bfloat16 on "
+                    "bfloat16 MFMA with float32 accumulation; everything else as the float32 run",
+            "value": len(h16) / r16["elapsed"],
+            "unit": "iter/s",
+            "ms_per_step": 1e3 * r16["elapsed"] / max(len(h16), 1),
+            "block_gemm_tflops_bf16": g16["flops"] / max(g16["ms"], 1e-9) / 1e9,
+            "energy": r16["res"]["energy"],
+            "dE_checkpoint": max([r["dE_prec2"] for r in ck] + [0.0]),
+            "dE_trajectory_after_steps": abs(r16["res"]["energy"] - res["energy"]),
+            "dE_trajectory_max_over_steps": max([abs(h16[i]["E"] - hist[i]["E"]) for i in range(n)] + [0.0]),
+            "timers_ms": {k: round(v["ms"], 3) for k, v in t16.items()},
         }
     if mode0 is not None:
         out["mode0_sequential"] = mode0

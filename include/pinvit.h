@@ -75,8 +75,9 @@ typedef struct {
   int precision;    /* 0: float64 everywhere; 1: the operator contractions of H psi and of
                      *    the two Ritz sandwiches run on float32 MFMA (operands rounded to
                      *    float32, float32 accumulation), while truncations, norms, the
-                     *    Rayleigh quotient lambda and the residual stay float64; other
-                     *    values give PV_EINVAL */
+                     *    Rayleigh quotient lambda and the residual stay float64; 2: the
+                     *    same contractions with operands rounded to bfloat16 (float32
+                     *    accumulation on bfloat16 MFMA); other values give PV_EINVAL */
   int truncation;   /* 0: sequential TT-SVD truncation (eq. ttsvdquasiopt), two-pass Gram
                      *    factorisations; 1: simultaneous truncation of all bonds from Gram
                      *    matrices (tolerance eps/sqrt(L-1) per bond), see pv_set_truncation */
@@ -338,10 +339,11 @@ pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_
  * Jacobi 10/3 n^3 each; tridiagonal solver: panel kernels 2/3 n^3 flops and 4/3 n^3
  * bytes (the symmetric products), trailing updates as GEMMs, back-transformation 2 n^2 k
  * for k wanted vectors; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic
- * bytes, for i < n classes (twelve classes: grouped GEMM float64, Jacobi eigensolver, MPO
- * W-step, copy/scale, split-K reduction, tridiagonal reduction panels, Cholesky panels,
- * grouped GEMM float32, eigenvectors of the tridiagonal matrix, back-transformation,
- * eigenvalues of the tridiagonal matrix, trailing updates of the tridiagonal reduction);
+ * bytes, for i < n classes (thirteen classes: grouped GEMM float64, Jacobi eigensolver,
+ * MPO W-step, copy/scale, split-K reduction, tridiagonal reduction panels, Cholesky
+ * panels, grouped GEMM float32, eigenvectors of the tridiagonal matrix,
+ * back-transformation, eigenvalues of the tridiagonal matrix, trailing updates of the
+ * tridiagonal reduction, grouped GEMM with bfloat16 operands);
  * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);
@@ -364,7 +366,8 @@ pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, 
  * operator contractions (the tile shape and split-K choice are the library's own):
  * column-major host arrays, op(A) = A (M x K, ld lda) for ta = 0 or A^T (A is K x M) for
  * ta = 1, likewise op(B) (K x N) with tb; C is M x N with ld ldc.  precision 0: float64
- * MFMA; 1: operands rounded to float32, float32 accumulation.  PV_EINVAL for bad sizes,
+ * MFMA; 1: operands rounded to float32, float32 accumulation; 2: operands rounded to
+ * bfloat16, float32 accumulation.  PV_EINVAL for bad sizes,
  * leading dimensions or flags.  For tests. */
 pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb,
                   int tb, double* C, int ldc, double alpha, double beta, int precision);

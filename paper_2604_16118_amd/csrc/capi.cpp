@@ -549,7 +549,7 @@ pv_status pv_apply_s(pv_ctx* ctx, int x, double eta, int cap, int* out, int* cap
 struct LowPrecision {
   Ctx& c;
   bool old;
-  explicit LowPrecision(Ctx& cx) : c(cx), old(cx.lowp) { c.lowp = c.prec == 1; }
+  explicit LowPrecision(Ctx& cx) : c(cx), old(cx.lowp) { c.lowp = c.prec != 0; }
   ~LowPrecision() { c.lowp = old; }
 };
 
@@ -563,8 +563,8 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
     if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
       fail(PV_EINVAL, "invalid parameters");
-    if (p.precision != 0 && p.precision != 1)
-      fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32 contractions)");
+    if (p.precision < 0 || p.precision > 2)
+      fail(PV_EINVAL, "precision must be 0 (float64), 1 (float32 contractions) or 2 (bfloat16 contractions)");
     c.prec = p.precision;
     if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
     c.trunc_mode = p.truncation;
@@ -869,7 +869,7 @@ pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, in
     if (M < 1 || N < 1 || K < 0) fail(PV_EINVAL, "sizes out of range");
     if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) fail(PV_EINVAL, "ta, tb must be 0 or 1");
     if (lda < (ta ? K : M) || lda < 1 || ldb < (tb ? N : K) || ldb < 1 || ldc < M) fail(PV_EINVAL, "leading dimension too small");
-    if (precision != 0 && precision != 1) fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32)");
+    if (precision < 0 || precision > 2) fail(PV_EINVAL, "precision must be 0 (float64), 1 (float32) or 2 (bfloat16)");
     gemm_host(ctx->c, M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta, precision);
   });
 }
@@ -1166,8 +1166,8 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
     if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
         !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
       fail(PV_EINVAL, "invalid parameters");
-    if (p.precision != 0 && p.precision != 1)
-      fail(PV_EINVAL, "precision must be 0 (float64) or 1 (float32 contractions)");
+    if (p.precision < 0 || p.precision > 2)
+      fail(PV_EINVAL, "precision must be 0 (float64), 1 (float32 contractions) or 2 (bfloat16 contractions)");
     if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
     c.prec = p.precision;
     c.trunc_mode = p.truncation;
@@ -1411,7 +1411,7 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
                                             "tridiag_reduce_f64", "cholesky_f64", "gemm_f32_mfma",
                                             "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64",
-                                            "tridiag_update_gemm_f64"};
+                                            "tridiag_update_gemm_f64", "gemm_bf16_mfma"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

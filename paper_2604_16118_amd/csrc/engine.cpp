@@ -317,7 +317,7 @@ struct GemmBatch {
     }
     if (!list.empty()) {
       if (tiles > INT32_MAX) fail(PV_EINVAL, "GEMM batch too large for one launch");
-      const int tc = cls >= 0 ? cls : (prec ? T_GEMM32 : T_GEMM);
+      const int tc = cls >= 0 ? cls : (prec == 3 ? T_GEMMBF16 : prec ? T_GEMM32 : T_GEMM);
       if (list.size() <= size_t(kGemmPack)) {  // descriptors in the kernel arguments
         GemmPack pack{};
         std::copy(list.begin(), list.end(), pack.d);
@@ -751,7 +751,7 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
     }
   Buf T1(c.pool, size_t(std::max<int64_t>(t1tot, 1)));
   GemmBatch gb;
-  gb.prec = c.lowp ? 1 : 0;
+  gb.prec = c.contraction_kernel();
   for (int na = 0; na <= N; ++na)
     for (int q = -2; q <= 2; ++q) {
       const int64_t o = t1off[na * 5 + q + 2];
@@ -867,7 +867,7 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
         const int64_t ld = src.ld[D.s_in][D.q_in + 2];
         if (int(gd.size()) <= slot) {
           gd.emplace_back();
-          gd.back().prec = c.lowp ? 1 : 0;
+          gd.back().prec = c.contraction_kernel();
         }
         for (int cc = 0; cc < B.cols; ++cc)
           gd[slot].add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
@@ -1086,7 +1086,7 @@ void gemm_host(Ctx& c, int M, int N, int K, const double* A_host, int lda, int t
   if (nb) PV_HIP(hipMemcpyAsync(B.p, B_host, nb * 8, hipMemcpyHostToDevice, c.stream));
   PV_HIP(hipMemcpyAsync(C.p, C_host, nc * 8, hipMemcpyHostToDevice, c.stream));
   GemmBatch g;
-  g.prec = precision;
+  g.prec = precision == 2 ? 3 : precision;
   g.add(A.p, lda, ta, B.p, ldb, tb, C.p, ldc, M, N, K, alpha, beta);
   g.run(c);
   PV_HIP(hipMemcpyAsync(C_host, C.p, nc * 8, hipMemcpyDeviceToHost, c.stream));

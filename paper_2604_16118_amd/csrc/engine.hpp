@@ -123,7 +123,7 @@ struct DevMpo {
   int64_t nnz = 0;
 };
 
-enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_TRIVAL, T_TRIGEMM, T_COUNT };
+enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_TRIVAL, T_TRIGEMM, T_GEMMBF16, T_COUNT };
 
 struct Ctx {
   int device = 0;
@@ -137,11 +137,14 @@ struct Ctx {
   std::vector<double> h, v;
   std::unique_ptr<DevMpo> hmpo;
   std::unique_ptr<DevMpo> ident;  // identity operator (dot products)
-  // precision of the contractions: 0 float64; 1 float32 MFMA for the operator contractions
-  // (H psi and the Ritz sandwiches) while truncations, norms and the Rayleigh quotient stay
-  // float64.  lowp is set while a float32-eligible contraction runs.
+  // precision of the contractions: 0 float64; 1 float32 MFMA, 2 bfloat16 operands on MFMA
+  // with float32 accumulation, for the operator contractions (H psi and the Ritz
+  // sandwiches) while truncations, norms and the Rayleigh quotient stay float64.  lowp is
+  // set while such a contraction runs.
   int prec = 0;
   bool lowp = false;
+  // GEMM kernel precision of an operator contraction (see launch_gemm)
+  int contraction_kernel() const { return lowp ? (prec == 2 ? 3 : 1) : 0; }
   std::vector<int> mpo_w;
   // preconditioner (Section 4.3, Section 7.1.1)
   std::vector<double> theta;

@@ -194,6 +194,145 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
       }
 }
 
+// bfloat16 bits of a double, rounded to nearest even through float (the standard bit
+// formula on the float: add 0x7fff plus the lowest kept bit, keep the upper half)
+__device__ inline unsigned short bf16_bits(double x) {
+  const float f = float(x);
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// PREC 3: operands rounded to bfloat16 on v_mfma_f32_16x16x16_bf16 (one instruction per
+// 16 x 16 sub-tile and K-tile of 16), float32 accumulation, C float64 in memory.  The LDS
+// tiles hold each row (of A) or column (of B) with its 16 k values contiguous, so that a
+// lane reads its four consecutive k values of a sub-tile with one 8-byte load.  The
+// instruction pairs the A and B values of the same (lane group, element), so the sum over
+// k does not depend on which k the hardware assigns to them; rows of A and columns of B
+// are lane % 16 and the result layout is that of the float32 instruction.
+template <int BM, int BN>
+__device__ __forceinline__ void gemm_tile_bf16(const GemmDesc& g, int tile) {
+  constexpr int BK = kGemmBK;
+  static_assert(BK == 16, "one bf16 MFMA per K-tile");
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  constexpr int KP = BK + 4;  // row pitch in bf16 elements (8-byte aligned rows)
+  __shared__ unsigned short As[2][BM][KP];
+  __shared__ unsigned short Bs[2][BN][KP];
+  gcdouble* gA = gbl(g.A);
+  gcdouble* gB = gbl(g.B);
+  gdouble* gC = gbl(g.C);
+  const int t = tile - g.tile0;
+  const int row0 = (g.colmajor ? t % g.tiles_m : t / g.tiles_n) * BM;
+  const int col0 = (g.colmajor ? t / g.tiles_m : t % g.tiles_n) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  int ai[LA], ak[LA], bj[LB], bk[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int e = tid + 256 * r;
+    if (!g.ta) { ai[r] = e % BM; ak[r] = e / BM; } else { ak[r] = e % BK; ai[r] = e / BK; }
+  }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int e = tid + 256 * r;
+    if (!g.tb) { bk[r] = e % BK; bj[r] = e / BK; } else { bj[r] = e % BN; bk[r] = e / BN; }
+  }
+  double ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int gi = row0 + ai[r], gk = k0 + ak[r];
+      ra[r] = (gi < g.M && gk < g.kend) ? (g.ta ? gA[gk + (int64_t)gi * g.lda] : gA[gi + (int64_t)gk * g.lda]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int gj = col0 + bj[r], gk = k0 + bk[r];
+      rb[r] = (gj < g.N && gk < g.kend) ? (g.tb ? gB[gj + (int64_t)gk * g.ldb] : gB[gk + (int64_t)gj * g.ldb]) : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) As[buf][ai[r]][ak[r]] = bf16_bits(ra[r]);
+#pragma unroll
+    for (int r = 0; r < LB; ++r) Bs[buf][bj[r]][bk[r]] = bf16_bits(rb[r]);
+  };
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  typedef short S4 __attribute__((ext_vector_type(4)));
+  F4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = F4{0, 0, 0, 0};
+  bool rv[TM], cv[TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a) rv[a] = row0 + wr * (BM / 2) + a * 16 < g.M;
+#pragma unroll
+  for (int b = 0; b < TN; ++b) cv[b] = col0 + wc * (BN / 2) + b * 16 < g.N;
+  int buf = 0;
+  if (g.kbeg < g.kend) {
+    load(g.kbeg);
+    stage(0);
+  }
+  __syncthreads();
+  for (int k0 = g.kbeg; k0 < g.kend; k0 += BK) {
+    const bool more = k0 + BK < g.kend;
+    if (more) load(k0 + BK);
+    S4 af[TM], bf[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+      af[a] = *reinterpret_cast<const S4*>(&As[buf][wr * (BM / 2) + a * 16 + li][4 * lk]);
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+      bf[b] = *reinterpret_cast<const S4*>(&Bs[buf][wc * (BN / 2) + b * 16 + li][4 * lk]);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        if (!(rv[a] && cv[b])) continue;
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  auto row_of = [&](int mi, int r) { return row0 + wr * (BM / 2) + mi * 16 + 4 * lk + r; };
+  auto col_of = [&](int nj) { return col0 + wc * (BN / 2) + nj * 16 + li; };
+  double cold[TM][TN][4];
+  if (g.beta != 0.0) {
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int nj = 0; nj < TN; ++nj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row_of(mi, r), j = col_of(nj);
+          const int ic = min(i, g.M - 1), jc = min(j, g.N - 1);
+          cold[mi][nj][r] = gC[ic + (int64_t)jc * g.ldc];
+        }
+  }
+#pragma unroll
+  for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < TN; ++nj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row_of(mi, r), j = col_of(nj);
+        if (i < g.M && j < g.N) {
+          double v = g.alpha * double(acc[mi][nj][r]);
+          if (g.beta != 0.0) v += g.beta * cold[mi][nj][r];
+          gC[i + (int64_t)j * g.ldc] = v;
+        }
+      }
+}
+
+template <int PREC, int BM, int BN>
+__device__ __forceinline__ void gemm_any(const GemmDesc& g, int tile) {
+  if constexpr (PREC == 3) gemm_tile_bf16<BM, BN>(g, tile);
+  else gemm_tile<PREC, BM, BN>(g, tile);
+}
+
 template <int PREC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob, int ntiles) {
   const int tile = gemm_tile_of_block(ntiles);
@@ -203,7 +342,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
     if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
   }
   const GemmDesc g = descs[lo];
-  gemm_tile<PREC, BM, BN>(g, tile);
+  gemm_any<PREC, BM, BN>(g, tile);
 }
 
 // The same with the descriptors in the kernel arguments (at most kGemmPack problems): no
@@ -215,7 +354,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const GemmPack pack, i
   for (int p = 1; p < nprob; ++p)
     if (pack.d[p].tile0 <= tile) lo = p;
   const GemmDesc g = pack.d[lo];
-  gemm_tile<PREC, BM, BN>(g, tile);
+  gemm_any<PREC, BM, BN>(g, tile);
 }
 
 void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s) {
@@ -226,6 +365,8 @@ void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int pr
     hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
   else if (prec == 1)
     hipLaunchKernelGGL((gemm_packed_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+  else if (prec == 3)
+    hipLaunchKernelGGL((gemm_packed_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
   else
     hipLaunchKernelGGL((gemm_packed_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
   PV_LAUNCH_CHECK();
@@ -238,6 +379,8 @@ void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, h
     hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   else if (prec == 1)
     hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
+  else if (prec == 3)
+    hipLaunchKernelGGL((gemm_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   else
     hipLaunchKernelGGL((gemm_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
   PV_LAUNCH_CHECK();

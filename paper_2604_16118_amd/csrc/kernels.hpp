@@ -87,7 +87,7 @@ struct ScaleDesc {
 
 // prec 0: float64 MFMA; prec 1: operands rounded to float32, float32 MFMA accumulation;
 // prec 2: float64 MFMA, the instance used for the trailing updates of the tridiagonal
-// reduction.
+// reduction; prec 3: operands rounded to bfloat16, float32 MFMA accumulation.
 void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s);
 // Batches of at most kGemmPack problems pass their descriptors in the kernel arguments.
 constexpr int kGemmPack = 16;

@@ -465,7 +465,7 @@ class Context:
         return W
 
     def timers(self):
-        n = 12
+        n = 13
         ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
         calls = np.zeros(n, np.int32)
         _check(lib().pv_timers(self._p, n, _dp(ms), _dp(fl), _dp(by), _ip(calls)))

@@ -53,8 +53,39 @@ def test_gemm_float32(ctx, M, N, K):
     assert np.abs(out - ref).max() > 0  # it did run in float32
 
 
+def _bf16(x):
+    """Round to the nearest bfloat16 (ties to even) through float32, as the kernel does."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(100, 90, 37), (200, 2000, 45), (2000, 200, 45), (1100, 1030, 70),
+                                   (65, 129, 17), (120, 96, 5000)])
+def test_gemm_bfloat16(ctx, M, N, K, ta, tb):
+    """Operands rounded to bfloat16 and float32 accumulation: against the exact product of
+    the rounded operands, the error is the float32 accumulation alone; against the
+    float64 product it is the operand rounding (8 bits)."""
+    rng = np.random.default_rng(M + 3 * N + 7 * K + ta)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    Ab, Bb = _bf16(A), _bf16(B)
+    ref_b = 1.5 * (Ab.T if ta else Ab) @ (Bb.T if tb else Bb) - 0.5 * C0
+    out = ctx.gemm(A, B, C0, ta=ta, tb=tb, alpha=1.5, beta=-0.5, precision=2)
+    amax, bmax = np.abs(A).max(), np.abs(B).max()
+    assert np.abs(out - ref_b).max() <= 1.5 * 4 * 6e-8 * np.sqrt(K) * amax * bmax * 4
+    ref = 1.5 * (A.T if ta else A) @ (B.T if tb else B) - 0.5 * C0
+    err = np.abs(out - ref).max()
+    assert 0 < err <= 1.5 * 2 * 4e-3 * np.sqrt(K) * amax * bmax * 4
+    t = ctx.timers()
+    assert t["gemm_bf16_mfma"]["calls"] > 0
+
+
 def test_gemm_rejects_bad_arguments(ctx):
     with pytest.raises(Exception):
         ctx.gemm(np.ones((3, 2)), np.ones((3, 2)))  # inner dimensions differ
     with pytest.raises(Exception):
-        ctx.gemm(np.ones((3, 2)), np.ones((2, 2)), precision=2)
+        ctx.gemm(np.ones((3, 2)), np.ones((2, 2)), precision=3)

@@ -99,12 +99,34 @@ def test_pinvit_float32_contractions_track_float64(ctx, kind, L, N, seed, cap, i
     assert t["gemm_f32_mfma"]["calls"] > 0
 
 
-def test_precision_bf16_is_rejected(ctx):
+def test_unknown_precision_is_rejected(ctx):
     p = make_problem("dense", 6, 3, 0)
     ctx.set_hamiltonian(p.h, p.v, 3, p.gamma)
     with pytest.raises(native.PvError) as e:
-        ctx.run(rank_cap=4, max_iter=1, tau=1e-12, c=0.5, delta=10.0, precision=2)
+        ctx.run(rank_cap=4, max_iter=1, tau=1e-12, c=0.5, delta=10.0, precision=3)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("kind,L,N,seed,cap,iters", [("dense", 8, 4, 0, 16, 20), ("decayed", 12, 6, 0, 24, 12)])
+def test_pinvit_bfloat16_contractions_stay_variational(ctx, kind, L, N, seed, cap, iters):
+    """bfloat16 operands (float32 accumulation) in the operator contractions: every energy
+    is the float64 Rayleigh quotient of its iterate, so it stays above the ground state;
+    the steps are perturbed at the 1e-3 level of the operand rounding, and the run still
+    converges towards the float64 run's energy."""
+    p = make_problem(kind, L, N, seed)
+    w = fock.lowest_eigs(p.h, p.v, N, p.gamma, k=2)
+    delta = w[1] / (w[1] - w[0])
+    ctx.set_hamiltonian(p.h, p.v, N, p.gamma)
+    kw = dict(rank_cap=cap, max_iter=iters, tau=1e-12, c=0.5, delta=delta, truncation=1)
+    _, h64, _ = ctx.run(precision=0, **kw)
+    ctx.timers_reset()
+    _, h16, _ = ctx.run(precision=2, **kw)
+    assert len(h16) == len(h64)
+    for a in h16:
+        assert a["lam"] >= w[0] - 1e-10
+    assert abs(h16[-1]["E"] - h64[-1]["E"]) <= 1e-2 * abs(h64[-1]["E"])
+    t = ctx.timers()
+    assert t["gemm_bf16_mfma"]["calls"] > 0 and t["gemm_f32_mfma"]["calls"] == 0
 
 
 def test_outer_iteration_matches_oracle(ctx):
