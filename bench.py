@@ -393,6 +393,125 @@ def learned_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def solve_samples(ctx, p, L, N, iterates, **kw):
+    """Training data of the solve form from the method itself on one problem: `iterates`
+    iterations of Algorithm 2 (exact H application), and for each iterate psi its residual
+    r = (H - lambda) psi, the exact solve t = (H + gamma)^{-1} r (pv_solve_h) and both at
+    every determinant of the N-particle sector (pv_mps_amplitudes).  Returns a list of
+    (psi handle, masks, r values, t values)."""
+    import itertools
+    import numpy as np
+    masks = np.array([sum(1 << i for i in c) for c in itertools.combinations(range(L), N)], dtype=np.uint64)
+    out, res, psi = [], None, -1
+    for _ in range(iterates):
+        res, _, nxt = ctx.run(max_iter=1, start=psi, resume=res, **kw)
+        if psi >= 0:
+            ctx.mps_free(psi)
+        psi = nxt
+        lam = ctx.expect_h(psi, psi) / ctx.dot(psi, psi)
+        y, _ = ctx.apply_h(psi, 0.0, 10 ** 6, 0)
+        r = ctx.lincomb(1.0, y, -lam, psi)
+        t, it, rr = ctx.solve_h(r, rel_tol=1e-10, max_iter=300)
+        rv, tv = ctx.amplitudes(r, masks), ctx.amplitudes(t, masks)
+        for h in (y, r, t):
+            ctx.mps_free(h)
+        keep = ctx.lincomb(1.0, psi, 0.0, psi)  # a handle of its own for the features
+        out.append((keep, masks, rv, tv, it, rr))
+    ctx.mps_free(psi)
+    return out
+
+
+def learned_solves_bench(a):
+    """The learned correction trained on exact solves of the method's own residuals (an
+    extension): training problems --train-L (N = L/2, decayed integrals, seeds 1 and 2),
+    each giving `--train-iterates` iterates whose residuals are solved exactly; the network
+    takes rounds of Adam steps on each (features of that iterate).  Evaluation: Algorithm 2
+    at --L/--N (seed 0, exact ranks, sequential truncation) with the plain S and with the
+    network attached (correction refreshed from the iterate every --refresh iterations),
+    both run until ||r|| <= --target-res or --steps iterations; iterations and seconds to the
+    target are reported."""
+    import numpy as np
+    from paper_2604_16118_amd import native
+    from synth import init_params, make_problem
+
+    sizes = [int(s) for s in a.train_L.split(",") if s] or [8, 10]
+    kw = dict(rank_cap=10 ** 6, tau=0.0, c=0.5, delta=10.0, m_zip=0, truncation=0)
+    sets, t_data = [], time.perf_counter()
+    for Lt in sizes:
+        for seed in (1, 2):
+            pt = make_problem("decayed", Lt, Lt // 2, seed)
+            ct = native.Context(0)  # one context per training problem keeps its iterates
+            ct.set_hamiltonian(pt.h, pt.v, Lt // 2, pt.gamma)
+            data = solve_samples(ct, pt, Lt, Lt // 2, a.train_iterates, **kw)
+            sets.append((ct, data))
+            print(f"# training data L={Lt} seed {seed}: {len(data)} residual solves "
+                  f"(CG steps {[d[4] for d in data]})", file=sys.stderr, flush=True)
+    t_data = time.perf_counter() - t_data
+    w = init_params(0)
+    t0 = time.perf_counter()
+    nsteps = 0
+
+    def set_losses(wt):
+        """the misfit of every training set at parameters wt (no step taken)"""
+        return [float(ct.learned_train_solves(wt, m, rv, tv, steps=0, psi=h)[1][0])
+                for ct, data in sets for (h, m, rv, tv, _, _) in data]
+
+    zero = set_losses(np.zeros_like(w))
+    before = set_losses(w)
+    for rnd in range(a.train_rounds):
+        for ct, data in sets:
+            for (h, masks, rv, tv, _, _) in data:
+                w, loss, _ = ct.learned_train_solves(w, masks, rv, tv, steps=a.train_steps, lr=a.lr, psi=h)
+                nsteps += a.train_steps
+        cur = set_losses(w)
+        print(f"# training round {rnd}: mean misfit {np.mean(cur):.4g} (zero correction {np.mean(zero):.4g})",
+              file=sys.stderr, flush=True)
+    after = set_losses(w)
+    first, last = float(np.mean(before)), float(np.mean(after))
+    t_train = time.perf_counter() - t0
+    for ct, _ in sets:
+        ct.close()
+    p = make_problem("decayed", a.L, a.N, 0)
+    ctx = native.Context(0)
+    ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
+    ev = dict(kw, max_iter=a.steps)
+
+    def to_target(h):
+        t = 0.0
+        for i, x in enumerate(h):
+            t += x["seconds"]
+            if x["r_norm"] <= a.target_res:
+                return [i + 1, t]
+        return None
+
+    runs = {}
+    for name in ("plain", "learned"):
+        ctx.set_learned_network(w if name == "learned" else None, refresh=a.refresh)
+        print(f"# evaluation L={a.L} N={a.N}: {name} run", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        _, h, x = ctx.run(**ev)
+        runs[name] = dict(hist=h, elapsed=time.perf_counter() - t)
+        ctx.mps_free(x)
+    ctx.close()
+    hp, hl = runs["plain"]["hist"], runs["learned"]["hist"]
+    out = {"metric": "iterations and seconds to ||r|| <= target: learned correction (trained on exact solves of "
+                     "the method's residuals) against the plain S",
+           "value": (to_target(hl) or [None])[0], "unit": "iterations (learned)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f32 network (bf16 weights), f64 PINVIT", "data": "synthetic",
+           "config": {"workload": f"Algorithm 2 on decayed integrals L={a.L} N={a.N} seed 0, exact ranks, "
+                                  f"sequential truncation, up to {a.steps} iterations; training on L in {sizes} "
+                                  f"(seeds 1, 2), {a.train_iterates} residual solves each",
+                      "refresh": a.refresh, "train_steps_per_set": a.train_steps, "rounds": a.train_rounds},
+           "target_residual": a.target_res,
+           "to_target_plain": to_target(hp), "to_target_learned": to_target(hl),
+           "r_norm_plain": [x["r_norm"] for x in hp], "r_norm_learned": [x["r_norm"] for x in hl],
+           "energy_plain": hp[-1]["E"], "energy_learned": hl[-1]["E"],
+           "loss_first_last": [first, last], "misfit_zero_correction": float(np.mean(zero)),
+           "misfit_per_set_after": after, "train_seconds": t_train, "train_steps": nsteps,
+           "data_seconds": t_data}
+    print(json.dumps(out), flush=True)
+
+
 def subspace_bench(a):
     """Algorithm 4 on D columns (pv_run_subspace): decayed integrals (seed 0) at the given
     L, N, rank cap and m_zip, simultaneous truncation.  `warmup` iterations from the D
@@ -507,6 +626,13 @@ def main():
                     help="print the traffic record of the dominant kernel from rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--cal-bytes", type=int, default=2 ** 30, help="size of the calibration copy")
     ap.add_argument("--commands", default="", help="commands that produced the counter CSVs (recorded)")
+    ap.add_argument("--learned-solves", action="store_true",
+                    help="instead of the timed run: the learned correction trained on exact residual solves, "
+                         "plain against learned to --target-res at --L/--N")
+    ap.add_argument("--train-iterates", type=int, default=4)
+    ap.add_argument("--train-rounds", type=int, default=3)
+    ap.add_argument("--refresh", type=int, default=5)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--precision-checkpoints", action="store_true",
                     help="instead of the timed run: one low-precision step from each float64 checkpoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -535,6 +661,9 @@ def main():
         return
     if a.learned:
         learned_bench(a)
+        return
+    if a.learned_solves:
+        learned_solves_bench(a)
         return
     if a.precision_checkpoints:
         precision_bench(a)

@@ -323,6 +323,35 @@ pv_status pv_learned_correction(pv_ctx* ctx, const float* params, int psi, doubl
 pv_status pv_learned_train(pv_ctx* ctx, float* params, int psi, const uint64_t* masks, int nmask, int steps,
                            float lr, double* loss, double* grad);
 
+/* The solve form of the training (an extension): the misfit
+ *     loss = sum_b (r_b / d(m_b) - t_b)^2 / sum_b t_b^2
+ * between the corrected diagonal preconditioner's action on a residual r of the method
+ * (r_b = <m_b|r>) and the exact solve t = (H + gamma)^{-1} r on the N-particle sector
+ * (t_b = <m_b|t>), d(m) the corrected diagonal of the determinant m; S^2 is close to
+ * 1/d, so the network learns to make S^2 act on the method's residuals like the exact
+ * inverse.  rvals, tvals: nmask doubles each (host).  Otherwise as pv_learned_train
+ * (features from psi, Adam, params updated in place, loss and grad outputs). */
+pv_status pv_learned_train_solves(pv_ctx* ctx, float* params, int psi, const uint64_t* masks, int nmask,
+                                  const double* rvals, const double* tvals, int steps, float lr, double* loss,
+                                  double* grad);
+/* Attach a network (PV_MLP_PARAMS float32 values, copied) to the runs of this context:
+ * pv_run recomputes the correction from the current iterate's features (densities and
+ * Rayleigh quotient) on its first iteration and every `refresh` iterations after, and
+ * sets up S with it as pv_set_correction does.  NULL detaches it (a new Hamiltonian
+ * does too).  PV_EINVAL for refresh < 1 or non-finite parameters. */
+pv_status pv_set_learned_network(pv_ctx* ctx, const float* params, int refresh);
+/* x = (H + gamma)^{-1} b on the N-particle sector by preconditioned conjugate gradients in
+ * block-sparse form: the products with H by the exact H application, the preconditioner
+ * S^2 (every term of both S applications kept), and every sum truncated only at its
+ * numerical zeros (no rank cap), until ||b - H x|| <= rel_tol ||b|| (recursive residual)
+ * or max_iter steps.  *out receives the handle of x; iters and rel_res (may be NULL) the
+ * steps taken and the final relative residual.  The ranks are those of the exact
+ * solution, so this is for the small sizes that generate training targets. */
+pv_status pv_solve_h(pv_ctx* ctx, int b, double rel_tol, int max_iter, int* out, int* iters, double* rel_res);
+/* out[i] = <m_i|x> for the determinants masks[i] (bit j = orbital j occupied; each must
+ * hold N particles, L <= 64), by transfer sweeps with their rank-one MPS. */
+pv_status pv_mps_amplitudes(pv_ctx* ctx, int handle, const uint64_t* masks, int n, double* out);
+
 /* Batched independent problems (many Hamiltonians of uneven size at once): runs pv_run from
  * the determinant on each of the `count` distinct contexts ctxs[i] (each with its
  * Hamiltonian already set) with parameters prm[i], writing res[i] and, when status is not

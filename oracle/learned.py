@@ -24,8 +24,9 @@ Training: Adam on the mean squared misfit between d and the exact diagonal of H 
 on sampled determinants,
     loss = mean_b (d(beta_b) - <beta_b|H + gamma|beta_b>)^2 / tbar^2,
     <beta|H + gamma|beta> = gamma + sum_i h_ii n_i + sum_{i != j} (v_ijji - v_ijij) n_i n_j,
-so that S approximates (H + gamma)^{-1/2} on the diagonal more closely.  Arithmetic here
-is float64.
+so that S approximates (H + gamma)^{-1/2} on the diagonal more closely.  The solve form
+(``exact_solve``, ``solve_loss_grad``, at the end) trains instead on exact solves of the
+method's own residuals.  Arithmetic here is float64.
 """
 from __future__ import annotations
 
@@ -183,3 +184,55 @@ def t_range(th, delta, N):
             nhi[n] = max(hi[n], hi[n - 1] + c)
         lo, hi = nlo, nhi
     return float(lo[N]), float(hi[N])
+
+
+# ---------------------------------------------------------------- exact-solve targets
+#
+# The training target of the solve form: the exact solve t = (H + gamma)^{-1} r on the
+# N-particle sector of a residual r that the method generates, and the corrected
+# diagonal preconditioner's action r / d on the same vector.  Trained on sampled
+# determinants b, the misfit
+#     loss = sum_b (r_b / d(beta_b) - t_b)^2 / sum_b t_b^2
+# asks S^2 (which is close to D^{-1}, alpha_0^2 t_min S(d/t_min)^2 ~ 1/d) to act on the
+# method's residuals like the exact inverse of H + gamma.
+
+
+def exact_solve(h, v, N, gamma, r):
+    """t = (H + gamma)^{-1} r on the N-particle sector (dense solve; r a 2^L vector)."""
+    from . import fock
+    L = h.shape[0]
+    basis = fock.sector_basis(L, N)
+    H = fock.sector_hamiltonian(h, v, N, gamma)
+    t = np.zeros(1 << L)
+    t[basis] = np.linalg.solve(H, r[basis])
+    return t
+
+
+def solve_loss_grad(p, X, dmax, th, masks, rvals, tvals, N):
+    """(loss, gradient) of the solve misfit above with respect to the (bfloat16-rounded)
+    parameters."""
+    L = len(th)
+    W1, b1, W2, b2, W3, b3 = unpack(p)
+    z, (h1, h2) = forward(p, X)
+    tz = np.tanh(z)
+    delta = (dmax * tz).reshape(L, N + 1)
+    d = approx_diagonal(th, delta, masks)
+    rv, tv = np.asarray(rvals, float), np.asarray(tvals, float)
+    nt = float(np.sum(tv * tv))
+    e = rv / d - tv
+    loss = float(np.sum(e * e)) / nt
+    gd = -2.0 * e * rv / (d * d) / nt   # d loss / d d_b
+    G = np.zeros((L, N + 1))
+    for b, m in enumerate(masks):
+        for i, n in _occ_left(int(m), L):
+            G[i, n] += gd[b]
+    dz = G.ravel() * dmax * (1.0 - tz * tz)
+    gW3 = h2.T @ dz
+    gb3 = np.array([dz.sum()])
+    da2 = np.outer(dz, W3) * (1.0 - h2 * h2)
+    gW2 = da2.T @ h1
+    gb2 = da2.sum(axis=0)
+    da1 = (da2 @ W2) * (1.0 - h1 * h1)
+    gW1 = da1.T @ X
+    gb1 = da1.sum(axis=0)
+    return loss, np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, gb3])

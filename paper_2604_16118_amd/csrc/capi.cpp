@@ -365,7 +365,9 @@ pv_status pv_set_hamiltonian(pv_ctx* ctx, int L, int N, const double* h, const d
     c.sync();
     c.mps.clear();
     c.L = L; c.N = N; c.gamma = gamma;
-    c.corr.clear();  // a correction belongs to one Hamiltonian
+    c.corr.clear();  // a correction (and an attached network) belongs to one Hamiltonian
+    c.net.clear();
+    c.net_refresh = 0;
     c.h.assign(h, h + size_t(L) * L);
     c.v.assign(v, v + nv);
     Mpo m = build_mpo(L, h, v, gamma / N);
@@ -600,6 +602,14 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       if (!(nrm > 0)) fail(PV_ENOCONV, "iterate vanished");
       psi = mps_scaled_copy(c, *psi, 1.0 / nrm, nullptr);
       const double lam = expect_h(c, *psi, *psi);
+      if (!c.net.empty() && it % c.net_refresh == 0) {
+        // the attached network corrects theta from the current iterate's features
+        std::vector<double> delta(size_t(L) * (N + 1));
+        compute_theta(c);
+        learned_correction(c, c.net.data(), *psi, lam, c.theta, delta.data());
+        c.corr = std::move(delta);
+        setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
+      }
       double est;
       if (s_prev < 0) {
         std::unique_ptr<Mps> y0;
@@ -1142,6 +1152,69 @@ pv_status pv_learned_train(pv_ctx* ctx, float* params, int psi, const uint64_t* 
     double lam = 0;
     auto x = feature_state(c, psi, &lam);
     learned_train(c, params, *x, lam, c.theta, masks, nmask, steps, lr, loss, grad);
+  });
+}
+
+pv_status pv_learned_train_solves(pv_ctx* ctx, float* params, int psi, const uint64_t* masks, int nmask,
+                                  const double* rvals, const double* tvals, int steps, float lr, double* loss,
+                                  double* grad) {
+  return guard([&] {
+    if (!ctx || !params || !masks || !rvals || !tvals) fail(PV_EINVAL, "null argument");
+    if (nmask < 1 || steps < 0 || !(lr >= 0)) fail(PV_EINVAL, "need nmask >= 1, steps >= 0, lr >= 0");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (c.L > 64) fail(PV_EINVAL, "sample masks hold at most 64 orbitals");
+    for (int b = 0; b < nmask; ++b)
+      if (!std::isfinite(rvals[b]) || !std::isfinite(tvals[b])) fail(PV_EINVAL, "samples not finite");
+    compute_theta(c);
+    double lam = 0;
+    auto x = feature_state(c, psi, &lam);
+    learned_train(c, params, *x, lam, c.theta, masks, nmask, steps, lr, loss, grad, rvals, tvals);
+  });
+}
+
+pv_status pv_set_learned_network(pv_ctx* ctx, const float* params, int refresh) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (!params) {
+      c.net.clear();
+      c.net_refresh = 0;
+      return;
+    }
+    if (refresh < 1) fail(PV_EINVAL, "refresh must be at least 1");
+    for (int i = 0; i < PV_MLP_PARAMS; ++i)
+      if (!std::isfinite(params[i])) fail(PV_EINVAL, "network parameters not finite");
+    c.net.assign(params, params + PV_MLP_PARAMS);
+    c.net_refresh = refresh;
+  });
+}
+
+pv_status pv_solve_h(pv_ctx* ctx, int b, double rel_tol, int max_iter, int* out, int* iters, double* rel_res) {
+  return guard([&] {
+    if (!ctx || !out) fail(PV_EINVAL, "null argument");
+    if (!(rel_tol > 0) || max_iter < 1) fail(PV_EINVAL, "need rel_tol > 0 and max_iter >= 1");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    if (c.alpha.empty()) setup_precond(c, 0.1, 1.0, 1.0);
+    int it = 0;
+    double rr = 0;
+    auto x = solve_h(c, get(c, b), rel_tol, max_iter, &it, &rr);
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = rr;
+    *out = put(c, std::move(x));
+  });
+}
+
+pv_status pv_mps_amplitudes(pv_ctx* ctx, int handle, const uint64_t* masks, int n, double* out) {
+  return guard([&] {
+    if (!ctx || (n > 0 && (!masks || !out))) fail(PV_EINVAL, "null argument");
+    if (n < 0) fail(PV_EINVAL, "negative count");
+    Ctx& c = ctx->c;
+    const Mps& x = get(c, handle);
+    if (x.L > 64) fail(PV_EINVAL, "masks hold at most 64 orbitals");
+    amplitudes(c, x, masks, n, out);
   });
 }
 

@@ -2072,6 +2072,67 @@ std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* ca
 }
 
 
+// ---------------------------------------------------------------- exact solves
+// x = H_gamma^{-1} b on the N-particle space by preconditioned conjugate gradients in
+// block-sparse form: the products with H (exact zip-up), the preconditioner S^2 (both
+// S applications with every term kept) and every sum truncated only at the numerical
+// zeros (eps 0, no rank cap).  Stops when ||b - H x|| <= rel_tol ||b|| (the recursive
+// residual) or after max_iter steps.
+std::unique_ptr<Mps> solve_h(Ctx& c, const Mps& b, double rel_tol, int max_iter, int* iters, double* rel_res) {
+  const int big = 1 << 30;
+  const double nb = norm2(c, b);
+  auto x = mps_zero_like(c, b);
+  if (!(nb > 0)) {
+    if (iters) *iters = 0;
+    if (rel_res) *rel_res = 0.0;
+    return x;
+  }
+  auto r = round_mps(c, b, 0.0, big, nullptr);
+  auto precondition = [&](const Mps& v) {
+    auto s1 = apply_s(c, v, 0.0, big, nullptr);
+    return apply_s(c, *s1, 0.0, big, nullptr);
+  };
+  auto z = precondition(*r);
+  auto p = mps_scaled_copy(c, *z, 1.0, nullptr);
+  double rz = dot(c, *r, *z);
+  int it = 0;
+  double rr = nb;
+  for (; it < max_iter; ++it) {
+    auto q = apply_h(c, *p, 0.0, big, 0, nullptr);
+    const double pq = dot(c, *p, *q);
+    if (!(pq > 0)) fail(PV_ENOTSPD, "H_gamma is not positive on the search direction");
+    const double alpha = rz / pq;
+    auto xs = mps_lincomb(c, 1.0, *x, alpha, *p);
+    x = round_mps(c, *xs, 0.0, big, nullptr);
+    auto rs = mps_lincomb(c, 1.0, *r, -alpha, *q);
+    r = round_mps(c, *rs, 0.0, big, nullptr);
+    rr = norm2(c, *r);
+    if (rr <= rel_tol * nb) { ++it; break; }
+    z = precondition(*r);
+    const double rz2 = dot(c, *r, *z);
+    const double beta = rz2 / rz;
+    rz = rz2;
+    auto ps = mps_lincomb(c, 1.0, *z, beta, *p);
+    p = round_mps(c, *ps, 0.0, big, nullptr);
+  }
+  if (iters) *iters = it;
+  if (rel_res) *rel_res = rr / nb;
+  return x;
+}
+
+// x at determinants (bit i of a mask = orbital i occupied): <det|x> by a transfer sweep
+// with the determinant's rank-one MPS.
+void amplitudes(Ctx& c, const Mps& x, const uint64_t* masks, int n, double* out) {
+  for (int b = 0; b < n; ++b) {
+    std::vector<int> occ;
+    for (int i = 0; i < x.L; ++i)
+      if ((masks[b] >> i) & 1u) occ.push_back(i);
+    if (int(occ.size()) != x.N) fail(PV_EINVAL, "a determinant with the wrong particle number");
+    auto d = mps_determinant(c, occ);
+    out[b] = dot(c, *d, x);
+  }
+}
+
 // ---------------------------------------------------------------- learned correction
 // <n_i> of x for every site in one diagonal-operator sweep (channel i: 0 on the empty and
 // 1 on the occupied state of site i, 1 elsewhere), divided by <x|x>.
@@ -2189,7 +2250,8 @@ void learned_correction(Ctx& c, const float* params, const Mps& x, double lam, c
 }
 
 void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::vector<double>& th,
-                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad) {
+                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad,
+                   const double* rvals, const double* tvals) {
   const int L = x.L, N = x.N;
   for (int b = 0; b < nmask; ++b) {
     if (L < 64 && (masks[b] >> L) != 0) fail(PV_EINVAL, "a sample occupies an orbital beyond L");
@@ -2214,7 +2276,19 @@ void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::v
   if (nmask) PV_HIP(hipMemcpyAsync(mk.p, masks, size_t(nmask) * 8, hipMemcpyHostToDevice, c.stream));
   PV_HIP(hipMemcpyAsync(jk.p, jkh.data(), jkh.size() * 8, hipMemcpyHostToDevice, c.stream));
   const uint64_t* md = reinterpret_cast<const uint64_t*>(mk.p);
-  launch_mlp_target(md, nmask, net.dev.p + L, jk.p, c.gamma, L, target.p, c.stream);
+  const bool solve_form = rvals != nullptr;
+  Buf rt;
+  double tt = 0.0;
+  if (solve_form) {
+    // the method's residual and its exact solve at the samples
+    rt = Buf(c.pool, 2 * size_t(nmask));
+    PV_HIP(hipMemcpyAsync(rt.p, rvals, size_t(nmask) * 8, hipMemcpyHostToDevice, c.stream));
+    PV_HIP(hipMemcpyAsync(rt.p + nmask, tvals, size_t(nmask) * 8, hipMemcpyHostToDevice, c.stream));
+    for (int b = 0; b < nmask; ++b) tt += tvals[b] * tvals[b];
+    if (!(tt > 0)) fail(PV_EINVAL, "the exact solve vanishes at every sample");
+  } else {
+    launch_mlp_target(md, nmask, net.dev.p + L, jk.p, c.gamma, L, target.p, c.stream);
+  }
   launch_mlp_round(wf, kMlpParams, net.wq.p, c.stream);
   net.G = Buf(c.pool, net.R);
   const double B = std::max(nmask, 1);
@@ -2222,8 +2296,12 @@ void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::v
   auto misfit = [&](int t) {
     net.forward();
     fill(c, net.G.p, net.R, 0.0);
-    launch_mlp_misfit(md, nmask, net.dev.p, net.delta.p, target.p, L, N, scale, lscale, net.G.p, lossd.p + t,
-                      c.stream);
+    if (solve_form)
+      launch_mlp_solve_misfit(md, nmask, net.dev.p, net.delta.p, rt.p, rt.p + nmask, L, N, 2.0 / tt, 1.0 / tt,
+                              net.G.p, lossd.p + t, c.stream);
+    else
+      launch_mlp_misfit(md, nmask, net.dev.p, net.delta.p, target.p, L, N, scale, lscale, net.G.p, lossd.p + t,
+                        c.stream);
   };
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   float p1 = 1.0f, p2 = 1.0f;

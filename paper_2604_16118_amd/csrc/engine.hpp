@@ -149,6 +149,10 @@ struct Ctx {
   // preconditioner (Section 4.3, Section 7.1.1)
   std::vector<double> theta;
   std::vector<double> corr;  // learned correction of theta, L x (N+1) row-major; empty: none
+  // network parameters (float32) attached for the runs, and the refresh period of the
+  // correction (iterations); empty: none
+  std::vector<float> net;
+  int net_refresh = 0;
   double t_min = 0, t_max = 0, T_ratio = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
   int m_minus = 0, m_plus = 0;
   std::vector<double> alpha, beta;
@@ -198,8 +202,16 @@ std::vector<double> densities(Ctx& c, const Mps& x);
 // learned correction of theta (th: theta_i, L values; hd: h_ii; lam: Rayleigh quotient of x)
 void learned_correction(Ctx& c, const float* params, const Mps& x, double lam, const std::vector<double>& th,
                         double* delta);
+// rvals/tvals (nmask each, host, may be null): train on the solve form of the misfit (the
+// method's residual and its exact solve at the samples) instead of the exact diagonal.
 void learned_train(Ctx& c, float* params, const Mps& x, double lam, const std::vector<double>& th,
-                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad);
+                   const uint64_t* masks, int nmask, int steps, float lr, double* loss, double* grad,
+                   const double* rvals = nullptr, const double* tvals = nullptr);
+// x = H_gamma^{-1} b by preconditioned conjugate gradients in block-sparse form (exact
+// products and sums up to numerical zeros).
+std::unique_ptr<Mps> solve_h(Ctx& c, const Mps& b, double rel_tol, int max_iter, int* iters, double* rel_res);
+// amplitudes <det_b|x> for determinants given as bit masks
+void amplitudes(Ctx& c, const Mps& x, const uint64_t* masks, int n, double* out);
 std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op);
 double dot(Ctx& c, const Mps& a, const Mps& b);
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket);

@@ -101,6 +101,46 @@ __global__ void misfit_kernel(const uint64_t* masks, int B, const double* th, co
   if (threadIdx.x == 0) atomicAdd(loss, acc[R]);
 }
 
+// Solve form of the misfit: per sampled determinant b the corrected diagonal d_b, the
+// preconditioned residual r_b / d_b against the exact solve t_b; loss += lscale e^2 with
+// e = r_b/d_b - t_b, and d loss / d d_b = -gscale e r_b / d_b^2 scattered onto the
+// correction entries of the occupied sites (LDS sums, one global add per entry).
+__global__ void solve_misfit_kernel(const uint64_t* masks, int B, const double* th, const double* delta,
+                                    const double* rv, const double* tv, int L, int N, double gscale,
+                                    double lscale, double* G, double* loss) {
+  extern __shared__ double acc[];
+  const int R = L * (N + 1);
+  for (int r = threadIdx.x; r <= R; r += blockDim.x) acc[r] = 0.0;
+  __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    const uint64_t m = masks[b];
+    double d = 0.0;
+    int n = 0;
+    for (int i = 0; i < L && n <= N; ++i) {
+      if (!((m >> i) & 1u)) continue;
+      if (n < N) d += th[i] + delta[i * (N + 1) + n];
+      ++n;
+    }
+    if (n == N) {
+      const double r = rv[b];
+      const double e = r / d - tv[b];
+      const double gd = -gscale * e * r / (d * d);
+      n = 0;
+      for (int i = 0; i < L; ++i) {
+        if (!((m >> i) & 1u)) continue;
+        atomicAdd(acc + i * (N + 1) + n, gd);
+        ++n;
+      }
+      atomicAdd(acc + R, lscale * e * e);
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (acc[r] != 0.0) atomicAdd(G + r, acc[r]);
+  if (threadIdx.x == 0) atomicAdd(loss, acc[R]);
+}
+
 __global__ void dz_kernel(const double* G, const double* tz, int R, double dmax, double* dz) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
@@ -182,6 +222,15 @@ void launch_mlp_misfit(const uint64_t* masks, int B, const double* th, const dou
   if (B > 0)
     hipLaunchKernelGGL(misfit_kernel, dim3(blocks(B)), dim3(kThreads), shm, s, masks, B, th, delta, target, L, N,
                        scale, lscale, G, loss);
+}
+
+void launch_mlp_solve_misfit(const uint64_t* masks, int B, const double* th, const double* delta, const double* rv,
+                             const double* tv, int L, int N, double gscale, double lscale, double* G, double* loss,
+                             hipStream_t s) {
+  const size_t shm = (size_t(L) * (N + 1) + 1) * sizeof(double);
+  if (B > 0)
+    hipLaunchKernelGGL(solve_misfit_kernel, dim3(blocks(B)), dim3(kThreads), shm, s, masks, B, th, delta, rv, tv, L,
+                       N, gscale, lscale, G, loss);
 }
 
 void launch_mlp_dz(const double* G, const double* tz, int R, double dmax, double* dz, hipStream_t s) {

@@ -29,6 +29,10 @@ void launch_mlp_target(const uint64_t* masks, int B, const double* hd, const dou
                        double* target, hipStream_t s);
 // e_b = sum_{i occ} (theta_i + delta[i(N+1) + n_i]) - target[b]; G[i(N+1) + n_i] += scale e_b;
 // loss[0] += lscale e_b^2 (G and loss cleared by the caller)
+// Solve form: rv, tv (B each) the residual and its exact solve at the sampled determinants.
+void launch_mlp_solve_misfit(const uint64_t* masks, int B, const double* th, const double* delta, const double* rv,
+                             const double* tv, int L, int N, double gscale, double lscale, double* G, double* loss,
+                             hipStream_t s);
 void launch_mlp_misfit(const uint64_t* masks, int B, const double* th, const double* delta, const double* target,
                        int L, int N, double scale, double lscale, double* G, double* loss, hipStream_t s);
 // dz[r] = G[r] dmax (1 - tz[r]^2)

@@ -22,7 +22,8 @@ EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
     "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_zform", "pv_run_batch",
-    "pv_set_correction", "pv_learned_correction", "pv_learned_train",
+    "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
+    "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
@@ -129,6 +130,12 @@ def lib():
         L.pv_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int,
                               dp, C.c_int, C.c_double, C.c_double, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        fp, up = C.POINTER(C.c_float), C.POINTER(C.c_uint64)
+        L.pv_learned_train_solves.argtypes = [C.c_void_p, fp, C.c_int, up, C.c_int, dp, dp, C.c_int, C.c_float,
+                                              dp, dp]
+        L.pv_set_learned_network.argtypes = [C.c_void_p, fp, C.c_int]
+        L.pv_solve_h.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, ip, ip, dp]
+        L.pv_mps_amplitudes.argtypes = [C.c_void_p, C.c_int, up, C.c_int, dp]
         L.pv_mpo_bond_dims.argtypes = [C.c_int, dp, dp, ip, ip]
         L.pv_mpo_dense.argtypes = [C.c_int, dp, dp, C.c_double, dp]
         _lib = L
@@ -383,6 +390,49 @@ class Context:
                                       C.c_float(lr), loss.ctypes.data_as(C.POINTER(C.c_double)),
                                       grad.ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None))
         return w, loss, grad
+
+    def learned_train_solves(self, params, masks, rvals, tvals, steps, lr=1e-3, psi=-1, want_grad=False):
+        """Adam steps on the solve form of the misfit (pv_learned_train_solves): the
+        residual values rvals and exact-solve values tvals at the determinants masks.
+        Returns (new float32 parameters, losses (steps + 1), gradient or None)."""
+        w = np.array(params, dtype=np.float32, copy=True)
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"params must have {MLP_PARAMS} entries")
+        m = np.ascontiguousarray(masks, dtype=np.uint64)
+        rv, tv = _f64(rvals), _f64(tvals)
+        if rv.size != m.size or tv.size != m.size:
+            raise ValueError("one residual and one solve value per sample")
+        loss = np.zeros(int(steps) + 1)
+        grad = np.zeros(MLP_PARAMS) if want_grad else None
+        _check(lib().pv_learned_train_solves(self._p, w.ctypes.data_as(C.POINTER(C.c_float)), int(psi),
+                                             m.ctypes.data_as(C.POINTER(C.c_uint64)), int(m.size), _dp(rv), _dp(tv),
+                                             int(steps), C.c_float(lr), loss.ctypes.data_as(C.POINTER(C.c_double)),
+                                             grad.ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None))
+        return w, loss, grad
+
+    def set_learned_network(self, params=None, refresh=1):
+        """Attach a network to the runs (pv_set_learned_network); None detaches it."""
+        if params is None:
+            _check(lib().pv_set_learned_network(self._p, None, 0))
+            return
+        w = np.ascontiguousarray(params, dtype=np.float32)
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"params must have {MLP_PARAMS} entries")
+        _check(lib().pv_set_learned_network(self._p, w.ctypes.data_as(C.POINTER(C.c_float)), int(refresh)))
+
+    def solve_h(self, b, rel_tol=1e-10, max_iter=200):
+        """(handle, iterations, relative residual) of x = (H + gamma)^{-1} b (pv_solve_h)."""
+        out, it, rr = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().pv_solve_h(self._p, int(b), float(rel_tol), int(max_iter), C.byref(out), C.byref(it),
+                                C.byref(rr)))  # argtypes convert the Python numbers
+        return out.value, it.value, rr.value
+
+    def amplitudes(self, handle, masks):
+        m = np.ascontiguousarray(masks, dtype=np.uint64)
+        out = np.zeros(m.size)
+        _check(lib().pv_mps_amplitudes(self._p, int(handle), m.ctypes.data_as(C.POINTER(C.c_uint64)), int(m.size),
+                                       _dp(out)))
+        return out
 
     def run_zform(self, start=-1, **kw):
         """Algorithm 2 on the variable x (pv_run_zform); keyword arguments as in run.  Returns

@@ -131,3 +131,48 @@ def test_corrected_run_reaches_the_same_eigenvalue(small):
     prm = pinvit.Params(cap=64, max_iter=40, tau=1e-9, correction=corr)
     _, hist, _ = pinvit.run(p.h, p.v, N, p.gamma, prm)
     assert 0 <= hist[-1]["lam"] - ed <= 1e-7 * abs(ed)
+
+
+def _solve_samples(p, L, N, seed):
+    """A residual of the method (first iterate of Algorithm 2) and its exact solve on all
+    determinants of the sector."""
+    x = fock.determinant(L, pinvit.initial_determinant(p.h, N))
+    hx = fock.apply_h(p.h, p.v, x, p.gamma)
+    r = hx - float(x @ hx) * x
+    t = learned.exact_solve(p.h, p.v, N, p.gamma, r)
+    masks = [int(m) for m in fock.sector_basis(L, N)]
+    return r, t, masks
+
+
+def test_exact_solve_inverts_the_sector_hamiltonian(small):
+    p, L, N = small, 6, 3
+    r, t, masks = _solve_samples(p, L, N, 0)
+    assert np.abs(fock.apply_h(p.h, p.v, t, p.gamma) - r).max() <= 1e-12 * np.abs(r).max()
+    # nothing outside the sector
+    other = np.setdiff1d(np.arange(1 << L), fock.sector_basis(L, N))
+    assert np.all(t[other] == 0.0)
+
+
+def test_solve_gradient_matches_finite_differences(small):
+    p, L, N = small, 6, 3
+    th, X = _features(p, N)
+    r, t, masks = _solve_samples(p, L, N, 0)
+    dm = learned.delta_max(th)
+    w = learned.bf16(init_params(3, out_scale=1.0))
+    loss, g = learned.solve_loss_grad(w, X, dm, th, masks, r[masks], t[masks], N)
+    # the loss at a zero correction is the misfit of the plain diagonal, a number in (0, 1]
+    w0 = np.zeros_like(w)
+    l0, _ = learned.solve_loss_grad(w0, X, dm, th, masks, r[masks], t[masks], N)
+    d0 = learned.approx_diagonal(th, np.zeros((L, N + 1)), masks)
+    tv = t[masks]
+    assert l0 == pytest.approx(np.sum((r[masks] / d0 - tv) ** 2) / np.sum(tv * tv), rel=1e-12)
+    rng = np.random.default_rng(6)
+    for k in rng.choice(len(w), size=12, replace=False):
+        # steps of two bfloat16 units: the misfit is far from quadratic in the parameters
+        hstep = 2.0 ** (math.floor(math.log2(abs(w[k]) + 1e-30)) - 6) if w[k] != 0 else 2.0 ** -14
+        wp, wm = w.copy(), w.copy()
+        wp[k] += hstep
+        wm[k] -= hstep
+        fp = learned.solve_loss_grad(wp, X, dm, th, masks, r[masks], tv, N)[0]
+        fm = learned.solve_loss_grad(wm, X, dm, th, masks, r[masks], tv, N)[0]
+        assert (fp - fm) / (2 * hstep) == pytest.approx(g[k], rel=2e-2, abs=1e-6 * np.abs(g).max())
