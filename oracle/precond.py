@@ -164,3 +164,37 @@ def apply_sorted(pre: Preconditioner, x: np.ndarray, eta: float, cap: int, N: in
     cap_bound |= cb
     margin = min(margin, mg)
     return y, cap_bound, rounds + 1, margin
+
+
+def _trunc_joint(X, L, N, eps, cap, truncation):
+    if truncation == "parallel":
+        return tt.truncate_parallel_joint(X, L, N, eps, cap)
+    return tt.truncate_joint(X, L, N, eps, cap)
+
+
+def apply_sorted_joint(pre: Preconditioner, X: np.ndarray, eta: float, cap: int, N: int,
+                       truncation: str = "sequential"):
+    """``apply_sorted`` on D columns held jointly (2^L x D): the terms S_m X, their
+    Frobenius norms, and every truncation of the sorted sum acting on the joint tensor.
+    Returns (Y, cap_bound)."""
+    L = pre.L
+    terms = [d[:, None] * X for d in pre.diagonals()]
+    norms = [float(np.linalg.norm(t)) for t in terms]
+    order = sorted(range(len(terms)), key=lambda m: (norms[m], m))
+    csum, j0 = 0.0, 0
+    for j, m in enumerate(order):
+        if csum + norms[m] <= eta / 3.0:
+            csum += norms[m]
+            j0 = j + 1
+        else:
+            break
+    rest = order[j0:]
+    total = sum(norms[m] for m in rest)
+    Y = np.zeros_like(X)
+    cap_bound = False
+    for m in rest:
+        eps_j = eta * norms[m] / (3.0 * total) if total > 0 else 0.0
+        Y, _, cb, _ = _trunc_joint(Y + terms[m], L, N, eps_j, cap, truncation)
+        cap_bound |= cb
+    Y, _, cb, _ = _trunc_joint(Y, L, N, eta / 3.0, cap, truncation)
+    return Y, cap_bound or cb

@@ -169,3 +169,92 @@ def run_subspace(h, v, N, gamma, prm: Params, D: int, X0=None):
         hist.append(rec)
         s_prev2, s_prev = s_prev, max(ns)
     return Phi, hist, pre
+
+
+def run_subspace_joint(h, v, N, gamma, prm: Params, D: int, X0=None):
+    """Algorithm 4 with the D columns held jointly (Section 6.2): the same steps as
+    ``run_subspace``, with every truncation acting on the joint tensor (the column index as
+    one more mode after orbital L, one tolerance for all columns in the Frobenius norm,
+    ranks shared): the products H Psi and the residuals R = H Psi - Psi Lambda with e1, e2,
+    the sorted S sums with their tolerances (``precond.apply_sorted_joint``), and the update
+    Psi <- trunc_{s_min eta_in}(Bas W).  The normalisations Psi <- Phi V and the Ritz
+    combinations act on the column index only.  Same records as ``run_subspace``."""
+    L = h.shape[0]
+    if 2 * D > math.comb(L, N):
+        raise ValueError("the 2D Ritz vectors need a sector of dimension at least 2D")
+    pre = precond.Preconditioner(h, v, N, gamma, prm.c0, prm.c_lower, prm.c_upper, prm.correction)
+    mode = prm.truncation
+
+    def trunc(X, eps):
+        Y, _, cb, _ = precond._trunc_joint(X, L, N, eps, prm.cap, mode)
+        return Y, cb
+
+    def hmul(X):
+        return np.stack([fock.apply_h(h, v, X[:, j], gamma) for j in range(X.shape[1])], axis=1)
+
+    eps_num = prm.eps_num if prm.eps_num is not None else 0.5 * (1.0 - prm.c)
+    zeta = eps_num / (1.0 + prm.c)
+    eta = math.inf
+    if X0 is None:
+        Phi = np.stack([fock.determinant(L, occ) for occ in start_determinants(h, N, D)], axis=1)
+    else:
+        Phi = np.array(X0, dtype=np.float64)
+    hist = []
+    s_prev = s_prev2 = None
+    for it in range(prm.max_iter):
+        HPhi = hmul(Phi)
+        Hm, Em = Phi.T @ HPhi, Phi.T @ Phi
+        lam, V = _gen_eig_lowest(0.5 * (Hm + Hm.T), 0.5 * (Em + Em.T), D)
+        Psi, HPsi = Phi @ V, HPhi @ V
+        if s_prev is None:
+            Y0, _ = trunc(HPsi, 0.0)
+            R0, _ = trunc(Y0 - Psi * lam[None, :], 0.0)
+            est = pre.s_max * float(np.max(np.linalg.norm(R0, axis=0)))
+        elif s_prev2 is None or s_prev2 <= 0.0:
+            est = s_prev
+        else:
+            est = s_prev * min(1.0, s_prev / s_prev2)
+        eta = min(2.0 * eta, 0.8 * zeta * est)
+        retries = 0
+        while True:
+            e12 = eta / (3.0 * pre.s_max)
+            Y, cb1 = trunc(HPsi, e12)
+            R, cb2 = trunc(Y - Psi * lam[None, :], e12)
+            S, cb3 = precond.apply_sorted_joint(pre, R, eta / 3.0, prm.cap, N, mode)
+            ns = np.linalg.norm(S, axis=0)
+            cap_bound = cb1 or cb2 or cb3
+            if ns.min() >= (1.0 + 1.0 / zeta) * eta or cap_bound or retries >= prm.max_retries:
+                break
+            eta *= 0.8
+            retries += 1
+        rho = [(ns[i] + eta) / (math.sqrt(1.0 - prm.c) * math.sqrt(lam[i])) for i in range(D)]
+        bound = bounds.eigvec_error_bound(rho[0], prm.delta)
+        rec = dict(it=it, lam=lam.copy(), E=lam - gamma, rho=np.array(rho), bound=bound,
+                   s_norm=ns.copy(), eta=eta, retries=retries, cap_bound=bool(cap_bound))
+        if bound <= prm.tau:
+            rec["stop"] = True
+            hist.append(rec)
+            return Psi, hist, pre
+        P, _ = precond.apply_sorted_joint(pre, S, pre.s_max * eta / 3.0, prm.cap, N, mode)
+        npn = np.linalg.norm(P, axis=0)
+        if np.all(npn == 0.0):
+            rec["stop"] = True
+            rec["direction_vanished"] = True
+            hist.append(rec)
+            return Psi, hist, pre
+        if np.any(npn == 0.0):
+            raise RuntimeError("a search direction vanished while others did not")
+        Bas = np.concatenate([Psi, P / npn[None, :]], axis=1)
+        HBas = hmul(Bas)
+        B, M = Bas.T @ HBas, Bas.T @ Bas
+        lam_s, W = _gen_eig_lowest(0.5 * (B + B.T), 0.5 * (M + M.T), D)
+        eta_in = math.inf
+        for i in range(D):
+            q = math.sqrt(lam_s[i] / (lam_s[i] + prm.t_eig * (lam[i] - lam_s[i])))
+            eta_in = min(eta_in, bounds.delta_a(rho[i], q) * math.sqrt(lam_s[i]) / math.sqrt(1.0 + prm.c))
+        eta_psi = eta_in * pre.s_min
+        Phi, cb5 = trunc(Bas @ W, eta_psi)
+        rec.update(lam_star=lam_s.copy(), eta_psi=eta_psi, cap_bound=rec["cap_bound"] or bool(cb5))
+        hist.append(rec)
+        s_prev2, s_prev = s_prev, float(ns.max())
+    return Phi, hist, pre

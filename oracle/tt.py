@@ -199,3 +199,96 @@ def truncate_parallel(x: np.ndarray, L: int, N: int, eps: float, cap: int,
             Y[np.ix_(ri, li)] = (U @ (U.T @ B)).T
         y = Y.reshape(-1)
     return y, rho, cap_bound, min_margin
+
+
+# ---------------------------------------------------------------- joint truncation
+#
+# D columns X (2^L x D) held jointly (Section 6.2, joint tensor parameterisation): the
+# column index is one more mode of the tensor, placed after orbital L.  The k-th
+# matricisation then has the configurations of orbitals 1..k as rows and those of
+# orbitals k+1..L together with the column index as columns; it is block diagonal in the
+# particle number n of orbitals 1..k (the index carries none).  Truncations act on the
+# joint tensor with one tolerance for all columns (Frobenius norm).
+
+
+def joint_blocks(X: np.ndarray, L: int, N: int, k: int):
+    """{n: (left_idx, right_idx, B_n)}, B_n = rows x (right configs x D)."""
+    D = X.shape[1]
+    T = X.reshape(1 << (L - k), 1 << k, D)  # [right bits, left bits, column]
+    pl = _popcount_table(k)
+    pr = _popcount_table(L - k)
+    out = {}
+    for n in sectors(L, N, k):
+        li = np.nonzero(pl == n)[0]
+        ri = np.nonzero(pr == N - n)[0]
+        B = np.transpose(T[np.ix_(ri, li, np.arange(D))], (1, 0, 2)).reshape(len(li), len(ri) * D)
+        out[n] = (li, ri, B.copy())
+    return out
+
+
+def _put_joint(X, L, k, li, ri, B):
+    D = X.shape[1]
+    T = X.reshape(1 << (L - k), 1 << k, D)
+    T[np.ix_(ri, li, np.arange(D))] = np.transpose(B.reshape(len(li), len(ri), D), (1, 0, 2))
+
+
+def truncate_joint(X: np.ndarray, L: int, N: int, eps: float, cap: int, zero_tol: float = ZERO_TOL):
+    """Sequential TT-SVD truncation of the joint tensor (``truncate`` with the column index
+    as the last mode): ||X - Y||_F <= eps, ranks shared by all columns.
+    Returns (Y, rho, cap_bound, min_margin)."""
+    delta = eps / math.sqrt(L - 1) if L > 1 else eps
+    Y = X.copy()
+    rho = [dict() for _ in range(L + 1)]
+    rho[0] = {0: 1}
+    rho[L] = {N: X.shape[1]}
+    cap_bound, min_margin = False, math.inf
+    for k in range(1, L):
+        bl = joint_blocks(Y, L, N, k)
+        svd, sv = {}, {}
+        for n, (li, ri, B) in bl.items():
+            if B.size == 0:
+                svd[n], sv[n] = np.zeros((B.shape[0], 0)), np.zeros(0)
+                continue
+            U, s, _ = np.linalg.svd(B, full_matrices=False)
+            svd[n], sv[n] = U, s
+        kept, cb, margin = select(sv, delta, cap, zero_tol)
+        cap_bound |= cb
+        min_margin = min(min_margin, margin)
+        for n, (li, ri, B) in bl.items():
+            U = svd[n][:, :kept[n]]
+            _put_joint(Y, L, k, li, ri, U @ (U.T @ B))
+        rho[k] = dict(kept)
+    return Y, rho, cap_bound, min_margin
+
+
+def truncate_parallel_joint(X: np.ndarray, L: int, N: int, eps: float, cap: int,
+                            zero_tol: float = ZERO_TOL_PARALLEL):
+    """``truncate_parallel`` of the joint tensor: P_1 ... P_{L-1} X with P_k from the k-th
+    joint matricisation of X itself, tolerance eps/sqrt(L-1) per bond (``select_floor``).
+    Returns (Y, rho, cap_bound, min_margin)."""
+    delta = eps / math.sqrt(L - 1) if L > 1 else eps
+    rho = [dict() for _ in range(L + 1)]
+    rho[0] = {0: 1}
+    rho[L] = {N: X.shape[1]}
+    cap_bound, min_margin = False, math.inf
+    proj = {}
+    for k in range(1, L):
+        bl = joint_blocks(X, L, N, k)
+        svd, sv = {}, {}
+        for n, (li, ri, B) in bl.items():
+            if B.size == 0:
+                svd[n], sv[n] = np.zeros((B.shape[0], 0)), np.zeros(0)
+                continue
+            U, s, _ = np.linalg.svd(B, full_matrices=False)
+            svd[n], sv[n] = U, s
+        kept, cb, margin = select_floor(sv, delta, cap, zero_tol)
+        cap_bound |= cb
+        min_margin = min(min_margin, margin)
+        rho[k] = dict(kept)
+        proj[k] = {n: svd[n][:, :kept[n]] for n in bl}
+    Y = X.copy()
+    for k in range(L - 1, 0, -1):
+        for n, (li, ri, B) in joint_blocks(Y, L, N, k).items():
+            U = proj[k][n]
+            _put_joint(Y, L, k, li, ri, U @ (U.T @ B))
+    return Y, rho, cap_bound, min_margin
