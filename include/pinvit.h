@@ -21,6 +21,8 @@
  * - Block table rho: an (L+1) x (N+1) int32 array, row-major, rho[k*(N+1)+n] is the
  *   dimension of sector n on bond k (n = number of particles among orbitals 1..k).
  *   Entries outside K_k = {max(0,N-L+k)..min(N,k)} are 0; rho[0][0] = rho[L][N] = 1.
+ * - A joint MPS (several columns, pv_run_subspace_joint) has rho[L][N] = D, the column
+ *   index; its last blocks have D columns.
  * - MPS data layout (export and import): sites k = 1..L in order; inside a site,
  *   left sectors n in K_{k-1} ascending; for each, the unoccupied block U_{k,n}
  *   (rho[k-1][n] x rho[k][n], present when n is in K_k) followed by the occupied
@@ -283,6 +285,20 @@ pv_status pv_run_zform(pv_ctx* ctx, const pv_params* prm, int start, pv_result* 
  * not positive definite. */
 pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* starts, pv_result* res,
                           pv_subspace_iter* hist, int hist_cap, int* psi);
+
+/* Algorithm 4 with the D columns held jointly (Section 6.2, joint tensor parameterisation):
+ * one block-sparse MPS whose right boundary rho[L][N] = D is the column index (the
+ * paper's additional core at position K+1).  The steps are those of pv_run_subspace, but
+ * every product with H, residual (R = H Psi - Psi Lambda), sorted S sum and truncation acts
+ * on all columns at once: one tolerance for the joint tensor (Frobenius norm) and ranks
+ * shared by the columns, which need a rank cap of up to the sum of the columns' ranks.
+ * The normalisation Psi <- Phi V and the Ritz combinations [Psi | P] W are applied to the
+ * column index (the last core).  start: a handle of a joint MPS with D columns
+ * (pv_mps_create with rho[L][N] = D, columns in the last core's column index), or -1 for
+ * the D start determinants of pv_run_subspace; *psi (may be NULL) receives the handle of
+ * the final joint MPS.  res, hist and the errors as pv_run_subspace. */
+pv_status pv_run_subspace_joint(pv_ctx* ctx, const pv_params* prm, int D, int start, pv_result* res,
+                                pv_subspace_iter* hist, int hist_cap, int* psi);
 
 /* Learned correction of the preconditioner diagonal (an extension, not in the paper).
  * The correction Delta (L x (N+1), row-major, entry [i][n]) changes theta_i to

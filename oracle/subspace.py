@@ -235,7 +235,7 @@ def run_subspace_joint(h, v, N, gamma, prm: Params, D: int, X0=None):
             rec["stop"] = True
             hist.append(rec)
             return Psi, hist, pre
-        P, _ = precond.apply_sorted_joint(pre, S, pre.s_max * eta / 3.0, prm.cap, N, mode)
+        P, cb4 = precond.apply_sorted_joint(pre, S, pre.s_max * eta / 3.0, prm.cap, N, mode)
         npn = np.linalg.norm(P, axis=0)
         if np.all(npn == 0.0):
             rec["stop"] = True
@@ -254,7 +254,7 @@ def run_subspace_joint(h, v, N, gamma, prm: Params, D: int, X0=None):
             eta_in = min(eta_in, bounds.delta_a(rho[i], q) * math.sqrt(lam_s[i]) / math.sqrt(1.0 + prm.c))
         eta_psi = eta_in * pre.s_min
         Phi, cb5 = trunc(Bas @ W, eta_psi)
-        rec.update(lam_star=lam_s.copy(), eta_psi=eta_psi, cap_bound=rec["cap_bound"] or bool(cb5))
+        rec.update(lam_star=lam_s.copy(), eta_psi=eta_psi, cap_bound=rec["cap_bound"] or bool(cb4 or cb5))
         hist.append(rec)
         s_prev2, s_prev = s_prev, float(ns.max())
     return Phi, hist, pre

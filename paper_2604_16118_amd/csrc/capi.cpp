@@ -405,7 +405,8 @@ pv_status pv_mps_create(pv_ctx* ctx, const int32_t* rho, const double* data, siz
         if (!probe.valid(k, nn) && x != 0) fail(PV_EINVAL, "nonzero rank outside the sector set K_k");
         r[k][nn] = x;
       }
-    if (r[0][0] != 1 || r[L][N] != 1) fail(PV_EINVAL, "rho[0][0] and rho[L][N] must be 1");
+    if (r[0][0] != 1 || r[L][N] < 1 || r[L][N] > PV_SUBSPACE_MAX_D)
+      fail(PV_EINVAL, "rho[0][0] must be 1 and rho[L][N] (the number of columns) 1..PV_SUBSPACE_MAX_D");
     auto m = mps_alloc(c, L, N, r);
     if (size_t(m->size()) != n) fail(PV_EINVAL, "data length does not match the block table");
     if (!data && n) fail(PV_EINVAL, "null data");
@@ -1478,6 +1479,216 @@ pv_status pv_run_subspace(pv_ctx* ctx, const pv_params* prm, int D, const int* s
     res->iterations = rows;
     if (psi_out)
       for (int i = 0; i < D; ++i) psi_out[i] = put(c, std::move(phi[i]));
+  });
+}
+
+// Algorithm 4 with the D columns held jointly (Section 6.2): one MPS whose right boundary
+// is the column index.  The same steps as pv_run_subspace, with every product, residual,
+// S sum and truncation acting on all columns at once (one tolerance, shared ranks), the
+// normalisation and the Ritz combinations applied to the column index (the last core).
+pv_status pv_run_subspace_joint(pv_ctx* ctx, const pv_params* prm, int D, int start, pv_result* res,
+                                pv_subspace_iter* hist, int hist_cap, int* psi_out) {
+  return guard([&] {
+    if (!ctx || !prm || !res) fail(PV_EINVAL, "null argument");
+    if (D < 1 || D > PV_SUBSPACE_MAX_D) fail(PV_EINVAL, "D out of range");
+    Ctx& c = ctx->c;
+    if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+    {
+      double dim = 1.0;
+      for (int i = 1; i <= c.N; ++i) dim = dim * double(c.L - c.N + i) / double(i);
+      if (2.0 * D > dim + 0.5) fail(PV_EINVAL, "the 2D Ritz vectors need a sector of dimension at least 2D");
+    }
+    const pv_params p = *prm;
+    if (p.rank_cap < 1 || p.max_iter < 0 || !(p.c > 0 && p.c < 1) || !(p.delta > 1) || !(p.c0 > 0 && p.c0 < 1) ||
+        !(p.t_eig > 0 && p.t_eig < 1) || !(p.tau >= 0))
+      fail(PV_EINVAL, "invalid parameters");
+    if (p.precision < 0 || p.precision > 2)
+      fail(PV_EINVAL, "precision must be 0 (float64), 1 (float32 contractions) or 2 (bfloat16 contractions)");
+    if (p.truncation != 0 && p.truncation != 1) fail(PV_EINVAL, "truncation mode must be 0 or 1");
+    c.prec = p.precision;
+    c.trunc_mode = p.truncation;
+    setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0);
+    const int L = c.L, N = c.N, cap = p.rank_cap, mz = p.m_zip;
+    const double eps_num = p.eps_num > 0 ? p.eps_num : 0.5 * (1.0 - p.c);
+    const double zeta = eps_num / (1.0 + p.c);
+    double eta = std::numeric_limits<double>::infinity();
+    double s_prev = -1, s_prev2 = -1;
+    std::unique_ptr<Mps> phi;
+    if (start >= 0) {
+      const Mps& s0 = get(c, start);
+      if (s0.rho[L][N] != D) fail(PV_EINVAL, "the start holds a different number of columns");
+      phi = mps_scaled_copy(c, s0, 1.0, nullptr);
+    } else {
+      const auto dets = subspace_starts(c.h, L, N, D);
+      phi = mps_determinant(c, dets[0]);
+      for (int i = 1; i < D; ++i) {
+        auto d = mps_determinant(c, dets[i]);
+        phi = mps_lincomb(c, 1.0, *phi, 1.0, *d, true);
+      }
+    }
+    // symmetric part of a column-major D x D result, row-major for small_pencil
+    auto sym = [](const std::vector<double>& v, int n) {
+      std::vector<double> o(size_t(n) * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) o[size_t(i) * n + j] = 0.5 * (v[size_t(i) + size_t(n) * j] + v[size_t(j) + size_t(n) * i]);
+      return o;
+    };
+    auto col_norms = [&](const Mps& x) {
+      auto g = dot_matrix(c, x, x);
+      std::vector<double> nv(D);
+      for (int i = 0; i < D; ++i) nv[i] = std::sqrt(std::max(g[size_t(i) + size_t(D) * i], 0.0));
+      return nv;
+    };
+    auto diag = [&](const std::vector<double>& d) {
+      std::vector<double> W(size_t(D) * D, 0.0);
+      for (int i = 0; i < D; ++i) W[size_t(i) + size_t(D) * i] = d[i];
+      return W;
+    };
+    int rows = 0;
+    *res = pv_result{};
+    for (int it = 0; it < p.max_iter; ++it) {
+      const auto t0 = std::chrono::steady_clock::now();
+      pv_subspace_iter rec{};
+      // 1. Rayleigh-Ritz on span phi; psi = phi C (the index core times C)
+      std::vector<double> lam, Cm;
+      small_pencil(D, sym(expect_matrix(c, *phi, *phi), D), sym(dot_matrix(c, *phi, *phi), D), D, lam, Cm);
+      std::vector<double> Wc(size_t(D) * D);
+      for (int j = 0; j < D; ++j)
+        for (int i = 0; i < D; ++i) Wc[size_t(j) + size_t(D) * i] = Cm[size_t(j) * D + i];
+      for (int i = 0; i < D; ++i)
+        if (!(lam[i] > 0)) fail(PV_ENOTSPD, "Rayleigh quotient is not positive (H_gamma not positive definite)");
+      auto psi = mps_index_transform(c, *phi, Wc, D);
+      auto psil = mps_index_transform(c, *psi, diag(lam), D);  // psi Lambda
+      // 2. start value of eta_res (largest column norm)
+      double est = 0.0;
+      if (s_prev < 0) {
+        std::unique_ptr<Mps> y0;
+        {
+          LowPrecision lp(c);
+          y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
+        }
+        auto d0 = mps_lincomb(c, 1.0, *y0, -1.0, *psil);
+        auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
+        for (double v : col_norms(*r0)) est = std::max(est, c.s_max * v);
+      } else if (s_prev2 <= 0) {
+        est = s_prev;
+      } else {
+        est = s_prev * std::min(1.0, s_prev / s_prev2);
+      }
+      eta = std::min(2.0 * eta, 0.8 * zeta * est);
+      // 3.-4. joint residual R = H psi - psi Lambda and S = S(R)
+      int retries = 0;
+      bool capb = false;
+      std::unique_ptr<Mps> S;
+      std::vector<double> ns;
+      while (true) {
+        bool cb1 = false, cb2 = false, cb3 = false;
+        const double e12 = eta / (3.0 * c.s_max);
+        std::unique_ptr<Mps> y;
+        {
+          LowPrecision lp(c);
+          y = apply_h(c, *psi, e12, cap, mz, &cb1);
+        }
+        auto d = mps_lincomb(c, 1.0, *y, -1.0, *psil);
+        y.reset();
+        auto r = round_mps(c, *d, e12, cap, &cb2);
+        d.reset();
+        S = apply_s(c, *r, eta / 3.0, cap, &cb3);
+        ns = col_norms(*S);
+        capb = cb1 || cb2 || cb3;
+        if (*std::min_element(ns.begin(), ns.end()) >= (1.0 + 1.0 / zeta) * eta || capb || retries >= p.max_retries)
+          break;
+        eta *= 0.8;
+        ++retries;
+      }
+      std::vector<double> rho(D);
+      for (int i = 0; i < D; ++i) rho[i] = (ns[i] + eta) / (std::sqrt(1.0 - p.c) * std::sqrt(lam[i]));
+      const double bound = error_bound(rho[0], p.delta);
+      for (int i = 0; i < D; ++i) {
+        rec.lambda[i] = lam[i];
+        rec.energy[i] = lam[i] - c.gamma;
+        rec.rho[i] = rho[i];
+        rec.s_norm[i] = ns[i];
+      }
+      rec.bound = bound;
+      rec.eta_res = eta;
+      rec.retries = retries;
+      rec.cap_bound = capb ? 1 : 0;
+      res->energy = lam[0] - c.gamma;
+      res->lambda = lam[0];
+      res->rho = rho[0];
+      res->bound = bound;
+      res->eta_res = eta;
+      auto finish = [&]() {
+        rec.stopped = 1;
+        rec.max_rank = psi->max_rank();
+        c.sync();
+        rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (hist && rows < hist_cap) hist[rows] = rec;
+        ++rows;
+        res->converged = 1;
+        phi = std::move(psi);
+      };
+      if (bound <= p.tau) {
+        finish();
+        break;
+      }
+      // 6. directions P = S(S R), columns normalised; Rayleigh-Ritz on [psi | P]
+      bool cb4 = false;
+      auto P = apply_s(c, *S, c.s_max * eta / 3.0, cap, &cb4);
+      S.reset();
+      const auto np = col_norms(*P);
+      int vanished = 0;
+      for (double v : np) vanished += !(v > 0);
+      if (vanished == D) {
+        finish();
+        break;
+      }
+      if (vanished) fail(PV_ENOCONV, "a search direction vanished while others did not");
+      std::vector<double> inv(D);
+      for (int i = 0; i < D; ++i) inv[i] = 1.0 / np[i];
+      auto pn = mps_index_transform(c, *P, diag(inv), D);
+      P.reset();
+      auto bas = mps_lincomb(c, 1.0, *psi, 1.0, *pn, true);  // 2D columns
+      pn.reset();
+      const int n2 = 2 * D;
+      std::vector<double> Bm, Mm;
+      {
+        LowPrecision lp(c);
+        Bm = sym(expect_matrix(c, *bas, *bas), n2);
+      }
+      Mm = sym(dot_matrix(c, *bas, *bas), n2);
+      std::vector<double> lam_s, W;
+      small_pencil(n2, Bm, Mm, D, lam_s, W);
+      // 7. truncation tolerance and the update psi <- trunc(bas W)
+      double eta_in = std::numeric_limits<double>::infinity();
+      for (int i = 0; i < D; ++i) {
+        const double q = std::sqrt(lam_s[i] / (lam_s[i] + p.t_eig * (lam[i] - lam_s[i])));
+        eta_in = std::min(eta_in, delta_a(rho[i], q) * std::sqrt(lam_s[i]) / std::sqrt(1.0 + p.c));
+      }
+      const double eta_psi = eta_in * c.s_min;
+      std::vector<double> Wc2(size_t(n2) * D);
+      for (int l = 0; l < n2; ++l)
+        for (int i = 0; i < D; ++i) Wc2[size_t(l) + size_t(n2) * i] = W[size_t(l) * D + i];
+      auto comb = mps_index_transform(c, *bas, Wc2, D);
+      bas.reset();
+      bool cb5 = false;
+      phi = round_mps(c, *comb, eta_psi, cap, &cb5);
+      c.sync();
+      for (int i = 0; i < D; ++i) rec.lambda_star[i] = lam_s[i];
+      rec.eta_psi = eta_psi;
+      rec.cap_bound |= (cb4 || cb5) ? 1 : 0;
+      rec.max_rank = phi->max_rank();
+      rec.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (hist && rows < hist_cap) hist[rows] = rec;
+      ++rows;
+      s_prev2 = s_prev;
+      s_prev = *std::max_element(ns.begin(), ns.end());
+      res->s_last = s_prev;
+      res->s_prev = s_prev2;
+    }
+    res->iterations = rows;
+    if (psi_out) *psi_out = put(c, std::move(phi));
   });
 }
 

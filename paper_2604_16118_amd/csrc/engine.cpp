@@ -1040,15 +1040,61 @@ static const DevMpo& identity_mpo(Ctx& c, int L) {
   return *c.ident;
 }
 
+// sum_i v[i + D i] of a D x D result (column-major), v[0] for one column
+static double trace_of(const std::vector<double>& v, int Da, int Db) {
+  if (v.empty()) return 0.0;
+  if (Da != Db) fail(PV_EINVAL, "inner product of MPS with different numbers of columns");
+  double t = 0.0;
+  for (int i = 0; i < Da; ++i) t += v[size_t(i) + size_t(Da) * i];
+  return t;
+}
+
 double dot(Ctx& c, const Mps& a, const Mps& b) {
   auto v = env_sweep(c, a, b, identity_mpo(c, a.L));
-  return v.empty() ? 0.0 : v[0];
+  return trace_of(v, a.rho[a.L][a.N], b.rho[b.L][b.N]);
+}
+
+std::vector<double> dot_matrix(Ctx& c, const Mps& a, const Mps& b) {
+  return env_sweep(c, a, b, identity_mpo(c, a.L));
+}
+
+std::vector<double> expect_matrix(Ctx& c, const Mps& bra, const Mps& ket) {
+  if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+  return env_sweep(c, bra, ket, *c.hmpo);
+}
+
+// x with its column index transformed: the last core's blocks times W (Din x Dout,
+// column-major, host): column j of the result is sum_i W_ij (column i of x).
+std::unique_ptr<Mps> mps_index_transform(Ctx& c, const Mps& x, const std::vector<double>& W, int Dout) {
+  const int L = x.L, N = x.N, Din = x.rho[L][N];
+  if (int64_t(W.size()) != int64_t(Din) * Dout) fail(PV_EINVAL, "index transform of the wrong size");
+  auto rho = x.rho;
+  rho[L][N] = Dout;
+  auto y = mps_alloc(c, L, N, rho);
+  CopyBatch cb;
+  for (int k = 1; k < L; ++k) cb.add(x.site[k - 1].p, 1, y->site[k - 1].p, 1, int(x.site_size(k)), 1, 1.0);
+  cb.run(c);
+  Buf w(c.pool, W.size());
+  PV_HIP(hipMemcpyAsync(w.p, W.data(), W.size() * 8, hipMemcpyHostToDevice, c.stream));
+  GemmBatch g;
+  CopyBatch zero;
+  for (int n = 0; n <= N; ++n) {
+    if (!x.valid(L - 1, n)) continue;
+    const int r = x.rows(L, n);
+    if (r == 0) continue;
+    if (y->ucols(L, n)) g.add(x.U(L, n), r, 0, w.p, Din, 0, y->U(L, n), r, r, Dout, Din, 1.0, 0.0);
+    if (y->ocols(L, n)) g.add(x.O(L, n), r, 0, w.p, Din, 0, y->O(L, n), r, r, Dout, Din, 1.0, 0.0);
+  }
+  g.run(c);
+  c.sync();  // the host W goes out of scope with the caller
+  c.scratch.push_back(std::move(w));
+  return y;
 }
 
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
   auto v = env_sweep(c, bra, ket, *c.hmpo);
-  return v.empty() ? 0.0 : v[0];
+  return trace_of(v, bra.rho[bra.L][bra.N], ket.rho[ket.L][ket.N]);
 }
 
 void sym_eig_tridiag_device(Ctx& c, int n, const double* A, double* w, double* V, double* work, EigDesc* desc) {
@@ -1171,14 +1217,18 @@ std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const doubl
   return m;
 }
 
-// a x + b y by concatenation of blocks (Section 2.3).
-std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y) {
+// a x + b y by concatenation of blocks (Section 2.3).  With index_concat the right
+// boundaries (column indices of joint MPS) are concatenated too: the last cores go block
+// diagonal and the result holds the columns of x followed by those of y (Section 6.2).
+std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y, bool index_concat) {
   const int L = x.L, N = x.N;
   if (y.L != L || y.N != N) fail(PV_EINVAL, "lincomb: mismatched chains");
+  if (!index_concat && x.rho[L][N] != y.rho[L][N]) fail(PV_EINVAL, "lincomb: different numbers of columns");
   auto rho = empty_rho(L, N);
   for (int k = 0; k <= L; ++k)
     for (int n = 0; n <= N; ++n)
-      if (x.valid(k, n)) rho[k][n] = (k == 0 || k == L) ? 1 : x.rho[k][n] + y.rho[k][n];
+      if (x.valid(k, n))
+        rho[k][n] = k == 0 ? 1 : k < L ? x.rho[k][n] + y.rho[k][n] : index_concat ? x.rho[k][n] + y.rho[k][n] : x.rho[k][n];
   auto m = mps_alloc(c, L, N, rho);
   CopyBatch zero, cb;  // every site cleared in one launch, then the blocks copied in
   for (int k = 1; k <= L; ++k) zero.add_fill(m->site[k - 1].p, m->site_size(k), 0.0);
@@ -1197,7 +1247,7 @@ std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const
         double* dst = kind ? m->O(k, n) : m->U(k, n);
         const double* sx = kind ? x.O(k, n) : x.U(k, n);
         const double* sy = kind ? y.O(k, n) : y.U(k, n);
-        const int cy0 = (k == L) ? 0 : cx;  // column offset of y part
+        const int cy0 = (k == L && !index_concat) ? 0 : cx;  // column offset of y part
         cb.add(sx, rx, dst + rx0, R, rx, cx, fx);
         cb.add(sy, ry, dst + ry0 + int64_t(R) * cy0, R, ry, cy, fy);
       }
@@ -1560,7 +1610,12 @@ BondGrams right_grams(Ctx& c, const Mps& x) {
   const int L = x.L, N = x.N;
   BondGrams g = alloc_grams(c, x);
   fill(c, g.buf.p, int64_t(g.buf.n), 0.0);
-  fill(c, g.buf.p + g.off[L][N], 1, 1.0);
+  {
+    // identity over the right boundary (the column index of a joint MPS, else 1 x 1)
+    CopyBatch one;
+    one.add_fill_strided(g.buf.p + g.off[L][N], x.rho[L][N] + 1, x.rho[L][N], 1.0);
+    one.run(c);
+  }
   for (int k = L; k >= 2; --k) {
     std::vector<Buf> T(N + 1);
     GemmBatch gb, g2;
@@ -1833,14 +1888,16 @@ std::unique_ptr<Mps> apply_h(Ctx& c, const Mps& xin, double eps, int cap, int m_
       r1[n2] = t2.off[1][n2] >= 0 ? t2.rows[1][n2] : 0;
     }
     if (k == L) {
-      // last core: M itself (single column)
-      y->rho[L][N] = 1;
+      // last core: the panel itself, one column per column of x (the right boundary: 1, or
+      // the column index of a joint MPS)
+      const int D = x.rho[L][N];
+      y->rho[L][N] = D;
       alloc_site(c, *y, L);
       CopyBatch cb;
       fill(c, y->site[L - 1].p, y->site_size(L), 0.0);
-      if (r0[N] && y->ucols(L, N)) cb.add(t2.buf.p + t2.off[0][N], r0[N], y->U(L, N), y->rows(L, N), r0[N], 1, 1.0);
+      if (r0[N] && y->ucols(L, N)) cb.add(t2.buf.p + t2.off[0][N], r0[N], y->U(L, N), y->rows(L, N), r0[N], D, 1.0);
       if (r1[N] && N >= 1 && y->ocols(L, N - 1))
-        cb.add(t2.buf.p + t2.off[1][N], r1[N], y->O(L, N - 1), y->rows(L, N - 1), r1[N], 1, 1.0);
+        cb.add(t2.buf.p + t2.off[1][N], r1[N], y->O(L, N - 1), y->rows(L, N - 1), r1[N], D, 1.0);
       cb.run(c);
       c.scratch.push_back(std::move(t2.buf));
       break;
@@ -2040,8 +2097,14 @@ std::unique_ptr<Mps> apply_s(Ctx& c, const Mps& x, double eta, int cap, bool* ca
     }
   auto op = diag_mpo(c, L, M, d0, d1);
   std::vector<double> n2 = env_sweep(c, x, x, *op);
+  // final environment: bra column a, channel m, ket column b at a + D (m + M b)
+  const int D = x.rho[L][x.N];
   std::vector<double> nrm(M);
-  for (int m = 0; m < M; ++m) nrm[m] = std::sqrt(std::max(n2[m], 0.0));
+  for (int m = 0; m < M; ++m) {
+    double t = 0.0;
+    for (int i = 0; i < D; ++i) t += n2[size_t(i) + size_t(D) * (m + size_t(M) * i)];
+    nrm[m] = std::sqrt(std::max(t, 0.0));
+  }
   std::vector<int> order(M);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int a, int b) { return nrm[a] != nrm[b] ? nrm[a] < nrm[b] : a < b; });

@@ -194,7 +194,14 @@ struct Ctx {
 // ---- operations (engine.cpp) ----
 std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vector<int>>& rho);
 std::unique_ptr<Mps> mps_determinant(Ctx& c, const std::vector<int>& occ);
-std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y);
+std::unique_ptr<Mps> mps_lincomb(Ctx& c, double a, const Mps& x, double b, const Mps& y, bool index_concat = false);
+// Joint MPS (several columns): the right boundary rho[L][N] = D is the column index
+// (Section 6.2, the index core after orbital L).  dot and expect_h return the traces over
+// the columns; the matrices of all column pairs (D_a x D_b, column-major):
+std::vector<double> dot_matrix(Ctx& c, const Mps& a, const Mps& b);
+std::vector<double> expect_matrix(Ctx& c, const Mps& bra, const Mps& ket);
+// column j of the result = sum_i W[i + Din j] (column i of x)
+std::unique_ptr<Mps> mps_index_transform(Ctx& c, const Mps& x, const std::vector<double>& W, int Dout);
 std::unique_ptr<Mps> mps_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ_scale);
 std::unique_ptr<Mps> mps_zero_like(Ctx& c, const Mps& x);
 std::unique_ptr<Mps> mps_sector_scaled_copy(Ctx& c, const Mps& x, double a, const double* occ);

@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_zform", "pv_run_batch",
+    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_subspace_joint", "pv_run_zform", "pv_run_batch",
     "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
@@ -120,6 +120,8 @@ def lib():
                                    C.POINTER(Iter), C.c_int, ip]
         L.pv_run_subspace.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, ip, C.POINTER(Result),
                                       C.POINTER(SubspaceIter), C.c_int, ip]
+        L.pv_run_subspace_joint.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int, C.c_int, C.POINTER(Result),
+                                            C.POINTER(SubspaceIter), C.c_int, ip]
         L.pv_run_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Params), C.POINTER(Result), ip]
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
@@ -473,6 +475,29 @@ class Context:
                              stop=bool(h.stopped)))
         return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
                     iterations=res.iterations, converged=bool(res.converged)), rows, list(out)
+
+    def run_subspace_joint(self, D, start=-1, **kw):
+        """Algorithm 4 with the columns held jointly (pv_run_subspace_joint).  Returns
+        (result dict of column 1, rows, handle of the final joint MPS)."""
+        if not 1 <= D <= SUBSPACE_MAX_D:
+            raise ValueError(f"D must be in 1..{SUBSPACE_MAX_D}")
+        kw.setdefault("max_iter", 20)
+        n = max(kw["max_iter"], 1)
+        prm = make_params(**kw)
+        res = Result()
+        hist = (SubspaceIter * n)()
+        out = C.c_int()
+        _check(lib().pv_run_subspace_joint(self._p, C.byref(prm), int(D), int(start), C.byref(res), hist, n,
+                                           C.byref(out)))
+        rows = []
+        for h in hist[:res.iterations]:
+            rows.append(dict(lam=np.array(h.lambda_[:D]), E=np.array(h.energy[:D]), rho=np.array(h.rho[:D]),
+                             s_norm=np.array(h.s_norm[:D]), lam_star=np.array(h.lambda_star[:D]),
+                             bound=h.bound, eta=h.eta_res, eta_psi=h.eta_psi, seconds=h.seconds,
+                             retries=h.retries, cap_bound=bool(h.cap_bound), max_rank=h.max_rank,
+                             stop=bool(h.stopped)))
+        return dict(energy=res.energy, lam=res.lambda_, rho=res.rho, bound=res.bound,
+                    iterations=res.iterations, converged=bool(res.converged)), rows, out.value
 
     def sym_eig(self, A, method, nvec=None):
         A = _f64(np.asfortranarray(A))
