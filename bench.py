@@ -534,6 +534,22 @@ def subspace_bench(a):
     t1 = time.perf_counter()
     for h in cols + cols2:
         ctx.mps_free(h)
+    joint = None
+    if a.joint:
+        # the same iterations on one joint MPS (Section 6.2), whose shared ranks may reach
+        # the sum of the columns' ranks: cap and m_zip D times those of one column
+        cj = dict(common, rank_cap=D * a.cap, m_zip=D * a.m_zip if a.m_zip > 0 else a.m_zip)
+        _, hwj, hj = ctx.run_subspace_joint(D, max_iter=a.warmup, **cj)
+        print(f"# joint D={D}: warmup {a.warmup} it, ranks {[r['max_rank'] for r in hwj]}", file=sys.stderr,
+              flush=True)
+        t2 = time.perf_counter()
+        _, histj, hj2 = ctx.run_subspace_joint(D, start=hj, max_iter=a.steps, **cj)
+        t3 = time.perf_counter()
+        ctx.mps_free(hj)
+        ctx.mps_free(hj2)
+        joint = {"value": len(histj) / (t3 - t2), "unit": "iter/s", "ms_per_step": 1e3 * (t3 - t2) / max(len(histj), 1),
+                 "rank_cap": D * a.cap, "energies": [float(x) for x in histj[-1]["E"]] if histj else [],
+                 "max_rank": max([r["max_rank"] for r in histj] + [0])}
     ctx.close()
     out = {"metric": f"subspace PINVIT (Alg. 4) iterations/s, D={D} columns", "value": len(hist) / (t1 - t0),
            "unit": "iter/s", "n_gpus": 1, "steps": len(hist), "warmup": a.warmup,
@@ -544,6 +560,8 @@ def subspace_bench(a):
                       "D": D, "rank_cap": a.cap, "m_zip": a.m_zip},
            "energies": [float(x) for x in hist[-1]["E"]] if hist else [],
            "max_rank": max([r["max_rank"] for r in hist] + [0])}
+    if joint is not None:
+        out["joint"] = joint
     print(json.dumps(out), flush=True)
 
 
@@ -616,6 +634,8 @@ def main():
                     help="instead of the L=48 run: z-form against psi-form at --L/--N/--cap/--m-zip")
     ap.add_argument("--subspace", type=int, default=0, metavar="D",
                     help="instead of the L=48 run: Algorithm 4 on D columns at --L/--N/--cap/--m-zip")
+    ap.add_argument("--joint", action="store_true",
+                    help="with --subspace: also run the columns as one joint MPS (cap and m_zip times D)")
     ap.add_argument("--learned", action="store_true",
                     help="train the learned preconditioner correction and compare runs with and without it")
     ap.add_argument("--train-steps", type=int, default=200)

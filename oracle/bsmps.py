@@ -44,12 +44,23 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.linalg
 
 from . import bounds, precond, tt
 from .mps import block_shapes, to_dense as _dense_of_export, unpack
 from .tt import sectors
 
 # ---------------------------------------------------------------- block-sparse MPS
+
+
+def _svd(M):
+    """Thin SVD.  LAPACK's divide-and-conquer driver (NumPy's) now and then reports
+    non-convergence on strongly graded blocks; the QR-iteration driver then computes
+    the same factorisation."""
+    try:
+        return np.linalg.svd(M, full_matrices=False)
+    except np.linalg.LinAlgError:
+        return scipy.linalg.svd(M, full_matrices=False, lapack_driver="gesvd")
 
 
 def _valid(L, N, k, n):
@@ -225,7 +236,7 @@ def right_orthogonalize(x: BMps, zero_tol: float = tt.ZERO_TOL) -> BMps:
             if C.size == 0:
                 svd[n] = (np.zeros((C.shape[0], 0)), np.zeros(0), np.zeros((0, C.shape[1])))
                 continue
-            U, S, Vt = np.linalg.svd(C, full_matrices=False)
+            U, S, Vt = _svd(C)
             svd[n] = (U, S, Vt)
             if S.size:
                 smax = max(smax, S[0])
@@ -280,7 +291,7 @@ def truncate(x: BMps, eps: float, cap: int, zero_tol: float = tt.ZERO_TOL):
                 svd[n] = (np.zeros((M.shape[0], 0)), np.zeros(0), np.zeros((0, M.shape[1])))
                 sv[n] = np.zeros(0)
                 continue
-            svd[n] = np.linalg.svd(M, full_matrices=False)
+            svd[n] = _svd(M)
             sv[n] = svd[n][1]
         kept, cb, margin = tt.select(sv, delta, cap, zero_tol)
         cap_bound |= cb
@@ -318,7 +329,7 @@ def _left_factors(x: BMps):
             if M.size == 0:
                 R[k][n] = np.zeros((0, M.shape[1]))
                 continue
-            _, S, Vt = np.linalg.svd(M, full_matrices=False)
+            _, S, Vt = _svd(M)
             R[k][n] = S[:, None] * Vt
     return R
 
@@ -339,7 +350,7 @@ def _right_factors(x: BMps):
             if M.size == 0:
                 R[k][n] = np.zeros((M.shape[0], 0))
                 continue
-            U, S, _ = np.linalg.svd(M, full_matrices=False)
+            U, S, _ = _svd(M)
             R[k][n] = U * S
     return R
 
@@ -368,7 +379,7 @@ def truncate_parallel(x: BMps, eps: float, cap: int, zero_tol: float = tt.ZERO_T
                 svd[n] = (np.zeros((C.shape[0], 0)), np.zeros(0), np.zeros((0, C.shape[1])))
                 sv[n] = np.zeros(0)
                 continue
-            svd[n] = np.linalg.svd(C, full_matrices=False)
+            svd[n] = _svd(C)
             sv[n] = svd[n][1]
         kept, cb, margin = tt.select_floor(sv, delta, cap, zero_tol)
         cap_bound |= cb
@@ -731,7 +742,7 @@ def zipup(x: BMps, mpo: Mpo, m_zip: int, zero_tol: float = tt.ZERO_TOL, per_cut:
                 svd[n2] = (np.zeros((P.shape[0], 0)), np.zeros(0), np.zeros((0, P.shape[1])))
                 sv[n2] = np.zeros(0)
                 continue
-            svd[n2] = np.linalg.svd(P, full_matrices=False)
+            svd[n2] = _svd(P)
             sv[n2] = svd[n2][1]
         kept, _, _ = tt.select(sv, 0.0, zcap, zero_tol)
         smax = max([s[0] for s in sv.values() if s.size] + [0.0])
