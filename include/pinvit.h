@@ -200,6 +200,15 @@ pv_status pv_mps_free(pv_ctx* ctx, int handle);
  *   single-pass factorisations. */
 pv_status pv_set_truncation(pv_ctx* ctx, int mode);
 
+/* Tuning of the symmetric eigensolver behind every truncation (the Householder reduction
+ * to tridiagonal form, Section 2.2's SVDs taken through Gram matrices): a batch of at most
+ * max_problems matrices is reduced one Householder step per launch with several
+ * workgroups per matrix; a larger batch by panels of 32 steps with one workgroup per
+ * matrix and GEMM trailing updates.  Both give the same decomposition up to rounding.
+ * Default PV_TRIDIAG_STEPS_DEFAULT.  PV_EINVAL for max_problems < 0. */
+#define PV_TRIDIAG_STEPS_DEFAULT 1073741824
+pv_status pv_set_tridiag_steps(pv_ctx* ctx, int max_problems);
+
 /* <a|b> (Euclidean inner product) by a transfer sweep. */
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out);
 /* <bra|H_gamma|ket> by an environment sweep with the MPO (eq. exactrq, one term). */

@@ -483,6 +483,14 @@ pv_status pv_set_truncation(pv_ctx* ctx, int mode) {
   });
 }
 
+pv_status pv_set_tridiag_steps(pv_ctx* ctx, int max_problems) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    if (max_problems < 0) fail(PV_EINVAL, "max_problems must be >= 0");
+    ctx->c.tri_step_max = max_problems;
+  });
+}
+
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out) {
   return guard([&] {
     if (!ctx || !out) fail(PV_EINVAL, "null argument");

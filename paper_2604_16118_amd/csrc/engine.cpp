@@ -126,11 +126,11 @@ void Ctx::begin(int cls, hipEvent_t& a) {
   PV_HIP(hipEventRecord(a, stream));
 }
 
-void Ctx::end(int cls, hipEvent_t a, double flops, double bytes) {
+void Ctx::end(int cls, hipEvent_t a, double flops, double bytes, int weight) {
   if (!a) return;
   hipEvent_t b = event();
   PV_HIP(hipEventRecord(b, stream));
-  pending.push_back({cls, a, b, flops, bytes});
+  pending.push_back({cls, a, b, flops, bytes, weight});
 }
 
 void Ctx::fork() {
@@ -162,10 +162,10 @@ void Ctx::sync() {
   for (auto& p : pending) {
     float ms = 0.f;
     PV_HIP(hipEventElapsedTime(&ms, p.a, p.b));
-    t_ms[p.cls] += ms;
-    t_flops[p.cls] += p.flops;
-    t_bytes[p.cls] += p.bytes;
-    t_calls[p.cls] += 1;
+    t_ms[p.cls] += double(ms) * p.weight;
+    t_flops[p.cls] += p.flops * p.weight;
+    t_bytes[p.cls] += p.bytes * p.weight;
+    t_calls[p.cls] += p.weight;
     event_pool.push_back(p.a);
     event_pool.push_back(p.b);
   }
@@ -413,6 +413,12 @@ constexpr double kZeroTolPar = 1e-6;
 constexpr double kVecCut = 1e-12;  // tridiagonal solver: no eigenvector below this
 
 
+// Step-per-launch reduction: workgroups per launch aimed at (two per compute unit for the
+// largest kernel instance) and the most per problem.
+constexpr int kTriStepWorkgroups = 512;
+constexpr int kTriStepMaxG = 64;
+constexpr int kTriStepTimeEvery = 8;
+
 // Matrices above this size go to the tridiagonal solver when the job allows it.
 constexpr int kTridiagMin = 40;
 // Algorithmic flops of a symmetric eigendecomposition with eigenvectors, counted as the
@@ -431,6 +437,9 @@ struct EigPlan {
 
 }  // namespace
 
+static void tri_panels(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri, double ftri,
+                       double btri);
+
 // Tridiagonal solver, first half, for the problems `tri` (host copies of the descriptors)
 // whose device copy is `d`: reduction (preparation, panels with trailing GEMM updates,
 // finish) and the eigenvalues.  ftri/btri: algorithmic flops and bytes of the panels.
@@ -442,7 +451,54 @@ void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int n
   c.begin(T_COPY, a);
   launch_tri_prepare(d, np, ntri, c.stream);
   c.end(T_COPY, a, 0, bprep);
-  // blocked reduction: panel kernel, then the trailing update of every problem as a GEMM
+  if (np <= c.tri_step_max) {
+    // one step per launch on several workgroups per problem.  The problems go in order of
+    // decreasing size, so those still reducing at step k are a prefix of the list; each
+    // launch covers only them and spreads the workgroup budget over them (the instances
+    // for n <= 512 hold fewer registers: twice the workgroups fit).
+    const int target = ntri <= 512 ? 2 * kTriStepWorkgroups : kTriStepWorkgroups;
+    std::vector<EigDesc> srt(tri);
+    std::stable_sort(srt.begin(), srt.end(), [](const EigDesc& x, const EigDesc& y) { return x.n > y.n; });
+    // (a single problem uses the caller's descriptor: nothing is allocated then)
+    const EigDesc* ds = np == 1 ? d : c.upload(srt);
+    const int last = std::max(ntri - 2, 0);
+    int act = np;
+    for (int k = 0; k <= last; ++k) {
+      while (act > 0 && std::max(srt[act - 1].n - 2, 0) < k) --act;
+      if (act == 0) break;
+      const int G = std::clamp(target / act, 1, kTriStepMaxG);
+      // every kTriStepTimeEvery-th launch is timed and stands for the launches up to the
+      // next timed one: events around each of these short launches would lengthen the run
+      if (k % kTriStepTimeEvery != 0) {
+        launch_tri_step(ds, act, ntri, k, G, c.stream);
+        continue;
+      }
+      // algorithmic work of step k: the trailing block of every problem read and written
+      // once (read only at k = 0), 6 flops per element (rank-2 update and product)
+      double fl = 0, by = 0;
+      for (int i = 0; i < act; ++i) {
+        const double m = std::max(srt[i].n - k - 1, 0);
+        fl += 6.0 * m * m;
+        by += (k > 0 ? 16.0 : 8.0) * m * m;
+      }
+      c.begin(T_TRI, a);
+      launch_tri_step(ds, act, ntri, k, G, c.stream);
+      c.end(T_TRI, a, fl, by, std::min(kTriStepTimeEvery, last + 1 - k));
+    }
+  } else {
+    tri_panels(c, tri, d, ntri, ftri, btri);
+  }
+  c.begin(T_TRIVAL, a);
+  launch_eig_tridiag(d, np, ntri, 2, c.stream);
+  c.end(T_TRIVAL, a, 0, 0);
+}
+
+// Blocked reduction: panel kernel (one workgroup per problem), then the trailing update of
+// every problem as a GEMM, then the last 2 x 2 blocks.
+static void tri_panels(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int ntri, double ftri,
+                       double btri) {
+  const int np = int(tri.size());
+  hipEvent_t a;
   const double nsteps = std::max(ntri - 2, 1);
   for (int k0 = 0; k0 + 2 < ntri; k0 += kTriPanel) {
     const double share = std::min<double>(kTriPanel, ntri - 2 - k0) / nsteps;
@@ -466,9 +522,6 @@ void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int n
   c.begin(T_COPY, a);
   launch_tri_finish(d, np, c.stream);
   c.end(T_COPY, a, 0, 0);
-  c.begin(T_TRIVAL, a);
-  launch_eig_tridiag(d, np, ntri, 2, c.stream);
-  c.end(T_TRIVAL, a, 0, 0);
 }
 
 // Second half: eigenvectors by inverse iteration and the back-transformation, for the

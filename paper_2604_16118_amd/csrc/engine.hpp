@@ -160,7 +160,8 @@ struct Ctx {
   std::map<int, std::unique_ptr<Mps>> mps;
   int next_handle = 1;
   // timers
-  struct Pending { int cls; hipEvent_t a, b; double flops, bytes; };
+  // weight: launches the timed one stands for (sampled timing of short repeated launches)
+  struct Pending { int cls; hipEvent_t a, b; double flops, bytes; int weight; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   double t_ms[T_COUNT] = {0}, t_flops[T_COUNT] = {0}, t_bytes[T_COUNT] = {0};
@@ -171,6 +172,9 @@ struct Ctx {
   // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
   //    intermediate-rank H application.
   int trunc_mode = 0;
+  // eigensolver batches of at most this many tridiagonal problems are reduced one step per
+  // launch on several workgroups per problem; larger ones by one-workgroup panels
+  int tri_step_max = PV_TRIDIAG_STEPS_DEFAULT;
 
   // side stream for an independent chain of launches: fork() orders it behind the main
   // stream's work so far and redirects `stream` to it; unfork() restores the main stream;
@@ -185,7 +189,7 @@ struct Ctx {
   void sync();
   hipEvent_t event();
   void begin(int cls, hipEvent_t& a);
-  void end(int cls, hipEvent_t a, double flops, double bytes);
+  void end(int cls, hipEvent_t a, double flops, double bytes, int weight = 1);
   template <class T>
   T* upload(const std::vector<T>& v);  // staged async copy into a pool buffer kept in `scratch`
   std::vector<Buf> scratch;            // freed at sync

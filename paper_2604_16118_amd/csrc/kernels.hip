@@ -1224,6 +1224,200 @@ __global__ __launch_bounds__(kPanelThreads) void tridiag_panel_kernel(const EigD
   }
 }
 
+// 1b'. The same reduction one step per launch, G workgroups per problem (for batches of
+//     few problems, where one workgroup per matrix leaves most compute units idle).  The
+//     full symmetric working copy is updated every step; workgroup g of a problem owns the
+//     columns j = g (mod G), so a column stays with one workgroup (and one XCD's L2) for
+//     the whole reduction.  Launch k (k = 0 .. n - 2):
+//       - every workgroup reads p_{k-1} (= beta_{k-1} A^(k-1) v_{k-1}) and v_{k-1} and
+//         forms q_{k-1} = p_{k-1} - (beta_{k-1}/2)(p_{k-1}^T v_{k-1}) v_{k-1};
+//       - it forms column k of A^(k) = A^(k-1) - v_{k-1} q_{k-1}^T - q_{k-1} v_{k-1}^T from
+//         the stored column k (which holds A^(k-1)) and from it the reflector v_k, beta_k
+//         (the same arithmetic in every workgroup, so every copy agrees bit for bit);
+//       - on its own columns j >= k + 1 (rows >= k + 1) it applies step k - 1's update,
+//         stores the result and takes p_k[j] = beta_k (column j)^T v_k, which by symmetry is
+//         entry j of beta_k A^(k) v_k: no reduction across workgroups is needed, the launch
+//         boundary is the only synchronisation.
+//     Workgroup 0 records d_k, e_k, beta_k and v_k, and moves v_{k-1} below the diagonal of
+//     column k - 1 (which no workgroup reads in launch k).  Launch n - 2 applies the last
+//     update to the final 2 x 2 block and records it.  Both products of the rank-2 update
+//     are rounded before they are added, so the updated copy stays exactly symmetric.
+//     p and v alternate between two n-vectors by the parity of k, after the working copy.
+constexpr int kStepThreads = 256;
+static_assert(kStepThreads % 64 == 0 && kEigMax % kStepThreads == 0, "step kernel layout");
+
+__device__ inline double sym_rank2(double vi, double qj, double qi, double vj) {
+#pragma clang fp contract(off)
+  return vi * qj + qi * vj;
+}
+
+// rows r0 .. n - 1 of a column, lane-strided 64-row chunks (zero past the end)
+template <int CH>
+__device__ inline void step_load_col(gcdouble* col, int r0, int n, int lane, double (&a)[CH]) {
+#pragma unroll
+  for (int u = 0; u < CH; ++u) {
+    const int i = r0 + 64 * u + lane;
+    a[u] = i < n ? col[i] : 0.0;
+  }
+}
+
+// Each launch is latency bound (a few hundred rows per problem and step), so every load
+// that does not depend on the step's own results is issued at the start: the first own
+// column of each wavefront, and p_{k-1}, v_{k-1} and column k (at most kStepVec rows per
+// thread); the next own column is loaded while the current one is processed.  CH 64-row
+// chunks cover a column (n <= 64 CH), VEC = CH / 4 rows per thread the column-k pass; the
+// smaller instances hold fewer registers and so keep more wavefronts per compute unit.
+template <int CH>
+__global__ __launch_bounds__(kStepThreads) void tridiag_step_kernel(const EigDesc* __restrict__ descs, int k,
+                                                                    int G) {
+  constexpr int kStepChunks = CH;
+  constexpr int kStepVec = CH * 64 / kStepThreads;
+  static_assert(kStepVec >= 1 && kStepVec * kStepThreads == 64 * CH, "step kernel instance");
+  __shared__ double red[kStepThreads / 64];
+  __shared__ double vprev[64 * CH], qprev[64 * CH], vcur[64 * CH];
+  const int prob = blockIdx.x / G, g = blockIdx.x - prob * G;
+  const EigDesc D = descs[prob];
+  const int n = D.n;
+  if (n <= 0 || n > 64 * CH || k > max(n - 2, 0)) return;
+  gdouble* A = gbl(D.work);
+  if (*tri_diag_flag(A, n) != 0.0) return;
+  const int tid = threadIdx.x, bs = kStepThreads;
+  const int lane = tid & 63, wave = tid >> 6, nw = bs >> 6;
+  const int64_t lda = n;
+  gdouble* tail = tri_tail(A, n);
+  gdouble* betas = tail;
+  gdouble* dd = tail + n;
+  gdouble* ee = tail + 2 * n;
+  gdouble* pbuf = A + (int64_t)n * n;
+  gdouble* vbuf = pbuf + 2 * lda;
+  if (n == 1) {
+    if (g == 0 && tid == 0) {
+      dd[0] = A[0];
+      ee[0] = 0.0;
+      betas[0] = 0.0;
+    }
+    return;
+  }
+  const bool upd = k > 0;
+  // first own column of this wavefront (columns j = g mod G, j >= k + 1)
+  int j = k + 1 + ((g - (k + 1)) % G + G) % G + wave * G;
+  double cur[kStepChunks];
+  if (j < n) step_load_col(A + (int64_t)j * lda, k + 1, n, lane, cur);
+  gcdouble* pp = pbuf + (int64_t)((k + 1) & 1) * lda;  // step k - 1's vectors
+  gcdouble* vp = vbuf + (int64_t)((k + 1) & 1) * lda;
+  double pv[kStepVec], vv[kStepVec], ck[kStepVec];
+#pragma unroll
+  for (int u = 0; u < kStepVec; ++u) {
+    const int i = k + tid + u * bs;
+    const bool in = i < n;
+    pv[u] = upd && in ? pp[i] : 0.0;
+    vv[u] = upd && in ? vp[i] : 0.0;
+    ck[u] = in ? A[i + (int64_t)k * lda] : 0.0;
+  }
+  const double bprev = upd ? betas[k - 1] : 0.0;
+  // q_{k-1} = p_{k-1} - (beta_{k-1}/2)(p_{k-1}^T v_{k-1}) v_{k-1}  (p carries beta)
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < kStepVec; ++u) part += pv[u] * vv[u];
+  const double K = 0.5 * bprev * block_sum(part, red, tid, bs);
+  double qq[kStepVec];
+#pragma unroll
+  for (int u = 0; u < kStepVec; ++u) {
+    const int i = k + tid + u * bs;
+    qq[u] = pv[u] - K * vv[u];
+    if (i < n) {
+      vprev[i] = vv[u];
+      qprev[i] = qq[u];
+    }
+  }
+  __syncthreads();
+  // v_{k-1} goes below the diagonal of column k - 1 for the back-transformation
+  if (g == 0 && bprev != 0.0) {
+#pragma unroll
+    for (int u = 0; u < kStepVec; ++u) {
+      const int i = k + tid + u * bs;
+      if (i < n) A[i + (int64_t)(k - 1) * lda] = vv[u];
+    }
+  }
+  // column k of A^(k), rows k .. n - 1
+  const double qk = qprev[k], vk = vprev[k];
+  part = 0.0;
+#pragma unroll
+  for (int u = 0; u < kStepVec; ++u) {
+    const int i = k + tid + u * bs;
+    if (upd) ck[u] -= sym_rank2(vv[u], qk, qq[u], vk);
+    if (i < n) vcur[i] = ck[u];
+    if (i >= k + 2 && i < n) part += ck[u] * ck[u];
+  }
+  const double sig2 = block_sum(part, red, tid, bs);  // also publishes vcur
+  if (k == n - 2) {  // the final 2 x 2 block
+    if (g == 0 && tid == 0) {
+      double a = A[(n - 1) + (int64_t)(n - 1) * lda];
+      if (upd) a -= sym_rank2(vprev[n - 1], qprev[n - 1], qprev[n - 1], vprev[n - 1]);
+      dd[n - 2] = vcur[n - 2];
+      ee[n - 2] = vcur[n - 1];
+      betas[n - 2] = 0.0;
+      dd[n - 1] = a;
+      ee[n - 1] = 0.0;
+      betas[n - 1] = 0.0;
+    }
+    return;
+  }
+  // reflector H_k = I - beta v v^T with v_{k+1} = 1 mapping column k below the diagonal
+  // onto alpha e_{k+1}
+  const double x0 = vcur[k + 1], akk = vcur[k];
+  double beta = 0.0, alpha = x0, inv = 0.0;
+  if (sig2 != 0.0) {
+    const double nrm = sqrt(x0 * x0 + sig2);
+    alpha = x0 > 0.0 ? -nrm : nrm;
+    const double v0 = x0 - alpha;
+    beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
+    inv = 1.0 / v0;
+  }
+  __syncthreads();  // every thread has read x0 and akk before vcur becomes v
+  gdouble* vout = vbuf + (int64_t)(k & 1) * lda;
+  gdouble* pout = pbuf + (int64_t)(k & 1) * lda;
+#pragma unroll
+  for (int u = 0; u < kStepVec; ++u) {
+    const int i = k + tid + u * bs;
+    if (i >= n) continue;
+    const double v = (beta == 0.0 || i == k) ? 0.0 : (i == k + 1 ? 1.0 : ck[u] * inv);
+    vcur[i] = v;
+    if (g == 0) vout[i] = v;
+  }
+  if (g == 0 && tid == 0) {
+    ee[k] = alpha;
+    dd[k] = akk;
+    betas[k] = beta;
+  }
+  __syncthreads();
+  // own columns j >= k + 1: step k - 1's update, then p_k[j] = beta_k (column j)^T v_k
+  while (j < n) {
+    const int jn = j + nw * G;
+    double nxt[kStepChunks];
+    if (jn < n) step_load_col(A + (int64_t)jn * lda, k + 1, n, lane, nxt);
+    gdouble* col = A + (int64_t)j * lda;
+    const double qj = qprev[j], vj = vprev[j];
+    double dot = 0.0;
+#pragma unroll
+    for (int u = 0; u < kStepChunks; ++u) {
+      const int i = k + 1 + 64 * u + lane;
+      if (i >= n) continue;
+      double a = cur[u];
+      if (upd) {
+        a -= sym_rank2(vprev[i], qj, qprev[i], vj);
+        col[i] = a;
+      }
+      dot += a * vcur[i];
+    }
+    dot = wave_sum_d(dot);
+    if (lane == 0) pout[j] = beta * dot;
+#pragma unroll
+    for (int u = 0; u < kStepChunks; ++u) cur[u] = nxt[u];
+    j = jn;
+  }
+}
+
 // 1c. Last 2 x 2 block (or the single entry) of T, after the last trailing update.
 __global__ void tridiag_finish_kernel(const EigDesc* __restrict__ descs, int nprob) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1711,6 +1905,19 @@ void launch_tri_panel(const EigDesc* d, int nprob, int nmax, int k0, hipStream_t
   const size_t shm = tridiag_panel_lds(nmax, threads);
   lds_opt_in((const void*)tridiag_panel_kernel, shm, &granted);
   hipLaunchKernelGGL(tridiag_panel_kernel, dim3(nprob), dim3(threads), shm, s, d, k0);
+  PV_LAUNCH_CHECK();
+}
+
+void launch_tri_step(const EigDesc* d, int nprob, int nmax, int k, int G, hipStream_t s) {
+  if (nprob <= 0 || k > std::max(nmax - 2, 0)) return;
+  if (nmax > kEigMax) throw std::runtime_error("eig: matrix larger than supported");
+  if (G < 1 || int64_t(nprob) * G > (int64_t(1) << 30)) throw std::runtime_error("eig: bad workgroup count");
+  if (nmax <= 256)
+    hipLaunchKernelGGL(tridiag_step_kernel<4>, dim3(nprob * G), dim3(kStepThreads), 0, s, d, k, G);
+  else if (nmax <= 512)
+    hipLaunchKernelGGL(tridiag_step_kernel<8>, dim3(nprob * G), dim3(kStepThreads), 0, s, d, k, G);
+  else
+    hipLaunchKernelGGL(tridiag_step_kernel<16>, dim3(nprob * G), dim3(kStepThreads), 0, s, d, k, G);
   PV_LAUNCH_CHECK();
 }
 

@@ -115,6 +115,10 @@ constexpr int kTriPanel = 32;
 void launch_tri_prepare(const EigDesc* d_desc, int nprob, int nmax, hipStream_t s);
 void launch_tri_panel(const EigDesc* d_desc, int nprob, int nmax, int k0, hipStream_t s);
 void launch_tri_finish(const EigDesc* d_desc, int nprob, hipStream_t s);
+// The reduction one step per launch instead of the panels: after launch_tri_prepare, one
+// launch_tri_step for every k = 0 .. max(nmax - 2, 0), with G workgroups per problem; it
+// leaves the same state as the panels and launch_tri_finish (no trailing GEMMs).
+void launch_tri_step(const EigDesc* d_desc, int nprob, int nmax, int k, int G, hipStream_t s);
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
 inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 2; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in

@@ -21,7 +21,7 @@ STATUS = {0: "PV_OK", -1: "PV_EINVAL", -2: "PV_ENOMEM", -3: "PV_EDEVICE", -4: "P
 EXPORTS = [
     "pv_last_error", "pv_create", "pv_destroy", "pv_set_hamiltonian", "pv_precond_info",
     "pv_mps_create", "pv_mps_determinant", "pv_mps_layout", "pv_mps_download", "pv_mps_free",
-    "pv_set_truncation", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_subspace_joint", "pv_run_zform", "pv_run_batch",
+    "pv_set_truncation", "pv_set_tridiag_steps", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_subspace_joint", "pv_run_zform", "pv_run_batch",
     "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
@@ -65,6 +65,7 @@ class OuterIter(C.Structure):
 
 
 SUBSPACE_MAX_D = 8
+TRIDIAG_STEPS_DEFAULT = 1 << 30  # PV_TRIDIAG_STEPS_DEFAULT
 
 
 class SubspaceIter(C.Structure):
@@ -105,6 +106,7 @@ def lib():
         L.pv_mps_download.argtypes = [C.c_void_p, C.c_int, dp, C.c_size_t]
         L.pv_mps_free.argtypes = [C.c_void_p, C.c_int]
         L.pv_set_truncation.argtypes = [C.c_void_p, C.c_int]
+        L.pv_set_tridiag_steps.argtypes = [C.c_void_p, C.c_int]
         L.pv_dot.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.pv_expect_h.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         L.pv_lincomb.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_int, ip]
@@ -276,6 +278,11 @@ class Context:
 
     def set_truncation(self, mode):
         _check(lib().pv_set_truncation(self._p, int(mode)))
+
+    def set_tridiag_steps(self, max_problems):
+        """Eigensolver batches of at most max_problems matrices use the step-per-launch
+        reduction, larger ones the panel kernel (pv_set_tridiag_steps)."""
+        _check(lib().pv_set_tridiag_steps(self._p, int(max_problems)))
 
     def dot(self, a, b):
         out = C.c_double()

@@ -144,6 +144,27 @@ def test_sym_eig_at_gram_sizes_of_the_workload(ctx, kind, n):
     _check(A, w, V, 1)
 
 
+@pytest.mark.parametrize("kind", ["rand", "gram_graded", "cluster", "degenerate", "zero_rows"])
+@pytest.mark.parametrize("n", [2, 3, 41, 130, 538])
+def test_sym_eig_step_and_panel_reductions_agree(ctx, kind, n):
+    """The two reductions to tridiagonal form (one Householder step per launch on several
+    workgroups, and panels of 32 steps on one workgroup with GEMM trailing updates) each
+    pass the checks, and their eigenvalues agree to rounding."""
+    rng = np.random.default_rng(9000 + n + sorted(CASES).index(kind))
+    A = CASES[kind](n, rng)
+    A = (A + A.T) / 2
+    out = {}
+    try:
+        for name, limit in (("steps", 1 << 30), ("panels", 0)):
+            ctx.set_tridiag_steps(limit)
+            out[name] = ctx.sym_eig(A, 1)
+            _check(A, *out[name], 1)
+    finally:
+        ctx.set_tridiag_steps(native.TRIDIAG_STEPS_DEFAULT)
+    an = max(np.abs(np.linalg.eigvalsh(A)).max(), 1e-300)
+    assert np.abs(out["steps"][0] - out["panels"][0]).max() <= 1e-13 * an * max(1.0, n / 100)
+
+
 @pytest.mark.parametrize("method", [0, 1])
 def test_sym_eig_zero_and_diagonal(ctx, method):
     n = 50

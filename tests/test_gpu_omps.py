@@ -80,8 +80,14 @@ def _compare_runs(ctx, kind, L, N, seed, cap, m_zip, iters, mode, tol):
     return hist_g
 
 
-def test_run_with_binding_m_zip_and_cap_matches_oracle_L12(ctx):
-    hist = _compare_runs(ctx, "decayed", 12, 6, 0, 24, 16, 8, "sequential", 1e-10)
+@pytest.mark.parametrize("reduction", ["steps", "panels"])
+def test_run_with_binding_m_zip_and_cap_matches_oracle_L12(ctx, reduction):
+    # both reductions to tridiagonal form inside the Gram eigensolvers
+    ctx.set_tridiag_steps(native.TRIDIAG_STEPS_DEFAULT if reduction == "steps" else 0)
+    try:
+        hist = _compare_runs(ctx, "decayed", 12, 6, 0, 24, 16, 8, "sequential", 1e-10)
+    finally:
+        ctx.set_tridiag_steps(native.TRIDIAG_STEPS_DEFAULT)
     assert all(r["zip_bound"] for r in hist) and all(r["cap_bound"] for r in hist[2:])
 
 
