@@ -33,7 +33,8 @@ PEAK = {  # MI355X published peaks
 # library timer class -> (HIP kernel, roofline bound)
 KERNELS = {
     "gemm_f64_mfma": ("gemm_kernel<0>", "mfma"),
-    "tridiag_reduce_f64": ("tridiag_panel_kernel", "hbm"),
+    "tridiag_reduce_f64": ("tridiag_step_kernel", "hbm"),
+    "tridiag_tail_f64": ("tridiag_tail_kernel", "alu"),
     "tridiag_update_gemm_f64": ("gemm_kernel<2>", "mfma"),
     "tridiag_vectors_f64": ("tridiag_vec_kernel", "alu"),
     "tridiag_back_f64": ("tridiag_back_kernel", "alu"),
@@ -54,8 +55,8 @@ TIMED_RANGE = "pinvit_timed"
 # and split-K reductions (about 25,000 launches in three L=48 iterations) are left out there
 # and timed in an instrumented pass of as many further steps, which gives the per-class
 # breakdown.
-LIVE_CLASSES = ("jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "cholesky_f64", "tridiag_vectors_f64",
-                "tridiag_back_f64", "tridiag_values_f64")
+LIVE_CLASSES = ("jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "tridiag_tail_f64", "cholesky_f64",
+                "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64")
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_16118_amd", "csrc", "kernels.hip")
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 

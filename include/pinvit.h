@@ -391,13 +391,17 @@ pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_
 /* Kernel timing of the last pv_run / op, accumulated with HIP events per kernel class:
  * out[i] = milliseconds, flops[i] = algorithmic flops (GEMM: sum 2mnk; eigenproblems:
  * Jacobi 10/3 n^3 each; tridiagonal solver: panel kernels 2/3 n^3 flops and 4/3 n^3
- * bytes (the symmetric products), trailing updates as GEMMs, back-transformation 2 n^2 k
- * for k wanted vectors; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic
- * bytes, for i < n classes (thirteen classes: grouped GEMM float64, Jacobi eigensolver,
- * MPO W-step, copy/scale, split-K reduction, tridiagonal reduction panels, Cholesky
- * panels, grouped GEMM float32, eigenvectors of the tridiagonal matrix,
+ * bytes (the symmetric products), trailing updates as GEMMs, step launches 6 m^2 flops
+ * and 16 m^2 bytes for a trailing block of order m (the block read and written), the
+ * LDS tail 4/3 m^3 flops and 8 m^2 bytes, back-transformation 2 n^2 k for k wanted
+ * vectors; Cholesky panels: n^3/3 over all panels), bytes[i] = algorithmic bytes, for
+ * i < n classes (fourteen classes: grouped GEMM float64, Jacobi eigensolver, MPO W-step,
+ * copy/scale, split-K reduction, tridiagonal reduction (panels or step launches),
+ * Cholesky panels, grouped GEMM float32, eigenvectors of the tridiagonal matrix,
  * back-transformation, eigenvalues of the tridiagonal matrix, trailing updates of the
- * tridiagonal reduction, grouped GEMM with bfloat16 operands);
+ * tridiagonal reduction, grouped GEMM with bfloat16 operands, the LDS tail of the step
+ * reduction); the step launches are timed one in eight, each standing for the launches
+ * up to the next timed one;
  * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
 const char* pv_timer_name(int i);

@@ -1703,7 +1703,7 @@ pv_status pv_run_subspace_joint(pv_ctx* ctx, const pv_params* prm, int D, int st
 static const char* kTimerNames[T_COUNT] = {"gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "copy_scale", "reduce",
                                             "tridiag_reduce_f64", "cholesky_f64", "gemm_f32_mfma",
                                             "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64",
-                                            "tridiag_update_gemm_f64", "gemm_bf16_mfma"};
+                                            "tridiag_update_gemm_f64", "gemm_bf16_mfma", "tridiag_tail_f64"};
 
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls) {
   return guard([&] {

@@ -187,6 +187,7 @@ T* Ctx::upload(const std::vector<T>& v) {
   return out;
 }
 template GemmDesc* Ctx::upload(const std::vector<GemmDesc>&);
+template int* Ctx::upload(const std::vector<int>&);
 
 static Buf scratch_buf(Ctx& c, size_t n) {
   return Buf(c.pool, n);
@@ -325,9 +326,16 @@ struct GemmBatch {
         launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream);
         c.end(tc, a, flops, bytes);
       } else {
+        std::vector<int> tmap(static_cast<size_t>(tiles));
+        for (size_t i = 0; i < list.size(); ++i) {
+          const GemmDesc& g = list[i];
+          const int64_t nt = int64_t((g.M + kGemmBM - 1) / kGemmBM) * ((g.N + kGemmBN - 1) / kGemmBN);
+          std::fill(tmap.begin() + g.tile0, tmap.begin() + g.tile0 + nt, int(i));
+        }
         GemmDesc* dd = c.upload(list);
+        int* dm = c.upload(tmap);
         hipEvent_t a; c.begin(tc, a);
-        launch_gemm(dd, int(list.size()), int(tiles), prec, c.stream);
+        launch_gemm(dd, dm, int(tiles), prec, c.stream);
         c.end(tc, a, flops, bytes);
       }
     }
@@ -461,10 +469,13 @@ void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int n
     std::stable_sort(srt.begin(), srt.end(), [](const EigDesc& x, const EigDesc& y) { return x.n > y.n; });
     // (a single problem uses the caller's descriptor: nothing is allocated then)
     const EigDesc* ds = np == 1 ? d : c.upload(srt);
-    const int last = std::max(ntri - 2, 0);
+    // a problem takes step launches for k < n - tri_tail_rows(); the tail kernel then
+    // finishes every problem at once
+    const int T = tri_tail_rows();
+    const int last = std::max(ntri - T - 1, -1);
     int act = np;
     for (int k = 0; k <= last; ++k) {
-      while (act > 0 && std::max(srt[act - 1].n - 2, 0) < k) --act;
+      while (act > 0 && srt[act - 1].n - T <= k) --act;
       if (act == 0) break;
       const int G = std::clamp(target / act, 1, kTriStepMaxG);
       // every kTriStepTimeEvery-th launch is timed and stands for the launches up to the
@@ -484,6 +495,19 @@ void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int n
       c.begin(T_TRI, a);
       launch_tri_step(ds, act, ntri, k, G, c.stream);
       c.end(T_TRI, a, fl, by, std::min(kTriStepTimeEvery, last + 1 - k));
+    }
+    {
+      // the tail: per problem about 4/3 m^3 flops over its m = min(n, T) trailing rows,
+      // the block read once and the reflectors written
+      double fl = 0, by = 0;
+      for (const EigDesc& e : tri) {
+        const double m = std::min(e.n, T);
+        fl += 4.0 / 3.0 * m * m * m;
+        by += 8.0 * m * m;
+      }
+      c.begin(T_TRITAIL, a);
+      launch_tri_tail(d, np, c.stream);
+      c.end(T_TRITAIL, a, fl, by);
     }
   } else {
     tri_panels(c, tri, d, ntri, ftri, btri);

@@ -123,7 +123,7 @@ struct DevMpo {
   int64_t nnz = 0;
 };
 
-enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_TRIVAL, T_TRIGEMM, T_GEMMBF16, T_COUNT };
+enum TimerClass { T_GEMM = 0, T_EIG, T_WSTEP, T_COPY, T_REDUCE, T_TRI, T_CHOL, T_GEMM32, T_TRIVEC, T_TRIBACK, T_TRIVAL, T_TRIGEMM, T_GEMMBF16, T_TRITAIL, T_COUNT };
 
 struct Ctx {
   int device = 0;

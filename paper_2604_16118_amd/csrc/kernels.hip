@@ -333,15 +333,14 @@ __device__ __forceinline__ void gemm_any(const GemmDesc& g, int tile) {
   else gemm_tile<PREC, BM, BN>(g, tile);
 }
 
+// tmap[tile] is the problem of each tile: one load instead of a search over the
+// descriptors (batches reach thousands of problems of a few tiles each, where a chain of
+// dependent descriptor loads costs as much as the tile's own K loop)
 template <int PREC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, int nprob, int ntiles) {
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, const int* __restrict__ tmap,
+                                                   int ntiles) {
   const int tile = gemm_tile_of_block(ntiles);
-  int lo = 0, hi = nprob - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
-  }
-  const GemmDesc g = descs[lo];
+  const GemmDesc g = descs[tmap[tile]];
   gemm_any<PREC, BM, BN>(g, tile);
 }
 
@@ -372,17 +371,17 @@ void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int pr
   PV_LAUNCH_CHECK();
 }
 
-void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s) {
+void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s) {
   if (total_tiles <= 0) return;
   const dim3 g(total_tiles), b(256);
   if (prec == 0)
-    hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
   else if (prec == 1)
-    hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
   else if (prec == 3)
-    hipLaunchKernelGGL((gemm_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
   else
-    hipLaunchKernelGGL((gemm_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, nprob, total_tiles);
+    hipLaunchKernelGGL((gemm_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
   PV_LAUNCH_CHECK();
 }
 
@@ -1418,6 +1417,161 @@ __global__ __launch_bounds__(kStepThreads) void tridiag_step_kernel(const EigDes
   }
 }
 
+// 1b''. The last steps of the step-per-launch reduction, one workgroup per problem with the
+//      trailing block (at most kTailMax rows) in LDS, where a step costs four workgroup
+//      barriers instead of a launch.  Entered at k0 = max(n - kTailMax, 0): the stored
+//      columns >= k0 hold A^(k0-1), and for k0 > 0 step k0 - 1's p and v wait in the
+//      alternating vectors, as the step kernel leaves them.  Steps k0 .. n - 3 then run as
+//      in the step kernel (same reflector, same symmetric rank-2 form, but every update is
+//      applied at once), and the final 2 x 2 block is recorded.  Wave w owns the columns
+//      j = w (mod waves): it forms their partial products with v along the rows (summed
+//      over the waves through LDS, so no cross-lane reductions), updates them, and the owner
+//      of the next reflector's column leaves its squared norm for the next step.
+constexpr int kTailMax = 128;
+constexpr int kTailLd = kTailMax + 1;
+constexpr int kTailThreads = 1024;
+constexpr int kTailWaves = kTailThreads / 64;
+
+__global__ __launch_bounds__(kTailThreads) void tridiag_tail_kernel(const EigDesc* __restrict__ descs) {
+  // S[i + kTailLd j]: trailing block entry (i, j); then kTailWaves x kTailMax row partials
+  extern __shared__ double S[];
+  double* part = S + kTailLd * kTailMax;
+  __shared__ double vsh[kTailMax], psh[kTailMax], red[kTailWaves];
+  __shared__ double sh_sig2;
+  const EigDesc D = descs[blockIdx.x];
+  const int n = D.n;
+  if (n <= 0) return;
+  gdouble* A = gbl(D.work);
+  if (*tri_diag_flag(A, n) != 0.0) return;
+  const int tid = threadIdx.x, bs = kTailThreads;
+  const int lane = tid & 63, wave = tid >> 6, nw = kTailWaves;
+  const int64_t lda = n;
+  gdouble* tail = tri_tail(A, n);
+  gdouble* betas = tail;
+  gdouble* dd = tail + n;
+  gdouble* ee = tail + 2 * n;
+  if (n == 1) {
+    if (tid == 0) {
+      dd[0] = A[0];
+      ee[0] = 0.0;
+      betas[0] = 0.0;
+    }
+    return;
+  }
+  const int k0 = max(n - kTailMax, 0), m0 = n - k0;
+  // pending update of step k0 - 1: v in vsh, q = p - (beta/2)(p^T v) v in psh (local rows)
+  if (k0 > 0) {
+    gcdouble* pp = A + (int64_t)n * n + (int64_t)((k0 - 1) & 1) * lda;
+    gcdouble* vp = A + (int64_t)n * n + 2 * lda + (int64_t)((k0 - 1) & 1) * lda;
+    const double bprev = betas[k0 - 1];
+    double pv = 0.0;
+    for (int i = tid; i < m0; i += bs) {
+      const double v = vp[k0 + i], p = pp[k0 + i];
+      vsh[i] = v;
+      psh[i] = p;
+      pv += p * v;
+    }
+    const double K = 0.5 * bprev * block_sum(pv, red, tid, bs);
+    for (int i = tid; i < m0; i += bs) psh[i] -= K * vsh[i];
+    __syncthreads();
+    if (bprev != 0.0)
+      for (int i = tid; i < m0; i += bs) A[(k0 + i) + (int64_t)(k0 - 1) * lda] = vsh[i];
+  }
+  for (int j = wave; j < m0; j += nw) {
+    gcdouble* col = A + (int64_t)(k0 + j) * lda + k0;
+    const double qj = k0 > 0 ? psh[j] : 0.0, vj = k0 > 0 ? vsh[j] : 0.0;
+    for (int i = lane; i < m0; i += 64) {
+      double a = col[i];
+      if (k0 > 0) a -= sym_rank2(vsh[i], qj, psh[i], vj);
+      S[i + kTailLd * j] = a;
+    }
+  }
+  {
+    // squared norm of column 0 below its subdiagonal entry
+    double sq = 0.0;
+    __syncthreads();
+    for (int i = 2 + tid; i < m0; i += bs) sq += S[i] * S[i];
+    const double t = block_sum(sq, red, tid, bs);
+    if (tid == 0) sh_sig2 = t;
+    __syncthreads();
+  }
+  for (int c = 0; k0 + c + 2 < n; ++c) {
+    const int k = k0 + c;
+    // reflector of column c below the diagonal
+    const double sig2 = sh_sig2;
+    const double x0 = S[c + 1 + kTailLd * c];
+    double beta = 0.0, alpha = x0, inv = 0.0;
+    if (sig2 != 0.0) {
+      const double nrm = sqrt(x0 * x0 + sig2);
+      alpha = x0 > 0.0 ? -nrm : nrm;
+      const double v0 = x0 - alpha;
+      beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
+      inv = 1.0 / v0;
+    }
+    if (tid == 0) {
+      ee[k] = alpha;
+      dd[k] = S[c + kTailLd * c];
+      betas[k] = beta;
+    }
+    for (int i = c + 1 + tid; i < m0; i += bs) {
+      const double v = beta == 0.0 ? 0.0 : (i == c + 1 ? 1.0 : S[i + kTailLd * c] * inv);
+      vsh[i] = v;
+      if (beta != 0.0) A[(k0 + i) + (int64_t)k * lda] = v;  // below the diagonal of column k
+    }
+    __syncthreads();
+    const int nxt = c + 1;  // the next reflector's column
+    if (beta != 0.0) {
+      // row partials of A22 v over each wavefront's columns, then p = beta A22 v
+      for (int i = c + 1 + lane; i < m0; i += 64) {
+        double acc = 0.0;
+        for (int j = c + 1 + ((wave - (c + 1)) % nw + nw) % nw; j < m0; j += nw) acc += S[i + kTailLd * j] * vsh[j];
+        part[wave * kTailMax + i] = acc;
+      }
+      __syncthreads();
+      for (int i = c + 1 + tid; i < m0; i += bs) {
+        double p = 0.0;
+#pragma unroll 4
+        for (int w = 0; w < nw; ++w) p += part[w * kTailMax + i];
+        psh[i] = beta * p;
+      }
+      __syncthreads();
+      // K = (beta/2) p^T v (every wavefront forms it), q = p - K v, rank-2 update
+      double pv = 0.0;
+      for (int i = c + 1 + lane; i < m0; i += 64) pv += psh[i] * vsh[i];
+      const double K = 0.5 * beta * wave_sum_d(pv);
+      for (int j = c + 1 + ((wave - (c + 1)) % nw + nw) % nw; j < m0; j += nw) {
+        const double qj = psh[j] - K * vsh[j], vj = vsh[j];
+        double sq = 0.0;
+        for (int i = c + 1 + lane; i < m0; i += 64) {
+          const double qi = psh[i] - K * vsh[i];
+          const double a = S[i + kTailLd * j] - sym_rank2(vsh[i], qj, qi, vj);
+          S[i + kTailLd * j] = a;
+          if (j == nxt && i >= nxt + 2) sq += a * a;
+        }
+        if (j == nxt) {
+          sq = wave_sum_d(sq);
+          if (lane == 0) sh_sig2 = sq;
+        }
+      }
+    } else if (wave == nxt % nw) {  // H_k = I: the block is unchanged
+      double sq = 0.0;
+      for (int i = nxt + 2 + lane; i < m0; i += 64) sq += S[i + kTailLd * nxt] * S[i + kTailLd * nxt];
+      sq = wave_sum_d(sq);
+      if (lane == 0) sh_sig2 = sq;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {  // the final 2 x 2 block
+    const int c = m0 - 2;
+    dd[n - 2] = S[c + kTailLd * c];
+    ee[n - 2] = S[c + 1 + kTailLd * c];
+    dd[n - 1] = S[c + 1 + kTailLd * (c + 1)];
+    ee[n - 1] = 0.0;
+    betas[n - 2] = 0.0;
+    betas[n - 1] = 0.0;
+  }
+}
+
 // 1c. Last 2 x 2 block (or the single entry) of T, after the last trailing update.
 __global__ void tridiag_finish_kernel(const EigDesc* __restrict__ descs, int nprob) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1874,16 +2028,11 @@ static std::mutex g_attr_mutex;
 static void lds_opt_in(const void* fn, size_t shm, size_t* granted) {
   if (shm <= 65536) return;
   std::lock_guard<std::mutex> lock(g_attr_mutex);
-  if (*granted == 0) {
-    int dev = 0, v = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
-    (void)hipGetLastError();
-    const size_t want = v > 1024 ? size_t(v) - 1024 : 0;
-    if (want > 0 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
-      *granted = want;
-    (void)hipGetLastError();
-  }
+  if (shm <= *granted) return;
+  // the request is exactly the dynamic size: the kernel's static LDS counts against the
+  // same per-workgroup limit, so asking for the device maximum can be refused
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)) == hipSuccess) *granted = shm;
+  (void)hipGetLastError();
   if (shm > *granted) throw std::runtime_error("eig: tridiagonal solver needs more LDS than the device grants");
 }
 
@@ -1920,6 +2069,17 @@ void launch_tri_step(const EigDesc* d, int nprob, int nmax, int k, int G, hipStr
     hipLaunchKernelGGL(tridiag_step_kernel<16>, dim3(nprob * G), dim3(kStepThreads), 0, s, d, k, G);
   PV_LAUNCH_CHECK();
 }
+
+void launch_tri_tail(const EigDesc* d, int nprob, hipStream_t s) {
+  if (nprob <= 0) return;
+  static size_t granted = 0;
+  const size_t shm = sizeof(double) * (kTailLd + kTailWaves) * kTailMax;
+  lds_opt_in((const void*)tridiag_tail_kernel, shm, &granted);
+  hipLaunchKernelGGL(tridiag_tail_kernel, dim3(nprob), dim3(kTailThreads), shm, s, d);
+  PV_LAUNCH_CHECK();
+}
+
+int tri_tail_rows() { return kTailMax; }
 
 void launch_tri_finish(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return;

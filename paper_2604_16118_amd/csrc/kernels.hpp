@@ -88,7 +88,8 @@ struct ScaleDesc {
 // prec 0: float64 MFMA; prec 1: operands rounded to float32, float32 MFMA accumulation;
 // prec 2: float64 MFMA, the instance used for the trailing updates of the tridiagonal
 // reduction; prec 3: operands rounded to bfloat16, float32 MFMA accumulation.
-void launch_gemm(const GemmDesc* d_desc, int nprob, int total_tiles, int prec, hipStream_t s);
+// d_tmap[t] = index of the descriptor that owns tile t (tiles numbered by tile0).
+void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s);
 // Batches of at most kGemmPack problems pass their descriptors in the kernel arguments.
 constexpr int kGemmPack = 16;
 struct GemmPack {
@@ -119,6 +120,11 @@ void launch_tri_finish(const EigDesc* d_desc, int nprob, hipStream_t s);
 // launch_tri_step for every k = 0 .. max(nmax - 2, 0), with G workgroups per problem; it
 // leaves the same state as the panels and launch_tri_finish (no trailing GEMMs).
 void launch_tri_step(const EigDesc* d_desc, int nprob, int nmax, int k, int G, hipStream_t s);
+// The remaining steps of every problem from k0 = max(n - tri_tail_rows(), 0) on, one
+// workgroup per problem with the trailing block in LDS; the step launches for a problem
+// stop at k0 - 1.  Leaves d, e, beta and the reflectors as the step launches would.
+void launch_tri_tail(const EigDesc* d_desc, int nprob, hipStream_t s);
+int tri_tail_rows();
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
 inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 2; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in

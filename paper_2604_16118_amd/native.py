@@ -547,7 +547,7 @@ class Context:
         return W
 
     def timers(self):
-        n = 13
+        n = 14
         ms, fl, by = np.zeros(n), np.zeros(n), np.zeros(n)
         calls = np.zeros(n, np.int32)
         _check(lib().pv_timers(self._p, n, _dp(ms), _dp(fl), _dp(by), _ip(calls)))
