@@ -261,6 +261,22 @@ struct GemmBatch {
     g.ta = ta; g.tb = tb; g.alpha = alpha; g.beta = beta;
     d.push_back(g);
   }
+  // C_s = alpha A_s op(B) + beta C_s for s = 0 .. nouter - 1, A_s = A + s a_outer (m1 x K,
+  // ld lda), C_s = C + s c_outer (m1 x N, ld ldc): one product whose rows are (r, s).  The
+  // bfloat16 kernel has no such rows: it gets one problem per s.
+  void add_rows2(const double* A, int lda, int64_t a_outer, const double* B, int ldb, int tb, double* C, int ldc,
+                 int64_t c_outer, int m1, int nouter, int N, int K, double alpha, double beta) {
+    if (m1 <= 0 || nouter <= 0 || N <= 0) return;
+    if (prec == 3 || nouter == 1 || int64_t(m1) * nouter > INT32_MAX / 2) {
+      for (int s = 0; s < nouter; ++s) add(A + s * a_outer, lda, 0, B, ldb, tb, C + s * c_outer, ldc, m1, N, K, alpha, beta);
+      return;
+    }
+    add(A, lda, 0, B, ldb, tb, C, ldc, m1 * nouter, N, K, alpha, beta);
+    GemmDesc& g = d.back();
+    g.m1 = m1;
+    g.a_outer = a_outer;
+    g.c_outer = c_outer;
+  }
   bool empty() const { return d.empty(); }
   void run(Ctx& c) {
     if (d.empty()) return;
@@ -280,7 +296,7 @@ struct GemmBatch {
       bytes += 8.0 * (double(g0.M) * g0.K + double(g0.K) * g0.N + double(g0.M) * g0.N * (g0.beta != 0 ? 2 : 1));
       const int tm = (g0.M + kGemmBM - 1) / kGemmBM, tn = (g0.N + kGemmBN - 1) / kGemmBN;
       int S = 1;
-      if (tm * tn < 128 && g0.K >= 1024) {
+      if (tm * tn < 128 && g0.K >= 1024 && g0.m1 == 0) {
         S = std::min((g0.K + 511) / 512, (256 + tm * tn - 1) / (tm * tn));
         S = std::max(S, 1);
       }
@@ -924,7 +940,8 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
     launch_wstep(dt, int(tasks.size()), de, c.stream);
     c.end(T_WSTEP, a, 0, bytes);
   }
-  // dense charge blocks of W_k: T2[a, b', c'] += sum_b T1[a, b, c'] W[b, b'], one GEMM per c'
+  // dense charge blocks of W_k: T2[a, b', c'] += sum_b T1[a, b, c'] W[b, b'], one product whose
+  // rows run over the pairs (a, c')
   if (!st.dense.empty()) {
     // several dense blocks may accumulate into one output block: the k-th contribution to
     // each output goes to launch k, so no launch has two problems writing the same output
@@ -946,9 +963,9 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
           gd.emplace_back();
           gd.back().prec = c.contraction_kernel();
         }
-        for (int cc = 0; cc < B.cols; ++cc)
-          gd[slot].add(base + ld * cc, B.rows, 0, D.W.p, D.w_in, 0, B.out + int64_t(B.rows) * B.wq_out * cc, B.rows,
-                       B.rows, B.wq_out, D.w_in, 1.0, 1.0);
+        // one product over all c': rows (a, c') of T1 and T2
+        gd[slot].add_rows2(base, B.rows, ld, D.W.p, D.w_in, 0, B.out, B.rows, int64_t(B.rows) * B.wq_out, B.rows,
+                           B.cols, B.wq_out, D.w_in, 1.0, 1.0);
         ++slot;
       }
     }

@@ -71,7 +71,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
   constexpr bool F64 = PREC != 1;
   typedef typename std::conditional<F64, double, float>::type T;
   constexpr int BK = kGemmBK;
-  constexpr int TM = BM / 32, TN = BN / 32;  // MFMA tiles per wave
+  constexpr int KS = BK / 4;                             // MFMA k-steps per K-tile
+  constexpr int TM = BM / 32, TN = BN / 32;              // MFMA tiles per wave
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread per K-tile
   // double-buffered K-tiles: the global loads of tile t+1 are held in registers while the
   // MFMAs of tile t run, then written to the other LDS buffer (one barrier per K-tile)
@@ -83,7 +84,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
   const int t = tile - g.tile0;
   const int row0 = (g.colmajor ? t % g.tiles_m : t / g.tiles_n) * BM;
   const int col0 = (g.colmajor ? t / g.tiles_m : t % g.tiles_n) * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the wavefront index is uniform: taken from the first lane it lives in a scalar
+  // register, so the sub-tile conditions below are scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
   // per-thread element coordinates inside a K-tile (fastest index along contiguous memory)
@@ -98,24 +102,49 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
     const int e = tid + 256 * r;
     if (!g.tb) { bk[r] = e % BK; bj[r] = e / BK; } else { bj[r] = e % BN; bk[r] = e / BN; }
   }
+  // out-of-range elements load from a clamped (valid) address and are replaced by zero
+  // when they are written to LDS, so the loads are straight-line code whose results are
+  // first needed at the end of the K-tile
+  // the row (of A) and column (of B) part of each thread's addresses is fixed for the tile
+  const int64_t sAi = g.ta ? g.lda : 1, sAk = g.ta ? 1 : g.lda;
+  const int64_t sBj = g.tb ? 1 : g.ldb, sBk = g.tb ? g.ldb : 1;
+  gcdouble* pa[LA];
+  gcdouble* pb[LB];
+  bool rowa[LA], colb[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int gi = row0 + ai[r];
+    rowa[r] = gi < g.M;
+    const int ci = min(gi, g.M - 1);
+    pa[r] = g.m1 > 0 ? gA + (ci % g.m1) + (int64_t)(ci / g.m1) * g.a_outer : gA + ci * sAi;
+  }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int gj = col0 + bj[r];
+    colb[r] = gj < g.N;
+    pb[r] = gB + min(gj, g.N - 1) * sBj;
+  }
   double ra[LA], rb[LB];
+  bool oka[LA], okb[LB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
-      const int gi = row0 + ai[r], gk = k0 + ak[r];
-      ra[r] = (gi < g.M && gk < g.kend) ? (g.ta ? gA[gk + (int64_t)gi * g.lda] : gA[gi + (int64_t)gk * g.lda]) : 0.0;
+      const int gk = k0 + ak[r];
+      oka[r] = rowa[r] && gk < g.kend;
+      ra[r] = pa[r][min(gk, g.kend - 1) * sAk];
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
-      const int gj = col0 + bj[r], gk = k0 + bk[r];
-      rb[r] = (gj < g.N && gk < g.kend) ? (g.tb ? gB[gj + (int64_t)gk * g.ldb] : gB[gk + (int64_t)gj * g.ldb]) : 0.0;
+      const int gk = k0 + bk[r];
+      okb[r] = colb[r] && gk < g.kend;
+      rb[r] = pb[r][min(gk, g.kend - 1) * sBk];
     }
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) As[buf][ak[r]][ai[r]] = T(ra[r]);
+    for (int r = 0; r < LA; ++r) As[buf][ak[r]][ai[r]] = oka[r] ? T(ra[r]) : T(0);
 #pragma unroll
-    for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = T(rb[r]);
+    for (int r = 0; r < LB; ++r) Bs[buf][bk[r]][bj[r]] = okb[r] ? T(rb[r]) : T(0);
   };
   typedef T T4 __attribute__((ext_vector_type(4)));
   T4 acc[TM][TN];
@@ -123,49 +152,73 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = T4{0, 0, 0, 0};
-  // 16 x 16 sub-tiles that lie wholly outside C (edge tiles of a problem) are skipped:
-  // the conditions are the same for the whole wavefront
+  // 16 x 16 sub-tiles that lie wholly outside C (edge tiles of a problem) are skipped;
+  // interior tiles run a loop without any condition around the MFMAs
   bool rv[TM], cv[TN];
+  bool full = true;
 #pragma unroll
-  for (int a = 0; a < TM; ++a) rv[a] = row0 + wr * (BM / 2) + a * 16 < g.M;
+  for (int a = 0; a < TM; ++a) { rv[a] = row0 + wr * (BM / 2) + a * 16 < g.M; full = full && rv[a]; }
 #pragma unroll
-  for (int b = 0; b < TN; ++b) cv[b] = col0 + wc * (BN / 2) + b * 16 < g.N;
-  int buf = 0;
+  for (int b = 0; b < TN; ++b) { cv[b] = col0 + wc * (BN / 2) + b * 16 < g.N; full = full && cv[b]; }
+  auto kloop = [&](auto all_valid) {
+    int buf = 0;
+    for (int k0 = g.kbeg; k0 < g.kend; k0 += BK) {
+      const bool more = k0 + BK < g.kend;
+      if (more) load(k0 + BK);
+      // fragments of the next k-step are read from LDS before the MFMAs of the current one
+      T af[2][TM], bf[2][TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) af[0][a] = As[buf][lk][wr * (BM / 2) + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bf[0][b] = Bs[buf][lk][wc * (BN / 2) + b * 16 + li];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int a = 0; a < TM; ++a) af[cur ^ 1][a] = As[buf][4 * (ks + 1) + lk][wr * (BM / 2) + a * 16 + li];
+#pragma unroll
+          for (int b = 0; b < TN; ++b) bf[cur ^ 1][b] = Bs[buf][4 * (ks + 1) + lk][wc * (BN / 2) + b * 16 + li];
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b) {
+            if constexpr (!decltype(all_valid)::value) {
+              if (!(rv[a] && cv[b])) continue;
+            }
+            if constexpr (F64)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][a], bf[cur][b], acc[a][b], 0, 0, 0);
+            else
+              acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][a], bf[cur][b], acc[a][b], 0, 0, 0);
+          }
+      }
+      if (more) stage(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  };
   if (g.kbeg < g.kend) {
     load(g.kbeg);
     stage(0);
   }
   __syncthreads();
-  for (int k0 = g.kbeg; k0 < g.kend; k0 += BK) {
-    const bool more = k0 + BK < g.kend;
-    if (more) load(k0 + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T af[TM], bf[TN];
-#pragma unroll
-      for (int a = 0; a < TM; ++a) af[a] = As[buf][kk + lk][wr * (BM / 2) + a * 16 + li];
-#pragma unroll
-      for (int b = 0; b < TN; ++b) bf[b] = Bs[buf][kk + lk][wc * (BN / 2) + b * 16 + li];
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          if (!(rv[a] && cv[b])) continue;
-          if constexpr (F64)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-          else
-            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bf[b], acc[a][b], 0, 0, 0);
-        }
-    }
-    if (more) stage(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
+  if (full) kloop(std::true_type{});
+  else kloop(std::false_type{});
   // result element r of lane l: row 4r + l/16 (float64 instruction), row 4 (l/16) + r
   // (float32 instruction), column l % 16 (measured on gfx950).  With beta != 0 all loads of C
   // are issued before any is used, so their latencies overlap.
   auto row_of = [&](int mi, int r) { return row0 + wr * (BM / 2) + mi * 16 + (F64 ? 4 * r + lk : 4 * lk + r); };
   auto col_of = [&](int nj) { return col0 + wc * (BN / 2) + nj * 16 + li; };
+  // offset of row i of C (two-level rows when m1 > 0)
+  int64_t crow[TM][4];
+#pragma unroll
+  for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ic = min(row_of(mi, r), g.M - 1);
+      crow[mi][r] = g.m1 > 0 ? (ic % g.m1) + (int64_t)(ic / g.m1) * g.c_outer : (int64_t)ic;
+    }
   double cold[TM][TN][4];
   if (g.beta != 0.0) {
 #pragma unroll
@@ -174,9 +227,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
       for (int nj = 0; nj < TN; ++nj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = row_of(mi, r), j = col_of(nj);
-          const int ic = min(i, g.M - 1), jc = min(j, g.N - 1);
-          cold[mi][nj][r] = gC[ic + (int64_t)jc * g.ldc];
+          const int jc = min(col_of(nj), g.N - 1);
+          cold[mi][nj][r] = gC[crow[mi][r] + (int64_t)jc * g.ldc];
         }
   }
 #pragma unroll
@@ -189,7 +241,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc& g, int tile) {
         if (i < g.M && j < g.N) {
           double v = g.alpha * double(acc[mi][nj][r]);
           if (g.beta != 0.0) v += g.beta * cold[mi][nj][r];
-          gC[i + (int64_t)j * g.ldc] = v;
+          gC[crow[mi][r] + (int64_t)j * g.ldc] = v;
         }
       }
 }
@@ -337,7 +389,7 @@ __device__ __forceinline__ void gemm_any(const GemmDesc& g, int tile) {
 // descriptors (batches reach thousands of problems of a few tiles each, where a chain of
 // dependent descriptor loads costs as much as the tile's own K loop)
 template <int PREC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs, const int* __restrict__ tmap,
+__global__ __launch_bounds__(256, 4) void gemm_kernel(const GemmDesc* __restrict__ descs, const int* __restrict__ tmap,
                                                    int ntiles) {
   const int tile = gemm_tile_of_block(ntiles);
   const GemmDesc g = descs[tmap[tile]];
@@ -347,7 +399,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 // The same with the descriptors in the kernel arguments (at most kGemmPack problems): no
 // upload has to precede the launch.
 template <int PREC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_packed_kernel(const GemmPack pack, int nprob, int ntiles) {
+__global__ __launch_bounds__(256, 4) void gemm_packed_kernel(const GemmPack pack, int nprob, int ntiles) {
   const int tile = gemm_tile_of_block(ntiles);
   int lo = 0;
   for (int p = 1; p < nprob; ++p)

@@ -21,6 +21,11 @@ struct GemmDesc {
   // 1 = row blocks fastest (tiles sharing a column block of B are neighbours); tiles_m =
   // number of row blocks
   int tiles_m, colmajor;
+  // m1 > 0: the rows of op(A) and C are pairs (r, s) with i = r + m1 s (ta = 0 only): row i
+  // of A starts at A + r + s * a_outer, row i of C at C + r + s * c_outer.  A batch of
+  // products that share B and differ by fixed strides in A and C runs as one product.
+  int m1;
+  int64_t a_outer, c_outer;
 };
 
 // Split-K reduction: C = alpha * sum_s P[s] + beta * C, P[s] is M x N with ld M.
