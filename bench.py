@@ -32,7 +32,7 @@ PEAK = {  # MI355X published peaks
 }
 # library timer class -> (HIP kernel, roofline bound)
 KERNELS = {
-    "gemm_f64_mfma": ("gemm_kernel<0>", "mfma"),
+    "gemm_f64_mfma": ("gemm_kernel<0>+gemm_packed_kernel<0>", "mfma"),
     "tridiag_reduce_f64": ("tridiag_step_kernel", "hbm"),
     "tridiag_tail_f64": ("tridiag_tail_kernel", "alu"),
     "tridiag_update_gemm_f64": ("gemm_kernel<2>", "mfma"),
@@ -51,12 +51,16 @@ KERNELS = {
 
 TIMED_RANGE = "pinvit_timed"
 # Kernel classes timed with HIP events inside the timed region.  Each timed launch records two
-# events on the stream, a few microseconds of host time per launch; the grouped GEMMs, copies
-# and split-K reductions (about 25,000 launches in three L=48 iterations) are left out there
-# and timed in an instrumented pass of as many further steps, which gives the per-class
-# breakdown.
-LIVE_CLASSES = ("jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "tridiag_tail_f64", "cholesky_f64",
-                "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64")
+# events on the stream, a few microseconds of host time per launch; the copies and split-K
+# reductions are left out there, and an instrumented pass of as many further steps with
+# every launch of every class timed gives the per-class breakdown.
+LIVE_CLASSES = ("gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "tridiag_tail_f64",
+                "cholesky_f64", "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64")
+# the float64 GEMM launches (about 5,000 per L=48 iteration) are timed on a pseudo-random one
+# in eight of them in the timed region (events around all of them lengthen an iteration by
+# about 6%); the tridiagonal step launches are always timed one in eight
+SAMPLED_CLASSES = ("gemm_f64_mfma",)
+SAMPLE_EVERY = 8
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_16118_amd", "csrc", "kernels.hip")
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
@@ -74,17 +78,33 @@ def _counter_rows(path: str):
             yield int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])
 
 
+def _kernel_matches(full_name: str, label: str) -> bool:
+    """Whether a profiler kernel name (e.g. 'void pv::gemm_kernel<0, 64, 64>(...)') is one
+    of the kernels of a label ('gemm_kernel<0>+gemm_packed_kernel<0>', 'tridiag_step_kernel';
+    template arguments after the first are ignored)."""
+    base = full_name.split("(")[0].replace("void ", "").strip().split("::")[-1]
+    for k in label.split("+"):
+        k = k.strip()
+        if "<" in k:
+            if base.startswith(k[:-1]) and len(base) >= len(k) and base[len(k) - 1] in ",>":
+                return True
+        elif base == k or base.startswith(k + "<"):
+            return True
+    return False
+
+
 def pmc_traffic(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str,
                 bench_json: str, cal_bytes: int, commands: str) -> dict:
     """HBM traffic per launch of the dominant kernel of a bench run from two rocprofv3
     --pmc passes of the same deterministic command (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch).  Each counter is scaled by the ratio of the true size to what it reads for a
     plain device copy of cal_bytes bytes (the largest dispatch of the calibration run).  The
-    timed launches are the last `launches` dispatches of the kernel, since the timed steps
-    end the program."""
+    label may join several kernels with '+' (one kernel class launched through several
+    kernels); the launches counted are the last `launches` dispatches of those kernels:
+    the instrumented pass that ends a --no-mixed run repeats the timed steps."""
     with open(bench_json) as f:
         b = json.loads(f.read().strip().splitlines()[-1])
-    kernel, n = b["roofline"]["kernel"], b["roofline"]["launches"]
+    kernel, n = b["roofline"]["kernel"], int(round(b["roofline"]["launches"]))
 
     def factor(path):
         v = max(c for _, _, c in _counter_rows(path))
@@ -93,7 +113,7 @@ def pmc_traffic(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_cs
     ff, fw = factor(cal_fetch_csv), factor(cal_write_csv)
 
     def per_launch(path, fac):
-        vals = sorted((d, c) for d, k, c in _counter_rows(path) if k.split("(")[0].endswith(kernel))
+        vals = sorted((d, c) for d, k, c in _counter_rows(path) if _kernel_matches(k, kernel))
         vals = [c for _, c in vals[-n:]]
         assert len(vals) == n, f"{path}: {len(vals)} dispatches of {kernel}, expected {n}"
         return sum(vals) * 1024.0 * fac / n
@@ -288,6 +308,7 @@ def zform_bench(a):
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
     kw = dict(rank_cap=a.cap, max_iter=a.steps, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=0)
     ctx.set_timed_classes(LIVE_CLASSES)
+    ctx.set_timer_sampling(SAMPLED_CLASSES, SAMPLE_EVERY)
     t0 = time.perf_counter()
     _, hz, x = ctx.run_zform(**kw)
     t1 = time.perf_counter()
@@ -527,6 +548,7 @@ def subspace_bench(a):
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
     common = dict(rank_cap=a.cap, tau=0.0, c=0.5, delta=10.0, m_zip=a.m_zip, truncation=1)
     ctx.set_timed_classes(LIVE_CLASSES)
+    ctx.set_timer_sampling(SAMPLED_CLASSES, SAMPLE_EVERY)
     _, hw, cols = ctx.run_subspace(D, max_iter=a.warmup, **common)
     print(f"# subspace D={D}: warmup {a.warmup} it, ranks {[r['max_rank'] for r in hw]}", file=sys.stderr, flush=True)
     ctx.timers_reset()
@@ -709,6 +731,7 @@ def main():
               f"{[r['max_rank'] for r in hist_w]}", file=sys.stderr, flush=True)
         ctx.timers_reset()
         ctx.set_timed_classes(LIVE_CLASSES)
+        ctx.set_timer_sampling(SAMPLED_CLASSES, SAMPLE_EVERY)
         if mark and rtx:
             rtx.roctxRangePushA(TIMED_RANGE.encode())
         t0 = time.perf_counter()
@@ -717,9 +740,10 @@ def main():
         if mark and rtx:
             rtx.roctxRangePop()
         live = ctx.timers()
-        # instrumented pass: as many further steps with every kernel class timed
+        # instrumented pass: as many further steps with every launch of every class timed
         ctx.timers_reset()
         ctx.set_timed_classes(None)
+        ctx.set_timer_sampling(None)
         res_i, _, psi3 = ctx.run(max_iter=a.steps, start=psi2, resume=res, **common)
         tm = ctx.timers()
         for q in ((psi2, psi3) if keep_warm else (psi, psi2, psi3)):

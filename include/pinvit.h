@@ -412,6 +412,15 @@ pv_status pv_timers_reset(pv_ctx* ctx);
  * the launches after the call (the context's stream is synchronised first). */
 pv_status pv_set_timer_mask(pv_ctx* ctx, uint32_t mask);
 
+/* Sampled timing for classes with many short launches: a class in mask (and in the timer
+ * mask) records events on a pseudo-random one-in-every subset of its launches (chosen by
+ * a hash of the launch's index, so no regular launch pattern biases it), and each timed
+ * launch counts for `every` launches in pv_timers (milliseconds, flops, bytes and calls).
+ * The averages per launch are those of the sample.  every = 1: every launch.  PV_EINVAL
+ * for every < 1.  The step launches of the tridiagonal reduction are always timed one in
+ * eight. */
+pv_status pv_set_timer_sampling(pv_ctx* ctx, uint32_t mask, int every);
+
 /* Symmetric eigenproblem on the device (the eigensolvers behind the Gram
  * factorisations): A is n x n column-major (upper triangle read), w receives the
  * eigenvalues descending, V (n x n) the eigenvectors.  method 0: cyclic Jacobi with

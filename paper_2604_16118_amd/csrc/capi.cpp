@@ -1729,6 +1729,17 @@ pv_status pv_set_timer_mask(pv_ctx* ctx, uint32_t mask) {
   });
 }
 
+pv_status pv_set_timer_sampling(pv_ctx* ctx, uint32_t mask, int every) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    if (every < 1) fail(PV_EINVAL, "sampling period must be >= 1");
+    ctx->c.sync();
+    ctx->c.sample_mask = mask;
+    ctx->c.sample_every = every;
+    for (auto& n : ctx->c.sample_count) n = 0;
+  });
+}
+
 pv_status pv_timers_reset(pv_ctx* ctx) {
   return guard([&] {
     if (!ctx) fail(PV_EINVAL, "null context");

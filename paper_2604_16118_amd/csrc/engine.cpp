@@ -122,6 +122,14 @@ hipEvent_t Ctx::event() {
 
 void Ctx::begin(int cls, hipEvent_t& a) {
   if (!((timer_mask >> cls) & 1u)) { a = nullptr; return; }
+  if ((sample_mask >> cls) & 1u) {
+    // splitmix64 of the launch index: no period that a regular launch pattern could alias
+    uint64_t x = sample_count[cls]++ + 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    if (x % uint64_t(sample_every) != 0) { a = nullptr; return; }
+  }
   a = event();
   PV_HIP(hipEventRecord(a, stream));
 }
@@ -130,6 +138,7 @@ void Ctx::end(int cls, hipEvent_t a, double flops, double bytes, int weight) {
   if (!a) return;
   hipEvent_t b = event();
   PV_HIP(hipEventRecord(b, stream));
+  if ((sample_mask >> cls) & 1u) weight *= sample_every;
   pending.push_back({cls, a, b, flops, bytes, weight});
 }
 

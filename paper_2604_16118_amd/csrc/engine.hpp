@@ -168,6 +168,11 @@ struct Ctx {
   int t_calls[T_COUNT] = {0};
   // kernel classes timed with HIP events (bit c: class c); an untimed launch records no event
   uint32_t timer_mask = ~0u;
+  // classes timed on a pseudo-random one-in-sample_every subset of their launches, each
+  // timed launch standing for sample_every (selection by a hash of the launch's index)
+  uint32_t sample_mask = 0;
+  int sample_every = 1;
+  uint64_t sample_count[32] = {0};
   // 0: sequential TT-SVD truncation with two-pass Gram factorisations (exact path);
   // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
   //    intermediate-rank H application.

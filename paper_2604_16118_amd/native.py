@@ -24,7 +24,7 @@ EXPORTS = [
     "pv_set_truncation", "pv_set_tridiag_steps", "pv_dot", "pv_expect_h", "pv_lincomb", "pv_round", "pv_apply_h", "pv_apply_s", "pv_run", "pv_run_outer", "pv_run_subspace", "pv_run_subspace_joint", "pv_run_zform", "pv_run_batch",
     "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
-    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_set_timer_sampling", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
 ]
 
 
@@ -128,6 +128,7 @@ def lib():
         L.pv_timers.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, ip]
         L.pv_timers_reset.argtypes = [C.c_void_p]
         L.pv_set_timer_mask.argtypes = [C.c_void_p, C.c_uint32]
+        L.pv_set_timer_sampling.argtypes = [C.c_void_p, C.c_uint32, C.c_int]
         L.pv_sym_eig.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_sym_eig_top.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_int]
         L.pv_sym_eig_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -568,3 +569,14 @@ class Context:
                 raise ValueError(f"unknown kernel classes {sorted(unknown)}")
             mask = sum(1 << index[n] for n in set(names))
         _check(lib().pv_set_timer_mask(self._p, mask))
+
+    def set_timer_sampling(self, names=None, every=1):
+        """Time the named classes on a pseudo-random one-in-`every` subset of their launches
+        (pv_set_timer_sampling); None or every = 1: every launch."""
+        index = {lib().pv_timer_name(i).decode(): i for i in range(32) if lib().pv_timer_name(i)}
+        names = names or []
+        unknown = set(names) - set(index)
+        if unknown:
+            raise ValueError(f"unknown kernel classes {sorted(unknown)}")
+        mask = sum(1 << index[n] for n in set(names))
+        _check(lib().pv_set_timer_sampling(self._p, mask, int(every)))

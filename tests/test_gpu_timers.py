@@ -38,3 +38,27 @@ def test_untimed_class_accumulates_nothing(ctx):
 def test_unknown_class_is_rejected(ctx):
     with pytest.raises(ValueError):
         ctx.set_timed_classes(["no_such_class"])
+
+
+def test_sampled_timing_counts_for_the_launches_it_stands_for(ctx):
+    """One-in-eight sampled timing: every timed launch counts for eight, the selection is
+    deterministic (the same launches after a reset) and results do not depend on it."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((70, 40))
+    B = rng.standard_normal((40, 30))
+    counts = []
+    for _ in range(2):
+        ctx.timers_reset()
+        ctx.set_timed_classes(["gemm_f64_mfma"])
+        ctx.set_timer_sampling(["gemm_f64_mfma"], 8)
+        outs = [ctx.gemm(A, B) for _ in range(64)]
+        t = ctx.timers()["gemm_f64_mfma"]
+        counts.append(t["calls"])
+        assert t["calls"] % 8 == 0 and 8 <= t["calls"] <= 160
+        assert t["ms"] > 0.0
+        assert all(np.array_equal(o, outs[0]) for o in outs)
+    ctx.set_timer_sampling(None)
+    ctx.set_timed_classes(None)
+    assert counts[0] == counts[1]
+    with pytest.raises(Exception):
+        ctx.set_timer_sampling(["gemm_f64_mfma"], 0)
