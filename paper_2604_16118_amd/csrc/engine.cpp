@@ -198,6 +198,22 @@ T* Ctx::upload(const std::vector<T>& v) {
 template GemmDesc* Ctx::upload(const std::vector<GemmDesc>&);
 template int* Ctx::upload(const std::vector<int>&);
 
+template <class T, class U>
+std::pair<T*, U*> Ctx::upload2(const std::vector<T>& a, const std::vector<U>& b) {
+  if (a.empty() || b.empty()) return {upload(a), upload(b)};
+  const size_t ba = a.size() * sizeof(T), bb = b.size() * sizeof(U);
+  // the staging area places each array at a 256-byte boundary, one after the other
+  if (!staging.fits(ba + bb + 256)) sync();
+  char* ha = static_cast<char*>(staging.put(a.data(), ba));
+  char* hb = static_cast<char*>(staging.put(b.data(), bb));
+  const size_t off = size_t(hb - ha), bytes = off + bb;
+  Buf buf(pool, (bytes + sizeof(double) - 1) / sizeof(double));
+  PV_HIP(hipMemcpyAsync(buf.p, ha, bytes, hipMemcpyHostToDevice, stream));
+  char* d = reinterpret_cast<char*>(buf.p);
+  scratch.push_back(std::move(buf));
+  return {reinterpret_cast<T*>(d), reinterpret_cast<U*>(d + off)};
+}
+
 static Buf scratch_buf(Ctx& c, size_t n) {
   return Buf(c.pool, n);
 }
@@ -357,8 +373,7 @@ struct GemmBatch {
           const int64_t nt = int64_t((g.M + kGemmBM - 1) / kGemmBM) * ((g.N + kGemmBN - 1) / kGemmBN);
           std::fill(tmap.begin() + g.tile0, tmap.begin() + g.tile0 + nt, int(i));
         }
-        GemmDesc* dd = c.upload(list);
-        int* dm = c.upload(tmap);
+        auto [dd, dm] = c.upload2(list, tmap);
         hipEvent_t a; c.begin(tc, a);
         launch_gemm(dd, dm, int(tiles), prec, c.stream);
         c.end(tc, a, flops, bytes);
@@ -943,8 +958,7 @@ T2Data site_contract(Ctx& c, int k, const Mps& ket, const std::vector<int>& bra_
       }
     }
   if (!tasks.empty()) {
-    WTask* dt = c.upload(tasks);
-    WEntry* de = c.upload(entries);
+    auto [dt, de] = c.upload2(tasks, entries);
     hipEvent_t a; c.begin(T_WSTEP, a);
     launch_wstep(dt, int(tasks.size()), de, c.stream);
     c.end(T_WSTEP, a, 0, bytes);

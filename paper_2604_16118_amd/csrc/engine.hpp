@@ -197,6 +197,9 @@ struct Ctx {
   void end(int cls, hipEvent_t a, double flops, double bytes, int weight = 1);
   template <class T>
   T* upload(const std::vector<T>& v);  // staged async copy into a pool buffer kept in `scratch`
+  // two arrays in one copy (each copy costs a command and a gap on the stream)
+  template <class T, class U>
+  std::pair<T*, U*> upload2(const std::vector<T>& a, const std::vector<U>& b);
   std::vector<Buf> scratch;            // freed at sync
 };
 
