@@ -309,6 +309,7 @@ struct GemmBatch {
     std::vector<ReduceDesc> red;
     std::vector<CopyDesc> zero_k;
     int64_t tiles = 0, red_elems = 0, zk_elems = 0;
+    double red_bytes = 0;  // the S partials read, C read when beta != 0, C written
     double flops = 0, bytes = 0;
     for (const GemmDesc& g0 : d) {
       if (g0.K <= 0) {  // C = beta C (beta 0: C cleared without reading it)
@@ -348,6 +349,7 @@ struct GemmBatch {
         }
         red.push_back(ReduceDesc{g0.C, part.p, g0.M, g0.N, g0.ldc, S, g0.alpha, g0.beta, red_elems});
         red_elems += int64_t(g0.M) * g0.N;
+        red_bytes += 8.0 * double(g0.M) * g0.N * (S + 1 + (g0.beta != 0.0 ? 1 : 0));
         c.scratch.push_back(std::move(part));
       }
     }
@@ -383,7 +385,7 @@ struct GemmBatch {
       ReduceDesc* dr = c.upload(red);
       hipEvent_t a; c.begin(T_REDUCE, a);
       launch_reduce(dr, int(red.size()), red_elems, c.stream);
-      c.end(T_REDUCE, a, 0, 8.0 * red_elems);
+      c.end(T_REDUCE, a, 0, red_bytes);
     }
     d.clear();
   }
