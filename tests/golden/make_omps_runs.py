@@ -24,9 +24,13 @@ from synth import make_problem  # noqa: E402
 # the plain float64 workload at L = 24: decayed integrals seed 0, N = 12, rank cap 128,
 # the exact H application (m_zip <= 0: intermediate ranks up to the full sector
 # dimensions, at most 4096 per bond), sequential truncation, 50 iterations
+# the same with the intermediate rank of the H application capped at 512 (the zip cap of the
+# L = 48 benchmark), which keeps every Gram matrix of the GPU path within order 1024
 RUNS = {
     "L24_N12_cap128_exact": dict(kind="decayed", L=24, N=12, seed=0, cap=128, m_zip=0, iters=50,
                                  truncation="sequential", c=0.5, delta=10.0, tau=0.0),
+    "L24_N12_cap128_mzip512": dict(kind="decayed", L=24, N=12, seed=0, cap=128, m_zip=512, iters=50,
+                                   truncation="sequential", c=0.5, delta=10.0, tau=0.0),
 }
 
 
