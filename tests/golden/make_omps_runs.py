@@ -1,7 +1,12 @@
 """Writes the stored Algorithm 2 histories of the block-sparse MPS oracle that the GPU
 parity tests compare with (runs too long to repeat inside a test).
 
-Usage:  python tests/golden/make_omps_runs.py [name ...]   (default: every run below)
+Usage:  python tests/golden/make_omps_runs.py [--qr-svd] [name ...]   (default: every run below)
+
+--qr-svd takes every SVD of the oracle with LAPACK's QR-iteration driver instead of its
+divide-and-conquer one, a rounding-level change of the same method, and writes
+omps_<name>_qrsvd.json: how far two correct runs of the method drift apart under the
+binding rank cap.
 
 Each run writes tests/golden/omps_<name>.json: the parameters and, per iteration, the
 energy, Rayleigh quotient, residual bound, norms, tolerance, retries, flags and the block
@@ -34,8 +39,12 @@ RUNS = {
 }
 
 
-def make(name: str) -> str:
+def make(name: str, qr_svd: bool = False) -> str:
     cfg = RUNS[name]
+    if qr_svd:
+        import scipy.linalg
+        bsmps._svd = lambda M: scipy.linalg.svd(M, full_matrices=False, lapack_driver="gesvd")
+        name = name + "_qrsvd"
     p = make_problem(cfg["kind"], cfg["L"], cfg["N"], cfg["seed"])
     prm = pinvit.Params(cap=cfg["cap"], max_iter=cfg["iters"], tau=cfg["tau"], c=cfg["c"],
                         delta=cfg["delta"], truncation=cfg["truncation"])
@@ -61,5 +70,8 @@ def make(name: str) -> str:
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(RUNS)):
-        print(make(name), flush=True)
+    args = sys.argv[1:]
+    qr = "--qr-svd" in args
+    names = [a for a in args if a != "--qr-svd"]
+    for name in (names or list(RUNS)):
+        print(make(name, qr), flush=True)

@@ -268,3 +268,28 @@ def test_run_with_binding_m_zip_is_variational_and_never_certified():
     for r in hist:
         assert r["lam"] >= w[0] - 1e-10
         assert r["zip_bound"] and r["zip_disc"] > 0 and r["cap_bound"] and not r.get("stop")
+
+
+def test_stored_L24_runs_under_two_svd_drivers():
+    """The stored L = 24 runs (N = 12, cap 128, m_zip 512, 50 iterations) of the oracle with
+    LAPACK's divide-and-conquer and QR-iteration SVD drivers: a rounding-level change of
+    the same method.  Ranks, retries and flags agree in every iteration; the energies
+    agree to rounding for the first 15 iterations and then drift apart at most to the
+    1e-5 level, as the binding rank cap amplifies rounding differences (the same profile
+    the GPU run shows against the oracle)."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    paths = [os.path.join(here, f) for f in ("omps_L24_N12_cap128_mzip512.json",
+                                             "omps_L24_N12_cap128_mzip512_qrsvd.json")]
+    if not all(os.path.exists(q) for q in paths):
+        pytest.skip("stored runs not written")
+    a, b = (json.load(open(q))["history"] for q in paths)
+    assert len(a) == len(b) == 50
+    rel = []
+    for ra, rb in zip(a, b):
+        for key in ("retries", "cap_bound", "zip_bound", "max_rank"):
+            assert ra[key] == rb[key], (ra["it"], key)
+        rel.append(abs(ra["E"] - rb["E"]) / abs(rb["E"]))
+    assert max(rel[:16]) <= 1e-13
+    assert max(rel) <= 1e-4
