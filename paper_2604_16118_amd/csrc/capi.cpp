@@ -340,6 +340,7 @@ void pv_destroy(pv_ctx* ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.side_stream) (void)hipStreamSynchronize(ctx->c.side_stream);
+    release_aux(ctx->c);
     for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
     for (auto& p : ctx->c.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->c.fork_event) (void)hipEventDestroy(ctx->c.fork_event);
@@ -603,6 +604,11 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       std::vector<int> occ(idx.begin(), idx.begin() + N);
       psi = mps_determinant(c, occ);
     }
+    // a sweep started on the auxiliary stream reads psi: on every way out, it ends first
+    struct Drain {
+      Ctx& c;
+      ~Drain() { expect_h_drain(c); }
+    } drain{c};
     int rows = 0;
     *res = pv_result{};
     for (int it = 0; it < p.max_iter; ++it) {
@@ -610,8 +616,20 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       const double nrm = std::sqrt(dot(c, *psi, *psi));
       if (!(nrm > 0)) fail(PV_ENOCONV, "iterate vanished");
       psi = mps_scaled_copy(c, *psi, 1.0 / nrm, nullptr);
-      const double lam = expect_h(c, *psi, *psi);
+      // the Rayleigh quotient's sweep reads psi only: it runs beside the intermediate-rank
+      // application of H below and is collected where lambda is first used
+      expect_h_begin(c, *psi, *psi);
+      double lam = 0.0;
+      bool have_lam = false;
+      auto lam_now = [&] {
+        if (!have_lam) {
+          lam = expect_h_end(c);
+          have_lam = true;
+        }
+        return lam;
+      };
       if (!c.net.empty() && it % c.net_refresh == 0) {
+        lam_now();
         // the attached network corrects theta from the current iterate's features
         std::vector<double> delta(size_t(L) * (N + 1));
         compute_theta(c);
@@ -626,7 +644,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
           LowPrecision lp(c);
           y0 = apply_h(c, *psi, 0.0, cap, mz, nullptr);
         }
-        auto d0 = mps_lincomb(c, 1.0, *y0, -lam, *psi);
+        auto d0 = mps_lincomb(c, 1.0, *y0, -lam_now(), *psi);
         auto r0 = round_mps(c, *d0, 0.0, cap, nullptr);
         est = c.s_max * mnorm(*r0);
       } else if (s_prev2 <= 0) {
@@ -648,7 +666,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
           LowPrecision lp(c);
           y = apply_h(c, *psi, e12, cap, mz, &cb1, &zd2);
         }
-        auto d = mps_lincomb(c, 1.0, *y, -lam, *psi);
+        auto d = mps_lincomb(c, 1.0, *y, -lam_now(), *psi);
         y.reset();
         r = round_mps(c, *d, e12, cap, &cb2);
         d.reset();
@@ -659,6 +677,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
         eta *= 0.8;
         ++retries;
       }
+      lam_now();
       bool cb4 = false;
       auto pdir = apply_s(c, *s, c.s_max * eta / 3.0, cap, &cb4);
       const double nr = mnorm(*r);
@@ -710,8 +729,10 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       double h12, h22;
       {
         LowPrecision lp(c);  // the Ritz sandwiches may use the low-precision contractions
-        h12 = expect_h(c, *psi, *z2);
+        // the two sandwiches run side by side, h12 on the auxiliary stream
+        expect_h_begin(c, *psi, *z2);
         h22 = expect_h(c, *z2, *z2);
+        h12 = expect_h_end(c);
       }
       const double o12 = dot(c, *psi, *z2);
       const double hm[3] = {lam, h12, h22}, mm[3] = {1.0, o12, 1.0};

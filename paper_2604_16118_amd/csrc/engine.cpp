@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 namespace pv {
@@ -732,35 +733,89 @@ void fill(Ctx& c, double* p, int64_t n, double v) {
 // sum sigma^2 <= delta^2, at most cap, at least one.
 constexpr double kZeroTol = 1e-12;
 
+// Two runs of values in descending order merged into out (ties: the first run's value first).
+static void merge_desc(const double* a, size_t na, const double* b, size_t nb, double* out) {
+  size_t i = 0, j = 0, k = 0;
+  while (i < na && j < nb) {
+    const double x = a[i], y = b[j];
+    const bool t = y > x;
+    out[k++] = t ? y : x;
+    j += t;
+    i += !t;
+  }
+  while (i < na) out[k++] = a[i++];
+  while (j < nb) out[k++] = b[j++];
+}
+
+// The candidate values are put in descending order by merging the sectors' lists (each
+// already descending from the eigensolver; sorted first otherwise); the sector counts of
+// the leading s then follow from the s-th value, ties going to the lower sectors first,
+// which is the order (value, sector, index) of the rule.
 std::vector<int> select_ranks(const std::vector<std::vector<double>>& sig, double delta, int cap,
                               bool* cap_bound, double zero_tol = kZeroTol) {
-  struct E { double s; int n, j; };
-  std::vector<E> all;
-  double smax = 0.0;
-  for (int n = 0; n < int(sig.size()); ++n)
-    for (int j = 0; j < int(sig[n].size()); ++j) {
-      all.push_back({sig[n][j], n, j});
-      smax = std::max(smax, sig[n][j]);
-    }
   std::vector<int> kept(sig.size(), 0);
-  if (all.empty() || !(smax > 0.0)) return kept;
-  std::vector<E> cand;
-  for (const E& e : all)
-    if (e.s > zero_tol * smax) cand.push_back(e);
-  std::sort(cand.begin(), cand.end(), [](const E& a, const E& b) {
-    if (a.s != b.s) return a.s > b.s;
-    if (a.n != b.n) return a.n < b.n;
-    return a.j < b.j;
-  });
+  double smax = 0.0;
+  size_t tot = 0;
+  for (const auto& v : sig) {
+    tot += v.size();
+    for (double x : v) smax = std::max(smax, x);
+  }
+  if (tot == 0 || !(smax > 0.0)) return kept;
+  const double zl = zero_tol * smax;
+  std::vector<double> cand, buf;
+  cand.reserve(tot);
+  std::vector<size_t> runs{0}, next;
+  for (const auto& v : sig) {
+    const size_t b0 = cand.size();
+    for (double x : v)
+      if (x > zl) cand.push_back(x);
+    if (!std::is_sorted(cand.begin() + b0, cand.end(), std::greater<double>()))
+      std::sort(cand.begin() + b0, cand.end(), std::greater<double>());
+    if (cand.size() > b0) runs.push_back(cand.size());
+  }
+  buf.resize(cand.size());
+  while (runs.size() > 2) {
+    next.assign(1, 0);
+    for (size_t r = 0; r + 1 < runs.size(); r += 2) {
+      if (r + 2 < runs.size()) {
+        merge_desc(cand.data() + runs[r], runs[r + 1] - runs[r], cand.data() + runs[r + 1], runs[r + 2] - runs[r + 1],
+                   buf.data() + runs[r]);
+        next.push_back(runs[r + 2]);
+      } else {
+        std::copy(cand.begin() + runs[r], cand.begin() + runs[r + 1], buf.begin() + runs[r]);
+        next.push_back(runs[r + 1]);
+      }
+    }
+    cand.swap(buf);
+    runs.swap(next);
+  }
   const int m = int(cand.size());
-  std::vector<double> tail(m + 1, 0.0);
-  for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + cand[i].s * cand[i].s;
+  // the least s whose discarded tail (summed from the smallest value up) is <= delta^2
   int s_tol = m;
-  for (int s = 0; s <= m; ++s)
-    if (tail[s] <= delta * delta) { s_tol = s; break; }
+  {
+    std::vector<double> tail(size_t(m) + 1, 0.0);
+    for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + cand[i] * cand[i];
+    for (int s = 0; s <= m; ++s)
+      if (tail[s] <= delta * delta) { s_tol = s; break; }
+  }
   if (s_tol > cap && cap_bound) *cap_bound = true;
-  const int s = std::max(1, std::min(s_tol, cap));
-  for (int i = 0; i < s && i < m; ++i) kept[cand[i].n] += 1;
+  const int s = std::min(std::max(1, std::min(s_tol, cap)), m);
+  if (s <= 0) return kept;
+  const double th = cand[size_t(s) - 1];
+  int taken = 0;
+  for (size_t n = 0; n < sig.size(); ++n) {
+    int c = 0;
+    for (double x : sig[n]) c += (x > zl && x > th) ? 1 : 0;
+    kept[n] = c;
+    taken += c;
+  }
+  for (size_t n = 0; n < sig.size() && taken < s; ++n) {
+    int c = 0;
+    for (double x : sig[n]) c += (x > zl && x == th) ? 1 : 0;
+    c = std::min(c, s - taken);
+    kept[n] += c;
+    taken += c;
+  }
   return kept;
 }
 
@@ -777,11 +832,23 @@ double dropped_weight(const std::vector<std::vector<double>>& sig, const std::ve
   return d2;
 }
 
+// through a pinned buffer of the context: a copy into pageable memory would have the
+// runtime lock the destination's pages first, which costs far more than the copy itself
 std::vector<double> download(Ctx& c, const double* p, size_t n) {
-  std::vector<double> h(n);
-  if (n) PV_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  if (n > c.dl_n) {
+    c.sync();
+    if (c.dl_host) PV_HIP(hipHostFree(c.dl_host));
+    c.dl_host = nullptr;
+    c.dl_n = 0;
+    const size_t cap = std::max<size_t>(n + n / 2, 4096);
+    void* h = nullptr;
+    PV_HIP(hipHostMalloc(&h, cap * sizeof(double), hipHostMallocDefault));
+    c.dl_host = static_cast<double*>(h);
+    c.dl_n = cap;
+  }
+  if (n) PV_HIP(hipMemcpyAsync(c.dl_host, p, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
   c.sync();
-  return h;
+  return std::vector<double>(c.dl_host, c.dl_host + n);
 }
 
 // ---------------------------------------------------------------- environments
@@ -1110,7 +1177,15 @@ static std::unique_ptr<DevMpo> diag_mpo(Ctx& c, int L, int w, const std::vector<
 }
 
 // ---------------------------------------------------------------- sweeps
-std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op) {
+// the sweep's launches on c.stream; the result is the block of bra sector N of the
+// environment at cut L (rows x cols, column-major) inside E
+struct EnvEnd {
+  Buf E;
+  const double* res = nullptr;
+  int64_t rows = 0, cols = 0;
+};
+
+static EnvEnd env_sweep_dev(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op) {
   const int L = ket.L, N = ket.N;
   if (bra.L != L || bra.N != N || op.L != L) fail(PV_EINVAL, "env_sweep: mismatched chains");
   auto vb = [&](int m, int n) { return bra.valid(m, n); };
@@ -1147,7 +1222,17 @@ std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevM
     Le = std::move(Ln);
   }
   // cut L: bra sector N, one row; columns = w_0 states x ket dim 1
-  std::vector<double> out = download(c, E.p + Le.off[N], size_t(Le.rows[N] * Le.ncols[N]));
+  EnvEnd r;
+  r.res = E.p + Le.off[N];
+  r.rows = Le.rows[N];
+  r.cols = Le.ncols[N];
+  r.E = std::move(E);
+  return r;
+}
+
+std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op) {
+  EnvEnd r = env_sweep_dev(c, bra, ket, op);
+  std::vector<double> out = download(c, r.res, size_t(r.rows * r.cols));
   return out;
 }
 
@@ -1214,6 +1299,115 @@ double expect_h(Ctx& c, const Mps& bra, const Mps& ket) {
   if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
   auto v = env_sweep(c, bra, ket, *c.hmpo);
   return trace_of(v, bra.rho[bra.L][bra.N], ket.rho[ket.L][ket.N]);
+}
+
+// ---- overlapped sweeps: an auxiliary context (pool, staging, timers) on a stream of its own
+static Ctx& aux_ctx(Ctx& c) {
+  if (!c.aux) {
+    auto a = std::make_unique<Ctx>();
+    a->device = c.device;
+    a->use_side = false;
+    PV_HIP(hipStreamCreate(&a->stream));
+    c.aux = std::move(a);
+    c.aux->staging.init(size_t(64) << 20);
+    PV_HIP(hipEventCreateWithFlags(&c.aux_ready, hipEventDisableTiming));
+  }
+  return *c.aux;
+}
+
+void expect_h_drain(Ctx& c) noexcept {
+  if (!c.aux_pending) return;
+  c.aux_pending = false;
+  if (!c.aux_inline && c.aux) {
+    try {
+      c.aux->sync();
+    } catch (...) {
+      (void)hipStreamSynchronize(c.aux->stream);
+    }
+  }
+}
+
+void expect_h_begin(Ctx& c, const Mps& bra, const Mps& ket) {
+  if (!c.hmpo) fail(PV_ESTATE, "no Hamiltonian set");
+  expect_h_drain(c);
+  c.aux_da = bra.rho[bra.L][bra.N];
+  c.aux_db = ket.rho[ket.L][ket.N];
+  if (!c.use_side) {
+    // contexts sharing the device from several host threads: the sweep runs in place
+    c.aux_value = expect_h(c, bra, ket);
+    c.aux_inline = true;
+    c.aux_pending = true;
+    return;
+  }
+  Ctx& a = aux_ctx(c);
+  a.prec = c.prec;
+  a.lowp = c.lowp;
+  a.trunc_mode = c.trunc_mode;
+  a.timer_mask = c.timer_mask;
+  a.sample_mask = c.sample_mask;
+  a.sample_every = c.sample_every;
+  // the operands are complete once the main stream's work so far is
+  PV_HIP(hipEventRecord(c.aux_ready, c.stream));
+  PV_HIP(hipStreamWaitEvent(a.stream, c.aux_ready, 0));
+  c.aux_inline = false;
+  c.aux_pending = true;
+  EnvEnd r = env_sweep_dev(a, bra, ket, *c.hmpo);
+  const size_t n = size_t(r.rows * r.cols);
+  if (n > c.aux_host_n) {
+    a.sync();
+    if (c.aux_host) PV_HIP(hipHostFree(c.aux_host));
+    c.aux_host = nullptr;
+    c.aux_host_n = 0;
+    void* h = nullptr;
+    PV_HIP(hipHostMalloc(&h, n * sizeof(double), hipHostMallocDefault));
+    c.aux_host = static_cast<double*>(h);
+    c.aux_host_n = n;
+  }
+  c.aux_n = n;
+  if (n) PV_HIP(hipMemcpyAsync(c.aux_host, r.res, n * sizeof(double), hipMemcpyDeviceToHost, a.stream));
+  a.scratch.push_back(std::move(r.E));
+}
+
+double expect_h_end(Ctx& c) {
+  if (!c.aux_pending) fail(PV_ESTATE, "no overlapped sweep is running");
+  c.aux_pending = false;
+  if (c.aux_inline) return c.aux_value;
+  Ctx& a = *c.aux;
+  a.sync();
+  for (int k = 0; k < T_COUNT; ++k) {
+    c.t_ms[k] += a.t_ms[k];
+    c.t_flops[k] += a.t_flops[k];
+    c.t_bytes[k] += a.t_bytes[k];
+    c.t_calls[k] += a.t_calls[k];
+    a.t_ms[k] = a.t_flops[k] = a.t_bytes[k] = 0.0;
+    a.t_calls[k] = 0;
+  }
+  std::vector<double> v(c.aux_host, c.aux_host + c.aux_n);
+  return trace_of(v, c.aux_da, c.aux_db);
+}
+
+void release_aux(Ctx& c) noexcept {
+  expect_h_drain(c);
+  if (c.aux) {
+    Ctx& a = *c.aux;
+    (void)hipStreamSynchronize(a.stream);
+    for (auto e : a.event_pool) (void)hipEventDestroy(e);
+    for (auto& p : a.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    a.event_pool.clear();
+    a.pending.clear();
+    a.scratch.clear();
+    hipStream_t s = a.stream;
+    c.aux.reset();
+    if (s) (void)hipStreamDestroy(s);
+  }
+  if (c.aux_ready) (void)hipEventDestroy(c.aux_ready);
+  c.aux_ready = nullptr;
+  if (c.aux_host) (void)hipHostFree(c.aux_host);
+  c.aux_host = nullptr;
+  c.aux_host_n = 0;
+  if (c.dl_host) (void)hipHostFree(c.dl_host);
+  c.dl_host = nullptr;
+  c.dl_n = 0;
 }
 
 void sym_eig_tridiag_device(Ctx& c, int n, const double* A, double* w, double* V, double* work, EigDesc* desc) {
@@ -1879,11 +2073,9 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
       if (EB.woff[k][n] >= 0)
         for (int j = 0; j < x.rho[k][n]; ++j) sig[n].push_back(std::sqrt(std::max(sb2[EB.woff[k][n] + j], 0.0)));
     // same selection rules with the Gram-level numerical-zero cut-off
-    struct E { double s; int n, j; };
-    std::vector<E> all;
     double smax = 0;
     for (int n = 0; n <= N; ++n)
-      for (int j = 0; j < int(sig[n].size()); ++j) { all.push_back({sig[n][j], n, j}); smax = std::max(smax, sig[n][j]); }
+      for (double v : sig[n]) smax = std::max(smax, v);
     std::vector<int> keep(N + 1, 0);
     if (smax > 0) {
       std::vector<std::vector<double>> sig2(N + 1);

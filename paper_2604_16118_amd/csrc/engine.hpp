@@ -191,6 +191,19 @@ struct Ctx {
   void unfork();
   void join();
 
+  // auxiliary context on a stream of its own, for a sweep that runs beside the main
+  // stream's work (expect_h_begin / expect_h_end); created on first use
+  std::unique_ptr<Ctx> aux;
+  hipEvent_t aux_ready = nullptr;
+  double* aux_host = nullptr;  // pinned host copy of the overlapped sweep's result
+  size_t aux_host_n = 0, aux_n = 0;
+  bool aux_pending = false, aux_inline = false;
+  int aux_da = 0, aux_db = 0;
+  double aux_value = 0.0;
+  // pinned host buffer of download()
+  double* dl_host = nullptr;
+  size_t dl_n = 0;
+
   void sync();
   hipEvent_t event();
   void begin(int cls, hipEvent_t& a);
@@ -234,6 +247,14 @@ void amplitudes(Ctx& c, const Mps& x, const uint64_t* masks, int n, double* out)
 std::vector<double> env_sweep(Ctx& c, const Mps& bra, const Mps& ket, const DevMpo& op);
 double dot(Ctx& c, const Mps& a, const Mps& b);
 double expect_h(Ctx& c, const Mps& bra, const Mps& ket);
+// <bra|H|ket> started on the auxiliary stream behind the main stream's work so far (in
+// place when use_side is off) and collected by expect_h_end; bra and ket stay alive and
+// unmodified until then.  expect_h_drain waits for and drops a started sweep;
+// release_aux frees the auxiliary context and the pinned host buffers.
+void expect_h_begin(Ctx& c, const Mps& bra, const Mps& ket);
+double expect_h_end(Ctx& c);
+void expect_h_drain(Ctx& c) noexcept;
+void release_aux(Ctx& c) noexcept;
 std::unique_ptr<Mps> round_mps(Ctx& c, const Mps& x, double eps, int cap, bool* cap_bound);
 // trunc(H x; eps, cap) with intermediate rank m_zip; *zip_disc2 (may be null) is
 // incremented by the sum of the squared singular values that m_zip dropped in the panels
