@@ -50,15 +50,14 @@ KERNELS = {
 
 
 TIMED_RANGE = "pinvit_timed"
-# Kernel classes timed with HIP events inside the timed region.  Each timed launch records two
-# events on the stream, a few microseconds of host time per launch; the copies and split-K
-# reductions are left out there, and an instrumented pass of as many further steps with
-# every launch of every class timed gives the per-class breakdown.
-LIVE_CLASSES = ("gemm_f64_mfma", "jacobi_eig_f64", "mpo_wstep", "tridiag_reduce_f64", "tridiag_tail_f64",
-                "cholesky_f64", "tridiag_vectors_f64", "tridiag_back_f64", "tridiag_values_f64")
-# the float64 GEMM launches (about 5,000 per L=48 iteration) are timed on a pseudo-random one
-# in eight of them in the timed region (events around all of them lengthen an iteration by
-# about 6%); the tridiagonal step launches are always timed one in eight
+# Kernel classes timed with HIP events inside the timed region (--live).  Each timed launch
+# records two events on the stream, which costs host time and a marker on the device; the
+# default times only the dominant class of the L=48 workload, the float64 GEMM, on a
+# pseudo-random one in eight of its launches (events around all of them lengthen an
+# iteration by about 6%).  An instrumented pass of as many further steps with every launch
+# of every class timed gives the per-class breakdown, and the roofline of a dominant class
+# that is not timed live.
+LIVE_CLASSES = ("gemm_f64_mfma",)
 SAMPLED_CLASSES = ("gemm_f64_mfma",)
 SAMPLE_EVERY = 8
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_16118_amd", "csrc", "kernels.hip")
@@ -637,6 +636,7 @@ def batch_bench(a):
 
 
 def main():
+    global LIVE_CLASSES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -647,6 +647,8 @@ def main():
     ap.add_argument("--m-zip", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-contraction runs")
+    ap.add_argument("--live", default=",".join(LIVE_CLASSES),
+                    help="comma-separated kernel classes timed with HIP events in the timed region")
     ap.add_argument("--checkpoints", type=int, default=2,
                     help="float64 checkpoints from which one step per precision is compared")
     ap.add_argument("--mode0-steps", type=int, default=0,
@@ -681,6 +683,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     a = ap.parse_args()
+    LIVE_CLASSES = tuple(c for c in a.live.split(",") if c)
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
         return
