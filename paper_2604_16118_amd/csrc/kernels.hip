@@ -1470,33 +1470,38 @@ __global__ __launch_bounds__(kStepThreads) void tridiag_step_kernel(const EigDes
 }
 
 // 1b''. The last steps of the step-per-launch reduction, one workgroup per problem with the
-//      trailing block (at most kTailMax rows) in LDS, where a step costs four workgroup
-//      barriers instead of a launch.  Entered at k0 = max(n - kTailMax, 0): the stored
-//      columns >= k0 hold A^(k0-1), and for k0 > 0 step k0 - 1's p and v wait in the
+//      trailing block (at most kTailMax rows) held in registers, where a step costs four
+//      workgroup barriers instead of a launch.  Entered at k0 = max(n - kTailMax, 0): the
+//      stored columns >= k0 hold A^(k0-1), and for k0 > 0 step k0 - 1's p and v wait in the
 //      alternating vectors, as the step kernel leaves them.  Steps k0 .. n - 3 then run as
 //      in the step kernel (same reflector, same symmetric rank-2 form, but every update is
 //      applied at once), and the final 2 x 2 block is recorded.  Wave w owns the columns
-//      j = w (mod waves): it forms their partial products with v along the rows (summed
-//      over the waves through LDS, so no cross-lane reductions), updates them, and the owner
-//      of the next reflector's column leaves its squared norm for the next step.
-constexpr int kTailMax = 128;
-constexpr int kTailLd = kTailMax + 1;
+//      j = w (mod waves), lane l the rows l, l + 64, l + 128 of them (kTailCols x kTailRows
+//      values per lane): the wave forms their partial products with v along the rows
+//      (summed over the waves through LDS, so no cross-lane reductions), updates them, and
+//      the owner of the next reflector's column leaves it and its squared norm in LDS for
+//      the next step.  Every step runs over the whole block: v and p are zero outside the
+//      active rows, which leaves the finished rows and columns unchanged.
+constexpr int kTailMax = 192;
 constexpr int kTailThreads = 1024;
 constexpr int kTailWaves = kTailThreads / 64;
+constexpr int kTailCols = kTailMax / kTailWaves;  // columns per wavefront
+constexpr int kTailRows = kTailMax / 64;          // rows per lane and column
+static_assert(kTailCols * kTailWaves == kTailMax && kTailRows * 64 == kTailMax, "tail layout");
 
 __global__ __launch_bounds__(kTailThreads) void tridiag_tail_kernel(const EigDesc* __restrict__ descs) {
-  // S[i + kTailLd j]: trailing block entry (i, j); then kTailWaves x kTailMax row partials
-  extern __shared__ double S[];
-  double* part = S + kTailLd * kTailMax;
-  __shared__ double vsh[kTailMax], psh[kTailMax], red[kTailWaves];
-  __shared__ double sh_sig2;
+  __shared__ double part[kTailWaves * kTailMax];  // row partials of A v, one row of kTailMax per wave
+  // xsh/sh_sig2: the next reflector's column and its squared norm below the subdiagonal,
+  // in two buffers by the parity of the step (read in step c, written for step c + 1)
+  __shared__ double vsh[kTailMax], psh[kTailMax], xsh[2][kTailMax], red[kTailWaves];
+  __shared__ double sh_sig2[2];
   const EigDesc D = descs[blockIdx.x];
   const int n = D.n;
   if (n <= 0) return;
   gdouble* A = gbl(D.work);
   if (*tri_diag_flag(A, n) != 0.0) return;
   const int tid = threadIdx.x, bs = kTailThreads;
-  const int lane = tid & 63, wave = tid >> 6, nw = kTailWaves;
+  const int lane = tid & 63, wave = tid >> 6;
   const int64_t lda = n;
   gdouble* tail = tri_tail(A, n);
   gdouble* betas = tail;
@@ -1511,6 +1516,11 @@ __global__ __launch_bounds__(kTailThreads) void tridiag_tail_kernel(const EigDes
     return;
   }
   const int k0 = max(n - kTailMax, 0), m0 = n - k0;
+  for (int i = tid; i < kTailMax; i += bs) {
+    vsh[i] = 0.0;
+    psh[i] = 0.0;
+  }
+  __syncthreads();
   // pending update of step k0 - 1: v in vsh, q = p - (beta/2)(p^T v) v in psh (local rows)
   if (k0 > 0) {
     gcdouble* pp = A + (int64_t)n * n + (int64_t)((k0 - 1) & 1) * lda;
@@ -1529,29 +1539,41 @@ __global__ __launch_bounds__(kTailThreads) void tridiag_tail_kernel(const EigDes
     if (bprev != 0.0)
       for (int i = tid; i < m0; i += bs) A[(k0 + i) + (int64_t)(k0 - 1) * lda] = vsh[i];
   }
-  for (int j = wave; j < m0; j += nw) {
-    gcdouble* col = A + (int64_t)(k0 + j) * lda + k0;
-    const double qj = k0 > 0 ? psh[j] : 0.0, vj = k0 > 0 ? vsh[j] : 0.0;
-    for (int i = lane; i < m0; i += 64) {
-      double a = col[i];
-      if (k0 > 0) a -= sym_rank2(vsh[i], qj, psh[i], vj);
-      S[i + kTailLd * j] = a;
+  // the block into registers (zero outside it), with the pending update applied; the owner
+  // of column 0 publishes it and its squared norm below the subdiagonal entry
+  double a[kTailCols][kTailRows];
+#pragma unroll
+  for (int t = 0; t < kTailCols; ++t) {
+    const int j = wave + kTailWaves * t;
+    const double qj = psh[j], vj = vsh[j];
+    double sq = 0.0;
+#pragma unroll
+    for (int r = 0; r < kTailRows; ++r) {
+      const int i = lane + 64 * r;
+      double x = 0.0;
+      if (i < m0 && j < m0) {
+        x = A[(k0 + i) + (int64_t)(k0 + j) * lda];
+        if (k0 > 0) x -= sym_rank2(vsh[i], qj, psh[i], vj);
+      }
+      a[t][r] = x;
+      if (j == 0) {
+        xsh[0][i] = x;
+        if (i >= 2) sq += x * x;
+      }
+    }
+    if (j == 0) {
+      sq = wave_sum_d(sq);
+      if (lane == 0) sh_sig2[0] = sq;
     }
   }
-  {
-    // squared norm of column 0 below its subdiagonal entry
-    double sq = 0.0;
-    __syncthreads();
-    for (int i = 2 + tid; i < m0; i += bs) sq += S[i] * S[i];
-    const double t = block_sum(sq, red, tid, bs);
-    if (tid == 0) sh_sig2 = t;
-    __syncthreads();
-  }
+  __syncthreads();
   for (int c = 0; k0 + c + 2 < n; ++c) {
     const int k = k0 + c;
-    // reflector of column c below the diagonal
-    const double sig2 = sh_sig2;
-    const double x0 = S[c + 1 + kTailLd * c];
+    // reflector of column c below the diagonal, formed by every thread from column c
+    // (published before the last barrier)
+    const int b = c & 1;
+    const double sig2 = sh_sig2[b];
+    const double x0 = xsh[b][c + 1];
     double beta = 0.0, alpha = x0, inv = 0.0;
     if (sig2 != 0.0) {
       const double nrm = sqrt(x0 * x0 + sig2);
@@ -1560,68 +1582,98 @@ __global__ __launch_bounds__(kTailThreads) void tridiag_tail_kernel(const EigDes
       beta = 2.0 * v0 * v0 / (v0 * v0 + sig2);
       inv = 1.0 / v0;
     }
+    auto vof = [&](int i) {
+      return (beta == 0.0 || i <= c || i >= m0) ? 0.0 : (i == c + 1 ? 1.0 : xsh[b][i] * inv);
+    };
     if (tid == 0) {
       ee[k] = alpha;
-      dd[k] = S[c + kTailLd * c];
+      dd[k] = xsh[b][c];
       betas[k] = beta;
     }
-    for (int i = c + 1 + tid; i < m0; i += bs) {
-      const double v = beta == 0.0 ? 0.0 : (i == c + 1 ? 1.0 : S[i + kTailLd * c] * inv);
-      vsh[i] = v;
-      if (beta != 0.0) A[(k0 + i) + (int64_t)k * lda] = v;  // below the diagonal of column k
-    }
-    __syncthreads();
+    if (beta != 0.0)
+      for (int i = c + 1 + tid; i < m0; i += bs) A[(k0 + i) + (int64_t)k * lda] = vof(i);  // below the diagonal of column k
+    double vr[kTailRows];
+#pragma unroll
+    for (int r = 0; r < kTailRows; ++r) vr[r] = vof(lane + 64 * r);
     const int nxt = c + 1;  // the next reflector's column
+    double K = 0.0;
     if (beta != 0.0) {
       // row partials of A22 v over each wavefront's columns, then p = beta A22 v
-      for (int i = c + 1 + lane; i < m0; i += 64) {
-        double acc = 0.0;
-        for (int j = c + 1 + ((wave - (c + 1)) % nw + nw) % nw; j < m0; j += nw) acc += S[i + kTailLd * j] * vsh[j];
-        part[wave * kTailMax + i] = acc;
+      double acc[kTailRows] = {};
+#pragma unroll
+      for (int t = 0; t < kTailCols; ++t) {
+        const int j = wave + kTailWaves * t;
+        if (j <= c || j >= m0) continue;
+        const double vj = vof(j);
+#pragma unroll
+        for (int r = 0; r < kTailRows; ++r) acc[r] += a[t][r] * vj;
+      }
+#pragma unroll
+      for (int r = 0; r < kTailRows; ++r) {
+        if (64 * r + 63 <= c || 64 * r >= m0) continue;  // a chunk of finished (or absent) rows
+        part[wave * kTailMax + lane + 64 * r] = acc[r];
       }
       __syncthreads();
-      for (int i = c + 1 + tid; i < m0; i += bs) {
+      for (int i = tid; i < kTailMax; i += bs) {
         double p = 0.0;
+        if (i > c && i < m0) {
 #pragma unroll 4
-        for (int w = 0; w < nw; ++w) p += part[w * kTailMax + i];
-        psh[i] = beta * p;
+          for (int w = 0; w < kTailWaves; ++w) p += part[w * kTailMax + i];
+          p *= beta;
+        }
+        psh[i] = p;
       }
       __syncthreads();
-      // K = (beta/2) p^T v (every wavefront forms it), q = p - K v, rank-2 update
+      // K = (beta/2) p^T v (every wavefront forms it)
       double pv = 0.0;
-      for (int i = c + 1 + lane; i < m0; i += 64) pv += psh[i] * vsh[i];
-      const double K = 0.5 * beta * wave_sum_d(pv);
-      for (int j = c + 1 + ((wave - (c + 1)) % nw + nw) % nw; j < m0; j += nw) {
-        const double qj = psh[j] - K * vsh[j], vj = vsh[j];
-        double sq = 0.0;
-        for (int i = c + 1 + lane; i < m0; i += 64) {
-          const double qi = psh[i] - K * vsh[i];
-          const double a = S[i + kTailLd * j] - sym_rank2(vsh[i], qj, qi, vj);
-          S[i + kTailLd * j] = a;
-          if (j == nxt && i >= nxt + 2) sq += a * a;
-        }
-        if (j == nxt) {
-          sq = wave_sum_d(sq);
-          if (lane == 0) sh_sig2 = sq;
+#pragma unroll
+      for (int r = 0; r < kTailRows; ++r) pv += psh[lane + 64 * r] * vr[r];
+      K = 0.5 * beta * wave_sum_d(pv);
+    }
+    // q = p - K v and the rank-2 update of the own columns (the identity when beta = 0);
+    // the owner of column nxt publishes it
+#pragma unroll
+    for (int t = 0; t < kTailCols; ++t) {
+      const int j = wave + kTailWaves * t;
+      if (j <= c || j >= m0) continue;  // finished (or absent) columns stay as they are
+      double sq = 0.0;
+      if (beta != 0.0) {
+        const double vj = vof(j), qj = psh[j] - K * vj;
+#pragma unroll
+        for (int r = 0; r < kTailRows; ++r) {
+          if (64 * r + 63 <= c || 64 * r >= m0) continue;
+          const double qi = psh[lane + 64 * r] - K * vr[r];
+          a[t][r] -= sym_rank2(vr[r], qj, qi, vj);
         }
       }
-    } else if (wave == nxt % nw) {  // H_k = I: the block is unchanged
-      double sq = 0.0;
-      for (int i = nxt + 2 + lane; i < m0; i += 64) sq += S[i + kTailLd * nxt] * S[i + kTailLd * nxt];
-      sq = wave_sum_d(sq);
-      if (lane == 0) sh_sig2 = sq;
+      if (j == nxt) {
+#pragma unroll
+        for (int r = 0; r < kTailRows; ++r) {
+          if (64 * r + 63 <= c || 64 * r >= m0) continue;
+          const int i = lane + 64 * r;
+          xsh[b ^ 1][i] = a[t][r];
+          if (i >= nxt + 2) sq += a[t][r] * a[t][r];
+        }
+        sq = wave_sum_d(sq);
+        if (lane == 0) sh_sig2[b ^ 1] = sq;
+      }
     }
     __syncthreads();
   }
-  if (tid == 0) {  // the final 2 x 2 block
+  // the final 2 x 2 block: column m0 - 2 is in xsh, entry (m0 - 1, m0 - 1) with its owner
+  if (tid == 0) {
     const int c = m0 - 2;
-    dd[n - 2] = S[c + kTailLd * c];
-    ee[n - 2] = S[c + 1 + kTailLd * c];
-    dd[n - 1] = S[c + 1 + kTailLd * (c + 1)];
+    dd[n - 2] = xsh[c & 1][c];
+    ee[n - 2] = xsh[c & 1][c + 1];
     ee[n - 1] = 0.0;
     betas[n - 2] = 0.0;
     betas[n - 1] = 0.0;
   }
+#pragma unroll
+  for (int t = 0; t < kTailCols; ++t)
+#pragma unroll
+    for (int r = 0; r < kTailRows; ++r)
+      if (wave + kTailWaves * t == m0 - 1 && lane + 64 * r == m0 - 1) dd[n - 1] = a[t][r];
 }
 
 // 1c. Last 2 x 2 block (or the single entry) of T, after the last trailing update.
@@ -2124,10 +2176,7 @@ void launch_tri_step(const EigDesc* d, int nprob, int nmax, int k, int G, hipStr
 
 void launch_tri_tail(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return;
-  static size_t granted = 0;
-  const size_t shm = sizeof(double) * (kTailLd + kTailWaves) * kTailMax;
-  lds_opt_in((const void*)tridiag_tail_kernel, shm, &granted);
-  hipLaunchKernelGGL(tridiag_tail_kernel, dim3(nprob), dim3(kTailThreads), shm, s, d);
+  hipLaunchKernelGGL(tridiag_tail_kernel, dim3(nprob), dim3(kTailThreads), 0, s, d);
   PV_LAUNCH_CHECK();
 }
 

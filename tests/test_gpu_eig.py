@@ -145,7 +145,7 @@ def test_sym_eig_at_gram_sizes_of_the_workload(ctx, kind, n):
 
 
 @pytest.mark.parametrize("kind", ["rand", "gram_graded", "cluster", "degenerate", "zero_rows"])
-@pytest.mark.parametrize("n", [2, 3, 41, 130, 538])
+@pytest.mark.parametrize("n", [2, 3, 41, 130, 192, 193, 257, 538])
 def test_sym_eig_step_and_panel_reductions_agree(ctx, kind, n):
     """The two reductions to tridiagonal form (one Householder step per launch on several
     workgroups, and panels of 32 steps on one workgroup with GEMM trailing updates) each
