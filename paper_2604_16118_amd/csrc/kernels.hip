@@ -726,25 +726,21 @@ __device__ inline void sturm_counts(const double* d, const double* e2, int n, co
 __device__ void tri_factor(const double* d, const double* e, int n, double sigma, double tiny,
                            gdouble* u, gdouble* v, gdouble* w, gdouble* mult, gdouble* piv, int64_t ld) {
   double cd = d[0] - sigma, cs1 = n > 1 ? e[0] : 0.0, cs2 = 0.0;
+  // both cases of the pivot choice by selects (one division per step, no divergence
+  // between the lanes, which take different choices): no interchange, m = sub / cd (0 for
+  // cd = 0); interchange, m = cd / sub
   auto step = [&](int i, double sub, double a1, double s1) {
-    double ui, vi, wi;
-    if (fabs(cd) >= fabs(sub)) {
-      piv[i * ld] = 0.0;
-      const double m = cd != 0.0 ? sub / cd : 0.0;
-      mult[i * ld] = m;
-      ui = cd; vi = cs1; wi = cs2;
-      cd = a1 - m * cs1;
-      cs1 = s1 - m * cs2;
-      cs2 = 0.0;
-    } else {
-      piv[i * ld] = 1.0;
-      const double m = cd / sub;
-      mult[i * ld] = m;
-      ui = sub; vi = a1; wi = s1;
-      cd = cs1 - m * a1;
-      cs1 = cs2 - m * s1;
-      cs2 = 0.0;
-    }
+    const bool sw = !(fabs(cd) >= fabs(sub));
+    const double num = sw ? cd : sub, den = sw ? sub : cd;
+    const double m = (sw || cd != 0.0) ? num / den : 0.0;
+    piv[i * ld] = sw ? 1.0 : 0.0;
+    mult[i * ld] = m;
+    const double ui = sw ? sub : cd, vi = sw ? a1 : cs1, wi = sw ? s1 : cs2;
+    const double ncd = sw ? cs1 - m * a1 : a1 - m * cs1;
+    const double ncs = sw ? cs2 - m * s1 : s1 - m * cs2;
+    cd = ncd;
+    cs1 = ncs;
+    cs2 = 0.0;
     u[i * ld] = 1.0 / (ui == 0.0 ? tiny : ui);
     v[i * ld] = vi;
     w[i * ld] = wi;
@@ -770,30 +766,46 @@ __device__ void tri_factor(const double* d, const double* e, int n, double sigma
 
 // Solve with the factors of tri_factor for the right-hand side scale * x, in place; returns
 // the squared norm of the solution.  The loads of kSolveBatch rows are issued before the
-// first of them is used, so a pass waits once per batch rather than once per row.
+// first of them is used, so a pass waits once per batch rather than once per row; and the
+// loads of the next batch are issued before the current batch's results are stored: loads
+// and stores share one in-order memory counter, so a wait for loads issued after stores
+// would also wait for the stores to be acknowledged.
 constexpr int kSolveBatch = 8;
 __device__ double tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdouble* mult, gcdouble* piv, gdouble* x,
                             int64_t ld, double scale) {
+  constexpr int B = kSolveBatch;
   // forward: apply the row operations to the right-hand side
   double cur = scale * x[0];
   auto forward = [&](int i, double nx, double m, double pv) {
     const double nxt = scale * nx;
-    if (pv == 0.0) { x[i * ld] = cur; cur = nxt - m * cur; }
-    else { x[i * ld] = nxt; cur = cur - m * nxt; }
+    const bool sw = pv != 0.0;  // rows interchanged at step i
+    x[i * ld] = sw ? nxt : cur;
+    cur = sw ? cur - m * nxt : nxt - m * cur;
   };
-  int i = 0;
-  for (; i + kSolveBatch <= n - 1; i += kSolveBatch) {
-    double nx[kSolveBatch], mm[kSolveBatch], pp[kSolveBatch];
+  const int nbf = (n - 1) / B;  // full batches over rows 0 .. n - 2
+  {
+    double nx0[B], mm0[B], pp0[B], nx1[B], mm1[B], pp1[B];
+    auto ld0 = [&](int i) {
 #pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) {
-      nx[b] = x[(i + 1 + b) * ld];
-      mm[b] = mult[(i + b) * ld];
-      pp[b] = piv[(i + b) * ld];
+      for (int b = 0; b < B; ++b) { nx0[b] = x[(i + 1 + b) * ld]; mm0[b] = mult[(i + b) * ld]; pp0[b] = piv[(i + b) * ld]; }
+    };
+    auto ld1 = [&](int i) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) { nx1[b] = x[(i + 1 + b) * ld]; mm1[b] = mult[(i + b) * ld]; pp1[b] = piv[(i + b) * ld]; }
+    };
+    if (nbf > 0) ld0(0);
+    for (int k = 0; k < nbf; k += 2) {
+      const int i = k * B;
+      if (k + 1 < nbf) ld1(i + B);
+#pragma unroll
+      for (int b = 0; b < B; ++b) forward(i + b, nx0[b], mm0[b], pp0[b]);
+      if (k + 1 >= nbf) break;
+      if (k + 2 < nbf) ld0(i + 2 * B);
+#pragma unroll
+      for (int b = 0; b < B; ++b) forward(i + B + b, nx1[b], mm1[b], pp1[b]);
     }
-#pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) forward(i + b, nx[b], mm[b], pp[b]);
   }
-  for (; i < n - 1; ++i) forward(i, x[(i + 1) * ld], mult[i * ld], piv[i * ld]);
+  for (int i = nbf * B; i < n - 1; ++i) forward(i, x[(i + 1) * ld], mult[i * ld], piv[i * ld]);
   // back substitution
   double x1 = cur * u[(n - 1) * ld];
   x[(n - 1) * ld] = x1;
@@ -809,35 +821,64 @@ __device__ double tri_solve(int n, gcdouble* u, gcdouble* v, gcdouble* w, gcdoub
     x1 = x0;
     x0 = xi;
   };
-  i = n - 3;
-  for (; i + 1 >= kSolveBatch; i -= kSolveBatch) {
-    double xx[kSolveBatch], vv[kSolveBatch], ww[kSolveBatch], uu[kSolveBatch];
+  // rows n - 3 down to 0 in batches of B (row i - b of the batch starting at i)
+  const int nbb = (n - 2) / B;
+  {
+    double xx0[B], vv0[B], ww0[B], uu0[B], xx1[B], vv1[B], ww1[B], uu1[B];
+    auto lb0 = [&](int i) {
 #pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) {
-      const int64_t o = (i - b) * ld;
-      xx[b] = x[o];
-      vv[b] = v[o];
-      ww[b] = w[o];
-      uu[b] = u[o];
+      for (int b = 0; b < B; ++b) {
+        const int64_t o = (i - b) * ld;
+        xx0[b] = x[o]; vv0[b] = v[o]; ww0[b] = w[o]; uu0[b] = u[o];
+      }
+    };
+    auto lb1 = [&](int i) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int64_t o = (i - b) * ld;
+        xx1[b] = x[o]; vv1[b] = v[o]; ww1[b] = w[o]; uu1[b] = u[o];
+      }
+    };
+    if (nbb > 0) lb0(n - 3);
+    for (int k = 0; k < nbb; k += 2) {
+      const int i = n - 3 - k * B;
+      if (k + 1 < nbb) lb1(i - B);
+#pragma unroll
+      for (int b = 0; b < B; ++b) backward(i - b, xx0[b], vv0[b], ww0[b], uu0[b]);
+      if (k + 1 >= nbb) break;
+      if (k + 2 < nbb) lb0(i - 2 * B);
+#pragma unroll
+      for (int b = 0; b < B; ++b) backward(i - B - b, xx1[b], vv1[b], ww1[b], uu1[b]);
     }
-#pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) backward(i - b, xx[b], vv[b], ww[b], uu[b]);
   }
-  for (; i >= 0; --i) backward(i, x[i * ld], v[i * ld], w[i * ld], u[i * ld]);
+  for (int i = n - 3 - nbb * B; i >= 0; --i) backward(i, x[i * ld], v[i * ld], w[i * ld], u[i * ld]);
   return q;
 }
 
-// x <- scale * x for n elements at stride ld, kSolveBatch loads at a time.
+// x <- scale * x for n elements at stride ld, kSolveBatch loads at a time, each batch's
+// loads issued before the previous batch's stores.
 __device__ void strided_scale(int n, gdouble* x, int64_t ld, double scale) {
-  int i = 0;
-  for (; i + kSolveBatch <= n; i += kSolveBatch) {
-    double xx[kSolveBatch];
+  constexpr int B = kSolveBatch;
+  const int nb = n / B;
+  double a0[B], a1[B];
+  if (nb > 0)
 #pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) xx[b] = x[(i + b) * ld];
+    for (int b = 0; b < B; ++b) a0[b] = x[b * ld];
+  for (int k = 0; k < nb; k += 2) {
+    const int i = k * B;
+    if (k + 1 < nb)
 #pragma unroll
-    for (int b = 0; b < kSolveBatch; ++b) x[(i + b) * ld] = scale * xx[b];
+      for (int b = 0; b < B; ++b) a1[b] = x[(i + B + b) * ld];
+#pragma unroll
+    for (int b = 0; b < B; ++b) x[(i + b) * ld] = scale * a0[b];
+    if (k + 1 >= nb) break;
+    if (k + 2 < nb)
+#pragma unroll
+      for (int b = 0; b < B; ++b) a0[b] = x[(i + 2 * B + b) * ld];
+#pragma unroll
+    for (int b = 0; b < B; ++b) x[(i + B + b) * ld] = scale * a1[b];
   }
-  for (; i < n; ++i) x[i * ld] *= scale;
+  for (int i = nb * B; i < n; ++i) x[i * ld] *= scale;
 }
 
 constexpr int kRedThreads = 512;  // reduction kernels: 8 wavefronts with room for 256 VGPRs
@@ -1711,20 +1752,31 @@ __device__ int tri_blocks(const EigDesc& D, int n, double* dd, double* ee, doubl
     ee[i] = gd[n + i];
   }
   __syncthreads();
+  // ||T||_inf: a maximum, so the order of the partial maxima does not matter
+  __shared__ double red_tn[64];
   double tn = 0.0;
-  for (int i = 0; i < n; ++i)
+  for (int i = tid; i < n; i += bs)
     tn = fmax(tn, fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0));
-  __syncthreads();
-  if (tid == 0) {
-    int nb = 0;
-    bstart[nb++] = 0;
-    for (int i = 0; i + 1 < n; ++i)
-      if (fabs(ee[i]) <= kSplitTol * tn) {
+  tn = block_max(tn, red_tn, tid, bs);
+  // split points in increasing order: the first wavefront takes 64 off-diagonals at a time
+  // and places the split ones by the rank of their lane in the ballot
+  if (tid < 64) {
+    int nb = 1;
+    if (tid == 0) bstart[0] = 0;
+    for (int i0 = 0; i0 + 1 < n; i0 += 64) {
+      const int i = i0 + tid;
+      const bool sp = i + 1 < n && fabs(ee[i]) <= kSplitTol * tn;
+      const unsigned long long mask = __ballot(sp);
+      if (sp) {
         ee[i] = 0.0;
-        bstart[nb++] = i + 1;
+        bstart[nb + __popcll(mask & ((1ull << tid) - 1ull))] = i + 1;
       }
-    bstart[nb] = n;
-    *sh_nblk = nb;
+      nb += __popcll(mask);
+    }
+    if (tid == 0) {
+      bstart[nb] = n;
+      *sh_nblk = nb;
+    }
   }
   __syncthreads();
   for (int i = tid; i < n; i += bs) e2[i] = ee[i] * ee[i];
@@ -1885,7 +1937,8 @@ __global__ __launch_bounds__(kVectorPositions) void tridiag_vec_kernel(const Eig
   (void)e2;
   // 3. inverse iteration within each block; vectors vanish outside their block
   double lmax = 0.0;
-  for (int i = 0; i < n; ++i) lmax = fmax(lmax, fabs(lam[i]));
+  for (int i = tid; i < n; i += bs) lmax = fmax(lmax, fabs(lam[i]));
+  lmax = block_max(lmax, red, tid, bs);
   // with a shift every |eigenvalue| of A is at least (1 - kShiftTol) |mu|: nothing is cut
   const double cut = shift != 0.0 ? 0.0 : D.abs_tol * lmax;
   const double ctol = kClusterTol * fmax(tn, 1e-300);
