@@ -1823,11 +1823,18 @@ __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const Ei
       if (sub == 0) glam[t] = dd[s];
       continue;
     }
+    // Gershgorin interval of the block: the group's lanes take every kSectLanes-th row and
+    // combine their minima and maxima (exact in any order)
     double lo = 1e300, hi = -1e300;
-    for (int i = s; i < s + m; ++i) {
+    for (int i = s + sub; i < s + m; i += kSectLanes) {
       const double r = (i > s ? fabs(ee[i - 1]) : 0.0) + (i < s + m - 1 ? fabs(ee[i]) : 0.0);
       lo = fmin(lo, dd[i] - r);
       hi = fmax(hi, dd[i] + r);
+    }
+#pragma unroll
+    for (int off = kSectLanes / 2; off > 0; off >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, off, 64));
+      hi = fmax(hi, __shfl_xor(hi, off, 64));
     }
     double a = lo - 1e-14 * tn - 1e-300, b = hi + 1e-14 * tn + 1e-300;
     const int target = t - s;
