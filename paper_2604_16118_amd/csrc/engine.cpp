@@ -2067,32 +2067,40 @@ std::unique_ptr<Mps> round_parallel(Ctx& c, const Mps& x, double eps, int cap, b
   BondEig EB = eig_grams(c, x, Bg, 1, L - 1, &plan);
   std::vector<double> sb2 = download(c, EB.w.p, EB.w.n);
   auto rho = x.rho;
+  // the bonds are decided independently: on host threads unless several contexts share
+  // the host already (batches)
+  std::vector<char> bound(size_t(L), 0);
+#pragma omp parallel for schedule(dynamic, 1) if (c.use_side)
   for (int k = 1; k < L; ++k) {
     std::vector<std::vector<double>> sig(N + 1);
     for (int n = 0; n <= N; ++n)
-      if (EB.woff[k][n] >= 0)
-        for (int j = 0; j < x.rho[k][n]; ++j) sig[n].push_back(std::sqrt(std::max(sb2[EB.woff[k][n] + j], 0.0)));
+      if (EB.woff[k][n] >= 0) {
+        sig[n].resize(size_t(x.rho[k][n]));
+        for (int j = 0; j < x.rho[k][n]; ++j) sig[n][j] = std::sqrt(std::max(sb2[EB.woff[k][n] + j], 0.0));
+      }
     // same selection rules with the Gram-level numerical-zero cut-off
     double smax = 0;
     for (int n = 0; n <= N; ++n)
       for (double v : sig[n]) smax = std::max(smax, v);
     std::vector<int> keep(N + 1, 0);
     if (smax > 0) {
-      std::vector<std::vector<double>> sig2(N + 1);
       double floor2 = 0.0;  // weight of the values at the numerical-zero level
       for (int n = 0; n <= N; ++n)
-        for (double v : sig[n]) {
-          if (v > kZeroTolPar * smax) sig2[n].push_back(v);
-          else floor2 += v * v;
-        }
-      keep = select_ranks(sig2, delta, cap, cap_bound);
+        for (double v : sig[n])
+          if (!(v > kZeroTolPar * smax)) floor2 += v * v;
+      bool cb = false;
+      keep = select_ranks(sig, delta, cap, &cb, kZeroTolPar);
       // the dropped zero-level values are only known to that level: the tolerance is
       // certified only when their weight fits in it too (exact requests, delta = 0, aside)
-      if (delta > 0 && floor2 > delta * delta && cap_bound) *cap_bound = true;
+      if (delta > 0 && floor2 > delta * delta) cb = true;
+      bound[size_t(k)] = cb ? 1 : 0;
     }
     for (int n = 0; n <= N; ++n)
       if (x.valid(k, n)) rho[k][n] = keep[n];
   }
+  if (cap_bound)
+    for (int k = 1; k < L; ++k)
+      if (bound[size_t(k)]) *cap_bound = true;
   // eigenvectors of the kept singular values only
   {
     std::vector<int> nvec;
