@@ -811,6 +811,13 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    if bound == "mfma":
+        # the device's attainable float64 MFMA rate (register operands only, measured now)
+        att = ctx.mfma_f64_rate()
+        roof["attainable"] = att
+        roof["frac_attainable"] = roof["achieved"] / att if att > 0 else None
+        roof["attainable_note"] = ("pv_mfma_f64_rate: eight workgroups of four wavefronts per compute unit, "
+                                   "chains of four independent 16x16x4 float64 MFMAs on registers")
     rec = traffic_record(kernel)
     roof["traffic"] = rec["traffic_bytes_per_launch"] if rec else None
     roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"

@@ -399,8 +399,8 @@ pv_status pv_run_batch(pv_ctx* const* ctxs, int count, const pv_params* prm, pv_
  * copy/scale, split-K reduction, tridiagonal reduction (panels or step launches),
  * Cholesky panels, grouped GEMM float32, eigenvectors of the tridiagonal matrix,
  * back-transformation, eigenvalues of the tridiagonal matrix, trailing updates of the
- * tridiagonal reduction, grouped GEMM with bfloat16 operands, the LDS tail of the step
- * reduction); the step launches are timed one in eight, each standing for the launches
+ * tridiagonal reduction, grouped GEMM with bfloat16 operands, the tail of the step
+ * reduction (last 192 steps in one workgroup)); the step launches are timed one in eight, each standing for the launches
  * up to the next timed one;
  * names via pv_timer_name. */
 pv_status pv_timers(pv_ctx* ctx, int n, double* ms, double* flops, double* bytes, int* calls);
@@ -428,6 +428,14 @@ pv_status pv_set_timer_sampling(pv_ctx* ctx, uint32_t mask, int every);
  * bisection and inverse iteration (eigenvectors of eigenvalues <= 1e-12 max|lambda|
  * are returned as zero).  For tests. */
 pv_status pv_sym_eig(pv_ctx* ctx, int n, const double* A, double* w, double* V, int method);
+
+/* Attainable float64 MFMA rate of the context's device in TFLOP/s, measured: eight
+ * workgroups of four wavefronts per compute unit, each wavefront a chain of 20,000 steps
+ * of four independent 16x16x4 float64 MFMA products on register operands (no memory
+ * traffic), timed with HIP events on the context's stream (about 20 ms).  The ceiling
+ * against which the grouped GEMM's rate can be read beside the published peak.
+ * PV_EINVAL for null arguments. */
+pv_status pv_mfma_f64_rate(pv_ctx* ctx, double* tflops);
 
 /* C = alpha op(A) op(B) + beta C on the device through the grouped block GEMM of the
  * operator contractions (the tile shape and split-K choice are the library's own):

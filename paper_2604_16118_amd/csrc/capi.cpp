@@ -902,6 +902,36 @@ pv_status pv_sym_eig_noalloc(pv_ctx* ctx, int n, const double* A, double* w, dou
   });
 }
 
+pv_status pv_mfma_f64_rate(pv_ctx* ctx, double* tflops) {
+  return guard([&] {
+    if (!ctx || !tflops) fail(PV_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    int ncu = 0;
+    PV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+    // eight workgroups of four wavefronts per compute unit: eight wavefronts per SIMD
+    const int blocks = 8 * std::max(ncu, 1), iters = 20000;
+    Buf out(c.pool, size_t(blocks) * 256);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PV_HIP(hipEventCreate(&e0));
+    PV_HIP(hipEventCreate(&e1));
+    struct Events {
+      hipEvent_t a, b;
+      ~Events() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } ev{e0, e1};
+    c.sync();
+    launch_mfma_rate(out.p, blocks, iters, c.stream);  // warm-up
+    PV_HIP(hipEventRecord(e0, c.stream));
+    launch_mfma_rate(out.p, blocks, iters, c.stream);
+    PV_HIP(hipEventRecord(e1, c.stream));
+    PV_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double flops = double(blocks) * 4.0 * iters * 4.0 * 2048.0;
+    *tflops = ms > 0.f ? flops / (double(ms) * 1e-3) / 1e12 : 0.0;
+    c.sync();
+  });
+}
+
 pv_status pv_gemm(pv_ctx* ctx, int M, int N, int K, const double* A, int lda, int ta, const double* B, int ldb,
                   int tb, double* C, int ldc, double alpha, double beta, int precision) {
   return guard([&] {

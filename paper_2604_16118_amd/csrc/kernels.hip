@@ -2234,6 +2234,32 @@ void launch_tri_step(const EigDesc* d, int nprob, int nmax, int k, int G, hipStr
   PV_LAUNCH_CHECK();
 }
 
+// Attainable float64 MFMA rate of the device: each wavefront runs a chain of four
+// independent 16x16x4 products per step on register operands only (no memory traffic)
+// and writes its accumulators once.
+__global__ __launch_bounds__(256) void mfma_rate_kernel(double* __restrict__ out, int iters) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = d4{0, 0, 0, 0};
+  double a = 1e-3 * threadIdx.x, b = 1.0 + blockIdx.x;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+    a += 1e-30;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  gbl(out)[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+void launch_mfma_rate(double* out, int blocks, int iters, hipStream_t s) {
+  if (blocks <= 0 || iters <= 0) return;
+  hipLaunchKernelGGL(mfma_rate_kernel, dim3(blocks), dim3(256), 0, s, out, iters);
+  PV_LAUNCH_CHECK();
+}
+
 void launch_tri_tail(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return;
   hipLaunchKernelGGL(tridiag_tail_kernel, dim3(nprob), dim3(kTailThreads), 0, s, d);

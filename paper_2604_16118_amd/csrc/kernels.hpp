@@ -130,6 +130,9 @@ void launch_tri_step(const EigDesc* d_desc, int nprob, int nmax, int k, int G, h
 // stop at k0 - 1.  Leaves d, e, beta and the reflectors as the step launches would.
 void launch_tri_tail(const EigDesc* d_desc, int nprob, hipStream_t s);
 int tri_tail_rows();
+// Float64 MFMA rate probe: blocks workgroups of 256 threads, iters steps of four
+// 16x16x4 products per wavefront (2048 flops each); out takes 256 doubles per workgroup.
+void launch_mfma_rate(double* out, int blocks, int iters, hipStream_t s);
 void launch_eig_tridiag(const EigDesc* d_desc, int nprob, int nmax, int phases, hipStream_t s);
 inline size_t tri_work_doubles(int n) { return size_t(7) * n * n + size_t(5) * n + 2; }
 // Blocked Cholesky factorisation W W^T ~ A of a symmetric positive semidefinite matrix, in

@@ -25,6 +25,7 @@ EXPORTS = [
     "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_set_timer_sampling", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
+    "pv_mfma_f64_rate",
 ]
 
 
@@ -135,6 +136,7 @@ def lib():
         L.pv_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int,
                               dp, C.c_int, C.c_double, C.c_double, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.pv_mfma_f64_rate.argtypes = [C.c_void_p, dp]
         fp, up = C.POINTER(C.c_float), C.POINTER(C.c_uint64)
         L.pv_learned_train_solves.argtypes = [C.c_void_p, fp, C.c_int, up, C.c_int, dp, dp, C.c_int, C.c_float,
                                               dp, dp]
@@ -539,6 +541,12 @@ class Context:
                              _dp(B.ravel(order="F")), B.shape[0], int(bool(tb)),
                              _dp(Cm), M, float(alpha), float(beta), int(precision)))
         return Cm
+
+    def mfma_f64_rate(self):
+        """Attainable float64 MFMA rate of the device in TFLOP/s (pv_mfma_f64_rate)."""
+        r = C.c_double(0.0)
+        _check(lib().pv_mfma_f64_rate(self._p, C.byref(r)))
+        return r.value
 
     def cholesky(self, A):
         A = _f64(np.asfortranarray(A))

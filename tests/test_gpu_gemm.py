@@ -89,3 +89,11 @@ def test_gemm_rejects_bad_arguments(ctx):
         ctx.gemm(np.ones((3, 2)), np.ones((3, 2)))  # inner dimensions differ
     with pytest.raises(Exception):
         ctx.gemm(np.ones((3, 2)), np.ones((2, 2)), precision=3)
+
+
+def test_mfma_f64_rate_probe(ctx):
+    """The attainable float64 MFMA rate the bench reports beside the published peak: a
+    positive rate that does not exceed the published 78.6 TFLOP/s (the probe's flop count
+    is exact, so a rate above the peak would mean a wrong count or timing)."""
+    r = ctx.mfma_f64_rate()
+    assert 1.0 < r <= 78.6 * 1.02, r
