@@ -666,6 +666,8 @@ constexpr int kSectLanes = 8;
 constexpr int kSectPoints = 2;
 constexpr int kSectQ = kSectLanes * kSectPoints;
 constexpr int kValuesPositions = kValuesThreads / kSectLanes;  // eigenvalues per workgroup
+// batches of at most this many eigenvalues in all take a wavefront per eigenvalue
+constexpr int64_t kSectWideMax = 4096;
 static_assert(64 % kSectLanes == 0, "a multisection group lies within one wavefront");
 constexpr int kVectorPositions = 64;   // eigenvectors (threads) per workgroup of inverse iteration
 constexpr int kBackRows = kEigMax / 64;  // rows per lane when a wavefront holds a column
@@ -1792,7 +1794,11 @@ __device__ int tri_blocks(const EigDesc& D, int n, double* dd, double* ee, doubl
 //    of the kSectQ points whose count exceeds t-s and a to the point before it.  Every lane
 //    of a group computes the same points from the same bracket, so the group stays in step.
 //    The unshifted values go to the work area.
+template <int LANES>
 __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const EigDesc* __restrict__ descs) {
+  static_assert(64 % LANES == 0, "a multisection group lies within one wavefront");
+  constexpr int kQ = LANES * kSectPoints;
+  constexpr int kPositions = kValuesThreads / LANES;
   __shared__ int sh_nblk;
   // d, e, e2: n doubles each; block starts: n + 1 ints
   extern __shared__ double tsm[];
@@ -1809,10 +1815,10 @@ __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const Ei
   double tn = 0.0;
   const int nblk = tri_blocks(D, n, dd, ee, e2, bstart, &sh_nblk, &tn);
   const double tiny = fmax(tn * 1e-300, 1e-300) + tn * 2.2e-16 * 1e-3;
-  const int sub = threadIdx.x % kSectLanes, grp = threadIdx.x / kSectLanes;
+  const int sub = threadIdx.x % LANES, grp = threadIdx.x / LANES;
   const int gbase = (threadIdx.x & 63) - sub;  // first lane of the group in its wavefront
-  constexpr uint64_t kGroupMask = kSectLanes == 64 ? ~0ull : (1ull << kSectLanes) - 1;
-  for (int t = t0 + grp; t < t1; t += kValuesPositions) {
+  constexpr uint64_t kGroupMask = LANES == 64 ? ~0ull : (1ull << LANES) - 1;
+  for (int t = t0 + grp; t < t1; t += kPositions) {
     int lo_b = 0, hi_b = nblk - 1;
     while (lo_b < hi_b) {
       const int mid = (lo_b + hi_b + 1) >> 1;
@@ -1823,16 +1829,16 @@ __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const Ei
       if (sub == 0) glam[t] = dd[s];
       continue;
     }
-    // Gershgorin interval of the block: the group's lanes take every kSectLanes-th row and
+    // Gershgorin interval of the block: the group's lanes take every LANES-th row and
     // combine their minima and maxima (exact in any order)
     double lo = 1e300, hi = -1e300;
-    for (int i = s + sub; i < s + m; i += kSectLanes) {
+    for (int i = s + sub; i < s + m; i += LANES) {
       const double r = (i > s ? fabs(ee[i - 1]) : 0.0) + (i < s + m - 1 ? fabs(ee[i]) : 0.0);
       lo = fmin(lo, dd[i] - r);
       hi = fmax(hi, dd[i] + r);
     }
 #pragma unroll
-    for (int off = kSectLanes / 2; off > 0; off >>= 1) {
+    for (int off = LANES / 2; off > 0; off >>= 1) {
       lo = fmin(lo, __shfl_xor(lo, off, 64));
       hi = fmax(hi, __shfl_xor(hi, off, 64));
     }
@@ -1842,7 +1848,7 @@ __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const Ei
       const double mid = 0.5 * (a + b);
       if (mid <= a || mid >= b) break;
       if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) * 2.0 || b - a <= 1e-18 * tn) break;
-      const double h = (b - a) * (1.0 / (kSectQ + 1));
+      const double h = (b - a) * (1.0 / (kQ + 1));
       auto point = [&](int j) { return fmin(fmax(a + (j + 1) * h, a), b); };
       double x[kSectPoints];
       int cnt[kSectPoints];
@@ -1855,7 +1861,7 @@ __global__ __launch_bounds__(kValuesThreads) void tridiag_values_kernel(const Ei
         if (cnt[p] > target) first = p;
       const uint64_t above = (__ballot(first < kSectPoints) >> gbase) & kGroupMask;
       if (above == 0) {
-        a = point(kSectQ - 1);
+        a = point(kQ - 1);
       } else {
         const int l = __builtin_ctzll(above);
         const int j = l * kSectPoints + __shfl(first, gbase + l, 64);
@@ -2281,12 +2287,23 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipSt
   const int threads = tridiag_threads(nmax);
   static size_t granted_values = 0, granted_vec = 0;
   const size_t shm_w = tridiag_values_lds(nmax), shm_v = tridiag_vec_lds(nmax);
-  lds_opt_in((const void*)tridiag_values_kernel, shm_w, &granted_values);
+  static size_t granted_values_wide = 0;
+  lds_opt_in((const void*)tridiag_values_kernel<kSectLanes>, shm_w, &granted_values);
+  lds_opt_in((const void*)tridiag_values_kernel<64>, shm_w, &granted_values_wide);
   lds_opt_in((const void*)tridiag_vec_kernel, shm_v, &granted_vec);
   if (phases & 2) {
-    // one lane group per eigenvalue, kValuesPositions per workgroup, several workgroups per matrix
-    const int parts = (nmax + kValuesPositions - 1) / kValuesPositions;
-    hipLaunchKernelGGL(tridiag_values_kernel, dim3(parts, nprob), dim3(kValuesThreads), shm_w, s, d);
+    // one lane group per eigenvalue, several workgroups per matrix.  The Sturm sweeps are
+    // bound by instruction issue in each wavefront; a small batch leaves most SIMDs idle,
+    // so it takes a whole wavefront per eigenvalue (128 points per round, about half the
+    // rounds of 16 points)
+    if (int64_t(nprob) * nmax <= kSectWideMax) {
+      const int pos = kValuesThreads / 64;
+      const int parts = (nmax + pos - 1) / pos;
+      hipLaunchKernelGGL(tridiag_values_kernel<64>, dim3(parts, nprob), dim3(kValuesThreads), shm_w, s, d);
+    } else {
+      const int parts = (nmax + kValuesPositions - 1) / kValuesPositions;
+      hipLaunchKernelGGL(tridiag_values_kernel<kSectLanes>, dim3(parts, nprob), dim3(kValuesThreads), shm_w, s, d);
+    }
     PV_LAUNCH_CHECK();
     hipLaunchKernelGGL(tridiag_rank_kernel, dim3(nprob), dim3(threads), size_t(nmax) * sizeof(double), s, d);
     PV_LAUNCH_CHECK();
