@@ -731,19 +731,26 @@ __device__ void tri_factor(const double* d, const double* e, int n, double sigma
   // both cases of the pivot choice by selects (one division per step, no divergence
   // between the lanes, which take different choices): no interchange, m = sub / cd (0 for
   // cd = 0); interchange, m = cd / sub
+  // The pivot is den in both cases, so one reciprocal serves the multiplier and u: the
+  // hardware estimate refined by two Newton steps r <- r + r (1 - den r) (a few ulps,
+  // like a rounding of m and u), a shorter dependent chain than an IEEE division.
   auto step = [&](int i, double sub, double a1, double s1) {
     const bool sw = !(fabs(cd) >= fabs(sub));
     const double num = sw ? cd : sub, den = sw ? sub : cd;
-    const double m = (sw || cd != 0.0) ? num / den : 0.0;
+    const double dz = den == 0.0 ? tiny : den;
+    double r = __builtin_amdgcn_rcp(dz);
+    r = fma(r, fma(-dz, r, 1.0), r);
+    r = fma(r, fma(-dz, r, 1.0), r);
+    const double m = (sw || cd != 0.0) ? num * r : 0.0;
     piv[i * ld] = sw ? 1.0 : 0.0;
     mult[i * ld] = m;
-    const double ui = sw ? sub : cd, vi = sw ? a1 : cs1, wi = sw ? s1 : cs2;
+    const double vi = sw ? a1 : cs1, wi = sw ? s1 : cs2;
     const double ncd = sw ? cs1 - m * a1 : a1 - m * cs1;
     const double ncs = sw ? cs2 - m * s1 : s1 - m * cs2;
     cd = ncd;
     cs1 = ncs;
     cs2 = 0.0;
-    u[i * ld] = 1.0 / (ui == 0.0 ? tiny : ui);
+    u[i * ld] = r;
     v[i * ld] = vi;
     w[i * ld] = wi;
   };
