@@ -2127,13 +2127,19 @@ __global__ __launch_bounds__(256) void tridiag_sort_kernel(const EigDesc* __rest
 }
 
 // 4. Back-transformation V = H_0 ... H_{n-3} Z_T: wavefront w of workgroup (x, p) owns
-// columns 8x + 2w and 8x + 2w + 1 of problem p, lane l holds rows l + 64 j (j < 16).
+// columns 8x + 2w and 8x + 2w + 1 of problem p, lane l holds rows l + 64 j (j < ROWS).
+// The reflectors go in pairs (k, k - 1): with a = v_k^T z, b = v_{k-1}^T z and
+// c = v_{k-1}^T v_k from one round of wavefront sums,
+//   H_{k-1} H_k z = z - d_k v_k - d_{k-1} v_{k-1},  d_k = beta_k a,
+//   d_{k-1} = beta_{k-1} (b - c d_k),
+// so a pair costs one chain of cross-lane sums instead of two.
+template <int ROWS>
 __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __restrict__ descs) {
   const EigDesc D = descs[blockIdx.y];
   const int n = D.n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = 8 * blockIdx.x + 2 * wave;
-  if (c0 >= n) return;
+  if (c0 >= n || n > 64 * ROWS) return;
   gdouble* Vout = gbl(D.V);
   const int nvec = D.nvec < 0 ? n : min(D.nvec, n);
   if (c0 >= nvec) {  // columns beyond the wanted ones are zero
@@ -2148,36 +2154,74 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const EigDesc* __rest
   gcdouble* A = gbl(D.work);
   gcdouble* ZT = A + 6 * nn0;
   gcdouble* betas = A + 7 * nn0;
-  double z0[kBackRows], z1[kBackRows];
+  double z0[ROWS], z1[ROWS];
 #pragma unroll
-  for (int j = 0; j < kBackRows; ++j) {
+  for (int j = 0; j < ROWS; ++j) {
     const int r = lane + 64 * j;
     z0[j] = r < n ? ZT[r + (int64_t)c0 * n] : 0.0;
     z1[j] = (r < n && two) ? ZT[r + (int64_t)(c0 + 1) * n] : 0.0;
   }
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = betas[k];
-    if (beta == 0.0) continue;
-    gcdouble* vk = A + (int64_t)k * n;  // v_r = A[r, k] for r > k
-    double v[kBackRows];
-    double d0 = 0.0, d1 = 0.0;
+  // reflector k: v_r = A[r, k] for r > k (zero when beta_k = 0: the column then holds no
+  // reflector)
+  auto load = [&](int k, double beta, double (&v)[ROWS]) {
+    gcdouble* vk = A + (int64_t)k * n;
 #pragma unroll
-    for (int j = 0; j < kBackRows; ++j) {
+    for (int j = 0; j < ROWS; ++j) {
       const int r = lane + 64 * j;
-      v[j] = (r > k && r < n) ? vk[r] : 0.0;
-      d0 += v[j] * z0[j];
-      d1 += v[j] * z1[j];
+      v[j] = (beta != 0.0 && r > k && r < n) ? vk[r] : 0.0;
     }
-    d0 = beta * wave_sum_d(d0);
-    d1 = beta * wave_sum_d(d1);
+  };
+  int k = n - 3;
+  for (; k >= 1; k -= 2) {
+    const double bk = betas[k], bl = betas[k - 1];
+    double vk[ROWS], vl[ROWS];
+    load(k, bk, vk);
+    load(k - 1, bl, vl);
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, c = 0.0;
 #pragma unroll
-    for (int j = 0; j < kBackRows; ++j) {
-      z0[j] -= d0 * v[j];
-      z1[j] -= d1 * v[j];
+    for (int j = 0; j < ROWS; ++j) {
+      a0 += vk[j] * z0[j];
+      a1 += vk[j] * z1[j];
+      b0 += vl[j] * z0[j];
+      b1 += vl[j] * z1[j];
+      c += vl[j] * vk[j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, 64);
+      a1 += __shfl_xor(a1, off, 64);
+      b0 += __shfl_xor(b0, off, 64);
+      b1 += __shfl_xor(b1, off, 64);
+      c += __shfl_xor(c, off, 64);
+    }
+    const double dk0 = bk * a0, dk1 = bk * a1;
+    const double dl0 = bl * (b0 - c * dk0), dl1 = bl * (b1 - c * dk1);
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      z0[j] -= dk0 * vk[j] + dl0 * vl[j];
+      z1[j] -= dk1 * vk[j] + dl1 * vl[j];
+    }
+  }
+  if (k == 0) {  // an odd number of reflectors: the last one alone
+    const double bk = betas[0];
+    double vk[ROWS];
+    load(0, bk, vk);
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      a0 += vk[j] * z0[j];
+      a1 += vk[j] * z1[j];
+    }
+    a0 = bk * wave_sum_d(a0);
+    a1 = bk * wave_sum_d(a1);
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      z0[j] -= a0 * vk[j];
+      z1[j] -= a1 * vk[j];
     }
   }
 #pragma unroll
-  for (int j = 0; j < kBackRows; ++j) {
+  for (int j = 0; j < ROWS; ++j) {
     const int r = lane + 64 * j;
     if (r < n) {
       Vout[r + (int64_t)c0 * n] = z0[j];
@@ -2325,7 +2369,13 @@ void launch_eig_tridiag(const EigDesc* d, int nprob, int nmax, int phases, hipSt
     PV_LAUNCH_CHECK();
   }
   if (phases & 8) {
-    hipLaunchKernelGGL(tridiag_back_kernel, dim3((nmax + 7) / 8, nprob), dim3(256), 0, s, d);
+    const dim3 g((nmax + 7) / 8, nprob);
+    if (nmax <= 256)
+      hipLaunchKernelGGL(tridiag_back_kernel<4>, g, dim3(256), 0, s, d);
+    else if (nmax <= 512)
+      hipLaunchKernelGGL(tridiag_back_kernel<8>, g, dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL(tridiag_back_kernel<kBackRows>, g, dim3(256), 0, s, d);
     PV_LAUNCH_CHECK();
   }
 }
