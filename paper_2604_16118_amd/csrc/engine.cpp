@@ -312,6 +312,23 @@ struct GemmBatch {
     int64_t tiles = 0, red_elems = 0, zk_elems = 0;
     double red_bytes = 0;  // the S partials read, C read when beta != 0, C written
     double flops = 0, bytes = 0;
+    // split-K choice on 64 x 64 tiles
+    auto split_of = [](const GemmDesc& g0) {
+      const int tm = (g0.M + kGemmBM - 1) / kGemmBM, tn = (g0.N + kGemmBN - 1) / kGemmBN;
+      int S = 1;
+      if (tm * tn < 128 && g0.K >= 1024 && g0.m1 == 0) {
+        S = std::min((g0.K + 511) / 512, (256 + tm * tn - 1) / (tm * tn));
+        S = std::max(S, 1);
+      }
+      return S;
+    };
+    // a float64 launch of few 64 x 64 tiles takes the small tiles
+    int64_t tiles64 = 0;
+    for (const GemmDesc& g0 : d)
+      if (g0.K > 0)
+        tiles64 += int64_t((g0.M + kGemmBM - 1) / kGemmBM) * ((g0.N + kGemmBN - 1) / kGemmBN) * split_of(g0);
+    const bool small = (prec == 0 || prec == 2) && tiles64 <= kGemmSmallTiles;
+    const int TM = small ? kGemmSmall : kGemmBM, TN = small ? kGemmSmall : kGemmBN;
     for (const GemmDesc& g0 : d) {
       if (g0.K <= 0) {  // C = beta C (beta 0: C cleared without reading it)
         CopyDesc cd{g0.beta != 0.0 ? g0.C : nullptr, g0.C, g0.M, g0.N, g0.ldc, g0.ldc, g0.beta, zk_elems};
@@ -321,12 +338,8 @@ struct GemmBatch {
       }
       flops += 2.0 * g0.M * g0.N * double(g0.K);
       bytes += 8.0 * (double(g0.M) * g0.K + double(g0.K) * g0.N + double(g0.M) * g0.N * (g0.beta != 0 ? 2 : 1));
-      const int tm = (g0.M + kGemmBM - 1) / kGemmBM, tn = (g0.N + kGemmBN - 1) / kGemmBN;
-      int S = 1;
-      if (tm * tn < 128 && g0.K >= 1024 && g0.m1 == 0) {
-        S = std::min((g0.K + 511) / 512, (256 + tm * tn - 1) / (tm * tn));
-        S = std::max(S, 1);
-      }
+      const int tm = (g0.M + TM - 1) / TM, tn = (g0.N + TN - 1) / TN;
+      int S = split_of(g0);
       if (S == 1) {
         GemmDesc g = g0;
         g.tile0 = int(tiles); g.tiles_n = tn; g.kbeg = 0; g.kend = g.K;
@@ -367,18 +380,18 @@ struct GemmBatch {
         GemmPack pack{};
         std::copy(list.begin(), list.end(), pack.d);
         hipEvent_t a; c.begin(tc, a);
-        launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream);
+        launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream, small);
         c.end(tc, a, flops, bytes);
       } else {
         std::vector<int> tmap(static_cast<size_t>(tiles));
         for (size_t i = 0; i < list.size(); ++i) {
           const GemmDesc& g = list[i];
-          const int64_t nt = int64_t((g.M + kGemmBM - 1) / kGemmBM) * ((g.N + kGemmBN - 1) / kGemmBN);
+          const int64_t nt = int64_t((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
           std::fill(tmap.begin() + g.tile0, tmap.begin() + g.tile0 + nt, int(i));
         }
         auto [dd, dm] = c.upload2(list, tmap);
         hipEvent_t a; c.begin(tc, a);
-        launch_gemm(dd, dm, int(tiles), prec, c.stream);
+        launch_gemm(dd, dm, int(tiles), prec, c.stream, small);
         c.end(tc, a, flops, bytes);
       }
     }

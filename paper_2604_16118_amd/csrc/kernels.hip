@@ -408,11 +408,16 @@ __global__ __launch_bounds__(256, 4) void gemm_packed_kernel(const GemmPack pack
   gemm_any<PREC, BM, BN>(g, tile);
 }
 
-void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s) {
+void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s, bool small) {
   if (total_tiles <= 0) return;
   if (nprob < 1 || nprob > kGemmPack) throw std::runtime_error("gemm: a packed launch takes 1 to kGemmPack problems");
+  if (small && prec != 0 && prec != 2) throw std::runtime_error("gemm: small tiles are float64 only");
   const dim3 g(total_tiles), b(256);
-  if (prec == 0)
+  if (small && prec == 0)
+    hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmSmall, kGemmSmall>), g, b, 0, s, pack, nprob, total_tiles);
+  else if (small)
+    hipLaunchKernelGGL((gemm_packed_kernel<2, kGemmSmall, kGemmSmall>), g, b, 0, s, pack, nprob, total_tiles);
+  else if (prec == 0)
     hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
   else if (prec == 1)
     hipLaunchKernelGGL((gemm_packed_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
@@ -423,10 +428,15 @@ void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int pr
   PV_LAUNCH_CHECK();
 }
 
-void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s) {
+void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s, bool small) {
   if (total_tiles <= 0) return;
+  if (small && prec != 0 && prec != 2) throw std::runtime_error("gemm: small tiles are float64 only");
   const dim3 g(total_tiles), b(256);
-  if (prec == 0)
+  if (small && prec == 0)
+    hipLaunchKernelGGL((gemm_kernel<0, kGemmSmall, kGemmSmall>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+  else if (small)
+    hipLaunchKernelGGL((gemm_kernel<2, kGemmSmall, kGemmSmall>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+  else if (prec == 0)
     hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
   else if (prec == 1)
     hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);

@@ -94,13 +94,15 @@ struct ScaleDesc {
 // prec 2: float64 MFMA, the instance used for the trailing updates of the tridiagonal
 // reduction; prec 3: operands rounded to bfloat16, float32 MFMA accumulation.
 // d_tmap[t] = index of the descriptor that owns tile t (tiles numbered by tile0).
-void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s);
+void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s,
+                 bool small = false);
 // Batches of at most kGemmPack problems pass their descriptors in the kernel arguments.
 constexpr int kGemmPack = 16;
 struct GemmPack {
   GemmDesc d[kGemmPack];
 };
-void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s);
+void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s,
+                        bool small = false);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 // mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
 // problems of one launch must admit the chosen mode at size nmax.
@@ -158,6 +160,12 @@ void launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
 constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
+// float64 launches of at most kGemmSmallTiles 64 x 64 tiles (fewer than one workgroup per
+// compute unit) run kGemmSmall x kGemmSmall tiles instead: four times the workgroups for
+// MFMA chains a quarter as long.  Each element's products are summed in the same order
+// (same K-steps, same position in its 16 x 16 MFMA block), so the results are the same bits.
+constexpr int kGemmSmall = 32;
+constexpr int64_t kGemmSmallTiles = 256;
 constexpr int kGemmGroup = 4;  // consecutive tiles kept on one XCD
 constexpr int kEigMax = 1024;
 
