@@ -477,9 +477,10 @@ constexpr double kZeroTolPar = 1e-6;
 constexpr double kVecCut = 1e-12;  // tridiagonal solver: no eigenvector below this
 
 
-// Step-per-launch reduction: workgroups per launch aimed at (two per compute unit for the
-// largest kernel instance) and the most per problem.
-constexpr int kTriStepWorkgroups = 512;
+// Step-per-launch reduction: workgroups per launch aimed at (as many per compute unit as
+// the instance's registers let run at once: three for n > 512, five for n <= 512) and the
+// most per problem.
+constexpr int kTriStepWorkgroups = 768, kTriStepWorkgroupsSmall = 1280;
 constexpr int kTriStepMaxG = 64;
 constexpr int kTriStepTimeEvery = 8;
 
@@ -519,8 +520,8 @@ void tri_values(Ctx& c, const std::vector<EigDesc>& tri, const EigDesc* d, int n
     // one step per launch on several workgroups per problem.  The problems go in order of
     // decreasing size, so those still reducing at step k are a prefix of the list; each
     // launch covers only them and spreads the workgroup budget over them (the instances
-    // for n <= 512 hold fewer registers: twice the workgroups fit).
-    const int target = ntri <= 512 ? 2 * kTriStepWorkgroups : kTriStepWorkgroups;
+    // for n <= 512 hold fewer registers: more workgroups fit).
+    const int target = ntri <= 512 ? kTriStepWorkgroupsSmall : kTriStepWorkgroups;
     std::vector<EigDesc> srt(tri);
     std::stable_sort(srt.begin(), srt.end(), [](const EigDesc& x, const EigDesc& y) { return x.n > y.n; });
     // (a single problem uses the caller's descriptor: nothing is allocated then)
