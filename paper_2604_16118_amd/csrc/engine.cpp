@@ -481,7 +481,7 @@ constexpr double kVecCut = 1e-12;  // tridiagonal solver: no eigenvector below t
 // the instance's registers let run at once: three for n > 512, five for n <= 512) and the
 // most per problem.
 constexpr int kTriStepWorkgroups = 768, kTriStepWorkgroupsSmall = 1280;
-constexpr int kTriStepMaxG = 64;
+constexpr int kTriStepMaxG = 128;
 constexpr int kTriStepTimeEvery = 8;
 
 // Matrices above this size go to the tridiagonal solver when the job allows it.
