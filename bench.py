@@ -824,7 +824,8 @@ def main():
     roof["kernel"] = kernel
     roof["launches"] = dom["calls"]
     roof["avg_launch_ms"] = dom["ms"] / max(dom["calls"], 1)
-    roof["timing"] = ("HIP events on its launches in the timed region" if dom_name in LIVE_CLASSES
+    roof["timing"] = ("HIP events on its launches in the timed region (the GEMM launches record their own "
+                      "start and stop times through hipExtLaunchKernelGGL)" if dom_name in LIVE_CLASSES
                       else "HIP events on its launches in the instrumented pass")
     g = tm["gemm_f64_mfma"]
     out = {

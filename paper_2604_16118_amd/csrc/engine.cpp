@@ -121,18 +121,37 @@ hipEvent_t Ctx::event() {
   return e;
 }
 
-void Ctx::begin(int cls, hipEvent_t& a) {
-  if (!((timer_mask >> cls) & 1u)) { a = nullptr; return; }
-  if ((sample_mask >> cls) & 1u) {
+// whether this launch of class cls is timed (the class's mask bit, then the sample)
+static bool timed_launch(Ctx& c, int cls) {
+  if (!((c.timer_mask >> cls) & 1u)) return false;
+  if ((c.sample_mask >> cls) & 1u) {
     // splitmix64 of the launch index: no period that a regular launch pattern could alias
-    uint64_t x = sample_count[cls]++ + 0x9E3779B97F4A7C15ull;
+    uint64_t x = c.sample_count[cls]++ + 0x9E3779B97F4A7C15ull;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
     x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
     x ^= x >> 31;
-    if (x % uint64_t(sample_every) != 0) { a = nullptr; return; }
+    if (x % uint64_t(c.sample_every) != 0) return false;
   }
+  return true;
+}
+
+void Ctx::begin(int cls, hipEvent_t& a) {
+  if (!timed_launch(*this, cls)) { a = nullptr; return; }
   a = event();
   PV_HIP(hipEventRecord(a, stream));
+}
+
+void Ctx::begin_ext(int cls, hipEvent_t& a, hipEvent_t& b) {
+  a = b = nullptr;
+  if (!timed_launch(*this, cls)) return;
+  a = event();
+  b = event();
+}
+
+void Ctx::end_ext(int cls, hipEvent_t a, hipEvent_t b, double flops, double bytes, int weight) {
+  if (!a || !b) return;
+  if ((sample_mask >> cls) & 1u) weight *= sample_every;
+  pending.push_back({cls, a, b, flops, bytes, weight});
 }
 
 void Ctx::end(int cls, hipEvent_t a, double flops, double bytes, int weight) {
@@ -379,9 +398,10 @@ struct GemmBatch {
       if (list.size() <= size_t(kGemmPack)) {  // descriptors in the kernel arguments
         GemmPack pack{};
         std::copy(list.begin(), list.end(), pack.d);
-        hipEvent_t a; c.begin(tc, a);
-        launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream, small);
-        c.end(tc, a, flops, bytes);
+        hipEvent_t a, b;
+        c.begin_ext(tc, a, b);
+        launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream, small, a, b);
+        c.end_ext(tc, a, b, flops, bytes);
       } else {
         std::vector<int> tmap(static_cast<size_t>(tiles));
         for (size_t i = 0; i < list.size(); ++i) {
@@ -390,9 +410,10 @@ struct GemmBatch {
           std::fill(tmap.begin() + g.tile0, tmap.begin() + g.tile0 + nt, int(i));
         }
         auto [dd, dm] = c.upload2(list, tmap);
-        hipEvent_t a; c.begin(tc, a);
-        launch_gemm(dd, dm, int(tiles), prec, c.stream, small);
-        c.end(tc, a, flops, bytes);
+        hipEvent_t a, b;
+        c.begin_ext(tc, a, b);
+        launch_gemm(dd, dm, int(tiles), prec, c.stream, small, a, b);
+        c.end_ext(tc, a, b, flops, bytes);
       }
     }
     if (!red.empty()) {

@@ -208,6 +208,11 @@ struct Ctx {
   hipEvent_t event();
   void begin(int cls, hipEvent_t& a);
   void end(int cls, hipEvent_t a, double flops, double bytes, int weight = 1);
+  // the same for a launch that records its own start and stop times (an extended launch
+  // given the two events): begin_ext hands out the events (nulls when the launch is not
+  // timed), end_ext files them; no marker packet goes on the stream
+  void begin_ext(int cls, hipEvent_t& a, hipEvent_t& b);
+  void end_ext(int cls, hipEvent_t a, hipEvent_t b, double flops, double bytes, int weight = 1);
   template <class T>
   T* upload(const std::vector<T>& v);  // staged async copy into a pool buffer kept in `scratch`
   // two arrays in one copy (each copy costs a command and a gap on the stream)

@@ -1,5 +1,6 @@
 // HIP kernels for gfx950: grouped FP64 MFMA GEMM, batched Jacobi eigensolver,
 // MPO W-step, block copies/scalings and a wavefront-shuffle reduction.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -11,6 +12,8 @@
 
 #include <type_traits>
 #include "kernels.hpp"
+
+#include <hip/hip_ext.h>
 
 namespace pv {
 
@@ -408,42 +411,52 @@ __global__ __launch_bounds__(256, 4) void gemm_packed_kernel(const GemmPack pack
   gemm_any<PREC, BM, BN>(g, tile);
 }
 
-void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s, bool small) {
+// The events, when given, take the launch's own start and stop times (an extended launch:
+// no marker packets around it, so they time the kernel's execution alone).
+void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s, bool small,
+                        hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (total_tiles <= 0) return;
   if (nprob < 1 || nprob > kGemmPack) throw std::runtime_error("gemm: a packed launch takes 1 to kGemmPack problems");
   if (small && prec != 0 && prec != 2) throw std::runtime_error("gemm: small tiles are float64 only");
   const dim3 g(total_tiles), b(256);
+  auto go = [&](auto kernel) {
+    hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev_start, ev_stop, 0, pack, nprob, total_tiles);
+  };
   if (small && prec == 0)
-    hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmSmall, kGemmSmall>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<0, kGemmSmall, kGemmSmall>);
   else if (small)
-    hipLaunchKernelGGL((gemm_packed_kernel<2, kGemmSmall, kGemmSmall>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<2, kGemmSmall, kGemmSmall>);
   else if (prec == 0)
-    hipLaunchKernelGGL((gemm_packed_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<0, kGemmBM, kGemmBN>);
   else if (prec == 1)
-    hipLaunchKernelGGL((gemm_packed_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<1, kGemmBM, kGemmBN>);
   else if (prec == 3)
-    hipLaunchKernelGGL((gemm_packed_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<3, kGemmBM, kGemmBN>);
   else
-    hipLaunchKernelGGL((gemm_packed_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, pack, nprob, total_tiles);
+    go(gemm_packed_kernel<2, kGemmBM, kGemmBN>);
   PV_LAUNCH_CHECK();
 }
 
-void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s, bool small) {
+void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s, bool small,
+                 hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (total_tiles <= 0) return;
   if (small && prec != 0 && prec != 2) throw std::runtime_error("gemm: small tiles are float64 only");
   const dim3 g(total_tiles), b(256);
+  auto go = [&](auto kernel) {
+    hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev_start, ev_stop, 0, d_desc, d_tmap, total_tiles);
+  };
   if (small && prec == 0)
-    hipLaunchKernelGGL((gemm_kernel<0, kGemmSmall, kGemmSmall>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<0, kGemmSmall, kGemmSmall>);
   else if (small)
-    hipLaunchKernelGGL((gemm_kernel<2, kGemmSmall, kGemmSmall>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<2, kGemmSmall, kGemmSmall>);
   else if (prec == 0)
-    hipLaunchKernelGGL((gemm_kernel<0, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<0, kGemmBM, kGemmBN>);
   else if (prec == 1)
-    hipLaunchKernelGGL((gemm_kernel<1, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<1, kGemmBM, kGemmBN>);
   else if (prec == 3)
-    hipLaunchKernelGGL((gemm_kernel<3, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<3, kGemmBM, kGemmBN>);
   else
-    hipLaunchKernelGGL((gemm_kernel<2, kGemmBM, kGemmBN>), g, b, 0, s, d_desc, d_tmap, total_tiles);
+    go(gemm_kernel<2, kGemmBM, kGemmBN>);
   PV_LAUNCH_CHECK();
 }
 

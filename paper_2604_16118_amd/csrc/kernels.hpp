@@ -95,14 +95,14 @@ struct ScaleDesc {
 // reduction; prec 3: operands rounded to bfloat16, float32 MFMA accumulation.
 // d_tmap[t] = index of the descriptor that owns tile t (tiles numbered by tile0).
 void launch_gemm(const GemmDesc* d_desc, const int* d_tmap, int total_tiles, int prec, hipStream_t s,
-                 bool small = false);
+                 bool small = false, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Batches of at most kGemmPack problems pass their descriptors in the kernel arguments.
 constexpr int kGemmPack = 16;
 struct GemmPack {
   GemmDesc d[kGemmPack];
 };
 void launch_gemm_packed(const GemmPack& pack, int nprob, int total_tiles, int prec, hipStream_t s,
-                        bool small = false);
+                        bool small = false, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_reduce(const ReduceDesc* d_desc, int nd, int64_t total, hipStream_t s);
 // mode: 2 = matrix and vectors in LDS, 1 = matrix in LDS, 0 = global memory; all
 // problems of one launch must admit the chosen mode at size nmax.
