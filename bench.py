@@ -609,6 +609,7 @@ def batch_bench(a):
         p = make_problem("decayed", L, N, seed)
         c = native.Context(0)
         c.set_hamiltonian(p.h, p.v, N, p.gamma)
+        c.set_gemm_tiles(a.gemm_tiles)
         ctxs.append(c)
     params = [dict(rank_cap=cap, max_iter=a.steps, tau=0.0, c=0.5, delta=10.0, m_zip=cap, truncation=1)
               for _, _, cap, _ in specs]
@@ -631,8 +632,25 @@ def batch_bench(a):
                                   f"rank cap in [32, 256], seeds 0..{a.batch - 1}, {a.steps} iterations each",
                       "problems": a.batch},
            "sequential_iter_per_s": iters / t_seq, "speedup_vs_sequential": t_seq / t_bat,
-           "energies_identical": same}
+           "energies_identical": same, "gemm_tiles": gemm_tiles_summary(a.gemm_tiles, native.gemm_tune_table())}
     print(json.dumps(out), flush=True)
+
+
+def gemm_tiles_summary(mode, rows):
+    """The float64 GEMM tile choice of the run: the mode and, for the autotuner, its decided
+    keys as [kernel precision, log2 64x64 tiles, log2 K, choice (0: 64x64, 1: 32x32),
+    TFLOP/s of 64x64, TFLOP/s of 32x32] (rates from the exploration launches)."""
+    out = {"mode": mode}
+    if mode == "tune":
+        dec = [r for r in rows if r["choice"] >= 0]
+        out["keys"] = len(rows)
+        out["decided"] = len(dec)
+        out["small_chosen"] = sum(r["choice"] == 1 for r in dec)
+        # the rule takes 32 x 32 for at most 256 tiles: every key below 2^8 tiles, most of 2^8 .. 2^9 - 1 not
+        out["rule_agrees"] = sum((r["choice"] == 1) == (r["tiles_log2"] <= 7) for r in dec)
+        out["table"] = [[r["prec"], r["tiles_log2"], r["k_log2"], r["choice"], round(r["tflops64"], 2),
+                         round(r["tflops32"], 2)] for r in dec]
+    return out
 
 
 def main():
@@ -680,6 +698,9 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--precision-checkpoints", action="store_true",
                     help="instead of the timed run: one low-precision step from each float64 checkpoint")
+    ap.add_argument("--gemm-tiles", choices=("rule", "tune"), default="tune",
+                    help="float64 GEMM tile shape: the fixed rule by launch size, or the online autotuner "
+                         "(it explores during the warmup; the shapes give identical results)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     a = ap.parse_args()
@@ -723,6 +744,7 @@ def main():
     t = time.perf_counter()
     ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
     print(f"# setup {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    ctx.set_gemm_tiles(a.gemm_tiles)
     rtx = _roctx()
 
     def run_mode(precision: int, mark: bool, keep_warm: bool = False):
@@ -859,6 +881,7 @@ def main():
                                "gbs": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 2)}
                            for k, v in tm.items()},
         "roofline": roof,
+        "gemm_tiles": gemm_tiles_summary(a.gemm_tiles, native.gemm_tune_table()),
     }
     if r32 is not None:
         h32, t32 = r32["hist"], r32["timers"]

@@ -209,6 +209,41 @@ pv_status pv_set_truncation(pv_ctx* ctx, int mode);
 #define PV_TRIDIAG_STEPS_DEFAULT 1073741824
 pv_status pv_set_tridiag_steps(pv_ctx* ctx, int max_problems);
 
+/* Tile shape of the float64 grouped GEMM (the operator contractions, environments, Gram
+ * matrices and trailing updates; no passage of the paper: a tuning of this library).
+ * Two shapes exist, 64 x 64 and 32 x 32 tiles; both form every element of C by the same
+ * chain of MFMA products in the same order, so the shape never changes a result bit,
+ * only the time.  Modes:
+ *   PV_GEMM_TILES_RULE  (default) 32 x 32 for launches of at most 256 64 x 64 tiles;
+ *   PV_GEMM_TILES_TUNE  online autotuner: a launch is keyed by (device, kernel, log2 of
+ *                       its 64 x 64 tile count, log2 of its longest K); the first eight
+ *                       launches of a key alternate the shapes, each timed by its own
+ *                       start and stop events (read at the context's next
+ *                       synchronisation), then the key keeps the shape with the smaller
+ *                       time per flop; the rule decides meanwhile;
+ *   PV_GEMM_TILES_TABLE the tuner's decided keys without further exploration, the rule
+ *                       for the others;
+ *   PV_GEMM_TILES_SMALL, PV_GEMM_TILES_LARGE  one shape forced (measurement, tests).
+ * The table is one per process, shared by every context and host thread.  The
+ * float32 and bfloat16 kernels have the 64 x 64 shape only.  The context's stream is
+ * synchronised first.  PV_EINVAL for other modes. */
+#define PV_GEMM_TILES_RULE 0
+#define PV_GEMM_TILES_TUNE 1
+#define PV_GEMM_TILES_TABLE 2
+#define PV_GEMM_TILES_SMALL 3
+#define PV_GEMM_TILES_LARGE 4
+pv_status pv_set_gemm_tiles(pv_ctx* ctx, int mode);
+
+/* The autotuner's table: *n_rows receives the number of keys; the first
+ * min(n_rows, max_rows) rows of 9 doubles go to rows (host, row-major): device, kernel
+ * precision (0 float64, 2 float64 trailing updates), log2 bucket of the 64 x 64 tile
+ * count, log2 bucket of the longest K, choice (-1 undecided, 0: 64 x 64, 1: 32 x 32),
+ * samples of the 64 x 64 and of the 32 x 32 shape, and their measured rates in TFLOP/s.
+ * rows may be NULL when max_rows is 0.  PV_EINVAL for a null n_rows or a negative
+ * max_rows.  pv_gemm_tune_clear empties the table (no context may be running). */
+pv_status pv_gemm_tune_table(double* rows, int max_rows, int* n_rows);
+pv_status pv_gemm_tune_clear(void);
+
 /* <a|b> (Euclidean inner product) by a transfer sweep. */
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out);
 /* <bra|H_gamma|ket> by an environment sweep with the MPO (eq. exactrq, one term). */

@@ -342,6 +342,8 @@ void pv_destroy(pv_ctx* ctx) {
     if (ctx->c.side_stream) (void)hipStreamSynchronize(ctx->c.side_stream);
     release_aux(ctx->c);
     for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
+    for (auto& p : ctx->c.tune_pending)
+      if (p.owns) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto& p : ctx->c.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->c.fork_event) (void)hipEventDestroy(ctx->c.fork_event);
     if (ctx->c.join_event) (void)hipEventDestroy(ctx->c.join_event);
@@ -490,6 +492,30 @@ pv_status pv_set_tridiag_steps(pv_ctx* ctx, int max_problems) {
     if (max_problems < 0) fail(PV_EINVAL, "max_problems must be >= 0");
     ctx->c.tri_step_max = max_problems;
   });
+}
+
+pv_status pv_set_gemm_tiles(pv_ctx* ctx, int mode) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null context");
+    if (mode < PV_GEMM_TILES_RULE || mode > PV_GEMM_TILES_LARGE) fail(PV_EINVAL, "mode must lie in 0 .. 4");
+    ctx->c.sync();  // samples in flight are filed under the mode that issued them
+    ctx->c.gemm_tiles = mode;
+  });
+}
+
+pv_status pv_gemm_tune_table(double* rows, int max_rows, int* n_rows) {
+  return guard([&] {
+    if (!n_rows || (max_rows > 0 && !rows)) fail(PV_EINVAL, "null argument");
+    if (max_rows < 0) fail(PV_EINVAL, "max_rows must be >= 0");
+    const std::vector<double> t = gemm_tune_rows();
+    const int n = int(t.size() / 9);
+    *n_rows = n;
+    std::copy(t.begin(), t.begin() + 9 * std::min(n, max_rows), rows);
+  });
+}
+
+pv_status pv_gemm_tune_clear(void) {
+  return guard([&] { gemm_tune_clear(); });
 }
 
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out) {

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 
 namespace pv {
 
@@ -184,10 +186,112 @@ void Ctx::join() {
   pool.hold(false);
 }
 
+// ---------------------------------------------------------------- GEMM tile autotuner
+// The two float64 tile shapes (64 x 64 and 32 x 32) run the same chain of MFMA products
+// for every element of C (the same K-tiles and k-steps in the same order, the same split
+// of K), so the shape changes a launch's time and never a bit of its result.  A launch is
+// keyed by (device, kernel precision, floor(log2) of its count of 64 x 64 tiles including
+// split-K parts, floor(log2) of its longest K range).  In the online mode the first
+// 2 kTuneSamples launches of a key alternate the two shapes, each timed by the launch's own
+// start and stop events; once both shapes have kTuneSamples samples, the key takes the
+// shape with the smaller time per flop (the launches of one key differ in size).  Until
+// then, and for keys never seen, the fixed rule decides.  The table lives for the process
+// and is shared by every context (guarded by a mutex: batched runs tune from many host
+// threads).
+namespace {
+struct TuneKey {
+  int dev, prec, bt, bk;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, prec, bt, bk) < std::tie(o.dev, o.prec, o.bt, o.bk);
+  }
+};
+struct TuneEntry {
+  double ms[2] = {0, 0}, flops[2] = {0, 0};
+  int n[2] = {0, 0};
+  int issued = 0;
+  int choice = -1;
+};
+constexpr int kTuneSamples = 4;
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+
+int floor_log2(int64_t x) {
+  int b = 0;
+  while (x > 1) { x >>= 1; ++b; }
+  return b;
+}
+
+// the tile shape of a float64 launch (true: 32 x 32); cand receives the shape an
+// exploration launch times (-1: none)
+bool gemm_tiles_choice(Ctx& c, int prec, int64_t tiles64, int kmax, int& cand, int& bt, int& bk) {
+  cand = -1;
+  const bool rule = tiles64 <= kGemmSmallTiles;
+  switch (c.gemm_tiles) {
+    case PV_GEMM_TILES_SMALL: return true;
+    case PV_GEMM_TILES_LARGE: return false;
+    case PV_GEMM_TILES_TUNE:
+    case PV_GEMM_TILES_TABLE: break;
+    default: return rule;
+  }
+  bt = floor_log2(std::max<int64_t>(tiles64, 1));
+  bk = floor_log2(std::max(kmax, 1));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const TuneKey key{c.device, prec, bt, bk};
+  if (c.gemm_tiles == PV_GEMM_TILES_TABLE) {
+    auto it = g_tune.find(key);
+    return it != g_tune.end() && it->second.choice >= 0 ? it->second.choice == 1 : rule;
+  }
+  TuneEntry& e = g_tune[key];
+  if (e.choice >= 0) return e.choice == 1;
+  if (e.issued >= 2 * kTuneSamples) return rule;  // samples still in flight
+  cand = e.issued++ & 1;
+  return cand == 1;
+}
+
+}  // namespace
+
+std::vector<double> gemm_tune_rows() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::vector<double> rows;
+  for (const auto& [k, e] : g_tune) {
+    const double r0 = e.ms[0] > 0 ? e.flops[0] / (e.ms[0] * 1e9) : 0.0;
+    const double r1 = e.ms[1] > 0 ? e.flops[1] / (e.ms[1] * 1e9) : 0.0;
+    const double row[9] = {double(k.dev), double(k.prec), double(k.bt), double(k.bk), double(e.choice),
+                           double(e.n[0]), double(e.n[1]), r0, r1};
+    rows.insert(rows.end(), row, row + 9);
+  }
+  return rows;
+}
+
+void gemm_tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
 void Ctx::sync() {
   if (side_stream) PV_HIP(hipStreamSynchronize(side_stream));
   if (main_stream && main_stream != stream) PV_HIP(hipStreamSynchronize(main_stream));
   PV_HIP(hipStreamSynchronize(stream));
+  // the autotuner's samples first: their events may also be a timer's, which the timer
+  // loop below returns to the pool
+  for (auto& p : tune_pending) {
+    float ms = 0.f;
+    PV_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      TuneEntry& e = g_tune[TuneKey{device, p.prec, p.bt, p.bk}];
+      e.ms[p.cand] += double(ms);
+      e.flops[p.cand] += p.flops;
+      e.n[p.cand] += 1;
+      if (e.choice < 0 && e.n[0] >= kTuneSamples && e.n[1] >= kTuneSamples)
+        e.choice = e.ms[1] * e.flops[0] < e.ms[0] * e.flops[1] ? 1 : 0;
+    }
+    if (p.owns) {
+      event_pool.push_back(p.a);
+      event_pool.push_back(p.b);
+    }
+  }
+  tune_pending.clear();
   for (auto& p : pending) {
     float ms = 0.f;
     PV_HIP(hipEventElapsedTime(&ms, p.a, p.b));
@@ -292,6 +396,15 @@ static std::vector<std::vector<int>> empty_rho(int L, int N) {
 // ---------------------------------------------------------------- batched launches
 namespace {
 
+// events for an exploration launch of the tile autotuner that the timers did not time
+// (true: the tuner owns them and returns them to the pool)
+bool tune_events(Ctx& c, int cand, hipEvent_t& a, hipEvent_t& b) {
+  if (cand < 0 || a) return false;
+  a = c.event();
+  b = c.event();
+  return true;
+}
+
 struct GemmBatch {
   std::vector<GemmDesc> d;
   int prec = 0;  // 1: float32 MFMA (operator contractions in the mixed-precision mode)
@@ -346,7 +459,10 @@ struct GemmBatch {
     for (const GemmDesc& g0 : d)
       if (g0.K > 0)
         tiles64 += int64_t((g0.M + kGemmBM - 1) / kGemmBM) * ((g0.N + kGemmBN - 1) / kGemmBN) * split_of(g0);
-    const bool small = (prec == 0 || prec == 2) && tiles64 <= kGemmSmallTiles;
+    int kmax = 0;
+    for (const GemmDesc& g0 : d) kmax = std::max(kmax, g0.K / split_of(g0));
+    int cand = -1, bt = 0, bk = 0;
+    const bool small = (prec == 0 || prec == 2) && gemm_tiles_choice(c, prec, tiles64, kmax, cand, bt, bk);
     const int TM = small ? kGemmSmall : kGemmBM, TN = small ? kGemmSmall : kGemmBN;
     for (const GemmDesc& g0 : d) {
       if (g0.K <= 0) {  // C = beta C (beta 0: C cleared without reading it)
@@ -400,8 +516,10 @@ struct GemmBatch {
         std::copy(list.begin(), list.end(), pack.d);
         hipEvent_t a, b;
         c.begin_ext(tc, a, b);
+        const bool owns = tune_events(c, cand, a, b);
         launch_gemm_packed(pack, int(list.size()), int(tiles), prec, c.stream, small, a, b);
-        c.end_ext(tc, a, b, flops, bytes);
+        if (cand >= 0) c.tune_pending.push_back({prec, bt, bk, cand, a, b, flops, owns});
+        if (!owns) c.end_ext(tc, a, b, flops, bytes);
       } else {
         std::vector<int> tmap(static_cast<size_t>(tiles));
         for (size_t i = 0; i < list.size(); ++i) {
@@ -412,8 +530,10 @@ struct GemmBatch {
         auto [dd, dm] = c.upload2(list, tmap);
         hipEvent_t a, b;
         c.begin_ext(tc, a, b);
+        const bool owns = tune_events(c, cand, a, b);
         launch_gemm(dd, dm, int(tiles), prec, c.stream, small, a, b);
-        c.end_ext(tc, a, b, flops, bytes);
+        if (cand >= 0) c.tune_pending.push_back({prec, bt, bk, cand, a, b, flops, owns});
+        if (!owns) c.end_ext(tc, a, b, flops, bytes);
       }
     }
     if (!red.empty()) {
@@ -1379,6 +1499,7 @@ void expect_h_begin(Ctx& c, const Mps& bra, const Mps& ket) {
   a.lowp = c.lowp;
   a.trunc_mode = c.trunc_mode;
   a.timer_mask = c.timer_mask;
+  a.gemm_tiles = c.gemm_tiles;
   a.sample_mask = c.sample_mask;
   a.sample_every = c.sample_every;
   // the operands are complete once the main stream's work so far is

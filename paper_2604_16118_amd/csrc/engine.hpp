@@ -177,6 +177,12 @@ struct Ctx {
   // 1: simultaneous Gram truncation of all bonds, single-pass factorisations in the
   //    intermediate-rank H application.
   int trunc_mode = 0;
+  // float64 GEMM tile shape (PV_GEMM_TILES_*): the fixed rule by launch size, the online
+  // autotuner, its table without exploration, or one shape forced
+  int gemm_tiles = 0;
+  // launches of the autotuner's exploration whose events are read at the next sync
+  struct TunePending { int prec, bt, bk, cand; hipEvent_t a, b; double flops; bool owns; };
+  std::vector<TunePending> tune_pending;
   // eigensolver batches of at most this many tridiagonal problems are reduced one step per
   // launch on several workgroups per problem; larger ones by one-workgroup panels
   int tri_step_max = PV_TRIDIAG_STEPS_DEFAULT;
@@ -220,6 +226,13 @@ struct Ctx {
   std::pair<T*, U*> upload2(const std::vector<T>& a, const std::vector<U>& b);
   std::vector<Buf> scratch;            // freed at sync
 };
+
+// ---- GEMM tile autotuner (engine.cpp): one table per process, shared by every context ----
+// rows of 9 values: device, kernel precision, log2 bucket of the launch's 64 x 64 tiles,
+// log2 bucket of its longest K, choice (-1 undecided, 0: 64 x 64, 1: 32 x 32), samples of
+// each shape, and each shape's measured rate in TFLOP/s
+std::vector<double> gemm_tune_rows();
+void gemm_tune_clear();
 
 // ---- operations (engine.cpp) ----
 std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vector<int>>& rho);

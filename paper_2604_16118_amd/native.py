@@ -25,7 +25,7 @@ EXPORTS = [
     "pv_set_correction", "pv_learned_correction", "pv_learned_train", "pv_learned_train_solves",
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_set_timer_sampling", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
-    "pv_mfma_f64_rate",
+    "pv_mfma_f64_rate", "pv_set_gemm_tiles", "pv_gemm_tune_table", "pv_gemm_tune_clear",
 ]
 
 
@@ -67,6 +67,8 @@ class OuterIter(C.Structure):
 
 SUBSPACE_MAX_D = 8
 TRIDIAG_STEPS_DEFAULT = 1 << 30  # PV_TRIDIAG_STEPS_DEFAULT
+# float64 GEMM tile modes (PV_GEMM_TILES_*)
+GEMM_TILES = {"rule": 0, "tune": 1, "table": 2, "small": 3, "large": 4}
 
 
 class SubspaceIter(C.Structure):
@@ -137,6 +139,9 @@ def lib():
                               dp, C.c_int, C.c_double, C.c_double, C.c_int]
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.pv_mfma_f64_rate.argtypes = [C.c_void_p, dp]
+        L.pv_set_gemm_tiles.argtypes = [C.c_void_p, C.c_int]
+        L.pv_gemm_tune_table.argtypes = [dp, C.c_int, ip]
+        L.pv_gemm_tune_clear.argtypes = []
         fp, up = C.POINTER(C.c_float), C.POINTER(C.c_uint64)
         L.pv_learned_train_solves.argtypes = [C.c_void_p, fp, C.c_int, up, C.c_int, dp, dp, C.c_int, C.c_float,
                                               dp, dp]
@@ -190,6 +195,27 @@ def _ip(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def gemm_tune_table():
+    """The GEMM tile autotuner's table (pv_gemm_tune_table): one dict per key."""
+    n = C.c_int()
+    _check(lib().pv_gemm_tune_table(None, 0, C.byref(n)))
+    rows = np.zeros(max(n.value, 1) * 9)
+    _check(lib().pv_gemm_tune_table(_dp(rows), n.value, C.byref(n)))
+    names = ("device", "prec", "tiles_log2", "k_log2", "choice", "n64", "n32", "tflops64", "tflops32")
+    out = []
+    for r in rows[: 9 * n.value].reshape(-1, 9):
+        d = dict(zip(names, r.tolist()))
+        for k in names[:7]:
+            d[k] = int(d[k])
+        out.append(d)
+    return out
+
+
+def gemm_tune_clear():
+    """Empty the GEMM tile autotuner's table (pv_gemm_tune_clear)."""
+    _check(lib().pv_gemm_tune_clear())
 
 
 def mpo_bond_dims(h, v):
@@ -281,6 +307,11 @@ class Context:
 
     def set_truncation(self, mode):
         _check(lib().pv_set_truncation(self._p, int(mode)))
+
+    def set_gemm_tiles(self, mode):
+        """Tile shape of the float64 GEMM: "rule", "tune", "table", "small" or "large"
+        (pv_set_gemm_tiles)."""
+        _check(lib().pv_set_gemm_tiles(self._p, GEMM_TILES[mode] if isinstance(mode, str) else int(mode)))
 
     def set_tridiag_steps(self, max_problems):
         """Eigensolver batches of at most max_problems matrices use the step-per-launch
