@@ -86,6 +86,26 @@ def test_drivers_reject_null_arguments_without_touching_a_device():
         assert L.pv_last_error()
 
 
+def test_gemm_tuner_table_is_host_state():
+    """The GEMM tile autotuner's table lives in host memory: it can be read and cleared
+    without a device, an empty table has no rows, and the tile switch rejects a null
+    context and modes outside 0 .. 4 before any HIP call."""
+    import ctypes as C
+    L = native.lib()
+    native.gemm_tune_clear()
+    assert native.gemm_tune_table() == []
+    n = C.c_int(-5)
+    assert L.pv_gemm_tune_table(None, 0, C.byref(n)) == 0 and n.value == 0
+    assert L.pv_gemm_tune_table(None, -1, C.byref(n)) == -1
+    assert L.pv_gemm_tune_table(None, 0, None) == -1
+    assert L.pv_set_gemm_tiles(None, native.GEMM_TILES["tune"]) == -1
+    assert L.pv_last_error()
+    import re
+    with open(HEADER) as f:
+        defs = dict(re.findall(r"#define PV_GEMM_TILES_([A-Z]+) (\d+)", f.read()))
+    assert {k.lower(): int(v) for k, v in defs.items()} == native.GEMM_TILES
+
+
 @pytest.mark.parametrize("kind,L", [("dense", 8), ("decayed", 12), ("decayed", 16)])
 def test_mpo_bond_states_match_the_block_sparse_oracle(kind, L):
     """The library's MPO and the block-sparse oracle's (built independently from the same
