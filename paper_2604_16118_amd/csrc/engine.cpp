@@ -462,7 +462,8 @@ struct GemmBatch {
     int kmax = 0;
     for (const GemmDesc& g0 : d) kmax = std::max(kmax, g0.K / split_of(g0));
     int cand = -1, bt = 0, bk = 0;
-    const bool small = (prec == 0 || prec == 2) && gemm_tiles_choice(c, prec, tiles64, kmax, cand, bt, bk);
+    // (a batch of K = 0 products only launches no GEMM and takes no tuning sample)
+    const bool small = (prec == 0 || prec == 2) && tiles64 > 0 && gemm_tiles_choice(c, prec, tiles64, kmax, cand, bt, bk);
     const int TM = small ? kGemmSmall : kGemmBM, TN = small ? kGemmSmall : kGemmBN;
     for (const GemmDesc& g0 : d) {
       if (g0.K <= 0) {  // C = beta C (beta 0: C cleared without reading it)
