@@ -636,6 +636,59 @@ def batch_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def judge_bench(a):
+    """The per-step judge of a corrected S (pv_set_learned_judge) on an untrained
+    correction: Algorithm 2 at --L/--N (decayed integrals seed 0, exact ranks, sequential
+    truncation) for --steps iterations with the plain S, with the correction of an
+    untrained network (random weights, output layer scaled by 20, so most entries sit at
+    the bound +-(min theta)/2) for the start determinant, and with that correction under the
+    judge; iterations and seconds to ||r|| <= --target-res for each."""
+    from paper_2604_16118_amd import native
+    from synth import init_params, make_problem
+
+    p = make_problem("decayed", a.L, a.N, 0)
+    ctx = native.Context(0)
+    ctx.set_hamiltonian(p.h, p.v, a.N, p.gamma)
+    corr = ctx.learned_correction(init_params(7, out_scale=20.0))
+    ev = dict(rank_cap=4096, max_iter=a.steps, tau=0.0, truncation=0)
+
+    def to_target(h):
+        t = 0.0
+        for i, x in enumerate(h):
+            t += x["seconds"]
+            if x["r_norm"] <= a.target_res:
+                return [i + 1, t]
+        return None
+
+    runs = {}
+    for name in ("plain", "corrected", "judged"):
+        ctx.set_correction(None if name == "plain" else corr)
+        ctx.set_learned_judge(name == "judged")
+        print(f"# judge bench L={a.L} N={a.N}: {name} run", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        _, h, x = ctx.run(**ev)
+        runs[name] = dict(hist=h, elapsed=time.perf_counter() - t, counts=ctx.learned_judge_counts())
+        ctx.mps_free(x)
+    ctx.set_learned_judge(False)
+    ctx.set_correction(None)
+    ctx.close()
+    out = {"metric": "iterations and seconds to ||r|| <= target: plain S, a harmful correction, and the same "
+                     "correction under the per-step judge",
+           "value": (to_target(runs["judged"]["hist"]) or [None])[0], "unit": "iterations (judged)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"Algorithm 2 on decayed integrals L={a.L} N={a.N} seed 0, exact ranks, "
+                                  f"sequential truncation, {a.steps} iterations; correction of an untrained network "
+                                  f"(seed 7, output scale 20) for the start determinant"},
+           "correction_abs_max": float(abs(corr).max()),
+           "target_residual": a.target_res}
+    for name, r in runs.items():
+        h = r["hist"]
+        out[name] = {"to_target": to_target(h), "seconds": r["elapsed"], "iterations": len(h),
+                     "seconds_per_iteration": r["elapsed"] / max(len(h), 1), "last_r_norm": h[-1]["r_norm"],
+                     "energy": h[-1]["E"], "judge_wins_plain_corrected": list(r["counts"])}
+    print(json.dumps(out), flush=True)
+
+
 def gemm_tiles_summary(mode, rows):
     """The float64 GEMM tile choice of the run: the mode and, for the autotuner, its decided
     keys as [kernel precision, log2 64x64 tiles, log2 K, choice (0: 64x64, 1: 32x32),
@@ -698,6 +751,9 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--precision-checkpoints", action="store_true",
                     help="instead of the timed run: one low-precision step from each float64 checkpoint")
+    ap.add_argument("--judge", action="store_true",
+                    help="the per-step judge of a corrected S against the plain S on an untrained correction "
+                         "(use with --L 10 --N 5 --steps 180)")
     ap.add_argument("--gemm-tiles", choices=("rule", "tune"), default="tune",
                     help="float64 GEMM tile shape: the fixed rule by launch size, or the online autotuner "
                          "(it explores during the warmup; the shapes give identical results)")
@@ -731,6 +787,9 @@ def main():
         return
     if a.learned_solves:
         learned_solves_bench(a)
+        return
+    if a.judge:
+        judge_bench(a)
         return
     if a.precision_checkpoints:
         precision_bench(a)

@@ -400,6 +400,20 @@ pv_status pv_learned_train_solves(pv_ctx* ctx, float* params, int psi, const uin
  * sets up S with it as pv_set_correction does.  NULL detaches it (a new Hamiltonian
  * does too).  PV_EINVAL for refresh < 1 or non-finite parameters. */
 pv_status pv_set_learned_network(pv_ctx* ctx, const float* params, int refresh);
+
+/* Per-step judge of a corrected S (the learned correction, an extension without a paper
+ * passage; the plain S of Section 4.3 is the fallback).  With on = 1 and a correction in
+ * force (pv_set_correction or an attached network), every iteration of pv_run forms the
+ * search direction twice from the same residual r and tolerance eta: with the corrected
+ * S, and with the plain S (its own s_max and s_min).  The direction whose 2 x 2 Ritz
+ * value (eq. reducedevp) is lower makes the step; the corrected one on ties.  The update's
+ * truncation tolerance takes the chosen S's s_min; the iteration's rho and bound are
+ * those of the corrected S.  A judged iteration costs two more S applications, two
+ * sandwiches and an inner product.  Default off.  pv_learned_judge_counts returns how
+ * many steps of the last pv_run each S won.  PV_EINVAL for on outside {0, 1} or null
+ * arguments. */
+pv_status pv_set_learned_judge(pv_ctx* ctx, int on);
+pv_status pv_learned_judge_counts(pv_ctx* ctx, int* plain, int* corrected);
 /* x = (H + gamma)^{-1} b on the N-particle sector by preconditioned conjugate gradients in
  * block-sparse form: the products with H by the exact H application, the preconditioner
  * S^2 (every term of both S applications kept), and every sum truncated only at its

@@ -591,6 +591,26 @@ struct LowPrecision {
   ~LowPrecision() { c.lowp = old; }
 };
 
+// The plain S (no correction) for the life of the object: the correction and the set-up
+// of its S are restored on every way out.
+struct PlainS {
+  Ctx& c;
+  const pv_params& p;
+  std::vector<double> keep;
+  PlainS(Ctx& cx, const pv_params& pp) : c(cx), p(pp), keep(std::move(cx.corr)) {
+    c.corr.clear();
+    setup();
+  }
+  ~PlainS() {
+    c.corr = std::move(keep);
+    try {
+      setup();
+    } catch (...) {
+    }
+  }
+  void setup() { setup_precond(c, p.c0, p.c_lower > 0 ? p.c_lower : 1.0, p.c_upper > 0 ? p.c_upper : 1.0); }
+};
+
 pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, pv_iter* hist,
                  int hist_cap, int* psi_out) {
   return guard([&] {
@@ -637,6 +657,7 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
     } drain{c};
     int rows = 0;
     *res = pv_result{};
+    c.judge_plain = c.judge_corr = 0;
     for (int it = 0; it < p.max_iter; ++it) {
       const auto t0 = std::chrono::steady_clock::now();
       const double nrm = std::sqrt(dot(c, *psi, *psi));
@@ -764,14 +785,54 @@ pv_status pv_run(pv_ctx* ctx, const pv_params* prm, int start, pv_result* res, p
       const double hm[3] = {lam, h12, h22}, mm[3] = {1.0, o12, 1.0};
       double lam_s, v[2];
       ritz2(hm, mm, &lam_s, v);
+      double s_min_step = c.s_min;
+      bool cbj = false;
+      if (c.judge && !c.corr.empty()) {
+        // the judge: the same residual r through the plain S (its own s_max and s_min, the
+        // same eta); the direction whose Ritz value is lower makes the step (the corrected
+        // one on ties), and the update's tolerance takes that S's s_min
+        PlainS plain(c, p);
+        bool cj1 = false, cj2 = false;
+        auto sB = apply_s(c, *r, eta / 3.0, cap, &cj1);
+        auto pB = apply_s(c, *sB, c.s_max * eta / 3.0, cap, &cj2);
+        sB.reset();
+        const double npB = mnorm(*pB);
+        bool plain_wins = false;
+        if (npB > 0) {
+          auto zB = mps_scaled_copy(c, *pB, 1.0 / npB, nullptr);
+          pB.reset();
+          double h12B, h22B;
+          {
+            LowPrecision lp(c);
+            expect_h_begin(c, *psi, *zB);
+            h22B = expect_h(c, *zB, *zB);
+            h12B = expect_h_end(c);
+          }
+          const double o12B = dot(c, *psi, *zB);
+          const double hmB[3] = {lam, h12B, h22B}, mmB[3] = {1.0, o12B, 1.0};
+          double lamB, vB[2];
+          ritz2(hmB, mmB, &lamB, vB);
+          if (lamB < lam_s) {
+            plain_wins = true;
+            lam_s = lamB;
+            v[0] = vB[0];
+            v[1] = vB[1];
+            z2 = std::move(zB);
+            s_min_step = c.s_min;
+            cbj = cj1 || cj2;
+          }
+        }
+        ++(plain_wins ? c.judge_plain : c.judge_corr);
+      }
       const double q = std::sqrt(lam_s / (lam_s + p.t_eig * (lam - lam_s)));
       const double da = delta_a(rho, q);
       const double eta_in = da * std::sqrt(lam_s) / std::sqrt(1.0 + p.c);
-      const double eta_psi = eta_in * c.s_min;
+      const double eta_psi = eta_in * s_min_step;
       auto comb = mps_lincomb(c, v[0], *psi, v[1], *z2);
       bool cb5 = false;
       psi = round_mps(c, *comb, eta_psi, cap, &cb5);
       c.sync();
+      rec.cap_bound |= cbj ? 1 : 0;
       rec.lambda_star = lam_s;
       rec.eta_psi = eta_psi;
       rec.cap_bound |= cb5 ? 1 : 0;
@@ -1274,6 +1335,22 @@ pv_status pv_set_learned_network(pv_ctx* ctx, const float* params, int refresh) 
       if (!std::isfinite(params[i])) fail(PV_EINVAL, "network parameters not finite");
     c.net.assign(params, params + PV_MLP_PARAMS);
     c.net_refresh = refresh;
+  });
+}
+
+pv_status pv_set_learned_judge(pv_ctx* ctx, int on) {
+  return guard([&] {
+    if (!ctx) fail(PV_EINVAL, "null argument");
+    if (on != 0 && on != 1) fail(PV_EINVAL, "on must be 0 or 1");
+    ctx->c.judge = on != 0;
+  });
+}
+
+pv_status pv_learned_judge_counts(pv_ctx* ctx, int* plain, int* corrected) {
+  return guard([&] {
+    if (!ctx || !plain || !corrected) fail(PV_EINVAL, "null argument");
+    *plain = ctx->c.judge_plain;
+    *corrected = ctx->c.judge_corr;
   });
 }
 

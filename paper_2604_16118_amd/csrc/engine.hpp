@@ -153,6 +153,10 @@ struct Ctx {
   // correction (iterations); empty: none
   std::vector<float> net;
   int net_refresh = 0;
+  // per-step judge of a corrected S: each iteration of pv_run also forms the direction
+  // with the plain S and takes the one with the lower Ritz value; steps won by each
+  bool judge = false;
+  int judge_plain = 0, judge_corr = 0;
   double t_min = 0, t_max = 0, T_ratio = 0, hs = 0, a0 = 0, s_min = 0, s_max = 0;
   int m_minus = 0, m_plus = 0;
   std::vector<double> alpha, beta;

@@ -26,6 +26,7 @@ EXPORTS = [
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_set_timer_sampling", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
     "pv_mfma_f64_rate", "pv_set_gemm_tiles", "pv_gemm_tune_table", "pv_gemm_tune_clear",
+    "pv_set_learned_judge", "pv_learned_judge_counts",
 ]
 
 
@@ -140,6 +141,8 @@ def lib():
         L.pv_cholesky.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.pv_mfma_f64_rate.argtypes = [C.c_void_p, dp]
         L.pv_set_gemm_tiles.argtypes = [C.c_void_p, C.c_int]
+        L.pv_set_learned_judge.argtypes = [C.c_void_p, C.c_int]
+        L.pv_learned_judge_counts.argtypes = [C.c_void_p, ip, ip]
         L.pv_gemm_tune_table.argtypes = [dp, C.c_int, ip]
         L.pv_gemm_tune_clear.argtypes = []
         fp, up = C.POINTER(C.c_float), C.POINTER(C.c_uint64)
@@ -307,6 +310,16 @@ class Context:
 
     def set_truncation(self, mode):
         _check(lib().pv_set_truncation(self._p, int(mode)))
+
+    def set_learned_judge(self, on):
+        """Per-step judge of a corrected S against the plain S (pv_set_learned_judge)."""
+        _check(lib().pv_set_learned_judge(self._p, int(bool(on))))
+
+    def learned_judge_counts(self):
+        """(steps won by the plain S, steps won by the corrected S) in the last run."""
+        a, b = C.c_int(), C.c_int()
+        _check(lib().pv_learned_judge_counts(self._p, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def set_gemm_tiles(self, mode):
         """Tile shape of the float64 GEMM: "rule", "tune", "table", "small" or "large"
