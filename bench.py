@@ -127,6 +127,30 @@ def pmc_traffic(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_cs
             "commands": commands}
 
 
+def pmc_summary(path: str) -> str:
+    """Totals of every counter per kernel over all dispatches of a rocprofv3 --pmc CSV
+    (counter_collection.csv), as a markdown table: kernel (template arguments kept),
+    dispatches, then one column per counter."""
+    import csv
+    from collections import defaultdict
+    tot = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    names = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            tot[k][c] += float(r["Counter_Value"])
+            disp[k].add(r["Dispatch_Id"])
+    rows = sorted(tot, key=lambda k: -tot[k].get(names[0], 0.0) if names else 0.0)
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---:|" + "---:|" * len(names)]
+    for k in rows:
+        out.append(f"| {k} | {len(disp[k])} | " + " | ".join(f"{tot[k].get(c, 0.0):.4g}" for c in names) + " |")
+    return "\n".join(out)
+
+
 def traffic_record(kernel: str):
     """Counter-derived HBM bytes per launch for `kernel`, or None when none was taken or
     the kernel source changed since."""
@@ -751,6 +775,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--precision-checkpoints", action="store_true",
                     help="instead of the timed run: one low-precision step from each float64 checkpoint")
+    ap.add_argument("--pmc-summary", metavar="COUNTER_CSV",
+                    help="per-kernel totals of every counter in a rocprofv3 --pmc CSV, then exit")
     ap.add_argument("--judge", action="store_true",
                     help="the per-step judge of a corrected S against the plain S on an untrained correction "
                          "(use with --L 10 --N 5 --steps 180)")
@@ -766,6 +792,9 @@ def main():
         return
     if a.summarize:
         print(summarize(a.summarize))
+        return
+    if a.pmc_summary:
+        print(pmc_summary(a.pmc_summary))
         return
     if a.pmc_traffic:
         print(json.dumps(pmc_traffic(*a.pmc_traffic, cal_bytes=a.cal_bytes, commands=a.commands), indent=1))
