@@ -118,13 +118,23 @@ def pmc_traffic(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_cs
         return sum(vals) * 1024.0 * fac / n
 
     rd, wr = per_launch(fetch_csv, ff), per_launch(write_csv, fw)
-    alg = b["roofline"]["achieved"] * 1e9 * b["roofline"]["avg_launch_ms"] * 1e-3 \
-        if b["roofline"]["unit"] == "GB/s" else None
+    alg, note = None, None
+    if b["roofline"]["unit"] == "GB/s":
+        alg = b["roofline"]["achieved"] * 1e9 * b["roofline"]["avg_launch_ms"] * 1e-3
+        note = "the roofline's achieved rate times its average launch time"
+    else:
+        # a flop-bound class: its bytes from the instrumented pass of the same command
+        cls = next((c for c, (k, _) in KERNELS.items() if k == kernel), None)
+        kc = b.get("kernel_classes", {}).get(cls) if cls else None
+        if kc and kc["calls"] > 0:
+            alg = kc["gbs"] * 1e6 * kc["ms"] / kc["calls"]
+            note = (f"kernel_classes.{cls} of the bench line: {kc['gbs']:.2f} GB/s over {kc['ms']:.1f} ms, "
+                    f"{kc['calls']} launches (8 (MK + KN + MN) bytes per problem, 2 MN when beta != 0)")
     return {"kernel": kernel, "kernel_source_sha256": _kernel_hash(), "launches": n,
             "fetch_factor": ff, "write_factor": fw, "read_bytes_per_launch": rd,
             "write_bytes_per_launch": wr, "traffic_bytes_per_launch": rd + wr,
-            "algorithmic_bytes_per_launch": alg, "workload": b["config"]["workload"],
-            "commands": commands}
+            "algorithmic_bytes_per_launch": alg, "algorithmic_note": note,
+            "workload": b["config"]["workload"], "commands": commands}
 
 
 def pmc_summary(path: str) -> str:
