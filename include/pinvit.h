@@ -243,6 +243,14 @@ pv_status pv_set_gemm_tiles(pv_ctx* ctx, int mode);
  * max_rows.  pv_gemm_tune_clear empties the table (no context may be running). */
 pv_status pv_gemm_tune_table(double* rows, int max_rows, int* n_rows);
 pv_status pv_gemm_tune_clear(void);
+/* Load n_rows rows (host, row-major, the layout pv_gemm_tune_table writes) into the table,
+ * replacing the entries of their keys: a table measured once (on this device model and
+ * workload) serves later processes in PV_GEMM_TILES_TABLE mode without exploring.  The
+ * stored rates are kept (pv_gemm_tune_table returns them unchanged).  Every row is checked
+ * before any is loaded: PV_EINVAL for non-finite values, a kernel precision other than 0
+ * or 2, a choice outside -1..1, negative counts, rates or buckets, or NULL rows with
+ * n_rows > 0. */
+pv_status pv_gemm_tune_load(const double* rows, int n_rows);
 
 /* <a|b> (Euclidean inner product) by a transfer sweep. */
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out);

@@ -518,6 +518,13 @@ pv_status pv_gemm_tune_clear(void) {
   return guard([&] { gemm_tune_clear(); });
 }
 
+pv_status pv_gemm_tune_load(const double* rows, int n_rows) {
+  return guard([&] {
+    if (n_rows < 0 || (n_rows > 0 && !rows)) fail(PV_EINVAL, "need n_rows >= 0 and rows for n_rows > 0");
+    gemm_tune_load(rows, n_rows);
+  });
+}
+
 pv_status pv_dot(pv_ctx* ctx, int a, int b, double* out) {
   return guard([&] {
     if (!ctx || !out) fail(PV_EINVAL, "null argument");

@@ -268,6 +268,37 @@ void gemm_tune_clear() {
   g_tune.clear();
 }
 
+void gemm_tune_load(const double* rows, int n) {
+  // validate every row before changing the table
+  for (int i = 0; i < n; ++i) {
+    const double* r = rows + size_t(9) * i;
+    for (int j = 0; j < 9; ++j)
+      if (!std::isfinite(r[j])) fail(PV_EINVAL, "tuner row " + std::to_string(i) + " is not finite");
+    const bool ints = r[0] == std::floor(r[0]) && r[1] == std::floor(r[1]) && r[2] == std::floor(r[2]) &&
+                      r[3] == std::floor(r[3]) && r[4] == std::floor(r[4]) && r[5] == std::floor(r[5]) &&
+                      r[6] == std::floor(r[6]);
+    if (!ints || r[0] < 0 || r[0] > 63 || (r[1] != 0 && r[1] != 2) || r[2] < 0 || r[2] > 62 || r[3] < 0 ||
+        r[3] > 30 || r[4] < -1 || r[4] > 1 || r[5] < 0 || r[6] < 0 || r[5] > 1e9 || r[6] > 1e9 || r[7] < 0 ||
+        r[8] < 0)
+      fail(PV_EINVAL, "tuner row " + std::to_string(i) + " out of range");
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int i = 0; i < n; ++i) {
+    const double* r = rows + size_t(9) * i;
+    TuneEntry e;
+    e.choice = int(r[4]);
+    e.n[0] = int(r[5]);
+    e.n[1] = int(r[6]);
+    e.issued = e.n[0] + e.n[1];
+    // one millisecond per shape at the stored rate (the table keeps rates, not times)
+    for (int j = 0; j < 2; ++j) {
+      e.ms[j] = r[7 + j] > 0 ? 1.0 : 0.0;
+      e.flops[j] = r[7 + j] * 1e9;
+    }
+    g_tune[TuneKey{int(r[0]), int(r[1]), int(r[2]), int(r[3])}] = e;
+  }
+}
+
 void Ctx::sync() {
   if (side_stream) PV_HIP(hipStreamSynchronize(side_stream));
   if (main_stream && main_stream != stream) PV_HIP(hipStreamSynchronize(main_stream));

@@ -237,6 +237,8 @@ struct Ctx {
 // each shape, and each shape's measured rate in TFLOP/s
 std::vector<double> gemm_tune_rows();
 void gemm_tune_clear();
+// n rows in the layout of gemm_tune_rows, validated, replacing the entries of their keys
+void gemm_tune_load(const double* rows, int n);
 
 // ---- operations (engine.cpp) ----
 std::unique_ptr<Mps> mps_alloc(Ctx& c, int L, int N, const std::vector<std::vector<int>>& rho);

@@ -26,7 +26,7 @@ EXPORTS = [
     "pv_set_learned_network", "pv_solve_h", "pv_mps_amplitudes",
     "pv_timers", "pv_timer_name", "pv_timers_reset", "pv_set_timer_mask", "pv_set_timer_sampling", "pv_sym_eig", "pv_sym_eig_top", "pv_sym_eig_noalloc", "pv_gemm", "pv_cholesky", "pv_mpo_bond_dims", "pv_mpo_dense",
     "pv_mfma_f64_rate", "pv_set_gemm_tiles", "pv_gemm_tune_table", "pv_gemm_tune_clear",
-    "pv_set_learned_judge", "pv_learned_judge_counts",
+    "pv_set_learned_judge", "pv_learned_judge_counts", "pv_gemm_tune_load",
 ]
 
 
@@ -145,6 +145,7 @@ def lib():
         L.pv_learned_judge_counts.argtypes = [C.c_void_p, ip, ip]
         L.pv_gemm_tune_table.argtypes = [dp, C.c_int, ip]
         L.pv_gemm_tune_clear.argtypes = []
+        L.pv_gemm_tune_load.argtypes = [dp, C.c_int]
         fp, up = C.POINTER(C.c_float), C.POINTER(C.c_uint64)
         L.pv_learned_train_solves.argtypes = [C.c_void_p, fp, C.c_int, up, C.c_int, dp, dp, C.c_int, C.c_float,
                                               dp, dp]
@@ -214,6 +215,15 @@ def gemm_tune_table():
             d[k] = int(d[k])
         out.append(d)
     return out
+
+
+def gemm_tune_load(rows):
+    """Load tuner rows (dicts as gemm_tune_table returns them) into the table
+    (pv_gemm_tune_load)."""
+    names = ("device", "prec", "tiles_log2", "k_log2", "choice", "n64", "n32", "tflops64", "tflops32")
+    a = np.array([[float(r[k]) for k in names] for r in rows], dtype=np.float64).reshape(-1, 9)
+    a = np.ascontiguousarray(a)
+    _check(lib().pv_gemm_tune_load(_dp(a) if len(rows) else None, len(rows)))
 
 
 def gemm_tune_clear():

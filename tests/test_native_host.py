@@ -106,6 +106,33 @@ def test_gemm_tuner_table_is_host_state():
     assert {k.lower(): int(v) for k, v in defs.items()} == native.GEMM_TILES
 
 
+def test_gemm_tuner_table_round_trips_and_rejects_bad_rows():
+    """A stored tuner table loads back as it was written (counts, choices; rates to
+    rounding), a row of an existing key replaces it, and rows out of range are rejected
+    before any is loaded."""
+    native.gemm_tune_clear()
+    rows = [dict(device=0, prec=0, tiles_log2=10, k_log2=7, choice=1, n64=4, n32=4, tflops64=19.52, tflops32=21.82),
+            dict(device=0, prec=2, tiles_log2=3, k_log2=9, choice=-1, n64=1, n32=0, tflops64=0.5, tflops32=0.0)]
+    native.gemm_tune_load(rows)
+    got = native.gemm_tune_table()
+    assert len(got) == 2
+    for a, b in zip(sorted(got, key=lambda r: r["prec"]), rows):
+        for k in ("device", "prec", "tiles_log2", "k_log2", "choice", "n64", "n32"):
+            assert a[k] == b[k]
+        assert a["tflops64"] == pytest.approx(b["tflops64"], rel=1e-14)
+        assert a["tflops32"] == pytest.approx(b["tflops32"], rel=1e-14)
+    native.gemm_tune_load([dict(rows[0], choice=0)])
+    assert [r["choice"] for r in native.gemm_tune_table() if r["prec"] == 0] == [0]
+    for bad in (dict(rows[0], prec=1), dict(rows[0], choice=2), dict(rows[0], n64=-1),
+                dict(rows[0], tflops32=float("nan")), dict(rows[0], k_log2=2.5)):
+        with pytest.raises(native.PvError):
+            native.gemm_tune_load([dict(rows[0], tiles_log2=20), bad])
+        assert all(r["tiles_log2"] != 20 for r in native.gemm_tune_table())
+    native.gemm_tune_load([])
+    native.gemm_tune_clear()
+    assert native.gemm_tune_table() == []
+
+
 @pytest.mark.parametrize("kind,L", [("dense", 8), ("decayed", 12), ("decayed", 16)])
 def test_mpo_bond_states_match_the_block_sparse_oracle(kind, L):
     """The library's MPO and the block-sparse oracle's (built independently from the same
