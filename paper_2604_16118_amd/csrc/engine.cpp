@@ -289,7 +289,8 @@ void gemm_tune_load(const double* rows, int n) {
     e.choice = int(r[4]);
     e.n[0] = int(r[5]);
     e.n[1] = int(r[6]);
-    e.issued = e.n[0] + e.n[1];
+    // an undecided key explores again from the start (both shapes get their samples)
+    e.issued = e.choice >= 0 ? e.n[0] + e.n[1] : 0;
     // one millisecond per shape at the stored rate (the table keeps rates, not times)
     for (int j = 0; j < 2; ++j) {
       e.ms[j] = r[7 + j] > 0 ? 1.0 : 0.0;
