@@ -1,5 +1,6 @@
 // Allocation-free entry point: the symmetric eigensolver on caller-owned device buffers,
 // with its work area in a file-scope device array instead of the context's memory pool.
+#include <algorithm>
 #include <mutex>
 
 #include "engine.hpp"
@@ -50,15 +51,21 @@ void sym_eig_noalloc(Ctx& c, int n, const double* A, double* w, double* V) {
                         ", the largest order the fixed work array of pv_sym_eig_noalloc holds");
   PV_HIP(hipSetDevice(c.device));
   double* base = noalloc_scratch(c.device);
+  // no timing events, and the step reduction whatever the context's setting: the panel
+  // reduction's trailing updates go through the GEMM, whose split-K partials are allocated
   const uint32_t mask = c.timer_mask;
+  const int steps = c.tri_step_max;
   c.timer_mask = 0;
+  c.tri_step_max = std::max(steps, 1);
   try {
     sym_eig_tridiag_device(c, n, A, w, V, base + kDescDoubles, reinterpret_cast<EigDesc*>(base));
   } catch (...) {
     c.timer_mask = mask;
+    c.tri_step_max = steps;
     throw;
   }
   c.timer_mask = mask;
+  c.tri_step_max = steps;
 }
 
 }  // namespace pv

@@ -56,3 +56,31 @@ def test_noalloc_eigensolver_rejects_an_order_beyond_its_array():
         with pytest.raises(native.PvError) as e:
             ctx.sym_eig_noalloc(n, dA.data_ptr(), dw.data_ptr(), dV.data_ptr())
         assert e.value.status == -1 and "512" in str(e.value)
+
+
+def test_noalloc_eigensolver_keeps_the_step_reduction_under_the_panel_setting():
+    """pv_set_tridiag_steps(ctx, 0) sends the context's own eigensolves to the panel
+    reduction, whose trailing GEMM updates allocate their split-K partials; the
+    allocation-free call keeps the step reduction and its fixed work area (the same bits as
+    without the setting) and leaves the context's setting in force for its own solves."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 300
+    A = _matrix(n, 3)
+    with native.Context(0) as ctx:
+        dA = torch.from_numpy(A.ravel(order="F").copy()).to("cuda")
+        out = []
+        for steps in (native.TRIDIAG_STEPS_DEFAULT, 0):
+            print(f"# pv_sym_eig_noalloc n={n} with pv_set_tridiag_steps({steps})", flush=True)
+            ctx.set_tridiag_steps(steps)
+            dw = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+            dV = torch.full((n * n,), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            ctx.sym_eig_noalloc(n, dA.data_ptr(), dw.data_ptr(), dV.data_ptr())
+            out.append((dw.cpu().numpy(), dV.cpu().numpy()))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+        w_panel, _ = ctx.sym_eig(A, 1)  # the context's own solve, on the panels
+        an = np.abs(out[0][0]).max()
+        assert np.abs(w_panel - out[0][0]).max() <= 1e-12 * an
+        ctx.set_tridiag_steps(native.TRIDIAG_STEPS_DEFAULT)
