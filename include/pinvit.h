@@ -520,8 +520,9 @@ pv_status pv_sym_eig_top(pv_ctx* ctx, int n, const double* A, double* w, double*
  * device array sized for n <= PV_NOALLOC_MAX_N (about 14.7 MB, held on every device the
  * library runs on until the process ends); PV_EINVAL for larger n.  Every call on one
  * device shares that array, so calls that overlap on one device (several contexts or
- * threads at once) race; no kernel timing is recorded.  No hipMalloc, hipFree or HIP
- * event creation happens inside the call. */
+ * threads at once) race; no kernel timing is recorded.  The call always takes the
+ * step reduction to tridiagonal form, whatever pv_set_tridiag_steps says for the context.
+ * No hipMalloc, hipFree or HIP event creation happens inside the call. */
 #define PV_NOALLOC_MAX_N 512
 pv_status pv_sym_eig_noalloc(pv_ctx* ctx, int n, const double* A, double* w, double* V);
 
